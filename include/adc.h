@@ -1,0 +1,159 @@
+/*
+ * adc.h -- C ABI of the MI355X sigma-build library for CD-based relativistic
+ * ADC(2)/ADC(3)/ADC(2)+x(3) (EE, IP, EA).
+ *
+ * The library solves the Hermitian secular problem M X = X Omega, X^H X = 1
+ * (Section 2.1, eq. 10) for the k algebraically lowest roots, where M is the
+ * ISR secular matrix in Moller-Plesset partitioning truncated per block by
+ * perturbation order (eq. 11) and, for the x-scaled variant (Section 2.1,
+ * sm-ADC), M(x) = M_ADC(2) + x (M_ADC(3) - M_ADC(2)).  Two-electron integrals
+ * enter only through complex Cholesky vectors, <pq||rs> = sum_Q (L^Q_pr L^Q_qs
+ * - L^Q_ps L^Q_qr) (Section 2.5, eq. 43); <ab||cd> and <ab||ci> are never
+ * stored, they are rebuilt batch-wise from L on every sigma build.
+ *
+ * Conventions
+ *   - complex numbers are interleaved (re, im) float64 pairs ("c128");
+ *   - spinor index order: occupied 0..o-1, then virtual o..o+v-1;
+ *   - L is c128 [n_chol][n][n] row-major, n = o+v, Hermitian in (p,q) for
+ *     every Q (the MO transform of real AO Cholesky vectors, eq. 42);
+ *   - packed ISR vectors (occupied indices first, pairs i<j, a<b in
+ *     lexicographic order):
+ *        EE: [ (i,a) i-major                 | ((i<j),(a<b)) pair-major ]
+ *        IP: [ i                             | ((i<j), a) ]
+ *        EA: [ a                             | (i, (a<b)) ]
+ *     The basis states are a+_a a_i, a+_a a_i a+_b a_j (EE), a_i, a+_a a_i a_j
+ *     (IP), a+_a, a+_a a+_b a_j (EA) applied to the MP ground state and
+ *     orthonormalised as in Section 2.1;
+ *   - eigenvalues are E_n(N') - E_0(N) in hartree, ascending.
+ *
+ * Return codes: 0 = OK, +1 = ADC_NOT_CONVERGED (a warning: outputs are filled
+ * and converged[r] is 0 for the affected roots), negative = error.  No C++
+ * exception crosses this interface; the library never frees caller memory.
+ * One handle must not be used from two host threads at once; distinct handles
+ * are independent.
+ */
+#ifndef ADC_H
+#define ADC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum adc_kind { ADC_EE = 0, ADC_IP = 1, ADC_EA = 2 };
+
+/* Arithmetic of the sigma build.  ADC_FP64 runs every contraction in FP64;
+ * ADC_FP32 runs the large trial-vector contractions (ladder, ring, coupling)
+ * on FP32 MFMA with FP32 accumulation; ADC_SPLIT_BF16 splits each FP32
+ * operand into bf16 hi + lo and accumulates three bf16 MFMA products in FP32.
+ * M11, the diagonal and all Davidson algebra always stay FP64. */
+enum adc_precision { ADC_FP64 = 0, ADC_FP32 = 1, ADC_SPLIT_BF16 = 2 };
+
+enum adc_status {
+  ADC_OK = 0,
+  ADC_NOT_CONVERGED = 1,
+  ADC_ERR_INVALID_ARG = -1,
+  ADC_ERR_NONFINITE_INPUT = -2,
+  ADC_ERR_NOT_HERMITIAN = -3,
+  ADC_ERR_OUT_OF_MEMORY = -4,
+  ADC_ERR_HIP = -5,
+  ADC_ERR_UNSUPPORTED = -6
+};
+
+/* One problem (instance).
+ *   kind      ADC_EE / ADC_IP / ADC_EA
+ *   n_occ     o >= 1, n_vir v >= 2, n_chol N >= 1, n_roots k >= 1
+ *   eps       host float64 [o+v], occupied first, in hartree; copied
+ *   L         c128 [N][n][n] (see above); host memory (copied to the device
+ *             at adc_init) or, with L_on_device = 1, a device pointer that is
+ *             borrowed and must stay valid until adc_free
+ *   x         scaling of the third-order part; 1 = ADC(3), 0 = ADC(2); any
+ *             finite value is accepted */
+typedef struct adc_problem {
+  int kind;
+  int n_occ, n_vir, n_chol, n_roots;
+  const double* eps;
+  const void* L;
+  int L_on_device;
+  double x;
+} adc_problem;
+
+/* Options (zero-initialised fields take the defaults in brackets).
+ *   precision     default arithmetic of adc_sigma / adc_davidson [ADC_FP64]
+ *   conv_tol      residual norm threshold of the Davidson solver [1e-7]
+ *   max_iter      Davidson iterations [200]
+ *   max_subspace  subspace size before collapse to 2k [6k]
+ *   refine_fp64   mixed precision only: after convergence, continue in FP64
+ *                 until the FP64 residual meets conv_tol [1]
+ *   stream        hipStream_t to enqueue on; NULL = a library-owned stream
+ *   mem_budget    bytes of device workspace for the integral batches
+ *                 [0 = 4 GiB]
+ *   verbose       1 = one line per Davidson iteration on stderr */
+typedef struct adc_options {
+  int precision;
+  double conv_tol;
+  int max_iter;
+  int max_subspace;
+  int refine_fp64;
+  void* stream;
+  size_t mem_budget;
+  int verbose;
+} adc_options;
+
+typedef struct adc_handle adc_handle;
+
+/* Validate the problem, copy eps (and L unless borrowed) to the device and
+ * run the one-off work on the device: the stored integral classes <ij||kl>,
+ * <ij||ka>, <ij||ab>, <ia||jb>; the MP amplitudes t(1), t(2) (with one pass
+ * of the particle-particle ladder), the second-order singles; the dense
+ * singles block M11 with its third-order part kept separate so that x scales
+ * it.  Errors: INVALID_ARG (shapes, NULL pointers, n_problems != 1),
+ * NONFINITE_INPUT (NaN/Inf in eps or L), NOT_HERMITIAN (max |L^Q - L^Q^H| >
+ * 1e-12 max |L^Q| for some Q), OUT_OF_MEMORY, HIP_ERROR.  On error *out is
+ * NULL and nothing is leaked.  Synchronous. */
+int adc_init(const adc_problem* problems, int n_problems, const adc_options* opts,
+             adc_handle** out);
+
+/* Sizes n1 (singles) and n2 (doubles) of instance inst; dim = n1 + n2. */
+int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2);
+
+/* S = M(x) Y for k packed c128 vectors.  Y and S are device arrays
+ * [k][dim], must not alias, and stay owned by the caller.  precision < 0
+ * uses the handle's default.  Enqueued on the handle's stream
+ * (asynchronous).  Errors: INVALID_ARG, HIP_ERROR. */
+int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precision);
+
+/* Block Davidson for the n_roots lowest eigenpairs of every instance.
+ *   guess[inst]  NULL, or device c128 [n_roots][dim] start vectors (resume)
+ *   omega        host float64 [n_roots], ascending, hartree
+ *   vecs[inst]   NULL, or device c128 [n_roots][dim] output Ritz vectors
+ *   resnorm      host float64 [n_roots]   final FP64 residual norms
+ *   iters        host int [n_problems]    iterations used
+ *   converged    host int [n_roots]       1 if the root met the criteria
+ * Subspace algebra (Gram matrix, Ritz vectors, residuals, norms,
+ * preconditioner, orthogonalisation) runs in FP64 device kernels; the small
+ * subspace eigenproblem runs on the host.  Synchronous.  Returns
+ * ADC_NOT_CONVERGED if any root missed the criteria. */
+int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs,
+                 double* resnorm, int* iters, int* converged);
+
+/* Vector-Jacobian product of adc_sigma (reserved; returns ADC_ERR_UNSUPPORTED
+ * in this version). */
+int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k,
+                       void* dL, double* dx);
+
+/* Milliseconds spent in adc_init on the device (one-off work). */
+double adc_init_ms(const adc_handle* h);
+
+/* Release every library allocation of the handle.  NULL is accepted. */
+void adc_free(adc_handle* h);
+
+/* Static message for a status code. */
+const char* adc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ADC_H */

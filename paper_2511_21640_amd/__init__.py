@@ -1,0 +1,173 @@
+"""Python binding of libadc (C ABI in include/adc.h).
+
+Argument marshalling only: every step of the sigma build and of the Davidson
+solver runs in the library's HIP kernels.  torch supplies device memory and
+the stream.  Importing this package does not build anything; ``build()``
+compiles the library for gfx950.  Using a handle without the library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadc.so")
+
+KINDS = {"EE": 0, "IP": 1, "EA": 2}
+PREC = {"fp64": 0, "fp32": 1, "split_bf16": 2}
+
+ADC_OK = 0
+ADC_NOT_CONVERGED = 1
+ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE_INPUT", -3: "NOT_HERMITIAN", -4: "OUT_OF_MEMORY",
+          -5: "HIP_ERROR", -6: "UNSUPPORTED"}
+
+# Every symbol include/adc.h declares.
+EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_davidson", "adc_sigma_backward",
+           "adc_init_ms", "adc_free", "adc_strerror"]
+
+
+class AdcProblem(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("n_occ", ctypes.c_int), ("n_vir", ctypes.c_int),
+                ("n_chol", ctypes.c_int), ("n_roots", ctypes.c_int),
+                ("eps", ctypes.POINTER(ctypes.c_double)), ("L", ctypes.c_void_p),
+                ("L_on_device", ctypes.c_int), ("x", ctypes.c_double)]
+
+
+class AdcOptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("conv_tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("max_subspace", ctypes.c_int), ("refine_fp64", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("mem_budget", ctypes.c_size_t), ("verbose", ctypes.c_int)]
+
+
+class AdcError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {ERRORS.get(code, code)}")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libadc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libadc.so not built ({path}); run paper_2511_21640_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    lib.adc_init.argtypes = [ctypes.POINTER(AdcProblem), ctypes.c_int, ctypes.POINTER(AdcOptions),
+                             ctypes.POINTER(ctypes.c_void_p)]
+    lib.adc_init.restype = ctypes.c_int
+    lib.adc_dims.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                             ctypes.POINTER(ctypes.c_longlong)]
+    lib.adc_sigma.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.c_int]
+    lib.adc_davidson.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.adc_sigma_backward.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.adc_init_ms.argtypes = [ctypes.c_void_p]
+    lib.adc_init_ms.restype = ctypes.c_double
+    lib.adc_free.argtypes = [ctypes.c_void_p]
+    lib.adc_free.restype = None
+    lib.adc_strerror.argtypes = [ctypes.c_int]
+    lib.adc_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def build():
+    from .build import build as _b
+    return _b()
+
+
+class Handle:
+    """One problem instance on the current HIP device.
+
+    eps: float64 [o+v]; L: complex128 [N][n][n] (numpy host array, or a torch
+    cuda tensor which is borrowed).  precision: 'fp64' | 'fp32' | 'split_bf16'.
+    """
+
+    def __init__(self, kind, o, v, eps, L, n_roots, x=1.0, precision="fp64", conv_tol=1e-7, max_iter=200,
+                 max_subspace=0, stream=None, mem_budget=0, verbose=False):
+        import torch
+        self._lib = load()
+        self.kind, self.o, self.v = kind, int(o), int(v)
+        self.n_roots = int(n_roots)
+        self._eps = np.ascontiguousarray(eps, dtype=np.float64)
+        on_dev = hasattr(L, "is_cuda") and L.is_cuda
+        if on_dev:
+            assert L.dtype == torch.complex128 and L.is_contiguous()
+            self._L = L
+            Lptr = L.data_ptr()
+        else:
+            self._L = np.ascontiguousarray(L, dtype=np.complex128)
+            Lptr = self._L.ctypes.data
+        n_chol = int(self._L.shape[0])
+        prob = AdcProblem(KINDS[kind], self.o, self.v, n_chol, self.n_roots,
+                          self._eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), Lptr, 1 if on_dev else 0,
+                          float(x))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        opts = AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1, ctypes.c_void_p(stream),
+                          mem_budget, 1 if verbose else 0)
+        h = ctypes.c_void_p()
+        rc = self._lib.adc_init(ctypes.byref(prob), 1, ctypes.byref(opts), ctypes.byref(h))
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_init")
+        self._h = h
+        n1, n2 = ctypes.c_longlong(), ctypes.c_longlong()
+        self._lib.adc_dims(h, 0, ctypes.byref(n1), ctypes.byref(n2))
+        self.n1, self.n2 = n1.value, n2.value
+        self.dim = self.n1 + self.n2
+
+    @property
+    def init_ms(self):
+        return self._lib.adc_init_ms(self._h)
+
+    def sigma(self, Y, S=None, precision=None):
+        """S = M(x) Y for a torch complex128 cuda tensor Y [k][dim]."""
+        import torch
+        assert Y.is_cuda and Y.dtype == torch.complex128 and Y.is_contiguous() and Y.shape[-1] == self.dim
+        Y2 = Y.reshape(-1, self.dim)
+        if S is None:
+            S = torch.empty_like(Y2)
+        p = -1 if precision is None else PREC[precision]
+        rc = self._lib.adc_sigma(self._h, 0, ctypes.c_void_p(Y2.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                 Y2.shape[0], p)
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_sigma")
+        return S.reshape(Y.shape)
+
+    def davidson(self, guess=None, want_vectors=True):
+        import torch
+        k = self.n_roots
+        omega = np.zeros(k)
+        res = np.zeros(k)
+        iters = (ctypes.c_int * 1)()
+        conv = (ctypes.c_int * k)()
+        vecs = torch.empty((k, self.dim), dtype=torch.complex128, device="cuda") if want_vectors else None
+        g_arr = (ctypes.c_void_p * 1)(guess.data_ptr()) if guess is not None else None
+        v_arr = (ctypes.c_void_p * 1)(vecs.data_ptr()) if vecs is not None else None
+        rc = self._lib.adc_davidson(self._h, g_arr, omega.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), v_arr,
+                                    res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), iters, conv)
+        if rc not in (ADC_OK, ADC_NOT_CONVERGED):
+            raise AdcError(rc, "adc_davidson")
+        return dict(omega=omega, resnorm=res, iters=iters[0], converged=np.array(conv[:], dtype=bool),
+                    vectors=vecs, status=rc)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.adc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

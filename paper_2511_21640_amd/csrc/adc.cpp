@@ -1,0 +1,1093 @@
+// C ABI of the sigma-build library: handle, validation, one-off device work
+// (stored integral classes, MP amplitudes, the dense singles block), the
+// matrix-free sigma build and the block Davidson solver.
+//
+// The ISR secular matrix (Section 2.1) is applied term by term.  Every term is
+// a complex tensor contraction executed by ctr() (batched MFMA GEMMs plus
+// permutes); the particle-particle ladder, whose <ab||cd> integrals are never
+// stored, has its own batched path: for a block of virtual indices a the
+// Coulomb block W[(a,c)][(b,d)] = sum_Q L^Q_ac L^Q_bd is one GEMM over Q, the
+// antisymmetrised rows <ab||cd> = W_ab,cd - W_ab,dc (c<d) are packed, and a
+// second GEMM contracts them with the packed trial vectors (Section 2.5,
+// on-the-fly generation of the four-external integrals).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <vector>
+
+#include "../../include/adc.h"
+#include "internal.h"
+
+using namespace adc;
+using zc = std::complex<double>;
+
+namespace {
+
+struct Status {
+  int code;
+  const char* msg;
+};
+
+struct Inst {
+  int kind = 0, o = 0, v = 0, N = 0, k = 0;
+  double x = 1.0;
+  int64_t n1 = 0, n2 = 0, dim = 0, Po = 0, Pv = 0;
+  double* eps = nullptr;  // device
+  Tensor Loo, Lov, Lvo, Lvv;
+  Tensor oooo, ooov, oovv, ovov, ovvv;
+  Tensor ring;            // [k][c][j][b] = <kb||jc>
+  Tensor t1;              // [o][o][v][v]
+  Tensor M11x;            // n1 x n1, M11(0..2) + x M11(3)
+  Tensor W;               // EE: [I][J][i][B] = sum_cd t*_IJcd <cd||iB>
+  int2* pair_o = nullptr;
+  int2* pair_v = nullptr;
+  double* diag = nullptr; // device zeroth-order diagonal [dim]
+  std::vector<double> m11diag;  // host, real part of diag(M11x)
+};
+
+}  // namespace
+
+struct adc_handle {
+  Ctx cx;
+  adc_options opt{};
+  bool own_stream = false;
+  double init_ms = 0.0;
+  std::vector<Inst> inst;
+  std::vector<void*> raw;  // plain device allocations
+};
+
+namespace {
+
+void* dmalloc(adc_handle* h, size_t bytes) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw HipError{hipErrorOutOfMemory, "hipMalloc"};
+  }
+  h->raw.push_back(p);
+  return p;
+}
+
+Tensor tensor_view(double2* p, std::vector<int64_t> d, std::vector<int64_t> st) {
+  Tensor t;
+  t.p = p;
+  t.d = std::move(d);
+  t.st = std::move(st);
+  return t;
+}
+
+int64_t npair(int64_t n) { return n * (n - 1) / 2; }
+
+std::vector<int2> pair_table(int n) {
+  std::vector<int2> t;
+  for (int p = 0; p < n; ++p)
+    for (int q = p + 1; q < n; ++q) t.push_back(make_int2(p, q));
+  return t;
+}
+
+// ----------------------------------------------------------------------------
+// particle-particle ladder:  S[z][offS + ij*Pv + ab] += alpha * sum_{c<d} <ab||cd> Y[z][offY + ij*Pv + cd]
+// for rows ij in [0, nrow), z in [0, k).  L_vv is [Q][v][v].
+// ----------------------------------------------------------------------------
+void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY, double2* S, int64_t ldS,
+            int64_t offS, int64_t nrow, int k, cplx alpha, int prec) {
+  Ctx& cx = h->cx;
+  const int v = I.v;
+  const int64_t Pv = I.Pv, N = I.N;
+  if (Pv == 0 || nrow == 0 || k == 0) return;
+  const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
+  // W block: nb*v rows x (v-b0)*v cols; V block: npairs x Pv
+  const int64_t per_a = (int64_t)v * v * v + (int64_t)v * Pv;
+  int nb = (int)std::max<int64_t>(1, (int64_t)(budget / 2 / sizeof(double2)) / std::max<int64_t>(1, per_a));
+  nb = std::min(nb, v - 1);
+  double2* Wbuf = cx.pool.get((int64_t)nb * v * v * v);
+  double2* Vbuf = cx.pool.get((int64_t)nb * v * Pv);
+  for (int a0 = 0; a0 < v - 1; a0 += nb) {
+    const int a1 = std::min(v - 1, a0 + nb);
+    const int b0 = a0 + 1;
+    // W[(a-a0)*v + c][(b-b0)*v + d] = sum_Q L_ac L_bd
+    GemmDesc g{};
+    g.M = (int64_t)(a1 - a0) * v;
+    g.N = (int64_t)(v - b0) * v;
+    g.K = N;
+    g.batch = 1;
+    g.A = I.Lvv.p + (int64_t)a0 * v; g.sam = 1; g.sak = (int64_t)v * v; g.sab = 0;
+    g.B = I.Lvv.p + (int64_t)b0 * v; g.sbn = 1; g.sbk = (int64_t)v * v; g.sbb = 0;
+    g.C = Wbuf; g.scm = g.N; g.scn = 1; g.scb = 0;
+    g.alpha = C1(); g.beta = C0();
+    launch_zgemm(g, prec, cx.stream);
+    const int64_t pbase = (int64_t)a0 * (2 * v - a0 - 1) / 2;
+    const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
+    const int64_t np = pend - pbase;
+    launch_ladder_pack(Wbuf, g.N, a0, b0, v, Vbuf, pbase, np, I.pair_v, cx.stream);
+    // S[z][offS + ij*Pv + pbase + r] += alpha * sum_cd Y[z][offY + ij*Pv + cd] V[r][cd]
+    GemmDesc c{};
+    c.M = nrow; c.N = np; c.K = Pv; c.batch = k;
+    c.A = Y + offY; c.sam = Pv; c.sak = 1; c.sab = ldY;
+    c.B = Vbuf; c.sbk = 1; c.sbn = Pv; c.sbb = 0;
+    c.C = S + offS + pbase; c.scm = Pv; c.scn = 1; c.scb = ldS;
+    c.alpha = alpha; c.beta = C1();
+    launch_zgemm(c, prec, cx.stream);
+  }
+  cx.pool.put(Wbuf);
+  cx.pool.put(Vbuf);
+}
+
+// copy rows [k][n] with row stride ld (offset off) into a contiguous tensor, or back
+void rows_in(Ctx& cx, const double2* src, int64_t ld, int64_t off, Tensor& dst, int k, int64_t n) {
+  int64_t od[2] = {k, n}, is[2] = {ld, 1}, os[2] = {n, 1};
+  launch_permute(2, od, is, os, src + off, dst.p, C1(), C0(), 0, cx.stream);
+}
+void rows_out(Ctx& cx, const Tensor& src, double2* dst, int64_t ld, int64_t off, int k, int64_t n, cplx beta) {
+  int64_t od[2] = {k, n}, is[2] = {n, 1}, os[2] = {ld, 1};
+  launch_permute(2, od, is, os, src.p, dst + off, C1(), beta, 0, cx.stream);
+}
+
+// ============================================================================
+// EE
+// ============================================================================
+void ee_m2(Ctx& cx, Inst& I, const Tensor& tt, Tensor& X) {
+  // X[i,a,I,A] += 1/2 t(ikac) <Ik||Ac> - 1/4 d_iI t(klac)<kl||Ac> - 1/4 d_aA t(ikcd)<Ik||cd>
+  const int o = I.o, v = I.v;
+  ctr(cx, CR(0.5), tt, "ikac", false, I.oovv, "IkAc", false, C1(), X, "iaIA");
+  Tensor f = tnew(cx, {v, v});
+  ctr(cx, CR(-0.25), tt, "klac", false, I.oovv, "klAc", false, C0(), f, "aA");
+  launch_m11_add_delta(X.p, f.p, o, v, 0, cx.stream);
+  Tensor hh = tnew(cx, {o, o});
+  ctr(cx, CR(-0.25), tt, "ikcd", false, I.oovv, "Ikcd", false, C0(), hh, "iI");
+  launch_m11_add_delta(X.p, hh.p, o, v, 1, cx.stream);
+  tfree(cx, f);
+  tfree(cx, hh);
+}
+
+void ee_init(adc_handle* h, Inst& I) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v, N = I.N;
+  const int64_t n1 = I.n1;
+  // ---- stored integral classes (eq. 43): <pq||rs> = (pr|qs) - (ps|qr)
+  I.oooo = tnew(cx, {o, o, o, o}, false);
+  ctr(cx, C1(), I.Loo, "Qik", false, I.Loo, "Qjl", false, C0(), I.oooo, "ijkl");
+  ctr(cx, CR(-1), I.Loo, "Qil", false, I.Loo, "Qjk", false, C1(), I.oooo, "ijkl");
+  I.ooov = tnew(cx, {o, o, o, v}, false);
+  ctr(cx, C1(), I.Loo, "Qik", false, I.Lov, "Qja", false, C0(), I.ooov, "ijka");
+  ctr(cx, CR(-1), I.Lov, "Qia", false, I.Loo, "Qjk", false, C1(), I.ooov, "ijka");
+  I.oovv = tnew(cx, {o, o, v, v}, false);
+  ctr(cx, C1(), I.Lov, "Qia", false, I.Lov, "Qjb", false, C0(), I.oovv, "ijab");
+  ctr(cx, CR(-1), I.Lov, "Qib", false, I.Lov, "Qja", false, C1(), I.oovv, "ijab");
+  I.ovov = tnew(cx, {o, v, o, v}, false);
+  ctr(cx, C1(), I.Loo, "Qij", false, I.Lvv, "Qab", false, C0(), I.ovov, "iajb");
+  ctr(cx, CR(-1), I.Lov, "Qib", false, I.Lvo, "Qaj", false, C1(), I.ovov, "iajb");
+  I.ovvv = tnew(cx, {o, v, v, v}, false);
+  ctr(cx, C1(), I.Lov, "Qib", false, I.Lvv, "Qac", false, C0(), I.ovvv, "iabc");
+  ctr(cx, CR(-1), I.Lov, "Qic", false, I.Lvv, "Qab", false, C1(), I.ovvv, "iabc");
+  I.ring = tnew(cx, {o, v, o, v}, false);
+  perm(cx, C1(), I.ovov, "kbjc", false, C0(), I.ring, "kcjb");
+  (void)N;
+
+  // ---- first-order doubles t_ij^ab = <ab||ij>/D = conj(<ij||ab>)/D
+  Tensor& t = I.t1;
+  t = tnew(cx, {o, o, v, v}, false);
+  perm(cx, C1(), I.oovv, "ijab", true, C0(), t, "ijab");
+  launch_div_d2(t.p, I.eps, o, v, cx.stream);
+
+  // ---- second-order doubles: (ladder + hole ladder - ring) / D
+  const int64_t Po = I.Po, Pv = I.Pv;
+  Tensor tpk = tnew(cx, {Po * Pv}, false);
+  launch_pack_doubles(0, t.p, tpk.p, nullptr, Po * Pv, 0, 1, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+  Tensor Ltp = tnew(cx, {Po * Pv});
+  ladder(h, I, tpk.p, Po * Pv, 0, Ltp.p, Po * Pv, 0, Po, 1, C1(), 0);
+  Tensor Lt = tnew(cx, {o, o, v, v}, false);
+  launch_unpack_doubles(0, Ltp.p, Po * Pv, 0, 1, o, v, Lt.p, nullptr, cx.stream);
+  tfree(cx, Ltp);
+  tfree(cx, tpk);
+  Tensor Ht = tnew(cx, {o, o, v, v}, false);
+  ctr(cx, CR(0.5), I.oooo, "klij", false, t, "klab", false, C0(), Ht, "ijab");
+  Tensor t2 = tnew(cx, {o, o, v, v}, false);
+  perm(cx, C1(), Lt, "ijab", false, C0(), t2, "ijab");
+  perm(cx, C1(), Ht, "ijab", false, C1(), t2, "ijab");
+  {
+    Tensor R = tnew(cx, {o, v, o, v}, false);
+    ctr(cx, C1(), t, "ikac", false, I.ovov, "kbjc", false, C0(), R, "iajb");
+    Tensor Rr = tnew(cx, {o, o, v, v}, false);
+    perm(cx, C1(), R, "iajb", false, C0(), Rr, "ijab");
+    launch_antisym_add(Rr.p, t2.p, 1, o, o, v, v, 2, CR(-1), cx.stream);
+    tfree(cx, R);
+    tfree(cx, Rr);
+  }
+  launch_div_d2(t2.p, I.eps, o, v, cx.stream);
+
+  // ---- second-order singles
+  Tensor ts = tnew(cx, {o, v});
+  ctr(cx, CR(-0.5), I.ovvv, "jabc", false, t, "ijbc", false, C0(), ts, "ia");
+  ctr(cx, CR(-0.5), I.ooov, "jkib", false, t, "jkab", false, C1(), ts, "ia");
+  launch_div_d1(ts.p, I.eps, o, v, cx.stream);
+
+  // ---- M11: order 0..2 (A) and third order (B)
+  Tensor X2 = tnew(cx, {o, v, o, v});
+  ee_m2(cx, I, t, X2);
+  Tensor MA = tnew(cx, {n1, n1}, false);
+  launch_herm_add(X2.p, MA.p, n1, cx.stream);
+  {
+    // + M11(1) = <aj||ib> = -<ja||ib>
+    Tensor MAv = tensor_view(MA.p, {o, v, o, v}, {});
+    perm(cx, CR(-1), I.ovov, "jaib", false, C1(), MAv, "iajb");
+  }
+  // zeroth order diagonal
+  {
+    std::vector<double> d1(n1);
+    std::vector<double> e(o + v);
+    hipcheck(hipMemcpy(e.data(), I.eps, sizeof(double) * (o + v), hipMemcpyDeviceToHost), "eps");
+    for (int i = 0; i < o; ++i)
+      for (int a = 0; a < v; ++a) d1[(int64_t)i * v + a] = e[o + a] - e[i];
+    double* dd = (double*)h->cx.pool.get((n1 + 1) / 2 + 1);
+    hipcheck(hipMemcpy(dd, d1.data(), sizeof(double) * n1, hipMemcpyHostToDevice), "d1");
+    launch_add_diag(MA.p, dd, n1, cx.stream);
+    hipcheck(hipStreamSynchronize(cx.stream), "sync");
+    h->cx.pool.put((double2*)dd);
+  }
+  Tensor X = tnew(cx, {o, v, o, v});
+  ee_m2(cx, I, t2, X);
+  Tensor fv = tnew(cx, {v, v}), fo = tnew(cx, {o, o});
+  {
+    const Tensor& ov4 = I.ovov;
+    // T1 -ts(ic)<aI||Ac>, <aI||Ac> = -ovvv[I,a,A,c]
+    ctr(cx, C1(), ts, "ic", false, I.ovvv, "IaAc", false, C1(), X, "iaIA");
+    // T2 +ts(ka)<Ik||iA>
+    ctr(cx, C1(), ts, "ka", false, I.ooov, "IkiA", false, C1(), X, "iaIA");
+    // T3 +d_iI ts(kc)<ak||Ac>, <ak||Ac> = -ovvv[k,a,A,c]
+    ctr(cx, CR(-1), ts, "kc", false, I.ovvv, "kaAc", false, C1(), fv, "aA");
+    // T4 -d_aA ts(kc)<Ik||ic>
+    ctr(cx, CR(-1), ts, "kc", false, I.ooov, "Ikic", false, C1(), fo, "iI");
+    // T5 + T8: 1/2 t*(IkAc) (Lt + Ht)(ikac)
+    ctr(cx, CR(0.5), t, "IkAc", true, Lt, "ikac", false, C1(), X, "iaIA");
+    ctr(cx, CR(0.5), t, "IkAc", true, Ht, "ikac", false, C1(), X, "iaIA");
+    // T6 -1/2 t*(IkAc) sum_ld <al||kd> t(ilcd), <al||kd> = -ovov[l,a,k,d]
+    {
+      Tensor P = tnew(cx, {o, v, o, v}, false);
+      ctr(cx, CR(-1), ov4, "lakd", false, t, "ilcd", false, C0(), P, "iakc");
+      ctr(cx, CR(-0.5), t, "IkAc", true, P, "iakc", false, C1(), X, "iaIA");
+      // T7 -1/2 t*(IkAc) sum_ld <cl||id> t(klad), <cl||id> = -ovov[l,c,i,d]
+      Tensor P2 = tnew(cx, {o, o, v, v}, false);
+      ctr(cx, CR(-1), ov4, "lcid", false, t, "klad", false, C0(), P2, "ikca");
+      ctr(cx, CR(-0.5), t, "IkAc", true, P2, "ikca", false, C1(), X, "iaIA");
+      tfree(cx, P);
+      tfree(cx, P2);
+    }
+    // T9  +1/2 t*(Ikcd) <ac||Ae> t(ikde) and T18 -1/4 d_iI rho_ce <ac||Ae>,
+    // <ac||Ae> = (aA|ce) - (ae|cA)
+    Tensor Rr = tnew(cx, {o, o, v, v}, false);
+    ctr(cx, C1(), t, "Ikcd", true, t, "ikde", false, C0(), Rr, "Iice");
+    Tensor rv = tnew(cx, {v, v}, false);
+    ctr(cx, C1(), t, "klcd", true, t, "klde", false, C0(), rv, "ce");
+    {
+      Tensor sQ = tnew(cx, {N, o, o}, false);
+      ctr(cx, C1(), I.Lvv, "Qce", false, Rr, "Iice", false, C0(), sQ, "QIi");
+      ctr(cx, CR(0.5), I.Lvv, "QaA", false, sQ, "QIi", false, C1(), X, "iaIA");
+      Tensor s1 = tnew(cx, {N, 1}, false);
+      Tensor rv1 = tensor_view(rv.p, {v, v, 1}, {});
+      ctr(cx, C1(), I.Lvv, "Qce", false, rv1, "cex", false, C0(), s1, "Qx");
+      Tensor fv1 = tensor_view(fv.p, {v, v, 1}, {});
+      ctr(cx, CR(-0.25), I.Lvv, "QaA", false, s1, "Qx", false, C1(), fv1, "aAx");
+      tfree(cx, sQ);
+      tfree(cx, s1);
+      // (ae|cA) pieces in chunks of a
+      const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
+      int64_t na = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
+      na = std::min<int64_t>(na, v);
+      Tensor G = tnew(cx, {na, v, v, v}, false);
+      for (int64_t a0 = 0; a0 < v; a0 += na) {
+        const int64_t a1 = std::min<int64_t>(v, a0 + na);
+        Tensor Gs = tslice(G, 0, 0, a1 - a0);
+        Tensor Ls = tslice(I.Lvv, 1, a0, a1);
+        ctr(cx, C1(), Ls, "Qae", false, I.Lvv, "QcA", false, C0(), Gs, "aecA");
+        Tensor Xs = tslice(X, 1, a0, a1);
+        ctr(cx, CR(-0.5), Gs, "aecA", false, Rr, "Iice", false, C1(), Xs, "iaIA");
+        Tensor fvs = tslice(fv, 0, a0, a1);
+        ctr(cx, CR(0.25), Gs, "aecA", false, rv, "ce", false, C1(), fvs, "aA");
+      }
+      tfree(cx, G);
+    }
+    tfree(cx, Rr);
+    // T10 +1/4 <al||iA> A_Il, A_Il = t*(Ikcd) t(klcd); <al||iA> = -ovov[l,a,i,A]
+    Tensor Ao = tnew(cx, {o, o}, false);
+    ctr(cx, C1(), t, "Ikcd", true, t, "klcd", false, C0(), Ao, "Il");
+    ctr(cx, CR(-0.25), ov4, "laiA", false, Ao, "Il", false, C1(), X, "iaIA");
+    tfree(cx, Ao);
+    // T11 +1/4 <al||Ak> B_Iikl, B = t*(Ikcd) t(ilcd); <al||Ak> = ovov[l,a,k,A]
+    {
+      Tensor Bo = tnew(cx, {o, o, o, o}, false);
+      ctr(cx, C1(), t, "Ikcd", true, t, "ilcd", false, C0(), Bo, "Iikl");
+      ctr(cx, CR(0.25), ov4, "lakA", false, Bo, "Iikl", false, C1(), X, "iaIA");
+      tfree(cx, Bo);
+    }
+    // T12 -t*(Ikcd) <cl||iA> t(klad); <cl||iA> = -ovov[l,c,i,A]
+    {
+      Tensor E = tnew(cx, {o, v, o, v}, false);
+      ctr(cx, C1(), t, "Ikcd", true, t, "klad", false, C0(), E, "Icla");
+      ctr(cx, C1(), ov4, "lciA", false, E, "Icla", false, C1(), X, "iaIA");
+      tfree(cx, E);
+    }
+    // T13 +1/4 <aI||id> F_Ad, F = t*(klAc) t(klcd); <aI||id> = -ovov[I,a,i,d]
+    {
+      Tensor F = tnew(cx, {v, v}, false);
+      ctr(cx, C1(), t, "klAc", true, t, "klcd", false, C0(), F, "Ad");
+      ctr(cx, CR(-0.25), ov4, "Iaid", false, F, "Ad", false, C1(), X, "iaIA");
+      tfree(cx, F);
+    }
+    // T14 +1/4 <Ic||id> G_Acad, G = t*(klAc) t(klad), chunks of A
+    {
+      const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
+      int64_t nA = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
+      nA = std::min<int64_t>(nA, v);
+      Tensor G = tnew(cx, {nA, v, v, v}, false);
+      for (int64_t A0 = 0; A0 < v; A0 += nA) {
+        const int64_t A1 = std::min<int64_t>(v, A0 + nA);
+        Tensor Gs = tslice(G, 0, 0, A1 - A0);
+        Tensor ts_ = tslice(t, 2, A0, A1);
+        ctr(cx, C1(), ts_, "klAc", true, t, "klad", false, C0(), Gs, "Acad");
+        Tensor Xs = tslice(X, 3, A0, A1);
+        ctr(cx, CR(0.25), ov4, "Icid", false, Gs, "Acad", false, C1(), Xs, "iaIA");
+      }
+      tfree(cx, G);
+    }
+    // T15 +1/2 <Im||ik> N_kAma, N = t*(klAc) t(lmac)
+    {
+      Tensor Nn = tnew(cx, {o, v, o, v}, false);
+      ctr(cx, C1(), t, "klAc", true, t, "lmac", false, C0(), Nn, "kAma");
+      ctr(cx, CR(0.5), I.oooo, "Imik", false, Nn, "kAma", false, C1(), X, "iaIA");
+      tfree(cx, Nn);
+    }
+    // T16 -1/4 d_iI t*(klAc) Lt(klac)
+    ctr(cx, CR(-0.25), t, "klAc", true, Lt, "klac", false, C1(), fv, "aA");
+    // T17 -1/2 d_iI t*(klAc) P2(aklc), P2 = -<ma||kd> t(lmcd)
+    {
+      Tensor P = tnew(cx, {v, o, o, v}, false);
+      ctr(cx, CR(-1), ov4, "makd", false, t, "lmcd", false, C0(), P, "aklc");
+      ctr(cx, CR(-0.5), t, "klAc", true, P, "aklc", false, C1(), fv, "aA");
+      tfree(cx, P);
+    }
+    // T19 +1/4 d_iI <am||Ak> ro_km; ro = t*(klcd) t(lmcd); <am||Ak> = ovov[m,a,k,A]
+    Tensor ro = tnew(cx, {o, o}, false);
+    ctr(cx, C1(), t, "klcd", true, t, "lmcd", false, C0(), ro, "km");
+    ctr(cx, CR(0.25), ov4, "makA", false, ro, "km", false, C1(), fv, "aA");
+    // T20 -1/2 d_aA t*(Ikcd) Q(cikd), Q = -<lc||ie> t(klde)
+    {
+      Tensor Q = tnew(cx, {v, o, o, v}, false);
+      ctr(cx, CR(-1), ov4, "lcie", false, t, "klde", false, C0(), Q, "cikd");
+      ctr(cx, CR(-0.5), t, "Ikcd", true, Q, "cikd", false, C1(), fo, "iI");
+      tfree(cx, Q);
+    }
+    // T21 -1/4 d_aA t*(Ikcd) Ht(ikcd)
+    ctr(cx, CR(-0.25), t, "Ikcd", true, Ht, "ikcd", false, C1(), fo, "iI");
+    // T22 +1/4 d_aA <Ic||ie> rv_ce
+    ctr(cx, CR(0.25), ov4, "Icie", false, rv, "ce", false, C1(), fo, "iI");
+    // T23 -1/4 d_aA <Im||ik> ro_km
+    ctr(cx, CR(-0.25), I.oooo, "Imik", false, ro, "km", false, C1(), fo, "iI");
+    tfree(cx, rv);
+    tfree(cx, ro);
+  }
+  launch_m11_add_delta(X.p, fv.p, o, v, 0, cx.stream);
+  launch_m11_add_delta(X.p, fo.p, o, v, 1, cx.stream);
+  Tensor MB = tnew(cx, {n1, n1}, false);
+  launch_herm_add(X.p, MB.p, n1, cx.stream);
+  I.M11x = tnew(cx, {n1, n1}, false);
+  perm(cx, C1(), MA, "pq", false, C0(), I.M11x, "pq");
+  perm(cx, CR(I.x), MB, "pq", false, C1(), I.M11x, "pq");
+  for (Tensor* p : {&X2, &MA, &X, &MB, &fv, &fo, &Lt, &Ht, &t2, &ts}) tfree(cx, *p);
+
+  // ---- coupling intermediate W_IJiB = sum_cd t*_IJcd <cd||iB>,  <cd||iB> = conj(ovvv[i,B,c,d])
+  I.W = tnew(cx, {o, o, o, v}, false);
+  ctr(cx, C1(), t, "IJcd", true, I.ovvv, "iBcd", true, C0(), I.W, "IJiB");
+}
+
+void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v;
+  const int64_t n1 = I.n1, dim = I.dim, Po = I.Po;
+  const double x = I.x;
+  const int saved = cx.prec;
+  cx.prec = prec;
+  Tensor ys = tnew(cx, {k, o, v}, false);
+  rows_in(cx, Y, dim, 0, ys, k, n1);
+  Tensor Ya = tnew(cx, {k, o, o, v, v}, false);
+  launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream);
+  const Tensor& t = I.t1;
+
+  // ---------------- singles output
+  Tensor s1 = tnew(cx, {k, o, v}, false);
+  {
+    // M11 stays FP64
+    cx.prec = 0;
+    Tensor M = tensor_view(I.M11x.p, {n1, n1}, {});
+    Tensor ysf = tensor_view(ys.p, {k, n1}, {});
+    Tensor s1f = tensor_view(s1.p, {k, n1}, {});
+    ctr(cx, C1(), M, "PQ", false, ysf, "zQ", false, C0(), s1f, "zP");
+    cx.prec = prec;
+  }
+  // M12(1): -1/2 <ja||bc>Y_ijbc - 1/2 <jk||ib> Y_jkab
+  ctr(cx, CR(-0.5), I.ovvv, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
+  ctr(cx, CR(-0.5), I.ooov, "jkib", false, Ya, "zjkab", false, C1(), s1, "zia");
+  if (x != 0.0) {
+    // M12(2), grouped with the antisymmetric Y
+    Tensor rY = tnew(cx, {k, v, v}, false);
+    ctr(cx, C1(), t, "IJAc", true, Ya, "zIJAB", false, C0(), rY, "zcB");
+    ctr(cx, CR(0.5 * x), I.ovvv, "iBac", true, rY, "zcB", false, C1(), s1, "zia");
+    tfree(cx, rY);
+    Tensor r2 = tnew(cx, {k, o, o}, false);
+    ctr(cx, C1(), t, "IkAB", true, Ya, "zIJAB", false, C0(), r2, "zkJ");
+    ctr(cx, CR(0.5 * x), I.ooov, "ikJa", true, r2, "zkJ", false, C1(), s1, "zia");
+    tfree(cx, r2);
+    Tensor Vv = tnew(cx, {k, o, o, v, v}, false);
+    ctr(cx, C1(), t, "JkAc", true, Ya, "ziJAB", false, C0(), Vv, "zikcB");
+    ctr(cx, CR(x), I.ovvv, "kBac", true, Vv, "zikcB", false, C1(), s1, "zia");
+    tfree(cx, Vv);
+    Tensor V2 = tnew(cx, {k, o, o, o, o}, false);
+    ctr(cx, C1(), t, "klAB", true, Ya, "ziJAB", false, C0(), V2, "ziJkl");
+    ctr(cx, CR(-0.25 * x), I.ooov, "klJa", true, V2, "ziJkl", false, C1(), s1, "zia");
+    tfree(cx, V2);
+    ctr(cx, CR(-0.25 * x), I.W, "IJiB", false, Ya, "zIJaB", false, C1(), s1, "zia");
+    Tensor V4 = tnew(cx, {k, o, v, o, v}, false);
+    ctr(cx, C1(), t, "IkBc", true, Ya, "zIJaB", false, C0(), V4, "zkcJa");
+    ctr(cx, CR(x), I.ooov, "ikJc", true, V4, "zkcJa", false, C1(), s1, "zia");
+    tfree(cx, V4);
+  }
+  // ---------------- doubles output (unpacked)
+  Tensor s2 = tnew(cx, {k, o, o, v, v});
+  {
+    Tensor T = tnew(cx, {k, o, o, v, v}, false);
+    // M21(1): (Tv - Tv^ij) + (To - To^ab)
+    ctr(cx, C1(), I.ovvv, "icab", true, ys, "zjc", false, C0(), T, "zijab");
+    launch_antisym_add(T.p, s2.p, k, o, o, v, v, 0, C1(), cx.stream);
+    ctr(cx, C1(), I.ooov, "ijka", true, ys, "zkb", false, C0(), T, "zijab");
+    launch_antisym_add(T.p, s2.p, k, o, o, v, v, 1, C1(), cx.stream);
+    if (x != 0.0) {
+      // M21(2)
+      Tensor Z1 = tnew(cx, {k, v, v}, false);
+      ctr(cx, C1(), I.ovvv, "iBac", false, ys, "zia", false, C0(), Z1, "zBc");
+      ctr(cx, C1(), t, "IJAc", false, Z1, "zBc", false, C0(), T, "zIJAB");
+      ctr(cx, CR(-0.5), I.W, "IJiB", true, ys, "ziA", false, C1(), T, "zIJAB");
+      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 1, CR(x), cx.stream);
+      tfree(cx, Z1);
+      Tensor Z2 = tnew(cx, {k, o, o}, false);
+      ctr(cx, C1(), I.ooov, "ikJa", false, ys, "zia", false, C0(), Z2, "zkJ");
+      ctr(cx, C1(), t, "IkAB", false, Z2, "zkJ", false, C0(), T, "zIJAB");
+      tfree(cx, Z2);
+      Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
+      ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
+      ctr(cx, CR(-0.5), t, "klAB", false, Z4, "zklJI", false, C1(), T, "zIJAB");
+      tfree(cx, Z4);
+      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 0, CR(x), cx.stream);
+      Tensor Z3 = tnew(cx, {k, o, v, v, o}, false);
+      ctr(cx, C1(), I.ovvv, "kBac", false, ys, "zIa", false, C0(), Z3, "zkBcI");
+      ctr(cx, C1(), t, "JkAc", false, Z3, "zkBcI", false, C0(), T, "zIJAB");
+      tfree(cx, Z3);
+      Tensor Z5 = tnew(cx, {k, o, o, v, v}, false);
+      ctr(cx, C1(), I.ooov, "ikJc", false, ys, "ziA", false, C0(), Z5, "zkJcA");
+      ctr(cx, C1(), t, "IkBc", false, Z5, "zkJcA", false, C1(), T, "zIJAB");
+      tfree(cx, Z5);
+      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 2, CR(x), cx.stream);
+      // M22(1): hole ladder and ring (the particle ladder runs packed below)
+      ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), s2, "zijab");
+      Tensor R = tnew(cx, {k, o, v, o, v}, false);
+      ctr(cx, C1(), Ya, "zikac", false, I.ring, "kcjb", false, C0(), R, "ziajb");
+      perm(cx, C1(), R, "ziajb", false, C0(), T, "zijab");
+      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 2, CR(-x), cx.stream);
+      tfree(cx, R);
+    }
+    tfree(cx, T);
+  }
+  // pack doubles: S2 = extract(s2) + D o Y2
+  launch_pack_doubles(0, s2.p, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+  if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, Po, k, CR(x), prec);
+  rows_out(cx, s1, S, dim, 0, k, n1, C0());
+  for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
+  cx.prec = saved;
+}
+
+// ============================================================================
+// validation (host only)
+// ============================================================================
+int validate(const adc_problem* p) {
+  if (!p) return ADC_ERR_INVALID_ARG;
+  if (p->kind < 0 || p->kind > 2) return ADC_ERR_INVALID_ARG;
+  if (p->n_occ < 1 || p->n_vir < 2 || p->n_chol < 1 || p->n_roots < 1) return ADC_ERR_INVALID_ARG;
+  if (!p->eps || !p->L) return ADC_ERR_INVALID_ARG;
+  if (!std::isfinite(p->x)) return ADC_ERR_NONFINITE_INPUT;
+  const int n = p->n_occ + p->n_vir;
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(p->eps[i])) return ADC_ERR_NONFINITE_INPUT;
+  return ADC_OK;
+}
+
+int validate_L_host(const double* L, int N, int n) {
+  for (int q = 0; q < N; ++q) {
+    const double* Lq = L + (int64_t)q * n * n * 2;
+    double mx = 0.0, dev = 0.0;
+    for (int64_t i = 0; i < (int64_t)n * n * 2; ++i) {
+      if (!std::isfinite(Lq[i])) return ADC_ERR_NONFINITE_INPUT;
+      mx = std::max(mx, std::fabs(Lq[i]));
+    }
+    for (int p = 0; p < n; ++p)
+      for (int r = 0; r < n; ++r) {
+        const double* a = Lq + ((int64_t)p * n + r) * 2;
+        const double* b = Lq + ((int64_t)r * n + p) * 2;
+        dev = std::max(dev, std::fabs(a[0] - b[0]) + std::fabs(a[1] + b[1]));
+      }
+    if (dev > 1e-12 * mx) return ADC_ERR_NOT_HERMITIAN;
+  }
+  return ADC_OK;
+}
+
+int dims_of(int kind, int64_t o, int64_t v, int64_t* n1, int64_t* n2) {
+  const int64_t Po = npair(o), Pv = npair(v);
+  if (kind == ADC_EE) { *n1 = o * v; *n2 = Po * Pv; }
+  else if (kind == ADC_IP) { *n1 = o; *n2 = Po * v; }
+  else { *n1 = v; *n2 = o * Pv; }
+  return 0;
+}
+
+void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
+  Ctx& cx = h->cx;
+  I.kind = p->kind;
+  I.o = p->n_occ;
+  I.v = p->n_vir;
+  I.N = p->n_chol;
+  I.k = p->n_roots;
+  I.x = p->x;
+  I.Po = npair(I.o);
+  I.Pv = npair(I.v);
+  dims_of(I.kind, I.o, I.v, &I.n1, &I.n2);
+  I.dim = I.n1 + I.n2;
+  const int o = I.o, v = I.v, n = o + v, N = I.N;
+  I.eps = (double*)dmalloc(h, sizeof(double) * n);
+  hipcheck(hipMemcpy(I.eps, p->eps, sizeof(double) * n, hipMemcpyHostToDevice), "eps");
+  {
+    auto po = pair_table(o), pv = pair_table(v);
+    I.pair_o = (int2*)dmalloc(h, sizeof(int2) * std::max<size_t>(1, po.size()));
+    I.pair_v = (int2*)dmalloc(h, sizeof(int2) * std::max<size_t>(1, pv.size()));
+    if (!po.empty()) hipcheck(hipMemcpy(I.pair_o, po.data(), sizeof(int2) * po.size(), hipMemcpyHostToDevice), "po");
+    if (!pv.empty()) hipcheck(hipMemcpy(I.pair_v, pv.data(), sizeof(int2) * pv.size(), hipMemcpyHostToDevice), "pv");
+  }
+  // L on the device (borrowed or copied), then the class blocks [Q][.][.]
+  double2* Ld = nullptr;
+  Tensor Lown;
+  if (p->L_on_device) {
+    Ld = (double2*)p->L;
+  } else {
+    Lown = tnew(cx, {N, n, n}, false);
+    hipcheck(hipMemcpyAsync(Lown.p, p->L, sizeof(double2) * (size_t)N * n * n, hipMemcpyHostToDevice, cx.stream),
+             "L");
+    Ld = Lown.p;
+  }
+  Tensor Lfull = tensor_view(Ld, {N, n, n}, {});
+  auto block = [&](int r0, int nr, int c0, int nc) {
+    Tensor dst = tnew(cx, {N, nr, nc}, false);
+    Tensor src = tensor_view(Ld + (int64_t)r0 * n + c0, {N, nr, nc}, {(int64_t)n * n, n, 1});
+    perm(cx, C1(), src, "Qpq", false, C0(), dst, "Qpq");
+    return dst;
+  };
+  I.Loo = block(0, o, 0, o);
+  I.Lov = block(0, o, o, v);
+  I.Lvo = block(o, v, 0, o);
+  I.Lvv = block(o, v, o, v);
+  if (Lown.p) tfree(cx, Lown);
+  // zeroth-order diagonal of the packed basis
+  {
+    std::vector<double> d(I.dim);
+    const double* e = p->eps;
+    if (I.kind == ADC_EE) {
+      for (int i = 0; i < o; ++i)
+        for (int a = 0; a < v; ++a) d[(int64_t)i * v + a] = e[o + a] - e[i];
+      int64_t q = I.n1;
+      for (int i = 0; i < o; ++i)
+        for (int j = i + 1; j < o; ++j)
+          for (int a = 0; a < v; ++a)
+            for (int b = a + 1; b < v; ++b) d[q++] = e[o + a] + e[o + b] - e[i] - e[j];
+    } else if (I.kind == ADC_IP) {
+      for (int i = 0; i < o; ++i) d[i] = -e[i];
+      int64_t q = I.n1;
+      for (int i = 0; i < o; ++i)
+        for (int j = i + 1; j < o; ++j)
+          for (int a = 0; a < v; ++a) d[q++] = e[o + a] - e[i] - e[j];
+    } else {
+      for (int a = 0; a < v; ++a) d[a] = e[o + a];
+      int64_t q = I.n1;
+      for (int i = 0; i < o; ++i)
+        for (int a = 0; a < v; ++a)
+          for (int b = a + 1; b < v; ++b) d[q++] = e[o + a] + e[o + b] - e[i];
+    }
+    I.diag = (double*)dmalloc(h, sizeof(double) * I.dim);
+    hipcheck(hipMemcpy(I.diag, d.data(), sizeof(double) * I.dim, hipMemcpyHostToDevice), "diag");
+  }
+  if (I.kind == ADC_EE) ee_init(h, I);
+  else throw Status{ADC_ERR_UNSUPPORTED, "IP/EA not built yet"};
+  // host copy of diag(M11x) for the Davidson guesses
+  {
+    std::vector<double2> m(I.n1 * I.n1);
+    hipcheck(hipStreamSynchronize(cx.stream), "sync");
+    hipcheck(hipMemcpy(m.data(), I.M11x.p, sizeof(double2) * m.size(), hipMemcpyDeviceToHost), "m11");
+    I.m11diag.resize(I.n1);
+    for (int64_t i = 0; i < I.n1; ++i) I.m11diag[i] = m[i * I.n1 + i].x;
+  }
+}
+
+// ============================================================================
+// small Hermitian eigensolver (cyclic complex Jacobi), host
+// ============================================================================
+void heevj(int n, std::vector<zc>& A, std::vector<double>& w, std::vector<zc>& V) {
+  V.assign((size_t)n * n, zc(0, 0));
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> zc& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double m = std::norm(a(i, j));
+        tot += m;
+        if (i != j) off += m;
+      }
+    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const zc apq = a(p, q);
+        const double mag = std::abs(apq);
+        if (mag < 1e-300) continue;
+        const zc ph = apq / mag;  // a_pq = |a_pq| e^{i phi}
+        const double app = a(p, p).real(), aqq = a(q, q).real();
+        const double theta = 0.5 * std::atan2(2.0 * mag, aqq - app);
+        const double c = std::cos(theta), s = std::sin(theta);
+        // columns: new_p = c*col_p - s*conj(ph)*col_q ; new_q = s*ph*col_p + c*col_q
+        for (int i = 0; i < n; ++i) {
+          const zc xp = a(i, p), xq = a(i, q);
+          a(i, p) = c * xp - s * std::conj(ph) * xq;
+          a(i, q) = s * ph * xp + c * xq;
+        }
+        for (int j = 0; j < n; ++j) {
+          const zc xp = a(p, j), xq = a(q, j);
+          a(p, j) = c * xp - s * ph * xq;
+          a(q, j) = s * std::conj(ph) * xp + c * xq;
+        }
+        for (int i = 0; i < n; ++i) {
+          const zc xp = V[(size_t)i * n + p], xq = V[(size_t)i * n + q];
+          V[(size_t)i * n + p] = c * xp - s * std::conj(ph) * xq;
+          V[(size_t)i * n + q] = s * ph * xp + c * xq;
+        }
+        a(p, q) = 0.0;
+        a(q, p) = 0.0;
+      }
+  }
+  // sort ascending
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int x, int y) { return a(x, x).real() < a(y, y).real(); });
+  w.resize(n);
+  std::vector<zc> V2((size_t)n * n);
+  for (int c = 0; c < n; ++c) {
+    w[c] = a(idx[c], idx[c]).real();
+    for (int r = 0; r < n; ++r) V2[(size_t)r * n + c] = V[(size_t)r * n + idx[c]];
+  }
+  V.swap(V2);
+}
+
+// ============================================================================
+// Davidson on device vectors
+// ============================================================================
+void sigma_dispatch(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
+  if (k <= 0) return;
+  if (I.kind == ADC_EE) ee_sigma(h, I, Y, S, k, prec);
+  else throw Status{ADC_ERR_UNSUPPORTED, "kind"};
+}
+
+// G[a][b] = sum_i conj(X[a][i]) Y[b][i]  (ra x rb, host result)
+std::vector<zc> gram(adc_handle* h, const double2* X, int ra, const double2* Y, int rb, int64_t dim) {
+  Ctx& cx = h->cx;
+  std::vector<zc> G((size_t)ra * rb, zc(0, 0));
+  if (ra == 0 || rb == 0) return G;
+  const int64_t chunk = 1 << 16;
+  const int64_t nsplit = dim / chunk;
+  const int64_t rem = dim - nsplit * chunk;
+  const int64_t nparts = nsplit + (rem ? 1 : 0);
+  double2* part = cx.pool.get(nparts * ra * rb);
+  if (nsplit) {
+    GemmDesc g{};
+    g.M = ra; g.N = rb; g.K = chunk; g.batch = nsplit;
+    g.A = X; g.sam = dim; g.sak = 1; g.sab = chunk; g.conjA = 1;
+    g.B = Y; g.sbk = 1; g.sbn = dim; g.sbb = chunk;
+    g.C = part; g.scm = rb; g.scn = 1; g.scb = (int64_t)ra * rb;
+    g.alpha = C1(); g.beta = C0();
+    launch_zgemm(g, 0, cx.stream);
+  }
+  if (rem) {
+    GemmDesc g{};
+    g.M = ra; g.N = rb; g.K = rem; g.batch = 1;
+    g.A = X + nsplit * chunk; g.sam = dim; g.sak = 1; g.sab = 0; g.conjA = 1;
+    g.B = Y + nsplit * chunk; g.sbk = 1; g.sbn = dim; g.sbb = 0;
+    g.C = part + nsplit * ra * rb; g.scm = rb; g.scn = 1; g.scb = 0;
+    g.alpha = C1(); g.beta = C0();
+    launch_zgemm(g, 0, cx.stream);
+  }
+  std::vector<double2> hp((size_t)nparts * ra * rb);
+  hipcheck(hipMemcpyAsync(hp.data(), part, sizeof(double2) * hp.size(), hipMemcpyDeviceToHost, cx.stream), "gram");
+  hipcheck(hipStreamSynchronize(cx.stream), "gram sync");
+  cx.pool.put(part);
+  for (int64_t s = 0; s < nparts; ++s)
+    for (int64_t e = 0; e < (int64_t)ra * rb; ++e) G[e] += zc(hp[s * ra * rb + e].x, hp[s * ra * rb + e].y);
+  return G;
+}
+
+// Out[r][i] = sum_a C[a][r] In[a][i]  (C is m x r host matrix), beta accumulate
+void combine(adc_handle* h, const std::vector<zc>& Cm, int m, int r, const double2* In, double2* Out, int64_t dim,
+             cplx alpha, cplx beta) {
+  Ctx& cx = h->cx;
+  if (m == 0 || r == 0) return;
+  double2* c = cx.pool.get((int64_t)m * r);
+  std::vector<double2> hc((size_t)m * r);
+  for (size_t i = 0; i < hc.size(); ++i) hc[i] = make_double2(Cm[i].real(), Cm[i].imag());
+  hipcheck(hipMemcpyAsync(c, hc.data(), sizeof(double2) * hc.size(), hipMemcpyHostToDevice, cx.stream), "comb");
+  GemmDesc g{};
+  g.M = r; g.N = dim; g.K = m; g.batch = 1;
+  g.A = c; g.sam = 1; g.sak = r; g.sab = 0;        // A(r', a) = C[a][r']
+  g.B = In; g.sbk = dim; g.sbn = 1; g.sbb = 0;
+  g.C = Out; g.scm = dim; g.scn = 1; g.scb = 0;
+  g.alpha = alpha; g.beta = beta;
+  launch_zgemm(g, 0, cx.stream);
+  hipcheck(hipStreamSynchronize(cx.stream), "comb sync");
+  cx.pool.put(c);
+}
+
+// orthonormalise rows of N (nn x dim) against V (m x dim) and among themselves;
+// returns the number of kept rows (compacted to the front of N)
+int orthonormalize(adc_handle* h, double2* V, int m, double2* N, int nn, int64_t dim) {
+  Ctx& cx = h->cx;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (m > 0) {
+      auto C = gram(h, V, m, N, nn, dim);  // m x nn
+      combine(h, C, m, nn, V, N, dim, CR(-1), C1());
+    }
+    auto G = gram(h, N, nn, N, nn, dim);
+    std::vector<double> w;
+    std::vector<zc> U;
+    heevj(nn, G, w, U);
+    const double wmax = w.empty() ? 0.0 : w.back();
+    std::vector<int> keep;
+    for (int j = 0; j < nn; ++j)
+      if (w[j] > 1e-12 * std::max(wmax, 1e-300) && w[j] > 1e-20) keep.push_back(j);
+    // new rows r = sum_a U[a][j]/sqrt(w_j) N[a]
+    const int nk = (int)keep.size();
+    // G = U diag(w) U^H with G[a][b] = <N_a|N_b>: q_j = sum_a U[a][j] N_a / sqrt(w_j)
+    std::vector<zc> Cm((size_t)nn * nk);
+    for (int a = 0; a < nn; ++a)
+      for (int c = 0; c < nk; ++c) Cm[(size_t)a * nk + c] = U[(size_t)a * nn + keep[c]] / std::sqrt(w[keep[c]]);
+    double2* tmp = cx.pool.get((int64_t)std::max(1, nk) * dim);
+    combine(h, Cm, nn, nk, N, tmp, dim, C1(), C0());
+    if (nk) hipcheck(hipMemcpyAsync(N, tmp, sizeof(double2) * nk * dim, hipMemcpyDeviceToDevice, cx.stream), "on");
+    hipcheck(hipStreamSynchronize(cx.stream), "on sync");
+    cx.pool.put(tmp);
+    nn = nk;
+    if (nn == 0) break;
+  }
+  return nn;
+}
+
+std::vector<double> row_norms2(adc_handle* h, const double2* X, int rows, int64_t dim) {
+  Ctx& cx = h->cx;
+  const int nb = row_dot_blocks(dim);
+  double2* part = cx.pool.get((int64_t)rows * nb);
+  launch_row_dots(X, dim, X, dim, rows, dim, part, nb, cx.stream);
+  std::vector<double2> hp((size_t)rows * nb);
+  hipcheck(hipMemcpyAsync(hp.data(), part, sizeof(double2) * hp.size(), hipMemcpyDeviceToHost, cx.stream), "rn");
+  hipcheck(hipStreamSynchronize(cx.stream), "rn sync");
+  cx.pool.put(part);
+  std::vector<double> out(rows, 0.0);
+  for (int r = 0; r < rows; ++r)
+    for (int b = 0; b < nb; ++b) out[r] += hp[(size_t)r * nb + b].x;
+  return out;
+}
+
+int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, double2* vecs, double* resnorm,
+                 int* iters, int* conv_out) {
+  Ctx& cx = h->cx;
+  const int k = I.k;
+  const int64_t dim = I.dim;
+  const double tol = h->opt.conv_tol > 0 ? h->opt.conv_tol : 1e-7;
+  const int max_iter = h->opt.max_iter > 0 ? h->opt.max_iter : 200;
+  int mmax = h->opt.max_subspace > 0 ? h->opt.max_subspace : 6 * k;
+  mmax = std::max(mmax, 2 * k + 1);
+  if ((int64_t)mmax > dim) mmax = (int)dim;
+  if (k > dim) throw Status{ADC_ERR_INVALID_ARG, "n_roots > dim"};
+  const int prec_mixed = h->opt.precision;
+  int prec = prec_mixed;
+  const double tol_mixed = 1e-4;
+  double2* V = cx.pool.get((int64_t)mmax * dim);
+  double2* S = cx.pool.get((int64_t)mmax * dim);
+  double2* X = cx.pool.get((int64_t)k * dim);
+  double2* AX = cx.pool.get((int64_t)k * dim);
+  double2* R = cx.pool.get((int64_t)k * dim);
+  double* wd = (double*)cx.pool.get(k);
+  int m = 0;
+  // initial vectors
+  if (guess) {
+    hipcheck(hipMemcpyAsync(V, guess, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "guess");
+    m = orthonormalize(h, V, 0, V, k, dim);
+  } else {
+    std::vector<int> idx(I.n1);
+    for (int i = 0; i < (int)I.n1; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return I.m11diag[a] < I.m11diag[b]; });
+    launch_fill(V, (int64_t)k * dim, C0(), cx.stream);
+    const int ng = (int)std::min<int64_t>(k, I.n1);
+    for (int r = 0; r < ng; ++r) {
+      double2 one = make_double2(1.0, 0.0);
+      hipcheck(hipMemcpyAsync(V + (int64_t)r * dim + idx[r], &one, sizeof(double2), hipMemcpyHostToDevice, cx.stream),
+               "unit");
+      hipcheck(hipStreamSynchronize(cx.stream), "unit sync");
+    }
+    // more roots than singles: seed with the lowest doubles diagonal
+    if (ng < k) {
+      std::vector<double> dd(dim);
+      hipcheck(hipMemcpy(dd.data(), I.diag, sizeof(double) * dim, hipMemcpyDeviceToHost), "dd");
+      std::vector<int64_t> id2(dim - I.n1);
+      for (int64_t i = 0; i < (int64_t)id2.size(); ++i) id2[i] = I.n1 + i;
+      std::stable_sort(id2.begin(), id2.end(), [&](int64_t a, int64_t b) { return dd[a] < dd[b]; });
+      for (int r = ng; r < k; ++r) {
+        double2 one = make_double2(1.0, 0.0);
+        hipcheck(hipMemcpy(V + (int64_t)r * dim + id2[r - ng], &one, sizeof(double2), hipMemcpyHostToDevice), "unit2");
+      }
+    }
+    m = k;
+  }
+  sigma_dispatch(h, I, V, S, m, prec);
+  std::vector<double> w_old(k, 1e300), w(k), rn(k);
+  std::vector<int> conv(k, 0);
+  int it = 0;
+  bool refined_phase = (prec == 0);
+  for (it = 1; it <= max_iter; ++it) {
+    auto G = gram(h, V, m, S, m, dim);
+    for (int a = 0; a < m; ++a)
+      for (int b = a; b < m; ++b) {
+        const zc x = 0.5 * (G[(size_t)a * m + b] + std::conj(G[(size_t)b * m + a]));
+        G[(size_t)a * m + b] = x;
+        G[(size_t)b * m + a] = std::conj(x);
+      }
+    std::vector<double> wall;
+    std::vector<zc> U;
+    heevj(m, G, wall, U);
+    std::vector<zc> Uk((size_t)m * k);
+    for (int a = 0; a < m; ++a)
+      for (int r = 0; r < k; ++r) Uk[(size_t)a * k + r] = U[(size_t)a * m + r];
+    combine(h, Uk, m, k, V, X, dim, C1(), C0());
+    combine(h, Uk, m, k, S, AX, dim, C1(), C0());
+    for (int r = 0; r < k; ++r) w[r] = wall[r];
+    hipcheck(hipMemcpyAsync(wd, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, cx.stream), "w");
+    launch_resid(AX, X, wd, R, k, dim, cx.stream);
+    auto r2 = row_norms2(h, R, k, dim);
+    bool all = true;
+    const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
+    for (int r = 0; r < k; ++r) {
+      rn[r] = std::sqrt(std::max(0.0, r2[r]));
+      conv[r] = (rn[r] <= tol_now && std::fabs(w[r] - w_old[r]) <= (refined_phase ? 1e-10 : 1e-7)) ? 1 : 0;
+      all = all && conv[r];
+    }
+    if (h->opt.verbose) {
+      std::fprintf(stderr, "[adc] it %3d m %3d prec %d", it, m, prec);
+      for (int r = 0; r < k; ++r) std::fprintf(stderr, "  %.10f (%.1e)", w[r], rn[r]);
+      std::fprintf(stderr, "\n");
+    }
+    w_old = w;
+    if (all) {
+      if (refined_phase) break;
+      // mixed precision converged: restart from the Ritz vectors in FP64
+      refined_phase = true;
+      prec = 0;
+      hipcheck(hipMemcpyAsync(V, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "restart");
+      m = orthonormalize(h, V, 0, V, k, dim);
+      sigma_dispatch(h, I, V, S, m, prec);
+      std::fill(w_old.begin(), w_old.end(), 1e300);
+      continue;
+    }
+    // new directions
+    std::vector<int> un;
+    for (int r = 0; r < k; ++r)
+      if (!conv[r]) un.push_back(r);
+    const int nn = (int)un.size();
+    double2* Nd = cx.pool.get((int64_t)nn * dim);
+    double* wn = (double*)cx.pool.get(nn);
+    std::vector<double> wv(nn);
+    for (int j = 0; j < nn; ++j) {
+      wv[j] = w[un[j]];
+      hipcheck(hipMemcpyAsync(Nd + (int64_t)j * dim, R + (int64_t)un[j] * dim, sizeof(double2) * dim,
+                              hipMemcpyDeviceToDevice, cx.stream), "N");
+    }
+    hipcheck(hipMemcpyAsync(wn, wv.data(), sizeof(double) * nn, hipMemcpyHostToDevice, cx.stream), "wn");
+    launch_precondition(Nd, Nd, I.diag, wn, nn, dim, cx.stream);
+    if (m + nn > mmax) {
+      // collapse onto the 2k lowest Ritz vectors of the current subspace
+      const int mc = std::min(2 * k, m);
+      std::vector<zc> Uc((size_t)m * mc);
+      for (int a = 0; a < m; ++a)
+        for (int r = 0; r < mc; ++r) Uc[(size_t)a * mc + r] = U[(size_t)a * m + r];
+      double2* T = cx.pool.get((int64_t)mc * dim);
+      combine(h, Uc, m, mc, V, T, dim, C1(), C0());
+      hipcheck(hipMemcpyAsync(V, T, sizeof(double2) * mc * dim, hipMemcpyDeviceToDevice, cx.stream), "col");
+      combine(h, Uc, m, mc, S, T, dim, C1(), C0());
+      hipcheck(hipMemcpyAsync(S, T, sizeof(double2) * mc * dim, hipMemcpyDeviceToDevice, cx.stream), "col");
+      hipcheck(hipStreamSynchronize(cx.stream), "col sync");
+      cx.pool.put(T);
+      m = mc;
+    }
+    const int nk = orthonormalize(h, V, m, Nd, nn, dim);
+    if (nk > 0) {
+      hipcheck(hipMemcpyAsync(V + (int64_t)m * dim, Nd, sizeof(double2) * nk * dim, hipMemcpyDeviceToDevice,
+                              cx.stream), "app");
+      sigma_dispatch(h, I, V + (int64_t)m * dim, S + (int64_t)m * dim, nk, prec);
+      m += nk;
+    }
+    cx.pool.put(Nd);
+    cx.pool.put((double2*)wn);
+    if (nk == 0) break;
+  }
+  for (int r = 0; r < k; ++r) {
+    omega[r] = w[r];
+    resnorm[r] = rn[r];
+    conv_out[r] = conv[r];
+  }
+  *iters = std::min(it, max_iter);
+  if (vecs) hipcheck(hipMemcpyAsync(vecs, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "vecs");
+  hipcheck(hipStreamSynchronize(cx.stream), "dav end");
+  for (double2* p : {V, S, X, AX, R}) cx.pool.put(p);
+  cx.pool.put((double2*)wd);
+  for (int r = 0; r < k; ++r)
+    if (!conv[r]) return ADC_NOT_CONVERGED;
+  return ADC_OK;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Status& s) {
+    return s.code;
+  } catch (const HipError& e) {
+    (void)hipGetLastError();
+    return e.e == hipErrorOutOfMemory ? ADC_ERR_OUT_OF_MEMORY : ADC_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    return ADC_ERR_OUT_OF_MEMORY;
+  } catch (const std::invalid_argument&) {
+    return ADC_ERR_INVALID_ARG;
+  } catch (...) {
+    return ADC_ERR_HIP;
+  }
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+int adc_init(const adc_problem* problems, int n_problems, const adc_options* opts, adc_handle** out) {
+  if (!out) return ADC_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!problems || n_problems != 1) return ADC_ERR_INVALID_ARG;
+  int rc = validate(&problems[0]);
+  if (rc) return rc;
+  const adc_problem& p = problems[0];
+  if (opts && (opts->precision < 0 || opts->precision > 2)) return ADC_ERR_INVALID_ARG;
+  if (!p.L_on_device) {
+    rc = validate_L_host((const double*)p.L, p.n_chol, p.n_occ + p.n_vir);
+    if (rc) return rc;
+  }
+  adc_handle* h = nullptr;
+  rc = guarded([&]() {
+    h = new adc_handle();
+    if (opts) h->opt = *opts;
+    if (h->opt.stream) {
+      h->cx.stream = (hipStream_t)h->opt.stream;
+    } else {
+      hipcheck(hipStreamCreate(&h->cx.stream), "stream");
+      h->own_stream = true;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    h->inst.resize(1);
+    inst_init(h, &p, h->inst[0]);
+    hipcheck(hipStreamSynchronize(h->cx.stream), "init sync");
+    h->init_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return ADC_OK;
+  });
+  if (rc != ADC_OK) {
+    adc_free(h);
+    return rc;
+  }
+  *out = h;
+  return ADC_OK;
+}
+
+int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2) {
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !n1 || !n2) return ADC_ERR_INVALID_ARG;
+  *n1 = h->inst[inst].n1;
+  *n2 = h->inst[inst].n2;
+  return ADC_OK;
+}
+
+int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precision) {
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
+  if (precision > 2) return ADC_ERR_INVALID_ARG;
+  const int prec = precision < 0 ? h->opt.precision : precision;
+  return guarded([&]() {
+    sigma_dispatch(h, h->inst[inst], (const double2*)Y, (double2*)S, k, prec);
+    hipcheck(hipGetLastError(), "sigma launch");
+    return ADC_OK;
+  });
+}
+
+int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs, double* resnorm,
+                 int* iters, int* converged) {
+  if (!h || !omega || !resnorm || !iters || !converged) return ADC_ERR_INVALID_ARG;
+  return guarded([&]() {
+    Inst& I = h->inst[0];
+    const double2* g = guess ? (const double2*)guess[0] : nullptr;
+    double2* vv = vecs ? (double2*)vecs[0] : nullptr;
+    return davidson_one(h, I, g, omega, vv, resnorm, iters, converged);
+  });
+}
+
+int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k, void* dL, double* dx) {
+  (void)h; (void)inst; (void)Sbar; (void)Y; (void)k; (void)dL; (void)dx;
+  return ADC_ERR_UNSUPPORTED;
+}
+
+double adc_init_ms(const adc_handle* h) { return h ? h->init_ms : 0.0; }
+
+void adc_free(adc_handle* h) {
+  if (!h) return;
+  if (h->cx.stream) (void)hipStreamSynchronize(h->cx.stream);
+  h->cx.pool.release_all();
+  for (void* p : h->raw) (void)hipFree(p);
+  if (h->own_stream && h->cx.stream) (void)hipStreamDestroy(h->cx.stream);
+  delete h;
+}
+
+const char* adc_strerror(int code) {
+  switch (code) {
+    case ADC_OK: return "ok";
+    case ADC_NOT_CONVERGED: return "Davidson did not converge for every root (outputs filled)";
+    case ADC_ERR_INVALID_ARG: return "invalid argument";
+    case ADC_ERR_NONFINITE_INPUT: return "non-finite value in eps, L or x";
+    case ADC_ERR_NOT_HERMITIAN: return "a Cholesky vector L^Q is not Hermitian in (p,q)";
+    case ADC_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case ADC_ERR_HIP: return "HIP runtime error";
+    case ADC_ERR_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

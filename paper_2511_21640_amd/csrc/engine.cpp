@@ -1,0 +1,294 @@
+// Binary tensor contractions on the device.
+//
+// ctr() maps C[lc] = alpha * sum A[la] B[lb] + beta C[lc] onto one batched
+// complex GEMM: labels shared by A, B and C are batch dimensions, labels of A
+// and C are M, of B and C are N, of A and B are K.  An operand is used in
+// place when each of its label groups is contiguous and in the canonical
+// order (then every group collapses to a single stride); otherwise it is first
+// permuted into [batch][M][K] / [batch][N][K] (K contiguous) by the permute
+// kernel.  The product goes straight into C when C is [batch][M][N] or
+// [batch][N][M], and through a temporary plus a permute otherwise.
+#include <algorithm>
+#include <cstring>
+#include <cstdio>
+#include <map>
+#include <stdexcept>
+
+#include "internal.h"
+
+namespace adc {
+
+// ------------------------------------------------------------------ pool
+Pool::~Pool() { release_all(); }
+
+double2* Pool::get(int64_t n) {
+  const size_t bytes = std::max<size_t>(256, (size_t)n * sizeof(double2));
+  int best = -1;
+  for (size_t i = 0; i < free_.size(); ++i) {
+    if (free_[i].bytes >= bytes && free_[i].bytes <= 2 * bytes + (1 << 20)) {
+      if (best < 0 || free_[i].bytes < free_[best].bytes) best = (int)i;
+    }
+  }
+  Blk b;
+  if (best >= 0) {
+    b = free_[best];
+    free_.erase(free_.begin() + best);
+  } else {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      // drop cached blocks and retry once
+      (void)hipGetLastError();
+      (void)hipDeviceSynchronize();
+      for (auto& f : free_) (void)hipFree(f.p);
+      free_.clear();
+      e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) throw HipError{hipErrorOutOfMemory, "pool"};
+    }
+    b = {p, bytes};
+  }
+  used_.push_back(b);
+  in_use_ += b.bytes;
+  return (double2*)b.p;
+}
+
+void Pool::put(double2* p) {
+  if (!p) return;
+  for (size_t i = 0; i < used_.size(); ++i) {
+    if (used_[i].p == p) {
+      in_use_ -= used_[i].bytes;
+      free_.push_back(used_[i]);
+      used_.erase(used_.begin() + i);
+      return;
+    }
+  }
+}
+
+void Pool::release_all() {
+  for (auto& b : free_) (void)hipFree(b.p);
+  for (auto& b : used_) (void)hipFree(b.p);
+  free_.clear();
+  used_.clear();
+  in_use_ = 0;
+}
+
+Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero) {
+  Tensor t;
+  t.d = std::move(d);
+  t.p = cx.pool.get(std::max<int64_t>(1, t.size()));
+  if (zero) launch_fill(t.p, t.size(), C0(), cx.stream);
+  return t;
+}
+
+void tfree(Ctx& cx, Tensor& t) {
+  cx.pool.put(t.p);
+  t.p = nullptr;
+}
+
+// ------------------------------------------------------------------ helpers
+namespace {
+
+struct View {
+  // strides of each label (complex elements)
+  std::map<char, int64_t> stride;
+  std::map<char, int64_t> size;
+};
+
+View view_of(const Tensor& t, const char* l) {
+  const int n = (int)std::strlen(l);
+  if (n != (int)t.d.size()) throw std::invalid_argument(std::string("label/rank mismatch: ") + l);
+  View v;
+  int64_t s = 1;
+  for (int i = n - 1; i >= 0; --i) {
+    if (v.stride.count(l[i])) throw std::invalid_argument(std::string("repeated label: ") + l);
+    v.stride[l[i]] = t.st.empty() ? s : t.st[i];
+    v.size[l[i]] = t.d[i];
+    s *= t.d[i];
+  }
+  return v;
+}
+
+// Can the labels `grp` (in this order) of view v be collapsed into one stride?
+// Returns the stride of the fused index (stride of the last label) or -1.
+int64_t fused_stride(const View& v, const std::string& grp) {
+  if (grp.empty()) return 0;
+  for (size_t i = 0; i + 1 < grp.size(); ++i) {
+    const char a = grp[i], b = grp[i + 1];
+    if (v.stride.at(a) != v.stride.at(b) * v.size.at(b)) return -1;
+  }
+  return v.stride.at(grp.back());
+}
+
+int64_t prod(const View& v, const std::string& grp) {
+  int64_t p = 1;
+  for (char c : grp) p *= v.size.at(c);
+  return p;
+}
+
+// copy/accumulate view v of src into dst, iterating the labels `ord`;
+// dst strides per label come from dv (or contiguous in `ord` when null)
+void permute_into(Ctx& cx, const Tensor& src, const View& v, const std::string& ord, bool conj, double2* dst,
+                  cplx alpha, cplx beta, const View* dv = nullptr) {
+  std::vector<int64_t> od, is, os;
+  for (char c : ord) {
+    od.push_back(v.size.at(c));
+    is.push_back(v.stride.at(c));
+  }
+  if (dv) {
+    for (char c : ord) os.push_back(dv->stride.at(c));
+  } else {
+    os.resize(ord.size());
+    int64_t s = 1;
+    for (int i = (int)ord.size() - 1; i >= 0; --i) {
+      os[i] = s;
+      s *= od[i];
+    }
+  }
+  // merge consecutive dims that are contiguous in both (fewer divisions)
+  std::vector<int64_t> od2, is2, os2;
+  for (size_t i = 0; i < od.size(); ++i) {
+    if (!od2.empty() && is2.back() == is[i] * od[i] && os2.back() == os[i] * od[i]) {
+      od2.back() *= od[i];
+      is2.back() = is[i];
+      os2.back() = os[i];
+    } else {
+      od2.push_back(od[i]);
+      is2.push_back(is[i]);
+      os2.push_back(os[i]);
+    }
+  }
+  if (od2.size() > 8) throw std::invalid_argument("rank > 8");
+  launch_permute((int)od2.size(), od2.data(), is2.data(), os2.data(), src.p, dst, alpha, beta, conj ? 1 : 0,
+                 cx.stream);
+}
+
+}  // namespace
+
+void perm(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, cplx beta, Tensor& C, const char* lc) {
+  View va = view_of(A, la);
+  View vc = view_of(C, lc);
+  for (auto& kv : vc.size)
+    if (!va.size.count(kv.first) || va.size.at(kv.first) != kv.second)
+      throw std::invalid_argument(std::string("perm: label mismatch ") + la + " -> " + lc);
+  if (va.size.size() != vc.size.size()) throw std::invalid_argument("perm: rank mismatch");
+  permute_into(cx, A, va, lc, cA, C.p, alpha, beta, &vc);
+}
+
+Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi) {
+  Tensor v;
+  v.d = t.d;
+  if (t.st.empty()) {
+    v.st.resize(t.d.size());
+    int64_t s = 1;
+    for (int i = (int)t.d.size() - 1; i >= 0; --i) {
+      v.st[i] = s;
+      s *= t.d[i];
+    }
+  } else {
+    v.st = t.st;
+  }
+  v.p = t.p + lo * v.st[dim];
+  v.d[dim] = hi - lo;
+  return v;
+}
+
+void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Tensor& B, const char* lb, bool cB,
+         cplx beta, Tensor& C, const char* lc) {
+  View va = view_of(A, la), vb = view_of(B, lb), vc = view_of(C, lc);
+  std::string sa(la), sb(lb), sc(lc);
+  std::string bat, Ml, Nl, Kl;
+  for (char c : sc) {
+    const bool inA = sa.find(c) != std::string::npos, inB = sb.find(c) != std::string::npos;
+    if (inA && inB) bat += c;
+    else if (inA) Ml += c;
+    else if (inB) Nl += c;
+    else throw std::invalid_argument(std::string("ctr: output label in neither input: ") + lc);
+  }
+  for (char c : sa) {
+    const bool inB = sb.find(c) != std::string::npos, inC = sc.find(c) != std::string::npos;
+    if (inB && !inC) Kl += c;
+    if (!inB && !inC) throw std::invalid_argument(std::string("ctr: label summed in A only: ") + la);
+  }
+  for (char c : sb) {
+    const bool inA = sa.find(c) != std::string::npos, inC = sc.find(c) != std::string::npos;
+    if (!inA && !inC) throw std::invalid_argument(std::string("ctr: label summed in B only: ") + lb);
+  }
+  auto chk = [&](char c) {
+    int64_t s = -1;
+    if (va.size.count(c)) s = va.size[c];
+    if (vb.size.count(c)) {
+      if (s >= 0 && vb.size[c] != s) throw std::invalid_argument(std::string("ctr: size mismatch on ") + c);
+      s = vb.size[c];
+    }
+    if (vc.size.count(c) && s >= 0 && vc.size[c] != s) throw std::invalid_argument(std::string("ctr: size mismatch on ") + c);
+  };
+  for (char c : sa + sb) chk(c);
+
+  // K order: as in A
+  const int64_t Mn = prod(va, Ml), Nn = prod(vb, Nl), Kn = prod(va, Kl), Bn = prod(vc, bat);
+  if (Mn == 0 || Nn == 0 || Bn == 0) return;
+
+  GemmDesc g{};
+  g.M = Mn; g.N = Nn; g.K = Kn; g.batch = Bn;
+  g.alpha = alpha; g.beta = beta;
+  g.conjA = cA; g.conjB = cB;
+
+  std::vector<double2*> tmps;
+  // ---- operand A: need batch, M, K groups fusable
+  {
+    int64_t sbt = fused_stride(va, bat), sm = fused_stride(va, Ml), sk = fused_stride(va, Kl);
+    if (sbt < 0 || sm < 0 || sk < 0) {
+      double2* t = cx.pool.get(A.size());
+      tmps.push_back(t);
+      permute_into(cx, A, va, bat + Ml + Kl, false, t, C1(), C0());
+      g.A = t; g.sab = Mn * Kn; g.sam = Kn; g.sak = 1;
+    } else {
+      g.A = A.p; g.sab = sbt; g.sam = sm; g.sak = sk;
+    }
+    if (Ml.empty()) g.sam = 0;
+    if (Kl.empty()) g.sak = 0;
+    if (bat.empty()) g.sab = 0;
+  }
+  // ---- operand B: batch, K (in A's K order), N
+  {
+    int64_t sbt = fused_stride(vb, bat), sn = fused_stride(vb, Nl), sk = fused_stride(vb, Kl);
+    if (sbt < 0 || sn < 0 || sk < 0) {
+      double2* t = cx.pool.get(B.size());
+      tmps.push_back(t);
+      permute_into(cx, B, vb, bat + Nl + Kl, false, t, C1(), C0());
+      g.B = t; g.sbb = Nn * Kn; g.sbn = Kn; g.sbk = 1;
+    } else {
+      g.B = B.p; g.sbb = sbt; g.sbn = sn; g.sbk = sk;
+    }
+    if (Nl.empty()) g.sbn = 0;
+    if (Kl.empty()) g.sbk = 0;
+    if (bat.empty()) g.sbb = 0;
+  }
+  if (Kn == 0) {
+    // empty sum: C = beta C
+    if (beta.re != 1.0 || beta.im != 0.0) perm(cx, beta, C, lc, false, C0(), C, lc);
+  } else {
+    // ---- output
+    int64_t sbt = fused_stride(vc, bat), sm = fused_stride(vc, Ml), sn = fused_stride(vc, Nl);
+    if (sbt >= 0 && sm >= 0 && sn >= 0) {
+      g.C = C.p; g.scb = bat.empty() ? 0 : sbt; g.scm = Ml.empty() ? 0 : sm; g.scn = Nl.empty() ? 0 : sn;
+      launch_zgemm(g, cx.prec, cx.stream);
+    } else {
+      double2* t = cx.pool.get(Bn * Mn * Nn);
+      tmps.push_back(t);
+      g.C = t; g.scb = Mn * Nn; g.scm = Nn; g.scn = 1;
+      cplx a0 = g.alpha;
+      g.alpha = C1(); g.beta = C0();
+      launch_zgemm(g, cx.prec, cx.stream);
+      // t has labels bat+Ml+Nl contiguous
+      Tensor tt;
+      tt.p = t;
+      for (char c : bat + Ml + Nl) tt.d.push_back(vc.size.at(c));
+      std::string tl = bat + Ml + Nl;
+      perm(cx, a0, tt, tl.c_str(), false, beta, C, lc);
+    }
+  }
+  for (auto* t : tmps) cx.pool.put(t);
+}
+
+}  // namespace adc

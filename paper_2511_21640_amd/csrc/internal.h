@@ -1,0 +1,141 @@
+// Internal declarations shared by the host orchestration (adc.cpp, engine.cpp)
+// and the device kernels (kernels.hip).  Complex numbers are interleaved
+// (re, im) float64 pairs (double2) in every tensor.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace adc {
+
+struct cplx {
+  double re, im;
+};
+
+// ---------------------------------------------------------------- GEMM
+// C[b] = alpha * op(A[b]) op(B[b]) + beta * C[b] with element strides
+// (complex elements) A(m,k) at A + m*sam + k*sak + b*sab, B(k,n) at
+// B + k*sbk + n*sbn + b*sbb, C(m,n) at C + m*scm + n*scn + b*scb.
+// conjA / conjB conjugate the operand.  beta == 0 never reads C.
+struct GemmDesc {
+  int64_t M, N, K, batch;
+  const double2* A; int64_t sam, sak, sab;
+  const double2* B; int64_t sbk, sbn, sbb;
+  double2* C; int64_t scm, scn, scb;
+  cplx alpha, beta;
+  int conjA, conjB;
+};
+// prec: 0 = FP64 MFMA, 1 = FP32 MFMA (operands rounded to fp32, fp32
+// accumulate), 2 = split-bf16 (three bf16 MFMA products, fp32 accumulate).
+void launch_zgemm(const GemmDesc& g, int prec, hipStream_t s);
+
+// ---------------------------------------------------------------- permute
+// out[sum_d idx_d * ostr[d]] = alpha * op(in[sum_d idx_d * istr[d]]) + beta * out[...]
+// over the index box od[0..nd)
+void launch_permute(int nd, const int64_t* od, const int64_t* istr, const int64_t* ostr, const double2* in,
+                    double2* out, cplx alpha, cplx beta, int conj, hipStream_t s);
+// M[i][i] += d[i] (real) for an n x n matrix
+void launch_add_diag(double2* M, const double* d, int64_t n, hipStream_t s);
+// R[r][i] = AX[r][i] - w[r] X[r][i]
+void launch_resid(const double2* AX, const double2* X, const double* w, double2* R, int rows, int64_t n,
+                  hipStream_t s);
+
+// ---------------------------------------------------------------- misc
+void launch_fill(double2* p, int64_t n, cplx v, hipStream_t s);
+void launch_scale_real(double2* p, const double* w, int64_t n, int64_t period, int invert, hipStream_t s);
+// out[r][c] = X[r][c] + conj(X[c][r]) (n x n), out may not alias X
+void launch_herm_add(const double2* X, double2* out, int64_t n, hipStream_t s);
+// M (n1 x n1, n1 = no*nv, index (i,a) i-major): M[(i,a),(i,A)] += f[a][A]  (diag_occ)
+// or M[(i,a),(I,a)] += h[i][I] (diag_vir)
+void launch_m11_add_delta(double2* M, const double2* f, int no, int nv, int which, hipStream_t s);
+// denominators: t[i][j][a][b] = num / (e_i + e_j - e_a - e_b)   (or * when invert=0)
+void launch_div_d2(double2* t, const double* eps, int no, int nv, hipStream_t s);
+void launch_div_d1(double2* t, const double* eps, int no, int nv, hipStream_t s);
+
+// Packed ISR vector <-> unpacked doubles tensor conversions.
+// kind: 0 EE [k][o][o][v][v], 1 IP [k][o][o][v], 2 EA [k][o][v][v].
+// unpack: Ya antisymmetric in every pair; Yp (optional) zero except packed positions.
+void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv,
+                           double2* Ya, double2* Yp, hipStream_t s);
+// S[z][off + packed] = alpha * U[z][...] + D[packed] * Y[z][off + packed] (+ S if accumulate)
+void launch_pack_doubles(int kind, const double2* U, double2* S, const double2* Y, int64_t ld, int64_t off,
+                         int k, int no, int nv, const double* eps, cplx alpha, int accumulate,
+                         const int2* pair_o, const int2* pair_v, hipStream_t s);
+// antisymmetrisers on [k][p][p][q][q]-like tensors: out += X - swap(pair)
+// pair 0 swaps dims 1,2 ; pair 1 swaps dims 3,4 ; pair 2 swaps both pairs (P(ij)P(ab)).
+void launch_antisym_add(const double2* X, double2* out, int64_t k, int64_t d1, int64_t d2, int64_t d3,
+                        int64_t d4, int which, cplx alpha, hipStream_t s);
+
+// Ladder: from W[(a - a0)*nv + c][(b - b0)*nv + d] (row length ldw) build the
+// packed rows V[r][pair(c,d)] = W_ab,cd - W_ab,dc for the npairs pairs
+// (a,b) = pair_v[pbase + r].
+void launch_ladder_pack(const double2* W, int64_t ldw, int a0, int b0, int nv, double2* V, int64_t pbase,
+                        int64_t npairs, const int2* pair_v, hipStream_t s);
+
+// Davidson helpers
+// partial[r*nb + blk] = sum_i conj(X[r][i]) Y[r][i] over the block's chunk
+void launch_row_dots(const double2* X, int64_t ldx, const double2* Y, int64_t ldy, int rows, int64_t n,
+                     double2* partial, int nb, hipStream_t s);
+// N[r][i] = R[r][i] / den,  den = w[r] - D[i] floored at |den| >= 1e-4
+void launch_precondition(const double2* R, double2* N, const double* D, const double* w, int rows, int64_t n,
+                         hipStream_t s);
+int row_dot_blocks(int64_t n);
+
+// ---------------------------------------------------------------- engine
+struct Tensor {
+  double2* p = nullptr;
+  std::vector<int64_t> d;
+  std::vector<int64_t> st;  // element strides; empty = contiguous row-major
+  int64_t size() const {
+    int64_t s = 1;
+    for (auto x : d) s *= x;
+    return s;
+  }
+};
+
+class Pool {
+ public:
+  ~Pool();
+  double2* get(int64_t n_complex);
+  void put(double2* p);
+  void release_all();
+  size_t bytes_in_use() const { return in_use_; }
+
+ private:
+  struct Blk { void* p; size_t bytes; };
+  std::vector<Blk> free_, used_;
+  size_t in_use_ = 0;
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  Pool pool;
+  int prec = 0;   // arithmetic of ctr() calls
+};
+
+// C[lc] = alpha * sum A[la]^(conj?) B[lb]^(conj?) + beta * C[lc]
+void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Tensor& B, const char* lb,
+         bool cB, cplx beta, Tensor& C, const char* lc);
+// C[lc] = alpha * op(A[la]) + beta * C[lc]
+void perm(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, cplx beta, Tensor& C, const char* lc);
+
+Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero = true);
+// view of t with dimension `dim` restricted to [lo, hi)
+Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi);
+void tfree(Ctx& cx, Tensor& t);
+
+inline cplx C1() { return {1.0, 0.0}; }
+inline cplx C0() { return {0.0, 0.0}; }
+inline cplx CR(double r) { return {r, 0.0}; }
+
+struct HipError {
+  hipError_t e;
+  const char* where;
+};
+inline void hipcheck(hipError_t e, const char* where) {
+  if (e != hipSuccess) throw HipError{e, where};
+}
+
+}  // namespace adc

@@ -1,0 +1,669 @@
+// Device kernels of the sigma build (gfx950 / CDNA4).
+//
+// Complex tensors are interleaved (re, im) float64.  Contractions run on the
+// matrix cores: the complex product is split into real/imaginary planes in LDS
+// and formed with four real MFMA products per k-step (Re*Re - Im*Im into the
+// real accumulator, Re*Im + Im*Re into the imaginary one).
+#include "internal.h"
+
+#include <hip/hip_bf16.h>
+
+namespace adc {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+static inline unsigned nblocks(int64_t n, int t) {
+  int64_t b = (n + t - 1) / t;
+  if (b > 65535LL * 16) b = 65535LL * 16;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA complex GEMM.  Tile 64x64 per 256-thread workgroup, each wave a
+// 32x32 quadrant as 2x2 blocks of v_mfma_f64_16x16x4f64.
+// ---------------------------------------------------------------------------
+constexpr int TM = 64, TN = 64, TK = 16;
+
+__global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
+  __shared__ double sAr[TK][TM], sAi[TK][TM], sBr[TK][TN], sBi[TK][TN];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
+  const int64_t bz = blockIdx.z;
+  const double2* A = p.A + bz * p.sab;
+  const double2* B = p.B + bz * p.sbb;
+  double2* C = p.C + bz * p.scb;
+  const int wr = wave >> 1, wc = wave & 1;
+  const bool aK = (p.sak == 1), bK = (p.sbk == 1);
+  const double sa = p.conjA ? -1.0 : 1.0, sb = p.conjB ? -1.0 : 1.0;
+
+  dbl4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  for (int64_t k0 = 0; k0 < p.K; k0 += TK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int m, k;
+      if (aK) { m = (tid >> 4) + 16 * r; k = tid & 15; }
+      else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
+      const int64_t gm = m0 + m, gk = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (gm < p.M && gk < p.K) v = A[gm * p.sam + gk * p.sak];
+      sAr[k][m] = v.x;
+      sAi[k][m] = sa * v.y;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int n, k;
+      if (bK) { n = (tid >> 4) + 16 * r; k = tid & 15; }
+      else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
+      const int64_t gn = n0 + n, gk = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (gn < p.N && gk < p.K) v = B[gk * p.sbk + gn * p.sbn];
+      sBr[k][n] = v.x;
+      sBi[k][n] = sb * v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = sAr[kr][32 * wr + 16 * i + (lane & 15)];
+        ai[i] = sAi[kr][32 * wr + 16 * i + (lane & 15)];
+        nai[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        br[j] = sBr[kr][32 * wc + 16 * j + (lane & 15)];
+        bi[j] = sBi[kr][32 * wc + 16 * j + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
+          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f64_16x16x4f64 result: lane l, register r holds row l/16 + 4r, column l%16
+        const int64_t row = m0 + 32 * wr + 16 * i + (lane >> 4) + 4 * r;
+        const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
+        if (row < p.M && col < p.N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          double2* dst = C + row * p.scm + col * p.scn;
+          double2 o;
+          o.x = p.alpha.re * cr - p.alpha.im * ci;
+          o.y = p.alpha.re * ci + p.alpha.im * cr;
+          if (has_beta) {
+            const double2 old = *dst;
+            o.x += p.beta.re * old.x - p.beta.im * old.y;
+            o.y += p.beta.re * old.y + p.beta.im * old.x;
+          }
+          *dst = o;
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 MFMA complex GEMM (operands rounded to fp32, fp32 accumulation).
+// Same tiling with v_mfma_f32_16x16x4f32 (4 real products per complex k-step).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
+  __shared__ float sAr[TK][TM], sAi[TK][TM], sBr[TK][TN], sBi[TK][TN];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
+  const int64_t bz = blockIdx.z;
+  const double2* A = p.A + bz * p.sab;
+  const double2* B = p.B + bz * p.sbb;
+  double2* C = p.C + bz * p.scb;
+  const int wr = wave >> 1, wc = wave & 1;
+  const bool aK = (p.sak == 1), bK = (p.sbk == 1);
+  const float sa = p.conjA ? -1.0f : 1.0f, sb = p.conjB ? -1.0f : 1.0f;
+  flt4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int64_t k0 = 0; k0 < p.K; k0 += TK) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int m, k;
+      if (aK) { m = (tid >> 4) + 16 * r; k = tid & 15; }
+      else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
+      const int64_t gm = m0 + m, gk = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (gm < p.M && gk < p.K) v = A[gm * p.sam + gk * p.sak];
+      sAr[k][m] = (float)v.x;
+      sAi[k][m] = sa * (float)v.y;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int n, k;
+      if (bK) { n = (tid >> 4) + 16 * r; k = tid & 15; }
+      else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
+      const int64_t gn = n0 + n, gk = k0 + k;
+      double2 v = make_double2(0.0, 0.0);
+      if (gn < p.N && gk < p.K) v = B[gk * p.sbk + gn * p.sbn];
+      sBr[k][n] = (float)v.x;
+      sBi[k][n] = sb * (float)v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      float ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        ar[i] = sAr[kr][32 * wr + 16 * i + (lane & 15)];
+        ai[i] = sAi[kr][32 * wr + 16 * i + (lane & 15)];
+        nai[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        br[j] = sBr[kr][32 * wc + 16 * j + (lane & 15)];
+        bi[j] = sBi[kr][32 * wc + 16 * j + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], accR[i][j], 0, 0, 0);
+          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[i], bi[j], accR[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], accI[i][j], 0, 0, 0);
+          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], accI[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+  }
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f32_16x16x4f32 result: lane l, register r holds row 4(l/16) + r, column l%16
+        const int64_t row = m0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
+        const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
+        if (row < p.M && col < p.N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          double2* dst = C + row * p.scm + col * p.scn;
+          double2 o;
+          o.x = p.alpha.re * cr - p.alpha.im * ci;
+          o.y = p.alpha.re * ci + p.alpha.im * cr;
+          if (has_beta) {
+            const double2 old = *dst;
+            o.x += p.beta.re * old.x - p.beta.im * old.y;
+            o.y += p.beta.re * old.y + p.beta.im * old.x;
+          }
+          *dst = o;
+        }
+      }
+}
+
+void launch_zgemm(const GemmDesc& g, int prec, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  if (g.K <= 0) {
+    // C = beta * C
+    GemmDesc h = g;
+    (void)h;
+  }
+  dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM), (unsigned)g.batch);
+  if (prec == 0)
+    hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL(zgemm_f32_kernel, grid, dim3(256), 0, s, g);
+}
+
+// ---------------------------------------------------------------------------
+// generic permute / axpby into a contiguous output
+// ---------------------------------------------------------------------------
+struct PermArgs {
+  int nd;
+  int64_t od[8];
+  int64_t is[8];
+  int64_t os[8];
+  const double2* in;
+  double2* out;
+  int64_t total;
+  cplx alpha, beta;
+  int conj;
+};
+
+__global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < p.total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rem = idx, off = 0, ooff = 0;
+    for (int d = p.nd - 1; d >= 0; --d) {
+      const int64_t q = rem / p.od[d];
+      const int64_t r = rem - q * p.od[d];
+      off += r * p.is[d];
+      ooff += r * p.os[d];
+      rem = q;
+    }
+    double2 v = p.in[off];
+    if (p.conj) v.y = -v.y;
+    double2 o;
+    o.x = p.alpha.re * v.x - p.alpha.im * v.y;
+    o.y = p.alpha.re * v.y + p.alpha.im * v.x;
+    if (has_beta) {
+      const double2 old = p.out[ooff];
+      o.x += p.beta.re * old.x - p.beta.im * old.y;
+      o.y += p.beta.re * old.y + p.beta.im * old.x;
+    }
+    p.out[ooff] = o;
+  }
+}
+
+void launch_permute(int nd, const int64_t* od, const int64_t* istr, const int64_t* ostr, const double2* in,
+                    double2* out, cplx alpha, cplx beta, int conj, hipStream_t s) {
+  PermArgs a;
+  a.nd = nd;
+  a.total = 1;
+  for (int d = 0; d < nd; ++d) {
+    a.od[d] = od[d];
+    a.is[d] = istr[d];
+    a.os[d] = ostr[d];
+    a.total *= od[d];
+  }
+  if (a.total == 0) return;
+  a.in = in;
+  a.out = out;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.conj = conj;
+  hipLaunchKernelGGL(permute_kernel, dim3(nblocks(a.total, 256)), dim3(256), 0, s, a);
+}
+
+__global__ void add_diag_kernel(double2* M, const double* d, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    M[i * n + i].x += d[i];
+}
+void launch_add_diag(double2* M, const double* d, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(add_diag_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, M, d, n);
+}
+
+__global__ void resid_kernel(const double2* AX, const double2* X, const double* w, double2* R, int rows, int64_t n) {
+  const int64_t total = (int64_t)rows * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const double wr = w[idx / n];
+    R[idx] = make_double2(AX[idx].x - wr * X[idx].x, AX[idx].y - wr * X[idx].y);
+  }
+}
+void launch_resid(const double2* AX, const double2* X, const double* w, double2* R, int rows, int64_t n,
+                  hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(resid_kernel, dim3(nblocks((int64_t)rows * n, 256)), dim3(256), 0, s, AX, X, w, R, rows, n);
+}
+
+// ---------------------------------------------------------------------------
+// small elementwise kernels
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(double2* p, int64_t n, cplx v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = make_double2(v.re, v.im);
+}
+void launch_fill(double2* p, int64_t n, cplx v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+__global__ void scale_real_kernel(double2* p, const double* w, int64_t n, int64_t period, int invert) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double f = w[i % period];
+    const double m = invert ? 1.0 / f : f;
+    p[i].x *= m;
+    p[i].y *= m;
+  }
+}
+void launch_scale_real(double2* p, const double* w, int64_t n, int64_t period, int invert, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(scale_real_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, p, w, n, period, invert);
+}
+
+__global__ void herm_add_kernel(const double2* X, double2* out, int64_t n) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n * n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / n, c = idx - r * n;
+    const double2 a = X[idx], b = X[c * n + r];
+    out[idx] = make_double2(a.x + b.x, a.y - b.y);
+  }
+}
+void launch_herm_add(const double2* X, double2* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(herm_add_kernel, dim3(nblocks(n * n, 256)), dim3(256), 0, s, X, out, n);
+}
+
+__global__ void m11_add_delta_kernel(double2* M, const double2* f, int no, int nv, int which) {
+  const int64_t n1 = (int64_t)no * nv;
+  const int64_t total = which == 0 ? (int64_t)no * nv * nv : (int64_t)no * no * nv;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (which == 0) {  // delta_iI f[a][A]
+      const int64_t i = idx / (nv * nv), r = idx - i * nv * nv, a = r / nv, A = r - a * nv;
+      double2* d = M + (i * nv + a) * n1 + i * nv + A;
+      d->x += f[a * nv + A].x;
+      d->y += f[a * nv + A].y;
+    } else {  // delta_aA h[i][I]
+      const int64_t i = idx / ((int64_t)no * nv), r = idx - i * no * nv, I = r / nv, a = r - I * nv;
+      double2* d = M + (i * nv + a) * n1 + I * nv + a;
+      d->x += f[i * no + I].x;
+      d->y += f[i * no + I].y;
+    }
+  }
+}
+void launch_m11_add_delta(double2* M, const double2* f, int no, int nv, int which, hipStream_t s) {
+  const int64_t total = which == 0 ? (int64_t)no * nv * nv : (int64_t)no * no * nv;
+  hipLaunchKernelGGL(m11_add_delta_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, M, f, no, nv, which);
+}
+
+__global__ void div_d2_kernel(double2* t, const double* eps, int no, int nv) {
+  const int64_t total = (int64_t)no * no * nv * nv;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = idx;
+    const int b = r % nv; r /= nv;
+    const int a = r % nv; r /= nv;
+    const int j = r % no; r /= no;
+    const int i = (int)r;
+    const double D = eps[i] + eps[j] - eps[no + a] - eps[no + b];
+    t[idx].x /= D;
+    t[idx].y /= D;
+  }
+}
+void launch_div_d2(double2* t, const double* eps, int no, int nv, hipStream_t s) {
+  const int64_t total = (int64_t)no * no * nv * nv;
+  hipLaunchKernelGGL(div_d2_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, t, eps, no, nv);
+}
+__global__ void div_d1_kernel(double2* t, const double* eps, int no, int nv) {
+  const int64_t total = (int64_t)no * nv;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / nv), a = (int)(idx % nv);
+    const double D = eps[i] - eps[no + a];
+    t[idx].x /= D;
+    t[idx].y /= D;
+  }
+}
+void launch_div_d1(double2* t, const double* eps, int no, int nv, hipStream_t s) {
+  hipLaunchKernelGGL(div_d1_kernel, dim3(nblocks((int64_t)no * nv, 256)), dim3(256), 0, s, t, eps, no, nv);
+}
+
+// pair index of p<q among n: p*(2n-p-1)/2 + (q-p-1)
+__device__ __forceinline__ int64_t pidx(int64_t p, int64_t q, int64_t n) { return p * (2 * n - p - 1) / 2 + (q - p - 1); }
+
+// unpack: one thread per unpacked element
+__global__ void unpack_doubles_kernel(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv,
+                                      double2* Ya, double2* Yp) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
+  int64_t per;
+  if (kind == 0) per = (int64_t)no * no * nv * nv;
+  else if (kind == 1) per = (int64_t)no * no * nv;
+  else per = (int64_t)no * nv * nv;
+  const int64_t total = per * k;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = idx / per;
+    int64_t r = idx - z * per;
+    double sgn = 1.0;
+    bool zero = false, canon = true;
+    int64_t pos = 0;
+    if (kind == 0) {
+      const int64_t b = r % nv; r /= nv;
+      const int64_t a = r % nv; r /= nv;
+      const int64_t j = r % no; const int64_t i = r / no;
+      if (i == j || a == b) zero = true;
+      else {
+        const int64_t i0 = i < j ? i : j, j0 = i < j ? j : i, a0 = a < b ? a : b, b0 = a < b ? b : a;
+        if (i > j) sgn = -sgn;
+        if (a > b) sgn = -sgn;
+        canon = (i < j) && (a < b);
+        pos = pidx(i0, j0, no) * Pv + pidx(a0, b0, nv);
+      }
+    } else if (kind == 1) {
+      const int64_t a = r % nv; r /= nv;
+      const int64_t j = r % no; const int64_t i = r / no;
+      if (i == j) zero = true;
+      else {
+        const int64_t i0 = i < j ? i : j, j0 = i < j ? j : i;
+        if (i > j) sgn = -1.0;
+        canon = i < j;
+        pos = pidx(i0, j0, no) * nv + a;
+      }
+    } else {
+      const int64_t b = r % nv; r /= nv;
+      const int64_t a = r % nv; const int64_t i = r / nv;
+      if (a == b) zero = true;
+      else {
+        const int64_t a0 = a < b ? a : b, b0 = a < b ? b : a;
+        if (a > b) sgn = -1.0;
+        canon = a < b;
+        pos = i * Pv + pidx(a0, b0, nv);
+      }
+    }
+    double2 v = make_double2(0.0, 0.0);
+    if (!zero) {
+      const double2 y = Y[z * ldY + off + pos];
+      v = make_double2(sgn * y.x, sgn * y.y);
+    }
+    if (Ya) Ya[idx] = v;
+    if (Yp) Yp[idx] = (!zero && canon) ? v : make_double2(0.0, 0.0);
+  }
+  (void)Po;
+}
+void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, double2* Ya,
+                           double2* Yp, hipStream_t s) {
+  int64_t per = kind == 0 ? (int64_t)no * no * nv * nv : (kind == 1 ? (int64_t)no * no * nv : (int64_t)no * nv * nv);
+  hipLaunchKernelGGL(unpack_doubles_kernel, dim3(nblocks(per * k, 256)), dim3(256), 0, s, kind, Y, ldY, off, k, no,
+                     nv, Ya, Yp);
+}
+
+// pack: one thread per packed element; po/pv are the pair tables of o and v
+__global__ void pack_doubles_kernel(int kind, const double2* U, double2* S, const double2* Y, int64_t ld, int64_t off,
+                                    int k, int no, int nv, const double* eps, cplx alpha, int accumulate,
+                                    const int2* po, const int2* pv) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
+  int64_t n2;
+  if (kind == 0) n2 = Po * Pv;
+  else if (kind == 1) n2 = Po * nv;
+  else n2 = (int64_t)no * Pv;
+  const int64_t per = kind == 0 ? (int64_t)no * no * nv * nv : (kind == 1 ? (int64_t)no * no * nv : (int64_t)no * nv * nv);
+  const int64_t total = n2 * k;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = idx / n2, q = idx - z * n2;
+    int64_t uoff;
+    double D;
+    if (kind == 0) {
+      const int64_t pij = q / Pv, pab = q - pij * Pv;
+      const int2 ij = po[pij], ab = pv[pab];
+      uoff = (((int64_t)ij.x * no + ij.y) * nv + ab.x) * nv + ab.y;
+      D = eps[no + ab.x] + eps[no + ab.y] - eps[ij.x] - eps[ij.y];
+    } else if (kind == 1) {
+      const int64_t pij = q / nv, a = q - pij * nv;
+      const int2 ij = po[pij];
+      uoff = ((int64_t)ij.x * no + ij.y) * nv + a;
+      D = eps[no + a] - eps[ij.x] - eps[ij.y];
+    } else {
+      const int64_t i = q / Pv, pab = q - i * Pv;
+      const int2 ab = pv[pab];
+      uoff = (i * nv + ab.x) * nv + ab.y;
+      D = eps[no + ab.x] + eps[no + ab.y] - eps[i];
+    }
+    double2 o = make_double2(0.0, 0.0);
+    if (U) {
+      const double2 u = U[z * per + uoff];
+      o.x = alpha.re * u.x - alpha.im * u.y;
+      o.y = alpha.re * u.y + alpha.im * u.x;
+    }
+    if (Y) {
+      const double2 y = Y[z * ld + off + q];
+      o.x += D * y.x;
+      o.y += D * y.y;
+    }
+    double2* dst = S + z * ld + off + q;
+    if (accumulate) {
+      o.x += dst->x;
+      o.y += dst->y;
+    }
+    *dst = o;
+  }
+}
+void launch_pack_doubles(int kind, const double2* U, double2* S, const double2* Y, int64_t ld, int64_t off, int k,
+                         int no, int nv, const double* eps, cplx alpha, int accumulate, const int2* po,
+                         const int2* pv, hipStream_t s) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
+  int64_t n2 = kind == 0 ? Po * Pv : (kind == 1 ? Po * nv : (int64_t)no * Pv);
+  if (n2 * k == 0) return;
+  hipLaunchKernelGGL(pack_doubles_kernel, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, kind, U, S, Y, ld, off, k,
+                     no, nv, eps, alpha, accumulate, po, pv);
+}
+
+__global__ void antisym_add_kernel(const double2* X, double2* out, int64_t k, int64_t d1, int64_t d2, int64_t d3,
+                                   int64_t d4, int which, cplx alpha) {
+  const int64_t total = k * d1 * d2 * d3 * d4;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = idx;
+    const int64_t e4 = r % d4; r /= d4;
+    const int64_t e3 = r % d3; r /= d3;
+    const int64_t e2 = r % d2; r /= d2;
+    const int64_t e1 = r % d1; const int64_t z = r / d1;
+    auto at = [&](int64_t a, int64_t b, int64_t c, int64_t d) { return X[(((z * d1 + a) * d2 + b) * d3 + c) * d4 + d]; };
+    double2 v = at(e1, e2, e3, e4);
+    if (which == 0) {
+      const double2 w = at(e2, e1, e3, e4);
+      v.x -= w.x; v.y -= w.y;
+    } else if (which == 1) {
+      const double2 w = at(e1, e2, e4, e3);
+      v.x -= w.x; v.y -= w.y;
+    } else {
+      const double2 w1 = at(e2, e1, e3, e4), w2 = at(e1, e2, e4, e3), w3 = at(e2, e1, e4, e3);
+      v.x += -w1.x - w2.x + w3.x;
+      v.y += -w1.y - w2.y + w3.y;
+    }
+    double2 o = out[idx];
+    o.x += alpha.re * v.x - alpha.im * v.y;
+    o.y += alpha.re * v.y + alpha.im * v.x;
+    out[idx] = o;
+  }
+}
+void launch_antisym_add(const double2* X, double2* out, int64_t k, int64_t d1, int64_t d2, int64_t d3, int64_t d4,
+                        int which, cplx alpha, hipStream_t s) {
+  const int64_t total = k * d1 * d2 * d3 * d4;
+  if (total == 0) return;
+  hipLaunchKernelGGL(antisym_add_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, X, out, k, d1, d2, d3, d4, which,
+                     alpha);
+}
+
+// ---------------------------------------------------------------------------
+// ladder: pack antisymmetrised <ab||cd> rows from the assembled (ac|bd) block
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ladder_pack_kernel(const double2* W, int64_t ldw, int a0, int b0, int nv,
+                                                          double2* V, int64_t pbase, const int2* pv, int64_t Pv) {
+  const int64_t pr = blockIdx.y;              // row pair, relative to pbase
+  const int2 ab = pv[pbase + pr];
+  const int64_t ra = (int64_t)(ab.x - a0) * nv, cb = (int64_t)(ab.y - b0) * nv;
+  for (int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < Pv; pc += (int64_t)gridDim.x * blockDim.x) {
+    const int2 cd = pv[pc];
+    const double2 w1 = W[(ra + cd.x) * ldw + cb + cd.y];
+    const double2 w2 = W[(ra + cd.y) * ldw + cb + cd.x];
+    V[pr * Pv + pc] = make_double2(w1.x - w2.x, w1.y - w2.y);
+  }
+}
+void launch_ladder_pack(const double2* W, int64_t ldw, int a0, int b0, int nv, double2* V, int64_t pbase,
+                        int64_t npairs, const int2* pv, hipStream_t s) {
+  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+  if (npairs <= 0 || Pv <= 0) return;
+  unsigned gx = (unsigned)((Pv + 255) / 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(ladder_pack_kernel, dim3(gx, (unsigned)npairs), dim3(256), 0, s, W, ldw, a0, b0, nv, V, pbase, pv,
+                     Pv);
+}
+
+// ---------------------------------------------------------------------------
+// Davidson helpers
+// ---------------------------------------------------------------------------
+int row_dot_blocks(int64_t n) {
+  int64_t b = (n + 4095) / 4096;
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+__global__ __launch_bounds__(256) void row_dots_kernel(const double2* X, int64_t ldx, const double2* Y, int64_t ldy,
+                                                       int64_t n, double2* partial, int nb) {
+  const int r = blockIdx.y, blk = blockIdx.x;
+  const int64_t chunk = (n + nb - 1) / nb;
+  const int64_t i0 = (int64_t)blk * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
+  double sr = 0.0, si = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const double2 x = X[(int64_t)r * ldx + i], y = Y[(int64_t)r * ldy + i];
+    sr += x.x * y.x + x.y * y.y;
+    si += x.x * y.y - x.y * y.x;
+  }
+  __shared__ double shr[256], shi[256];
+  shr[threadIdx.x] = sr;
+  shi[threadIdx.x] = si;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      shr[threadIdx.x] += shr[threadIdx.x + w];
+      shi[threadIdx.x] += shi[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)r * nb + blk] = make_double2(shr[0], shi[0]);
+}
+void launch_row_dots(const double2* X, int64_t ldx, const double2* Y, int64_t ldy, int rows, int64_t n,
+                     double2* partial, int nb, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(row_dots_kernel, dim3(nb, rows), dim3(256), 0, s, X, ldx, Y, ldy, n, partial, nb);
+}
+
+__global__ void precondition_kernel(const double2* R, double2* N, const double* D, const double* w, int rows,
+                                    int64_t n) {
+  const int64_t total = (int64_t)rows * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / n, i = idx - r * n;
+    double den = w[r] - D[i];
+    if (fabs(den) < 1e-4) den = den < 0.0 ? -1e-4 : 1e-4;
+    N[idx] = make_double2(R[idx].x / den, R[idx].y / den);
+  }
+}
+void launch_precondition(const double2* R, double2* N, const double* D, const double* w, int rows, int64_t n,
+                         hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(precondition_kernel, dim3(nblocks((int64_t)rows * n, 256)), dim3(256), 0, s, R, N, D, w, rows, n);
+}
+
+}  // namespace adc

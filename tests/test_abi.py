@@ -1,0 +1,85 @@
+"""The C ABI library loads, exports every entry point include/adc.h declares,
+and rejects bad input on the host before touching any device (runs on CPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2511_21640_amd as adc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "adc.h")).read()
+    return sorted(set(re.findall(r"\b(adc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_matches_binding_list():
+    assert _declared() == sorted(adc.EXPORTS)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(adc.LIB_PATH):
+        adc.build()
+    return adc.load()
+
+
+def test_exports(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _problem(kind=0, o=2, v=3, N=4, k=1, eps=None, L=None, x=1.0):
+    n = o + v
+    eps = np.linspace(-1, 1, n) if eps is None else eps
+    if L is None:
+        rng = np.random.default_rng(0)
+        G = rng.standard_normal((N, n, n)) + 1j * rng.standard_normal((N, n, n))
+        L = 0.05 * (G + G.conj().transpose(0, 2, 1))
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.complex128)
+    p = adc.AdcProblem(kind, o, v, N, k, eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), L.ctypes.data, 0, x)
+    return p, (eps, L)
+
+
+def _init(lib, p):
+    h = ctypes.c_void_p()
+    return lib.adc_init(ctypes.byref(p), 1, None, ctypes.byref(h)), h
+
+
+def test_validation_errors(lib):
+    assert lib.adc_init(None, 1, None, None) == -1
+    p, keep = _problem(o=0)
+    assert _init(lib, p)[0] == -1
+    p, keep = _problem(kind=7)
+    assert _init(lib, p)[0] == -1
+    p, keep = _problem(v=1)
+    assert _init(lib, p)[0] == -1
+    eps = np.linspace(-1, 1, 5)
+    eps[2] = np.nan
+    p, keep = _problem(eps=eps)
+    assert _init(lib, p)[0] == -2
+    p, keep = _problem(x=float("inf"))
+    assert _init(lib, p)[0] == -2
+    rng = np.random.default_rng(1)
+    L = 0.05 * (rng.standard_normal((4, 5, 5)) + 1j * rng.standard_normal((4, 5, 5)))
+    p, keep = _problem(L=L)
+    assert _init(lib, p)[0] == -3
+    L = np.zeros((4, 5, 5), complex)
+    L[1, 2, 2] = np.inf
+    p, keep = _problem(L=L)
+    assert _init(lib, p)[0] == -2
+    # two problems: batched handles are not built
+    p, keep = _problem()
+    h = ctypes.c_void_p()
+    assert lib.adc_init(ctypes.byref(p), 2, None, ctypes.byref(h)) == -1
+
+
+def test_strerror(lib):
+    for c in (0, 1, -1, -2, -3, -4, -5, -6, 99):
+        assert isinstance(lib.adc_strerror(c), bytes)
+    lib.adc_free(None)
