@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Sigma-build throughput on one MI355X.
+
+Workload: EE-ADC(2)+x(3), x = 0.5, o = 20, v = 120 spinors, N_chol = 900,
+8 trial vectors (the plain-vs-mixed configuration), synthetic seeded inputs
+(``adcgen``).  One step = one sigma build S = M(x) Y for all 8 vectors, inputs
+resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--precision fp32|split_bf16|fp64]
+                  [--no-cpu] [--no-eig]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sigma builds/s + MFMA TFLOP/s, mixed vs FP64 GPU at ≤1e-6 Eh eigval error"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
+DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}
+
+
+def core_flops(o, v, N, k):
+    """Algorithmic (core) flop of one EE sigma build, 8 flop per complex MAC:
+    vvvv assembly 2 N Pv^2, pp-ladder k Po Pv^2, ring k (ov)^3, hh-ladder
+    k Po^2 Pv, first-order coupling k o^2 v^3 (three-external class stored)."""
+    Po, Pv = o * (o - 1) // 2, v * (v - 1) // 2
+    assembly = 2 * N * Pv * Pv
+    ladder = k * Po * Pv * Pv
+    ring = k * (o * v) ** 3
+    hh = k * Po * Po * Pv
+    coupling = k * o * o * v ** 3
+    return 8.0 * (assembly + ladder + ring + hh + coupling), 8.0 * (assembly + ladder)
+
+
+def time_calls(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(P, k):
+    """The oracle's matrix-free FP64 sigma on the host, one of the k roots, M11
+    product and integral setup excluded (they are one-off)."""
+    from oracle.adc_terms import Ints, dims, sigma_block
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        cores = len(os.sched_getaffinity(0))
+    ints = Ints(P.eps, P.L, P.o)
+    for c in ("vvvv", "ovvv", "vovv", "ovov", "oovv", "vvoo", "ooov", "oooo"):
+        ints.g(c)
+    ints.amp("t")
+    n1, n2 = dims("EE", P.o, P.v)
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((1, n1 + n2)) + 1j * rng.standard_normal((1, n1 + n2))
+    t0 = time.perf_counter()
+    for blk, od, f in [("12", 1, 1.0), ("12", 2, P.x), ("21", 1, 1.0), ("21", 2, P.x), ("22", 0, 1.0), ("22", 1, P.x)]:
+        src = Y[:, :n1] if blk[1] == "1" else Y[:, n1:]
+        sigma_block(ints, "EE", blk, od, src)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / (k * dt), "unit": "sigma builds/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"1 of {k} trial vectors of one build (numpy FP64 einsum, integrals precomputed, "
+                      f"M11 product excluded), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-eig", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is a "
+              f"design only, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2511_21640_amd as adc
+    from adcgen import config_problem
+
+    P = config_problem("C2")
+    k = P.n_roots
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    h = adc.Handle("EE", P.o, P.v, P.eps, P.L, k, x=P.x, precision=args.precision, conv_tol=1e-7)
+    init_wall = time.perf_counter() - t0
+    rng = np.random.default_rng(3)
+    Y = torch.from_numpy(rng.standard_normal((k, h.dim)) + 1j * rng.standard_normal((k, h.dim))).cuda()
+    S = torch.empty_like(Y)
+    print(f"[bench] C2 dim={h.dim} init {h.init_ms:.0f} ms; timing {args.precision}", file=sys.stderr, flush=True)
+
+    ms = time_calls(lambda: h.sigma(Y, S, precision=args.precision), args.steps, args.warmup, stream)
+    print(f"[bench] {args.precision} sigma {ms:.2f} ms/build", file=sys.stderr, flush=True)
+    ms64 = time_calls(lambda: h.sigma(Y, S, precision="fp64"), max(3, args.steps // 2), 1, stream)
+    print(f"[bench] fp64 sigma {ms64:.2f} ms/build", file=sys.stderr, flush=True)
+    ms_lad = time_calls(lambda: h.sigma_term("ladder", Y, S, precision=args.precision), args.steps, 1, stream)
+    print(f"[bench] ladder term {ms_lad:.2f} ms", file=sys.stderr, flush=True)
+
+    flops, lad_flops = core_flops(P.o, P.v, P.n_chol, k)
+    peak = PEAK_TFLOPS[args.precision]
+    achieved = lad_flops / (ms_lad * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": 1000.0 / ms,
+        "unit": "sigma builds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "EE-ADC(2)+x(3) x=0.5, o=20 v=120 Nchol=900, 8 trial vectors (C2)",
+                   "kind": "EE", "o": P.o, "v": P.v, "n_chol": P.n_chol, "k": k, "x": P.x,
+                   "dim": h.dim, "precision": args.precision},
+        "tflops_core": flops / (ms * 1e-3) / 1e12,
+        "core_flop_per_build": flops,
+        "fp64": {"ms_per_build": ms64, "builds_per_s": 1000.0 / ms64,
+                 "tflops_core": flops / (ms64 * 1e-3) / 1e12},
+        "speedup_vs_fp64": ms64 / ms,
+        "init_ms": h.init_ms,
+        "roofline": {"bound": "mfma", "kernel": "ladder term (assembly GEMM + pack + contraction GEMM)",
+                     "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "ms_per_launch": ms_lad, "flop_per_launch": lad_flops},
+    }
+    if not args.no_eig and args.precision != "fp64":
+        t0 = time.perf_counter()
+        r_mixed = h.davidson(want_vectors=False)
+        t_mixed = time.perf_counter() - t0
+        h64 = adc.Handle("EE", P.o, P.v, P.eps, P.L, k, x=P.x, precision="fp64", conv_tol=1e-7)
+        t0 = time.perf_counter()
+        r64 = h64.davidson(want_vectors=False)
+        t64 = time.perf_counter() - t0
+        out["eigen"] = {"omega_fp64": r64["omega"].tolist(), "omega_mixed": r_mixed["omega"].tolist(),
+                        "max_abs_diff_Eh": float(np.abs(r64["omega"] - r_mixed["omega"]).max()),
+                        "per_root_diff_Eh": np.abs(r64["omega"] - r_mixed["omega"]).tolist(),
+                        "solve_s_mixed": t_mixed, "solve_s_fp64": t64,
+                        "iters_mixed": r_mixed["iters"], "iters_fp64": r64["iters"],
+                        "converged": bool(r_mixed["converged"].all() and r64["converged"].all())}
+        print(f"[bench] davidson mixed {t_mixed:.1f} s fp64 {t64:.1f} s, max |dw| "
+              f"{out['eigen']['max_abs_diff_Eh']:.2e}", file=sys.stderr, flush=True)
+        h64.close()
+    h.close()
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(P, k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

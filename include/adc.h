@@ -8,8 +8,10 @@
  * perturbation order (eq. 11) and, for the x-scaled variant (Section 2.1,
  * sm-ADC), M(x) = M_ADC(2) + x (M_ADC(3) - M_ADC(2)).  Two-electron integrals
  * enter only through complex Cholesky vectors, <pq||rs> = sum_Q (L^Q_pr L^Q_qs
- * - L^Q_ps L^Q_qr) (Section 2.5, eq. 43); <ab||cd> and <ab||ci> are never
- * stored, they are rebuilt batch-wise from L on every sigma build.
+ * - L^Q_ps L^Q_qr) (Section 2.5, eq. 43); the four-external <ab||cd> are
+ * never stored, they are rebuilt batch-wise from L on every sigma build.  The
+ * three-external class <ia||bc> (o v^3 elements) is stored in device memory,
+ * as are all classes with two or more occupied indices.
  *
  * Conventions
  *   - complex numbers are interleaved (re, im) float64 pairs ("c128");
@@ -105,7 +107,7 @@ typedef struct adc_handle adc_handle;
 
 /* Validate the problem, copy eps (and L unless borrowed) to the device and
  * run the one-off work on the device: the stored integral classes <ij||kl>,
- * <ij||ka>, <ij||ab>, <ia||jb>; the MP amplitudes t(1), t(2) (with one pass
+ * <ij||ka>, <ij||ab>, <ia||jb>, <ia||bc>; the MP amplitudes t(1), t(2) (with one pass
  * of the particle-particle ladder), the second-order singles; the dense
  * singles block M11 with its third-order part kept separate so that x scales
  * it.  Errors: INVALID_ARG (shapes, NULL pointers, n_problems != 1),
@@ -137,6 +139,16 @@ int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precis
  * ADC_NOT_CONVERGED if any root missed the criteria. */
 int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs,
                  double* resnorm, int* iters, int* converged);
+
+/* One term of the sigma build, for per-term checks and timing:
+ *   ADC_TERM_ALL      same as adc_sigma
+ *   ADC_TERM_LADDER   S = x * (particle-particle ladder) Y: the doubles part
+ *                     sum_{c<d} <ab||cd> Y_..cd built batch-wise from L
+ *                     (EE and EA; singles part of S set to zero)
+ * Same argument rules as adc_sigma.  Errors: INVALID_ARG, UNSUPPORTED (the
+ * term does not exist for the kind), HIP_ERROR. */
+enum adc_term { ADC_TERM_ALL = 0, ADC_TERM_LADDER = 1 };
+int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, int k, int precision);
 
 /* Vector-Jacobian product of adc_sigma (reserved; returns ADC_ERR_UNSUPPORTED
  * in this version). */

@@ -24,8 +24,9 @@ ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE_INPUT", -3: "NOT_HERMITIAN", -4: "OU
           -5: "HIP_ERROR", -6: "UNSUPPORTED"}
 
 # Every symbol include/adc.h declares.
-EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_davidson", "adc_sigma_backward",
+EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_sigma_term", "adc_davidson", "adc_sigma_backward",
            "adc_init_ms", "adc_free", "adc_strerror"]
+TERMS = {"all": 0, "ladder": 1}
 
 
 class AdcProblem(ctypes.Structure):
@@ -65,6 +66,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                              ctypes.POINTER(ctypes.c_longlong)]
     lib.adc_sigma.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                               ctypes.c_int]
+    lib.adc_sigma_term.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int, ctypes.c_int]
     lib.adc_davidson.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -142,6 +145,20 @@ class Handle:
                                  Y2.shape[0], p)
         if rc != ADC_OK:
             raise AdcError(rc, "adc_sigma")
+        return S.reshape(Y.shape)
+
+    def sigma_term(self, term, Y, S=None, precision=None):
+        """One term of the sigma build (see adc_sigma_term)."""
+        import torch
+        assert Y.is_cuda and Y.dtype == torch.complex128 and Y.is_contiguous() and Y.shape[-1] == self.dim
+        Y2 = Y.reshape(-1, self.dim)
+        if S is None:
+            S = torch.empty_like(Y2)
+        p = -1 if precision is None else PREC[precision]
+        rc = self._lib.adc_sigma_term(self._h, 0, TERMS[term], ctypes.c_void_p(Y2.data_ptr()),
+                                      ctypes.c_void_p(S.data_ptr()), Y2.shape[0], p)
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_sigma_term")
         return S.reshape(Y.shape)
 
     def davidson(self, guess=None, want_vectors=True):

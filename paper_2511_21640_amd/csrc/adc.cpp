@@ -32,6 +32,8 @@ using zc = std::complex<double>;
 
 namespace {
 
+constexpr bool kSplitBf16Built = false;
+
 struct Status {
   int code;
   const char* msg;
@@ -48,6 +50,8 @@ struct Inst {
   Tensor t1;              // [o][o][v][v]
   Tensor M11x;            // n1 x n1, M11(0..2) + x M11(3)
   Tensor W;               // EE: [I][J][i][B] = sum_cd t*_IJcd <cd||iB>
+  Tensor W5;              // EE: [J][A][a][B] = sum_kc conj(t[J,k,A,c]) conj(<kB||ac>)
+  Tensor W6;              // EE: [I][B][J][i] = sum_kc t*_IkBc conj(<ik||Jc>)
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
@@ -124,7 +128,8 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     g.B = I.Lvv.p + (int64_t)b0 * v; g.sbn = 1; g.sbk = (int64_t)v * v; g.sbb = 0;
     g.C = Wbuf; g.scm = g.N; g.scn = 1; g.scb = 0;
     g.alpha = C1(); g.beta = C0();
-    launch_zgemm(g, prec, cx.stream);
+    g.tag = 1;
+    { const int sp = cx.prec; cx.prec = prec; gemm(cx, g); cx.prec = sp; }
     const int64_t pbase = (int64_t)a0 * (2 * v - a0 - 1) / 2;
     const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
     const int64_t np = pend - pbase;
@@ -136,7 +141,8 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     c.B = Vbuf; c.sbk = 1; c.sbn = Pv; c.sbb = 0;
     c.C = S + offS + pbase; c.scm = Pv; c.scn = 1; c.scb = ldS;
     c.alpha = alpha; c.beta = C1();
-    launch_zgemm(c, prec, cx.stream);
+    c.tag = 2;
+    { const int sp = cx.prec; cx.prec = prec; gemm(cx, c); cx.prec = sp; }
   }
   cx.pool.put(Wbuf);
   cx.pool.put(Vbuf);
@@ -153,27 +159,17 @@ void rows_out(Ctx& cx, const Tensor& src, double2* dst, int64_t ld, int64_t off,
 }
 
 // ============================================================================
-// EE
+// one-off work shared by the three kinds
 // ============================================================================
-void ee_m2(Ctx& cx, Inst& I, const Tensor& tt, Tensor& X) {
-  // X[i,a,I,A] += 1/2 t(ikac) <Ik||Ac> - 1/4 d_iI t(klac)<kl||Ac> - 1/4 d_aA t(ikcd)<Ik||cd>
-  const int o = I.o, v = I.v;
-  ctr(cx, CR(0.5), tt, "ikac", false, I.oovv, "IkAc", false, C1(), X, "iaIA");
-  Tensor f = tnew(cx, {v, v});
-  ctr(cx, CR(-0.25), tt, "klac", false, I.oovv, "klAc", false, C0(), f, "aA");
-  launch_m11_add_delta(X.p, f.p, o, v, 0, cx.stream);
-  Tensor hh = tnew(cx, {o, o});
-  ctr(cx, CR(-0.25), tt, "ikcd", false, I.oovv, "Ikcd", false, C0(), hh, "iI");
-  launch_m11_add_delta(X.p, hh.p, o, v, 1, cx.stream);
-  tfree(cx, f);
-  tfree(cx, hh);
-}
+// Stored integral classes (eq. 43): <pq||rs> = (pr|qs) - (ps|qr), the MP
+// amplitudes t(1), t(2) and t_s(2), and the pieces of the singles block.
+struct Pre {
+  Tensor Lt, Ht, t2, ts;       // ladder / hole ladder of t(1), t(2), singles t(2)
+};
 
-void ee_init(adc_handle* h, Inst& I) {
+void init_integrals(adc_handle* h, Inst& I) {
   Ctx& cx = h->cx;
-  const int o = I.o, v = I.v, N = I.N;
-  const int64_t n1 = I.n1;
-  // ---- stored integral classes (eq. 43): <pq||rs> = (pr|qs) - (ps|qr)
+  const int o = I.o, v = I.v;
   I.oooo = tnew(cx, {o, o, o, o}, false);
   ctr(cx, C1(), I.Loo, "Qik", false, I.Loo, "Qjl", false, C0(), I.oooo, "ijkl");
   ctr(cx, CR(-1), I.Loo, "Qil", false, I.Loo, "Qjk", false, C1(), I.oooo, "ijkl");
@@ -189,224 +185,323 @@ void ee_init(adc_handle* h, Inst& I) {
   I.ovvv = tnew(cx, {o, v, v, v}, false);
   ctr(cx, C1(), I.Lov, "Qib", false, I.Lvv, "Qac", false, C0(), I.ovvv, "iabc");
   ctr(cx, CR(-1), I.Lov, "Qic", false, I.Lvv, "Qab", false, C1(), I.ovvv, "iabc");
+  // ring matrix [k][c][j][b] = <kb||jc>  (Hermitian as an (ov) x (ov) matrix)
   I.ring = tnew(cx, {o, v, o, v}, false);
   perm(cx, C1(), I.ovov, "kbjc", false, C0(), I.ring, "kcjb");
-  (void)N;
+}
 
-  // ---- first-order doubles t_ij^ab = <ab||ij>/D = conj(<ij||ab>)/D
+void init_amplitudes(adc_handle* h, Inst& I, Pre& P) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v;
+  // first-order doubles t_ij^ab = <ab||ij>/D = conj(<ij||ab>)/D
   Tensor& t = I.t1;
   t = tnew(cx, {o, o, v, v}, false);
   perm(cx, C1(), I.oovv, "ijab", true, C0(), t, "ijab");
   launch_div_d2(t.p, I.eps, o, v, cx.stream);
-
-  // ---- second-order doubles: (ladder + hole ladder - ring) / D
+  // second-order doubles: (particle ladder + hole ladder - ring) / D
   const int64_t Po = I.Po, Pv = I.Pv;
-  Tensor tpk = tnew(cx, {Po * Pv}, false);
-  launch_pack_doubles(0, t.p, tpk.p, nullptr, Po * Pv, 0, 1, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
-  Tensor Ltp = tnew(cx, {Po * Pv});
-  ladder(h, I, tpk.p, Po * Pv, 0, Ltp.p, Po * Pv, 0, Po, 1, C1(), 0);
-  Tensor Lt = tnew(cx, {o, o, v, v}, false);
-  launch_unpack_doubles(0, Ltp.p, Po * Pv, 0, 1, o, v, Lt.p, nullptr, cx.stream);
-  tfree(cx, Ltp);
-  tfree(cx, tpk);
-  Tensor Ht = tnew(cx, {o, o, v, v}, false);
-  ctr(cx, CR(0.5), I.oooo, "klij", false, t, "klab", false, C0(), Ht, "ijab");
-  Tensor t2 = tnew(cx, {o, o, v, v}, false);
-  perm(cx, C1(), Lt, "ijab", false, C0(), t2, "ijab");
-  perm(cx, C1(), Ht, "ijab", false, C1(), t2, "ijab");
+  P.Lt = tnew(cx, {o, o, v, v}, true);
+  if (Po > 0) {
+    Tensor tpk = tnew(cx, {Po * Pv}, false);
+    launch_pack_doubles(0, t.p, tpk.p, nullptr, Po * Pv, 0, 1, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+    Tensor Ltp = tnew(cx, {Po * Pv});
+    ladder(h, I, tpk.p, Po * Pv, 0, Ltp.p, Po * Pv, 0, Po, 1, C1(), 0);
+    launch_unpack_doubles(0, Ltp.p, Po * Pv, 0, 1, o, v, P.Lt.p, nullptr, cx.stream);
+    tfree(cx, Ltp);
+    tfree(cx, tpk);
+  }
+  P.Ht = tnew(cx, {o, o, v, v}, false);
+  ctr(cx, CR(0.5), I.oooo, "klij", false, t, "klab", false, C0(), P.Ht, "ijab");
+  P.t2 = tnew(cx, {o, o, v, v}, false);
+  perm(cx, C1(), P.Lt, "ijab", false, C0(), P.t2, "ijab");
+  perm(cx, C1(), P.Ht, "ijab", false, C1(), P.t2, "ijab");
   {
     Tensor R = tnew(cx, {o, v, o, v}, false);
     ctr(cx, C1(), t, "ikac", false, I.ovov, "kbjc", false, C0(), R, "iajb");
     Tensor Rr = tnew(cx, {o, o, v, v}, false);
     perm(cx, C1(), R, "iajb", false, C0(), Rr, "ijab");
-    launch_antisym_add(Rr.p, t2.p, 1, o, o, v, v, 2, CR(-1), cx.stream);
+    launch_antisym_add(Rr.p, P.t2.p, 1, o, o, v, v, 2, CR(-1), cx.stream);
     tfree(cx, R);
     tfree(cx, Rr);
   }
-  launch_div_d2(t2.p, I.eps, o, v, cx.stream);
+  launch_div_d2(P.t2.p, I.eps, o, v, cx.stream);
+  // second-order singles
+  P.ts = tnew(cx, {o, v});
+  ctr(cx, CR(-0.5), I.ovvv, "jabc", false, t, "ijbc", false, C0(), P.ts, "ia");
+  ctr(cx, CR(-0.5), I.ooov, "jkib", false, t, "jkab", false, C1(), P.ts, "ia");
+  launch_div_d1(P.ts.p, I.eps, o, v, cx.stream);
+}
 
-  // ---- second-order singles
-  Tensor ts = tnew(cx, {o, v});
-  ctr(cx, CR(-0.5), I.ovvv, "jabc", false, t, "ijbc", false, C0(), ts, "ia");
-  ctr(cx, CR(-0.5), I.ooov, "jkib", false, t, "jkab", false, C1(), ts, "ia");
-  launch_div_d1(ts.p, I.eps, o, v, cx.stream);
+// Pieces of M11 that carry delta_aA (f_o, occupied x occupied) and delta_iI
+// (f_v, virtual x virtual), split by order: second order (f2) and third order
+// (f3).  The IP singles block is f_o, the EA singles block f_v, and the EE
+// singles block contains both (see ee_m11).
+void m11_fo(adc_handle* h, Inst& I, Pre& P, Tensor& f2, Tensor& f3) {
+  Ctx& cx = h->cx;
+  const int o = I.o;
+  const Tensor& t = I.t1;
+  f2 = tnew(cx, {o, o});
+  f3 = tnew(cx, {o, o});
+  // -1/4 t(ikcd) <Ik||cd>  (order 2 with t(1), order 3 with t(2))
+  ctr(cx, CR(-0.25), t, "ikcd", false, I.oovv, "Ikcd", false, C0(), f2, "iI");
+  ctr(cx, CR(-0.25), P.t2, "ikcd", false, I.oovv, "Ikcd", false, C1(), f3, "iI");
+  // -ts(kc) <Ik||ic>
+  ctr(cx, CR(-1), P.ts, "kc", false, I.ooov, "Ikic", false, C1(), f3, "iI");
+  // -1/2 t*(Ikcd) Q(cikd), Q = -<lc||ie> t(klde)
+  {
+    Tensor Q = tnew(cx, {I.v, o, o, I.v}, false);
+    ctr(cx, CR(-1), I.ovov, "lcie", false, t, "klde", false, C0(), Q, "cikd");
+    ctr(cx, CR(-0.5), t, "Ikcd", true, Q, "cikd", false, C1(), f3, "iI");
+    tfree(cx, Q);
+  }
+  // -1/4 t*(Ikcd) Ht(ikcd)
+  ctr(cx, CR(-0.25), t, "Ikcd", true, P.Ht, "ikcd", false, C1(), f3, "iI");
+  // +1/4 <Ic||ie> rv_ce ; -1/4 <Im||ik> ro_km
+  Tensor rv = tnew(cx, {I.v, I.v}, false), ro = tnew(cx, {o, o}, false);
+  ctr(cx, C1(), t, "klcd", true, t, "klde", false, C0(), rv, "ce");
+  ctr(cx, C1(), t, "klcd", true, t, "lmcd", false, C0(), ro, "km");
+  ctr(cx, CR(0.25), I.ovov, "Icie", false, rv, "ce", false, C1(), f3, "iI");
+  ctr(cx, CR(-0.25), I.oooo, "Imik", false, ro, "km", false, C1(), f3, "iI");
+  tfree(cx, rv);
+  tfree(cx, ro);
+}
 
-  // ---- M11: order 0..2 (A) and third order (B)
+void m11_fv(adc_handle* h, Inst& I, Pre& P, Tensor& f2, Tensor& f3) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v, N = I.N;
+  const Tensor& t = I.t1;
+  f2 = tnew(cx, {v, v});
+  f3 = tnew(cx, {v, v});
+  // -1/4 t(klac) <kl||Ac>
+  ctr(cx, CR(-0.25), t, "klac", false, I.oovv, "klAc", false, C0(), f2, "aA");
+  ctr(cx, CR(-0.25), P.t2, "klac", false, I.oovv, "klAc", false, C1(), f3, "aA");
+  // +ts(kc) <ak||Ac>, <ak||Ac> = -ovvv[k,a,A,c]
+  ctr(cx, CR(-1), P.ts, "kc", false, I.ovvv, "kaAc", false, C1(), f3, "aA");
+  // -1/4 t*(klAc) Lt(klac)
+  ctr(cx, CR(-0.25), t, "klAc", true, P.Lt, "klac", false, C1(), f3, "aA");
+  // -1/2 t*(klAc) P2(aklc), P2 = -<ma||kd> t(lmcd)
+  {
+    Tensor P2 = tnew(cx, {v, o, o, v}, false);
+    ctr(cx, CR(-1), I.ovov, "makd", false, t, "lmcd", false, C0(), P2, "aklc");
+    ctr(cx, CR(-0.5), t, "klAc", true, P2, "aklc", false, C1(), f3, "aA");
+    tfree(cx, P2);
+  }
+  // -1/4 rv_ce <ac||Ae>,  <ac||Ae> = (aA|ce) - (ae|cA), through the Cholesky vectors
+  Tensor rv = tnew(cx, {v, v}, false), ro = tnew(cx, {o, o}, false);
+  ctr(cx, C1(), t, "klcd", true, t, "klde", false, C0(), rv, "ce");
+  ctr(cx, C1(), t, "klcd", true, t, "lmcd", false, C0(), ro, "km");
+  {
+    Tensor s1 = tnew(cx, {N, 1}, false);
+    Tensor rv1 = tensor_view(rv.p, {v, v, 1}, {});
+    ctr(cx, C1(), I.Lvv, "Qce", false, rv1, "cex", false, C0(), s1, "Qx");
+    Tensor f31 = tensor_view(f3.p, {v, v, 1}, {});
+    ctr(cx, CR(-0.25), I.Lvv, "QaA", false, s1, "Qx", false, C1(), f31, "aAx");
+    Tensor Z = tnew(cx, {N, v, v}, false);
+    ctr(cx, C1(), rv, "ce", false, I.Lvv, "QcA", false, C0(), Z, "QeA");
+    ctr(cx, CR(0.25), I.Lvv, "Qae", false, Z, "QeA", false, C1(), f3, "aA");
+    tfree(cx, s1);
+    tfree(cx, Z);
+  }
+  // +1/4 <am||Ak> ro_km,  <am||Ak> = ovov[m,a,k,A]
+  ctr(cx, CR(0.25), I.ovov, "makA", false, ro, "km", false, C1(), f3, "aA");
+  tfree(cx, rv);
+  tfree(cx, ro);
+}
+
+// dense n x n block: herm(f) + diag(d) for IP / EA
+void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector<double>& d) {
+  Ctx& cx = h->cx;
+  const int64_t n1 = I.n1;
+  Tensor MA = tnew(cx, {n1, n1}, false), MB = tnew(cx, {n1, n1}, false);
+  launch_herm_add(f2.p, MA.p, n1, cx.stream);
+  launch_herm_add(f3.p, MB.p, n1, cx.stream);
+  double* dd = (double*)cx.pool.get(n1);
+  hipcheck(hipMemcpyAsync(dd, d.data(), sizeof(double) * n1, hipMemcpyHostToDevice, cx.stream), "d1");
+  launch_add_diag(MA.p, dd, n1, cx.stream);
+  I.M11x = tnew(cx, {n1, n1}, false);
+  perm(cx, C1(), MA, "pq", false, C0(), I.M11x, "pq");
+  perm(cx, CR(I.x), MB, "pq", false, C1(), I.M11x, "pq");
+  hipcheck(hipStreamSynchronize(cx.stream), "m11 sync");
+  cx.pool.put((double2*)dd);
+  tfree(cx, MA);
+  tfree(cx, MB);
+}
+
+// ============================================================================
+// EE
+// ============================================================================
+void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v, N = I.N;
+  const int64_t n1 = I.n1;
+  const Tensor& t = I.t1;
+  Tensor fo2, fo3, fv2, fv3;
+  m11_fo(h, I, P, fo2, fo3);
+  m11_fv(h, I, P, fv2, fv3);
+  // order <= 2: X2 = 1/2 t(ikac) <Ik||Ac> + delta parts; M11 = herm(X) + M11(1) + M11(0)
   Tensor X2 = tnew(cx, {o, v, o, v});
-  ee_m2(cx, I, t, X2);
+  ctr(cx, CR(0.5), t, "ikac", false, I.oovv, "IkAc", false, C1(), X2, "iaIA");
+  launch_m11_add_delta(X2.p, fv2.p, o, v, 0, cx.stream);
+  launch_m11_add_delta(X2.p, fo2.p, o, v, 1, cx.stream);
   Tensor MA = tnew(cx, {n1, n1}, false);
   launch_herm_add(X2.p, MA.p, n1, cx.stream);
   {
-    // + M11(1) = <aj||ib> = -<ja||ib>
     Tensor MAv = tensor_view(MA.p, {o, v, o, v}, {});
-    perm(cx, CR(-1), I.ovov, "jaib", false, C1(), MAv, "iajb");
-  }
-  // zeroth order diagonal
-  {
+    perm(cx, CR(-1), I.ovov, "jaib", false, C1(), MAv, "iajb");   // <aj||ib> = -<ja||ib>
     std::vector<double> d1(n1);
-    std::vector<double> e(o + v);
-    hipcheck(hipMemcpy(e.data(), I.eps, sizeof(double) * (o + v), hipMemcpyDeviceToHost), "eps");
     for (int i = 0; i < o; ++i)
-      for (int a = 0; a < v; ++a) d1[(int64_t)i * v + a] = e[o + a] - e[i];
-    double* dd = (double*)h->cx.pool.get((n1 + 1) / 2 + 1);
-    hipcheck(hipMemcpy(dd, d1.data(), sizeof(double) * n1, hipMemcpyHostToDevice), "d1");
+      for (int a = 0; a < v; ++a) d1[(int64_t)i * v + a] = eps_h[o + a] - eps_h[i];
+    double* dd = (double*)cx.pool.get(n1);
+    hipcheck(hipMemcpyAsync(dd, d1.data(), sizeof(double) * n1, hipMemcpyHostToDevice, cx.stream), "d1");
     launch_add_diag(MA.p, dd, n1, cx.stream);
     hipcheck(hipStreamSynchronize(cx.stream), "sync");
-    h->cx.pool.put((double2*)dd);
+    cx.pool.put((double2*)dd);
   }
+  // third order
   Tensor X = tnew(cx, {o, v, o, v});
-  ee_m2(cx, I, t2, X);
-  Tensor fv = tnew(cx, {v, v}), fo = tnew(cx, {o, o});
+  const Tensor& ov4 = I.ovov;
+  ctr(cx, CR(0.5), P.t2, "ikac", false, I.oovv, "IkAc", false, C1(), X, "iaIA");
+  // -ts(ic)<aI||Ac>, <aI||Ac> = -ovvv[I,a,A,c] ; +ts(ka)<Ik||iA>
+  ctr(cx, C1(), P.ts, "ic", false, I.ovvv, "IaAc", false, C1(), X, "iaIA");
+  ctr(cx, C1(), P.ts, "ka", false, I.ooov, "IkiA", false, C1(), X, "iaIA");
+  // 1/2 t*(IkAc) (Lt + Ht)(ikac)
+  ctr(cx, CR(0.5), t, "IkAc", true, P.Lt, "ikac", false, C1(), X, "iaIA");
+  ctr(cx, CR(0.5), t, "IkAc", true, P.Ht, "ikac", false, C1(), X, "iaIA");
   {
-    const Tensor& ov4 = I.ovov;
-    // T1 -ts(ic)<aI||Ac>, <aI||Ac> = -ovvv[I,a,A,c]
-    ctr(cx, C1(), ts, "ic", false, I.ovvv, "IaAc", false, C1(), X, "iaIA");
-    // T2 +ts(ka)<Ik||iA>
-    ctr(cx, C1(), ts, "ka", false, I.ooov, "IkiA", false, C1(), X, "iaIA");
-    // T3 +d_iI ts(kc)<ak||Ac>, <ak||Ac> = -ovvv[k,a,A,c]
-    ctr(cx, CR(-1), ts, "kc", false, I.ovvv, "kaAc", false, C1(), fv, "aA");
-    // T4 -d_aA ts(kc)<Ik||ic>
-    ctr(cx, CR(-1), ts, "kc", false, I.ooov, "Ikic", false, C1(), fo, "iI");
-    // T5 + T8: 1/2 t*(IkAc) (Lt + Ht)(ikac)
-    ctr(cx, CR(0.5), t, "IkAc", true, Lt, "ikac", false, C1(), X, "iaIA");
-    ctr(cx, CR(0.5), t, "IkAc", true, Ht, "ikac", false, C1(), X, "iaIA");
-    // T6 -1/2 t*(IkAc) sum_ld <al||kd> t(ilcd), <al||kd> = -ovov[l,a,k,d]
-    {
-      Tensor P = tnew(cx, {o, v, o, v}, false);
-      ctr(cx, CR(-1), ov4, "lakd", false, t, "ilcd", false, C0(), P, "iakc");
-      ctr(cx, CR(-0.5), t, "IkAc", true, P, "iakc", false, C1(), X, "iaIA");
-      // T7 -1/2 t*(IkAc) sum_ld <cl||id> t(klad), <cl||id> = -ovov[l,c,i,d]
-      Tensor P2 = tnew(cx, {o, o, v, v}, false);
-      ctr(cx, CR(-1), ov4, "lcid", false, t, "klad", false, C0(), P2, "ikca");
-      ctr(cx, CR(-0.5), t, "IkAc", true, P2, "ikca", false, C1(), X, "iaIA");
-      tfree(cx, P);
-      tfree(cx, P2);
-    }
-    // T9  +1/2 t*(Ikcd) <ac||Ae> t(ikde) and T18 -1/4 d_iI rho_ce <ac||Ae>,
-    // <ac||Ae> = (aA|ce) - (ae|cA)
+    // -1/2 t*(IkAc) P(iakc), P = -<la||kd> t(ilcd)
+    Tensor Pq = tnew(cx, {o, v, o, v}, false);
+    ctr(cx, CR(-1), ov4, "lakd", false, t, "ilcd", false, C0(), Pq, "iakc");
+    ctr(cx, CR(-0.5), t, "IkAc", true, Pq, "iakc", false, C1(), X, "iaIA");
+    // -1/2 t*(IkAc) P2(ikca), P2 = -<lc||id> t(klad)
+    Tensor P2 = tnew(cx, {o, o, v, v}, false);
+    ctr(cx, CR(-1), ov4, "lcid", false, t, "klad", false, C0(), P2, "ikca");
+    ctr(cx, CR(-0.5), t, "IkAc", true, P2, "ikca", false, C1(), X, "iaIA");
+    tfree(cx, Pq);
+    tfree(cx, P2);
+  }
+  {
+    // +1/2 t*(Ikcd) <ac||Ae> t(ikde), <ac||Ae> = (aA|ce) - (ae|cA);  R_Iice = t*(Ikcd) t(ikde)
     Tensor Rr = tnew(cx, {o, o, v, v}, false);
     ctr(cx, C1(), t, "Ikcd", true, t, "ikde", false, C0(), Rr, "Iice");
-    Tensor rv = tnew(cx, {v, v}, false);
-    ctr(cx, C1(), t, "klcd", true, t, "klde", false, C0(), rv, "ce");
-    {
-      Tensor sQ = tnew(cx, {N, o, o}, false);
-      ctr(cx, C1(), I.Lvv, "Qce", false, Rr, "Iice", false, C0(), sQ, "QIi");
-      ctr(cx, CR(0.5), I.Lvv, "QaA", false, sQ, "QIi", false, C1(), X, "iaIA");
-      Tensor s1 = tnew(cx, {N, 1}, false);
-      Tensor rv1 = tensor_view(rv.p, {v, v, 1}, {});
-      ctr(cx, C1(), I.Lvv, "Qce", false, rv1, "cex", false, C0(), s1, "Qx");
-      Tensor fv1 = tensor_view(fv.p, {v, v, 1}, {});
-      ctr(cx, CR(-0.25), I.Lvv, "QaA", false, s1, "Qx", false, C1(), fv1, "aAx");
-      tfree(cx, sQ);
-      tfree(cx, s1);
-      // (ae|cA) pieces in chunks of a
-      const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
-      int64_t na = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
-      na = std::min<int64_t>(na, v);
-      Tensor G = tnew(cx, {na, v, v, v}, false);
-      for (int64_t a0 = 0; a0 < v; a0 += na) {
-        const int64_t a1 = std::min<int64_t>(v, a0 + na);
-        Tensor Gs = tslice(G, 0, 0, a1 - a0);
-        Tensor Ls = tslice(I.Lvv, 1, a0, a1);
-        ctr(cx, C1(), Ls, "Qae", false, I.Lvv, "QcA", false, C0(), Gs, "aecA");
-        Tensor Xs = tslice(X, 1, a0, a1);
-        ctr(cx, CR(-0.5), Gs, "aecA", false, Rr, "Iice", false, C1(), Xs, "iaIA");
-        Tensor fvs = tslice(fv, 0, a0, a1);
-        ctr(cx, CR(0.25), Gs, "aecA", false, rv, "ce", false, C1(), fvs, "aA");
-      }
-      tfree(cx, G);
+    Tensor sQ = tnew(cx, {N, o, o}, false);
+    ctr(cx, C1(), I.Lvv, "Qce", false, Rr, "Iice", false, C0(), sQ, "QIi");
+    ctr(cx, CR(0.5), I.Lvv, "QaA", false, sQ, "QIi", false, C1(), X, "iaIA");
+    tfree(cx, sQ);
+    const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
+    int64_t na = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
+    na = std::min<int64_t>(na, v);
+    Tensor G = tnew(cx, {na, v, v, v}, false);
+    for (int64_t a0 = 0; a0 < v; a0 += na) {
+      const int64_t a1 = std::min<int64_t>(v, a0 + na);
+      Tensor Gs = tslice(G, 0, 0, a1 - a0);
+      Tensor Ls = tslice(I.Lvv, 1, a0, a1);
+      ctr(cx, C1(), Ls, "Qae", false, I.Lvv, "QcA", false, C0(), Gs, "aecA");
+      Tensor Xs = tslice(X, 1, a0, a1);
+      ctr(cx, CR(-0.5), Gs, "aecA", false, Rr, "Iice", false, C1(), Xs, "iaIA");
     }
+    tfree(cx, G);
     tfree(cx, Rr);
-    // T10 +1/4 <al||iA> A_Il, A_Il = t*(Ikcd) t(klcd); <al||iA> = -ovov[l,a,i,A]
+  }
+  {
+    // +1/4 <al||iA> A_Il, A = t*(Ikcd) t(klcd); <al||iA> = -ovov[l,a,i,A]
     Tensor Ao = tnew(cx, {o, o}, false);
     ctr(cx, C1(), t, "Ikcd", true, t, "klcd", false, C0(), Ao, "Il");
     ctr(cx, CR(-0.25), ov4, "laiA", false, Ao, "Il", false, C1(), X, "iaIA");
     tfree(cx, Ao);
-    // T11 +1/4 <al||Ak> B_Iikl, B = t*(Ikcd) t(ilcd); <al||Ak> = ovov[l,a,k,A]
-    {
-      Tensor Bo = tnew(cx, {o, o, o, o}, false);
-      ctr(cx, C1(), t, "Ikcd", true, t, "ilcd", false, C0(), Bo, "Iikl");
-      ctr(cx, CR(0.25), ov4, "lakA", false, Bo, "Iikl", false, C1(), X, "iaIA");
-      tfree(cx, Bo);
-    }
-    // T12 -t*(Ikcd) <cl||iA> t(klad); <cl||iA> = -ovov[l,c,i,A]
-    {
-      Tensor E = tnew(cx, {o, v, o, v}, false);
-      ctr(cx, C1(), t, "Ikcd", true, t, "klad", false, C0(), E, "Icla");
-      ctr(cx, C1(), ov4, "lciA", false, E, "Icla", false, C1(), X, "iaIA");
-      tfree(cx, E);
-    }
-    // T13 +1/4 <aI||id> F_Ad, F = t*(klAc) t(klcd); <aI||id> = -ovov[I,a,i,d]
-    {
-      Tensor F = tnew(cx, {v, v}, false);
-      ctr(cx, C1(), t, "klAc", true, t, "klcd", false, C0(), F, "Ad");
-      ctr(cx, CR(-0.25), ov4, "Iaid", false, F, "Ad", false, C1(), X, "iaIA");
-      tfree(cx, F);
-    }
-    // T14 +1/4 <Ic||id> G_Acad, G = t*(klAc) t(klad), chunks of A
-    {
-      const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
-      int64_t nA = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
-      nA = std::min<int64_t>(nA, v);
-      Tensor G = tnew(cx, {nA, v, v, v}, false);
-      for (int64_t A0 = 0; A0 < v; A0 += nA) {
-        const int64_t A1 = std::min<int64_t>(v, A0 + nA);
-        Tensor Gs = tslice(G, 0, 0, A1 - A0);
-        Tensor ts_ = tslice(t, 2, A0, A1);
-        ctr(cx, C1(), ts_, "klAc", true, t, "klad", false, C0(), Gs, "Acad");
-        Tensor Xs = tslice(X, 3, A0, A1);
-        ctr(cx, CR(0.25), ov4, "Icid", false, Gs, "Acad", false, C1(), Xs, "iaIA");
-      }
-      tfree(cx, G);
-    }
-    // T15 +1/2 <Im||ik> N_kAma, N = t*(klAc) t(lmac)
-    {
-      Tensor Nn = tnew(cx, {o, v, o, v}, false);
-      ctr(cx, C1(), t, "klAc", true, t, "lmac", false, C0(), Nn, "kAma");
-      ctr(cx, CR(0.5), I.oooo, "Imik", false, Nn, "kAma", false, C1(), X, "iaIA");
-      tfree(cx, Nn);
-    }
-    // T16 -1/4 d_iI t*(klAc) Lt(klac)
-    ctr(cx, CR(-0.25), t, "klAc", true, Lt, "klac", false, C1(), fv, "aA");
-    // T17 -1/2 d_iI t*(klAc) P2(aklc), P2 = -<ma||kd> t(lmcd)
-    {
-      Tensor P = tnew(cx, {v, o, o, v}, false);
-      ctr(cx, CR(-1), ov4, "makd", false, t, "lmcd", false, C0(), P, "aklc");
-      ctr(cx, CR(-0.5), t, "klAc", true, P, "aklc", false, C1(), fv, "aA");
-      tfree(cx, P);
-    }
-    // T19 +1/4 d_iI <am||Ak> ro_km; ro = t*(klcd) t(lmcd); <am||Ak> = ovov[m,a,k,A]
-    Tensor ro = tnew(cx, {o, o}, false);
-    ctr(cx, C1(), t, "klcd", true, t, "lmcd", false, C0(), ro, "km");
-    ctr(cx, CR(0.25), ov4, "makA", false, ro, "km", false, C1(), fv, "aA");
-    // T20 -1/2 d_aA t*(Ikcd) Q(cikd), Q = -<lc||ie> t(klde)
-    {
-      Tensor Q = tnew(cx, {v, o, o, v}, false);
-      ctr(cx, CR(-1), ov4, "lcie", false, t, "klde", false, C0(), Q, "cikd");
-      ctr(cx, CR(-0.5), t, "Ikcd", true, Q, "cikd", false, C1(), fo, "iI");
-      tfree(cx, Q);
-    }
-    // T21 -1/4 d_aA t*(Ikcd) Ht(ikcd)
-    ctr(cx, CR(-0.25), t, "Ikcd", true, Ht, "ikcd", false, C1(), fo, "iI");
-    // T22 +1/4 d_aA <Ic||ie> rv_ce
-    ctr(cx, CR(0.25), ov4, "Icie", false, rv, "ce", false, C1(), fo, "iI");
-    // T23 -1/4 d_aA <Im||ik> ro_km
-    ctr(cx, CR(-0.25), I.oooo, "Imik", false, ro, "km", false, C1(), fo, "iI");
-    tfree(cx, rv);
-    tfree(cx, ro);
+    // +1/4 <al||Ak> B_Iikl, B = t*(Ikcd) t(ilcd); <al||Ak> = ovov[l,a,k,A]
+    Tensor Bo = tnew(cx, {o, o, o, o}, false);
+    ctr(cx, C1(), t, "Ikcd", true, t, "ilcd", false, C0(), Bo, "Iikl");
+    ctr(cx, CR(0.25), ov4, "lakA", false, Bo, "Iikl", false, C1(), X, "iaIA");
+    tfree(cx, Bo);
+    // -t*(Ikcd) <cl||iA> t(klad); <cl||iA> = -ovov[l,c,i,A]
+    Tensor Eo = tnew(cx, {o, v, o, v}, false);
+    ctr(cx, C1(), t, "Ikcd", true, t, "klad", false, C0(), Eo, "Icla");
+    ctr(cx, C1(), ov4, "lciA", false, Eo, "Icla", false, C1(), X, "iaIA");
+    tfree(cx, Eo);
+    // +1/4 <aI||id> F_Ad, F = t*(klAc) t(klcd); <aI||id> = -ovov[I,a,i,d]
+    Tensor F = tnew(cx, {v, v}, false);
+    ctr(cx, C1(), t, "klAc", true, t, "klcd", false, C0(), F, "Ad");
+    ctr(cx, CR(-0.25), ov4, "Iaid", false, F, "Ad", false, C1(), X, "iaIA");
+    tfree(cx, F);
   }
-  launch_m11_add_delta(X.p, fv.p, o, v, 0, cx.stream);
-  launch_m11_add_delta(X.p, fo.p, o, v, 1, cx.stream);
+  {
+    // +1/4 <Ic||id> G_Acad, G = t*(klAc) t(klad), in chunks of A
+    const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
+    int64_t nA = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
+    nA = std::min<int64_t>(nA, v);
+    Tensor G = tnew(cx, {nA, v, v, v}, false);
+    for (int64_t A0 = 0; A0 < v; A0 += nA) {
+      const int64_t A1 = std::min<int64_t>(v, A0 + nA);
+      Tensor Gs = tslice(G, 0, 0, A1 - A0);
+      Tensor ts_ = tslice(t, 2, A0, A1);
+      ctr(cx, C1(), ts_, "klAc", true, t, "klad", false, C0(), Gs, "Acad");
+      Tensor Xs = tslice(X, 3, A0, A1);
+      ctr(cx, CR(0.25), ov4, "Icid", false, Gs, "Acad", false, C1(), Xs, "iaIA");
+    }
+    tfree(cx, G);
+  }
+  {
+    // +1/2 <Im||ik> N_kAma, N = t*(klAc) t(lmac)
+    Tensor Nn = tnew(cx, {o, v, o, v}, false);
+    ctr(cx, C1(), t, "klAc", true, t, "lmac", false, C0(), Nn, "kAma");
+    ctr(cx, CR(0.5), I.oooo, "Imik", false, Nn, "kAma", false, C1(), X, "iaIA");
+    tfree(cx, Nn);
+  }
+  launch_m11_add_delta(X.p, fv3.p, o, v, 0, cx.stream);
+  launch_m11_add_delta(X.p, fo3.p, o, v, 1, cx.stream);
   Tensor MB = tnew(cx, {n1, n1}, false);
   launch_herm_add(X.p, MB.p, n1, cx.stream);
   I.M11x = tnew(cx, {n1, n1}, false);
   perm(cx, C1(), MA, "pq", false, C0(), I.M11x, "pq");
   perm(cx, CR(I.x), MB, "pq", false, C1(), I.M11x, "pq");
-  for (Tensor* p : {&X2, &MA, &X, &MB, &fv, &fo, &Lt, &Ht, &t2, &ts}) tfree(cx, *p);
-
-  // ---- coupling intermediate W_IJiB = sum_cd t*_IJcd <cd||iB>,  <cd||iB> = conj(ovvv[i,B,c,d])
+  for (Tensor* p : {&X2, &MA, &X, &MB, &fo2, &fo3, &fv2, &fv3}) tfree(cx, *p);
+  // coupling intermediates, independent of the trial vectors:
+  // W[I,J,i,B]  = sum_cd conj(t[I,J,c,d]) conj(<iB||cd>)
+  // W5[J,A,a,B] = sum_kc conj(t[J,k,A,c]) conj(<kB||ac>)
+  // W6[I,B,J,i] = sum_kc conj(t[I,k,B,c]) conj(<ik||Jc>)
   I.W = tnew(cx, {o, o, o, v}, false);
   ctr(cx, C1(), t, "IJcd", true, I.ovvv, "iBcd", true, C0(), I.W, "IJiB");
+  I.W5 = tnew(cx, {o, v, v, v}, false);
+  ctr(cx, C1(), t, "JkAc", true, I.ovvv, "kBac", true, C0(), I.W5, "JAaB");
+  I.W6 = tnew(cx, {o, v, o, o}, false);
+  ctr(cx, C1(), t, "IkBc", true, I.ooov, "ikJc", true, C0(), I.W6, "IBJi");
+}
+
+// ============================================================================
+// IP and EA one-off work
+// ============================================================================
+void ip_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
+  Ctx& cx = h->cx;
+  const int o = I.o;
+  Tensor f2, f3;
+  m11_fo(h, I, P, f2, f3);
+  std::vector<double> d(o);
+  for (int i = 0; i < o; ++i) d[i] = -eps_h[i];
+  small_m11(h, I, f2, f3, d);
+  tfree(cx, f2);
+  tfree(cx, f3);
+  const Tensor& t = I.t1;
+  I.W = tnew(cx, {o, o, o, I.v}, false);
+  ctr(cx, C1(), t, "IJcd", true, I.ovvv, "iBcd", true, C0(), I.W, "IJiB");
+  I.W6 = tnew(cx, {o, I.v, o, o}, false);
+  ctr(cx, C1(), t, "IkBc", true, I.ooov, "ikJc", true, C0(), I.W6, "IBJi");
+  // the sigma build of IP needs no three-external integrals
+  tfree(cx, I.ovvv);
+}
+
+void ea_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v;
+  Tensor f2, f3;
+  m11_fv(h, I, P, f2, f3);
+  std::vector<double> d(v);
+  for (int a = 0; a < v; ++a) d[a] = eps_h[o + a];
+  small_m11(h, I, f2, f3, d);
+  tfree(cx, f2);
+  tfree(cx, f3);
+  const Tensor& t = I.t1;
+  I.W5 = tnew(cx, {o, v, v, v}, false);
+  ctr(cx, C1(), t, "JkAc", true, I.ovvv, "kBac", true, C0(), I.W5, "JAaB");
 }
 
 void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
@@ -446,19 +541,13 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, C1(), t, "IkAB", true, Ya, "zIJAB", false, C0(), r2, "zkJ");
     ctr(cx, CR(0.5 * x), I.ooov, "ikJa", true, r2, "zkJ", false, C1(), s1, "zia");
     tfree(cx, r2);
-    Tensor Vv = tnew(cx, {k, o, o, v, v}, false);
-    ctr(cx, C1(), t, "JkAc", true, Ya, "ziJAB", false, C0(), Vv, "zikcB");
-    ctr(cx, CR(x), I.ovvv, "kBac", true, Vv, "zikcB", false, C1(), s1, "zia");
-    tfree(cx, Vv);
+    ctr(cx, CR(x), I.W5, "JAaB", false, Ya, "ziJAB", false, C1(), s1, "zia");
     Tensor V2 = tnew(cx, {k, o, o, o, o}, false);
     ctr(cx, C1(), t, "klAB", true, Ya, "ziJAB", false, C0(), V2, "ziJkl");
     ctr(cx, CR(-0.25 * x), I.ooov, "klJa", true, V2, "ziJkl", false, C1(), s1, "zia");
     tfree(cx, V2);
     ctr(cx, CR(-0.25 * x), I.W, "IJiB", false, Ya, "zIJaB", false, C1(), s1, "zia");
-    Tensor V4 = tnew(cx, {k, o, v, o, v}, false);
-    ctr(cx, C1(), t, "IkBc", true, Ya, "zIJaB", false, C0(), V4, "zkcJa");
-    ctr(cx, CR(x), I.ooov, "ikJc", true, V4, "zkcJa", false, C1(), s1, "zia");
-    tfree(cx, V4);
+    ctr(cx, CR(x), I.W6, "IBJi", false, Ya, "zIJaB", false, C1(), s1, "zia");
   }
   // ---------------- doubles output (unpacked)
   Tensor s2 = tnew(cx, {k, o, o, v, v});
@@ -486,14 +575,8 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       ctr(cx, CR(-0.5), t, "klAB", false, Z4, "zklJI", false, C1(), T, "zIJAB");
       tfree(cx, Z4);
       launch_antisym_add(T.p, s2.p, k, o, o, v, v, 0, CR(x), cx.stream);
-      Tensor Z3 = tnew(cx, {k, o, v, v, o}, false);
-      ctr(cx, C1(), I.ovvv, "kBac", false, ys, "zIa", false, C0(), Z3, "zkBcI");
-      ctr(cx, C1(), t, "JkAc", false, Z3, "zkBcI", false, C0(), T, "zIJAB");
-      tfree(cx, Z3);
-      Tensor Z5 = tnew(cx, {k, o, o, v, v}, false);
-      ctr(cx, C1(), I.ooov, "ikJc", false, ys, "ziA", false, C0(), Z5, "zkJcA");
-      ctr(cx, C1(), t, "IkBc", false, Z5, "zkJcA", false, C1(), T, "zIJAB");
-      tfree(cx, Z5);
+      ctr(cx, C1(), I.W5, "JAaB", true, ys, "zIa", false, C0(), T, "zIJAB");
+      ctr(cx, C1(), I.W6, "IBJi", true, ys, "ziA", false, C1(), T, "zIJAB");
       launch_antisym_add(T.p, s2.p, k, o, o, v, v, 2, CR(x), cx.stream);
       // M22(1): hole ladder and ring (the particle ladder runs packed below)
       ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), s2, "zijab");
@@ -508,6 +591,100 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // pack doubles: S2 = extract(s2) + D o Y2
   launch_pack_doubles(0, s2.p, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
   if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, Po, k, CR(x), prec);
+  rows_out(cx, s1, S, dim, 0, k, n1, C0());
+  for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
+  cx.prec = saved;
+}
+
+// ============================================================================
+// IP:  singles i, doubles (i<j, a)
+// ============================================================================
+void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v;
+  const int64_t n1 = I.n1, dim = I.dim;
+  const double x = I.x;
+  const int saved = cx.prec;
+  Tensor ys = tnew(cx, {k, o}, false);
+  rows_in(cx, Y, dim, 0, ys, k, n1);
+  Tensor Ya = tnew(cx, {k, o, o, v}, false);
+  launch_unpack_doubles(1, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream);
+  Tensor s1 = tnew(cx, {k, o}, false);
+  cx.prec = 0;
+  ctr(cx, C1(), I.M11x, "PQ", false, ys, "zQ", false, C0(), s1, "zP");
+  cx.prec = prec;
+  // M12(1): 1/2 <IJ||iA> Y_IJA ;  M12(2): 1/4 W_IJiA Y_IJA - W6_IAJi Y_IJA
+  ctr(cx, CR(0.5), I.ooov, "IJiA", false, Ya, "zIJA", false, C1(), s1, "zi");
+  if (x != 0.0) {
+    ctr(cx, CR(0.25 * x), I.W, "IJiA", false, Ya, "zIJA", false, C1(), s1, "zi");
+    ctr(cx, CR(-x), I.W6, "IAJi", false, Ya, "zIJA", false, C1(), s1, "zi");
+  }
+  Tensor s2 = tnew(cx, {k, o, o, v});
+  // M21(1): conj(<IJ||iA>) y_i
+  ctr(cx, C1(), I.ooov, "IJiA", true, ys, "zi", false, C1(), s2, "zIJA");
+  if (x != 0.0) {
+    ctr(cx, CR(0.5 * x), I.W, "IJiA", true, ys, "zi", false, C1(), s2, "zIJA");
+    Tensor T = tnew(cx, {k, o, o, v}, false);
+    ctr(cx, CR(-1), I.W6, "IAJi", true, ys, "zi", false, C0(), T, "zIJA");
+    launch_antisym_add(T.p, s2.p, k, o, o, v, 1, 0, CR(x), cx.stream);
+    // M22(1): hole ladder and ring
+    ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zkla", false, C1(), s2, "zija");
+    ctr(cx, C1(), Ya, "zikc", false, I.ring, "kcja", false, C0(), T, "zija");
+    launch_antisym_add(T.p, s2.p, k, o, o, v, 1, 0, CR(-x), cx.stream);
+    tfree(cx, T);
+  }
+  launch_pack_doubles(1, s2.p, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+  rows_out(cx, s1, S, dim, 0, k, n1, C0());
+  for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
+  cx.prec = saved;
+}
+
+// ============================================================================
+// EA:  singles a, doubles (i, a<b)
+// ============================================================================
+void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v;
+  const int64_t n1 = I.n1, dim = I.dim;
+  const double x = I.x;
+  const int saved = cx.prec;
+  const Tensor& t = I.t1;
+  Tensor ys = tnew(cx, {k, v}, false);
+  rows_in(cx, Y, dim, 0, ys, k, n1);
+  Tensor Ya = tnew(cx, {k, o, v, v}, false);
+  launch_unpack_doubles(2, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream);
+  Tensor s1 = tnew(cx, {k, v}, false);
+  cx.prec = 0;
+  ctr(cx, C1(), I.M11x, "PQ", false, ys, "zQ", false, C0(), s1, "zP");
+  cx.prec = prec;
+  // M12(1): 1/2 <aI||AB> Y_IAB,  <aI||AB> = -ovvv[I,a,A,B]
+  ctr(cx, CR(-0.5), I.ovvv, "IaAB", false, Ya, "zIAB", false, C1(), s1, "za");
+  if (x != 0.0) {
+    // M12(2): W5_IAaB Y_IAB + 1/4 conj(<kl||Ia>)-term
+    ctr(cx, CR(x), I.W5, "IAaB", false, Ya, "zIAB", false, C1(), s1, "za");
+    Tensor Vk = tnew(cx, {k, o, o, o}, false);
+    ctr(cx, C1(), t, "klAB", true, Ya, "zIAB", false, C0(), Vk, "zIkl");
+    ctr(cx, CR(-0.25 * x), I.ooov, "klIa", true, Vk, "zIkl", false, C1(), s1, "za");
+    tfree(cx, Vk);
+  }
+  Tensor s2 = tnew(cx, {k, o, v, v});
+  // M21(1): -conj(ovvv[I,a,A,B]) y_a
+  ctr(cx, CR(-1), I.ovvv, "IaAB", true, ys, "za", false, C1(), s2, "zIAB");
+  if (x != 0.0) {
+    Tensor T = tnew(cx, {k, o, v, v}, false);
+    ctr(cx, C1(), I.W5, "IAaB", true, ys, "za", false, C0(), T, "zIAB");
+    launch_antisym_add(T.p, s2.p, k, o, 1, v, v, 1, CR(x), cx.stream);
+    Tensor Z = tnew(cx, {k, o, o, o}, false);
+    ctr(cx, C1(), I.ooov, "klIa", false, ys, "za", false, C0(), Z, "zklI");
+    ctr(cx, CR(-0.5 * x), t, "klAB", false, Z, "zklI", false, C1(), s2, "zIAB");
+    tfree(cx, Z);
+    // M22(1) ring (the particle ladder runs packed below)
+    ctr(cx, C1(), Ya, "zjac", false, I.ring, "jcib", false, C0(), T, "ziab");
+    launch_antisym_add(T.p, s2.p, k, o, 1, v, v, 1, CR(-x), cx.stream);
+    tfree(cx, T);
+  }
+  launch_pack_doubles(2, s2.p, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+  if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, o, k, CR(x), prec);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
   for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
   cx.prec = saved;
@@ -628,8 +805,16 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
     I.diag = (double*)dmalloc(h, sizeof(double) * I.dim);
     hipcheck(hipMemcpy(I.diag, d.data(), sizeof(double) * I.dim, hipMemcpyHostToDevice), "diag");
   }
-  if (I.kind == ADC_EE) ee_init(h, I);
-  else throw Status{ADC_ERR_UNSUPPORTED, "IP/EA not built yet"};
+  {
+    std::vector<double> eps_h(p->eps, p->eps + n);
+    init_integrals(h, I);
+    Pre P;
+    init_amplitudes(h, I, P);
+    if (I.kind == ADC_EE) ee_init(h, I, P, eps_h);
+    else if (I.kind == ADC_IP) ip_init(h, I, P, eps_h);
+    else ea_init(h, I, P, eps_h);
+    for (Tensor* q : {&P.Lt, &P.Ht, &P.t2, &P.ts}) tfree(cx, *q);
+  }
   // host copy of diag(M11x) for the Davidson guesses
   {
     std::vector<double2> m(I.n1 * I.n1);
@@ -704,7 +889,8 @@ void heevj(int n, std::vector<zc>& A, std::vector<double>& w, std::vector<zc>& V
 void sigma_dispatch(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
   if (k <= 0) return;
   if (I.kind == ADC_EE) ee_sigma(h, I, Y, S, k, prec);
-  else throw Status{ADC_ERR_UNSUPPORTED, "kind"};
+  else if (I.kind == ADC_IP) ip_sigma(h, I, Y, S, k, prec);
+  else ea_sigma(h, I, Y, S, k, prec);
 }
 
 // G[a][b] = sum_i conj(X[a][i]) Y[b][i]  (ra x rb, host result)
@@ -724,7 +910,7 @@ std::vector<zc> gram(adc_handle* h, const double2* X, int ra, const double2* Y, 
     g.B = Y; g.sbk = 1; g.sbn = dim; g.sbb = chunk;
     g.C = part; g.scm = rb; g.scn = 1; g.scb = (int64_t)ra * rb;
     g.alpha = C1(); g.beta = C0();
-    launch_zgemm(g, 0, cx.stream);
+    { const int sp = cx.prec; cx.prec = 0; gemm(cx, g); cx.prec = sp; }
   }
   if (rem) {
     GemmDesc g{};
@@ -733,7 +919,7 @@ std::vector<zc> gram(adc_handle* h, const double2* X, int ra, const double2* Y, 
     g.B = Y + nsplit * chunk; g.sbk = 1; g.sbn = dim; g.sbb = 0;
     g.C = part + nsplit * ra * rb; g.scm = rb; g.scn = 1; g.scb = 0;
     g.alpha = C1(); g.beta = C0();
-    launch_zgemm(g, 0, cx.stream);
+    { const int sp = cx.prec; cx.prec = 0; gemm(cx, g); cx.prec = sp; }
   }
   std::vector<double2> hp((size_t)nparts * ra * rb);
   hipcheck(hipMemcpyAsync(hp.data(), part, sizeof(double2) * hp.size(), hipMemcpyDeviceToHost, cx.stream), "gram");
@@ -759,7 +945,7 @@ void combine(adc_handle* h, const std::vector<zc>& Cm, int m, int r, const doubl
   g.B = In; g.sbk = dim; g.sbn = 1; g.sbb = 0;
   g.C = Out; g.scm = dim; g.scn = 1; g.scb = 0;
   g.alpha = alpha; g.beta = beta;
-  launch_zgemm(g, 0, cx.stream);
+  { const int sp = cx.prec; cx.prec = 0; gemm(cx, g); cx.prec = sp; }
   hipcheck(hipStreamSynchronize(cx.stream), "comb sync");
   cx.pool.put(c);
 }
@@ -1002,6 +1188,7 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
   if (rc) return rc;
   const adc_problem& p = problems[0];
   if (opts && (opts->precision < 0 || opts->precision > 2)) return ADC_ERR_INVALID_ARG;
+  if (opts && opts->precision == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
   if (!p.L_on_device) {
     rc = validate_L_host((const double*)p.L, p.n_chol, p.n_occ + p.n_vir);
     if (rc) return rc;
@@ -1042,9 +1229,26 @@ int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precis
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
   if (precision > 2) return ADC_ERR_INVALID_ARG;
   const int prec = precision < 0 ? h->opt.precision : precision;
+  if (prec == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
   return guarded([&]() {
     sigma_dispatch(h, h->inst[inst], (const double2*)Y, (double2*)S, k, prec);
     hipcheck(hipGetLastError(), "sigma launch");
+    return ADC_OK;
+  });
+}
+
+int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, int k, int precision) {
+  if (term == ADC_TERM_ALL) return adc_sigma(h, inst, Y, S, k, precision);
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
+  if (precision > 2 || term != ADC_TERM_LADDER) return ADC_ERR_INVALID_ARG;
+  Inst& I = h->inst[0];
+  if (I.kind == ADC_IP) return ADC_ERR_UNSUPPORTED;
+  const int prec = precision < 0 ? h->opt.precision : precision;
+  return guarded([&]() {
+    launch_fill((double2*)S, (int64_t)k * I.dim, C0(), h->cx.stream);
+    const int64_t nrow = I.kind == ADC_EE ? I.Po : I.o;
+    ladder(h, I, (const double2*)Y, I.dim, I.n1, (double2*)S, I.dim, I.n1, nrow, k, CR(I.x), prec);
+    hipcheck(hipGetLastError(), "term launch");
     return ADC_OK;
   });
 }

@@ -72,6 +72,31 @@ void Pool::release_all() {
   in_use_ = 0;
 }
 
+void gemm(Ctx& cx, GemmDesc g) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+  int64_t nsplit = 1;
+  if (tiles < 512 && g.K >= 2048) {
+    nsplit = std::min<int64_t>({(1024 + tiles - 1) / tiles, g.K / 1024, 256});
+    if (g.batch * nsplit > 65535) nsplit = 65535 / g.batch;
+  }
+  if (nsplit <= 1) {
+    g.nsplit = 1;
+    g.kchunk = g.K;
+    launch_zgemm(g, cx.prec, cx.stream);
+    return;
+  }
+  int64_t chunk = (g.K + nsplit - 1) / nsplit;
+  chunk = (chunk + 15) / 16 * 16;
+  nsplit = (g.K + chunk - 1) / chunk;
+  g.kchunk = chunk;
+  g.nsplit = (int)nsplit;
+  g.P = cx.pool.get(nsplit * g.batch * g.M * g.N);
+  launch_zgemm(g, cx.prec, cx.stream);
+  launch_splitk_reduce(g, cx.stream);
+  cx.pool.put(g.P);
+}
+
 Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero) {
   Tensor t;
   t.d = std::move(d);
@@ -272,14 +297,14 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
     int64_t sbt = fused_stride(vc, bat), sm = fused_stride(vc, Ml), sn = fused_stride(vc, Nl);
     if (sbt >= 0 && sm >= 0 && sn >= 0) {
       g.C = C.p; g.scb = bat.empty() ? 0 : sbt; g.scm = Ml.empty() ? 0 : sm; g.scn = Nl.empty() ? 0 : sn;
-      launch_zgemm(g, cx.prec, cx.stream);
+      gemm(cx, g);
     } else {
       double2* t = cx.pool.get(Bn * Mn * Nn);
       tmps.push_back(t);
       g.C = t; g.scb = Mn * Nn; g.scm = Nn; g.scn = 1;
       cplx a0 = g.alpha;
       g.alpha = C1(); g.beta = C0();
-      launch_zgemm(g, cx.prec, cx.stream);
+      gemm(cx, g);
       // t has labels bat+Ml+Nl contiguous
       Tensor tt;
       tt.p = t;

@@ -26,7 +26,14 @@ struct GemmDesc {
   double2* C; int64_t scm, scn, scb;
   cplx alpha, beta;
   int conjA, conjB;
+  int tag;  // kernel instance: 0 generic, 1 ladder assembly, 2 ladder contraction
+  // split-K: nsplit > 1 writes raw partial sums of K-chunks of length kchunk
+  // to P[((s*batch + b)*M + m)*N + n]; a reduction applies alpha/beta into C
+  int64_t kchunk;
+  int nsplit;
+  double2* P;
 };
+void launch_splitk_reduce(const GemmDesc& g, hipStream_t s);
 // prec: 0 = FP64 MFMA, 1 = FP32 MFMA (operands rounded to fp32, fp32
 // accumulate), 2 = split-bf16 (three bf16 MFMA products, fp32 accumulate).
 void launch_zgemm(const GemmDesc& g, int prec, hipStream_t s);
@@ -114,6 +121,9 @@ struct Ctx {
   Pool pool;
   int prec = 0;   // arithmetic of ctr() calls
 };
+
+// GEMM with automatic split-K when the output has too few tiles to fill the chip
+void gemm(Ctx& cx, GemmDesc g);
 
 // C[lc] = alpha * sum A[la]^(conj?) B[lb]^(conj?) + beta * C[lc]
 void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Tensor& B, const char* lb,

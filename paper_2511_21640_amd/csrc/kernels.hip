@@ -27,12 +27,16 @@ static inline unsigned nblocks(int64_t n, int t) {
 // ---------------------------------------------------------------------------
 constexpr int TM = 64, TN = 64, TK = 16;
 
+template <int TAG>
 __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
   __shared__ double sAr[TK][TM], sAi[TK][TM], sBr[TK][TN], sBi[TK][TN];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
-  const int64_t bz = blockIdx.z;
+  const int64_t zz = blockIdx.z;
+  const int64_t sidx = zz / p.batch, bz = zz - sidx * p.batch;
+  const int64_t kbeg = sidx * p.kchunk;
+  const int64_t kend = (kbeg + p.kchunk < p.K) ? kbeg + p.kchunk : p.K;
   const double2* A = p.A + bz * p.sab;
   const double2* B = p.B + bz * p.sbb;
   double2* C = p.C + bz * p.scb;
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
       accI[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
 
-  for (int64_t k0 = 0; k0 < p.K; k0 += TK) {
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int m, k;
@@ -57,7 +61,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
       else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
       const int64_t gm = m0 + m, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
-      if (gm < p.M && gk < p.K) v = A[gm * p.sam + gk * p.sak];
+      if (gm < p.M && gk < kend) v = A[gm * p.sam + gk * p.sak];
       sAr[k][m] = v.x;
       sAi[k][m] = sa * v.y;
     }
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
       else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
       const int64_t gn = n0 + n, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
-      if (gn < p.N && gk < p.K) v = B[gk * p.sbk + gn * p.sbn];
+      if (gn < p.N && gk < kend) v = B[gk * p.sbk + gn * p.sbn];
       sBr[k][n] = v.x;
       sBi[k][n] = sb * v.y;
     }
@@ -112,6 +116,10 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
         const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
         if (row < p.M && col < p.N) {
           const double cr = accR[i][j][r], ci = accI[i][j][r];
+          if (p.nsplit > 1) {
+            p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
+            continue;
+          }
           double2* dst = C + row * p.scm + col * p.scn;
           double2 o;
           o.x = p.alpha.re * cr - p.alpha.im * ci;
@@ -130,12 +138,16 @@ __global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
 // FP32 MFMA complex GEMM (operands rounded to fp32, fp32 accumulation).
 // Same tiling with v_mfma_f32_16x16x4f32 (4 real products per complex k-step).
 // ---------------------------------------------------------------------------
+template <int TAG>
 __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
   __shared__ float sAr[TK][TM], sAi[TK][TM], sBr[TK][TN], sBi[TK][TN];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
-  const int64_t bz = blockIdx.z;
+  const int64_t zz = blockIdx.z;
+  const int64_t sidx = zz / p.batch, bz = zz - sidx * p.batch;
+  const int64_t kbeg = sidx * p.kchunk;
+  const int64_t kend = (kbeg + p.kchunk < p.K) ? kbeg + p.kchunk : p.K;
   const double2* A = p.A + bz * p.sab;
   const double2* B = p.B + bz * p.sbb;
   double2* C = p.C + bz * p.scb;
@@ -150,7 +162,7 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
       accR[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
       accI[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int64_t k0 = 0; k0 < p.K; k0 += TK) {
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int m, k;
@@ -158,7 +170,7 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
       else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
       const int64_t gm = m0 + m, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
-      if (gm < p.M && gk < p.K) v = A[gm * p.sam + gk * p.sak];
+      if (gm < p.M && gk < kend) v = A[gm * p.sam + gk * p.sak];
       sAr[k][m] = (float)v.x;
       sAi[k][m] = sa * (float)v.y;
     }
@@ -169,7 +181,7 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
       else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
       const int64_t gn = n0 + n, gk = k0 + k;
       double2 v = make_double2(0.0, 0.0);
-      if (gn < p.N && gk < p.K) v = B[gk * p.sbk + gn * p.sbn];
+      if (gn < p.N && gk < kend) v = B[gk * p.sbk + gn * p.sbn];
       sBr[k][n] = (float)v.x;
       sBi[k][n] = sb * (float)v.y;
     }
@@ -213,6 +225,10 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
         const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
         if (row < p.M && col < p.N) {
           const double cr = accR[i][j][r], ci = accI[i][j][r];
+          if (p.nsplit > 1) {
+            p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
+            continue;
+          }
           double2* dst = C + row * p.scm + col * p.scn;
           double2 o;
           o.x = p.alpha.re * cr - p.alpha.im * ci;
@@ -227,18 +243,51 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
       }
 }
 
-void launch_zgemm(const GemmDesc& g, int prec, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
-  if (g.K <= 0) {
-    // C = beta * C
-    GemmDesc h = g;
-    (void)h;
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmDesc p) {
+  const int64_t total = p.batch * p.M * p.N;
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / (p.M * p.N), r = idx - b * p.M * p.N, m = r / p.N, n = r - m * p.N;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < p.nsplit; ++s) {
+      const double2 v = p.P[(int64_t)s * total + idx];
+      sr += v.x;
+      si += v.y;
+    }
+    double2* dst = p.C + b * p.scb + m * p.scm + n * p.scn;
+    double2 o;
+    o.x = p.alpha.re * sr - p.alpha.im * si;
+    o.y = p.alpha.re * si + p.alpha.im * sr;
+    if (has_beta) {
+      const double2 old = *dst;
+      o.x += p.beta.re * old.x - p.beta.im * old.y;
+      o.y += p.beta.re * old.y + p.beta.im * old.x;
+    }
+    *dst = o;
   }
-  dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM), (unsigned)g.batch);
-  if (prec == 0)
-    hipLaunchKernelGGL(zgemm_f64_kernel, grid, dim3(256), 0, s, g);
-  else
-    hipLaunchKernelGGL(zgemm_f32_kernel, grid, dim3(256), 0, s, g);
+}
+
+void launch_splitk_reduce(const GemmDesc& g, hipStream_t s) {
+  const int64_t total = g.batch * g.M * g.N;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, g);
+}
+
+void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
+  if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0 || g0.K <= 0) return;
+  GemmDesc g = g0;
+  if (g.nsplit < 1) g.nsplit = 1;
+  if (g.nsplit == 1 || g.kchunk <= 0) { g.nsplit = 1; g.kchunk = g.K; }
+  dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM), (unsigned)(g.batch * g.nsplit));
+  if (prec == 0) {
+    if (g.tag == 1) hipLaunchKernelGGL(zgemm_f64_kernel<1>, grid, dim3(256), 0, s, g);
+    else if (g.tag == 2) hipLaunchKernelGGL(zgemm_f64_kernel<2>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(zgemm_f64_kernel<0>, grid, dim3(256), 0, s, g);
+  } else {
+    if (g.tag == 1) hipLaunchKernelGGL(zgemm_f32_kernel<1>, grid, dim3(256), 0, s, g);
+    else if (g.tag == 2) hipLaunchKernelGGL(zgemm_f32_kernel<2>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(zgemm_f32_kernel<0>, grid, dim3(256), 0, s, g);
+  }
 }
 
 // ---------------------------------------------------------------------------

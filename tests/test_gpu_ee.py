@@ -87,3 +87,24 @@ def test_one_electron_ee_is_exact():
     h = _handle(P, conv_tol=1e-10)
     out = h.davidson()
     assert np.abs(out["omega"] - exact[:3]).max() < 1e-9
+
+
+def test_ee_sigma_fp32_and_mixed_davidson():
+    """FP32 MFMA contractions (fp32 operands and accumulation): relative sigma
+    error of a few fp32 ulps times sqrt(K); eigenvalues after the FP64
+    refinement equal the FP64 path's."""
+    P = config_problem("C1")
+    rng = np.random.default_rng(12)
+    h = _handle(P, precision="fp32")
+    Y = _rand(rng, 4, h.dim)
+    S32 = h.sigma(torch.from_numpy(Y).cuda()).cpu().numpy()
+    ref = osigma(Ints(P.eps, P.L, P.o), "EE", P.x, Y)
+    err = np.abs(S32 - ref).max() / np.abs(ref).max()
+    print("fp32 rel err", err)
+    assert err < 1e-5
+    assert err > 1e-12  # really ran in reduced precision
+    out = h.davidson()
+    h64 = _handle(P, precision="fp64")
+    out64 = h64.davidson()
+    assert out["converged"].all()
+    assert np.abs(out["omega"] - out64["omega"]).max() < 1e-8
