@@ -115,6 +115,14 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   nb = std::min(nb, v - 1);
   double2* Wbuf = cx.pool.get((int64_t)nb * v * v * v);
   double2* Vbuf = cx.pool.get((int64_t)nb * v * Pv);
+  // the k vectors' rows are stacked into one [k*nrow][Pv] operand (M = k*nrow)
+  const int64_t R = (int64_t)k * nrow;
+  double2* Yc = cx.pool.get(R * Pv);
+  double2* Sc = cx.pool.get(R * Pv);
+  {
+    int64_t od[2] = {k, nrow * Pv}, is[2] = {ldY, 1}, os[2] = {nrow * Pv, 1};
+    launch_permute(2, od, is, os, Y + offY, Yc, C1(), C0(), 0, cx.stream);
+  }
   for (int a0 = 0; a0 < v - 1; a0 += nb) {
     const int a1 = std::min(v - 1, a0 + nb);
     const int b0 = a0 + 1;
@@ -134,18 +142,24 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
     const int64_t np = pend - pbase;
     launch_ladder_pack(Wbuf, g.N, a0, b0, v, Vbuf, pbase, np, I.pair_v, cx.stream);
-    // S[z][offS + ij*Pv + pbase + r] += alpha * sum_cd Y[z][offY + ij*Pv + cd] V[r][cd]
+    // Sc[r][pbase + q] = sum_cd Yc[r][cd] V[q][cd]
     GemmDesc c{};
-    c.M = nrow; c.N = np; c.K = Pv; c.batch = k;
-    c.A = Y + offY; c.sam = Pv; c.sak = 1; c.sab = ldY;
+    c.M = R; c.N = np; c.K = Pv; c.batch = 1;
+    c.A = Yc; c.sam = Pv; c.sak = 1; c.sab = 0;
     c.B = Vbuf; c.sbk = 1; c.sbn = Pv; c.sbb = 0;
-    c.C = S + offS + pbase; c.scm = Pv; c.scn = 1; c.scb = ldS;
-    c.alpha = alpha; c.beta = C1();
+    c.C = Sc + pbase; c.scm = Pv; c.scn = 1; c.scb = 0;
+    c.alpha = C1(); c.beta = C0();
     c.tag = 2;
     { const int sp = cx.prec; cx.prec = prec; gemm(cx, c); cx.prec = sp; }
   }
+  {
+    int64_t od[2] = {k, nrow * Pv}, is[2] = {nrow * Pv, 1}, os[2] = {ldS, 1};
+    launch_permute(2, od, is, os, Sc, S + offS, alpha, C1(), 0, cx.stream);
+  }
   cx.pool.put(Wbuf);
   cx.pool.put(Vbuf);
+  cx.pool.put(Yc);
+  cx.pool.put(Sc);
 }
 
 // copy rows [k][n] with row stride ld (offset off) into a contiguous tensor, or back
@@ -1197,6 +1211,8 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
   rc = guarded([&]() {
     h = new adc_handle();
     if (opts) h->opt = *opts;
+    if (h->opt.mem_budget)
+      h->cx.max_temp = std::min<int64_t>((int64_t)1 << 29, (int64_t)(h->opt.mem_budget / sizeof(double2)));
     if (h->opt.stream) {
       h->cx.stream = (hipStream_t)h->opt.stream;
     } else {
@@ -1207,6 +1223,7 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
     h->inst.resize(1);
     inst_init(h, &p, h->inst[0]);
     hipcheck(hipStreamSynchronize(h->cx.stream), "init sync");
+    h->cx.pool.trim();
     h->init_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return ADC_OK;
   });

@@ -64,6 +64,11 @@ void Pool::put(double2* p) {
   }
 }
 
+void Pool::trim() {
+  for (auto& b : free_) (void)hipFree(b.p);
+  free_.clear();
+}
+
 void Pool::release_all() {
   for (auto& b : free_) (void)hipFree(b.p);
   for (auto& b : used_) (void)hipFree(b.p);
@@ -252,6 +257,48 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   // K order: as in A
   const int64_t Mn = prod(va, Ml), Nn = prod(vb, Nl), Kn = prod(va, Kl), Bn = prod(vc, bat);
   if (Mn == 0 || Nn == 0 || Bn == 0) return;
+
+  // Bound the temporaries: if an operand (or the output) needs a permuted copy
+  // larger than kChunk elements, split the contraction along its largest label
+  // (an output label when possible, so that the pieces write disjoint parts of
+  // C; otherwise a summed label, accumulating with beta = 1 after the first).
+  {
+    const int64_t kChunk = std::max<int64_t>(1, cx.max_temp);
+    const bool pA = fused_stride(va, bat) < 0 || fused_stride(va, Ml) < 0 || fused_stride(va, Kl) < 0;
+    const bool pB = fused_stride(vb, bat) < 0 || fused_stride(vb, Nl) < 0 || fused_stride(vb, Kl) < 0;
+    const bool pC = fused_stride(vc, bat) < 0 || fused_stride(vc, Ml) < 0 || fused_stride(vc, Nl) < 0;
+    const int64_t need = std::max({pA ? A.size() : 0, pB ? B.size() : 0, pC ? C.size() : 0});
+    if (need > kChunk) {
+      const Tensor* X = (pA && A.size() == need) ? &A : (pB && B.size() == need) ? &B : &C;
+      const std::string& sx = (X == &A) ? sa : (X == &B) ? sb : sc;
+      const View& vx = (X == &A) ? va : (X == &B) ? vb : vc;
+      char best = 0;
+      int64_t bext = 1;
+      for (int pass = 0; pass < 2 && !best; ++pass)
+        for (char c : sx) {
+          const bool inC = sc.find(c) != std::string::npos;
+          if ((pass == 0) != inC) continue;
+          if (vx.size.at(c) > bext) { bext = vx.size.at(c); best = c; }
+        }
+      if (best) {
+        const int64_t per = std::max<int64_t>(1, X->size() / bext);
+        int64_t step = std::max<int64_t>(1, kChunk / per);
+        step = std::min(step, (bext + 1) / 2);
+        const bool inC = sc.find(best) != std::string::npos;
+        auto sl = [&](const Tensor& t, const std::string& l, int64_t lo, int64_t hi) {
+          const size_t pos = l.find(best);
+          return pos == std::string::npos ? t : tslice(t, (int)pos, lo, hi);
+        };
+        for (int64_t lo = 0; lo < bext; lo += step) {
+          const int64_t hi = std::min(bext, lo + step);
+          Tensor As = sl(A, sa, lo, hi), Bs = sl(B, sb, lo, hi), Cs = sl(C, sc, lo, hi);
+          const cplx be = (inC || lo == 0) ? beta : C1();
+          ctr(cx, alpha, As, la, cA, Bs, lb, cB, be, Cs, lc);
+        }
+        return;
+      }
+    }
+  }
 
   GemmDesc g{};
   g.M = Mn; g.N = Nn; g.K = Kn; g.batch = Bn;

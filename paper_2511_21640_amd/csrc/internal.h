@@ -108,6 +108,7 @@ class Pool {
   double2* get(int64_t n_complex);
   void put(double2* p);
   void release_all();
+  void trim();  // return cached (unused) blocks to the device
   size_t bytes_in_use() const { return in_use_; }
 
  private:
@@ -120,6 +121,7 @@ struct Ctx {
   hipStream_t stream = nullptr;
   Pool pool;
   int prec = 0;   // arithmetic of ctr() calls
+  int64_t max_temp = (int64_t)1 << 29;  // largest permuted copy (complex elements) before ctr() splits
 };
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip

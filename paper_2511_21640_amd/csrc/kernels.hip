@@ -22,129 +22,53 @@ static inline unsigned nblocks(int64_t n, int t) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 MFMA complex GEMM.  Tile 64x64 per 256-thread workgroup, each wave a
-// 32x32 quadrant as 2x2 blocks of v_mfma_f64_16x16x4f64.
+// Complex GEMM on the matrix cores.
+//
+// One 256-thread workgroup (4 waves in a 2x2 arrangement) computes a
+// (32*WM) x (32*WN) tile; each wave owns WM x WN blocks of 16x16.  Per k-step
+// of 4 a wave issues four real MFMA per block (Re*Re, -Im*Im into the real
+// accumulator, Re*Im, Im*Re into the imaginary one).  The K loop is register
+// double-buffered: the next 16-deep slice is fetched from global memory into
+// registers while the MFMAs consume the current slice from LDS.  Tiles are
+// handed out so that each of the 8 XCDs (workgroups are dispatched round-robin
+// over them) works on a contiguous range of tiles and reuses row blocks in its
+// own L2.
 // ---------------------------------------------------------------------------
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TK = 16;
 
-template <int TAG>
-__global__ __launch_bounds__(256) void zgemm_f64_kernel(GemmDesc p) {
-  __shared__ double sAr[TK][TM], sAi[TK][TM], sBr[TK][TN], sBi[TK][TN];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
-  const int64_t zz = blockIdx.z;
-  const int64_t sidx = zz / p.batch, bz = zz - sidx * p.batch;
-  const int64_t kbeg = sidx * p.kchunk;
-  const int64_t kend = (kbeg + p.kchunk < p.K) ? kbeg + p.kchunk : p.K;
-  const double2* A = p.A + bz * p.sab;
-  const double2* B = p.B + bz * p.sbb;
-  double2* C = p.C + bz * p.scb;
-  const int wr = wave >> 1, wc = wave & 1;
-  const bool aK = (p.sak == 1), bK = (p.sbk == 1);
-  const double sa = p.conjA ? -1.0 : 1.0, sb = p.conjB ? -1.0 : 1.0;
-
-  dbl4 accR[2][2], accI[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accR[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    }
-
-  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int m, k;
-      if (aK) { m = (tid >> 4) + 16 * r; k = tid & 15; }
-      else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
-      const int64_t gm = m0 + m, gk = k0 + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (gm < p.M && gk < kend) v = A[gm * p.sam + gk * p.sak];
-      sAr[k][m] = v.x;
-      sAi[k][m] = sa * v.y;
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int n, k;
-      if (bK) { n = (tid >> 4) + 16 * r; k = tid & 15; }
-      else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
-      const int64_t gn = n0 + n, gk = k0 + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (gn < p.N && gk < kend) v = B[gk * p.sbk + gn * p.sbn];
-      sBr[k][n] = v.x;
-      sBi[k][n] = sb * v.y;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double ar[2], ai[2], nai[2], br[2], bi[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = sAr[kr][32 * wr + 16 * i + (lane & 15)];
-        ai[i] = sAi[kr][32 * wr + 16 * i + (lane & 15)];
-        nai[i] = -ai[i];
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        br[j] = sBr[kr][32 * wc + 16 * j + (lane & 15)];
-        bi[j] = sBi[kr][32 * wc + 16 * j + (lane & 15)];
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accR[i][j], 0, 0, 0);
-          accR[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], accI[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], accI[i][j], 0, 0, 0);
-        }
-    }
-    __syncthreads();
-  }
-  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // v_mfma_f64_16x16x4f64 result: lane l, register r holds row l/16 + 4r, column l%16
-        const int64_t row = m0 + 32 * wr + 16 * i + (lane >> 4) + 4 * r;
-        const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
-        if (row < p.M && col < p.N) {
-          const double cr = accR[i][j][r], ci = accI[i][j][r];
-          if (p.nsplit > 1) {
-            p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
-            continue;
-          }
-          double2* dst = C + row * p.scm + col * p.scn;
-          double2 o;
-          o.x = p.alpha.re * cr - p.alpha.im * ci;
-          o.y = p.alpha.re * ci + p.alpha.im * cr;
-          if (has_beta) {
-            const double2 old = *dst;
-            o.x += p.beta.re * old.x - p.beta.im * old.y;
-            o.y += p.beta.re * old.y + p.beta.im * old.x;
-          }
-          *dst = o;
-        }
-      }
+__device__ __forceinline__ dbl4 mfma16(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ flt4 mfma16(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef dbl4 type; };
+template <> struct Acc<float> { typedef flt4 type; };
 
-// ---------------------------------------------------------------------------
-// FP32 MFMA complex GEMM (operands rounded to fp32, fp32 accumulation).
-// Same tiling with v_mfma_f32_16x16x4f32 (4 real products per complex k-step).
-// ---------------------------------------------------------------------------
-template <int TAG>
-__global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
-  __shared__ float sAr[TK][TM], sAi[TK][TM], sBr[TK][TN], sBi[TK][TN];
+// row of register r in a 16x16 MFMA result held by lane l
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+template <typename T, int WM, int WN, int TAG>
+__global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc p) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int RA = BM * TK / 256, RB = BN * TK / 256;   // elements per thread
+  typedef typename Acc<T>::type acc_t;
+  __shared__ T sAr[TK][BM + 1], sAi[TK][BM + 1], sBr[TK][BN + 1], sBi[TK][BN + 1];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t m0 = (int64_t)blockIdx.y * TM, n0 = (int64_t)blockIdx.x * TN;
-  const int64_t zz = blockIdx.z;
+  // XCD-aware tile index
+  const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN, ntile = tilesM * tilesN;
+  const int64_t L = blockIdx.x;
+  int64_t tile = L;
+  {
+    const int64_t q = ntile / 8, r = ntile % 8, x = L % 8, slot = L / 8;
+    tile = x * q + (x < r ? x : r) + slot;
+  }
+  const int64_t m0 = (tile / tilesN) * BM, n0 = (tile % tilesN) * BN;
+  const int64_t zz = blockIdx.y;
   const int64_t sidx = zz / p.batch, bz = zz - sidx * p.batch;
   const int64_t kbeg = sidx * p.kchunk;
   const int64_t kend = (kbeg + p.kchunk < p.K) ? kbeg + p.kchunk : p.K;
@@ -153,76 +77,101 @@ __global__ __launch_bounds__(256) void zgemm_f32_kernel(GemmDesc p) {
   double2* C = p.C + bz * p.scb;
   const int wr = wave >> 1, wc = wave & 1;
   const bool aK = (p.sak == 1), bK = (p.sbk == 1);
-  const float sa = p.conjA ? -1.0f : 1.0f, sb = p.conjB ? -1.0f : 1.0f;
-  flt4 accR[2][2], accI[2][2];
+  const T sa = p.conjA ? T(-1) : T(1), sb = p.conjB ? T(-1) : T(1);
+
+  acc_t accR[WM][WN], accI[WM][WN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accR[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
-      accI[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WN; ++j) {
+      accR[i][j] = acc_t{0, 0, 0, 0};
+      accI[i][j] = acc_t{0, 0, 0, 0};
     }
-  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+  double2 ra[RA], rb[RB];
+  auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RA; ++r) {
       int m, k;
       if (aK) { m = (tid >> 4) + 16 * r; k = tid & 15; }
-      else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
+      else    { m = tid % BM; k = tid / BM + (256 / BM) * r; }
       const int64_t gm = m0 + m, gk = k0 + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (gm < p.M && gk < kend) v = A[gm * p.sam + gk * p.sak];
-      sAr[k][m] = (float)v.x;
-      sAi[k][m] = sa * (float)v.y;
+      ra[r] = (gm < p.M && gk < kend) ? A[gm * p.sam + gk * p.sak] : make_double2(0.0, 0.0);
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RB; ++r) {
       int n, k;
       if (bK) { n = (tid >> 4) + 16 * r; k = tid & 15; }
-      else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
+      else    { n = tid % BN; k = tid / BN + (256 / BN) * r; }
       const int64_t gn = n0 + n, gk = k0 + k;
-      double2 v = make_double2(0.0, 0.0);
-      if (gn < p.N && gk < kend) v = B[gk * p.sbk + gn * p.sbn];
-      sBr[k][n] = (float)v.x;
-      sBi[k][n] = sb * (float)v.y;
+      rb[r] = (gn < p.N && gk < kend) ? B[gk * p.sbk + gn * p.sbn] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      int m, k;
+      if (aK) { m = (tid >> 4) + 16 * r; k = tid & 15; }
+      else    { m = tid % BM; k = tid / BM + (256 / BM) * r; }
+      sAr[k][m] = (T)ra[r].x;
+      sAi[k][m] = sa * (T)ra[r].y;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int n, k;
+      if (bK) { n = (tid >> 4) + 16 * r; k = tid & 15; }
+      else    { n = tid % BN; k = tid / BN + (256 / BN) * r; }
+      sBr[k][n] = (T)rb[r].x;
+      sBi[k][n] = sb * (T)rb[r].y;
+    }
+  };
+  if (kbeg < kend) {
+    gload(kbeg);
+    sstore();
+  }
+  __syncthreads();
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TK) {
+    const bool more = k0 + TK < kend;
+    if (more) gload(k0 + TK);
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      float ar[2], ai[2], nai[2], br[2], bi[2];
+      T ar[WM], ai[WM], nai[WM], br[WN], bi[WN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = sAr[kr][32 * wr + 16 * i + (lane & 15)];
-        ai[i] = sAi[kr][32 * wr + 16 * i + (lane & 15)];
+      for (int i = 0; i < WM; ++i) {
+        ar[i] = sAr[kr][32 * WM / 2 * wr + 16 * i + (lane & 15)];
+        ai[i] = sAi[kr][32 * WM / 2 * wr + 16 * i + (lane & 15)];
         nai[i] = -ai[i];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        br[j] = sBr[kr][32 * wc + 16 * j + (lane & 15)];
-        bi[j] = sBi[kr][32 * wc + 16 * j + (lane & 15)];
+      for (int j = 0; j < WN; ++j) {
+        br[j] = sBr[kr][32 * WN / 2 * wc + 16 * j + (lane & 15)];
+        bi[j] = sBi[kr][32 * WN / 2 * wc + 16 * j + (lane & 15)];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], accR[i][j], 0, 0, 0);
-          accR[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[i], bi[j], accR[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], accI[i][j], 0, 0, 0);
-          accI[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], accI[i][j], 0, 0, 0);
+        for (int j = 0; j < WN; ++j) {
+          accR[i][j] = mfma16(ar[i], br[j], accR[i][j]);
+          accR[i][j] = mfma16(nai[i], bi[j], accR[i][j]);
+          accI[i][j] = mfma16(ar[i], bi[j], accI[i][j]);
+          accI[i][j] = mfma16(ai[i], br[j], accI[i][j]);
         }
     }
     __syncthreads();
+    if (more) {
+      sstore();
+      __syncthreads();
+    }
   }
   const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // v_mfma_f32_16x16x4f32 result: lane l, register r holds row 4(l/16) + r, column l%16
-        const int64_t row = m0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
-        const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
+        const int64_t row = m0 + 32 * WM / 2 * wr + 16 * i + acc_row<T>(lane, r);
+        const int64_t col = n0 + 32 * WN / 2 * wc + 16 * j + (lane & 15);
         if (row < p.M && col < p.N) {
           const double cr = accR[i][j][r], ci = accI[i][j][r];
           if (p.nsplit > 1) {
@@ -273,20 +222,35 @@ void launch_splitk_reduce(const GemmDesc& g, hipStream_t s) {
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, g);
 }
 
+template <typename T, int WM, int WN>
+static void launch_tile(const GemmDesc& g, hipStream_t s) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  const int64_t tiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+  dim3 grid((unsigned)tiles, (unsigned)(g.batch * g.nsplit));
+  if (g.tag == 1) hipLaunchKernelGGL((zgemm_kernel<T, WM, WN, 1>), grid, dim3(256), 0, s, g);
+  else if (g.tag == 2) hipLaunchKernelGGL((zgemm_kernel<T, WM, WN, 2>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((zgemm_kernel<T, WM, WN, 0>), grid, dim3(256), 0, s, g);
+}
+
+// Tile choice: the big tile (FP64 128x64, FP32 128x128) halves the operand
+// traffic per MFMA but pads M and N to multiples of 128; it is used only when
+// the padding wastes under 10% and the grid still fills the chip.
+static double pad_waste(int64_t n, int64_t t) { return (double)(((n + t - 1) / t) * t - n) / (double)n; }
+
 void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0 || g0.K <= 0) return;
   GemmDesc g = g0;
   if (g.nsplit < 1) g.nsplit = 1;
   if (g.nsplit == 1 || g.kchunk <= 0) { g.nsplit = 1; g.kchunk = g.K; }
-  dim3 grid((unsigned)((g.N + TN - 1) / TN), (unsigned)((g.M + TM - 1) / TM), (unsigned)(g.batch * g.nsplit));
+  const int64_t BNbig = prec == 0 ? 64 : 128;
+  const int64_t big = ((g.M + 127) / 128) * ((g.N + BNbig - 1) / BNbig) * g.batch * g.nsplit;
+  const bool use_big = big >= 256 && pad_waste(g.M, 128) < 0.10 && pad_waste(g.N, BNbig) < 0.10;
   if (prec == 0) {
-    if (g.tag == 1) hipLaunchKernelGGL(zgemm_f64_kernel<1>, grid, dim3(256), 0, s, g);
-    else if (g.tag == 2) hipLaunchKernelGGL(zgemm_f64_kernel<2>, grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(zgemm_f64_kernel<0>, grid, dim3(256), 0, s, g);
+    if (use_big) launch_tile<double, 4, 2>(g, s);
+    else launch_tile<double, 2, 2>(g, s);
   } else {
-    if (g.tag == 1) hipLaunchKernelGGL(zgemm_f32_kernel<1>, grid, dim3(256), 0, s, g);
-    else if (g.tag == 2) hipLaunchKernelGGL(zgemm_f32_kernel<2>, grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(zgemm_f32_kernel<0>, grid, dim3(256), 0, s, g);
+    if (use_big) launch_tile<float, 4, 4>(g, s);
+    else launch_tile<float, 2, 2>(g, s);
   }
 }
 

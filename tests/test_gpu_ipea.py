@@ -66,3 +66,17 @@ def test_davidson_matches_oracle(kind, o, v, N):
     print("gpu", out["omega"], out["iters"], "oracle", w, it)
     assert out["converged"].all()
     assert np.abs(out["omega"] - w).max() < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["EE", "IP", "EA"])
+def test_tiny_memory_budget_gives_same_sigma(kind):
+    """A 64 KiB budget forces one-row ladder batches, one-index chunks of the
+    v^4 intermediates and splitting of every contraction whose operand copy
+    exceeds 4096 elements; the result must still match the oracle."""
+    P = make_problem(kind, 4, 9, 25, seed=41, x=0.8, scale=0.2)
+    h = _handle(P, mem_budget=1 << 16)
+    rng = np.random.default_rng(41)
+    Y = _rand(rng, 2, h.dim)
+    S = h.sigma(torch.from_numpy(Y).cuda()).cpu().numpy()
+    ref = osigma(Ints(P.eps, P.L, P.o), kind, P.x, Y)
+    assert np.abs(S - ref).max() / np.abs(ref).max() < 1e-12
