@@ -32,7 +32,7 @@ using zc = std::complex<double>;
 
 namespace {
 
-constexpr bool kSplitBf16Built = false;
+constexpr bool kSplitBf16Built = true;
 
 struct Status {
   int code;

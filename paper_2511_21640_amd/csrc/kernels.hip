@@ -12,7 +12,6 @@ namespace adc {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
-typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
 static inline unsigned nblocks(int64_t n, int t) {
   int64_t b = (n + t - 1) / t;
@@ -222,6 +221,189 @@ void launch_splitk_reduce(const GemmDesc& g, hipStream_t s) {
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, g);
 }
 
+// ---------------------------------------------------------------------------
+// Split-bf16 complex GEMM.  Each operand value is rounded to fp32 and split
+// into bf16 hi = RNE(x) and lo = RNE(x - hi) when it is staged in LDS (four
+// planes: re hi/lo, im hi/lo, k contiguous).  A real product x*y is formed as
+// xh*yh + xh*yl + xl*yh with v_mfma_f32_16x16x32_bf16 (fp32 accumulation), so
+// a complex 16x16x32 block costs 12 MFMA.  64x64 tile, 4 waves, k-slices of
+// 32, register double buffering, XCD-aware tile order and split-K as above.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+constexpr int TKB = 32, PADB = 8;
+
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+  const __hip_bfloat16 h = __float2bfloat16(x);
+  const __hip_bfloat16 l = __float2bfloat16(x - __bfloat162float(h));
+  hi = __bfloat16_as_ushort(h);
+  lo = __bfloat16_as_ushort(l);
+}
+
+__device__ __forceinline__ flt4 mfma_bf16(us8 a, us8 b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                 0, 0);
+}
+
+template <int TAG>
+__global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc p) {
+  constexpr int BM = 64, BN = 64, RA = BM * TKB / 256, RB = BN * TKB / 256;
+  __shared__ __attribute__((aligned(16))) unsigned short sA[4][BM][TKB + PADB];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[4][BN][TKB + PADB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN, ntile = tilesM * tilesN;
+  const int64_t L = blockIdx.x;
+  int64_t tile;
+  {
+    const int64_t q = ntile / 8, r = ntile % 8, x = L % 8, slot = L / 8;
+    tile = x * q + (x < r ? x : r) + slot;
+  }
+  const int64_t m0 = (tile / tilesN) * BM, n0 = (tile % tilesN) * BN;
+  const int64_t zz = blockIdx.y;
+  const int64_t sidx = zz / p.batch, bz = zz - sidx * p.batch;
+  const int64_t kbeg = sidx * p.kchunk;
+  const int64_t kend = (kbeg + p.kchunk < p.K) ? kbeg + p.kchunk : p.K;
+  const double2* A = p.A + bz * p.sab;
+  const double2* B = p.B + bz * p.sbb;
+  double2* C = p.C + bz * p.scb;
+  const int wr = wave >> 1, wc = wave & 1;
+  const bool aK = (p.sak == 1), bK = (p.sbk == 1);
+  const float sa = p.conjA ? -1.f : 1.f, sb = p.conjB ? -1.f : 1.f;
+  flt4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+    }
+  double2 ra[RA], rb[RB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      int m, k;
+      if (aK) { m = (tid >> 5) + 8 * r; k = tid & 31; }
+      else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
+      const int64_t gm = m0 + m, gk = k0 + k;
+      ra[r] = (gm < p.M && gk < kend) ? A[gm * p.sam + gk * p.sak] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int n, k;
+      if (bK) { n = (tid >> 5) + 8 * r; k = tid & 31; }
+      else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
+      const int64_t gn = n0 + n, gk = k0 + k;
+      rb[r] = (gn < p.N && gk < kend) ? B[gk * p.sbk + gn * p.sbn] : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      int m, k;
+      if (aK) { m = (tid >> 5) + 8 * r; k = tid & 31; }
+      else    { m = tid & 63; k = (tid >> 6) + 4 * r; }
+      unsigned short h0, l0, h1, l1;
+      split_bf16((float)ra[r].x, h0, l0);
+      split_bf16(sa * (float)ra[r].y, h1, l1);
+      sA[0][m][k] = h0; sA[1][m][k] = l0; sA[2][m][k] = h1; sA[3][m][k] = l1;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      int n, k;
+      if (bK) { n = (tid >> 5) + 8 * r; k = tid & 31; }
+      else    { n = tid & 63; k = (tid >> 6) + 4 * r; }
+      unsigned short h0, l0, h1, l1;
+      split_bf16((float)rb[r].x, h0, l0);
+      split_bf16(sb * (float)rb[r].y, h1, l1);
+      sB[0][n][k] = h0; sB[1][n][k] = l0; sB[2][n][k] = h1; sB[3][n][k] = l1;
+    }
+  };
+  if (kbeg < kend) {
+    gload(kbeg);
+    sstore();
+  }
+  __syncthreads();
+  const int kq = 8 * (lane >> 4);
+  const us8 sgn = us8{0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TKB) {
+    const bool more = k0 + TKB < kend;
+    if (more) gload(k0 + TKB);
+    us8 a[2][4], b[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[i][q] = *(const us8*)&sA[q][32 * wr + 16 * i + (lane & 15)][kq];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[j][q] = *(const us8*)&sB[q][32 * wc + 16 * j + (lane & 15)][kq];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const us8 nih = a[i][2] ^ sgn, nil = a[i][3] ^ sgn;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        flt4 cr = accR[i][j], ci = accI[i][j];
+        cr = mfma_bf16(a[i][0], b[j][0], cr);
+        cr = mfma_bf16(a[i][0], b[j][1], cr);
+        cr = mfma_bf16(a[i][1], b[j][0], cr);
+        cr = mfma_bf16(nih, b[j][2], cr);
+        cr = mfma_bf16(nih, b[j][3], cr);
+        cr = mfma_bf16(nil, b[j][2], cr);
+        ci = mfma_bf16(a[i][0], b[j][2], ci);
+        ci = mfma_bf16(a[i][0], b[j][3], ci);
+        ci = mfma_bf16(a[i][1], b[j][2], ci);
+        ci = mfma_bf16(a[i][2], b[j][0], ci);
+        ci = mfma_bf16(a[i][2], b[j][1], ci);
+        ci = mfma_bf16(a[i][3], b[j][0], ci);
+        accR[i][j] = cr;
+        accI[i][j] = ci;
+      }
+    }
+    __syncthreads();
+    if (more) {
+      sstore();
+      __syncthreads();
+    }
+  }
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f32_16x16x32_bf16 result: lane l, register r holds row 4(l/16) + r, column l%16
+        const int64_t row = m0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
+        const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
+        if (row < p.M && col < p.N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          if (p.nsplit > 1) {
+            p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
+            continue;
+          }
+          double2* dst = C + row * p.scm + col * p.scn;
+          double2 o;
+          o.x = p.alpha.re * cr - p.alpha.im * ci;
+          o.y = p.alpha.re * ci + p.alpha.im * cr;
+          if (has_beta) {
+            const double2 old = *dst;
+            o.x += p.beta.re * old.x - p.beta.im * old.y;
+            o.y += p.beta.re * old.y + p.beta.im * old.x;
+          }
+          *dst = o;
+        }
+      }
+}
+
+static void launch_bf16x3(const GemmDesc& g, hipStream_t s) {
+  const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  dim3 grid((unsigned)tiles, (unsigned)(g.batch * g.nsplit));
+  if (g.tag == 1) hipLaunchKernelGGL(zgemm_bf16x3_kernel<1>, grid, dim3(256), 0, s, g);
+  else if (g.tag == 2) hipLaunchKernelGGL(zgemm_bf16x3_kernel<2>, grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL(zgemm_bf16x3_kernel<0>, grid, dim3(256), 0, s, g);
+}
+
 template <typename T, int WM, int WN>
 static void launch_tile(const GemmDesc& g, hipStream_t s) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
@@ -245,7 +427,9 @@ void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
   const int64_t BNbig = prec == 0 ? 64 : 128;
   const int64_t big = ((g.M + 127) / 128) * ((g.N + BNbig - 1) / BNbig) * g.batch * g.nsplit;
   const bool use_big = big >= 256 && pad_waste(g.M, 128) < 0.10 && pad_waste(g.N, BNbig) < 0.10;
-  if (prec == 0) {
+  if (prec == 2) {
+    launch_bf16x3(g, s);
+  } else if (prec == 0) {
     if (use_big) launch_tile<double, 4, 2>(g, s);
     else launch_tile<double, 2, 2>(g, s);
   } else {

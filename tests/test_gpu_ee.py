@@ -108,3 +108,24 @@ def test_ee_sigma_fp32_and_mixed_davidson():
     out64 = h64.davidson()
     assert out["converged"].all()
     assert np.abs(out["omega"] - out64["omega"]).max() < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["EE", "IP", "EA"])
+def test_split_bf16_sigma_and_mixed_davidson(kind):
+    """Split-bf16 contractions: x = hi + lo with hi, lo bf16 (16 mantissa bits
+    together), three products per real MAC in fp32; relative sigma error of a
+    few 2^-17 times sqrt(K).  After the FP64 refinement the eigenvalues equal
+    the FP64 path's."""
+    P = make_problem(kind, 6, 18, 80, seed=13, n_roots=4, x=1.0)
+    rng = np.random.default_rng(13)
+    h = _handle(P, precision="split_bf16")
+    Y = _rand(rng, 3, h.dim)
+    S = h.sigma(torch.from_numpy(Y).cuda()).cpu().numpy()
+    ref = osigma(Ints(P.eps, P.L, P.o), kind, P.x, Y)
+    err = np.abs(S - ref).max() / np.abs(ref).max()
+    print(kind, "split-bf16 rel err", err)
+    assert 1e-12 < err < 2e-5
+    out = h.davidson()
+    out64 = _handle(P, precision="fp64").davidson()
+    assert out["converged"].all()
+    assert np.abs(out["omega"] - out64["omega"]).max() < 1e-8
