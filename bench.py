@@ -6,7 +6,7 @@ Workload: EE-ADC(2)+x(3), x = 0.5, o = 20, v = 120 spinors, N_chol = 900,
 (``adcgen``).  One step = one sigma build S = M(x) Y for all 8 vectors, inputs
 resident in HBM.  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--precision fp32|split_bf16|fp64]
+  python bench.py [--steps K] [--warmup W] [--precision split_bf16|fp32|fp64]
                   [--no-cpu] [--no-eig]
 """
 import argparse
@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16", "fp64"])
+    ap.add_argument("--precision", default="split_bf16", choices=["fp32", "split_bf16", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
     args = ap.parse_args()
@@ -142,7 +142,9 @@ def main():
         "init_ms": h.init_ms,
         "roofline": {"bound": "mfma", "kernel": "ladder term (assembly GEMM + pack + contraction GEMM)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "ms_per_launch": ms_lad, "flop_per_launch": lad_flops},
+                     "traffic": None, "ms_per_launch": ms_lad, "flop_per_launch": lad_flops,
+                     "effective_peak": peak / 3.0 if args.precision == "split_bf16" else peak,
+                     "frac_effective": achieved / (peak / 3.0 if args.precision == "split_bf16" else peak)},
     }
     if not args.no_eig and args.precision != "fp64":
         t0 = time.perf_counter()

@@ -55,6 +55,11 @@ struct Inst {
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
+  // split-bf16 planes [4][rows][K padded to 32], built on first use
+  unsigned short* Lq = nullptr;     // rows (a,c) of L_vv, K = Q
+  int64_t Kq = 0;
+  unsigned short* ringp = nullptr;  // rows (j,b), K = (k,c): conj(ring) = ring^T
+  int64_t Kr = 0;
   std::vector<double> m11diag;  // host, real part of diag(M11x)
 };
 
@@ -98,6 +103,44 @@ std::vector<int2> pair_table(int n) {
   return t;
 }
 
+int64_t pad32(int64_t n) { return (n + 31) / 32 * 32; }
+
+unsigned short* planes_alloc(Ctx& cx, int64_t rows, int64_t Kp) {
+  return (unsigned short*)cx.pool.get((rows * Kp * 4 + 7) / 8);
+}
+
+void ensure_planes(adc_handle* h, Inst& I) {
+  Ctx& cx = h->cx;
+  const int64_t v = I.v, ov = (int64_t)I.o * I.v;
+  if (!I.Lq) {
+    I.Kq = pad32(I.N);
+    I.Lq = (unsigned short*)dmalloc(h, (size_t)v * v * I.Kq * 8);
+    launch_split_planes(I.Lvv.p, v * v, I.N, 1, v * v, 0, I.Lq, I.Kq, cx.stream);
+  }
+  if (!I.ringp) {
+    I.Kr = pad32(ov);
+    I.ringp = (unsigned short*)dmalloc(h, (size_t)ov * I.Kr * 8);
+    launch_split_planes(I.ring.p, ov, ov, ov, 1, 1, I.ringp, I.Kr, cx.stream);
+  }
+}
+
+// R[r][(j,b)] = sum_(k,c) X[r][(k,c)] <kb||jc> for rows r of X (contiguous [rows][ov]), split-bf16
+void ring_bf16(adc_handle* h, Inst& I, const double2* X, int64_t rows, double2* R) {
+  Ctx& cx = h->cx;
+  ensure_planes(h, I);
+  const int64_t ov = (int64_t)I.o * I.v;
+  unsigned short* Xp = planes_alloc(cx, rows, I.Kr);
+  launch_split_planes(X, rows, ov, ov, 1, 0, Xp, I.Kr, cx.stream);
+  BfGemm g{};
+  g.M = rows; g.N = ov; g.Kp = I.Kr;
+  g.A = Xp; g.lda = rows;
+  g.B = I.ringp; g.ldb = ov;
+  g.C = R; g.scm = ov; g.scn = 1;
+  g.alpha = C1(); g.beta = C0();
+  gemm_bf16p(cx, g);
+  cx.pool.put((double2*)Xp);
+}
+
 // ----------------------------------------------------------------------------
 // particle-particle ladder:  S[z][offS + ij*Pv + ab] += alpha * sum_{c<d} <ab||cd> Y[z][offY + ij*Pv + cd]
 // for rows ij in [0, nrow), z in [0, k).  L_vv is [Q][v][v].
@@ -123,6 +166,37 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     int64_t od[2] = {k, nrow * Pv}, is[2] = {ldY, 1}, os[2] = {nrow * Pv, 1};
     launch_permute(2, od, is, os, Y + offY, Yc, C1(), C0(), 0, cx.stream);
   }
+  if (prec == ADC_SPLIT_BF16) {
+    ensure_planes(h, I);
+    const int64_t Kv = pad32(Pv);
+    unsigned short* Yp = planes_alloc(cx, R, Kv);
+    unsigned short* Vp = planes_alloc(cx, (int64_t)nb * v, Kv);
+    launch_split_planes(Yc, R, Pv, Pv, 1, 0, Yp, Kv, cx.stream);
+    for (int a0 = 0; a0 < v - 1; a0 += nb) {
+      const int a1 = std::min(v - 1, a0 + nb);
+      const int b0 = a0 + 1;
+      BfGemm g{};
+      g.M = (int64_t)(a1 - a0) * v; g.N = (int64_t)(v - b0) * v; g.Kp = I.Kq;
+      g.A = I.Lq + (int64_t)a0 * v * I.Kq; g.lda = (int64_t)v * v;
+      g.B = I.Lq + (int64_t)b0 * v * I.Kq; g.ldb = (int64_t)v * v;
+      g.C = Wbuf; g.scm = g.N; g.scn = 1;
+      g.alpha = C1(); g.beta = C0(); g.tag = 1;
+      gemm_bf16p(cx, g);
+      const int64_t pbase = (int64_t)a0 * (2 * v - a0 - 1) / 2;
+      const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
+      const int64_t np = pend - pbase;
+      launch_ladder_pack_planes(Wbuf, g.N, a0, b0, v, Vp, pbase, np, I.pair_v, Kv, cx.stream);
+      BfGemm c{};
+      c.M = R; c.N = np; c.Kp = Kv;
+      c.A = Yp; c.lda = R;
+      c.B = Vp; c.ldb = np;
+      c.C = Sc + pbase; c.scm = Pv; c.scn = 1;
+      c.alpha = C1(); c.beta = C0(); c.tag = 2;
+      gemm_bf16p(cx, c);
+    }
+    cx.pool.put((double2*)Yp);
+    cx.pool.put((double2*)Vp);
+  } else
   for (int a0 = 0; a0 < v - 1; a0 += nb) {
     const int a1 = std::min(v - 1, a0 + nb);
     const int b0 = a0 + 1;
@@ -595,7 +669,14 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       // M22(1): hole ladder and ring (the particle ladder runs packed below)
       ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), s2, "zijab");
       Tensor R = tnew(cx, {k, o, v, o, v}, false);
-      ctr(cx, C1(), Ya, "zikac", false, I.ring, "kcjb", false, C0(), R, "ziajb");
+      if (prec == ADC_SPLIT_BF16) {
+        Tensor Yr = tnew(cx, {k, o, v, o, v}, false);
+        perm(cx, C1(), Ya, "zikac", false, C0(), Yr, "ziakc");
+        ring_bf16(h, I, Yr.p, (int64_t)k * o * v, R.p);
+        tfree(cx, Yr);
+      } else {
+        ctr(cx, C1(), Ya, "zikac", false, I.ring, "kcjb", false, C0(), R, "ziajb");
+      }
       perm(cx, C1(), R, "ziajb", false, C0(), T, "zijab");
       launch_antisym_add(T.p, s2.p, k, o, o, v, v, 2, CR(-x), cx.stream);
       tfree(cx, R);
@@ -643,7 +724,8 @@ void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     launch_antisym_add(T.p, s2.p, k, o, o, v, 1, 0, CR(x), cx.stream);
     // M22(1): hole ladder and ring
     ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zkla", false, C1(), s2, "zija");
-    ctr(cx, C1(), Ya, "zikc", false, I.ring, "kcja", false, C0(), T, "zija");
+    if (prec == ADC_SPLIT_BF16) ring_bf16(h, I, Ya.p, (int64_t)k * o, T.p);
+    else ctr(cx, C1(), Ya, "zikc", false, I.ring, "kcja", false, C0(), T, "zija");
     launch_antisym_add(T.p, s2.p, k, o, o, v, 1, 0, CR(-x), cx.stream);
     tfree(cx, T);
   }
@@ -693,7 +775,16 @@ void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, CR(-0.5 * x), t, "klAB", false, Z, "zklI", false, C1(), s2, "zIAB");
     tfree(cx, Z);
     // M22(1) ring (the particle ladder runs packed below)
-    ctr(cx, C1(), Ya, "zjac", false, I.ring, "jcib", false, C0(), T, "ziab");
+    if (prec == ADC_SPLIT_BF16) {
+      Tensor Yr = tnew(cx, {k, v, o, v}, false), Rr = tnew(cx, {k, v, o, v}, false);
+      perm(cx, C1(), Ya, "zjac", false, C0(), Yr, "zajc");
+      ring_bf16(h, I, Yr.p, (int64_t)k * v, Rr.p);
+      perm(cx, C1(), Rr, "zaib", false, C0(), T, "ziab");
+      tfree(cx, Yr);
+      tfree(cx, Rr);
+    } else {
+      ctr(cx, C1(), Ya, "zjac", false, I.ring, "jcib", false, C0(), T, "ziab");
+    }
     launch_antisym_add(T.p, s2.p, k, o, 1, v, v, 1, CR(-x), cx.stream);
     tfree(cx, T);
   }

@@ -102,6 +102,28 @@ void gemm(Ctx& cx, GemmDesc g) {
   cx.pool.put(g.P);
 }
 
+void gemm_bf16p(Ctx& cx, BfGemm g) {
+  if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
+  const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+  int64_t nsplit = 1;
+  if (tiles < 512 && g.Kp >= 2048) nsplit = std::min<int64_t>({(1024 + tiles - 1) / tiles, g.Kp / 1024, 256});
+  if (nsplit <= 1) {
+    g.nsplit = 1;
+    g.kchunk = g.Kp;
+    launch_bf16p(g, cx.stream);
+    return;
+  }
+  int64_t chunk = (g.Kp + nsplit - 1) / nsplit;
+  chunk = (chunk + 31) / 32 * 32;
+  nsplit = (g.Kp + chunk - 1) / chunk;
+  g.kchunk = chunk;
+  g.nsplit = (int)nsplit;
+  g.P = cx.pool.get(nsplit * g.M * g.N);
+  launch_bf16p(g, cx.stream);
+  launch_splitk_reduce_bf(g, cx.stream);
+  cx.pool.put(g.P);
+}
+
 Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero) {
   Tensor t;
   t.d = std::move(d);
@@ -306,6 +328,57 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   g.conjA = cA; g.conjB = cB;
 
   std::vector<double2*> tmps;
+  // ---- split-bf16: unbatched contractions run on pre-split operand planes
+  if (cx.prec == 2 && bat.empty() && Kn >= 32) {
+    const int64_t Kp = (Kn + 31) / 32 * 32;
+    // A as [M][K] with K contiguous
+    const double2* Ap = A.p;
+    int64_t sam = fused_stride(va, Ml), sak = fused_stride(va, Kl);
+    if (Ml.empty()) sam = 0;
+    if (sam < 0 || sak != 1) {
+      double2* t = cx.pool.get(A.size());
+      tmps.push_back(t);
+      permute_into(cx, A, va, Ml + Kl, false, t, C1(), C0());
+      Ap = t; sam = Kn; sak = 1;
+    }
+    const double2* Bp = B.p;
+    int64_t sbn = fused_stride(vb, Nl), sbk = fused_stride(vb, Kl);
+    if (Nl.empty()) sbn = 0;
+    if (sbn < 0 || sbk != 1) {
+      double2* t = cx.pool.get(B.size());
+      tmps.push_back(t);
+      permute_into(cx, B, vb, Nl + Kl, false, t, C1(), C0());
+      Bp = t; sbn = Kn; sbk = 1;
+    }
+    unsigned short* Aq = (unsigned short*)cx.pool.get((Mn * Kp * 4 + 7) / 8);
+    unsigned short* Bq = (unsigned short*)cx.pool.get((Nn * Kp * 4 + 7) / 8);
+    launch_split_planes(Ap, Mn, Kn, sam, 1, cA ? 1 : 0, Aq, Kp, cx.stream);
+    launch_split_planes(Bp, Nn, Kn, sbn, 1, cB ? 1 : 0, Bq, Kp, cx.stream);
+    BfGemm g{};
+    g.M = Mn; g.N = Nn; g.Kp = Kp;
+    g.A = Aq; g.lda = Mn;
+    g.B = Bq; g.ldb = Nn;
+    g.alpha = alpha; g.beta = beta;
+    const int64_t scm = fused_stride(vc, Ml), scn = fused_stride(vc, Nl);
+    if (scm >= 0 && scn >= 0) {
+      g.C = C.p; g.scm = Ml.empty() ? 0 : scm; g.scn = Nl.empty() ? 0 : scn;
+      gemm_bf16p(cx, g);
+    } else {
+      double2* t = cx.pool.get(Mn * Nn);
+      tmps.push_back(t);
+      g.C = t; g.scm = Nn; g.scn = 1; g.alpha = C1(); g.beta = C0();
+      gemm_bf16p(cx, g);
+      Tensor tt;
+      tt.p = t;
+      for (char c : Ml + Nl) tt.d.push_back(vc.size.at(c));
+      std::string tl = Ml + Nl;
+      perm(cx, alpha, tt, tl.c_str(), false, beta, C, lc);
+    }
+    cx.pool.put((double2*)Aq);
+    cx.pool.put((double2*)Bq);
+    for (auto* t : tmps) cx.pool.put(t);
+    return;
+  }
   // ---- operand A: need batch, M, K groups fusable
   {
     int64_t sbt = fused_stride(va, bat), sm = fused_stride(va, Ml), sk = fused_stride(va, Kl);

@@ -38,6 +38,28 @@ void launch_splitk_reduce(const GemmDesc& g, hipStream_t s);
 // accumulate), 2 = split-bf16 (three bf16 MFMA products, fp32 accumulate).
 void launch_zgemm(const GemmDesc& g, int prec, hipStream_t s);
 
+// ---------------------------------------------------------------- split-bf16 planes
+// C(m,n) = alpha * sum_k A(m,k) B(n,k) + beta C (note: B is given row-major in n)
+// with A, B as bf16 split planes [4][rows][Kp] (re hi, re lo, im hi, im lo).
+struct BfGemm {
+  int64_t M, N, Kp;
+  const unsigned short* A; int64_t lda;   // rows per plane of A (>= M)
+  const unsigned short* B; int64_t ldb;   // rows per plane of B (>= N)
+  double2* C; int64_t scm, scn;
+  cplx alpha, beta;
+  int tag;
+  int64_t kchunk;
+  int nsplit;
+  double2* P;
+};
+void launch_bf16p(const BfGemm& g, hipStream_t s);
+void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s);
+// dst planes [4][rows][Kp] from src(r, k) = src[r*srow + k*sk] (conj: negate im), zero for k >= K
+void launch_split_planes(const double2* src, int64_t rows, int64_t K, int64_t srow, int64_t sk, int conj,
+                         unsigned short* dst, int64_t Kp, hipStream_t s);
+void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
+                               int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s);
+
 // ---------------------------------------------------------------- permute
 // out[sum_d idx_d * ostr[d]] = alpha * op(in[sum_d idx_d * istr[d]]) + beta * out[...]
 // over the index box od[0..nd)
@@ -126,6 +148,7 @@ struct Ctx {
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);
+void gemm_bf16p(Ctx& cx, BfGemm g);
 
 // C[lc] = alpha * sum A[la]^(conj?) B[lb]^(conj?) + beta * C[lc]
 void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Tensor& B, const char* lb,

@@ -404,6 +404,257 @@ static void launch_bf16x3(const GemmDesc& g, hipStream_t s) {
   else hipLaunchKernelGGL(zgemm_bf16x3_kernel<0>, grid, dim3(256), 0, s, g);
 }
 
+static double pad_waste(int64_t n, int64_t t) { return (double)(((n + t - 1) / t) * t - n) / (double)n; }
+
+// ---------------------------------------------------------------------------
+// Split-bf16 GEMM on pre-split operands.  A and B are given as four planes
+// (re hi, re lo, im hi, im lo) of bf16, [plane][rows][Kp] with K contiguous
+// and zero-padded to Kp (a multiple of 32).  Tiles are streamed into LDS with
+// 16-byte loads; there is no per-element arithmetic before the MFMAs.
+// ---------------------------------------------------------------------------
+__global__ void split_planes_kernel(const double2* src, int64_t rows, int64_t K, int64_t srow, int64_t sk, int conj,
+                                    unsigned short* dst, int64_t Kp) {
+  const int64_t total = rows * Kp;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / Kp, k = idx - r * Kp;
+    unsigned short h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+    if (k < K) {
+      const double2 v = src[r * srow + k * sk];
+      split_bf16((float)v.x, h0, l0);
+      split_bf16(conj ? -(float)v.y : (float)v.y, h1, l1);
+    }
+    dst[idx] = h0;
+    dst[total + idx] = l0;
+    dst[2 * total + idx] = h1;
+    dst[3 * total + idx] = l1;
+  }
+}
+void launch_split_planes(const double2* src, int64_t rows, int64_t K, int64_t srow, int64_t sk, int conj,
+                         unsigned short* dst, int64_t Kp, hipStream_t s) {
+  if (rows * Kp == 0) return;
+  hipLaunchKernelGGL(split_planes_kernel, dim3(nblocks(rows * Kp, 256)), dim3(256), 0, s, src, rows, K, srow, sk, conj,
+                     dst, Kp);
+}
+
+template <int WM, int WN, int TAG>
+__global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int UA = 16 * BM / 256, UB = 16 * BN / 256;   // uint4 per thread per slice
+  __shared__ __attribute__((aligned(16))) unsigned short sA[4][BM][TKB + PADB];
+  __shared__ __attribute__((aligned(16))) unsigned short sB[4][BN][TKB + PADB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN, ntile = tilesM * tilesN;
+  const int64_t L = blockIdx.x;
+  int64_t tile;
+  {
+    const int64_t q = ntile / 8, r = ntile % 8, x = L % 8, slot = L / 8;
+    tile = x * q + (x < r ? x : r) + slot;
+  }
+  const int64_t m0 = (tile / tilesN) * BM, n0 = (tile % tilesN) * BN;
+  const int64_t sidx = blockIdx.y;
+  const int64_t kbeg = sidx * p.kchunk;
+  const int64_t kend = (kbeg + p.kchunk < p.Kp) ? kbeg + p.kchunk : p.Kp;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int64_t planeA = p.lda * p.Kp, planeB = p.ldb * p.Kp;
+  uint4 ra[UA], rb[UB];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < UA; ++r) {
+      const int e = tid + 256 * r;            // (plane, row, quarter)
+      const int q = e & 3, rp = e >> 2, pl = rp / BM, row = rp % BM;
+      const int64_t gm = m0 + row;
+      ra[r] = gm < p.M ? *(const uint4*)(p.A + pl * planeA + gm * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < UB; ++r) {
+      const int e = tid + 256 * r;
+      const int q = e & 3, rp = e >> 2, pl = rp / BN, row = rp % BN;
+      const int64_t gn = n0 + row;
+      rb[r] = gn < p.N ? *(const uint4*)(p.B + pl * planeB + gn * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int r = 0; r < UA; ++r) {
+      const int e = tid + 256 * r;
+      const int q = e & 3, rp = e >> 2, pl = rp / BM, row = rp % BM;
+      *(uint4*)&sA[pl][row][8 * q] = ra[r];
+    }
+#pragma unroll
+    for (int r = 0; r < UB; ++r) {
+      const int e = tid + 256 * r;
+      const int q = e & 3, rp = e >> 2, pl = rp / BN, row = rp % BN;
+      *(uint4*)&sB[pl][row][8 * q] = rb[r];
+    }
+  };
+  flt4 accR[WM][WN], accI[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      accR[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+    }
+  if (kbeg < kend) {
+    gload(kbeg);
+    sstore();
+  }
+  __syncthreads();
+  const int kq = 8 * (lane >> 4);
+  const us8 sgn = us8{0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TKB) {
+    const bool more = k0 + TKB < kend;
+    if (more) gload(k0 + TKB);
+    us8 b[WN][4];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[j][q] = *(const us8*)&sB[q][16 * WN * wc + 16 * j + (lane & 15)][kq];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      us8 a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = *(const us8*)&sA[q][16 * WM * wr + 16 * i + (lane & 15)][kq];
+      const us8 nih = a[2] ^ sgn, nil = a[3] ^ sgn;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        flt4 cr = accR[i][j], ci = accI[i][j];
+        cr = mfma_bf16(a[0], b[j][0], cr);
+        cr = mfma_bf16(a[0], b[j][1], cr);
+        cr = mfma_bf16(a[1], b[j][0], cr);
+        cr = mfma_bf16(nih, b[j][2], cr);
+        cr = mfma_bf16(nih, b[j][3], cr);
+        cr = mfma_bf16(nil, b[j][2], cr);
+        ci = mfma_bf16(a[0], b[j][2], ci);
+        ci = mfma_bf16(a[0], b[j][3], ci);
+        ci = mfma_bf16(a[1], b[j][2], ci);
+        ci = mfma_bf16(a[2], b[j][0], ci);
+        ci = mfma_bf16(a[2], b[j][1], ci);
+        ci = mfma_bf16(a[3], b[j][0], ci);
+        accR[i][j] = cr;
+        accI[i][j] = ci;
+      }
+    }
+    __syncthreads();
+    if (more) {
+      sstore();
+      __syncthreads();
+    }
+  }
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + 16 * WM * wr + 16 * i + 4 * (lane >> 4) + r;
+        const int64_t col = n0 + 16 * WN * wc + 16 * j + (lane & 15);
+        if (row < p.M && col < p.N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          if (p.nsplit > 1) {
+            p.P[(sidx * p.M + row) * p.N + col] = make_double2(cr, ci);
+            continue;
+          }
+          double2* dst = p.C + row * p.scm + col * p.scn;
+          double2 o;
+          o.x = p.alpha.re * cr - p.alpha.im * ci;
+          o.y = p.alpha.re * ci + p.alpha.im * cr;
+          if (has_beta) {
+            const double2 old = *dst;
+            o.x += p.beta.re * old.x - p.beta.im * old.y;
+            o.y += p.beta.re * old.y + p.beta.im * old.x;
+          }
+          *dst = o;
+        }
+      }
+}
+
+void launch_bf16p(const BfGemm& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
+  BfGemm h = g;
+  if (h.nsplit < 1 || h.kchunk <= 0) { h.nsplit = 1; h.kchunk = h.Kp; }
+  const int64_t big = ((h.M + 127) / 128) * ((h.N + 127) / 128) * h.nsplit;
+  const bool use_big = big >= 256 && pad_waste(h.M, 128) < 0.10 && pad_waste(h.N, 128) < 0.10;
+  if (use_big) {
+    const int64_t tiles = ((h.M + 127) / 128) * ((h.N + 127) / 128);
+    dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
+    if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16p_kernel<4, 4, 1>), grid, dim3(256), 0, s, h);
+    else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16p_kernel<4, 4, 2>), grid, dim3(256), 0, s, h);
+    else hipLaunchKernelGGL((zgemm_bf16p_kernel<4, 4, 0>), grid, dim3(256), 0, s, h);
+  } else {
+    const int64_t tiles = ((h.M + 63) / 64) * ((h.N + 63) / 64);
+    dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
+    if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16p_kernel<2, 2, 1>), grid, dim3(256), 0, s, h);
+    else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16p_kernel<2, 2, 2>), grid, dim3(256), 0, s, h);
+    else hipLaunchKernelGGL((zgemm_bf16p_kernel<2, 2, 0>), grid, dim3(256), 0, s, h);
+  }
+}
+
+__global__ void splitk_reduce_bf_kernel(BfGemm p) {
+  const int64_t total = p.M * p.N;
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = idx / p.N, n = idx - m * p.N;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < p.nsplit; ++s) {
+      const double2 v = p.P[(int64_t)s * total + idx];
+      sr += v.x;
+      si += v.y;
+    }
+    double2* dst = p.C + m * p.scm + n * p.scn;
+    double2 o;
+    o.x = p.alpha.re * sr - p.alpha.im * si;
+    o.y = p.alpha.re * si + p.alpha.im * sr;
+    if (has_beta) {
+      const double2 old = *dst;
+      o.x += p.beta.re * old.x - p.beta.im * old.y;
+      o.y += p.beta.re * old.y + p.beta.im * old.x;
+    }
+    *dst = o;
+  }
+}
+void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s) {
+  hipLaunchKernelGGL(splitk_reduce_bf_kernel, dim3(nblocks(g.M * g.N, 256)), dim3(256), 0, s, g);
+}
+
+// packed <ab||cd> rows written directly as split planes [4][npairs][Kp]
+__global__ __launch_bounds__(256) void ladder_pack_planes_kernel(const double2* W, int64_t ldw, int a0, int b0, int nv,
+                                                                 unsigned short* V, int64_t pbase, int64_t npairs,
+                                                                 const int2* pv, int64_t Pv, int64_t Kp) {
+  const int64_t pr = blockIdx.y;
+  const int2 ab = pv[pbase + pr];
+  const int64_t ra = (int64_t)(ab.x - a0) * nv, cb = (int64_t)(ab.y - b0) * nv;
+  const int64_t plane = npairs * Kp;
+  for (int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < Kp; pc += (int64_t)gridDim.x * blockDim.x) {
+    unsigned short h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+    if (pc < Pv) {
+      const int2 cd = pv[pc];
+      const double2 w1 = W[(ra + cd.x) * ldw + cb + cd.y];
+      const double2 w2 = W[(ra + cd.y) * ldw + cb + cd.x];
+      split_bf16((float)(w1.x - w2.x), h0, l0);
+      split_bf16((float)(w1.y - w2.y), h1, l1);
+    }
+    const int64_t o = pr * Kp + pc;
+    V[o] = h0;
+    V[plane + o] = l0;
+    V[2 * plane + o] = h1;
+    V[3 * plane + o] = l1;
+  }
+}
+void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
+                               int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s) {
+  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+  if (npairs <= 0 || Pv <= 0) return;
+  unsigned gx = (unsigned)((Kp + 255) / 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(ladder_pack_planes_kernel, dim3(gx, (unsigned)npairs), dim3(256), 0, s, W, ldw, a0, b0, nv, V,
+                     pbase, npairs, pv, Pv, Kp);
+}
+
 template <typename T, int WM, int WN>
 static void launch_tile(const GemmDesc& g, hipStream_t s) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
@@ -417,8 +668,6 @@ static void launch_tile(const GemmDesc& g, hipStream_t s) {
 // Tile choice: the big tile (FP64 128x64, FP32 128x128) halves the operand
 // traffic per MFMA but pads M and N to multiples of 128; it is used only when
 // the padding wastes under 10% and the grid still fills the chip.
-static double pad_waste(int64_t n, int64_t t) { return (double)(((n + t - 1) / t) * t - n) / (double)n; }
-
 void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0 || g0.K <= 0) return;
   GemmDesc g = g0;
