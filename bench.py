@@ -87,6 +87,10 @@ def main():
     ap.add_argument("--precision", default="split_bf16", choices=["fp32", "split_bf16", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
+    ap.add_argument("--only-ladder", action="store_true",
+                    help="time only the ladder term (for counter runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is a "
@@ -108,6 +112,20 @@ def main():
     S = torch.empty_like(Y)
     print(f"[bench] C2 dim={h.dim} init {h.init_ms:.0f} ms; timing {args.precision}", file=sys.stderr, flush=True)
 
+    if args.calib_copy:
+        src = torch.empty(1 << 26, dtype=torch.complex128, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 1073741824 bytes read, 1073741824 bytes written", file=sys.stderr,
+              flush=True)
+        del src, dst
+    if args.only_ladder:
+        ms_lad = time_calls(lambda: h.sigma_term("ladder", Y, S, precision=args.precision), args.steps,
+                            args.warmup, stream)
+        print(f"[bench] ladder term {ms_lad:.2f} ms", file=sys.stderr, flush=True)
+        h.close()
+        return
     ms = time_calls(lambda: h.sigma(Y, S, precision=args.precision), args.steps, args.warmup, stream)
     print(f"[bench] {args.precision} sigma {ms:.2f} ms/build", file=sys.stderr, flush=True)
     ms64 = time_calls(lambda: h.sigma(Y, S, precision="fp64"), max(3, args.steps // 2), 1, stream)
@@ -140,6 +158,7 @@ def main():
                  "tflops_core": flops / (ms64 * 1e-3) / 1e12},
         "speedup_vs_fp64": ms64 / ms,
         "init_ms": h.init_ms,
+        "init_wall_s": init_wall,
         "roofline": {"bound": "mfma", "kernel": "ladder term (assembly GEMM + pack + contraction GEMM)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None, "ms_per_launch": ms_lad, "flop_per_launch": lad_flops,
