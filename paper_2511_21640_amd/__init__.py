@@ -161,6 +161,29 @@ class Handle:
             raise AdcError(rc, "adc_sigma_term")
         return S.reshape(Y.shape)
 
+    def sigma_backward(self, Sbar, Y, want_dL=True, want_dx=True):
+        """Vector-Jacobian product of the sigma build (see adc_sigma_backward):
+        gradients of f = Re sum_z Sbar_z^H M(L, x) Y_z.  Returns (dL, dx): dL a
+        complex128 cuda tensor shaped like L, Hermitian-projected per Q (or
+        None), dx a float (or None)."""
+        import torch
+        for T in (Sbar, Y):
+            assert T.is_cuda and T.dtype == torch.complex128 and T.is_contiguous() and T.shape[-1] == self.dim
+        Y2 = Y.reshape(-1, self.dim)
+        S2 = Sbar.reshape(-1, self.dim)
+        assert S2.shape == Y2.shape
+        n = self.o + self.v
+        n_chol = int(self._L.shape[0])
+        dL = torch.empty((n_chol, n, n), dtype=torch.complex128, device=Y.device) if want_dL else None
+        dx = ctypes.c_double(0.0)
+        torch.cuda.current_stream().synchronize()
+        rc = self._lib.adc_sigma_backward(self._h, 0, ctypes.c_void_p(S2.data_ptr()), ctypes.c_void_p(Y2.data_ptr()),
+                                          Y2.shape[0], ctypes.c_void_p(dL.data_ptr()) if dL is not None else None,
+                                          ctypes.byref(dx) if want_dx else None)
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_sigma_backward")
+        return dL, (dx.value if want_dx else None)
+
     def davidson(self, guess=None, want_vectors=True):
         import torch
         k = self.n_roots

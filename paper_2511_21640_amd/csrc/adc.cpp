@@ -49,6 +49,7 @@ struct Inst {
   Tensor ring;            // [k][c][j][b] = <kb||jc>
   Tensor t1;              // [o][o][v][v]
   Tensor M11x;            // n1 x n1, M11(0..2) + x M11(3)
+  Tensor M11b;            // n1 x n1, M11(3) (the x derivative of M11x)
   Tensor W;               // EE: [I][J][i][B] = sum_cd t*_IJcd <cd||iB>
   Tensor W5;              // EE: [J][A][a][B] = sum_kc conj(t[J,k,A,c]) conj(<kB||ac>)
   Tensor W6;              // EE: [I][B][J][i] = sum_kc t*_IkBc conj(<ik||Jc>)
@@ -145,9 +146,23 @@ void ring_bf16(adc_handle* h, Inst& I, const double2* X, int64_t rows, double2* 
 // particle-particle ladder:  S[z][offS + ij*Pv + ab] += alpha * sum_{c<d} <ab||cd> Y[z][offY + ij*Pv + cd]
 // for rows ij in [0, nrow), z in [0, k).  L_vv is [Q][v][v].
 // ----------------------------------------------------------------------------
+void ladder_backward(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY);
+
 void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY, double2* S, int64_t ldS,
             int64_t offS, int64_t nrow, int k, cplx alpha, int prec) {
   Ctx& cx = h->cx;
+  if (cx.tape && cx.tape->recording) {
+    TapeOp op{};
+    op.kind = TapeOp::LADDER;
+    op.A.p = const_cast<double2*>(Y);
+    op.C.p = S;
+    op.alpha = alpha;
+    op.n[0] = ldY; op.n[1] = offY; op.n[2] = ldS; op.n[3] = offS; op.n[4] = nrow; op.n[5] = k;
+    op.inst = &I;
+    op.owner = h;
+    op.ladder_bw = ladder_backward;
+    tape_record(cx, op);
+  }
   const int v = I.v;
   const int64_t Pv = I.Pv, N = I.N;
   if (Pv == 0 || nrow == 0 || k == 0) return;
@@ -242,8 +257,9 @@ void rows_in(Ctx& cx, const double2* src, int64_t ld, int64_t off, Tensor& dst, 
   launch_permute(2, od, is, os, src + off, dst.p, C1(), C0(), 0, cx.stream);
 }
 void rows_out(Ctx& cx, const Tensor& src, double2* dst, int64_t ld, int64_t off, int k, int64_t n, cplx beta) {
-  int64_t od[2] = {k, n}, is[2] = {n, 1}, os[2] = {ld, 1};
-  launch_permute(2, od, is, os, src.p, dst + off, C1(), beta, 0, cx.stream);
+  Tensor s = tensor_view(src.p, {k, n}, {n, 1});
+  Tensor d = tensor_view(dst + off, {k, n}, {ld, 1});
+  perm(cx, C1(), s, "zp", false, beta, d, "zp");
 }
 
 // ============================================================================
@@ -285,16 +301,16 @@ void init_amplitudes(adc_handle* h, Inst& I, Pre& P) {
   Tensor& t = I.t1;
   t = tnew(cx, {o, o, v, v}, false);
   perm(cx, C1(), I.oovv, "ijab", true, C0(), t, "ijab");
-  launch_div_d2(t.p, I.eps, o, v, cx.stream);
+  rec_div_d2(cx, t, I.eps, o, v);
   // second-order doubles: (particle ladder + hole ladder - ring) / D
   const int64_t Po = I.Po, Pv = I.Pv;
   P.Lt = tnew(cx, {o, o, v, v}, true);
   if (Po > 0) {
     Tensor tpk = tnew(cx, {Po * Pv}, false);
-    launch_pack_doubles(0, t.p, tpk.p, nullptr, Po * Pv, 0, 1, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+    rec_pack_doubles(cx, 0, t, tpk.p, nullptr, Po * Pv, 0, 1, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v);
     Tensor Ltp = tnew(cx, {Po * Pv});
     ladder(h, I, tpk.p, Po * Pv, 0, Ltp.p, Po * Pv, 0, Po, 1, C1(), 0);
-    launch_unpack_doubles(0, Ltp.p, Po * Pv, 0, 1, o, v, P.Lt.p, nullptr, cx.stream);
+    rec_unpack_doubles(cx, 0, Ltp.p, Po * Pv, 0, 1, o, v, P.Lt, I.eps, I.pair_o, I.pair_v);
     tfree(cx, Ltp);
     tfree(cx, tpk);
   }
@@ -308,16 +324,16 @@ void init_amplitudes(adc_handle* h, Inst& I, Pre& P) {
     ctr(cx, C1(), t, "ikac", false, I.ovov, "kbjc", false, C0(), R, "iajb");
     Tensor Rr = tnew(cx, {o, o, v, v}, false);
     perm(cx, C1(), R, "iajb", false, C0(), Rr, "ijab");
-    launch_antisym_add(Rr.p, P.t2.p, 1, o, o, v, v, 2, CR(-1), cx.stream);
+    rec_antisym_add(cx, Rr, P.t2, 1, o, o, v, v, 2, CR(-1));
     tfree(cx, R);
     tfree(cx, Rr);
   }
-  launch_div_d2(P.t2.p, I.eps, o, v, cx.stream);
+  rec_div_d2(cx, P.t2, I.eps, o, v);
   // second-order singles
   P.ts = tnew(cx, {o, v});
   ctr(cx, CR(-0.5), I.ovvv, "jabc", false, t, "ijbc", false, C0(), P.ts, "ia");
   ctr(cx, CR(-0.5), I.ooov, "jkib", false, t, "jkab", false, C1(), P.ts, "ia");
-  launch_div_d1(P.ts.p, I.eps, o, v, cx.stream);
+  rec_div_d1(cx, P.ts, I.eps, o, v);
 }
 
 // Pieces of M11 that carry delta_aA (f_o, occupied x occupied) and delta_iI
@@ -401,8 +417,8 @@ void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector
   Ctx& cx = h->cx;
   const int64_t n1 = I.n1;
   Tensor MA = tnew(cx, {n1, n1}, false), MB = tnew(cx, {n1, n1}, false);
-  launch_herm_add(f2.p, MA.p, n1, cx.stream);
-  launch_herm_add(f3.p, MB.p, n1, cx.stream);
+  rec_herm_add(cx, f2, MA, n1);
+  rec_herm_add(cx, f3, MB, n1);
   double* dd = (double*)cx.pool.get(n1);
   hipcheck(hipMemcpyAsync(dd, d.data(), sizeof(double) * n1, hipMemcpyHostToDevice, cx.stream), "d1");
   launch_add_diag(MA.p, dd, n1, cx.stream);
@@ -412,7 +428,7 @@ void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector
   hipcheck(hipStreamSynchronize(cx.stream), "m11 sync");
   cx.pool.put((double2*)dd);
   tfree(cx, MA);
-  tfree(cx, MB);
+  I.M11b = MB;
 }
 
 // ============================================================================
@@ -429,10 +445,10 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   // order <= 2: X2 = 1/2 t(ikac) <Ik||Ac> + delta parts; M11 = herm(X) + M11(1) + M11(0)
   Tensor X2 = tnew(cx, {o, v, o, v});
   ctr(cx, CR(0.5), t, "ikac", false, I.oovv, "IkAc", false, C1(), X2, "iaIA");
-  launch_m11_add_delta(X2.p, fv2.p, o, v, 0, cx.stream);
-  launch_m11_add_delta(X2.p, fo2.p, o, v, 1, cx.stream);
+  rec_m11_add_delta(cx, X2, fv2, o, v, 0);
+  rec_m11_add_delta(cx, X2, fo2, o, v, 1);
   Tensor MA = tnew(cx, {n1, n1}, false);
-  launch_herm_add(X2.p, MA.p, n1, cx.stream);
+  rec_herm_add(cx, X2, MA, n1);
   {
     Tensor MAv = tensor_view(MA.p, {o, v, o, v}, {});
     perm(cx, CR(-1), I.ovov, "jaib", false, C1(), MAv, "iajb");   // <aj||ib> = -<ja||ib>
@@ -478,16 +494,20 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
     int64_t na = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
     na = std::min<int64_t>(na, v);
-    Tensor G = tnew(cx, {na, v, v, v}, false);
+    // under a tape every block gets its own buffer (the reverse sweep reads them all)
+    const bool taped = cx.tape && cx.tape->recording;
+    Tensor G = taped ? Tensor{} : tnew(cx, {na, v, v, v}, false);
     for (int64_t a0 = 0; a0 < v; a0 += na) {
       const int64_t a1 = std::min<int64_t>(v, a0 + na);
-      Tensor Gs = tslice(G, 0, 0, a1 - a0);
+      Tensor Gb = taped ? tnew(cx, {a1 - a0, v, v, v}, false) : Tensor{};
+      Tensor Gs = taped ? Gb : tslice(G, 0, 0, a1 - a0);
       Tensor Ls = tslice(I.Lvv, 1, a0, a1);
       ctr(cx, C1(), Ls, "Qae", false, I.Lvv, "QcA", false, C0(), Gs, "aecA");
       Tensor Xs = tslice(X, 1, a0, a1);
       ctr(cx, CR(-0.5), Gs, "aecA", false, Rr, "Iice", false, C1(), Xs, "iaIA");
+      if (taped) tfree(cx, Gb);
     }
-    tfree(cx, G);
+    if (!taped) tfree(cx, G);
     tfree(cx, Rr);
   }
   {
@@ -517,16 +537,19 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
     int64_t nA = std::max<int64_t>(1, (int64_t)(budget / 4 / sizeof(double2)) / ((int64_t)v * v * v));
     nA = std::min<int64_t>(nA, v);
-    Tensor G = tnew(cx, {nA, v, v, v}, false);
+    const bool taped = cx.tape && cx.tape->recording;
+    Tensor G = taped ? Tensor{} : tnew(cx, {nA, v, v, v}, false);
     for (int64_t A0 = 0; A0 < v; A0 += nA) {
       const int64_t A1 = std::min<int64_t>(v, A0 + nA);
-      Tensor Gs = tslice(G, 0, 0, A1 - A0);
+      Tensor Gb = taped ? tnew(cx, {A1 - A0, v, v, v}, false) : Tensor{};
+      Tensor Gs = taped ? Gb : tslice(G, 0, 0, A1 - A0);
       Tensor ts_ = tslice(t, 2, A0, A1);
       ctr(cx, C1(), ts_, "klAc", true, t, "klad", false, C0(), Gs, "Acad");
       Tensor Xs = tslice(X, 3, A0, A1);
       ctr(cx, CR(0.25), ov4, "Icid", false, Gs, "Acad", false, C1(), Xs, "iaIA");
+      if (taped) tfree(cx, Gb);
     }
-    tfree(cx, G);
+    if (!taped) tfree(cx, G);
   }
   {
     // +1/2 <Im||ik> N_kAma, N = t*(klAc) t(lmac)
@@ -535,14 +558,15 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     ctr(cx, CR(0.5), I.oooo, "Imik", false, Nn, "kAma", false, C1(), X, "iaIA");
     tfree(cx, Nn);
   }
-  launch_m11_add_delta(X.p, fv3.p, o, v, 0, cx.stream);
-  launch_m11_add_delta(X.p, fo3.p, o, v, 1, cx.stream);
+  rec_m11_add_delta(cx, X, fv3, o, v, 0);
+  rec_m11_add_delta(cx, X, fo3, o, v, 1);
   Tensor MB = tnew(cx, {n1, n1}, false);
-  launch_herm_add(X.p, MB.p, n1, cx.stream);
+  rec_herm_add(cx, X, MB, n1);
   I.M11x = tnew(cx, {n1, n1}, false);
   perm(cx, C1(), MA, "pq", false, C0(), I.M11x, "pq");
   perm(cx, CR(I.x), MB, "pq", false, C1(), I.M11x, "pq");
-  for (Tensor* p : {&X2, &MA, &X, &MB, &fo2, &fo3, &fv2, &fv3}) tfree(cx, *p);
+  I.M11b = MB;
+  for (Tensor* p : {&X2, &MA, &X, &fo2, &fo3, &fv2, &fv3}) tfree(cx, *p);
   // coupling intermediates, independent of the trial vectors:
   // W[I,J,i,B]  = sum_cd conj(t[I,J,c,d]) conj(<iB||cd>)
   // W5[J,A,a,B] = sum_kc conj(t[J,k,A,c]) conj(<kB||ac>)
@@ -643,16 +667,16 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     Tensor T = tnew(cx, {k, o, o, v, v}, false);
     // M21(1): (Tv - Tv^ij) + (To - To^ab)
     ctr(cx, C1(), I.ovvv, "icab", true, ys, "zjc", false, C0(), T, "zijab");
-    launch_antisym_add(T.p, s2.p, k, o, o, v, v, 0, C1(), cx.stream);
+    rec_antisym_add(cx, T, s2, k, o, o, v, v, 0, C1());
     ctr(cx, C1(), I.ooov, "ijka", true, ys, "zkb", false, C0(), T, "zijab");
-    launch_antisym_add(T.p, s2.p, k, o, o, v, v, 1, C1(), cx.stream);
+    rec_antisym_add(cx, T, s2, k, o, o, v, v, 1, C1());
     if (x != 0.0) {
       // M21(2)
       Tensor Z1 = tnew(cx, {k, v, v}, false);
       ctr(cx, C1(), I.ovvv, "iBac", false, ys, "zia", false, C0(), Z1, "zBc");
       ctr(cx, C1(), t, "IJAc", false, Z1, "zBc", false, C0(), T, "zIJAB");
       ctr(cx, CR(-0.5), I.W, "IJiB", true, ys, "ziA", false, C1(), T, "zIJAB");
-      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 1, CR(x), cx.stream);
+      rec_antisym_add(cx, T, s2, k, o, o, v, v, 1, CR(x));
       tfree(cx, Z1);
       Tensor Z2 = tnew(cx, {k, o, o}, false);
       ctr(cx, C1(), I.ooov, "ikJa", false, ys, "zia", false, C0(), Z2, "zkJ");
@@ -662,10 +686,10 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
       ctr(cx, CR(-0.5), t, "klAB", false, Z4, "zklJI", false, C1(), T, "zIJAB");
       tfree(cx, Z4);
-      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 0, CR(x), cx.stream);
+      rec_antisym_add(cx, T, s2, k, o, o, v, v, 0, CR(x));
       ctr(cx, C1(), I.W5, "JAaB", true, ys, "zIa", false, C0(), T, "zIJAB");
       ctr(cx, C1(), I.W6, "IBJi", true, ys, "ziA", false, C1(), T, "zIJAB");
-      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 2, CR(x), cx.stream);
+      rec_antisym_add(cx, T, s2, k, o, o, v, v, 2, CR(x));
       // M22(1): hole ladder and ring (the particle ladder runs packed below)
       ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), s2, "zijab");
       Tensor R = tnew(cx, {k, o, v, o, v}, false);
@@ -678,13 +702,13 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
         ctr(cx, C1(), Ya, "zikac", false, I.ring, "kcjb", false, C0(), R, "ziajb");
       }
       perm(cx, C1(), R, "ziajb", false, C0(), T, "zijab");
-      launch_antisym_add(T.p, s2.p, k, o, o, v, v, 2, CR(-x), cx.stream);
+      rec_antisym_add(cx, T, s2, k, o, o, v, v, 2, CR(-x));
       tfree(cx, R);
     }
     tfree(cx, T);
   }
   // pack doubles: S2 = extract(s2) + D o Y2
-  launch_pack_doubles(0, s2.p, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+  rec_pack_doubles(cx, 0, s2, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v);
   if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, Po, k, CR(x), prec);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
   for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
@@ -721,15 +745,15 @@ void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, CR(0.5 * x), I.W, "IJiA", true, ys, "zi", false, C1(), s2, "zIJA");
     Tensor T = tnew(cx, {k, o, o, v}, false);
     ctr(cx, CR(-1), I.W6, "IAJi", true, ys, "zi", false, C0(), T, "zIJA");
-    launch_antisym_add(T.p, s2.p, k, o, o, v, 1, 0, CR(x), cx.stream);
+    rec_antisym_add(cx, T, s2, k, o, o, v, 1, 0, CR(x));
     // M22(1): hole ladder and ring
     ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zkla", false, C1(), s2, "zija");
     if (prec == ADC_SPLIT_BF16) ring_bf16(h, I, Ya.p, (int64_t)k * o, T.p);
     else ctr(cx, C1(), Ya, "zikc", false, I.ring, "kcja", false, C0(), T, "zija");
-    launch_antisym_add(T.p, s2.p, k, o, o, v, 1, 0, CR(-x), cx.stream);
+    rec_antisym_add(cx, T, s2, k, o, o, v, 1, 0, CR(-x));
     tfree(cx, T);
   }
-  launch_pack_doubles(1, s2.p, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+  rec_pack_doubles(cx, 1, s2, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
   for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
   cx.prec = saved;
@@ -769,7 +793,7 @@ void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   if (x != 0.0) {
     Tensor T = tnew(cx, {k, o, v, v}, false);
     ctr(cx, C1(), I.W5, "IAaB", true, ys, "za", false, C0(), T, "zIAB");
-    launch_antisym_add(T.p, s2.p, k, o, 1, v, v, 1, CR(x), cx.stream);
+    rec_antisym_add(cx, T, s2, k, o, 1, v, v, 1, CR(x));
     Tensor Z = tnew(cx, {k, o, o, o}, false);
     ctr(cx, C1(), I.ooov, "klIa", false, ys, "za", false, C0(), Z, "zklI");
     ctr(cx, CR(-0.5 * x), t, "klAB", false, Z, "zklI", false, C1(), s2, "zIAB");
@@ -785,10 +809,10 @@ void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     } else {
       ctr(cx, C1(), Ya, "zjac", false, I.ring, "jcib", false, C0(), T, "ziab");
     }
-    launch_antisym_add(T.p, s2.p, k, o, 1, v, v, 1, CR(-x), cx.stream);
+    rec_antisym_add(cx, T, s2, k, o, 1, v, v, 1, CR(-x));
     tfree(cx, T);
   }
-  launch_pack_doubles(2, s2.p, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v, cx.stream);
+  rec_pack_doubles(cx, 2, s2, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v);
   if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, o, k, CR(x), prec);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
   for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
@@ -1155,12 +1179,23 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     }
     m = k;
   }
-  sigma_dispatch(h, I, V, S, m, prec);
+  auto now = []() { return std::chrono::steady_clock::now(); };
+  auto ms_since = [](std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+  };
+  double t_sigma = 0.0, t_sub = 0.0, t_orth = 0.0;
+  {
+    auto t0 = now();
+    sigma_dispatch(h, I, V, S, m, prec);
+    hipcheck(hipStreamSynchronize(cx.stream), "sigma sync");
+    t_sigma += ms_since(t0);
+  }
   std::vector<double> w_old(k, 1e300), w(k), rn(k);
   std::vector<int> conv(k, 0);
   int it = 0;
   bool refined_phase = (prec == 0);
   for (it = 1; it <= max_iter; ++it) {
+    auto t_it = now();
     auto G = gram(h, V, m, S, m, dim);
     for (int a = 0; a < m; ++a)
       for (int b = a; b < m; ++b) {
@@ -1187,8 +1222,10 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       conv[r] = (rn[r] <= tol_now && std::fabs(w[r] - w_old[r]) <= (refined_phase ? 1e-10 : 1e-7)) ? 1 : 0;
       all = all && conv[r];
     }
+    t_sub += ms_since(t_it);
     if (h->opt.verbose) {
-      std::fprintf(stderr, "[adc] it %3d m %3d prec %d", it, m, prec);
+      std::fprintf(stderr, "[adc] it %3d m %3d prec %d (sigma %.0f sub %.0f orth %.0f ms)", it, m, prec, t_sigma,
+                   t_sub, t_orth);
       for (int r = 0; r < k; ++r) std::fprintf(stderr, "  %.10f (%.1e)", w[r], rn[r]);
       std::fprintf(stderr, "\n");
     }
@@ -1234,11 +1271,16 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       cx.pool.put(T);
       m = mc;
     }
+    auto t_o = now();
     const int nk = orthonormalize(h, V, m, Nd, nn, dim);
+    t_orth += ms_since(t_o);
     if (nk > 0) {
       hipcheck(hipMemcpyAsync(V + (int64_t)m * dim, Nd, sizeof(double2) * nk * dim, hipMemcpyDeviceToDevice,
                               cx.stream), "app");
+      auto t_s = now();
       sigma_dispatch(h, I, V + (int64_t)m * dim, S + (int64_t)m * dim, nk, prec);
+      hipcheck(hipStreamSynchronize(cx.stream), "sigma sync");
+      t_sigma += ms_since(t_s);
       m += nk;
     }
     cx.pool.put(Nd);
@@ -1258,6 +1300,161 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   for (int r = 0; r < k; ++r)
     if (!conv[r]) return ADC_NOT_CONVERGED;
   return ADC_OK;
+}
+
+// ============================================================================
+// adjoint of the sigma build
+// ============================================================================
+// Reverse rule of the particle-particle ladder S[z][r][ab] += alpha sum_{c<d}
+// <ab||cd> Y[z][r][cd], with <ab||cd> = sum_Q (L_ac L_bd - L_ad L_bc):
+//  * Y: the packed <ab||cd> matrix is Hermitian, so G_Y += conj(alpha) ladder(G_S);
+//  * L_vv: with Gamma[ab][cd] = alpha sum_{z,r} conj(G_S[z][r][ab]) Y[z][r][cd]
+//    and its extension G4[a][b][c][d] = sign(b-a) sign(d-c) Gamma[pair(a,b)][pair(c,d)]
+//    (zero on a==b or c==d), G_L[Q][a][c] += sum_{b,d} conj(G4[a][b][c][d] L[Q][b][d]).
+//    G4 is formed per block of a from Gamma and contracted at once (never stored whole).
+void ladder_backward(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY) {
+  adc_handle* h = (adc_handle*)op.owner;
+  Inst& I = *(Inst*)op.inst;
+  const int v = I.v;
+  const int64_t Pv = I.Pv, N = I.N;
+  const int64_t ldY = op.n[0], offY = op.n[1], ldS = op.n[2], offS = op.n[3], nrow = op.n[4];
+  const int k = (int)op.n[5];
+  if (Pv == 0 || nrow == 0 || k == 0) return;
+  if (gY) ladder(h, I, gS, ldS, offS, gY, ldY, offY, nrow, k, {op.alpha.re, -op.alpha.im}, 0);
+  Tensor Gam = tnew(cx, {Pv, Pv}, false);
+  {
+    Tensor gSv = tensor_view(const_cast<double2*>(gS) + offS, {k, nrow, Pv}, {ldS, Pv, 1});
+    Tensor Yv = tensor_view(op.A.p + offY, {k, nrow, Pv}, {ldY, Pv, 1});
+    ctr(cx, op.alpha, gSv, "zrp", true, Yv, "zrq", false, C0(), Gam, "pq");
+  }
+  Tensor GL = grad_view(cx, I.Lvv);
+  const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
+  int64_t nx = std::max<int64_t>(1, (int64_t)(budget / 2 / sizeof(double2)) / ((int64_t)v * v * v));
+  nx = std::min<int64_t>(nx, v);
+  Tensor G4 = tnew(cx, {nx, v, v, v}, false);
+  for (int64_t x0 = 0; x0 < v; x0 += nx) {
+    const int64_t x1 = std::min<int64_t>(v, x0 + nx);
+    launch_expand_gamma(Gam.p, Pv, (int)x0, (int)x1, v, G4.p, cx.stream);
+    Tensor Gs = tslice(G4, 0, 0, x1 - x0);
+    Tensor GLs = tslice(GL, 1, x0, x1);
+    ctr(cx, C1(), Gs, "xybd", true, I.Lvv, "Qbd", true, C1(), GLs, "Qxy");
+  }
+  tfree(cx, G4);
+  tfree(cx, Gam);
+  (void)N;
+}
+
+void inst_release_derived(Ctx& cx, Inst& J) {
+  for (Tensor* t : {&J.oooo, &J.ooov, &J.oovv, &J.ovov, &J.ovvv, &J.ring, &J.t1, &J.M11x, &J.M11b, &J.W, &J.W5,
+                    &J.W6})
+    if (t->p) tfree(cx, *t);
+}
+
+// f = Re sum_z Sbar_z^H M(L, x) Y_z.  dL (device, [N][n][n]) receives the
+// Hermitian-projected G_L; *dx = f(x + 1) - f(x) (M is affine in x).
+void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* Y, int k, double2* dL, double* dx) {
+  Ctx& cx = h->cx;
+  const int o = I.o, v = I.v, n = o + v, N = I.N;
+  const int64_t dim = I.dim;
+  const int saved_prec = cx.prec;
+  cx.prec = 0;
+  hipcheck(hipStreamSynchronize(cx.stream), "bw sync");
+  if (dx) {
+    Tensor S0 = tnew(cx, {k, dim}, false), S1 = tnew(cx, {k, dim}, false);
+    sigma_dispatch(h, I, Y, S0.p, k, 0);
+    Tensor Mx = tnew(cx, {I.n1, I.n1}, false);
+    perm(cx, C1(), I.M11x, "pq", false, C0(), Mx, "pq");
+    perm(cx, C1(), I.M11b, "pq", false, C1(), Mx, "pq");
+    std::swap(I.M11x, Mx);
+    const double x0 = I.x;
+    I.x = x0 + 1.0;
+    try {
+      sigma_dispatch(h, I, Y, S1.p, k, 0);
+    } catch (...) {
+      I.x = x0;
+      std::swap(I.M11x, Mx);
+      throw;
+    }
+    I.x = x0;
+    std::swap(I.M11x, Mx);
+    tfree(cx, Mx);
+    perm(cx, CR(-1), S0, "zp", false, C1(), S1, "zp");
+    Tensor Sb = tensor_view(const_cast<double2*>(Sbar), {1, (int64_t)k * dim}, {});
+    Tensor D = tensor_view(S1.p, {(int64_t)k * dim, 1}, {});
+    Tensor r = tnew(cx, {1, 1}, false);
+    ctr(cx, C1(), Sb, "yp", true, D, "px", false, C0(), r, "yx");
+    double2 hv;
+    hipcheck(hipMemcpyAsync(&hv, r.p, sizeof(double2), hipMemcpyDeviceToHost, cx.stream), "dx");
+    hipcheck(hipStreamSynchronize(cx.stream), "dx sync");
+    *dx = hv.x;
+    for (Tensor* t : {&S0, &S1, &r}) tfree(cx, *t);
+  }
+  if (dL) {
+    Tape T;
+    Inst J;
+    struct Cleanup {
+      Ctx& cx;
+      Inst& J;
+      int prec;
+      ~Cleanup() {
+        tape_release(cx);
+        inst_release_derived(cx, J);
+        cx.pool.trim();
+        cx.prec = prec;
+      }
+    } cleanup{cx, J, saved_prec};
+    cx.tape = &T;
+    cx.pool.tape = &T;
+    for (Tensor* leaf : {&I.Loo, &I.Lov, &I.Lvo, &I.Lvv}) {
+      T.add(leaf->p, sizeof(double2) * (size_t)leaf->size(), true);
+      T.allocs.back().ref = true;
+    }
+    // fresh copies of the constant operands, so every recorded pointer is tracked
+    Tensor Yc = tnew(cx, {k, dim}, false), Sg = tnew(cx, {k, dim}, false);
+    hipcheck(hipMemcpyAsync(Yc.p, Y, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "bw Y");
+    J.kind = I.kind; J.o = o; J.v = v; J.N = N; J.k = I.k; J.x = I.x;
+    J.n1 = I.n1; J.n2 = I.n2; J.dim = dim; J.Po = I.Po; J.Pv = I.Pv;
+    J.eps = I.eps; J.Loo = I.Loo; J.Lov = I.Lov; J.Lvo = I.Lvo; J.Lvv = I.Lvv;
+    J.pair_o = I.pair_o; J.pair_v = I.pair_v; J.diag = I.diag;
+    std::vector<double> eps_h(n);
+    hipcheck(hipMemcpy(eps_h.data(), I.eps, sizeof(double) * n, hipMemcpyDeviceToHost), "bw eps");
+    T.recording = true;
+    init_integrals(h, J);
+    {
+      Pre P;
+      init_amplitudes(h, J, P);
+      if (J.kind == ADC_EE) ee_init(h, J, P, eps_h);
+      else if (J.kind == ADC_IP) ip_init(h, J, P, eps_h);
+      else ea_init(h, J, P, eps_h);
+      for (Tensor* q : {&P.Lt, &P.Ht, &P.t2, &P.ts}) tfree(cx, *q);
+    }
+    sigma_dispatch(h, J, Yc.p, Sg.p, k, 0);
+    T.recording = false;
+    {
+      Tensor gS = grad_view(cx, Sg);
+      hipcheck(hipMemcpyAsync(gS.p, Sbar, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "bw seed");
+    }
+    tape_backward(cx);
+    // gather the four class blocks into [N][n][n], then project onto Hermitian L^Q
+    Tensor G = tnew(cx, {N, n, n}, true);
+    auto put = [&](Tensor& leaf, int r0, int c0) {
+      const int i = T.find(leaf.p);
+      if (i < 0 || !T.allocs[i].grad) return;
+      Tensor g = grad_view(cx, leaf);
+      Tensor dst = tensor_view(G.p + (int64_t)r0 * n + c0, leaf.d, {(int64_t)n * n, n, 1});
+      perm(cx, C1(), g, "Qpq", false, C0(), dst, "Qpq");
+    };
+    put(I.Loo, 0, 0);
+    put(I.Lov, 0, o);
+    put(I.Lvo, o, 0);
+    put(I.Lvv, o, o);
+    launch_herm_project(G.p, dL, N, n, cx.stream);
+    tfree(cx, G);
+    tfree(cx, Yc);
+    tfree(cx, Sg);
+    hipcheck(hipStreamSynchronize(cx.stream), "bw end");
+  }
+  cx.prec = saved_prec;
 }
 
 template <class F>
@@ -1373,8 +1570,22 @@ int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* c
 }
 
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k, void* dL, double* dx) {
-  (void)h; (void)inst; (void)Sbar; (void)Y; (void)k; (void)dL; (void)dx;
-  return ADC_ERR_UNSUPPORTED;
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Sbar || !Y || k < 0) return ADC_ERR_INVALID_ARG;
+  return guarded([&]() {
+    Inst& I = h->inst[inst];
+    if (k == 0) {
+      if (dL) {
+        const int64_t n = I.o + I.v;
+        launch_fill((double2*)dL, (int64_t)I.N * n * n, C0(), h->cx.stream);
+        hipcheck(hipStreamSynchronize(h->cx.stream), "bw zero");
+      }
+      if (dx) *dx = 0.0;
+      return ADC_OK;
+    }
+    sigma_backward(h, I, (const double2*)Sbar, (const double2*)Y, k, (double2*)dL, dx);
+    hipcheck(hipGetLastError(), "backward launch");
+    return ADC_OK;
+  });
 }
 
 double adc_init_ms(const adc_handle* h) { return h ? h->init_ms : 0.0; }

@@ -49,11 +49,22 @@ double2* Pool::get(int64_t n) {
   }
   used_.push_back(b);
   in_use_ += b.bytes;
+  if (tape) tape->add(b.p, b.bytes, false);
   return (double2*)b.p;
 }
 
 void Pool::put(double2* p) {
   if (!p) return;
+  if (tape) {
+    const int i = tape->find(p);
+    if (i >= 0 && tape->allocs[i].base == (uintptr_t)p) {
+      if (tape->allocs[i].ref) {
+        tape->deferred.push_back(p);
+        return;
+      }
+      tape->allocs.erase(tape->allocs.begin() + i);
+    }
+  }
   for (size_t i = 0; i < used_.size(); ++i) {
     if (used_[i].p == p) {
       in_use_ -= used_[i].bytes;
@@ -216,7 +227,58 @@ void permute_into(Ctx& cx, const Tensor& src, const View& v, const std::string& 
 
 }  // namespace
 
+void tape_record(Ctx& cx, TapeOp op) {
+  Tape* t = cx.tape;
+  if (!t || !t->recording) return;
+  bool rg = op.kind == TapeOp::LADDER;  // the ladder always reads L_vv
+  for (const Tensor* x : {&op.A, &op.B}) rg = rg || (x->p && t->rg(x->p));
+  const int ic = op.C.p ? t->find(op.C.p) : -1;
+  // an op is kept when a gradient can flow through it, or when it overwrites
+  // a tensor that carries one (the sweep must then clear that gradient)
+  if (!rg && !(ic >= 0 && t->allocs[ic].rg)) return;
+  // the sweep reads operand values of products (and the ladder's trial
+  // vectors); a later write into such a buffer would corrupt them
+  if (ic >= 0 && t->allocs[ic].needed)
+    throw std::logic_error("recorded op overwrites a buffer whose values the reverse sweep needs");
+  if (rg && ic >= 0) t->allocs[ic].rg = true;
+  for (const Tensor* x : {&op.A, &op.B, &op.C}) {
+    const int i = x->p ? t->find(x->p) : -1;
+    if (i >= 0) t->allocs[i].ref = true;
+  }
+  auto need = [&](const Tensor& x) {
+    const int i = x.p ? t->find(x.p) : -1;
+    if (i >= 0) t->allocs[i].needed = true;
+  };
+  if (op.kind == TapeOp::CTR) {
+    if (t->rg(op.B.p)) need(op.A);
+    if (t->rg(op.A.p)) need(op.B);
+  } else if (op.kind == TapeOp::LADDER) {
+    need(op.A);
+  }
+  t->ops.push_back(std::move(op));
+}
+
+namespace {
+struct Pause {
+  Tape* t;
+  bool was;
+  explicit Pause(Ctx& cx) : t(cx.tape), was(cx.tape ? cx.tape->recording : false) {
+    if (t) t->recording = false;
+  }
+  ~Pause() {
+    if (t) t->recording = was;
+  }
+};
+}  // namespace
+
 void perm(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, cplx beta, Tensor& C, const char* lc) {
+  if (cx.tape && cx.tape->recording) {
+    TapeOp op{};
+    op.kind = TapeOp::PERM;
+    op.A = A; op.C = C; op.la = la; op.lc = lc; op.cA = cA; op.alpha = alpha; op.beta = beta;
+    tape_record(cx, op);
+  }
+  Pause pause(cx);
   View va = view_of(A, la);
   View vc = view_of(C, lc);
   for (auto& kv : vc.size)
@@ -246,6 +308,14 @@ Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi) {
 
 void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Tensor& B, const char* lb, bool cB,
          cplx beta, Tensor& C, const char* lc) {
+  if (cx.tape && cx.tape->recording) {
+    TapeOp op{};
+    op.kind = TapeOp::CTR;
+    op.A = A; op.B = B; op.C = C; op.la = la; op.lb = lb; op.lc = lc;
+    op.cA = cA; op.cB = cB; op.alpha = alpha; op.beta = beta;
+    tape_record(cx, op);
+  }
+  Pause pause(cx);
   View va = view_of(A, la), vb = view_of(B, lb), vc = view_of(C, lc);
   std::string sa(la), sb(lb), sc(lc);
   std::string bat, Ml, Nl, Kl;

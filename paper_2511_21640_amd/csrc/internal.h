@@ -103,6 +103,15 @@ void launch_antisym_add(const double2* X, double2* out, int64_t k, int64_t d1, i
 void launch_ladder_pack(const double2* W, int64_t ldw, int a0, int b0, int nv, double2* V, int64_t pbase,
                         int64_t npairs, const int2* pair_v, hipStream_t s);
 
+// adjoint helpers
+// gf[a][A] += sum_i gX[(i,a),(i,A)] (which 0) or gf[i][I] += sum_a gX[(i,a),(I,a)] (which 1)
+void launch_m11_delta_adjoint(const double2* gX, double2* gf, int no, int nv, int which, hipStream_t s);
+// G[(x-x0)*nv + y][b*nv + d] = Gamma'[pair(x,b)][pair(y,d)] with the signs of
+// the antisymmetric extension (zero when x==b or y==d), for x in [x0, x1)
+void launch_expand_gamma(const double2* Gam, int64_t Pv, int x0, int x1, int nv, double2* G, hipStream_t s);
+// dL[Q][p][q] = (G[Q][p][q] + conj(G[Q][q][p])) / 2
+void launch_herm_project(const double2* G, double2* dL, int64_t nq, int64_t n, hipStream_t s);
+
 // Davidson helpers
 // partial[r*nb + blk] = sum_i conj(X[r][i]) Y[r][i] over the block's chunk
 void launch_row_dots(const double2* X, int64_t ldx, const double2* Y, int64_t ldy, int rows, int64_t n,
@@ -124,9 +133,12 @@ struct Tensor {
   }
 };
 
+struct Tape;
+
 class Pool {
  public:
   ~Pool();
+  Tape* tape = nullptr;  // while set, allocations are registered and frees deferred
   double2* get(int64_t n_complex);
   void put(double2* p);
   void release_all();
@@ -139,7 +151,63 @@ class Pool {
   size_t in_use_ = 0;
 };
 
+// ---------------------------------------------------------------- reverse mode
+// A tape of the device operations of one recomputed init + sigma.  The
+// backward sweep (adjoint.cpp) walks it in reverse and forms, for a real
+// objective f, gradients G_X = df/dRe X + i df/dIm X of every recorded tensor.
+struct Ctx;
+struct TapeOp;
+using LadderBw = void (*)(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY);
+
+struct TapeOp {
+  enum Kind { CTR, PERM, DIV_D2, DIV_D1, ANTISYM, HERM_ADD, M11_DELTA, PACK, UNPACK, LADDER } kind;
+  Tensor A, B, C;
+  std::string la, lb, lc;
+  bool cA = false, cB = false;
+  cplx alpha{1.0, 0.0}, beta{0.0, 0.0};
+  // kind-specific integers:
+  //  ANTISYM  n = {k, d1, d2, d3, d4, which}
+  //  HERM_ADD n = {size}
+  //  M11_DELTA, DIV_*  n = {o, v, which}
+  //  PACK / UNPACK  n = {kind, ld, off, k, o, v, accumulate}
+  //  LADDER   n = {ldY, offY, ldS, offS, nrow, k}
+  int64_t n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const double* eps = nullptr;
+  const int2* po = nullptr;
+  const int2* pv = nullptr;
+  void* inst = nullptr;     // LADDER: the instance whose L_vv the ladder reads
+  void* owner = nullptr;    // LADDER: the library handle
+  LadderBw ladder_bw = nullptr;
+};
+
+struct Tape {
+  bool recording = false;
+  std::vector<TapeOp> ops;
+  struct Alloc {
+    uintptr_t base;
+    size_t bytes;
+    bool rg;           // its contents depend on the differentiated input
+    bool ref;          // referenced by a recorded op: kept alive until the sweep ends
+    bool needed;       // its values are read by the sweep (an operand of a recorded product)
+    double2* grad;     // gradient buffer of the same size, or null (= zero gradient)
+  };
+  std::vector<Alloc> allocs;
+  std::vector<double2*> deferred;  // frees postponed until the sweep ends
+  int find(const void* p) const {
+    const uintptr_t q = (uintptr_t)p;
+    for (int i = (int)allocs.size() - 1; i >= 0; --i)
+      if (q >= allocs[i].base && q < allocs[i].base + allocs[i].bytes) return i;
+    return -1;
+  }
+  bool rg(const void* p) const {
+    const int i = find(p);
+    return i >= 0 && allocs[i].rg;
+  }
+  void add(const void* p, size_t bytes, bool rg_) { allocs.push_back({(uintptr_t)p, bytes, rg_, false, false, nullptr}); }
+};
+
 struct Ctx {
+  Tape* tape = nullptr;  // non-null while recording
   hipStream_t stream = nullptr;
   Pool pool;
   int prec = 0;   // arithmetic of ctr() calls
@@ -157,6 +225,28 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
 void perm(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, cplx beta, Tensor& C, const char* lc);
 
 Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero = true);
+// record an op on the tape (no-op unless recording); marks the output as
+// requiring a gradient when any input does
+void tape_record(Ctx& cx, TapeOp op);
+// reverse sweep over cx.tape (adjoint.cpp); the gradient buffers of the
+// allocations stay in the tape for the caller to read
+void tape_backward(Ctx& cx);
+// gradient view of a recorded tensor (allocated zeroed on first use)
+Tensor grad_view(Ctx& cx, const Tensor& t);
+// drop the tape: deferred frees and gradient buffers go back to the pool
+void tape_release(Ctx& cx);
+// kernel launches that are recorded on the tape when one is active
+void rec_div_d2(Ctx& cx, Tensor& t, const double* eps, int o, int v);
+void rec_div_d1(Ctx& cx, Tensor& t, const double* eps, int o, int v);
+void rec_antisym_add(Ctx& cx, const Tensor& X, Tensor& out, int64_t k, int64_t d1, int64_t d2, int64_t d3, int64_t d4,
+                     int which, cplx alpha);
+void rec_herm_add(Ctx& cx, const Tensor& X, Tensor& out, int64_t n);
+void rec_m11_add_delta(Ctx& cx, Tensor& M, const Tensor& f, int o, int v, int which);
+void rec_pack_doubles(Ctx& cx, int kind, const Tensor& U, double2* S, const double2* Y, int64_t ld, int64_t off,
+                      int k, int o, int v, const double* eps, cplx alpha, int accumulate, const int2* po,
+                      const int2* pv);
+void rec_unpack_doubles(Ctx& cx, int kind, const double2* Y, int64_t ld, int64_t off, int k, int o, int v, Tensor& Ya,
+                        const double* eps, const int2* po, const int2* pv);
 // view of t with dimension `dim` restricted to [lo, hi)
 Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi);
 void tfree(Ctx& cx, Tensor& t);

@@ -1112,4 +1112,84 @@ void launch_precondition(const double2* R, double2* N, const double* D, const do
   hipLaunchKernelGGL(precondition_kernel, dim3(nblocks((int64_t)rows * n, 256)), dim3(256), 0, s, R, N, D, w, rows, n);
 }
 
+// ---------------------------------------------------------------------------
+// adjoint helpers
+// ---------------------------------------------------------------------------
+// which 0: gf[a][A] += sum_i gX[(i,a),(i,A)] ; which 1: gf[i][I] += sum_a gX[(i,a),(I,a)]
+__global__ void m11_delta_adjoint_kernel(const double2* gX, double2* gf, int no, int nv, int which) {
+  const int64_t n1 = (int64_t)no * nv;
+  const int64_t total = which == 0 ? (int64_t)nv * nv : (int64_t)no * no;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    if (which == 0) {
+      const int64_t a = idx / nv, A = idx - a * nv;
+      for (int64_t i = 0; i < no; ++i) {
+        const double2 g = gX[(i * nv + a) * n1 + i * nv + A];
+        acc.x += g.x;
+        acc.y += g.y;
+      }
+    } else {
+      const int64_t i = idx / no, I = idx - i * no;
+      for (int64_t a = 0; a < nv; ++a) {
+        const double2 g = gX[(i * nv + a) * n1 + I * nv + a];
+        acc.x += g.x;
+        acc.y += g.y;
+      }
+    }
+    gf[idx].x += acc.x;
+    gf[idx].y += acc.y;
+  }
+}
+void launch_m11_delta_adjoint(const double2* gX, double2* gf, int no, int nv, int which, hipStream_t s) {
+  const int64_t total = which == 0 ? (int64_t)nv * nv : (int64_t)no * no;
+  if (total == 0) return;
+  hipLaunchKernelGGL(m11_delta_adjoint_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, gX, gf, no, nv, which);
+}
+
+// G[(x - x0) nv + y][b nv + d] = s * Gam[pair(x,b)][pair(y,d)],
+// s = sign(b - x) sign(d - y), zero when x == b or y == d
+__global__ __launch_bounds__(256) void expand_gamma_kernel(const double2* Gam, int64_t Pv, int x0, int x1, int nv,
+                                                           double2* G) {
+  const int64_t v = nv;
+  const int64_t total = (int64_t)(x1 - x0) * v * v * v;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = idx;
+    const int64_t d = r % v; r /= v;
+    const int64_t b = r % v; r /= v;
+    const int64_t y = r % v;
+    const int64_t x = x0 + r / v;
+    double2 out = make_double2(0.0, 0.0);
+    if (x != b && y != d) {
+      const int64_t p = x < b ? pidx(x, b, v) : pidx(b, x, v);
+      const int64_t q = y < d ? pidx(y, d, v) : pidx(d, y, v);
+      const double2 g = Gam[p * Pv + q];
+      const double s = ((b > x) == (d > y)) ? 1.0 : -1.0;
+      out = make_double2(s * g.x, s * g.y);
+    }
+    G[idx] = out;
+  }
+}
+void launch_expand_gamma(const double2* Gam, int64_t Pv, int x0, int x1, int nv, double2* G, hipStream_t s) {
+  const int64_t total = (int64_t)(x1 - x0) * nv * nv * nv;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(expand_gamma_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Gam, Pv, x0, x1, nv, G);
+}
+
+// dL[Q][p][q] = (G[Q][p][q] + conj(G[Q][q][p])) / 2
+__global__ void herm_project_kernel(const double2* G, double2* dL, int64_t nq, int64_t n) {
+  const int64_t total = nq * n * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t Q = idx / (n * n), r = idx - Q * n * n, p = r / n, q = r - p * n;
+    const double2 a = G[idx], b = G[Q * n * n + q * n + p];
+    dL[idx] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  }
+}
+void launch_herm_project(const double2* G, double2* dL, int64_t nq, int64_t n, hipStream_t s) {
+  if (nq * n * n == 0) return;
+  hipLaunchKernelGGL(herm_project_kernel, dim3(nblocks(nq * n * n, 256)), dim3(256), 0, s, G, dL, nq, n);
+}
+
 }  // namespace adc
