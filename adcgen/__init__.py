@@ -25,7 +25,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Problem", "make_problem", "CONFIGS", "config_problem", "c4_draw"]
+__all__ = ["Problem", "make_problem", "CONFIGS", "config_problem", "c4_draw", "trial_vectors",
+           "hermitian_direction", "sample_indices"]
 
 
 @dataclass
@@ -103,3 +104,28 @@ def c4_draw(n_inst: int = 64):
         kind = ("EE", "IP", "EA")[t % 3]
         out.append((kind, o, v, 6 * (o + v), k, 4100 + t))
     return out
+
+
+def trial_vectors(k: int, dim: int, seed: int) -> np.ndarray:
+    """k complex Gaussian vectors of length dim, each of unit norm."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((k, dim)) + 1j * rng.standard_normal((k, dim))
+    return Z / np.linalg.norm(Z, axis=1, keepdims=True)
+
+
+def hermitian_direction(shape, seed: int, restrict_q=None) -> np.ndarray:
+    """A perturbation of L: Hermitian in the last two indices for every Q,
+    optionally zero for Q >= restrict_q, unit Frobenius norm."""
+    rng = np.random.default_rng(seed)
+    E = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    E = 0.5 * (E + np.conj(np.transpose(E, (0, 2, 1))))
+    if restrict_q is not None:
+        E[restrict_q:] = 0.0
+    return E / np.linalg.norm(E)
+
+
+def sample_indices(size: int, n: int, seed: int) -> np.ndarray:
+    """n distinct flat indices into an array of the given size, sorted."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(size, size=min(n, size), replace=False))
+

@@ -152,8 +152,23 @@ int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* c
 enum adc_term { ADC_TERM_ALL = 0, ADC_TERM_LADDER = 1 };
 int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, int k, int precision);
 
-/* Vector-Jacobian product of adc_sigma (reserved; returns ADC_ERR_UNSUPPORTED
- * in this version). */
+/* Vector-Jacobian product of the sigma build.  For the real functional
+ *     f(L, x) = Re sum_z Sbar_z^H M(L, x) Y_z
+ * with fixed packed vectors Y, Sbar (device c128 [k][dim], caller-owned):
+ *   dL   device c128 [n_chol][n][n] (caller-owned, overwritten), the gradient
+ *        G = df/dRe L + i df/dIm L projected onto Hermitian L^Q,
+ *        (G + G^H)/2 per Q; NULL skips it.  Only Hermitian perturbations of
+ *        the Cholesky vectors keep M Hermitian (Section 2.1, eq. 10; eq. 42).
+ *   dx   host double, df/dx = f(x+1) - f(x) (M is affine in x); NULL skips.
+ * With Sbar = Y = a normalised eigenvector y_r this is the eigenvalue
+ * gradient d omega_r = y_r^H dM y_r (Hellmann-Feynman).  The gradient with
+ * respect to Y is adc_sigma applied to Sbar (M is Hermitian).
+ * The one-off work of adc_init and the sigma build are recomputed on the
+ * device in FP64 with their intermediates kept, then differentiated in
+ * reverse; the <ab||cd> gradient blocks of the particle-particle ladder are
+ * formed per batch of a from L and never stored whole.  Device memory: about
+ * twice that of adc_init plus one workspace batch.  Synchronous.  Errors:
+ * INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR. */
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k,
                        void* dL, double* dx);
 

@@ -153,3 +153,41 @@ def test_c5_root_gradients_match_finite_differences():
     print("case C5 root gradients", flush=True)
     P = config_problem("C5")
     _fd_check(P, P.n_roots, 55, restrict_q=30)
+
+
+def test_c5_vjp_matches_oracle_gradient():
+    """Adjoint configuration (EE-ADC(3), o=16, v=96, Nchol=600): the device dL
+    and dx against the oracle gradient stored by tests/golden/make_c5_adjoint.py
+    (sampled and largest entries, norms, directional derivatives)."""
+    import json
+    import os
+    import time
+
+    from adcgen import hermitian_direction, trial_vectors
+
+    print("case C5 vjp vs stored oracle gradient", flush=True)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c5_adjoint.json")) as f:
+        ref = json.load(f)
+    P = config_problem(ref["config"])
+    h = adc.Handle(P.kind, P.o, P.v, P.eps, P.L, P.n_roots, x=P.x)
+    Y = torch.from_numpy(trial_vectors(ref["k"], h.dim, ref["y_seed"])).cuda()
+    Sb = torch.from_numpy(trial_vectors(ref["k"], h.dim, ref["sbar_seed"])).cuda()
+    h.sigma_backward(Sb, Y)  # warm the workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dL, dx = h.sigma_backward(Sb, Y)
+    torch.cuda.synchronize()
+    print(f"C5 backward {1e3 * (time.perf_counter() - t0):.0f} ms (init {h.init_ms:.0f} ms)", flush=True)
+    G = dL.cpu().numpy()
+    flat = G.reshape(-1)
+    mx = ref["max_abs"]
+    for i, re, im in ref["samples"] + ref["top"]:
+        assert abs(flat[i] - complex(re, im)) <= 1e-11 * mx, (i, flat[i], re, im)
+    assert abs(np.abs(flat).max() - mx) <= 1e-11 * mx
+    assert abs(np.linalg.norm(flat) - ref["fro"]) <= 1e-11 * ref["fro"]
+    for pr in ref["projections"]:
+        D = hermitian_direction(P.L.shape, pr["seed"], restrict_q=pr["restrict_q"])
+        got = float(np.real(np.vdot(G, D)))
+        assert abs(got - pr["value"]) <= 1e-10 * ref["fro"], (pr, got)
+    assert abs(dx - ref["dx"]) <= 1e-11 * max(1.0, abs(ref["dx"])), (dx, ref["dx"])
+    h.close()
