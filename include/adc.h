@@ -93,7 +93,16 @@ typedef struct adc_problem {
  *                 and the largest temporary copy a contraction may make
  *                 before it is split into pieces [0 = 4 GiB batches, 8 GiB
  *                 copies]; results do not depend on it
- *   verbose       1 = one line per Davidson iteration on stderr */
+ *   verbose       1 = one line per Davidson iteration on stderr
+ *   n_streams     several instances: number of lanes (device streams, each
+ *                 with its own workspace) the instances are spread over,
+ *                 most expensive first [min(n_problems, 4)]; lane 0 is
+ *                 `stream`, the others are library-owned non-blocking streams
+ *                 of default priority
+ *   graphs        1 = replay each small instance's sigma build from a
+ *                 captured hipGraph inside adc_davidson [0]
+ *   autotune      1 = time the tile and split-K candidates of every GEMM
+ *                 shape class once and keep the fastest [0] */
 typedef struct adc_options {
   int precision;
   double conv_tol;
@@ -103,16 +112,20 @@ typedef struct adc_options {
   void* stream;
   size_t mem_budget;
   int verbose;
+  int n_streams;
+  int graphs;
+  int autotune;
 } adc_options;
 
 typedef struct adc_handle adc_handle;
 
-/* Validate the problem, copy eps (and L unless borrowed) to the device and
- * run the one-off work on the device: the stored integral classes <ij||kl>,
+/* Validate the problems (n_problems >= 1 independent instances, each of any
+ * kind and size), copy eps (and L unless borrowed) to the device and run the
+ * one-off work of every instance on the device: the stored integral classes <ij||kl>,
  * <ij||ka>, <ij||ab>, <ia||jb>, <ia||bc>; the MP amplitudes t(1), t(2) (with one pass
  * of the particle-particle ladder), the second-order singles; the dense
  * singles block M11 with its third-order part kept separate so that x scales
- * it.  Errors: INVALID_ARG (shapes, NULL pointers, n_problems != 1),
+ * it.  Errors: INVALID_ARG (shapes, NULL pointers, n_problems < 1),
  * NONFINITE_INPUT (NaN/Inf in eps or L), NOT_HERMITIAN (max |L^Q - L^Q^H| >
  * 1e-12 max |L^Q| for some Q), OUT_OF_MEMORY, HIP_ERROR.  On error *out is
  * NULL and nothing is leaked.  Synchronous. */
@@ -128,13 +141,18 @@ int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2);
  * (asynchronous).  Errors: INVALID_ARG, HIP_ERROR. */
 int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precision);
 
-/* Block Davidson for the n_roots lowest eigenpairs of every instance.
- *   guess[inst]  NULL, or device c128 [n_roots][dim] start vectors (resume)
- *   omega        host float64 [n_roots], ascending, hartree
- *   vecs[inst]   NULL, or device c128 [n_roots][dim] output Ritz vectors
- *   resnorm      host float64 [n_roots]   final FP64 residual norms
- *   iters        host int [n_problems]    iterations used
- *   converged    host int [n_roots]       1 if the root met the criteria
+/* Block Davidson for the n_roots lowest eigenpairs of every instance.  The
+ * per-root outputs are concatenated over the instances in order (instance i
+ * starts at the sum of n_roots of instances < i); the lanes solve their
+ * instances concurrently.
+ *   guess        NULL, or guess[inst] = NULL or device c128 [n_roots][dim]
+ *                start vectors (resume)
+ *   omega        host float64 [sum n_roots], ascending per instance, hartree
+ *   vecs         NULL, or vecs[inst] = NULL or device c128 [n_roots][dim]
+ *                output Ritz vectors
+ *   resnorm      host float64 [sum n_roots]   final FP64 residual norms
+ *   iters        host int [n_problems]        iterations used
+ *   converged    host int [sum n_roots]       1 if the root met the criteria
  * Subspace algebra (Gram matrix, Ritz vectors, residuals, norms,
  * preconditioner, orthogonalisation) runs in FP64 device kernels; the small
  * subspace eigenproblem runs on the host.  Synchronous.  Returns

@@ -39,7 +39,8 @@ class AdcProblem(ctypes.Structure):
 class AdcOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("conv_tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_subspace", ctypes.c_int), ("refine_fp64", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("mem_budget", ctypes.c_size_t), ("verbose", ctypes.c_int)]
+                ("mem_budget", ctypes.c_size_t), ("verbose", ctypes.c_int), ("n_streams", ctypes.c_int),
+                ("graphs", ctypes.c_int), ("autotune", ctypes.c_int)]
 
 
 class AdcError(RuntimeError):
@@ -96,7 +97,7 @@ class Handle:
     """
 
     def __init__(self, kind, o, v, eps, L, n_roots, x=1.0, precision="fp64", conv_tol=1e-7, max_iter=200,
-                 max_subspace=0, stream=None, mem_budget=0, verbose=False):
+                 max_subspace=0, stream=None, mem_budget=0, verbose=False, graphs=False, autotune=False):
         import torch
         self._lib = load()
         self.kind, self.o, self.v = kind, int(o), int(v)
@@ -118,7 +119,7 @@ class Handle:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1, ctypes.c_void_p(stream),
-                          mem_budget, 1 if verbose else 0)
+                          mem_budget, 1 if verbose else 0, 0, 1 if graphs else 0, 1 if autotune else 0)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(ctypes.byref(prob), 1, ctypes.byref(opts), ctypes.byref(h))
         if rc != ADC_OK:
@@ -211,3 +212,90 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+
+class Batch:
+    """Several independent instances in one handle (adc_init with
+    n_problems > 1).  problems: list of dicts with keys kind, o, v, eps, L
+    (numpy), n_roots and optionally x.  The instances are spread over
+    n_streams lanes (longest first) and solved concurrently."""
+
+    def __init__(self, problems, precision="fp64", conv_tol=1e-7, max_iter=200, max_subspace=0, stream=None,
+                 mem_budget=0, verbose=False, n_streams=0, graphs=False, autotune=False):
+        import torch
+        self._lib = load()
+        self._keep = []
+        arr = (AdcProblem * len(problems))()
+        for i, p in enumerate(problems):
+            eps = np.ascontiguousarray(p["eps"], dtype=np.float64)
+            L = np.ascontiguousarray(p["L"], dtype=np.complex128)
+            self._keep += [eps, L]
+            arr[i] = AdcProblem(KINDS[p["kind"]], int(p["o"]), int(p["v"]), int(L.shape[0]), int(p["n_roots"]),
+                                eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), L.ctypes.data, 0,
+                                float(p.get("x", 1.0)))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        opts = AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1, ctypes.c_void_p(stream), mem_budget,
+                          1 if verbose else 0, int(n_streams), 1 if graphs else 0, 1 if autotune else 0)
+        h = ctypes.c_void_p()
+        rc = self._lib.adc_init(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
+        self._keep = []  # host copies are no longer needed
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_init")
+        self._h = h
+        self.n_roots = [int(p["n_roots"]) for p in problems]
+        self.dims = []
+        for i in range(len(problems)):
+            n1, n2 = ctypes.c_longlong(), ctypes.c_longlong()
+            self._lib.adc_dims(h, i, ctypes.byref(n1), ctypes.byref(n2))
+            self.dims.append(n1.value + n2.value)
+
+    @property
+    def init_ms(self):
+        return self._lib.adc_init_ms(self._h)
+
+    def sigma(self, inst, Y, precision=None):
+        import torch
+        assert Y.is_cuda and Y.dtype == torch.complex128 and Y.is_contiguous() and Y.shape[-1] == self.dims[inst]
+        Y2 = Y.reshape(-1, self.dims[inst])
+        S = torch.empty_like(Y2)
+        p = -1 if precision is None else PREC[precision]
+        rc = self._lib.adc_sigma(self._h, inst, ctypes.c_void_p(Y2.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                 Y2.shape[0], p)
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_sigma")
+        return S.reshape(Y.shape)
+
+    def davidson(self, want_vectors=False):
+        import torch
+        n = len(self.dims)
+        tot = sum(self.n_roots)
+        omega, res = np.zeros(tot), np.zeros(tot)
+        iters = (ctypes.c_int * n)()
+        conv = (ctypes.c_int * tot)()
+        vecs = [torch.empty((k, d), dtype=torch.complex128, device="cuda") for k, d in zip(self.n_roots, self.dims)] \
+            if want_vectors else None
+        v_arr = (ctypes.c_void_p * n)(*[v.data_ptr() for v in vecs]) if vecs is not None else None
+        rc = self._lib.adc_davidson(self._h, None, omega.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), v_arr,
+                                    res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), iters, conv)
+        if rc not in (ADC_OK, ADC_NOT_CONVERGED):
+            raise AdcError(rc, "adc_davidson")
+        out, o = [], 0
+        for i, k in enumerate(self.n_roots):
+            out.append(dict(omega=omega[o:o + k], resnorm=res[o:o + k], iters=iters[i],
+                            converged=np.array(conv[o:o + k], dtype=bool),
+                            vectors=vecs[i] if vecs is not None else None))
+            o += k
+        return out, rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.adc_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -20,8 +20,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
+#include <thread>
 #include <vector>
 
 #include "../../include/adc.h"
@@ -40,6 +42,7 @@ struct Status {
 };
 
 struct Inst {
+  Ctx* cx = nullptr;      // the lane (stream + pool) this instance runs on
   int kind = 0, o = 0, v = 0, N = 0, k = 0;
   double x = 1.0;
   int64_t n1 = 0, n2 = 0, dim = 0, Po = 0, Pv = 0;
@@ -62,17 +65,37 @@ struct Inst {
   unsigned short* ringp = nullptr;  // rows (j,b), K = (k,c): conj(ring) = ring^T
   int64_t Kr = 0;
   std::vector<double> m11diag;  // host, real part of diag(M11x)
+  // captured sigma builds (Davidson of small instances): one per (rows, precision)
+  struct Graph {
+    int rows = 0, prec = 0;
+    double2* Yin = nullptr;   // staging input  [rows][dim]
+    double2* Sout = nullptr;  // staging output [rows][dim]
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    std::vector<double2*> held;  // workspace blocks reserved for the graph
+  };
+  std::vector<Graph> graphs;
 };
 
 }  // namespace
 
+// Instances are spread over lanes: lane 0 is the handle's stream, further
+// lanes have their own non-blocking streams (default priority) and pools, so
+// that independent instances overlap on the device.  Each instance lives on
+// one lane; its tensors come from that lane's pool.
 struct adc_handle {
-  Ctx cx;
+  Ctx cx;                                   // lane 0
+  std::vector<std::unique_ptr<Ctx>> extra;  // lanes 1 ..
   adc_options opt{};
   bool own_stream = false;
   double init_ms = 0.0;
   std::vector<Inst> inst;
-  std::vector<void*> raw;  // plain device allocations
+  std::vector<std::vector<int>> lane_inst;  // instances of each lane, most expensive first
+  std::vector<void*> raw;                   // plain device allocations
+  std::mutex mu;                            // guards raw
+  int device = 0;
+  Ctx& lane(int i) { return i == 0 ? cx : *extra[(size_t)i - 1]; }
+  int n_lanes() const { return 1 + (int)extra.size(); }
 };
 
 namespace {
@@ -83,6 +106,7 @@ void* dmalloc(adc_handle* h, size_t bytes) {
     (void)hipGetLastError();
     throw HipError{hipErrorOutOfMemory, "hipMalloc"};
   }
+  std::lock_guard<std::mutex> lock(h->mu);
   h->raw.push_back(p);
   return p;
 }
@@ -111,7 +135,7 @@ unsigned short* planes_alloc(Ctx& cx, int64_t rows, int64_t Kp) {
 }
 
 void ensure_planes(adc_handle* h, Inst& I) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int64_t v = I.v, ov = (int64_t)I.o * I.v;
   if (!I.Lq) {
     I.Kq = pad32(I.N);
@@ -127,7 +151,7 @@ void ensure_planes(adc_handle* h, Inst& I) {
 
 // R[r][(j,b)] = sum_(k,c) X[r][(k,c)] <kb||jc> for rows r of X (contiguous [rows][ov]), split-bf16
 void ring_bf16(adc_handle* h, Inst& I, const double2* X, int64_t rows, double2* R) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   ensure_planes(h, I);
   const int64_t ov = (int64_t)I.o * I.v;
   unsigned short* Xp = planes_alloc(cx, rows, I.Kr);
@@ -150,7 +174,7 @@ void ladder_backward(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY);
 
 void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY, double2* S, int64_t ldS,
             int64_t offS, int64_t nrow, int k, cplx alpha, int prec) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   if (cx.tape && cx.tape->recording) {
     TapeOp op{};
     op.kind = TapeOp::LADDER;
@@ -272,7 +296,7 @@ struct Pre {
 };
 
 void init_integrals(adc_handle* h, Inst& I) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v;
   I.oooo = tnew(cx, {o, o, o, o}, false);
   ctr(cx, C1(), I.Loo, "Qik", false, I.Loo, "Qjl", false, C0(), I.oooo, "ijkl");
@@ -295,7 +319,7 @@ void init_integrals(adc_handle* h, Inst& I) {
 }
 
 void init_amplitudes(adc_handle* h, Inst& I, Pre& P) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v;
   // first-order doubles t_ij^ab = <ab||ij>/D = conj(<ij||ab>)/D
   Tensor& t = I.t1;
@@ -341,7 +365,7 @@ void init_amplitudes(adc_handle* h, Inst& I, Pre& P) {
 // (f3).  The IP singles block is f_o, the EA singles block f_v, and the EE
 // singles block contains both (see ee_m11).
 void m11_fo(adc_handle* h, Inst& I, Pre& P, Tensor& f2, Tensor& f3) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o;
   const Tensor& t = I.t1;
   f2 = tnew(cx, {o, o});
@@ -371,7 +395,7 @@ void m11_fo(adc_handle* h, Inst& I, Pre& P, Tensor& f2, Tensor& f3) {
 }
 
 void m11_fv(adc_handle* h, Inst& I, Pre& P, Tensor& f2, Tensor& f3) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v, N = I.N;
   const Tensor& t = I.t1;
   f2 = tnew(cx, {v, v});
@@ -414,7 +438,7 @@ void m11_fv(adc_handle* h, Inst& I, Pre& P, Tensor& f2, Tensor& f3) {
 
 // dense n x n block: herm(f) + diag(d) for IP / EA
 void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector<double>& d) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int64_t n1 = I.n1;
   Tensor MA = tnew(cx, {n1, n1}, false), MB = tnew(cx, {n1, n1}, false);
   rec_herm_add(cx, f2, MA, n1);
@@ -435,7 +459,7 @@ void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector
 // EE
 // ============================================================================
 void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v, N = I.N;
   const int64_t n1 = I.n1;
   const Tensor& t = I.t1;
@@ -583,7 +607,7 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
 // IP and EA one-off work
 // ============================================================================
 void ip_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o;
   Tensor f2, f3;
   m11_fo(h, I, P, f2, f3);
@@ -602,7 +626,7 @@ void ip_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
 }
 
 void ea_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v;
   Tensor f2, f3;
   m11_fv(h, I, P, f2, f3);
@@ -617,7 +641,7 @@ void ea_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
 }
 
 void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v;
   const int64_t n1 = I.n1, dim = I.dim, Po = I.Po;
   const double x = I.x;
@@ -719,7 +743,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
 // IP:  singles i, doubles (i<j, a)
 // ============================================================================
 void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v;
   const int64_t n1 = I.n1, dim = I.dim;
   const double x = I.x;
@@ -763,7 +787,7 @@ void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
 // EA:  singles a, doubles (i, a<b)
 // ============================================================================
 void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v;
   const int64_t n1 = I.n1, dim = I.dim;
   const double x = I.x;
@@ -862,7 +886,7 @@ int dims_of(int kind, int64_t o, int64_t v, int64_t* n1, int64_t* n2) {
 }
 
 void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   I.kind = p->kind;
   I.o = p->n_occ;
   I.v = p->n_vir;
@@ -1022,9 +1046,84 @@ void sigma_dispatch(adc_handle* h, Inst& I, const double2* Y, double2* S, int k,
   else ea_sigma(h, I, Y, S, k, prec);
 }
 
+// Sigma build of a small instance replayed from a captured hipGraph: the
+// launch sequence of one build is fixed for given rows and precision, so it is
+// captured once (after an eager warm-up that creates every workspace block and
+// precision plane) and replayed on staging buffers.  Worth it where kernel
+// launches, not arithmetic, dominate.
+constexpr double kGraphMaxCost = 5e9;  // complex MACs of one build
+
+double inst_cost(const Inst& I) {
+  const double o = I.o, v = I.v, N = I.N, k = I.k;
+  const double Po = o * (o - 1) / 2, Pv = v * (v - 1) / 2;
+  if (I.kind == ADC_EE) return 2 * N * Pv * Pv + k * (Po * Pv * Pv + std::pow(o * v, 3) + o * o * v * v * v);
+  if (I.kind == ADC_IP) return k * (o * std::pow(o * v, 2) + Po * Po * v) + N * o * o * v * v;
+  return 2 * N * Pv * Pv + k * (o * Pv * Pv + v * std::pow(o * v, 2));
+}
+
+void sigma_call(adc_handle* h, Inst& I, const double2* Y, double2* S, int rows, int prec) {
+  Ctx& cx = *I.cx;
+  if (rows <= 0) return;
+  if (!h->opt.graphs || inst_cost(I) > kGraphMaxCost) {
+    sigma_dispatch(h, I, Y, S, rows, prec);
+    return;
+  }
+  Inst::Graph* G = nullptr;
+  for (auto& g : I.graphs)
+    if (g.rows == rows && g.prec == prec) G = &g;
+  const size_t bytes = sizeof(double2) * (size_t)rows * I.dim;
+  if (!G) {
+    Inst::Graph ng;
+    ng.rows = rows;
+    ng.prec = prec;
+    ng.Yin = (double2*)dmalloc(h, bytes);
+    ng.Sout = (double2*)dmalloc(h, bytes);
+    hipcheck(hipMemcpyAsync(ng.Yin, Y, bytes, hipMemcpyDeviceToDevice, cx.stream), "graph in");
+    sigma_dispatch(h, I, ng.Yin, ng.Sout, rows, prec);  // warm-up: workspace, planes, tuning
+    hipcheck(hipStreamSynchronize(cx.stream), "graph warm");
+    cx.pool.begin_hold();
+    hipError_t e = hipStreamBeginCapture(cx.stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      try {
+        sigma_dispatch(h, I, ng.Yin, ng.Sout, rows, prec);
+      } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(cx.stream, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        for (double2* p : cx.pool.end_hold()) cx.pool.put(p);
+        throw;
+      }
+      e = hipStreamEndCapture(cx.stream, &ng.g);
+    }
+    ng.held = cx.pool.end_hold();
+    if (e == hipSuccess) e = hipGraphInstantiate(&ng.ex, ng.g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (ng.g) (void)hipGraphDestroy(ng.g);
+      for (double2* p : ng.held) cx.pool.put(p);
+      hipcheck(e, "graph capture");
+    }
+    I.graphs.push_back(std::move(ng));
+    G = &I.graphs.back();
+    // the warm-up already holds this call's result
+    hipcheck(hipMemcpyAsync(S, G->Sout, bytes, hipMemcpyDeviceToDevice, cx.stream), "graph out");
+    return;
+  }
+  hipcheck(hipMemcpyAsync(G->Yin, Y, bytes, hipMemcpyDeviceToDevice, cx.stream), "graph in");
+  hipcheck(hipGraphLaunch(G->ex, cx.stream), "graph launch");
+  hipcheck(hipMemcpyAsync(S, G->Sout, bytes, hipMemcpyDeviceToDevice, cx.stream), "graph out");
+}
+
+void release_graphs(Inst& I) {
+  for (auto& g : I.graphs) {
+    if (g.ex) (void)hipGraphExecDestroy(g.ex);
+    if (g.g) (void)hipGraphDestroy(g.g);
+    for (double2* p : g.held) I.cx->pool.put(p);
+  }
+  I.graphs.clear();
+}
+
 // G[a][b] = sum_i conj(X[a][i]) Y[b][i]  (ra x rb, host result)
-std::vector<zc> gram(adc_handle* h, const double2* X, int ra, const double2* Y, int rb, int64_t dim) {
-  Ctx& cx = h->cx;
+std::vector<zc> gram(Ctx& cx, const double2* X, int ra, const double2* Y, int rb, int64_t dim) {
   std::vector<zc> G((size_t)ra * rb, zc(0, 0));
   if (ra == 0 || rb == 0) return G;
   const int64_t chunk = 1 << 16;
@@ -1060,9 +1159,8 @@ std::vector<zc> gram(adc_handle* h, const double2* X, int ra, const double2* Y, 
 }
 
 // Out[r][i] = sum_a C[a][r] In[a][i]  (C is m x r host matrix), beta accumulate
-void combine(adc_handle* h, const std::vector<zc>& Cm, int m, int r, const double2* In, double2* Out, int64_t dim,
+void combine(Ctx& cx, const std::vector<zc>& Cm, int m, int r, const double2* In, double2* Out, int64_t dim,
              cplx alpha, cplx beta) {
-  Ctx& cx = h->cx;
   if (m == 0 || r == 0) return;
   double2* c = cx.pool.get((int64_t)m * r);
   std::vector<double2> hc((size_t)m * r);
@@ -1081,14 +1179,13 @@ void combine(adc_handle* h, const std::vector<zc>& Cm, int m, int r, const doubl
 
 // orthonormalise rows of N (nn x dim) against V (m x dim) and among themselves;
 // returns the number of kept rows (compacted to the front of N)
-int orthonormalize(adc_handle* h, double2* V, int m, double2* N, int nn, int64_t dim) {
-  Ctx& cx = h->cx;
+int orthonormalize(Ctx& cx, double2* V, int m, double2* N, int nn, int64_t dim) {
   for (int pass = 0; pass < 2; ++pass) {
     if (m > 0) {
-      auto C = gram(h, V, m, N, nn, dim);  // m x nn
-      combine(h, C, m, nn, V, N, dim, CR(-1), C1());
+      auto C = gram(cx, V, m, N, nn, dim);  // m x nn
+      combine(cx, C, m, nn, V, N, dim, CR(-1), C1());
     }
-    auto G = gram(h, N, nn, N, nn, dim);
+    auto G = gram(cx, N, nn, N, nn, dim);
     std::vector<double> w;
     std::vector<zc> U;
     heevj(nn, G, w, U);
@@ -1103,7 +1200,7 @@ int orthonormalize(adc_handle* h, double2* V, int m, double2* N, int nn, int64_t
     for (int a = 0; a < nn; ++a)
       for (int c = 0; c < nk; ++c) Cm[(size_t)a * nk + c] = U[(size_t)a * nn + keep[c]] / std::sqrt(w[keep[c]]);
     double2* tmp = cx.pool.get((int64_t)std::max(1, nk) * dim);
-    combine(h, Cm, nn, nk, N, tmp, dim, C1(), C0());
+    combine(cx, Cm, nn, nk, N, tmp, dim, C1(), C0());
     if (nk) hipcheck(hipMemcpyAsync(N, tmp, sizeof(double2) * nk * dim, hipMemcpyDeviceToDevice, cx.stream), "on");
     hipcheck(hipStreamSynchronize(cx.stream), "on sync");
     cx.pool.put(tmp);
@@ -1113,8 +1210,22 @@ int orthonormalize(adc_handle* h, double2* V, int m, double2* N, int nn, int64_t
   return nn;
 }
 
-std::vector<double> row_norms2(adc_handle* h, const double2* X, int rows, int64_t dim) {
-  Ctx& cx = h->cx;
+// out[r] = sum_i conj(X[r][i]) Y[r][i] for contiguous rows
+std::vector<zc> row_dots(Ctx& cx, const double2* X, const double2* Y, int rows, int64_t dim) {
+  const int nb = row_dot_blocks(dim);
+  double2* part = cx.pool.get((int64_t)rows * nb);
+  launch_row_dots(X, dim, Y, dim, rows, dim, part, nb, cx.stream);
+  std::vector<double2> hp((size_t)rows * nb);
+  hipcheck(hipMemcpyAsync(hp.data(), part, sizeof(double2) * hp.size(), hipMemcpyDeviceToHost, cx.stream), "rd");
+  hipcheck(hipStreamSynchronize(cx.stream), "rd sync");
+  cx.pool.put(part);
+  std::vector<zc> out(rows, zc(0, 0));
+  for (int r = 0; r < rows; ++r)
+    for (int b = 0; b < nb; ++b) out[r] += zc(hp[(size_t)r * nb + b].x, hp[(size_t)r * nb + b].y);
+  return out;
+}
+
+std::vector<double> row_norms2(Ctx& cx, const double2* X, int rows, int64_t dim) {
   const int nb = row_dot_blocks(dim);
   double2* part = cx.pool.get((int64_t)rows * nb);
   launch_row_dots(X, dim, X, dim, rows, dim, part, nb, cx.stream);
@@ -1130,7 +1241,7 @@ std::vector<double> row_norms2(adc_handle* h, const double2* X, int rows, int64_
 
 int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, double2* vecs, double* resnorm,
                  int* iters, int* conv_out) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int k = I.k;
   const int64_t dim = I.dim;
   const double tol = h->opt.conv_tol > 0 ? h->opt.conv_tol : 1e-7;
@@ -1152,7 +1263,7 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   // initial vectors
   if (guess) {
     hipcheck(hipMemcpyAsync(V, guess, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "guess");
-    m = orthonormalize(h, V, 0, V, k, dim);
+    m = orthonormalize(cx, V, 0, V, k, dim);
   } else {
     std::vector<int> idx(I.n1);
     for (int i = 0; i < (int)I.n1; ++i) idx[i] = i;
@@ -1174,7 +1285,9 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       std::stable_sort(id2.begin(), id2.end(), [&](int64_t a, int64_t b) { return dd[a] < dd[b]; });
       for (int r = ng; r < k; ++r) {
         double2 one = make_double2(1.0, 0.0);
-        hipcheck(hipMemcpy(V + (int64_t)r * dim + id2[r - ng], &one, sizeof(double2), hipMemcpyHostToDevice), "unit2");
+        hipcheck(hipMemcpyAsync(V + (int64_t)r * dim + id2[r - ng], &one, sizeof(double2), hipMemcpyHostToDevice,
+                                cx.stream), "unit2");
+        hipcheck(hipStreamSynchronize(cx.stream), "unit2 sync");
       }
     }
     m = k;
@@ -1186,7 +1299,7 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   double t_sigma = 0.0, t_sub = 0.0, t_orth = 0.0;
   {
     auto t0 = now();
-    sigma_dispatch(h, I, V, S, m, prec);
+    sigma_call(h, I, V, S, m, prec);
     hipcheck(hipStreamSynchronize(cx.stream), "sigma sync");
     t_sigma += ms_since(t0);
   }
@@ -1196,7 +1309,7 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   bool refined_phase = (prec == 0);
   for (it = 1; it <= max_iter; ++it) {
     auto t_it = now();
-    auto G = gram(h, V, m, S, m, dim);
+    auto G = gram(cx, V, m, S, m, dim);
     for (int a = 0; a < m; ++a)
       for (int b = a; b < m; ++b) {
         const zc x = 0.5 * (G[(size_t)a * m + b] + std::conj(G[(size_t)b * m + a]));
@@ -1209,12 +1322,12 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     std::vector<zc> Uk((size_t)m * k);
     for (int a = 0; a < m; ++a)
       for (int r = 0; r < k; ++r) Uk[(size_t)a * k + r] = U[(size_t)a * m + r];
-    combine(h, Uk, m, k, V, X, dim, C1(), C0());
-    combine(h, Uk, m, k, S, AX, dim, C1(), C0());
+    combine(cx, Uk, m, k, V, X, dim, C1(), C0());
+    combine(cx, Uk, m, k, S, AX, dim, C1(), C0());
     for (int r = 0; r < k; ++r) w[r] = wall[r];
     hipcheck(hipMemcpyAsync(wd, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, cx.stream), "w");
     launch_resid(AX, X, wd, R, k, dim, cx.stream);
-    auto r2 = row_norms2(h, R, k, dim);
+    auto r2 = row_norms2(cx, R, k, dim);
     bool all = true;
     const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
     for (int r = 0; r < k; ++r) {
@@ -1236,8 +1349,8 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       refined_phase = true;
       prec = 0;
       hipcheck(hipMemcpyAsync(V, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "restart");
-      m = orthonormalize(h, V, 0, V, k, dim);
-      sigma_dispatch(h, I, V, S, m, prec);
+      m = orthonormalize(cx, V, 0, V, k, dim);
+      sigma_call(h, I, V, S, m, prec);
       std::fill(w_old.begin(), w_old.end(), 1e300);
       continue;
     }
@@ -1256,6 +1369,28 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     }
     hipcheck(hipMemcpyAsync(wn, wv.data(), sizeof(double) * nn, hipMemcpyHostToDevice, cx.stream), "wn");
     launch_precondition(Nd, Nd, I.diag, wn, nn, dim, cx.stream);
+    {
+      // Olsen's correction t = P (r - e x), e = <x|P r> / <x|P x>, P = (w - D)^-1:
+      // keeps the new direction out of the span of the Ritz vector x when
+      // M is close to its diagonal
+      double2* Xu = cx.pool.get((int64_t)nn * dim);
+      double2* Xp = cx.pool.get((int64_t)nn * dim);
+      for (int j = 0; j < nn; ++j)
+        hipcheck(hipMemcpyAsync(Xu + (int64_t)j * dim, X + (int64_t)un[j] * dim, sizeof(double2) * dim,
+                                hipMemcpyDeviceToDevice, cx.stream), "Xu");
+      launch_precondition(Xu, Xp, I.diag, wn, nn, dim, cx.stream);
+      const auto a = row_dots(cx, Xu, Nd, nn, dim);
+      const auto b = row_dots(cx, Xu, Xp, nn, dim);
+      for (int j = 0; j < nn; ++j) {
+        if (std::abs(b[j]) < 1e-300) continue;
+        const zc e = a[j] / b[j];
+        const int64_t od[1] = {dim}, st[1] = {1};
+        launch_permute(1, od, st, st, Xp + (int64_t)j * dim, Nd + (int64_t)j * dim, {-e.real(), -e.imag()}, C1(), 0,
+                       cx.stream);
+      }
+      cx.pool.put(Xu);
+      cx.pool.put(Xp);
+    }
     if (m + nn > mmax) {
       // collapse onto the 2k lowest Ritz vectors of the current subspace
       const int mc = std::min(2 * k, m);
@@ -1263,29 +1398,44 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       for (int a = 0; a < m; ++a)
         for (int r = 0; r < mc; ++r) Uc[(size_t)a * mc + r] = U[(size_t)a * m + r];
       double2* T = cx.pool.get((int64_t)mc * dim);
-      combine(h, Uc, m, mc, V, T, dim, C1(), C0());
+      combine(cx, Uc, m, mc, V, T, dim, C1(), C0());
       hipcheck(hipMemcpyAsync(V, T, sizeof(double2) * mc * dim, hipMemcpyDeviceToDevice, cx.stream), "col");
-      combine(h, Uc, m, mc, S, T, dim, C1(), C0());
+      combine(cx, Uc, m, mc, S, T, dim, C1(), C0());
       hipcheck(hipMemcpyAsync(S, T, sizeof(double2) * mc * dim, hipMemcpyDeviceToDevice, cx.stream), "col");
       hipcheck(hipStreamSynchronize(cx.stream), "col sync");
       cx.pool.put(T);
       m = mc;
     }
     auto t_o = now();
-    const int nk = orthonormalize(h, V, m, Nd, nn, dim);
+    const int nk = orthonormalize(cx, V, m, Nd, nn, dim);
     t_orth += ms_since(t_o);
     if (nk > 0) {
       hipcheck(hipMemcpyAsync(V + (int64_t)m * dim, Nd, sizeof(double2) * nk * dim, hipMemcpyDeviceToDevice,
                               cx.stream), "app");
       auto t_s = now();
-      sigma_dispatch(h, I, V + (int64_t)m * dim, S + (int64_t)m * dim, nk, prec);
+      sigma_call(h, I, V + (int64_t)m * dim, S + (int64_t)m * dim, nk, prec);
       hipcheck(hipStreamSynchronize(cx.stream), "sigma sync");
       t_sigma += ms_since(t_s);
       m += nk;
     }
     cx.pool.put(Nd);
     cx.pool.put((double2*)wn);
-    if (nk == 0) break;
+    if (nk == 0) {
+      // no direction is left outside the subspace (it is invariant, e.g. the
+      // whole space of a tiny instance): the Ritz pairs are final, after an
+      // FP64 pass when the sweep ran in mixed precision
+      if (!refined_phase) {
+        refined_phase = true;
+        prec = 0;
+        hipcheck(hipMemcpyAsync(V, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "restart");
+        m = orthonormalize(cx, V, 0, V, k, dim);
+        sigma_call(h, I, V, S, m, prec);
+        std::fill(w_old.begin(), w_old.end(), 1e300);
+        continue;
+      }
+      for (int r = 0; r < k; ++r) conv[r] = rn[r] <= tol_now ? 1 : 0;
+      break;
+    }
   }
   for (int r = 0; r < k; ++r) {
     omega[r] = w[r];
@@ -1353,7 +1503,7 @@ void inst_release_derived(Ctx& cx, Inst& J) {
 // f = Re sum_z Sbar_z^H M(L, x) Y_z.  dL (device, [N][n][n]) receives the
 // Hermitian-projected G_L; *dx = f(x + 1) - f(x) (M is affine in x).
 void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* Y, int k, double2* dL, double* dx) {
-  Ctx& cx = h->cx;
+  Ctx& cx = *I.cx;
   const int o = I.o, v = I.v, n = o + v, N = I.N;
   const int64_t dim = I.dim;
   const int saved_prec = cx.prec;
@@ -1412,6 +1562,7 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     // fresh copies of the constant operands, so every recorded pointer is tracked
     Tensor Yc = tnew(cx, {k, dim}, false), Sg = tnew(cx, {k, dim}, false);
     hipcheck(hipMemcpyAsync(Yc.p, Y, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "bw Y");
+    J.cx = I.cx;
     J.kind = I.kind; J.o = o; J.v = v; J.N = N; J.k = I.k; J.x = I.x;
     J.n1 = I.n1; J.n2 = I.n2; J.dim = dim; J.Po = I.Po; J.Pv = I.Pv;
     J.eps = I.eps; J.Loo = I.Loo; J.Lov = I.Lov; J.Lvo = I.Lvo; J.Lvv = I.Lvv;
@@ -1475,6 +1626,53 @@ int guarded(F&& f) {
   }
 }
 
+// Rough cost of one sigma build (complex MACs), used to order instances
+// longest first and to balance them over the lanes.
+double sigma_cost(const adc_problem& p) {
+  const double o = p.n_occ, v = p.n_vir, N = p.n_chol, k = p.n_roots;
+  const double Po = o * (o - 1) / 2, Pv = v * (v - 1) / 2;
+  if (p.kind == ADC_EE) return 2 * N * Pv * Pv + k * (Po * Pv * Pv + std::pow(o * v, 3) + o * o * v * v * v);
+  if (p.kind == ADC_IP) return k * (o * std::pow(o * v, 2) + Po * Po * v) + N * o * o * v * v;
+  return 2 * N * Pv * Pv + k * (o * Pv * Pv + v * std::pow(o * v, 2));
+}
+
+// Run f(lane) for every lane, lanes > 0 on worker threads (each with the
+// handle's device current); returns the first error.
+template <class F>
+int for_lanes(adc_handle* h, F&& f) {
+  const int L = h->n_lanes();
+  std::vector<int> rc(L, ADC_OK);
+  std::vector<std::thread> th;
+  for (int l = 1; l < L; ++l)
+    th.emplace_back([&, l]() {
+      if (hipSetDevice(h->device) != hipSuccess) {
+        rc[l] = ADC_ERR_HIP;
+        return;
+      }
+      rc[l] = guarded([&]() { return f(l); });
+    });
+  rc[0] = guarded([&]() { return f(0); });
+  for (auto& t : th) t.join();
+  for (int l = 0; l < L; ++l)
+    if (rc[l] < 0) return rc[l];
+  for (int l = 0; l < L; ++l)
+    if (rc[l] != ADC_OK) return rc[l];
+  return ADC_OK;
+}
+
+// order a lane's stream after the handle's stream (before) or the handle's
+// stream after the lane (after); no-op for lane 0
+void lane_wait(adc_handle* h, Ctx& lane, bool before) {
+  if (&lane == &h->cx) return;
+  hipEvent_t e;
+  hipcheck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  hipStream_t from = before ? h->cx.stream : lane.stream, to = before ? lane.stream : h->cx.stream;
+  hipError_t r = hipEventRecord(e, from);
+  if (r == hipSuccess) r = hipStreamWaitEvent(to, e, 0);
+  (void)hipEventDestroy(e);
+  hipcheck(r, "lane order");
+}
+
 }  // namespace
 
 // ============================================================================
@@ -1485,35 +1683,66 @@ extern "C" {
 int adc_init(const adc_problem* problems, int n_problems, const adc_options* opts, adc_handle** out) {
   if (!out) return ADC_ERR_INVALID_ARG;
   *out = nullptr;
-  if (!problems || n_problems != 1) return ADC_ERR_INVALID_ARG;
-  int rc = validate(&problems[0]);
-  if (rc) return rc;
-  const adc_problem& p = problems[0];
+  if (!problems || n_problems < 1) return ADC_ERR_INVALID_ARG;
   if (opts && (opts->precision < 0 || opts->precision > 2)) return ADC_ERR_INVALID_ARG;
   if (opts && opts->precision == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
-  if (!p.L_on_device) {
-    rc = validate_L_host((const double*)p.L, p.n_chol, p.n_occ + p.n_vir);
+  if (opts && opts->n_streams < 0) return ADC_ERR_INVALID_ARG;
+  for (int i = 0; i < n_problems; ++i) {
+    int rc = validate(&problems[i]);
     if (rc) return rc;
+    if (!problems[i].L_on_device) {
+      rc = validate_L_host((const double*)problems[i].L, problems[i].n_chol, problems[i].n_occ + problems[i].n_vir);
+      if (rc) return rc;
+    }
   }
   adc_handle* h = nullptr;
-  rc = guarded([&]() {
+  int rc = guarded([&]() {
     h = new adc_handle();
     if (opts) h->opt = *opts;
-    if (h->opt.mem_budget)
-      h->cx.max_temp = std::min<int64_t>((int64_t)1 << 29, (int64_t)(h->opt.mem_budget / sizeof(double2)));
+    hipcheck(hipGetDevice(&h->device), "device");
     if (h->opt.stream) {
       h->cx.stream = (hipStream_t)h->opt.stream;
     } else {
       hipcheck(hipStreamCreate(&h->cx.stream), "stream");
       h->own_stream = true;
     }
+    int L = h->opt.n_streams > 0 ? h->opt.n_streams : 4;
+    L = std::max(1, std::min(L, n_problems));
+    for (int l = 1; l < L; ++l) {
+      h->extra.emplace_back(new Ctx());
+      hipcheck(hipStreamCreateWithFlags(&h->extra.back()->stream, hipStreamNonBlocking), "lane stream");
+    }
+    for (int l = 0; l < L; ++l) {
+      Ctx& c = h->lane(l);
+      c.autotune = h->opt.autotune != 0;
+      if (h->opt.mem_budget)
+        c.max_temp = std::min<int64_t>((int64_t)1 << 29, (int64_t)(h->opt.mem_budget / sizeof(double2)));
+    }
+    // longest processing time first: each instance to the least loaded lane
+    std::vector<int> order(n_problems);
+    for (int i = 0; i < n_problems; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return sigma_cost(problems[a]) > sigma_cost(problems[b]); });
+    std::vector<double> load(L, 0.0);
+    h->lane_inst.assign(L, {});
+    h->inst.resize(n_problems);
+    for (int i : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[l] += sigma_cost(problems[i]);
+      h->lane_inst[l].push_back(i);
+      h->inst[i].cx = &h->lane(l);
+    }
     auto t0 = std::chrono::steady_clock::now();
-    h->inst.resize(1);
-    inst_init(h, &p, h->inst[0]);
-    hipcheck(hipStreamSynchronize(h->cx.stream), "init sync");
-    h->cx.pool.trim();
+    const int r = for_lanes(h, [&](int l) {
+      for (int i : h->lane_inst[l]) inst_init(h, &problems[i], h->inst[i]);
+      Ctx& c = h->lane(l);
+      hipcheck(hipStreamSynchronize(c.stream), "init sync");
+      c.pool.trim();
+      return (int)ADC_OK;
+    });
+    if (r != ADC_OK) return r;
     h->init_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    return ADC_OK;
+    return (int)ADC_OK;
   });
   if (rc != ADC_OK) {
     adc_free(h);
@@ -1536,7 +1765,10 @@ int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precis
   const int prec = precision < 0 ? h->opt.precision : precision;
   if (prec == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
   return guarded([&]() {
-    sigma_dispatch(h, h->inst[inst], (const double2*)Y, (double2*)S, k, prec);
+    Inst& I = h->inst[inst];
+    lane_wait(h, *I.cx, true);
+    sigma_dispatch(h, I, (const double2*)Y, (double2*)S, k, prec);
+    lane_wait(h, *I.cx, false);
     hipcheck(hipGetLastError(), "sigma launch");
     return ADC_OK;
   });
@@ -1546,13 +1778,15 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
   if (term == ADC_TERM_ALL) return adc_sigma(h, inst, Y, S, k, precision);
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
   if (precision > 2 || term != ADC_TERM_LADDER) return ADC_ERR_INVALID_ARG;
-  Inst& I = h->inst[0];
+  Inst& I = h->inst[inst];
   if (I.kind == ADC_IP) return ADC_ERR_UNSUPPORTED;
   const int prec = precision < 0 ? h->opt.precision : precision;
   return guarded([&]() {
-    launch_fill((double2*)S, (int64_t)k * I.dim, C0(), h->cx.stream);
+    lane_wait(h, *I.cx, true);
+    launch_fill((double2*)S, (int64_t)k * I.dim, C0(), I.cx->stream);
     const int64_t nrow = I.kind == ADC_EE ? I.Po : I.o;
     ladder(h, I, (const double2*)Y, I.dim, I.n1, (double2*)S, I.dim, I.n1, nrow, k, CR(I.x), prec);
+    lane_wait(h, *I.cx, false);
     hipcheck(hipGetLastError(), "term launch");
     return ADC_OK;
   });
@@ -1561,11 +1795,25 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
 int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs, double* resnorm,
                  int* iters, int* converged) {
   if (!h || !omega || !resnorm || !iters || !converged) return ADC_ERR_INVALID_ARG;
+  // offsets of each instance's roots in the concatenated outputs
+  std::vector<int64_t> off(h->inst.size() + 1, 0);
+  for (size_t i = 0; i < h->inst.size(); ++i) off[i + 1] = off[i] + h->inst[i].k;
   return guarded([&]() {
-    Inst& I = h->inst[0];
-    const double2* g = guess ? (const double2*)guess[0] : nullptr;
-    double2* vv = vecs ? (double2*)vecs[0] : nullptr;
-    return davidson_one(h, I, g, omega, vv, resnorm, iters, converged);
+    hipcheck(hipStreamSynchronize(h->cx.stream), "dav start");
+    std::vector<int> st(h->inst.size(), ADC_OK);
+    const int r = for_lanes(h, [&](int l) {
+      for (int i : h->lane_inst[l]) {
+        Inst& I = h->inst[i];
+        const double2* g = guess ? (const double2*)guess[i] : nullptr;
+        double2* vv = vecs ? (double2*)vecs[i] : nullptr;
+        st[i] = davidson_one(h, I, g, omega + off[i], vv, resnorm + off[i], iters + i, converged + off[i]);
+      }
+      return (int)ADC_OK;
+    });
+    if (r != ADC_OK) return r;
+    for (int s_ : st)
+      if (s_ != ADC_OK) return s_;
+    return (int)ADC_OK;
   });
 }
 
@@ -1573,11 +1821,12 @@ int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y,
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Sbar || !Y || k < 0) return ADC_ERR_INVALID_ARG;
   return guarded([&]() {
     Inst& I = h->inst[inst];
+    hipcheck(hipStreamSynchronize(h->cx.stream), "bw start");
     if (k == 0) {
       if (dL) {
         const int64_t n = I.o + I.v;
-        launch_fill((double2*)dL, (int64_t)I.N * n * n, C0(), h->cx.stream);
-        hipcheck(hipStreamSynchronize(h->cx.stream), "bw zero");
+        launch_fill((double2*)dL, (int64_t)I.N * n * n, C0(), I.cx->stream);
+        hipcheck(hipStreamSynchronize(I.cx->stream), "bw zero");
       }
       if (dx) *dx = 0.0;
       return ADC_OK;
@@ -1593,6 +1842,16 @@ double adc_init_ms(const adc_handle* h) { return h ? h->init_ms : 0.0; }
 void adc_free(adc_handle* h) {
   if (!h) return;
   if (h->cx.stream) (void)hipStreamSynchronize(h->cx.stream);
+  for (auto& I : h->inst)
+    if (I.cx) {
+      (void)hipStreamSynchronize(I.cx->stream);
+      release_graphs(I);
+    }
+  for (auto& c : h->extra) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    c->pool.release_all();
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+  }
   h->cx.pool.release_all();
   for (void* p : h->raw) (void)hipFree(p);
   if (h->own_stream && h->cx.stream) (void)hipStreamDestroy(h->cx.stream);

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <cstdio>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 
 #include "internal.h"
@@ -23,6 +24,23 @@ Pool::~Pool() { release_all(); }
 
 double2* Pool::get(int64_t n) {
   const size_t bytes = std::max<size_t>(256, (size_t)n * sizeof(double2));
+  if (hold_) {
+    // reuse a block this capture has already released
+    int cb = -1;
+    size_t cbytes = 0;
+    for (size_t i = 0; i < cap_free_.size(); ++i)
+      for (const Blk& u : used_)
+        if (u.p == cap_free_[i] && u.bytes >= bytes && u.bytes <= 2 * bytes + (1 << 20) &&
+            (cb < 0 || u.bytes < cbytes)) {
+          cb = (int)i;
+          cbytes = u.bytes;
+        }
+    if (cb >= 0) {
+      void* p = cap_free_[cb];
+      cap_free_.erase(cap_free_.begin() + cb);
+      return (double2*)p;
+    }
+  }
   int best = -1;
   for (size_t i = 0; i < free_.size(); ++i) {
     if (free_[i].bytes >= bytes && free_[i].bytes <= 2 * bytes + (1 << 20)) {
@@ -50,11 +68,31 @@ double2* Pool::get(int64_t n) {
   used_.push_back(b);
   in_use_ += b.bytes;
   if (tape) tape->add(b.p, b.bytes, false);
+  if (hold_) touched_.push_back(b.p);
   return (double2*)b.p;
+}
+
+void Pool::begin_hold() {
+  hold_ = true;
+  touched_.clear();
+  cap_free_.clear();
+}
+
+std::vector<double2*> Pool::end_hold() {
+  hold_ = false;
+  std::vector<double2*> out;
+  for (void* p : touched_) out.push_back((double2*)p);
+  touched_.clear();
+  cap_free_.clear();
+  return out;
 }
 
 void Pool::put(double2* p) {
   if (!p) return;
+  if (hold_ && std::find(touched_.begin(), touched_.end(), (void*)p) != touched_.end()) {
+    cap_free_.push_back(p);
+    return;
+  }
   if (tape) {
     const int i = tape->find(p);
     if (i >= 0 && tape->allocs[i].base == (uintptr_t)p) {
@@ -88,14 +126,23 @@ void Pool::release_all() {
   in_use_ = 0;
 }
 
-void gemm(Ctx& cx, GemmDesc g) {
-  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
-  const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64) * g.batch;
+// ------------------------------------------------------------------ GEMM driver
+// Heuristic split-K: outputs with too few tiles to fill the 256 CUs split the
+// K loop into chunks whose partial sums a reduction kernel adds up.
+namespace {
+
+int64_t heuristic_nsplit(int64_t M, int64_t N, int64_t K, int64_t batch, int64_t kmin) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64) * batch;
   int64_t nsplit = 1;
-  if (tiles < 512 && g.K >= 2048) {
-    nsplit = std::min<int64_t>({(1024 + tiles - 1) / tiles, g.K / 1024, 256});
-    if (g.batch * nsplit > 65535) nsplit = 65535 / g.batch;
+  if (tiles < 512 && K >= 2 * kmin) {
+    nsplit = std::min<int64_t>({(1024 + tiles - 1) / tiles, K / kmin, 256});
+    if (batch * nsplit > 65535) nsplit = 65535 / batch;
   }
+  return std::max<int64_t>(1, nsplit);
+}
+
+void run_zgemm(Ctx& cx, GemmDesc g, int tile, int64_t nsplit) {
+  g.tile = tile;
   if (nsplit <= 1) {
     g.nsplit = 1;
     g.kchunk = g.K;
@@ -113,11 +160,8 @@ void gemm(Ctx& cx, GemmDesc g) {
   cx.pool.put(g.P);
 }
 
-void gemm_bf16p(Ctx& cx, BfGemm g) {
-  if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
-  const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
-  int64_t nsplit = 1;
-  if (tiles < 512 && g.Kp >= 2048) nsplit = std::min<int64_t>({(1024 + tiles - 1) / tiles, g.Kp / 1024, 256});
+void run_bf16p(Ctx& cx, BfGemm g, int tile, int64_t nsplit) {
+  g.tile = tile;
   if (nsplit <= 1) {
     g.nsplit = 1;
     g.kchunk = g.Kp;
@@ -133,6 +177,143 @@ void gemm_bf16p(Ctx& cx, BfGemm g) {
   launch_bf16p(g, cx.stream);
   launch_splitk_reduce_bf(g, cx.stream);
   cx.pool.put(g.P);
+}
+
+// ------------------------------------------------------------------ autotuner
+// Shape classes: kernel family, arithmetic, instance tag, and ceil(log2) of
+// M, N, K and the batch count.  The first GEMM of a class times every
+// candidate (tile size x split-K factor) on a scratch output and keeps the
+// fastest for the rest of the process.  Skipped while a stream is being
+// captured (timing needs host synchronisation) and for outputs above 2^26
+// elements (the scratch copy would be too large).
+struct TuneKey {
+  int fam, prec, tag, lm, ln, lk, lb;
+  bool operator<(const TuneKey& o) const {
+    const int a[7] = {fam, prec, tag, lm, ln, lk, lb}, b[7] = {o.fam, o.prec, o.tag, o.lm, o.ln, o.lk, o.lb};
+    for (int i = 0; i < 7; ++i)
+      if (a[i] != b[i]) return a[i] < b[i];
+    return false;
+  }
+};
+struct TuneChoice {
+  int tile;
+  int64_t nsplit;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune;
+
+int lg2(int64_t n) {
+  int l = 0;
+  while (((int64_t)1 << l) < n) ++l;
+  return l;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+std::vector<TuneChoice> candidates(int64_t heur, int ntiles) {
+  std::vector<int64_t> ns = {heur};
+  if (heur > 1) ns.push_back(1);
+  if (heur > 2) ns.push_back(heur / 2);
+  if (heur * 2 <= 256 && heur > 1) ns.push_back(heur * 2);
+  std::vector<TuneChoice> c;
+  for (int t = 0; t < ntiles; ++t)
+    for (int64_t n : ns) c.push_back({t, n});
+  return c;
+}
+
+// time fn(choice) for every candidate (one warm-up, two timed runs)
+template <class F>
+TuneChoice tune(Ctx& cx, const std::vector<TuneChoice>& cand, F&& fn) {
+  hipEvent_t e0, e1;
+  hipcheck(hipEventCreate(&e0), "tune ev");
+  hipcheck(hipEventCreate(&e1), "tune ev");
+  TuneChoice best = cand[0];
+  float tbest = 1e30f;
+  for (const TuneChoice& c : cand) {
+    fn(c);
+    hipcheck(hipEventRecord(e0, cx.stream), "tune rec");
+    fn(c);
+    fn(c);
+    hipcheck(hipEventRecord(e1, cx.stream), "tune rec");
+    hipcheck(hipEventSynchronize(e1), "tune sync");
+    float ms = 0.f;
+    hipcheck(hipEventElapsedTime(&ms, e0, e1), "tune time");
+    if (ms < tbest) {
+      tbest = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
+}
+
+}  // namespace
+
+void gemm(Ctx& cx, GemmDesc g) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
+  const int64_t heur = heuristic_nsplit(g.M, g.N, g.K, g.batch, 1024);
+  const int64_t out = g.M * g.N * g.batch;
+  if (!cx.autotune || cx.prec == 2 || out > ((int64_t)1 << 26)) {
+    run_zgemm(cx, g, -1, heur);
+    return;
+  }
+  const TuneKey key{0, cx.prec, g.tag, lg2(g.M), lg2(g.N), lg2(g.K), lg2(g.batch)};
+  TuneChoice ch{-1, heur};
+  bool found = false;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) { ch = it->second; found = true; }
+  }
+  if (!found && !capturing(cx.stream)) {
+    double2* scratch = cx.pool.get(out);
+    GemmDesc t = g;
+    t.C = scratch; t.scm = g.N; t.scn = 1; t.scb = g.M * g.N;
+    t.beta = {0.0, 0.0};
+    ch = tune(cx, candidates(heur, 2), [&](const TuneChoice& c) { run_zgemm(cx, t, c.tile, c.nsplit); });
+    cx.pool.put(scratch);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = ch;
+  }
+  run_zgemm(cx, g, ch.tile, std::min<int64_t>(ch.nsplit, std::max<int64_t>(1, g.K / 16)));
+}
+
+void gemm_bf16p(Ctx& cx, BfGemm g) {
+  if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
+  const int64_t heur = heuristic_nsplit(g.M, g.N, g.Kp, 1, 1024);
+  const int64_t out = g.M * g.N;
+  if (!cx.autotune || out > ((int64_t)1 << 26)) {
+    run_bf16p(cx, g, -1, heur);
+    return;
+  }
+  const TuneKey key{1, 2, g.tag, lg2(g.M), lg2(g.N), lg2(g.Kp), 0};
+  TuneChoice ch{-1, heur};
+  bool found = false;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) { ch = it->second; found = true; }
+  }
+  if (!found && !capturing(cx.stream)) {
+    double2* scratch = cx.pool.get(out);
+    BfGemm t = g;
+    t.C = scratch; t.scm = g.N; t.scn = 1;
+    t.beta = {0.0, 0.0};
+    ch = tune(cx, candidates(heur, 4), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
+    cx.pool.put(scratch);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = ch;
+  }
+  run_bf16p(cx, g, ch.tile, std::min<int64_t>(ch.nsplit, std::max<int64_t>(1, g.Kp / 32)));
 }
 
 Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero) {

@@ -32,6 +32,7 @@ struct GemmDesc {
   int64_t kchunk;
   int nsplit;
   double2* P;
+  int tile;  // -1 heuristic, 0 small tiles, 1 large tiles
 };
 void launch_splitk_reduce(const GemmDesc& g, hipStream_t s);
 // prec: 0 = FP64 MFMA, 1 = FP32 MFMA (operands rounded to fp32, fp32
@@ -51,6 +52,7 @@ struct BfGemm {
   int64_t kchunk;
   int nsplit;
   double2* P;
+  int tile;  // -1 heuristic, 0 small tiles, 1 large tiles
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);
 void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s);
@@ -141,6 +143,11 @@ class Pool {
   Tape* tape = nullptr;  // while set, allocations are registered and frees deferred
   double2* get(int64_t n_complex);
   void put(double2* p);
+  // Hold mode (for graph capture): blocks handed out from begin_hold() on
+  // are recycled only among themselves, and end_hold() returns them; they
+  // stay reserved (never handed out again) until passed to put() one by one.
+  void begin_hold();
+  std::vector<double2*> end_hold();
   void release_all();
   void trim();  // return cached (unused) blocks to the device
   size_t bytes_in_use() const { return in_use_; }
@@ -149,6 +156,8 @@ class Pool {
   struct Blk { void* p; size_t bytes; };
   std::vector<Blk> free_, used_;
   size_t in_use_ = 0;
+  bool hold_ = false;
+  std::vector<void*> touched_, cap_free_;
 };
 
 // ---------------------------------------------------------------- reverse mode
@@ -211,6 +220,7 @@ struct Ctx {
   hipStream_t stream = nullptr;
   Pool pool;
   int prec = 0;   // arithmetic of ctr() calls
+  bool autotune = false;  // time GEMM variants per shape class (see gemm())
   int64_t max_temp = (int64_t)1 << 29;  // largest permuted copy (complex elements) before ctr() splits
 };
 

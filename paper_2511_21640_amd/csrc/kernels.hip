@@ -503,7 +503,6 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
   }
   __syncthreads();
   const int kq = 8 * (lane >> 4);
-  const us8 sgn = us8{0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000, 0x8000};
   for (int64_t k0 = kbeg; k0 < kend; k0 += TKB) {
     const bool more = k0 + TKB < kend;
     if (more) gload(k0 + TKB);
@@ -517,7 +516,15 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
       us8 a[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[q] = *(const us8*)&sA[q][16 * WM * wr + 16 * i + (lane & 15)][kq];
-      const us8 nih = a[2] ^ sgn, nil = a[3] ^ sgn;
+      // negated imaginary planes: flip the sign bit of each bf16 (two per dword)
+      us8 nih, nil;
+      {
+        uint4 u2 = __builtin_bit_cast(uint4, a[2]), u3 = __builtin_bit_cast(uint4, a[3]);
+        u2.x ^= 0x80008000u; u2.y ^= 0x80008000u; u2.z ^= 0x80008000u; u2.w ^= 0x80008000u;
+        u3.x ^= 0x80008000u; u3.y ^= 0x80008000u; u3.z ^= 0x80008000u; u3.w ^= 0x80008000u;
+        nih = __builtin_bit_cast(us8, u2);
+        nil = __builtin_bit_cast(us8, u3);
+      }
 #pragma unroll
       for (int j = 0; j < WN; ++j) {
         flt4 cr = accR[i][j], ci = accI[i][j];
@@ -572,24 +579,32 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
       }
 }
 
+template <int WM, int WN>
+static void launch_bf16p_tile(const BfGemm& h, hipStream_t s) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  const int64_t tiles = ((h.M + BM - 1) / BM) * ((h.N + BN - 1) / BN);
+  dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
+  if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 1>), grid, dim3(256), 0, s, h);
+  else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 2>), grid, dim3(256), 0, s, h);
+  else hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 0>), grid, dim3(256), 0, s, h);
+}
+
+// tile: 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128 (rows x cols of C);
+// negative = heuristic
 void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
   BfGemm h = g;
   if (h.nsplit < 1 || h.kchunk <= 0) { h.nsplit = 1; h.kchunk = h.Kp; }
-  const int64_t big = ((h.M + 127) / 128) * ((h.N + 127) / 128) * h.nsplit;
-  const bool use_big = big >= 256 && pad_waste(h.M, 128) < 0.10 && pad_waste(h.N, 128) < 0.10;
-  if (use_big) {
-    const int64_t tiles = ((h.M + 127) / 128) * ((h.N + 127) / 128);
-    dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
-    if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16p_kernel<4, 4, 1>), grid, dim3(256), 0, s, h);
-    else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16p_kernel<4, 4, 2>), grid, dim3(256), 0, s, h);
-    else hipLaunchKernelGGL((zgemm_bf16p_kernel<4, 4, 0>), grid, dim3(256), 0, s, h);
-  } else {
-    const int64_t tiles = ((h.M + 63) / 64) * ((h.N + 63) / 64);
-    dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
-    if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16p_kernel<2, 2, 1>), grid, dim3(256), 0, s, h);
-    else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16p_kernel<2, 2, 2>), grid, dim3(256), 0, s, h);
-    else hipLaunchKernelGGL((zgemm_bf16p_kernel<2, 2, 0>), grid, dim3(256), 0, s, h);
+  int tile = h.tile;
+  if (tile < 0) {
+    const int64_t big = ((h.M + 127) / 128) * ((h.N + 127) / 128) * h.nsplit;
+    tile = (big >= 256 && pad_waste(h.M, 128) < 0.10 && pad_waste(h.N, 128) < 0.10) ? 1 : 0;
+  }
+  switch (tile) {
+    case 1: launch_bf16p_tile<4, 4>(h, s); break;
+    case 2: launch_bf16p_tile<4, 2>(h, s); break;
+    case 3: launch_bf16p_tile<2, 4>(h, s); break;
+    default: launch_bf16p_tile<2, 2>(h, s); break;
   }
 }
 
@@ -675,7 +690,8 @@ void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
   if (g.nsplit == 1 || g.kchunk <= 0) { g.nsplit = 1; g.kchunk = g.K; }
   const int64_t BNbig = prec == 0 ? 64 : 128;
   const int64_t big = ((g.M + 127) / 128) * ((g.N + BNbig - 1) / BNbig) * g.batch * g.nsplit;
-  const bool use_big = big >= 256 && pad_waste(g.M, 128) < 0.10 && pad_waste(g.N, BNbig) < 0.10;
+  const bool use_big = g.tile >= 0 ? g.tile == 1
+                                   : big >= 256 && pad_waste(g.M, 128) < 0.10 && pad_waste(g.N, BNbig) < 0.10;
   if (prec == 2) {
     launch_bf16x3(g, s);
   } else if (prec == 0) {

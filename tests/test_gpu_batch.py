@@ -1,0 +1,97 @@
+"""Batched solve: many uneven EE/IP/EA instances in one handle, spread over
+several lanes (streams) and solved concurrently.  Every instance must give the
+same result as when it is solved alone, and the oracle's."""
+import numpy as np
+import pytest
+
+from adcgen import make_problem
+from oracle.adc_terms import Ints, dense_matrix
+from oracle.adc_terms import sigma as osigma
+
+torch = pytest.importorskip("torch")
+import paper_2511_21640_amd as adc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _draw(n, seed):
+    """Uneven small instances, kinds cycling EE/IP/EA (the shape recipe of the
+    batched workload, scaled down so the oracle can diagonalise each one)."""
+    meta = np.random.default_rng(seed)
+    out = []
+    for t in range(n):
+        kind = ("EE", "IP", "EA")[t % 3]
+        o = int(meta.integers(1, 5))
+        v = int(meta.integers(4, 10))
+        k = int(meta.integers(1, 4))
+        x = float(meta.choice([0.0, 0.5, 1.0]))
+        n1 = {"EE": o * v, "IP": o, "EA": v}[kind]
+        k = min(k, n1)  # guesses come from the singles
+        out.append(make_problem(kind, o, v, 4 * (o + v), seed=700 + t, n_roots=k, x=x, scale=0.2))
+    return out
+
+
+def _spec(P):
+    return dict(kind=P.kind, o=P.o, v=P.v, eps=P.eps, L=P.L, n_roots=P.n_roots, x=P.x)
+
+
+@pytest.mark.parametrize("n_streams", [1, 3])
+def test_batch_matches_oracle(n_streams):
+    probs = _draw(10, 5)
+    print(f"case batch of {len(probs)} on {n_streams} lanes", flush=True)
+    B = adc.Batch([_spec(P) for P in probs], conv_tol=1e-9, n_streams=n_streams)
+    rng = np.random.default_rng(6)
+    for i, P in enumerate(probs):
+        Y = rng.standard_normal((2, B.dims[i])) + 1j * rng.standard_normal((2, B.dims[i]))
+        S = B.sigma(i, torch.from_numpy(Y).cuda()).cpu().numpy()
+        ref = osigma(Ints(P.eps, P.L, P.o), P.kind, P.x, Y)
+        assert np.abs(S - ref).max() <= 1e-12 * np.abs(ref).max(), i
+    res, rc = B.davidson()
+    for i, P in enumerate(probs):
+        w = np.linalg.eigvalsh(dense_matrix(Ints(P.eps, P.L, P.o), P.kind, P.x))[: P.n_roots]
+        assert res[i]["converged"].all(), (i, P.kind, P.o, P.v, P.n_roots, res[i])
+        assert np.abs(res[i]["omega"] - w).max() <= 1e-8, (i, res[i]["omega"], w)
+    assert rc == 0
+    B.close()
+
+
+def test_batch_matches_single_instance_solves():
+    """Mixed precision, larger uneven instances: the batched solve equals the
+    instance-by-instance solve root by root."""
+    probs = [make_problem("EE", 5, 16, 40, seed=801, n_roots=3, x=0.5),
+             make_problem("IP", 8, 30, 80, seed=802, n_roots=4, x=1.0),
+             make_problem("EA", 4, 20, 48, seed=803, n_roots=2, x=1.0),
+             make_problem("EE", 3, 9, 24, seed=804, n_roots=2, x=1.0),
+             make_problem("EA", 6, 12, 36, seed=805, n_roots=3, x=0.0)]
+    print("case batch vs single, split_bf16", flush=True)
+    B = adc.Batch([_spec(P) for P in probs], precision="split_bf16", conv_tol=1e-7, n_streams=3)
+    res, rc = B.davidson()
+    assert rc == 0
+    for i, P in enumerate(probs):
+        h = adc.Handle(P.kind, P.o, P.v, P.eps, P.L, P.n_roots, x=P.x, precision="fp64", conv_tol=1e-7)
+        r = h.davidson(want_vectors=False)
+        h.close()
+        assert np.abs(res[i]["omega"] - r["omega"]).max() <= 1e-6, (i, res[i]["omega"], r["omega"])
+    B.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split_bf16"])
+def test_graphs_and_autotune_match_eager(precision):
+    """Davidson with captured sigma graphs (replayed many times, with the
+    solver's own eager work between replays) and with autotuned GEMMs gives
+    the eager solve's roots."""
+    probs = _draw(7, 11)
+    print(f"case graphs+autotune {precision}", flush=True)
+    tol = 1e-9 if precision == "fp64" else 1e-7
+    A = adc.Batch([_spec(P) for P in probs], precision=precision, conv_tol=tol, n_streams=2)
+    ra, _ = A.davidson()
+    A.close()
+    G = adc.Batch([_spec(P) for P in probs], precision=precision, conv_tol=tol, n_streams=2, graphs=True,
+                  autotune=True)
+    rg, _ = G.davidson()
+    rg2, _ = G.davidson()  # replays of the graphs captured by the first solve
+    G.close()
+    for i in range(len(probs)):
+        for r in (rg[i], rg2[i]):
+            assert r["converged"].all()
+            assert np.abs(r["omega"] - ra[i]["omega"]).max() <= 1e-8, (i, r["omega"], ra[i]["omega"])
