@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-eig", action="store_true")
     ap.add_argument("--only-ladder", action="store_true",
                     help="time only the ladder term (for counter runs)")
+    ap.add_argument("--only-sigma", action="store_true",
+                    help="time only the sigma build at --precision (for kernel traces)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -128,6 +130,9 @@ def main():
         return
     ms = time_calls(lambda: h.sigma(Y, S, precision=args.precision), args.steps, args.warmup, stream)
     print(f"[bench] {args.precision} sigma {ms:.2f} ms/build", file=sys.stderr, flush=True)
+    if args.only_sigma:
+        h.close()
+        return
     ms64 = time_calls(lambda: h.sigma(Y, S, precision="fp64"), max(3, args.steps // 2), 1, stream)
     print(f"[bench] fp64 sigma {ms64:.2f} ms/build", file=sys.stderr, flush=True)
     ms_lad = time_calls(lambda: h.sigma_term("ladder", Y, S, precision=args.precision), args.steps, 1, stream)

@@ -7,8 +7,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadc.so")
 SOURCES = ["kernels.hip", "engine.cpp", "adjoint.cpp", "adc.cpp"]
+# -amdgpu-mfma-vgpr-form: keep MFMA accumulators in ordinary VGPRs instead of
+# AGPRs; without it the GEMM main loops copy every accumulator between the two
+# register files on each K step and run at one wave per SIMD.
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1",
          "-Wno-unused-result"]
 
 

@@ -194,6 +194,10 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   // W block: nb*v rows x (v-b0)*v cols; V block: npairs x Pv
   const int64_t per_a = (int64_t)v * v * v + (int64_t)v * Pv;
   int nb = (int)std::max<int64_t>(1, (int64_t)(budget / 2 / sizeof(double2)) / std::max<int64_t>(1, per_a));
+  // a block of nb values of a assembles columns b > a0 for every a in it, so
+  // the triangle b <= a inside the block (a fraction ~nb/v of the work) is
+  // wasted: keep blocks near v/8 when the GEMMs stay large enough
+  nb = std::min(nb, std::max(16, (v + 7) / 8));
   nb = std::min(nb, v - 1);
   double2* Wbuf = cx.pool.get((int64_t)nb * v * v * v);
   double2* Vbuf = cx.pool.get((int64_t)nb * v * Pv);
@@ -685,57 +689,53 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, CR(-0.25 * x), I.W, "IJiB", false, Ya, "zIJaB", false, C1(), s1, "zia");
     ctr(cx, CR(x), I.W6, "IBJi", false, Ya, "zIJaB", false, C1(), s1, "zia");
   }
-  // ---------------- doubles output (unpacked)
-  Tensor s2 = tnew(cx, {k, o, o, v, v});
-  {
-    Tensor T = tnew(cx, {k, o, o, v, v}, false);
-    // M21(1): (Tv - Tv^ij) + (To - To^ab)
-    ctr(cx, C1(), I.ovvv, "icab", true, ys, "zjc", false, C0(), T, "zijab");
-    rec_antisym_add(cx, T, s2, k, o, o, v, v, 0, C1());
-    ctr(cx, C1(), I.ooov, "ijka", true, ys, "zkb", false, C0(), T, "zijab");
-    rec_antisym_add(cx, T, s2, k, o, o, v, v, 1, C1());
-    if (x != 0.0) {
-      // M21(2)
-      Tensor Z1 = tnew(cx, {k, v, v}, false);
-      ctr(cx, C1(), I.ovvv, "iBac", false, ys, "zia", false, C0(), Z1, "zBc");
-      ctr(cx, C1(), t, "IJAc", false, Z1, "zBc", false, C0(), T, "zIJAB");
-      ctr(cx, CR(-0.5), I.W, "IJiB", true, ys, "ziA", false, C1(), T, "zIJAB");
-      rec_antisym_add(cx, T, s2, k, o, o, v, v, 1, CR(x));
-      tfree(cx, Z1);
-      Tensor Z2 = tnew(cx, {k, o, o}, false);
-      ctr(cx, C1(), I.ooov, "ikJa", false, ys, "zia", false, C0(), Z2, "zkJ");
-      ctr(cx, C1(), t, "IkAB", false, Z2, "zkJ", false, C0(), T, "zIJAB");
-      tfree(cx, Z2);
-      Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
-      ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
-      ctr(cx, CR(-0.5), t, "klAB", false, Z4, "zklJI", false, C1(), T, "zIJAB");
-      tfree(cx, Z4);
-      rec_antisym_add(cx, T, s2, k, o, o, v, v, 0, CR(x));
-      ctr(cx, C1(), I.W5, "JAaB", true, ys, "zIa", false, C0(), T, "zIJAB");
-      ctr(cx, C1(), I.W6, "IBJi", true, ys, "ziA", false, C1(), T, "zIJAB");
-      rec_antisym_add(cx, T, s2, k, o, o, v, v, 2, CR(x));
-      // M22(1): hole ladder and ring (the particle ladder runs packed below)
-      ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), s2, "zijab");
-      Tensor R = tnew(cx, {k, o, v, o, v}, false);
-      if (prec == ADC_SPLIT_BF16) {
-        Tensor Yr = tnew(cx, {k, o, v, o, v}, false);
-        perm(cx, C1(), Ya, "zikac", false, C0(), Yr, "ziakc");
-        ring_bf16(h, I, Yr.p, (int64_t)k * o * v, R.p);
-        tfree(cx, Yr);
-      } else {
-        ctr(cx, C1(), Ya, "zikac", false, I.ring, "kcjb", false, C0(), R, "ziajb");
-      }
-      perm(cx, C1(), R, "ziajb", false, C0(), T, "zijab");
-      rec_antisym_add(cx, T, s2, k, o, o, v, v, 2, CR(-x));
-      tfree(cx, R);
+  // ---------------- doubles output: every term goes, with its coefficient,
+  // into the accumulator of the antisymmetriser it needs (P(ij): A0, P(ab):
+  // A1, P(ij)P(ab): A2); one pass then antisymmetrises, packs and adds D Y
+  Tensor A0 = tnew(cx, {k, o, o, v, v}), A1 = tnew(cx, {k, o, o, v, v});
+  Tensor A2 = x != 0.0 ? tnew(cx, {k, o, o, v, v}) : Tensor{};
+  // M21(1): (Tv - Tv^ij) + (To - To^ab)
+  ctr(cx, C1(), I.ovvv, "icab", true, ys, "zjc", false, C1(), A0, "zijab");
+  ctr(cx, C1(), I.ooov, "ijka", true, ys, "zkb", false, C1(), A1, "zijab");
+  if (x != 0.0) {
+    // M21(2)
+    Tensor Z1 = tnew(cx, {k, v, v}, false);
+    ctr(cx, C1(), I.ovvv, "iBac", false, ys, "zia", false, C0(), Z1, "zBc");
+    ctr(cx, CR(x), t, "IJAc", false, Z1, "zBc", false, C1(), A1, "zIJAB");
+    ctr(cx, CR(-0.5 * x), I.W, "IJiB", true, ys, "ziA", false, C1(), A1, "zIJAB");
+    tfree(cx, Z1);
+    Tensor Z2 = tnew(cx, {k, o, o}, false);
+    ctr(cx, C1(), I.ooov, "ikJa", false, ys, "zia", false, C0(), Z2, "zkJ");
+    ctr(cx, CR(x), t, "IkAB", false, Z2, "zkJ", false, C1(), A0, "zIJAB");
+    tfree(cx, Z2);
+    Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
+    ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
+    ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
+    tfree(cx, Z4);
+    ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C1(), A2, "zIJAB");
+    ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
+    // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
+    // through P(ij)) and ring; the particle ladder runs packed below
+    ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
+    Tensor R = tnew(cx, {k, o, v, o, v}, false);
+    if (prec == ADC_SPLIT_BF16) {
+      Tensor Yr = tnew(cx, {k, o, v, o, v}, false);
+      perm(cx, C1(), Ya, "zikac", false, C0(), Yr, "ziakc");
+      ring_bf16(h, I, Yr.p, (int64_t)k * o * v, R.p);
+      tfree(cx, Yr);
+    } else {
+      ctr(cx, C1(), Ya, "zikac", false, I.ring, "kcjb", false, C0(), R, "ziajb");
     }
-    tfree(cx, T);
+    perm(cx, CR(-x), R, "ziajb", false, C1(), A2, "zijab");
+    tfree(cx, R);
   }
-  // pack doubles: S2 = extract(s2) + D o Y2
-  rec_pack_doubles(cx, 0, s2, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v);
+  rec_pack_ee(cx, A0, A1, A2, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v);
+  tfree(cx, A0);
+  tfree(cx, A1);
+  if (A2.p) tfree(cx, A2);
   if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, Po, k, CR(x), prec);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
-  for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
+  for (Tensor* p : {&ys, &Ya, &s1}) tfree(cx, *p);
   cx.prec = saved;
 }
 

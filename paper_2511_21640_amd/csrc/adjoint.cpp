@@ -205,6 +205,32 @@ void bw_op(Ctx& cx, const TapeOp& op) {
       launch_fill(gYa, k * per, C0(), cx.stream);
       break;
     }
+    case TapeOp::PACK_EE: {
+      // S = P(ij) A0 + P(ab) A1 + P(ij)P(ab) A2 at the packed positions (+ D Y):
+      // G_Ak += the same antisymmetriser applied to G_S embedded at the packed
+      // positions; the overwrite clears G_S
+      if (!has_grad(T, op.C.p)) break;
+      const int64_t ld = op.n[0], off = op.n[1], k = op.n[2], o = op.n[3], v = op.n[4];
+      const int64_t per = o * o * v * v;
+      double2* gS = grad_ptr(cx, op.C.p);
+      const Tensor* acc[3] = {&op.A, &op.B, &op.extra};
+      bool any = false;
+      for (const Tensor* t : acc) any = any || (t->p && T.rg(t->p));
+      if (any) {
+        double2* tmp = cx.pool.get(k * per);
+        launch_unpack_doubles(0, gS, ld, off, (int)k, (int)o, (int)v, nullptr, tmp, cx.stream);
+        for (int m = 0; m < 3; ++m)
+          if (acc[m]->p && T.rg(acc[m]->p))
+            launch_antisym_add(tmp, grad_ptr(cx, acc[m]->p), k, o, o, v, v, m, C1(), cx.stream);
+        cx.pool.put(tmp);
+      }
+      Tensor g;
+      g.p = gS + off;
+      g.d = {k, packed_n2(0, o, v)};
+      g.st = {ld, 1};
+      scale_view(cx, g, C0());
+      break;
+    }
     case TapeOp::LADDER: {
       if (!has_grad(T, op.C.p)) break;
       double2* gY = T.rg(op.A.p) ? grad_ptr(cx, op.A.p) : nullptr;
@@ -308,4 +334,25 @@ void rec_unpack_doubles(Ctx& cx, int kind, const double2* Y, int64_t ld, int64_t
   launch_unpack_doubles(kind, Y, ld, off, k, o, v, Ya.p, nullptr, cx.stream);
 }
 
+void rec_pack_ee(Ctx& cx, const Tensor& A0, const Tensor& A1, const Tensor& A2, double2* S, const double2* Y,
+                 int64_t ld, int64_t off, int k, int o, int v, const double* eps, const int2* po, const int2* pv) {
+  if (cx.tape && cx.tape->recording) {
+    TapeOp op{};
+    op.kind = TapeOp::PACK_EE;
+    op.A = A0; op.B = A1; op.extra = A2; op.C.p = S;
+    op.n[0] = ld; op.n[1] = off; op.n[2] = k; op.n[3] = o; op.n[4] = v;
+    // an op with three inputs: mark the output from all of them
+    Tape* t = cx.tape;
+    if (A2.p && t->rg(A2.p)) {
+      const int ic = t->find(S);
+      if (ic >= 0) t->allocs[ic].rg = true;
+      const int ia = t->find(A2.p);
+      if (ia >= 0) t->allocs[ia].ref = true;
+    }
+    tape_record(cx, op);
+  }
+  launch_pack_ee(A0.p, A1.p, A2.p, S, Y, ld, off, k, o, v, eps, po, pv, cx.stream);
+}
+
 }  // namespace adc
+

@@ -279,7 +279,8 @@ void gemm(Ctx& cx, GemmDesc g) {
     GemmDesc t = g;
     t.C = scratch; t.scm = g.N; t.scn = 1; t.scb = g.M * g.N;
     t.beta = {0.0, 0.0};
-    ch = tune(cx, candidates(heur, 2), [&](const TuneChoice& c) { run_zgemm(cx, t, c.tile, c.nsplit); });
+    ch = tune(cx, candidates(heur, cx.prec == 1 ? 3 : 2),
+              [&](const TuneChoice& c) { run_zgemm(cx, t, c.tile, c.nsplit); });
     cx.pool.put(scratch);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[key] = ch;

@@ -105,6 +105,12 @@ void launch_antisym_add(const double2* X, double2* out, int64_t k, int64_t d1, i
 void launch_ladder_pack(const double2* W, int64_t ldw, int a0, int b0, int nv, double2* V, int64_t pbase,
                         int64_t npairs, const int2* pair_v, hipStream_t s);
 
+// EE doubles: S[z][off + packed(ij,ab)] = P(ij) A0 + P(ab) A1 + P(ij)P(ab) A2 at
+// (i<j, a<b) + D Y (A2 may be null); A0..A2 are [k][o][o][v][v]
+void launch_pack_ee(const double2* A0, const double2* A1, const double2* A2, double2* S, const double2* Y, int64_t ld,
+                    int64_t off, int k, int no, int nv, const double* eps, const int2* po, const int2* pv,
+                    hipStream_t s);
+
 // adjoint helpers
 // gf[a][A] += sum_i gX[(i,a),(i,A)] (which 0) or gf[i][I] += sum_a gX[(i,a),(I,a)] (which 1)
 void launch_m11_delta_adjoint(const double2* gX, double2* gf, int no, int nv, int which, hipStream_t s);
@@ -169,7 +175,7 @@ struct TapeOp;
 using LadderBw = void (*)(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY);
 
 struct TapeOp {
-  enum Kind { CTR, PERM, DIV_D2, DIV_D1, ANTISYM, HERM_ADD, M11_DELTA, PACK, UNPACK, LADDER } kind;
+  enum Kind { CTR, PERM, DIV_D2, DIV_D1, ANTISYM, HERM_ADD, M11_DELTA, PACK, UNPACK, LADDER, PACK_EE } kind;
   Tensor A, B, C;
   std::string la, lb, lc;
   bool cA = false, cB = false;
@@ -180,10 +186,12 @@ struct TapeOp {
   //  M11_DELTA, DIV_*  n = {o, v, which}
   //  PACK / UNPACK  n = {kind, ld, off, k, o, v, accumulate}
   //  LADDER   n = {ldY, offY, ldS, offS, nrow, k}
+  //  PACK_EE  A, B, C = A0, A1, S; n = {ld, off, k, o, v}; the tensor A2 rides in `extra`
   int64_t n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const double* eps = nullptr;
   const int2* po = nullptr;
   const int2* pv = nullptr;
+  Tensor extra;
   void* inst = nullptr;     // LADDER: the instance whose L_vv the ladder reads
   void* owner = nullptr;    // LADDER: the library handle
   LadderBw ladder_bw = nullptr;
@@ -257,6 +265,8 @@ void rec_pack_doubles(Ctx& cx, int kind, const Tensor& U, double2* S, const doub
                       const int2* pv);
 void rec_unpack_doubles(Ctx& cx, int kind, const double2* Y, int64_t ld, int64_t off, int k, int o, int v, Tensor& Ya,
                         const double* eps, const int2* po, const int2* pv);
+void rec_pack_ee(Ctx& cx, const Tensor& A0, const Tensor& A1, const Tensor& A2, double2* S, const double2* Y,
+                 int64_t ld, int64_t off, int k, int o, int v, const double* eps, const int2* po, const int2* pv);
 // view of t with dimension `dim` restricted to [lo, hi)
 Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi);
 void tfree(Ctx& cx, Tensor& t);

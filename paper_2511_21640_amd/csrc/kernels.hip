@@ -597,8 +597,10 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (h.nsplit < 1 || h.kchunk <= 0) { h.nsplit = 1; h.kchunk = h.Kp; }
   int tile = h.tile;
   if (tile < 0) {
-    const int64_t big = ((h.M + 127) / 128) * ((h.N + 127) / 128) * h.nsplit;
-    tile = (big >= 256 && pad_waste(h.M, 128) < 0.10 && pad_waste(h.N, 128) < 0.10) ? 1 : 0;
+    // 128x64 (two waves per SIMD, 4x2 MFMA blocks per wave) when it fills the
+    // chip without much padding, else 64x64
+    const int64_t mid = ((h.M + 127) / 128) * ((h.N + 63) / 64) * h.nsplit;
+    tile = (mid >= 256 && pad_waste(h.M, 128) < 0.10 && pad_waste(h.N, 64) < 0.10) ? 2 : 0;
   }
   switch (tile) {
     case 1: launch_bf16p_tile<4, 4>(h, s); break;
@@ -680,25 +682,23 @@ static void launch_tile(const GemmDesc& g, hipStream_t s) {
   else hipLaunchKernelGGL((zgemm_kernel<T, WM, WN, 0>), grid, dim3(256), 0, s, g);
 }
 
-// Tile choice: the big tile (FP64 128x64, FP32 128x128) halves the operand
-// traffic per MFMA but pads M and N to multiples of 128; it is used only when
-// the padding wastes under 10% and the grid still fills the chip.
+// Tile choice: 64x64 by default.  With the accumulators in VGPRs it runs two
+// (FP64) or three (FP32) waves per SIMD and measures faster than the larger
+// tiles (FP64 128x64, FP32 128x128 / 128x64), which stay selectable (tile 1, 2).
 void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0 || g0.K <= 0) return;
   GemmDesc g = g0;
   if (g.nsplit < 1) g.nsplit = 1;
   if (g.nsplit == 1 || g.kchunk <= 0) { g.nsplit = 1; g.kchunk = g.K; }
-  const int64_t BNbig = prec == 0 ? 64 : 128;
-  const int64_t big = ((g.M + 127) / 128) * ((g.N + BNbig - 1) / BNbig) * g.batch * g.nsplit;
-  const bool use_big = g.tile >= 0 ? g.tile == 1
-                                   : big >= 256 && pad_waste(g.M, 128) < 0.10 && pad_waste(g.N, BNbig) < 0.10;
+  const bool use_big = g.tile == 1;
   if (prec == 2) {
     launch_bf16x3(g, s);
   } else if (prec == 0) {
     if (use_big) launch_tile<double, 4, 2>(g, s);
     else launch_tile<double, 2, 2>(g, s);
   } else {
-    if (use_big) launch_tile<float, 4, 4>(g, s);
+    if (g.tile == 2) launch_tile<float, 4, 2>(g, s);
+    else if (use_big) launch_tile<float, 4, 4>(g, s);
     else launch_tile<float, 2, 2>(g, s);
   }
 }
@@ -1126,6 +1126,54 @@ void launch_precondition(const double2* R, double2* N, const double* D, const do
                          hipStream_t s) {
   if (rows <= 0) return;
   hipLaunchKernelGGL(precondition_kernel, dim3(nblocks((int64_t)rows * n, 256)), dim3(256), 0, s, R, N, D, w, rows, n);
+}
+
+// EE doubles output, antisymmetrised and packed in one pass:
+//   S[z][off + pair(i,j)*Pv + pair(a,b)] = A0[ij ab] - A0[ji ab]            (P(ij))
+//        + A1[ij ab] - A1[ij ba]                                            (P(ab))
+//        + A2[ij ab] - A2[ji ab] - A2[ij ba] + A2[ji ba]                    (P(ij)P(ab))
+//        + D_ijab Y[z][off + ...]
+// for i<j, a<b; A0..A2 are [k][o][o][v][v] (A2 may be null)
+__global__ __launch_bounds__(256) void pack_ee_kernel(const double2* A0, const double2* A1, const double2* A2,
+                                                      double2* S, const double2* Y, int64_t ld, int64_t off, int k,
+                                                      int no, int nv, const double* eps, const int2* po,
+                                                      const int2* pv) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
+  const int64_t n2 = Po * Pv, per = (int64_t)no * no * nv * nv;
+  const int64_t total = n2 * k;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = idx / n2, q = idx - z * n2;
+    const int64_t pij = q / Pv, pab = q - pij * Pv;
+    const int2 ij = po[pij], ab = pv[pab];
+    const int64_t b0 = z * per;
+    const int64_t o_ijab = (((int64_t)ij.x * no + ij.y) * nv + ab.x) * nv + ab.y;
+    const int64_t o_jiab = (((int64_t)ij.y * no + ij.x) * nv + ab.x) * nv + ab.y;
+    const int64_t o_ijba = (((int64_t)ij.x * no + ij.y) * nv + ab.y) * nv + ab.x;
+    const int64_t o_jiba = (((int64_t)ij.y * no + ij.x) * nv + ab.y) * nv + ab.x;
+    double2 a = A0[b0 + o_ijab], c = A0[b0 + o_jiab];
+    double rx = a.x - c.x, ry = a.y - c.y;
+    a = A1[b0 + o_ijab];
+    c = A1[b0 + o_ijba];
+    rx += a.x - c.x;
+    ry += a.y - c.y;
+    if (A2) {
+      const double2 w1 = A2[b0 + o_ijab], w2 = A2[b0 + o_jiab], w3 = A2[b0 + o_ijba], w4 = A2[b0 + o_jiba];
+      rx += w1.x - w2.x - w3.x + w4.x;
+      ry += w1.y - w2.y - w3.y + w4.y;
+    }
+    const double D = eps[no + ab.x] + eps[no + ab.y] - eps[ij.x] - eps[ij.y];
+    const double2 y = Y[z * ld + off + q];
+    S[z * ld + off + q] = make_double2(rx + D * y.x, ry + D * y.y);
+  }
+}
+void launch_pack_ee(const double2* A0, const double2* A1, const double2* A2, double2* S, const double2* Y, int64_t ld,
+                    int64_t off, int k, int no, int nv, const double* eps, const int2* po, const int2* pv,
+                    hipStream_t s) {
+  const int64_t n2 = (int64_t)no * (no - 1) / 2 * ((int64_t)nv * (nv - 1) / 2);
+  if (n2 * k == 0) return;
+  hipLaunchKernelGGL(pack_ee_kernel, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, A0, A1, A2, S, Y, ld, off, k, no,
+                     nv, eps, po, pv);
 }
 
 // ---------------------------------------------------------------------------
