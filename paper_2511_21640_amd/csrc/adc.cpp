@@ -59,11 +59,9 @@ struct Inst {
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
-  // split-bf16 planes [4][rows][K padded to 32], built on first use
+  // split-bf16 planes [4][rows][K padded to 32] of L_vv, built on first use
   unsigned short* Lq = nullptr;     // rows (a,c) of L_vv, K = Q
   int64_t Kq = 0;
-  unsigned short* ringp = nullptr;  // rows (j,b), K = (k,c): conj(ring) = ring^T
-  int64_t Kr = 0;
   std::vector<double> m11diag;  // host, real part of diag(M11x)
   // captured sigma builds (Davidson of small instances): one per (rows, precision)
   struct Graph {
@@ -136,34 +134,12 @@ unsigned short* planes_alloc(Ctx& cx, int64_t rows, int64_t Kp) {
 
 void ensure_planes(adc_handle* h, Inst& I) {
   Ctx& cx = *I.cx;
-  const int64_t v = I.v, ov = (int64_t)I.o * I.v;
+  const int64_t v = I.v;
   if (!I.Lq) {
     I.Kq = pad32(I.N);
     I.Lq = (unsigned short*)dmalloc(h, (size_t)v * v * I.Kq * 8);
     launch_split_planes(I.Lvv.p, v * v, I.N, 1, v * v, 0, I.Lq, I.Kq, cx.stream);
   }
-  if (!I.ringp) {
-    I.Kr = pad32(ov);
-    I.ringp = (unsigned short*)dmalloc(h, (size_t)ov * I.Kr * 8);
-    launch_split_planes(I.ring.p, ov, ov, ov, 1, 1, I.ringp, I.Kr, cx.stream);
-  }
-}
-
-// R[r][(j,b)] = sum_(k,c) X[r][(k,c)] <kb||jc> for rows r of X (contiguous [rows][ov]), split-bf16
-void ring_bf16(adc_handle* h, Inst& I, const double2* X, int64_t rows, double2* R) {
-  Ctx& cx = *I.cx;
-  ensure_planes(h, I);
-  const int64_t ov = (int64_t)I.o * I.v;
-  unsigned short* Xp = planes_alloc(cx, rows, I.Kr);
-  launch_split_planes(X, rows, ov, ov, 1, 0, Xp, I.Kr, cx.stream);
-  BfGemm g{};
-  g.M = rows; g.N = ov; g.Kp = I.Kr;
-  g.A = Xp; g.lda = rows;
-  g.B = I.ringp; g.ldb = ov;
-  g.C = R; g.scm = ov; g.scn = 1;
-  g.alpha = C1(); g.beta = C0();
-  gemm_bf16p(cx, g);
-  cx.pool.put((double2*)Xp);
 }
 
 // ----------------------------------------------------------------------------
@@ -717,17 +693,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
     // through P(ij)) and ring; the particle ladder runs packed below
     ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
-    Tensor R = tnew(cx, {k, o, v, o, v}, false);
-    if (prec == ADC_SPLIT_BF16) {
-      Tensor Yr = tnew(cx, {k, o, v, o, v}, false);
-      perm(cx, C1(), Ya, "zikac", false, C0(), Yr, "ziakc");
-      ring_bf16(h, I, Yr.p, (int64_t)k * o * v, R.p);
-      tfree(cx, Yr);
-    } else {
-      ctr(cx, C1(), Ya, "zikac", false, I.ring, "kcjb", false, C0(), R, "ziajb");
-    }
-    perm(cx, CR(-x), R, "ziajb", false, C1(), A2, "zijab");
-    tfree(cx, R);
+    ctr(cx, CR(-x), Ya, "zikac", false, I.ring, "kcjb", false, C1(), A2, "zijab");
   }
   rec_pack_ee(cx, A0, A1, A2, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v);
   tfree(cx, A0);
@@ -772,8 +738,7 @@ void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     rec_antisym_add(cx, T, s2, k, o, o, v, 1, 0, CR(x));
     // M22(1): hole ladder and ring
     ctr(cx, CR(0.5 * x), I.oooo, "klij", false, Ya, "zkla", false, C1(), s2, "zija");
-    if (prec == ADC_SPLIT_BF16) ring_bf16(h, I, Ya.p, (int64_t)k * o, T.p);
-    else ctr(cx, C1(), Ya, "zikc", false, I.ring, "kcja", false, C0(), T, "zija");
+    ctr(cx, C1(), Ya, "zikc", false, I.ring, "kcja", false, C0(), T, "zija");
     rec_antisym_add(cx, T, s2, k, o, o, v, 1, 0, CR(-x));
     tfree(cx, T);
   }
@@ -823,16 +788,7 @@ void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, CR(-0.5 * x), t, "klAB", false, Z, "zklI", false, C1(), s2, "zIAB");
     tfree(cx, Z);
     // M22(1) ring (the particle ladder runs packed below)
-    if (prec == ADC_SPLIT_BF16) {
-      Tensor Yr = tnew(cx, {k, v, o, v}, false), Rr = tnew(cx, {k, v, o, v}, false);
-      perm(cx, C1(), Ya, "zjac", false, C0(), Yr, "zajc");
-      ring_bf16(h, I, Yr.p, (int64_t)k * v, Rr.p);
-      perm(cx, C1(), Rr, "zaib", false, C0(), T, "ziab");
-      tfree(cx, Yr);
-      tfree(cx, Rr);
-    } else {
-      ctr(cx, C1(), Ya, "zjac", false, I.ring, "jcib", false, C0(), T, "ziab");
-    }
+    ctr(cx, C1(), Ya, "zjac", false, I.ring, "jcib", false, C0(), T, "ziab");
     rec_antisym_add(cx, T, s2, k, o, 1, v, v, 1, CR(-x));
     tfree(cx, T);
   }

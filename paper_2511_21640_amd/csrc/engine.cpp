@@ -279,6 +279,7 @@ void gemm(Ctx& cx, GemmDesc g) {
     GemmDesc t = g;
     t.C = scratch; t.scm = g.N; t.scn = 1; t.scb = g.M * g.N;
     t.beta = {0.0, 0.0};
+    t.om = OutMap{};
     ch = tune(cx, candidates(heur, cx.prec == 1 ? 3 : 2),
               [&](const TuneChoice& c) { run_zgemm(cx, t, c.tile, c.nsplit); });
     cx.pool.put(scratch);
@@ -309,6 +310,7 @@ void gemm_bf16p(Ctx& cx, BfGemm g) {
     BfGemm t = g;
     t.C = scratch; t.scm = g.N; t.scn = 1;
     t.beta = {0.0, 0.0};
+    t.om = OutMap{};
     ch = tune(cx, candidates(heur, 4), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
     cx.pool.put(scratch);
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -368,6 +370,69 @@ int64_t prod(const View& v, const std::string& grp) {
   int64_t p = 1;
   for (char c : grp) p *= v.size.at(c);
   return p;
+}
+
+// Mixed-radix digits (at most four) of the label group `grp` of view v, with
+// adjacent labels that fuse merged; an empty group is one digit of extent 1.
+bool split_digits(const View& v, const std::string& grp, int& n, int64_t* d, int64_t* st) {
+  std::vector<int64_t> dd, ss;
+  for (char c : grp) {
+    const int64_t sz = v.size.at(c), sd = v.stride.at(c);
+    if (!dd.empty() && ss.back() == sd * sz) {
+      dd.back() *= sz;
+      ss.back() = sd;
+    } else {
+      dd.push_back(sz);
+      ss.push_back(sd);
+    }
+  }
+  if (dd.empty()) {
+    dd.push_back(1);
+    ss.push_back(0);
+  }
+  if (dd.size() > 4) return false;
+  n = (int)dd.size();
+  for (int q = 0; q < n; ++q) {
+    d[q] = dd[q];
+    st[q] = ss[q];
+  }
+  return true;
+}
+
+// Output layout of one label group of C: a single stride when the group fuses,
+// else a mixed-radix map of at most three digits (adjacent labels that fuse
+// are merged first).  Returns false when neither applies.
+bool group_map(const View& v, const std::string& grp, int64_t& stride, int& n, int64_t* d, int64_t* st) {
+  n = 0;
+  if (grp.empty()) {
+    stride = 0;
+    return true;
+  }
+  const int64_t f = fused_stride(v, grp);
+  if (f >= 0) {
+    stride = f;
+    return true;
+  }
+  if (prod(v, grp) >= ((int64_t)1 << 31)) return false;
+  std::vector<int64_t> dd, ss;
+  for (char c : grp) {
+    const int64_t sz = v.size.at(c), sd = v.stride.at(c);
+    if (!dd.empty() && ss.back() == sd * sz) {
+      dd.back() *= sz;
+      ss.back() = sd;
+    } else {
+      dd.push_back(sz);
+      ss.push_back(sd);
+    }
+  }
+  if (dd.size() > 3) return false;
+  n = (int)dd.size();
+  for (int q = 0; q < n; ++q) {
+    d[q] = dd[q];
+    st[q] = ss[q];
+  }
+  stride = 1;
+  return true;
 }
 
 // copy/accumulate view v of src into dst, iterating the labels `ord`;
@@ -540,7 +605,13 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
     const int64_t kChunk = std::max<int64_t>(1, cx.max_temp);
     const bool pA = fused_stride(va, bat) < 0 || fused_stride(va, Ml) < 0 || fused_stride(va, Kl) < 0;
     const bool pB = fused_stride(vb, bat) < 0 || fused_stride(vb, Nl) < 0 || fused_stride(vb, Kl) < 0;
-    const bool pC = fused_stride(vc, bat) < 0 || fused_stride(vc, Ml) < 0 || fused_stride(vc, Nl) < 0;
+    bool pC = fused_stride(vc, bat) < 0;
+    {
+      int64_t st0 = 0;
+      int nq = 0;
+      int64_t dq[3], sq[3];
+      pC = pC || !group_map(vc, Ml, st0, nq, dq, sq) || !group_map(vc, Nl, st0, nq, dq, sq);
+    }
     const int64_t need = std::max({pA ? A.size() : 0, pB ? B.size() : 0, pC ? C.size() : 0});
     if (need > kChunk) {
       const Tensor* X = (pA && A.size() == need) ? &A : (pB && B.size() == need) ? &B : &C;
@@ -583,37 +654,50 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   // ---- split-bf16: unbatched contractions run on pre-split operand planes
   if (cx.prec == 2 && bat.empty() && Kn >= 32) {
     const int64_t Kp = (Kn + 31) / 32 * 32;
-    // A as [M][K] with K contiguous
-    const double2* Ap = A.p;
-    int64_t sam = fused_stride(va, Ml), sak = fused_stride(va, Kl);
-    if (Ml.empty()) sam = 0;
-    if (sam < 0 || sak != 1) {
-      double2* t = cx.pool.get(A.size());
-      tmps.push_back(t);
-      permute_into(cx, A, va, Ml + Kl, false, t, C1(), C0());
-      Ap = t; sam = Kn; sak = 1;
-    }
-    const double2* Bp = B.p;
-    int64_t sbn = fused_stride(vb, Nl), sbk = fused_stride(vb, Kl);
-    if (Nl.empty()) sbn = 0;
-    if (sbn < 0 || sbk != 1) {
-      double2* t = cx.pool.get(B.size());
-      tmps.push_back(t);
-      permute_into(cx, B, vb, Nl + Kl, false, t, C1(), C0());
-      Bp = t; sbn = Kn; sbk = 1;
+    // K order: decreasing stride in the larger operand, so that its split
+    // reads run along its unit stride where the K labels allow it
+    std::string Ko = Kl;
+    {
+      const View& vl = A.size() >= B.size() ? va : vb;
+      std::stable_sort(Ko.begin(), Ko.end(), [&](char a, char b) { return vl.stride.at(a) > vl.stride.at(b); });
     }
     unsigned short* Aq = (unsigned short*)cx.pool.get((Mn * Kp * 4 + 7) / 8);
     unsigned short* Bq = (unsigned short*)cx.pool.get((Nn * Kp * 4 + 7) / 8);
-    launch_split_planes(Ap, Mn, Kn, sam, 1, cA ? 1 : 0, Aq, Kp, cx.stream);
-    launch_split_planes(Bp, Nn, Kn, sbn, 1, cB ? 1 : 0, Bq, Kp, cx.stream);
+    auto split = [&](const Tensor& X, const View& vx, const std::string& rl, bool conj, unsigned short* dst,
+                     int64_t rows) {
+      SplitNd sp{};
+      sp.dst = dst;
+      sp.rows = rows;
+      sp.K = Kn;
+      sp.Kp = Kp;
+      sp.conj = conj ? 1 : 0;
+      if (rows < ((int64_t)1 << 31) && Kp < ((int64_t)1 << 31) && split_digits(vx, rl, sp.nm, sp.md, sp.ms) &&
+          split_digits(vx, Ko, sp.nk, sp.kd, sp.ks)) {
+        sp.src = X.p;
+        const bool tiled = sp.ks[sp.nk - 1] != 1 && sp.ms[sp.nm - 1] == 1;
+        launch_split_nd(sp, tiled ? 1 : 0, cx.stream);
+        return;
+      }
+      // more than four digits: go through a contiguous copy
+      double2* t = cx.pool.get(X.size());
+      tmps.push_back(t);
+      permute_into(cx, X, vx, rl + Ko, false, t, C1(), C0());
+      sp.src = t;
+      sp.nm = 1; sp.md[0] = rows; sp.ms[0] = Kn;
+      sp.nk = 1; sp.kd[0] = Kn; sp.ks[0] = 1;
+      launch_split_nd(sp, 0, cx.stream);
+    };
+    split(A, va, Ml, cA, Aq, Mn);
+    split(B, vb, Nl, cB, Bq, Nn);
     BfGemm g{};
     g.M = Mn; g.N = Nn; g.Kp = Kp;
     g.A = Aq; g.lda = Mn;
     g.B = Bq; g.ldb = Nn;
     g.alpha = alpha; g.beta = beta;
-    const int64_t scm = fused_stride(vc, Ml), scn = fused_stride(vc, Nl);
-    if (scm >= 0 && scn >= 0) {
-      g.C = C.p; g.scm = Ml.empty() ? 0 : scm; g.scn = Nl.empty() ? 0 : scn;
+    int64_t scm = 0, scn = 0;
+    OutMap om{};
+    if (group_map(vc, Ml, scm, om.nm, om.md, om.ms) && group_map(vc, Nl, scn, om.nn, om.nd, om.ns)) {
+      g.C = C.p; g.scm = scm; g.scn = scn; g.om = om;
       gemm_bf16p(cx, g);
     } else {
       double2* t = cx.pool.get(Mn * Nn);
@@ -666,9 +750,11 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
     if (beta.re != 1.0 || beta.im != 0.0) perm(cx, beta, C, lc, false, C0(), C, lc);
   } else {
     // ---- output
-    int64_t sbt = fused_stride(vc, bat), sm = fused_stride(vc, Ml), sn = fused_stride(vc, Nl);
-    if (sbt >= 0 && sm >= 0 && sn >= 0) {
-      g.C = C.p; g.scb = bat.empty() ? 0 : sbt; g.scm = Ml.empty() ? 0 : sm; g.scn = Nl.empty() ? 0 : sn;
+    const int64_t sbt = fused_stride(vc, bat);
+    int64_t sm = 0, sn = 0;
+    OutMap om{};
+    if (sbt >= 0 && group_map(vc, Ml, sm, om.nm, om.md, om.ms) && group_map(vc, Nl, sn, om.nn, om.nd, om.ns)) {
+      g.C = C.p; g.scb = bat.empty() ? 0 : sbt; g.scm = sm; g.scn = sn; g.om = om;
       gemm(cx, g);
     } else {
       double2* t = cx.pool.get(Bn * Mn * Nn);

@@ -15,6 +15,16 @@ struct cplx {
 };
 
 // ---------------------------------------------------------------- GEMM
+// Optional N-d layout of a GEMM output: with nm > 0 the row index m is split
+// in the mixed radix md[0..nm) (last digit fastest) and its C offset is
+// sum_q digit_q * ms[q] (instead of m * scm); likewise nn/nd/ns for columns.
+// Lets one GEMM write straight into an output whose M or N labels are not one
+// fused stride.  Each group's extent must stay below 2^31.
+struct OutMap {
+  int nm, nn;
+  int64_t md[3], ms[3], nd[3], ns[3];
+};
+
 // C[b] = alpha * op(A[b]) op(B[b]) + beta * C[b] with element strides
 // (complex elements) A(m,k) at A + m*sam + k*sak + b*sab, B(k,n) at
 // B + k*sbk + n*sbn + b*sbb, C(m,n) at C + m*scm + n*scn + b*scb.
@@ -33,6 +43,7 @@ struct GemmDesc {
   int nsplit;
   double2* P;
   int tile;  // -1 heuristic, 0 small tiles, 1 large tiles
+  OutMap om;
 };
 void launch_splitk_reduce(const GemmDesc& g, hipStream_t s);
 // prec: 0 = FP64 MFMA, 1 = FP32 MFMA (operands rounded to fp32, fp32
@@ -53,12 +64,27 @@ struct BfGemm {
   int nsplit;
   double2* P;
   int tile;  // -1 heuristic, 0 small tiles, 1 large tiles
+  OutMap om;
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);
 void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s);
 // dst planes [4][rows][Kp] from src(r, k) = src[r*srow + k*sk] (conj: negate im), zero for k >= K
 void launch_split_planes(const double2* src, int64_t rows, int64_t K, int64_t srow, int64_t sk, int conj,
                          unsigned short* dst, int64_t Kp, hipStream_t s);
+// Split planes [4][rows][Kp] of an operand given as an N-d view: row r and
+// column k (< K) are split in mixed radices md/kd (last digit fastest, at most
+// four digits each) with source strides ms/ks; zero for K <= k < Kp.
+struct SplitNd {
+  const double2* src;
+  unsigned short* dst;
+  int nm, nk;
+  int64_t md[4], ms[4], kd[4], ks[4];
+  int64_t rows, K, Kp;
+  int conj;
+};
+// tiled = 1 stages 64 x 32 blocks through LDS so that reads run along the
+// rows (for sources whose unit stride is a row digit)
+void launch_split_nd(const SplitNd& p, int tiled, hipStream_t s);
 void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
                                int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s);
 

@@ -20,6 +20,20 @@ static inline unsigned nblocks(int64_t n, int t) {
   return (unsigned)b;
 }
 
+// C offset of a row (or column) index under an OutMap group (see internal.h)
+__device__ __forceinline__ int64_t omap(int64_t x, int n, const int64_t* d, const int64_t* st, int64_t s1) {
+  if (n == 0) return x * s1;
+  uint32_t u = (uint32_t)x;
+  int64_t off = 0;
+  for (int q = n - 1; q > 0; --q) {
+    const uint32_t dq = (uint32_t)d[q];
+    const uint32_t v = u / dq;
+    off += (int64_t)(u - v * dq) * st[q];
+    u = v;
+  }
+  return off + (int64_t)u * st[0];
+}
+
 // ---------------------------------------------------------------------------
 // Complex GEMM on the matrix cores.
 //
@@ -177,7 +191,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc p) {
             p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
             continue;
           }
-          double2* dst = C + row * p.scm + col * p.scn;
+          double2* dst = C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
           double2 o;
           o.x = p.alpha.re * cr - p.alpha.im * ci;
           o.y = p.alpha.re * ci + p.alpha.im * cr;
@@ -203,7 +217,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmDesc p) {
       sr += v.x;
       si += v.y;
     }
-    double2* dst = p.C + b * p.scb + m * p.scm + n * p.scn;
+    double2* dst = p.C + b * p.scb + omap(m, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(n, p.om.nn, p.om.nd, p.om.ns, p.scn);
     double2 o;
     o.x = p.alpha.re * sr - p.alpha.im * si;
     o.y = p.alpha.re * si + p.alpha.im * sr;
@@ -382,7 +396,7 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc p) {
             p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
             continue;
           }
-          double2* dst = C + row * p.scm + col * p.scn;
+          double2* dst = C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
           double2 o;
           o.x = p.alpha.re * cr - p.alpha.im * ci;
           o.y = p.alpha.re * ci + p.alpha.im * cr;
@@ -435,6 +449,79 @@ void launch_split_planes(const double2* src, int64_t rows, int64_t K, int64_t sr
   if (rows * Kp == 0) return;
   hipLaunchKernelGGL(split_planes_kernel, dim3(nblocks(rows * Kp, 256)), dim3(256), 0, s, src, rows, K, srow, sk, conj,
                      dst, Kp);
+}
+
+__device__ __forceinline__ int64_t digits_off(uint32_t x, int n, const int64_t* d, const int64_t* st) {
+  int64_t off = 0;
+  for (int q = n - 1; q > 0; --q) {
+    const uint32_t dq = (uint32_t)d[q];
+    const uint32_t v = x / dq;
+    off += (int64_t)(x - v * dq) * st[q];
+    x = v;
+  }
+  return off + (int64_t)x * st[0];
+}
+
+__device__ __forceinline__ void put_planes(unsigned short* dst, int64_t plane, int64_t at, double2 v, int conj) {
+  unsigned short h0, l0, h1, l1;
+  split_bf16((float)v.x, h0, l0);
+  split_bf16(conj ? -(float)v.y : (float)v.y, h1, l1);
+  dst[at] = h0;
+  dst[plane + at] = l0;
+  dst[2 * plane + at] = h1;
+  dst[3 * plane + at] = l1;
+}
+
+__global__ __launch_bounds__(256) void split_nd_kernel(SplitNd p) {
+  const int64_t total = p.rows * p.Kp, plane = total;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / p.Kp, k = idx - r * p.Kp;
+    double2 v = make_double2(0.0, 0.0);
+    if (k < p.K) v = p.src[digits_off((uint32_t)r, p.nm, p.md, p.ms) + digits_off((uint32_t)k, p.nk, p.kd, p.ks)];
+    put_planes(p.dst, plane, idx, v, p.conj);
+  }
+}
+
+__global__ __launch_bounds__(256) void split_nd_tiled_kernel(SplitNd p) {
+  __shared__ double2 tile[32][65];
+  const int64_t plane = p.rows * p.Kp;
+  const int64_t r0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 32;
+  const int t = threadIdx.x;
+  {
+    const int rr = t & 63;
+    const int64_t r = r0 + rr;
+    const int64_t ro = r < p.rows ? digits_off((uint32_t)r, p.nm, p.md, p.ms) : 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kk = (t >> 6) + 4 * e;
+      const int64_t k = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (r < p.rows && k < p.K) v = p.src[ro + digits_off((uint32_t)k, p.nk, p.kd, p.ks)];
+      tile[kk][rr] = v;
+    }
+  }
+  __syncthreads();
+  {
+    const int kk = t & 31;
+    const int64_t k = k0 + kk;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int rr = (t >> 5) + 8 * e;
+      const int64_t r = r0 + rr;
+      if (r < p.rows && k < p.Kp) put_planes(p.dst, plane, r * p.Kp + k, tile[kk][rr], p.conj);
+    }
+  }
+}
+
+void launch_split_nd(const SplitNd& p, int tiled, hipStream_t s) {
+  if (p.rows * p.Kp == 0) return;
+  if (tiled) {
+    dim3 grid((unsigned)((p.rows + 63) / 64), (unsigned)((p.Kp + 31) / 32));
+    hipLaunchKernelGGL(split_nd_tiled_kernel, grid, dim3(256), 0, s, p);
+  } else {
+    hipLaunchKernelGGL(split_nd_kernel, dim3(nblocks(p.rows * p.Kp, 256)), dim3(256), 0, s, p);
+  }
 }
 
 template <int WM, int WN, int TAG>
@@ -565,7 +652,7 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
             p.P[(sidx * p.M + row) * p.N + col] = make_double2(cr, ci);
             continue;
           }
-          double2* dst = p.C + row * p.scm + col * p.scn;
+          double2* dst = p.C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
           double2 o;
           o.x = p.alpha.re * cr - p.alpha.im * ci;
           o.y = p.alpha.re * ci + p.alpha.im * cr;
@@ -622,7 +709,7 @@ __global__ void splitk_reduce_bf_kernel(BfGemm p) {
       sr += v.x;
       si += v.y;
     }
-    double2* dst = p.C + m * p.scm + n * p.scn;
+    double2* dst = p.C + omap(m, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(n, p.om.nn, p.om.nd, p.om.ns, p.scn);
     double2 o;
     o.x = p.alpha.re * sr - p.alpha.im * si;
     o.y = p.alpha.re * si + p.alpha.im * sr;
@@ -718,17 +805,29 @@ struct PermArgs {
   int conj;
 };
 
+template <bool SMALL>
 __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
   const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < p.total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    int64_t rem = idx, off = 0, ooff = 0;
-    for (int d = p.nd - 1; d >= 0; --d) {
-      const int64_t q = rem / p.od[d];
-      const int64_t r = rem - q * p.od[d];
-      off += r * p.is[d];
-      ooff += r * p.os[d];
-      rem = q;
+    int64_t off = 0, ooff = 0;
+    if (SMALL) {  // 32-bit index arithmetic (total < 2^32)
+      uint32_t rem = (uint32_t)idx;
+      for (int d = p.nd - 1; d >= 0; --d) {
+        const uint32_t dd = (uint32_t)p.od[d], q = rem / dd, r = rem - q * dd;
+        off += (int64_t)r * p.is[d];
+        ooff += (int64_t)r * p.os[d];
+        rem = q;
+      }
+    } else {
+      int64_t rem = idx;
+      for (int d = p.nd - 1; d >= 0; --d) {
+        const int64_t q = rem / p.od[d];
+        const int64_t r = rem - q * p.od[d];
+        off += r * p.is[d];
+        ooff += r * p.os[d];
+        rem = q;
+      }
     }
     double2 v = p.in[off];
     if (p.conj) v.y = -v.y;
@@ -741,6 +840,67 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
       o.y += p.beta.re * old.y + p.beta.im * old.x;
     }
     p.out[ooff] = o;
+  }
+}
+
+// Transposing permute: dims di (unit input stride) and dO (unit output stride)
+// differ; 32 x 32 tiles of (di, dO) go through LDS so that both the reads and
+// the writes are coalesced.  The other dims (mixed radix, 32-bit) index the
+// tiles together with the tile position: blockIdx.x = rest * tiles + tile.
+struct PermTiled {
+  PermArgs a;
+  int di, dO;
+  int64_t tdi, tdo, ntile, nrest;
+};
+__global__ __launch_bounds__(256) void permute_tiled_kernel(PermTiled q) {
+  __shared__ double2 tile[32][33];
+  const PermArgs& p = q.a;
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  for (int64_t blk = blockIdx.x; blk < q.ntile * q.nrest; blk += gridDim.x) {
+    const int64_t rest = blk / q.ntile, tl = blk - rest * q.ntile;
+    const int64_t i0 = (tl / q.tdo) * 32, o0 = (tl % q.tdo) * 32;
+    int64_t ioff = 0, ooff = 0;
+    {
+      uint32_t rem = (uint32_t)rest;
+      for (int d = p.nd - 1; d >= 0; --d) {
+        if (d == q.di || d == q.dO) continue;
+        const uint32_t dd = (uint32_t)p.od[d], qq = rem / dd, r = rem - qq * dd;
+        ioff += (int64_t)r * p.is[d];
+        ooff += (int64_t)r * p.os[d];
+        rem = qq;
+      }
+    }
+    const int64_t ni = p.od[q.di], no = p.od[q.dO];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int a = t & 31, b = (t >> 5) + 8 * e;  // a along di, b along dO
+      const int64_t ia = i0 + a, ob = o0 + b;
+      double2 v = make_double2(0.0, 0.0);
+      if (ia < ni && ob < no) v = p.in[ioff + ia + ob * p.is[q.dO]];
+      tile[b][a] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int b = t & 31, a = (t >> 5) + 8 * e;
+      const int64_t ia = i0 + a, ob = o0 + b;
+      if (ia < ni && ob < no) {
+        double2 v = tile[b][a];
+        if (p.conj) v.y = -v.y;
+        double2 o;
+        o.x = p.alpha.re * v.x - p.alpha.im * v.y;
+        o.y = p.alpha.re * v.y + p.alpha.im * v.x;
+        double2* dst = p.out + ooff + ia * p.os[q.di] + ob;
+        if (has_beta) {
+          const double2 old = *dst;
+          o.x += p.beta.re * old.x - p.beta.im * old.y;
+          o.y += p.beta.re * old.y + p.beta.im * old.x;
+        }
+        *dst = o;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -761,7 +921,28 @@ void launch_permute(int nd, const int64_t* od, const int64_t* istr, const int64_
   a.alpha = alpha;
   a.beta = beta;
   a.conj = conj;
-  hipLaunchKernelGGL(permute_kernel, dim3(nblocks(a.total, 256)), dim3(256), 0, s, a);
+  int di = -1, dO = -1;
+  for (int d = 0; d < nd; ++d) {
+    if (istr[d] == 1 && di < 0) di = d;
+    if (ostr[d] == 1 && dO < 0) dO = d;
+  }
+  if (di >= 0 && dO >= 0 && di != dO && od[di] >= 8 && od[dO] >= 8 && a.total < ((int64_t)1 << 32)) {
+    PermTiled q;
+    q.a = a;
+    q.di = di;
+    q.dO = dO;
+    q.tdi = (od[di] + 31) / 32;
+    q.tdo = (od[dO] + 31) / 32;
+    q.ntile = q.tdi * q.tdo;
+    q.nrest = a.total / (od[di] * od[dO]);
+    const int64_t blocks = std::min<int64_t>(q.ntile * q.nrest, (int64_t)1 << 20);
+    hipLaunchKernelGGL(permute_tiled_kernel, dim3((unsigned)blocks), dim3(256), 0, s, q);
+    return;
+  }
+  if (a.total < ((int64_t)1 << 32))
+    hipLaunchKernelGGL(permute_kernel<true>, dim3(nblocks(a.total, 256)), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(permute_kernel<false>, dim3(nblocks(a.total, 256)), dim3(256), 0, s, a);
 }
 
 __global__ void add_diag_kernel(double2* M, const double* d, int64_t n) {
