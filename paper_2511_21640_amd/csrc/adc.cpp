@@ -668,11 +668,11 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // ---------------- doubles output: every term goes, with its coefficient,
   // into the accumulator of the antisymmetriser it needs (P(ij): A0, P(ab):
   // A1, P(ij)P(ab): A2); one pass then antisymmetrises, packs and adds D Y
-  Tensor A0 = tnew(cx, {k, o, o, v, v}), A1 = tnew(cx, {k, o, o, v, v});
-  Tensor A2 = x != 0.0 ? tnew(cx, {k, o, o, v, v}) : Tensor{};
-  // M21(1): (Tv - Tv^ij) + (To - To^ab)
-  ctr(cx, C1(), I.ovvv, "icab", true, ys, "zjc", false, C1(), A0, "zijab");
-  ctr(cx, C1(), I.ooov, "ijka", true, ys, "zkb", false, C1(), A1, "zijab");
+  Tensor A0 = tnew(cx, {k, o, o, v, v}, false), A1 = tnew(cx, {k, o, o, v, v}, false);
+  Tensor A2 = x != 0.0 ? tnew(cx, {k, o, o, v, v}, false) : Tensor{};
+  // M21(1): (Tv - Tv^ij) + (To - To^ab); these first terms initialise A0, A1
+  ctr(cx, C1(), I.ovvv, "icab", true, ys, "zjc", false, C0(), A0, "zijab");
+  ctr(cx, C1(), I.ooov, "ijka", true, ys, "zkb", false, C0(), A1, "zijab");
   if (x != 0.0) {
     // M21(2)
     Tensor Z1 = tnew(cx, {k, v, v}, false);
@@ -688,7 +688,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
     ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
     tfree(cx, Z4);
-    ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C1(), A2, "zIJAB");
+    ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C0(), A2, "zIJAB");
     ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
     // through P(ij)) and ring; the particle ladder runs packed below

@@ -593,6 +593,18 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   };
   for (char c : sa + sb) chk(c);
 
+  // GEMM epilogues give consecutive lanes consecutive columns: when C's unit
+  // stride label is a row (M) label, swap the operands so that it becomes a
+  // column label and the output writes coalesce
+  {
+    char unit = 0;
+    for (char c : sc)
+      if (vc.stride.at(c) == 1 && vc.size.at(c) > 1) unit = c;
+    if (unit && Ml.find(unit) != std::string::npos) {
+      ctr(cx, alpha, B, lb, cB, A, la, cA, beta, C, lc);
+      return;
+    }
+  }
   // K order: as in A
   const int64_t Mn = prod(va, Ml), Nn = prod(vb, Nl), Kn = prod(va, Kl), Bn = prod(vc, bat);
   if (Mn == 0 || Nn == 0 || Bn == 0) return;
@@ -651,6 +663,14 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   g.conjA = cA; g.conjB = cB;
 
   std::vector<double2*> tmps;
+  // split-bf16 mode: contractions over fewer than 32 summed elements are bound
+  // by their output traffic, not by arithmetic: run them in FP64
+  struct PrecGuard {
+    Ctx& cx;
+    int saved;
+    ~PrecGuard() { cx.prec = saved; }
+  } pg{cx, cx.prec};
+  if (cx.prec == 2 && Kn < 32) cx.prec = 0;
   // ---- split-bf16: unbatched contractions run on pre-split operand planes
   if (cx.prec == 2 && bat.empty() && Kn >= 32) {
     const int64_t Kp = (Kn + 31) / 32 * 32;
