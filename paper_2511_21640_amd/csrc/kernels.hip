@@ -524,10 +524,12 @@ void launch_split_nd(const SplitNd& p, int tiled, hipStream_t s) {
   }
 }
 
-template <int WM, int WN, int TAG>
-__global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
-  constexpr int BM = 32 * WM, BN = 32 * WN;
-  constexpr int UA = 16 * BM / 256, UB = 16 * BN / 256;   // uint4 per thread per slice
+// WR x WC waves, each computing (16 WM) x (16 WN) of the block tile
+template <int WM, int WN, int TAG, int WR = 2, int WC = 2>
+__global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16p_kernel(BfGemm p) {
+  constexpr int NT = 64 * WR * WC;
+  constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC;
+  constexpr int UA = 16 * BM / NT, UB = 16 * BN / NT;   // uint4 per thread per slice
   __shared__ __attribute__((aligned(16))) unsigned short sA[4][BM][TKB + PADB];
   __shared__ __attribute__((aligned(16))) unsigned short sB[4][BN][TKB + PADB];
   const int tid = threadIdx.x;
@@ -543,20 +545,20 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
   const int64_t sidx = blockIdx.y;
   const int64_t kbeg = sidx * p.kchunk;
   const int64_t kend = (kbeg + p.kchunk < p.Kp) ? kbeg + p.kchunk : p.Kp;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WC, wc = wave % WC;
   const int64_t planeA = p.lda * p.Kp, planeB = p.ldb * p.Kp;
   uint4 ra[UA], rb[UB];
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int r = 0; r < UA; ++r) {
-      const int e = tid + 256 * r;            // (plane, row, quarter)
+      const int e = tid + NT * r;            // (plane, row, quarter)
       const int q = e & 3, rp = e >> 2, pl = rp / BM, row = rp % BM;
       const int64_t gm = m0 + row;
       ra[r] = gm < p.M ? *(const uint4*)(p.A + pl * planeA + gm * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < UB; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       const int q = e & 3, rp = e >> 2, pl = rp / BN, row = rp % BN;
       const int64_t gn = n0 + row;
       rb[r] = gn < p.N ? *(const uint4*)(p.B + pl * planeB + gn * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
@@ -565,13 +567,13 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
   auto sstore = [&]() {
 #pragma unroll
     for (int r = 0; r < UA; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       const int q = e & 3, rp = e >> 2, pl = rp / BM, row = rp % BM;
       *(uint4*)&sA[pl][row][8 * q] = ra[r];
     }
 #pragma unroll
     for (int r = 0; r < UB; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       const int q = e & 3, rp = e >> 2, pl = rp / BN, row = rp % BN;
       *(uint4*)&sB[pl][row][8 * q] = rb[r];
     }
@@ -612,23 +614,19 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
         nih = __builtin_bit_cast(us8, u2);
         nil = __builtin_bit_cast(us8, u3);
       }
+      // the six split products of Re and of Im, issued term by term across the
+      // 2*WN independent accumulators of this row block so that consecutive
+      // MFMAs never depend on each other
+      const us8* ra[6] = {&a[0], &a[0], &a[1], &nih, &nih, &nil};
+      const int rbq[6] = {0, 1, 0, 2, 3, 2};
+      const us8* ia[6] = {&a[0], &a[0], &a[1], &a[2], &a[2], &a[3]};
+      const int ibq[6] = {2, 3, 2, 0, 1, 0};
 #pragma unroll
-      for (int j = 0; j < WN; ++j) {
-        flt4 cr = accR[i][j], ci = accI[i][j];
-        cr = mfma_bf16(a[0], b[j][0], cr);
-        cr = mfma_bf16(a[0], b[j][1], cr);
-        cr = mfma_bf16(a[1], b[j][0], cr);
-        cr = mfma_bf16(nih, b[j][2], cr);
-        cr = mfma_bf16(nih, b[j][3], cr);
-        cr = mfma_bf16(nil, b[j][2], cr);
-        ci = mfma_bf16(a[0], b[j][2], ci);
-        ci = mfma_bf16(a[0], b[j][3], ci);
-        ci = mfma_bf16(a[1], b[j][2], ci);
-        ci = mfma_bf16(a[2], b[j][0], ci);
-        ci = mfma_bf16(a[2], b[j][1], ci);
-        ci = mfma_bf16(a[3], b[j][0], ci);
-        accR[i][j] = cr;
-        accI[i][j] = ci;
+      for (int tm = 0; tm < 6; ++tm) {
+#pragma unroll
+        for (int j = 0; j < WN; ++j) accR[i][j] = mfma_bf16(*ra[tm], b[j][rbq[tm]], accR[i][j]);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) accI[i][j] = mfma_bf16(*ia[tm], b[j][ibq[tm]], accI[i][j]);
       }
     }
     __syncthreads();
@@ -666,18 +664,18 @@ __global__ __launch_bounds__(256) void zgemm_bf16p_kernel(BfGemm p) {
       }
 }
 
-template <int WM, int WN>
+template <int WM, int WN, int WR = 2, int WC = 2>
 static void launch_bf16p_tile(const BfGemm& h, hipStream_t s) {
-  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC, NT = 64 * WR * WC;
   const int64_t tiles = ((h.M + BM - 1) / BM) * ((h.N + BN - 1) / BN);
   dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
-  if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 1>), grid, dim3(256), 0, s, h);
-  else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 2>), grid, dim3(256), 0, s, h);
-  else hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 0>), grid, dim3(256), 0, s, h);
+  if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 1, WR, WC>), grid, dim3(NT), 0, s, h);
+  else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 2, WR, WC>), grid, dim3(NT), 0, s, h);
+  else hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 0, WR, WC>), grid, dim3(NT), 0, s, h);
 }
 
-// tile: 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128 (rows x cols of C);
-// negative = heuristic
+// tile: 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128 (rows x cols of C,
+// four waves), 4 = 128x128 and 5 = 128x64 with eight waves; negative = heuristic
 void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
   BfGemm h = g;
@@ -693,6 +691,8 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
     case 1: launch_bf16p_tile<4, 4>(h, s); break;
     case 2: launch_bf16p_tile<4, 2>(h, s); break;
     case 3: launch_bf16p_tile<2, 4>(h, s); break;
+    case 4: launch_bf16p_tile<4, 2, 2, 4>(h, s); break;  // 128 x 128, 8 waves
+    case 5: launch_bf16p_tile<2, 2, 4, 2>(h, s); break;  // 128 x 64, 8 waves
     default: launch_bf16p_tile<2, 2>(h, s); break;
   }
 }
