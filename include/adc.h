@@ -89,10 +89,11 @@ typedef struct adc_problem {
  *   refine_fp64   mixed precision only: after convergence, continue in FP64
  *                 until the FP64 residual meets conv_tol [1]
  *   stream        hipStream_t to enqueue on; NULL = a library-owned stream
- *   mem_budget    bytes of device workspace: sizes the <ab||cd> batches
- *                 and the largest temporary copy a contraction may make
- *                 before it is split into pieces [0 = 4 GiB batches, 8 GiB
- *                 copies]; results do not depend on it
+ *   mem_budget    bytes of device workspace: sizes the <ab||cd> batches,
+ *                 the largest temporary copy a contraction may make before it
+ *                 is split into pieces, and how many trial vectors one pass
+ *                 of the unpacked-doubles terms takes [0 = 4 GiB batches,
+ *                 8 GiB copies, 16 GiB per pass]; results do not depend on it
  *   verbose       1 = one line per Davidson iteration on stderr
  *   n_streams     several instances: number of lanes (device streams, each
  *                 with its own workspace) the instances are spread over,

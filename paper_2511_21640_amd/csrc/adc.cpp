@@ -699,7 +699,6 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   tfree(cx, A0);
   tfree(cx, A1);
   if (A2.p) tfree(cx, A2);
-  if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, Po, k, CR(x), prec);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
   for (Tensor* p : {&ys, &Ya, &s1}) tfree(cx, *p);
   cx.prec = saved;
@@ -793,7 +792,6 @@ void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     tfree(cx, T);
   }
   rec_pack_doubles(cx, 2, s2, S, Y, dim, n1, k, o, v, I.eps, C1(), 0, I.pair_o, I.pair_v);
-  if (x != 0.0) ladder(h, I, Y, dim, n1, S, dim, n1, o, k, CR(x), prec);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
   for (Tensor* p : {&ys, &Ya, &s1, &s2}) tfree(cx, *p);
   cx.prec = saved;
@@ -995,11 +993,31 @@ void heevj(int n, std::vector<zc>& A, std::vector<double>& w, std::vector<zc>& V
 // ============================================================================
 // Davidson on device vectors
 // ============================================================================
+// The terms other than the particle-particle ladder work on unpacked doubles
+// ([k][o][o][v][v] for EE): their workspace grows with the number of trial
+// vectors, so they take the vectors in groups that fit the workspace budget.
+// The ladder, whose <ab||cd> assembly does not depend on the vectors, then
+// runs once over all of them (it adds into the packed output).
 void sigma_dispatch(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
   if (k <= 0) return;
-  if (I.kind == ADC_EE) ee_sigma(h, I, Y, S, k, prec);
-  else if (I.kind == ADC_IP) ip_sigma(h, I, Y, S, k, prec);
-  else ea_sigma(h, I, Y, S, k, prec);
+  const int64_t o = I.o, v = I.v;
+  const int64_t unp = I.kind == ADC_EE ? o * o * v * v : (I.kind == ADC_IP ? o * o * v : o * v * v);
+  const size_t ws = h->opt.mem_budget ? h->opt.mem_budget : (size_t)16 << 30;
+  // unpacked vectors, three accumulators, operand planes and temporaries
+  const int64_t per_row = std::max<int64_t>(1, 6 * unp * (int64_t)sizeof(double2));
+  const int rows = (int)std::max<int64_t>(1, std::min<int64_t>(k, (int64_t)ws / per_row));
+  for (int r0 = 0; r0 < k; r0 += rows) {
+    const int nr = std::min(rows, k - r0);
+    const double2* Yr = Y + (int64_t)r0 * I.dim;
+    double2* Sr = S + (int64_t)r0 * I.dim;
+    if (I.kind == ADC_EE) ee_sigma(h, I, Yr, Sr, nr, prec);
+    else if (I.kind == ADC_IP) ip_sigma(h, I, Yr, Sr, nr, prec);
+    else ea_sigma(h, I, Yr, Sr, nr, prec);
+  }
+  if (I.x != 0.0 && I.kind != ADC_IP) {
+    const int64_t nrow = I.kind == ADC_EE ? I.Po : I.o;
+    ladder(h, I, Y, I.dim, I.n1, S, I.dim, I.n1, nrow, k, CR(I.x), prec);
+  }
 }
 
 // Sigma build of a small instance replayed from a captured hipGraph: the
@@ -1288,7 +1306,10 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
     for (int r = 0; r < k; ++r) {
       rn[r] = std::sqrt(std::max(0.0, r2[r]));
-      conv[r] = (rn[r] <= tol_now && std::fabs(w[r] - w_old[r]) <= (refined_phase ? 1e-10 : 1e-7)) ? 1 : 0;
+      // |d omega| between iterations: 1e-10 Eh, or tol^2 when that is looser
+      // (the eigenvalue error of a residual r is at most |r|^2 / gap)
+      const double dw_tol = refined_phase ? std::max(1e-10, tol * tol) : 1e-7;
+      conv[r] = (rn[r] <= tol_now && std::fabs(w[r] - w_old[r]) <= dw_tol) ? 1 : 0;
       all = all && conv[r];
     }
     t_sub += ms_since(t_it);
