@@ -22,6 +22,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sigma builds/s + MFMA TFLOP/s, mixed vs FP64 GPU at ≤1e-6 Eh eigval error"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
+# HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain 1 GiB copy) of one
+# split-bf16 ladder term at this workload, from the counter runs summarised in
+# profiles/ladder_c2_split_bf16.md; None for the other precisions (not measured)
+LADDER_TRAFFIC_BYTES = {"split_bf16": 17.061e9 + 3.398e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}
 
 
@@ -143,7 +147,8 @@ def run_c4(args):
             P = make_problem(kind, o, v, N, seed, n_roots=k, x=0.5)
             probs.append(dict(kind=kind, o=o, v=v, eps=P.eps, L=P.L, n_roots=k, x=0.5))
         t0 = time.perf_counter()
-        B = adc.Batch(probs, precision=args.precision, conv_tol=3e-5, n_streams=4, graphs=True, autotune=True)
+        B = adc.Batch(probs, precision=args.precision, conv_tol=3e-5, n_streams=4, graphs=True, autotune=True,
+                      verbose=args.verbose)
         torch.cuda.synchronize()
         t_init += time.perf_counter() - t0
         del probs
@@ -197,6 +202,7 @@ def main():
     ap.add_argument("--c4", type=int, default=0,
                     help="instead: batched solve of the first N instances of the 64-instance draw")
     ap.add_argument("--c4-budget-gb", type=float, default=200.0)
+    ap.add_argument("--verbose", action="store_true", help="one line per Davidson iteration on stderr")
     args = ap.parse_args()
     if args.c4:
         run_c4(args)
@@ -273,7 +279,8 @@ def main():
         "init_wall_s": init_wall,
         "roofline": {"bound": "mfma", "kernel": "ladder term (assembly GEMM + pack + contraction GEMM)",
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "ms_per_launch": ms_lad, "flop_per_launch": lad_flops,
+                     "traffic": LADDER_TRAFFIC_BYTES.get(args.precision), "traffic_unit": "bytes per launch",
+                     "ms_per_launch": ms_lad, "flop_per_launch": lad_flops,
                      "effective_peak": peak / 3.0 if args.precision == "split_bf16" else peak,
                      "frac_effective": achieved / (peak / 3.0 if args.precision == "split_bf16" else peak)},
     }
