@@ -167,16 +167,15 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   const int64_t Pv = I.Pv, N = I.N;
   if (Pv == 0 || nrow == 0 || k == 0) return;
   const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
-  // W block: nb*v rows x (v-b0)*v cols; V block: npairs x Pv
-  const int64_t per_a = (int64_t)v * v * v + (int64_t)v * Pv;
-  int nb = (int)std::max<int64_t>(1, (int64_t)(budget / 2 / sizeof(double2)) / std::max<int64_t>(1, per_a));
+  // W block: nb*v rows x (v-b0)*v cols, at most the workspace budget
+  const int64_t per_a = (int64_t)v * v * v;
+  int nb = (int)std::max<int64_t>(1, (int64_t)(budget / sizeof(double2)) / std::max<int64_t>(1, per_a));
   // a block of nb values of a assembles columns b > a0 for every a in it, so
   // the triangle b <= a inside the block (a fraction ~nb/v of the work) is
   // wasted: keep blocks near v/8 when the GEMMs stay large enough
   nb = std::min(nb, std::max(16, (v + 7) / 8));
   nb = std::min(nb, v - 1);
   double2* Wbuf = cx.pool.get((int64_t)nb * v * v * v);
-  double2* Vbuf = cx.pool.get((int64_t)nb * v * Pv);
   // the k vectors' rows are stacked into one [k*nrow][Pv] operand (M = k*nrow)
   const int64_t R = (int64_t)k * nrow;
   double2* Yc = cx.pool.get(R * Pv);
@@ -185,72 +184,96 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     int64_t od[2] = {k, nrow * Pv}, is[2] = {ldY, 1}, os[2] = {nrow * Pv, 1};
     launch_permute(2, od, is, os, Y + offY, Yc, C1(), C0(), 0, cx.stream);
   }
-  if (prec == ADC_SPLIT_BF16) {
+  // packed <ab||cd> rows of several a-blocks are collected (up to a quarter of
+  // the workspace) and contracted with the trial vectors in one GEMM, so that
+  // the contraction runs on large N even where the a-blocks are small
+  const bool bf = prec == ADC_SPLIT_BF16;
+  const int64_t Kv = pad32(Pv);
+  const int64_t row_bytes = bf ? Kv * 8 : Pv * (int64_t)sizeof(double2);
+  const int64_t max_np = (int64_t)nb * (v - 1);
+  const int64_t grp = std::min<int64_t>(Pv, std::max<int64_t>(max_np, (int64_t)(budget / 4) / row_bytes));
+  unsigned short* Yp = nullptr;
+  unsigned short* Vp = nullptr;
+  double2* Vbuf = nullptr;
+  if (bf) {
     ensure_planes(h, I);
-    const int64_t Kv = pad32(Pv);
-    unsigned short* Yp = planes_alloc(cx, R, Kv);
-    unsigned short* Vp = planes_alloc(cx, (int64_t)nb * v, Kv);
+    Yp = planes_alloc(cx, R, Kv);
+    Vp = planes_alloc(cx, grp, Kv);
     launch_split_planes(Yc, R, Pv, Pv, 1, 0, Yp, Kv, cx.stream);
-    for (int a0 = 0; a0 < v - 1; a0 += nb) {
-      const int a1 = std::min(v - 1, a0 + nb);
-      const int b0 = a0 + 1;
-      BfGemm g{};
-      g.M = (int64_t)(a1 - a0) * v; g.N = (int64_t)(v - b0) * v; g.Kp = I.Kq;
-      g.A = I.Lq + (int64_t)a0 * v * I.Kq; g.lda = (int64_t)v * v;
-      g.B = I.Lq + (int64_t)b0 * v * I.Kq; g.ldb = (int64_t)v * v;
-      g.C = Wbuf; g.scm = g.N; g.scn = 1;
-      g.alpha = C1(); g.beta = C0(); g.tag = 1;
-      gemm_bf16p(cx, g);
-      const int64_t pbase = (int64_t)a0 * (2 * v - a0 - 1) / 2;
-      const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
-      const int64_t np = pend - pbase;
-      launch_ladder_pack_planes(Wbuf, g.N, a0, b0, v, Vp, pbase, np, I.pair_v, Kv, cx.stream);
+  } else {
+    Vbuf = cx.pool.get(grp * Pv);
+  }
+  int64_t gbase = 0, gfill = 0;  // first pair of the collected rows, their number
+  auto contract = [&]() {
+    if (gfill == 0) return;
+    if (bf) {
       BfGemm c{};
-      c.M = R; c.N = np; c.Kp = Kv;
+      c.M = R; c.N = gfill; c.Kp = Kv;
       c.A = Yp; c.lda = R;
-      c.B = Vp; c.ldb = np;
-      c.C = Sc + pbase; c.scm = Pv; c.scn = 1;
+      c.B = Vp; c.ldb = grp;
+      c.C = Sc + gbase; c.scm = Pv; c.scn = 1;
       c.alpha = C1(); c.beta = C0(); c.tag = 2;
       gemm_bf16p(cx, c);
+    } else {
+      // Sc[r][gbase + q] = sum_cd Yc[r][cd] V[q][cd]
+      GemmDesc c{};
+      c.M = R; c.N = gfill; c.K = Pv; c.batch = 1;
+      c.A = Yc; c.sam = Pv; c.sak = 1; c.sab = 0;
+      c.B = Vbuf; c.sbk = 1; c.sbn = Pv; c.sbb = 0;
+      c.C = Sc + gbase; c.scm = Pv; c.scn = 1; c.scb = 0;
+      c.alpha = C1(); c.beta = C0();
+      c.tag = 2;
+      const int sp = cx.prec;
+      cx.prec = prec;
+      gemm(cx, c);
+      cx.prec = sp;
     }
-    cx.pool.put((double2*)Yp);
-    cx.pool.put((double2*)Vp);
-  } else
+    gbase += gfill;
+    gfill = 0;
+  };
   for (int a0 = 0; a0 < v - 1; a0 += nb) {
     const int a1 = std::min(v - 1, a0 + nb);
     const int b0 = a0 + 1;
-    // W[(a-a0)*v + c][(b-b0)*v + d] = sum_Q L_ac L_bd
-    GemmDesc g{};
-    g.M = (int64_t)(a1 - a0) * v;
-    g.N = (int64_t)(v - b0) * v;
-    g.K = N;
-    g.batch = 1;
-    g.A = I.Lvv.p + (int64_t)a0 * v; g.sam = 1; g.sak = (int64_t)v * v; g.sab = 0;
-    g.B = I.Lvv.p + (int64_t)b0 * v; g.sbn = 1; g.sbk = (int64_t)v * v; g.sbb = 0;
-    g.C = Wbuf; g.scm = g.N; g.scn = 1; g.scb = 0;
-    g.alpha = C1(); g.beta = C0();
-    g.tag = 1;
-    { const int sp = cx.prec; cx.prec = prec; gemm(cx, g); cx.prec = sp; }
     const int64_t pbase = (int64_t)a0 * (2 * v - a0 - 1) / 2;
     const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
     const int64_t np = pend - pbase;
-    launch_ladder_pack(Wbuf, g.N, a0, b0, v, Vbuf, pbase, np, I.pair_v, cx.stream);
-    // Sc[r][pbase + q] = sum_cd Yc[r][cd] V[q][cd]
-    GemmDesc c{};
-    c.M = R; c.N = np; c.K = Pv; c.batch = 1;
-    c.A = Yc; c.sam = Pv; c.sak = 1; c.sab = 0;
-    c.B = Vbuf; c.sbk = 1; c.sbn = Pv; c.sbb = 0;
-    c.C = Sc + pbase; c.scm = Pv; c.scn = 1; c.scb = 0;
-    c.alpha = C1(); c.beta = C0();
-    c.tag = 2;
-    { const int sp = cx.prec; cx.prec = prec; gemm(cx, c); cx.prec = sp; }
+    if (gfill + np > grp) contract();
+    // W[(a-a0)*v + c][(b-b0)*v + d] = sum_Q L_ac L_bd
+    const int64_t Mw = (int64_t)(a1 - a0) * v, Nw = (int64_t)(v - b0) * v;
+    if (bf) {
+      BfGemm g{};
+      g.M = Mw; g.N = Nw; g.Kp = I.Kq;
+      g.A = I.Lq + (int64_t)a0 * v * I.Kq; g.lda = (int64_t)v * v;
+      g.B = I.Lq + (int64_t)b0 * v * I.Kq; g.ldb = (int64_t)v * v;
+      g.C = Wbuf; g.scm = Nw; g.scn = 1;
+      g.alpha = C1(); g.beta = C0(); g.tag = 1;
+      gemm_bf16p(cx, g);
+      launch_ladder_pack_planes(Wbuf, Nw, a0, b0, v, Vp, grp, gfill, pbase, np, I.pair_v, Kv, cx.stream);
+    } else {
+      GemmDesc g{};
+      g.M = Mw; g.N = Nw; g.K = N; g.batch = 1;
+      g.A = I.Lvv.p + (int64_t)a0 * v; g.sam = 1; g.sak = (int64_t)v * v; g.sab = 0;
+      g.B = I.Lvv.p + (int64_t)b0 * v; g.sbn = 1; g.sbk = (int64_t)v * v; g.sbb = 0;
+      g.C = Wbuf; g.scm = Nw; g.scn = 1; g.scb = 0;
+      g.alpha = C1(); g.beta = C0();
+      g.tag = 1;
+      const int sp = cx.prec;
+      cx.prec = prec;
+      gemm(cx, g);
+      cx.prec = sp;
+      launch_ladder_pack(Wbuf, Nw, a0, b0, v, Vbuf + gfill * Pv, pbase, np, I.pair_v, cx.stream);
+    }
+    gfill += np;
   }
+  contract();
+  if (Yp) cx.pool.put((double2*)Yp);
+  if (Vp) cx.pool.put((double2*)Vp);
+  if (Vbuf) cx.pool.put(Vbuf);
   {
     int64_t od[2] = {k, nrow * Pv}, is[2] = {nrow * Pv, 1}, os[2] = {ldS, 1};
     launch_permute(2, od, is, os, Sc, S + offS, alpha, C1(), 0, cx.stream);
   }
   cx.pool.put(Wbuf);
-  cx.pool.put(Vbuf);
   cx.pool.put(Yc);
   cx.pool.put(Sc);
 }

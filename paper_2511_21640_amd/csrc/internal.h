@@ -85,8 +85,8 @@ struct SplitNd {
 // tiled = 1 stages 64 x 32 blocks through LDS so that reads run along the
 // rows (for sources whose unit stride is a row digit)
 void launch_split_nd(const SplitNd& p, int tiled, hipStream_t s);
-void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
-                               int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s);
+void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V, int64_t ldv,
+                               int64_t r0, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s);
 
 // ---------------------------------------------------------------- permute
 // out[sum_d idx_d * ostr[d]] = alpha * op(in[sum_d idx_d * istr[d]]) + beta * out[...]

@@ -725,14 +725,16 @@ void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s) {
   hipLaunchKernelGGL(splitk_reduce_bf_kernel, dim3(nblocks(g.M * g.N, 256)), dim3(256), 0, s, g);
 }
 
-// packed <ab||cd> rows written directly as split planes [4][npairs][Kp]
+// packed <ab||cd> rows written directly as split planes [4][ldv][Kp], at rows
+// r0 .. r0 + npairs of each plane
 __global__ __launch_bounds__(256) void ladder_pack_planes_kernel(const double2* W, int64_t ldw, int a0, int b0, int nv,
-                                                                 unsigned short* V, int64_t pbase, int64_t npairs,
-                                                                 const int2* pv, int64_t Pv, int64_t Kp) {
+                                                                 unsigned short* V, int64_t ldv, int64_t r0,
+                                                                 int64_t pbase, const int2* pv, int64_t Pv,
+                                                                 int64_t Kp) {
   const int64_t pr = blockIdx.y;
   const int2 ab = pv[pbase + pr];
   const int64_t ra = (int64_t)(ab.x - a0) * nv, cb = (int64_t)(ab.y - b0) * nv;
-  const int64_t plane = npairs * Kp;
+  const int64_t plane = ldv * Kp;
   for (int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < Kp; pc += (int64_t)gridDim.x * blockDim.x) {
     unsigned short h0 = 0, l0 = 0, h1 = 0, l1 = 0;
     if (pc < Pv) {
@@ -742,21 +744,21 @@ __global__ __launch_bounds__(256) void ladder_pack_planes_kernel(const double2* 
       split_bf16((float)(w1.x - w2.x), h0, l0);
       split_bf16((float)(w1.y - w2.y), h1, l1);
     }
-    const int64_t o = pr * Kp + pc;
+    const int64_t o = (r0 + pr) * Kp + pc;
     V[o] = h0;
     V[plane + o] = l0;
     V[2 * plane + o] = h1;
     V[3 * plane + o] = l1;
   }
 }
-void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
-                               int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s) {
+void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V, int64_t ldv,
+                               int64_t r0, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s) {
   const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
   if (npairs <= 0 || Pv <= 0) return;
   unsigned gx = (unsigned)((Kp + 255) / 256);
   if (gx > 64) gx = 64;
   hipLaunchKernelGGL(ladder_pack_planes_kernel, dim3(gx, (unsigned)npairs), dim3(256), 0, s, W, ldw, a0, b0, nv, V,
-                     pbase, npairs, pv, Pv, Kp);
+                     ldv, r0, pbase, pv, Pv, Kp);
 }
 
 template <typename T, int WM, int WN>
