@@ -98,6 +98,8 @@ def c4_device_gb(kind, o, v, N, k):
     res = N * n * n + 6 * o * o * v * v + o ** 4 + 2 * o ** 3 * v + 2 * n1 * n1
     if kind != "IP":
         res += 2 * o * v ** 3
+    if kind == "EE":
+        res += o * v * v * (v + o) + o * o * v * (2 * o + v)
     tr = (2 * 6 * k + 3 * k) * dim + min(k * 6 * unp, (16 << 30) // 16) + (4 << 30) // 16
     return res * 16 / 1e9, tr * 16 / 1e9
 

@@ -56,6 +56,11 @@ struct Inst {
   Tensor W;               // EE: [I][J][i][B] = sum_cd t*_IJcd <cd||iB>
   Tensor W5;              // EE: [J][A][a][B] = sum_kc conj(t[J,k,A,c]) conj(<kB||ac>)
   Tensor W6;              // EE: [I][B][J][i] = sum_kc t*_IkBc conj(<ik||Jc>)
+  // EE: the trial-independent factors of the doubles terms that share their
+  // output roles, concatenated along the summed index (one GEMM each):
+  //   E0[i][a][b][c | k] = conj(<ic||ab>) | t_ikab                (P(ij) terms)
+  //   E1[I][J][A][k | c | i] = conj(<IJ||kA>) | t_IJAc | conj(W_IJiA)  (P(ab) terms)
+  Tensor E0, E1;
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
@@ -604,6 +609,22 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   ctr(cx, C1(), t, "JkAc", true, I.ovvv, "kBac", true, C0(), I.W5, "JAaB");
   I.W6 = tnew(cx, {o, v, o, o}, false);
   ctr(cx, C1(), t, "IkBc", true, I.ooov, "ikJc", true, C0(), I.W6, "IBJi");
+  I.E0 = tnew(cx, {o, v, v, v + o}, false);
+  {
+    Tensor e = tslice(I.E0, 3, 0, v);
+    perm(cx, C1(), I.ovvv, "icab", true, C0(), e, "iabc");
+    Tensor f = tslice(I.E0, 3, v, v + o);
+    perm(cx, C1(), t, "ikab", false, C0(), f, "iabk");
+  }
+  I.E1 = tnew(cx, {o, o, v, 2 * o + v}, false);
+  {
+    Tensor e = tslice(I.E1, 3, 0, o);
+    perm(cx, C1(), I.ooov, "ijka", true, C0(), e, "ijak");
+    Tensor f = tslice(I.E1, 3, o, o + v);
+    perm(cx, C1(), t, "IJAc", false, C0(), f, "IJAc");
+    Tensor g = tslice(I.E1, 3, o + v, 2 * o + v);
+    perm(cx, C1(), I.W, "IJiA", true, C0(), g, "IJAi");
+  }
 }
 
 // ============================================================================
@@ -693,20 +714,38 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // A1, P(ij)P(ab): A2); one pass then antisymmetrises, packs and adds D Y
   Tensor A0 = tnew(cx, {k, o, o, v, v}, false), A1 = tnew(cx, {k, o, o, v, v}, false);
   Tensor A2 = x != 0.0 ? tnew(cx, {k, o, o, v, v}, false) : Tensor{};
-  // M21(1): (Tv - Tv^ij) + (To - To^ab); these first terms initialise A0, A1
-  ctr(cx, C1(), I.ovvv, "icab", true, ys, "zjc", false, C0(), A0, "zijab");
-  ctr(cx, C1(), I.ooov, "ijka", true, ys, "zkb", false, C0(), A1, "zijab");
+  // M21(1) and the M21(2) terms with the same output roles, one GEMM per
+  // accumulator over the concatenated summed index (the factors E0, E1 are
+  // built once; x goes on the trial-vector side):
+  //   A0 = sum_c conj(<ic||ab>) y_jc + x sum_k t_ikab Z2_kj,  Z2_kj = sum_ia <ik||ja> y_ia
+  //   A1 = sum_k conj(<ij||ka>) y_kb + x sum_c t_ijac Z1_bc + x/2 sum_i conj(W_IJiA) y_iB,
+  //        Z1_bc = sum_ia <ib||ac> y_ia; the last term is -x/2 conj(W_IJiB) y_iA
+  //        relabelled a <-> b, which P(ab) leaves unchanged up to the sign taken here
+  {
+    // at x = 0 the x parts of B0, B1 stay zero
+    Tensor B0 = tnew(cx, {k, o, v + o}, x == 0.0);
+    Tensor B1 = tnew(cx, {k, v, 2 * o + v}, x == 0.0);
+    Tensor b0c = tslice(B0, 2, 0, v), b0k = tslice(B0, 2, v, v + o);
+    Tensor b1k = tslice(B1, 2, 0, o), b1c = tslice(B1, 2, o, o + v), b1i = tslice(B1, 2, o + v, 2 * o + v);
+    perm(cx, C1(), ys, "zjc", false, C0(), b0c, "zjc");
+    perm(cx, C1(), ys, "zkb", false, C0(), b1k, "zbk");
+    if (x != 0.0) {
+      Tensor Z2 = tnew(cx, {k, o, o}, false);
+      ctr(cx, C1(), I.ooov, "ikJa", false, ys, "zia", false, C0(), Z2, "zkJ");
+      perm(cx, CR(x), Z2, "zkJ", false, C0(), b0k, "zJk");
+      tfree(cx, Z2);
+      Tensor Z1 = tnew(cx, {k, v, v}, false);
+      ctr(cx, C1(), I.ovvv, "iBac", false, ys, "zia", false, C0(), Z1, "zBc");
+      perm(cx, CR(x), Z1, "zBc", false, C0(), b1c, "zBc");
+      tfree(cx, Z1);
+      perm(cx, CR(0.5 * x), ys, "ziB", false, C0(), b1i, "zBi");
+    }
+    ctr(cx, C1(), I.E0, "iabq", false, B0, "zjq", false, C0(), A0, "zijab");
+    ctr(cx, C1(), I.E1, "IJAq", false, B1, "zBq", false, C0(), A1, "zIJAB");
+    tfree(cx, B0);
+    tfree(cx, B1);
+  }
   if (x != 0.0) {
-    // M21(2)
-    Tensor Z1 = tnew(cx, {k, v, v}, false);
-    ctr(cx, C1(), I.ovvv, "iBac", false, ys, "zia", false, C0(), Z1, "zBc");
-    ctr(cx, CR(x), t, "IJAc", false, Z1, "zBc", false, C1(), A1, "zIJAB");
-    ctr(cx, CR(-0.5 * x), I.W, "IJiB", true, ys, "ziA", false, C1(), A1, "zIJAB");
-    tfree(cx, Z1);
-    Tensor Z2 = tnew(cx, {k, o, o}, false);
-    ctr(cx, C1(), I.ooov, "ikJa", false, ys, "zia", false, C0(), Z2, "zkJ");
-    ctr(cx, CR(x), t, "IkAB", false, Z2, "zkJ", false, C1(), A0, "zIJAB");
-    tfree(cx, Z2);
     Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
     ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
     ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
@@ -1496,7 +1535,7 @@ void ladder_backward(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY) 
 
 void inst_release_derived(Ctx& cx, Inst& J) {
   for (Tensor* t : {&J.oooo, &J.ooov, &J.oovv, &J.ovov, &J.ovvv, &J.ring, &J.t1, &J.M11x, &J.M11b, &J.W, &J.W5,
-                    &J.W6})
+                    &J.W6, &J.E0, &J.E1})
     if (t->p) tfree(cx, *t);
 }
 
