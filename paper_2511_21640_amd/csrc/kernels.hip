@@ -418,8 +418,6 @@ static void launch_bf16x3(const GemmDesc& g, hipStream_t s) {
   else hipLaunchKernelGGL(zgemm_bf16x3_kernel<0>, grid, dim3(256), 0, s, g);
 }
 
-static double pad_waste(int64_t n, int64_t t) { return (double)(((n + t - 1) / t) * t - n) / (double)n; }
-
 // ---------------------------------------------------------------------------
 // Split-bf16 GEMM on pre-split operands.  A and B are given as four planes
 // (re hi, re lo, im hi, im lo) of bf16, [plane][rows][Kp] with K contiguous
@@ -682,10 +680,14 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (h.nsplit < 1 || h.kchunk <= 0) { h.nsplit = 1; h.kchunk = h.Kp; }
   int tile = h.tile;
   if (tile < 0) {
-    // 128x64 (two waves per SIMD, 4x2 MFMA blocks per wave) when it fills the
-    // chip without much padding, else 64x64
-    const int64_t mid = ((h.M + 127) / 128) * ((h.N + 63) / 64) * h.nsplit;
-    tile = (mid >= 256 && pad_waste(h.M, 128) < 0.10 && pad_waste(h.N, 64) < 0.10) ? 2 : 0;
+    // 128x64 (two waves per SIMD, 4x2 MFMA blocks per wave) or 64x64: the
+    // padded work of each divided by the fraction of peak it sustains on
+    // large shapes (0.46 and 0.37), the larger tile only when its grid still
+    // fills the chip
+    const double pm2 = (double)((h.M + 127) / 128) * 128, pm0 = (double)((h.M + 63) / 64) * 64;
+    const double pn = (double)((h.N + 63) / 64) * 64;
+    const int64_t grid2 = ((h.M + 127) / 128) * ((h.N + 63) / 64) * h.nsplit;
+    tile = (grid2 >= 256 && pm2 * pn / 0.46 < pm0 * pn / 0.37) ? 2 : 0;
   }
   switch (tile) {
     case 1: launch_bf16p_tile<4, 4>(h, s); break;
