@@ -218,13 +218,13 @@ bool capturing(hipStream_t s) {
   return st != hipStreamCaptureStatusNone;
 }
 
-std::vector<TuneChoice> candidates(int64_t heur, int ntiles) {
+std::vector<TuneChoice> candidates(int64_t heur, const std::vector<int>& tiles) {
   std::vector<int64_t> ns = {heur};
   if (heur > 1) ns.push_back(1);
   if (heur > 2) ns.push_back(heur / 2);
   if (heur * 2 <= 256 && heur > 1) ns.push_back(heur * 2);
   std::vector<TuneChoice> c;
-  for (int t = 0; t < ntiles; ++t)
+  for (int t : tiles)
     for (int64_t n : ns) c.push_back({t, n});
   return c;
 }
@@ -280,7 +280,7 @@ void gemm(Ctx& cx, GemmDesc g) {
     t.C = scratch; t.scm = g.N; t.scn = 1; t.scb = g.M * g.N;
     t.beta = {0.0, 0.0};
     t.om = OutMap{};
-    ch = tune(cx, candidates(heur, cx.prec == 1 ? 3 : 2),
+    ch = tune(cx, candidates(heur, cx.prec == 1 ? std::vector<int>{0, 1, 2} : std::vector<int>{0, 1}),
               [&](const TuneChoice& c) { run_zgemm(cx, t, c.tile, c.nsplit); });
     cx.pool.put(scratch);
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -311,7 +311,7 @@ void gemm_bf16p(Ctx& cx, BfGemm g) {
     t.C = scratch; t.scm = g.N; t.scn = 1;
     t.beta = {0.0, 0.0};
     t.om = OutMap{};
-    ch = tune(cx, candidates(heur, 4), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
+    ch = tune(cx, candidates(heur, {0, 2, 6}), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
     cx.pool.put(scratch);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[key] = ch;

@@ -63,7 +63,7 @@ struct BfGemm {
   int64_t kchunk;
   int nsplit;
   double2* P;
-  int tile;  // -1 heuristic, 0 small tiles, 1 large tiles
+  int tile;  // -1 heuristic, else a tile code of launch_bf16p
   OutMap om;
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);

@@ -662,6 +662,169 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16p_kernel(BfGemm p) {
       }
 }
 
+// ---------------------------------------------------------------------------
+// The same product with the operand tiles streamed straight from global memory
+// into LDS (global_load_lds_dwordx4: each lane's 16 bytes land at the wave's
+// LDS base + 16 * lane, no VGPR staging, no ds_write) and two LDS stages, so
+// that the loads of slice s+1 fly while slice s is multiplied and one barrier
+// per slice suffices.  A plane of a tile is [rows][32 bf16] (64 bytes per
+// row, no padding); the four 16-byte quarters of row R are stored XOR-
+// permuted by swz(R), which keeps the fragment reads (16 rows x one quarter
+// per instruction) free of bank conflicts for both 32 and 64 banks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+template <int WM, int WN, int TAG, int WR, int WC>
+__global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
+  constexpr int NW = WR * WC;
+  constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC;
+  constexpr int CA = 4 * BM / 16, CB = 4 * BN / 16;   // 1 KB chunks (16 rows of one plane) per stage
+  constexpr int NCH = CA + CB, PER = NCH / NW;
+  static_assert(NCH % NW == 0, "chunks must divide among the waves");
+  constexpr int STAGE = NCH * 1024;                    // bytes
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[2 * STAGE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN, ntile = tilesM * tilesN;
+  const int64_t L = blockIdx.x;
+  int64_t tile;
+  {
+    const int64_t q = ntile / 8, r = ntile % 8, x = L % 8, slot = L / 8;
+    tile = x * q + (x < r ? x : r) + slot;
+  }
+  const int64_t m0 = (tile / tilesN) * BM, n0 = (tile % tilesN) * BN;
+  const int64_t sidx = blockIdx.y;
+  const int64_t kbeg = sidx * p.kchunk;
+  const int64_t kend = (kbeg + p.kchunk < p.Kp) ? kbeg + p.kchunk : p.Kp;
+  const int wr = wave / WC, wc = wave % WC;
+  // source of this lane's 16 bytes in each of the wave's chunks (k offset 0);
+  // rows past the matrix edge re-read the last row: they only feed output
+  // rows/columns that are never stored
+  const unsigned short* src[PER];
+  int ldsoff[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int c = wave + NW * j;
+    const int rin = lane >> 2, slot = lane & 3;
+    if (c < CA) {
+      const int pl = c / (BM / 16), R = 16 * (c % (BM / 16)) + rin;
+      const int64_t gm = (m0 + R < p.M) ? m0 + R : p.M - 1;
+      src[j] = p.A + pl * p.lda * p.Kp + gm * p.Kp + 8 * (slot ^ swz(R));
+    } else {
+      const int cb = c - CA;
+      const int pl = cb / (BN / 16), R = 16 * (cb % (BN / 16)) + rin;
+      const int64_t gn = (n0 + R < p.N) ? n0 + R : p.N - 1;
+      src[j] = p.B + pl * p.ldb * p.Kp + gn * p.Kp + 8 * (slot ^ swz(R));
+    }
+    ldsoff[j] = c * 1024;
+  }
+  auto issue = [&](int64_t k0, int stage) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(src[j] + k0),
+                                       (__attribute__((address_space(3))) void*)(smem + stage * STAGE + ldsoff[j]),
+                                       16, 0, 0);
+  };
+  flt4 accR[WM][WN], accI[WM][WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      accR[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+    }
+  const int kq = lane >> 4, r16 = lane & 15;
+  // byte offsets of this lane's fragment rows inside a plane of the A / B tile
+  int offA[WM], offB[WN];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    const int R = 16 * WM * wr + 16 * i + r16;
+    offA[i] = R * 64 + 16 * (kq ^ swz(R));
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int R = 16 * WN * wc + 16 * j + r16;
+    offB[j] = CA * 1024 + R * 64 + 16 * (kq ^ swz(R));
+  }
+  if (kbeg < kend) issue(kbeg, 0);
+  int stage = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += TKB) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (k0 + TKB < kend) issue(k0 + TKB, stage ^ 1);
+    const unsigned char* sb = smem + stage * STAGE;
+    us8 b[WN][4];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[j][q] = *(const us8*)(sb + offB[j] + q * (BN / 16) * 1024);
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      us8 a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[q] = *(const us8*)(sb + offA[i] + q * (BM / 16) * 1024);
+      us8 nih, nil;
+      {
+        uint4 u2 = __builtin_bit_cast(uint4, a[2]), u3 = __builtin_bit_cast(uint4, a[3]);
+        u2.x ^= 0x80008000u; u2.y ^= 0x80008000u; u2.z ^= 0x80008000u; u2.w ^= 0x80008000u;
+        u3.x ^= 0x80008000u; u3.y ^= 0x80008000u; u3.z ^= 0x80008000u; u3.w ^= 0x80008000u;
+        nih = __builtin_bit_cast(us8, u2);
+        nil = __builtin_bit_cast(us8, u3);
+      }
+      const us8* ra[6] = {&a[0], &a[0], &a[1], &nih, &nih, &nil};
+      const int rbq[6] = {0, 1, 0, 2, 3, 2};
+      const us8* ia[6] = {&a[0], &a[0], &a[1], &a[2], &a[2], &a[3]};
+      const int ibq[6] = {2, 3, 2, 0, 1, 0};
+#pragma unroll
+      for (int tm = 0; tm < 6; ++tm) {
+#pragma unroll
+        for (int j = 0; j < WN; ++j) accR[i][j] = mfma_bf16(*ra[tm], b[j][rbq[tm]], accR[i][j]);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) accI[i][j] = mfma_bf16(*ia[tm], b[j][ibq[tm]], accI[i][j]);
+      }
+    }
+    stage ^= 1;
+  }
+  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + 16 * WM * wr + 16 * i + 4 * (lane >> 4) + r;
+        const int64_t col = n0 + 16 * WN * wc + 16 * j + (lane & 15);
+        if (row < p.M && col < p.N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          if (p.nsplit > 1) {
+            p.P[(sidx * p.M + row) * p.N + col] = make_double2(cr, ci);
+            continue;
+          }
+          double2* dst = p.C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
+          double2 o;
+          o.x = p.alpha.re * cr - p.alpha.im * ci;
+          o.y = p.alpha.re * ci + p.alpha.im * cr;
+          if (has_beta) {
+            const double2 old = *dst;
+            o.x += p.beta.re * old.x - p.beta.im * old.y;
+            o.y += p.beta.re * old.y + p.beta.im * old.x;
+          }
+          *dst = o;
+        }
+      }
+}
+
+template <int WM, int WN, int WR, int WC>
+static void launch_bf16d_tile(const BfGemm& h, hipStream_t s) {
+  constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC, NT = 64 * WR * WC;
+  const int64_t tiles = ((h.M + BM - 1) / BM) * ((h.N + BN - 1) / BN);
+  dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
+  if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 1, WR, WC>), grid, dim3(NT), 0, s, h);
+  else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 2, WR, WC>), grid, dim3(NT), 0, s, h);
+  else hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 0, WR, WC>), grid, dim3(NT), 0, s, h);
+}
+
 template <int WM, int WN, int WR = 2, int WC = 2>
 static void launch_bf16p_tile(const BfGemm& h, hipStream_t s) {
   constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC, NT = 64 * WR * WC;
@@ -680,14 +843,20 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (h.nsplit < 1 || h.kchunk <= 0) { h.nsplit = 1; h.kchunk = h.Kp; }
   int tile = h.tile;
   if (tile < 0) {
-    // 128x64 (two waves per SIMD, 4x2 MFMA blocks per wave) or 64x64: the
-    // padded work of each divided by the fraction of peak it sustains on
-    // large shapes (0.46 and 0.37), the larger tile only when its grid still
-    // fills the chip
-    const double pm2 = (double)((h.M + 127) / 128) * 128, pm0 = (double)((h.M + 63) / 64) * 64;
-    const double pn = (double)((h.N + 63) / 64) * 64;
-    const int64_t grid2 = ((h.M + 127) / 128) * ((h.N + 63) / 64) * h.nsplit;
-    tile = (grid2 >= 256 && pm2 * pn / 0.46 < pm0 * pn / 0.37) ? 2 : 0;
+    // the candidate with the least padded work divided by the fraction of
+    // peak it sustains on large random operands, times the wave quantisation
+    // of its grid over the workgroups the chip holds at once; a tile is only
+    // taken when its grid keeps at least half of those slots busy
+    struct Cand { int tile, bm, bn; double rate; int64_t slots; };
+    const Cand cand[3] = {{6, 128, 128, 0.39, 256}, {2, 128, 64, 0.35, 512}, {0, 64, 64, 0.31, 1024}};
+    double best = 0.0;
+    for (const Cand& c : cand) {
+      const int64_t tm = (h.M + c.bm - 1) / c.bm, tn = (h.N + c.bn - 1) / c.bn, nwg = tm * tn * h.nsplit;
+      if (c.tile != 0 && 2 * nwg < c.slots) continue;
+      const double waves = (double)((nwg + c.slots - 1) / c.slots) * (double)c.slots / (double)nwg;
+      const double cost = (double)(tm * c.bm) * (double)(tn * c.bn) / c.rate * waves;
+      if (tile < 0 || cost < best) { tile = c.tile; best = cost; }
+    }
   }
   switch (tile) {
     case 1: launch_bf16p_tile<4, 4>(h, s); break;
@@ -695,6 +864,9 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
     case 3: launch_bf16p_tile<2, 4>(h, s); break;
     case 4: launch_bf16p_tile<4, 2, 2, 4>(h, s); break;  // 128 x 128, 8 waves
     case 5: launch_bf16p_tile<2, 2, 4, 2>(h, s); break;  // 128 x 64, 8 waves
+    case 6: launch_bf16d_tile<4, 2, 2, 4>(h, s); break;  // 128 x 128, 8 waves, direct LDS loads
+    case 7: launch_bf16d_tile<4, 2, 2, 2>(h, s); break;  // 128 x 64, 4 waves, direct LDS loads
+    case 8: launch_bf16d_tile<4, 4, 2, 2>(h, s); break;  // 128 x 128, 4 waves, direct LDS loads
     default: launch_bf16p_tile<2, 2>(h, s); break;
   }
 }
