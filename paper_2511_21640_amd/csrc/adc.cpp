@@ -283,6 +283,16 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   cx.pool.put(Sc);
 }
 
+// the unpacked trial vectors of one sigma build stay unchanged until the
+// build ends: their split-bf16 planes are shared by the contractions that
+// read them in the same layout
+struct SplitScope {
+  Ctx& cx;
+  int id;
+  SplitScope(Ctx& c, std::vector<std::pair<const double2*, int64_t>> bufs) : cx(c), id(split_scope_begin(c, bufs)) {}
+  ~SplitScope() { split_scope_end(cx, id); }
+};
+
 // copy rows [k][n] with row stride ld (offset off) into a contiguous tensor, or back
 void rows_in(Ctx& cx, const double2* src, int64_t ld, int64_t off, Tensor& dst, int k, int64_t n) {
   int64_t od[2] = {k, n}, is[2] = {ld, 1}, os[2] = {n, 1};
@@ -675,6 +685,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   rows_in(cx, Y, dim, 0, ys, k, n1);
   Tensor Ya = tnew(cx, {k, o, o, v, v}, false);
   launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream);
+  SplitScope scope(cx, {{Ya.p, Ya.size()}, {ys.p, ys.size()}});
   const Tensor& t = I.t1;
 
   // ---------------- singles output
@@ -694,11 +705,14 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   if (x != 0.0) {
     // M12(2), grouped with the antisymmetric Y
     Tensor rY = tnew(cx, {k, v, v}, false);
-    ctr(cx, C1(), t, "IJAc", true, Ya, "zIJAB", false, C0(), rY, "zcB");
+    // Y is antisymmetric in its virtual pair: read it as Y_IJBA = -Y_IJAB so
+    // that it shares the layout (kept virtual first) of the M12(1) term above
+    ctr(cx, CR(-1.0), t, "IJAc", true, Ya, "zIJBA", false, C0(), rY, "zcB");
     ctr(cx, CR(0.5 * x), I.ovvv, "iBac", true, rY, "zcB", false, C1(), s1, "zia");
     tfree(cx, rY);
     Tensor r2 = tnew(cx, {k, o, o}, false);
-    ctr(cx, C1(), t, "IkAB", true, Ya, "zIJAB", false, C0(), r2, "zkJ");
+    // likewise Y_JIAB = -Y_IJAB (kept occupied first)
+    ctr(cx, CR(-1.0), t, "IkAB", true, Ya, "zJIAB", false, C0(), r2, "zkJ");
     ctr(cx, CR(0.5 * x), I.ooov, "ikJa", true, r2, "zkJ", false, C1(), s1, "zia");
     tfree(cx, r2);
     ctr(cx, CR(x), I.W5, "JAaB", false, Ya, "ziJAB", false, C1(), s1, "zia");
@@ -779,6 +793,7 @@ void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   rows_in(cx, Y, dim, 0, ys, k, n1);
   Tensor Ya = tnew(cx, {k, o, o, v}, false);
   launch_unpack_doubles(1, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream);
+  SplitScope scope(cx, {{Ya.p, Ya.size()}, {ys.p, ys.size()}});
   Tensor s1 = tnew(cx, {k, o}, false);
   cx.prec = 0;
   ctr(cx, C1(), I.M11x, "PQ", false, ys, "zQ", false, C0(), s1, "zP");
@@ -823,6 +838,7 @@ void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   rows_in(cx, Y, dim, 0, ys, k, n1);
   Tensor Ya = tnew(cx, {k, o, v, v}, false);
   launch_unpack_doubles(2, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream);
+  SplitScope scope(cx, {{Ya.p, Ya.size()}, {ys.p, ys.size()}});
   Tensor s1 = tnew(cx, {k, v}, false);
   cx.prec = 0;
   ctr(cx, C1(), I.M11x, "PQ", false, ys, "zQ", false, C0(), s1, "zP");
@@ -984,6 +1000,11 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
     else ea_init(h, I, P, eps_h);
     for (Tensor* q : {&P.Lt, &P.Ht, &P.t2, &P.ts}) tfree(cx, *q);
   }
+  // the trial-independent operands are frozen from here on: their split-bf16
+  // planes are kept per layout (at most their own size in bytes) and reused
+  // by every sigma build
+  for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1})
+    if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {
     std::vector<double2> m(I.n1 * I.n1);

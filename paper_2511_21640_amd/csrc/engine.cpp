@@ -553,6 +553,99 @@ Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi) {
   return v;
 }
 
+// ------------------------------------------------------------------ split cache
+namespace {
+
+bool same_layout(const SplitNd& a, const SplitNd& b) {
+  if (a.src != b.src || a.conj != b.conj || a.rows != b.rows || a.K != b.K || a.Kp != b.Kp || a.nm != b.nm ||
+      a.nk != b.nk)
+    return false;
+  for (int q = 0; q < a.nm; ++q)
+    if (a.md[q] != b.md[q] || a.ms[q] != b.ms[q]) return false;
+  for (int q = 0; q < a.nk; ++q)
+    if (a.kd[q] != b.kd[q] || a.ks[q] != b.ks[q]) return false;
+  return true;
+}
+
+// scope of the frozen range that holds every element the split reads, or -1
+int frozen_scope(const SplitCache& c, const SplitNd& sp) {
+  int64_t hi = 0;
+  for (int q = 0; q < sp.nm; ++q) {
+    if (sp.ms[q] < 0) return -1;
+    hi += (sp.md[q] - 1) * sp.ms[q];
+  }
+  for (int q = 0; q < sp.nk; ++q) {
+    if (sp.ks[q] < 0) return -1;
+    hi += (sp.kd[q] - 1) * sp.ks[q];
+  }
+  for (const auto& r : c.frozen)
+    if (sp.src >= r.p && sp.src + hi < r.p + r.n) return r.scope;
+  return -1;
+}
+
+}  // namespace
+
+// planes of sp from the cache (splitting them into a new entry on a miss), or
+// nullptr when the source is not frozen, while recording a tape, during graph
+// capture (no entry may be created there) or when the persistent budget is spent
+static unsigned short* split_cached(Ctx& cx, SplitNd sp, int64_t bytes, bool tiled) {
+  SplitCache& c = cx.scache;
+  if (cx.tape || c.frozen.empty()) return nullptr;
+  const int scope = frozen_scope(c, sp);
+  if (scope < 0) return nullptr;
+  for (const auto& e : c.entries)
+    if (same_layout(e.key, sp)) return e.planes;
+  if (scope == 0 && c.persistent_bytes + bytes > c.limit) return nullptr;
+  if (capturing(cx.stream)) return nullptr;
+  unsigned short* dst = (unsigned short*)cx.pool.get((bytes + 15) / 16);
+  sp.dst = dst;
+  launch_split_nd(sp, tiled ? 1 : 0, cx.stream);
+  c.entries.push_back({sp, dst, bytes, scope});
+  if (scope == 0) c.persistent_bytes += bytes;
+  return dst;
+}
+
+void split_freeze(Ctx& cx, const double2* p, int64_t n, int64_t extra_bytes) {
+  if (!p || n <= 0) return;
+  cx.scache.frozen.push_back({p, n, 0});
+  cx.scache.limit += extra_bytes;
+}
+
+static void drop_scope(Ctx& cx, int scope) {
+  SplitCache& c = cx.scache;
+  std::vector<SplitCache::Entry> keep;
+  for (auto& e : c.entries) {
+    if (e.scope == scope) {
+      cx.pool.put((double2*)e.planes);
+      if (scope == 0) c.persistent_bytes -= e.bytes;
+    } else {
+      keep.push_back(e);
+    }
+  }
+  c.entries.swap(keep);
+  std::vector<SplitCache::Range> fr;
+  for (auto& r : c.frozen)
+    if (r.scope != scope) fr.push_back(r);
+  c.frozen.swap(fr);
+}
+
+void split_thaw_all(Ctx& cx) {
+  drop_scope(cx, 0);
+  cx.scache.limit = 0;
+}
+
+int split_scope_begin(Ctx& cx, const std::vector<std::pair<const double2*, int64_t>>& bufs) {
+  if (cx.tape) return -1;
+  const int scope = cx.scache.next_scope++;
+  for (auto& b : bufs)
+    if (b.first && b.second > 0) cx.scache.frozen.push_back({b.first, b.second, scope});
+  return scope;
+}
+
+void split_scope_end(Ctx& cx, int scope) {
+  if (scope > 0) drop_scope(cx, scope);
+}
+
 void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Tensor& B, const char* lb, bool cB,
          cplx beta, Tensor& C, const char* lc) {
   if (cx.tape && cx.tape->recording) {
@@ -681,12 +774,13 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
       const View& vl = A.size() >= B.size() ? va : vb;
       std::stable_sort(Ko.begin(), Ko.end(), [&](char a, char b) { return vl.stride.at(a) > vl.stride.at(b); });
     }
-    unsigned short* Aq = (unsigned short*)cx.pool.get((Mn * Kp * 4 + 7) / 8);
-    unsigned short* Bq = (unsigned short*)cx.pool.get((Nn * Kp * 4 + 7) / 8);
-    auto split = [&](const Tensor& X, const View& vx, const std::string& rl, bool conj, unsigned short* dst,
-                     int64_t rows) {
+    std::vector<double2*> planes_tmp;
+    // planes of an operand: from the split cache when the source is frozen,
+    // else split into a temporary
+    auto split = [&](const Tensor& X, const View& vx, const std::string& rl, bool conj,
+                     int64_t rows) -> unsigned short* {
+      const int64_t pbytes = rows * Kp * 8;
       SplitNd sp{};
-      sp.dst = dst;
       sp.rows = rows;
       sp.K = Kn;
       sp.Kp = Kp;
@@ -695,20 +789,28 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
           split_digits(vx, Ko, sp.nk, sp.kd, sp.ks)) {
         sp.src = X.p;
         const bool tiled = sp.ks[sp.nk - 1] != 1 && sp.ms[sp.nm - 1] == 1;
+        if (unsigned short* hit = split_cached(cx, sp, pbytes, tiled)) return hit;
+        unsigned short* dst = (unsigned short*)cx.pool.get((pbytes + 15) / 16);
+        planes_tmp.push_back((double2*)dst);
+        sp.dst = dst;
         launch_split_nd(sp, tiled ? 1 : 0, cx.stream);
-        return;
+        return dst;
       }
       // more than four digits: go through a contiguous copy
+      unsigned short* dst = (unsigned short*)cx.pool.get((pbytes + 15) / 16);
+      planes_tmp.push_back((double2*)dst);
       double2* t = cx.pool.get(X.size());
       tmps.push_back(t);
       permute_into(cx, X, vx, rl + Ko, false, t, C1(), C0());
       sp.src = t;
+      sp.dst = dst;
       sp.nm = 1; sp.md[0] = rows; sp.ms[0] = Kn;
       sp.nk = 1; sp.kd[0] = Kn; sp.ks[0] = 1;
       launch_split_nd(sp, 0, cx.stream);
+      return dst;
     };
-    split(A, va, Ml, cA, Aq, Mn);
-    split(B, vb, Nl, cB, Bq, Nn);
+    unsigned short* Aq = split(A, va, Ml, cA, Mn);
+    unsigned short* Bq = split(B, vb, Nl, cB, Nn);
     BfGemm g{};
     g.M = Mn; g.N = Nn; g.Kp = Kp;
     g.A = Aq; g.lda = Mn;
@@ -730,8 +832,7 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
       std::string tl = Ml + Nl;
       perm(cx, alpha, tt, tl.c_str(), false, beta, C, lc);
     }
-    cx.pool.put((double2*)Aq);
-    cx.pool.put((double2*)Bq);
+    for (auto* t : planes_tmp) cx.pool.put(t);
     for (auto* t : tmps) cx.pool.put(t);
     return;
   }

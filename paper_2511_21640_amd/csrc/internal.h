@@ -249,6 +249,26 @@ struct Tape {
   void add(const void* p, size_t bytes, bool rg_) { allocs.push_back({(uintptr_t)p, bytes, rg_, false, false, nullptr}); }
 };
 
+// Split-bf16 operand planes kept between contractions.  A device buffer
+// registered as frozen promises not to change while registered; the planes
+// ctr() splits from it are kept per layout (source, digit maps, conjugation,
+// K) and reused.  Scope 0 holds trial-independent tensors until they are
+// unregistered (their planes count against `limit` bytes); other scopes hold
+// the buffers of one sigma build and are dropped by split_scope_end().
+struct SplitCache {
+  struct Range { const double2* p; int64_t n; int scope; };
+  struct Entry {
+    SplitNd key;  // dst unused
+    unsigned short* planes;
+    int64_t bytes;
+    int scope;
+  };
+  std::vector<Range> frozen;
+  std::vector<Entry> entries;
+  int64_t persistent_bytes = 0, limit = 0;
+  int next_scope = 1;
+};
+
 struct Ctx {
   Tape* tape = nullptr;  // non-null while recording
   hipStream_t stream = nullptr;
@@ -256,7 +276,17 @@ struct Ctx {
   int prec = 0;   // arithmetic of ctr() calls
   bool autotune = false;  // time GEMM variants per shape class (see gemm())
   int64_t max_temp = (int64_t)1 << 29;  // largest permuted copy (complex elements) before ctr() splits
+  SplitCache scache;
 };
+
+// register a trial-independent buffer of n complex elements (scope 0); the
+// planes of frozen buffers may use up to `extra_bytes` more
+void split_freeze(Ctx& cx, const double2* p, int64_t n, int64_t extra_bytes);
+// drop every scope-0 registration and its planes
+void split_thaw_all(Ctx& cx);
+// open a scope over buffers that stay unchanged until split_scope_end
+int split_scope_begin(Ctx& cx, const std::vector<std::pair<const double2*, int64_t>>& bufs);
+void split_scope_end(Ctx& cx, int scope);
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);
