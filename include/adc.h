@@ -94,7 +94,8 @@ typedef struct adc_problem {
  *                 is split into pieces, and how many trial vectors one pass
  *                 of the unpacked-doubles terms takes [0 = 4 GiB batches,
  *                 8 GiB copies, 16 GiB per pass]; results do not depend on it
- *   verbose       1 = one line per Davidson iteration on stderr
+ *   verbose       1 = one line per Davidson iteration on stderr; 2 = also
+ *                 one line per GEMM launch (shape, tile, split, output map)
  *   n_streams     several instances: number of lanes (device streams, each
  *                 with its own workspace) the instances are spread over,
  *                 most expensive first [min(n_problems, 4)]; lane 0 is

@@ -119,7 +119,7 @@ class Handle:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1, ctypes.c_void_p(stream),
-                          mem_budget, 1 if verbose else 0, 0, 1 if graphs else 0, 1 if autotune else 0)
+                          mem_budget, int(verbose), 0, 1 if graphs else 0, 1 if autotune else 0)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(ctypes.byref(prob), 1, ctypes.byref(opts), ctypes.byref(h))
         if rc != ADC_OK:
@@ -236,7 +236,7 @@ class Batch:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         opts = AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1, ctypes.c_void_p(stream), mem_budget,
-                          1 if verbose else 0, int(n_streams), 1 if graphs else 0, 1 if autotune else 0)
+                          int(verbose), int(n_streams), 1 if graphs else 0, 1 if autotune else 0)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
         self._keep = []  # host copies are no longer needed

@@ -1775,6 +1775,7 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
     for (int l = 0; l < L; ++l) {
       Ctx& c = h->lane(l);
       c.autotune = h->opt.autotune != 0;
+      c.verbose = h->opt.verbose;
       if (h->opt.mem_budget)
         c.max_temp = std::min<int64_t>((int64_t)1 << 29, (int64_t)(h->opt.mem_budget / sizeof(double2)));
     }

@@ -143,6 +143,9 @@ int64_t heuristic_nsplit(int64_t M, int64_t N, int64_t K, int64_t batch, int64_t
 
 void run_zgemm(Ctx& cx, GemmDesc g, int tile, int64_t nsplit) {
   g.tile = tile;
+  if (cx.verbose >= 2)
+    std::fprintf(stderr, "[gemm] %s M %lld N %lld K %lld batch %lld split %lld\n", cx.prec == 1 ? "fp32" : "fp64",
+                 (long long)g.M, (long long)g.N, (long long)g.K, (long long)g.batch, (long long)nsplit);
   if (nsplit <= 1) {
     g.nsplit = 1;
     g.kchunk = g.K;
@@ -160,11 +163,22 @@ void run_zgemm(Ctx& cx, GemmDesc g, int tile, int64_t nsplit) {
   cx.pool.put(g.P);
 }
 
+void log_bf16p(const Ctx& cx, const BfGemm& g) {
+  if (cx.verbose < 2) return;
+  std::fprintf(stderr, "[gemm] bf16x3 tag %d M %lld N %lld Kp %lld split %d tile %d rows(", g.tag, (long long)g.M,
+               (long long)g.N, (long long)g.Kp, g.nsplit, g.tile < 0 ? bf16p_pick_tile(g) : g.tile);
+  for (int q = 0; q < g.om.nm; ++q) std::fprintf(stderr, " %lldx%lld", (long long)g.om.md[q], (long long)g.om.ms[q]);
+  std::fprintf(stderr, " | %lld) cols(", (long long)g.scm);
+  for (int q = 0; q < g.om.nn; ++q) std::fprintf(stderr, " %lldx%lld", (long long)g.om.nd[q], (long long)g.om.ns[q]);
+  std::fprintf(stderr, " | %lld) beta %d\n", (long long)g.scn, (g.beta.re != 0.0 || g.beta.im != 0.0) ? 1 : 0);
+}
+
 void run_bf16p(Ctx& cx, BfGemm g, int tile, int64_t nsplit) {
   g.tile = tile;
   if (nsplit <= 1) {
     g.nsplit = 1;
     g.kchunk = g.Kp;
+    log_bf16p(cx, g);
     launch_bf16p(g, cx.stream);
     return;
   }
@@ -173,6 +187,7 @@ void run_bf16p(Ctx& cx, BfGemm g, int tile, int64_t nsplit) {
   nsplit = (g.Kp + chunk - 1) / chunk;
   g.kchunk = chunk;
   g.nsplit = (int)nsplit;
+  log_bf16p(cx, g);
   g.P = cx.pool.get(nsplit * g.M * g.N);
   launch_bf16p(g, cx.stream);
   launch_splitk_reduce_bf(g, cx.stream);

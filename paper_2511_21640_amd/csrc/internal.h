@@ -67,6 +67,8 @@ struct BfGemm {
   OutMap om;
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);
+// the tile launch_bf16p takes for g.tile < 0
+int bf16p_pick_tile(const BfGemm& g);
 void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s);
 // dst planes [4][rows][Kp] from src(r, k) = src[r*srow + k*sk] (conj: negate im), zero for k >= K
 void launch_split_planes(const double2* src, int64_t rows, int64_t K, int64_t srow, int64_t sk, int conj,
@@ -275,6 +277,7 @@ struct Ctx {
   Pool pool;
   int prec = 0;   // arithmetic of ctr() calls
   bool autotune = false;  // time GEMM variants per shape class (see gemm())
+  int verbose = 0;        // >= 2: one line per GEMM launch on stderr
   int64_t max_temp = (int64_t)1 << 29;  // largest permuted copy (complex elements) before ctr() splits
   SplitCache scache;
 };

@@ -34,6 +34,63 @@ __device__ __forceinline__ int64_t omap(int64_t x, int n, const int64_t* d, cons
   return off + (int64_t)u * st[0];
 }
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+// Epilogue of a complex GEMM tile held in MFMA accumulators: register r of
+// block (i, j) of this lane is element (rows[i][r], cols[j]).  The output
+// offsets of the rows and columns are computed once; with beta != 0 the old
+// values of a block row are all loaded before any of them is stored, so that
+// the loads are in flight together; every access is one 16-byte vector.  P
+// (split-K partials of this split, row-major M x N) replaces the output when
+// given.
+template <int WM, int WN, class AccT>
+__device__ __forceinline__ void store_tile(int64_t M, int64_t N, double2* C, double2* P, const OutMap& om,
+                                           int64_t scm, int64_t scn, cplx alpha, cplx beta,
+                                           const int64_t (&rows)[WM][4], const int64_t (&cols)[WN],
+                                           const AccT (&accR)[WM][WN], const AccT (&accI)[WM][WN]) {
+  if (P) {
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (rows[i][r] < M && cols[j] < N)
+            *(d2v*)(P + rows[i][r] * N + cols[j]) = d2v{(double)accR[i][j][r], (double)accI[i][j][r]};
+    return;
+  }
+  const bool has_beta = (beta.re != 0.0 || beta.im != 0.0);
+  int64_t coff[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) coff[j] = cols[j] < N ? omap(cols[j], om.nn, om.nd, om.ns, scn) : 0;
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    int64_t roff[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) roff[r] = rows[i][r] < M ? omap(rows[i][r], om.nm, om.md, om.ms, scm) : 0;
+    d2v old[WN][4];
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        old[j][r] = d2v{0.0, 0.0};
+        if (has_beta && rows[i][r] < M && cols[j] < N) old[j][r] = *(const d2v*)(C + roff[r] + coff[j]);
+      }
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (rows[i][r] < M && cols[j] < N) {
+          const double cr = accR[i][j][r], ci = accI[i][j][r];
+          d2v o;
+          o.x = alpha.re * cr - alpha.im * ci + beta.re * old[j][r].x - beta.im * old[j][r].y;
+          o.y = alpha.re * ci + alpha.im * cr + beta.re * old[j][r].y + beta.im * old[j][r].x;
+          *(d2v*)(C + roff[r] + coff[j]) = o;
+        }
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Complex GEMM on the matrix cores.
 //
@@ -176,33 +233,17 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc p) {
       __syncthreads();
     }
   }
-  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  {
+    int64_t rows[WM][4], cols[WN];
 #pragma unroll
-  for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
+      for (int r = 0; r < 4; ++r) rows[i][r] = m0 + 32 * WM / 2 * wr + 16 * i + acc_row<T>(lane, r);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + 32 * WM / 2 * wr + 16 * i + acc_row<T>(lane, r);
-        const int64_t col = n0 + 32 * WN / 2 * wc + 16 * j + (lane & 15);
-        if (row < p.M && col < p.N) {
-          const double cr = accR[i][j][r], ci = accI[i][j][r];
-          if (p.nsplit > 1) {
-            p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
-            continue;
-          }
-          double2* dst = C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
-          double2 o;
-          o.x = p.alpha.re * cr - p.alpha.im * ci;
-          o.y = p.alpha.re * ci + p.alpha.im * cr;
-          if (has_beta) {
-            const double2 old = *dst;
-            o.x += p.beta.re * old.x - p.beta.im * old.y;
-            o.y += p.beta.re * old.y + p.beta.im * old.x;
-          }
-          *dst = o;
-        }
-      }
+    for (int j = 0; j < WN; ++j) cols[j] = n0 + 32 * WN / 2 * wc + 16 * j + (lane & 15);
+    double2* P = p.nsplit > 1 ? p.P + (sidx * p.batch + bz) * p.M * p.N : nullptr;
+    store_tile<WM, WN>(p.M, p.N, C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+  }
 }
 
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmDesc p) {
@@ -380,34 +421,18 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc p) {
       __syncthreads();
     }
   }
-  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  {
+    // v_mfma_f32_16x16x32_bf16 result: lane l, register r holds row 4(l/16) + r, column l%16
+    int64_t rows[2][4], cols[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) rows[i][r] = m0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // v_mfma_f32_16x16x32_bf16 result: lane l, register r holds row 4(l/16) + r, column l%16
-        const int64_t row = m0 + 32 * wr + 16 * i + 4 * (lane >> 4) + r;
-        const int64_t col = n0 + 32 * wc + 16 * j + (lane & 15);
-        if (row < p.M && col < p.N) {
-          const double cr = accR[i][j][r], ci = accI[i][j][r];
-          if (p.nsplit > 1) {
-            p.P[((sidx * p.batch + bz) * p.M + row) * p.N + col] = make_double2(cr, ci);
-            continue;
-          }
-          double2* dst = C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
-          double2 o;
-          o.x = p.alpha.re * cr - p.alpha.im * ci;
-          o.y = p.alpha.re * ci + p.alpha.im * cr;
-          if (has_beta) {
-            const double2 old = *dst;
-            o.x += p.beta.re * old.x - p.beta.im * old.y;
-            o.y += p.beta.re * old.y + p.beta.im * old.x;
-          }
-          *dst = o;
-        }
-      }
+    for (int j = 0; j < 2; ++j) cols[j] = n0 + 32 * wc + 16 * j + (lane & 15);
+    double2* P = p.nsplit > 1 ? p.P + (sidx * p.batch + bz) * p.M * p.N : nullptr;
+    store_tile<2, 2>(p.M, p.N, C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+  }
 }
 
 static void launch_bf16x3(const GemmDesc& g, hipStream_t s) {
@@ -633,33 +658,17 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16p_kernel(BfGemm p) {
       __syncthreads();
     }
   }
-  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  {
+    int64_t rows[WM][4], cols[WN];
 #pragma unroll
-  for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
+      for (int r = 0; r < 4; ++r) rows[i][r] = m0 + 16 * WM * wr + 16 * i + 4 * (lane >> 4) + r;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + 16 * WM * wr + 16 * i + 4 * (lane >> 4) + r;
-        const int64_t col = n0 + 16 * WN * wc + 16 * j + (lane & 15);
-        if (row < p.M && col < p.N) {
-          const double cr = accR[i][j][r], ci = accI[i][j][r];
-          if (p.nsplit > 1) {
-            p.P[(sidx * p.M + row) * p.N + col] = make_double2(cr, ci);
-            continue;
-          }
-          double2* dst = p.C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
-          double2 o;
-          o.x = p.alpha.re * cr - p.alpha.im * ci;
-          o.y = p.alpha.re * ci + p.alpha.im * cr;
-          if (has_beta) {
-            const double2 old = *dst;
-            o.x += p.beta.re * old.x - p.beta.im * old.y;
-            o.y += p.beta.re * old.y + p.beta.im * old.x;
-          }
-          *dst = o;
-        }
-      }
+    for (int j = 0; j < WN; ++j) cols[j] = n0 + 16 * WN * wc + 16 * j + (lane & 15);
+    double2* P = p.nsplit > 1 ? p.P + sidx * p.M * p.N : nullptr;
+    store_tile<WM, WN>(p.M, p.N, p.C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -786,33 +795,17 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
     }
     stage ^= 1;
   }
-  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
+  {
+    int64_t rows[WM][4], cols[WN];
 #pragma unroll
-  for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
+      for (int r = 0; r < 4; ++r) rows[i][r] = m0 + 16 * WM * wr + 16 * i + 4 * (lane >> 4) + r;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + 16 * WM * wr + 16 * i + 4 * (lane >> 4) + r;
-        const int64_t col = n0 + 16 * WN * wc + 16 * j + (lane & 15);
-        if (row < p.M && col < p.N) {
-          const double cr = accR[i][j][r], ci = accI[i][j][r];
-          if (p.nsplit > 1) {
-            p.P[(sidx * p.M + row) * p.N + col] = make_double2(cr, ci);
-            continue;
-          }
-          double2* dst = p.C + omap(row, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(col, p.om.nn, p.om.nd, p.om.ns, p.scn);
-          double2 o;
-          o.x = p.alpha.re * cr - p.alpha.im * ci;
-          o.y = p.alpha.re * ci + p.alpha.im * cr;
-          if (has_beta) {
-            const double2 old = *dst;
-            o.x += p.beta.re * old.x - p.beta.im * old.y;
-            o.y += p.beta.re * old.y + p.beta.im * old.x;
-          }
-          *dst = o;
-        }
-      }
+    for (int j = 0; j < WN; ++j) cols[j] = n0 + 16 * WN * wc + 16 * j + (lane & 15);
+    double2* P = p.nsplit > 1 ? p.P + sidx * p.M * p.N : nullptr;
+    store_tile<WM, WN>(p.M, p.N, p.C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+  }
 }
 
 template <int WM, int WN, int WR, int WC>
@@ -835,29 +828,34 @@ static void launch_bf16p_tile(const BfGemm& h, hipStream_t s) {
   else hipLaunchKernelGGL((zgemm_bf16p_kernel<WM, WN, 0, WR, WC>), grid, dim3(NT), 0, s, h);
 }
 
+int bf16p_pick_tile(const BfGemm& h) {
+  // the candidate with the least padded work divided by the fraction of
+  // peak it sustains on large random operands, times the wave quantisation
+  // of its grid over the workgroups the chip holds at once; a tile is only
+  // taken when its grid keeps at least half of those slots busy
+  struct Cand { int tile, bm, bn; double rate; int64_t slots; };
+  const Cand cand[3] = {{6, 128, 128, 0.39, 256}, {2, 128, 64, 0.35, 512}, {0, 64, 64, 0.31, 1024}};
+  const int64_t nsplit = h.nsplit < 1 ? 1 : h.nsplit;
+  int tile = 0;
+  double best = -1.0;
+  for (const Cand& c : cand) {
+    const int64_t tm = (h.M + c.bm - 1) / c.bm, tn = (h.N + c.bn - 1) / c.bn, nwg = tm * tn * nsplit;
+    if (c.tile != 0 && 2 * nwg < c.slots) continue;
+    const double waves = (double)((nwg + c.slots - 1) / c.slots) * (double)c.slots / (double)nwg;
+    const double cost = (double)(tm * c.bm) * (double)(tn * c.bn) / c.rate * waves;
+    if (best < 0.0 || cost < best) { tile = c.tile; best = cost; }
+  }
+  return tile;
+}
+
 // tile: 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128 (rows x cols of C,
-// four waves), 4 = 128x128 and 5 = 128x64 with eight waves; negative = heuristic
+// four waves), 4 = 128x128 and 5 = 128x64 with eight waves, 6-8 the direct-
+// load kernels (zgemm_bf16d_kernel); negative = bf16p_pick_tile
 void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
   BfGemm h = g;
   if (h.nsplit < 1 || h.kchunk <= 0) { h.nsplit = 1; h.kchunk = h.Kp; }
-  int tile = h.tile;
-  if (tile < 0) {
-    // the candidate with the least padded work divided by the fraction of
-    // peak it sustains on large random operands, times the wave quantisation
-    // of its grid over the workgroups the chip holds at once; a tile is only
-    // taken when its grid keeps at least half of those slots busy
-    struct Cand { int tile, bm, bn; double rate; int64_t slots; };
-    const Cand cand[3] = {{6, 128, 128, 0.39, 256}, {2, 128, 64, 0.35, 512}, {0, 64, 64, 0.31, 1024}};
-    double best = 0.0;
-    for (const Cand& c : cand) {
-      const int64_t tm = (h.M + c.bm - 1) / c.bm, tn = (h.N + c.bn - 1) / c.bn, nwg = tm * tn * h.nsplit;
-      if (c.tile != 0 && 2 * nwg < c.slots) continue;
-      const double waves = (double)((nwg + c.slots - 1) / c.slots) * (double)c.slots / (double)nwg;
-      const double cost = (double)(tm * c.bm) * (double)(tn * c.bn) / c.rate * waves;
-      if (tile < 0 || cost < best) { tile = c.tile; best = cost; }
-    }
-  }
+  const int tile = h.tile < 0 ? bf16p_pick_tile(h) : h.tile;
   switch (tile) {
     case 1: launch_bf16p_tile<4, 4>(h, s); break;
     case 2: launch_bf16p_tile<4, 2>(h, s); break;
