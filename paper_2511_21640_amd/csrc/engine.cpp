@@ -275,7 +275,7 @@ TuneChoice tune(Ctx& cx, const std::vector<TuneChoice>& cand, F&& fn) {
 
 void gemm(Ctx& cx, GemmDesc g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
-  const int64_t heur = heuristic_nsplit(g.M, g.N, g.K, g.batch, 1024);
+  const int64_t heur = heuristic_nsplit(g.M, g.N, g.K, g.batch, 128);
   const int64_t out = g.M * g.N * g.batch;
   if (!cx.autotune || cx.prec == 2 || out > ((int64_t)1 << 26)) {
     run_zgemm(cx, g, -1, heur);
@@ -304,16 +304,56 @@ void gemm(Ctx& cx, GemmDesc g) {
   run_zgemm(cx, g, ch.tile, std::min<int64_t>(ch.nsplit, std::max<int64_t>(1, g.K / 16)));
 }
 
+// Tile and split-K of a split-bf16 GEMM from a cost model: the time of the
+// matrix work (padded tile work at the rate the tile sustains, per wave of
+// workgroups the chip holds at once), of the operand planes (each row block of
+// A is read once per column tile and vice versa), and of the output (split-K
+// partials written and read back); the matrix and operand terms overlap.
+static TuneChoice bf16_choice(int64_t M, int64_t N, int64_t Kp, bool beta) {
+  struct Cand { int tile, bm, bn; double rate; int64_t slots; };
+  const Cand cand[3] = {{6, 128, 128, 0.39, 256}, {2, 128, 64, 0.35, 512}, {0, 64, 64, 0.31, 1024}};
+  const double peak = 2.5e15, bw = 4.0e12, wbw = 3.5e12;
+  TuneChoice best{0, 1};
+  double tbest = -1.0;
+  for (const Cand& c : cand) {
+    const int64_t tm = (M + c.bm - 1) / c.bm, tn = (N + c.bn - 1) / c.bn, tiles = tm * tn;
+    // split-K so that the grid fills 1..4 waves of slots, each chunk at
+    // least 8 slices of 32
+    std::vector<int64_t> splits = {1};
+    for (int64_t w = 1; w <= 4; ++w) {
+      const int64_t ns = std::min<int64_t>({(w * c.slots + tiles - 1) / tiles, Kp / 256, 256});
+      if (ns > 1) splits.push_back(ns);
+    }
+    for (int64_t ns0 : splits) {
+      const int64_t chunk = ((Kp + ns0 - 1) / ns0 + 31) / 32 * 32, ns = (Kp + chunk - 1) / chunk;
+      const int64_t nwg = tiles * ns, waves = (nwg + c.slots - 1) / c.slots;
+      if (c.tile != 0 && 2 * nwg < c.slots) continue;
+      const double t_mma = (double)waves * c.bm * c.bn * (double)chunk * 24.0 / (c.rate * peak / c.slots);
+      // an operand of a few MB stays in the L2 and is fetched once
+      const double pa = (double)M * Kp * 8.0, pb = (double)N * Kp * 8.0;
+      const double t_in = ((pa > 4e6 ? (double)tn : 1.0) * pa + (pb > 4e6 ? (double)tm : 1.0) * pb) / bw;
+      const double out = (double)M * N * 16.0;
+      const double t_out = ns > 1 ? (2.0 * ns * out + out * (beta ? 2.0 : 1.0)) / bw + 5e-6
+                                  : out * (beta ? 2.0 : 1.0) / wbw;
+      const double t = std::max(t_mma, t_in) + t_out;
+      if (tbest < 0.0 || t < tbest) { tbest = t; best = {c.tile, ns}; }
+    }
+  }
+  return best;
+}
+
 void gemm_bf16p(Ctx& cx, BfGemm g) {
   if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
-  const int64_t heur = heuristic_nsplit(g.M, g.N, g.Kp, 1, 1024);
+  const bool beta = g.beta.re != 0.0 || g.beta.im != 0.0;
+  const TuneChoice model = bf16_choice(g.M, g.N, g.Kp, beta);
+  const int64_t heur = model.nsplit;
   const int64_t out = g.M * g.N;
   if (!cx.autotune || out > ((int64_t)1 << 26)) {
-    run_bf16p(cx, g, -1, heur);
+    run_bf16p(cx, g, model.tile, model.nsplit);
     return;
   }
   const TuneKey key{1, 2, g.tag, lg2(g.M), lg2(g.N), lg2(g.Kp), 0};
-  TuneChoice ch{-1, heur};
+  TuneChoice ch = model;
   bool found = false;
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -771,14 +811,15 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   g.conjA = cA; g.conjB = cB;
 
   std::vector<double2*> tmps;
-  // split-bf16 mode: contractions over fewer than 32 summed elements are bound
-  // by their output traffic, not by arithmetic: run them in FP64
+  // split-bf16 mode: contractions over fewer than 32 summed elements with a
+  // small output run in FP64 (one launch instead of two splits and a GEMM);
+  // large ones stay on the split-bf16 kernels, whose output path is faster
   struct PrecGuard {
     Ctx& cx;
     int saved;
     ~PrecGuard() { cx.prec = saved; }
   } pg{cx, cx.prec};
-  if (cx.prec == 2 && Kn < 32) cx.prec = 0;
+  if (cx.prec == 2 && Kn < 32 && Mn * Nn * Bn <= ((int64_t)1 << 20)) cx.prec = 0;
   // ---- split-bf16: unbatched contractions run on pre-split operand planes
   if (cx.prec == 2 && bat.empty() && Kn >= 32) {
     const int64_t Kp = (Kn + 31) / 32 * 32;
