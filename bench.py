@@ -86,8 +86,8 @@ def cpu_baseline(P, k):
 def c4_device_gb(kind, o, v, N, k):
     """Rough device memory of one instance of the batched workload, GB:
     (resident, transient).  Resident: L blocks, stored integral classes,
-    amplitudes and intermediates, M11.  Transient (while its lane solves it):
-    Davidson subspace (6k vectors of V and S, three k-blocks), the sigma
+    amplitudes and intermediates, M11, the cached split-bf16 planes.
+    Transient (while its lane solves it): Davidson subspace (6k vectors of V and S, three k-blocks), the sigma
     workspace of one pass (unpacked doubles, at most 16 GiB) and the ladder
     batch (4 GiB)."""
     n = o + v
@@ -99,7 +99,14 @@ def c4_device_gb(kind, o, v, N, k):
     if kind != "IP":
         res += 2 * o * v ** 3
     if kind == "EE":
-        res += o * v * v * (v + o) + o * o * v * (2 * o + v)
+        res += o * v * v * (v + o) + o * o * v * (2 * o + v) + o * v ** 3 + o ** 3 * v
+    elif kind == "EA":
+        res += o * v ** 3
+    else:
+        res += o ** 3 * v
+    # split-bf16 planes of the frozen trial-independent operands (at most
+    # their own size in bytes)
+    res += (res - N * n * n - 2 * n1 * n1)
     tr = (2 * 6 * k + 3 * k) * dim + min(k * 6 * unp, (16 << 30) // 16) + (4 << 30) // 16
     return res * 16 / 1e9, tr * 16 / 1e9
 

@@ -61,6 +61,9 @@ struct Inst {
   //   E0[i][a][b][c | k] = conj(<ic||ab>) | t_ikab                (P(ij) terms)
   //   E1[I][J][A][k | c | i] = conj(<IJ||kA>) | t_IJAc | conj(W_IJiA)  (P(ab) terms)
   Tensor E0, E1;
+  // the singles-output terms that read the unpacked trial vectors in one
+  // layout, summed into one factor per layout (x enters them; see build_sx)
+  Tensor X1, X2;
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
@@ -476,6 +479,8 @@ void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector
 // ============================================================================
 // EE
 // ============================================================================
+void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2);
+
 void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   Ctx& cx = *I.cx;
   const int o = I.o, v = I.v, N = I.N;
@@ -635,11 +640,42 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     Tensor g = tslice(I.E1, 3, o + v, 2 * o + v);
     perm(cx, C1(), I.W, "IJiA", true, C0(), g, "IJAi");
   }
+  build_sx(cx, I, I.x, I.X1, I.X2);
 }
 
 // ============================================================================
 // IP and EA one-off work
 // ============================================================================
+// Trial-independent factors of the singles output that share the layout in
+// which they read the unpacked doubles Y (one contraction each):
+//   EE: X1_jabc = -1/2 <ja||bc> + x W5_jbac
+//       X2_jkib = -1/2 <jk||ib> - x/4 W_jkib + x W6_jbki
+//   IP: X1_IJiA = 1/2 <IJ||iA> + x/4 W_IJiA - x W6_IAJi
+//   EA: X1_IaAB = -1/2 ovvv_IaAB + x W5_IAaB
+// (the M12(1) terms and the M12(2) terms in W, W5, W6).  x enters here, so a
+// change of x needs new factors.
+void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2) {
+  const int o = I.o, v = I.v;
+  if (I.kind == ADC_EE) {
+    X1 = tnew(cx, {o, v, v, v}, false);
+    perm(cx, CR(-0.5), I.ovvv, "jabc", false, C0(), X1, "jabc");
+    perm(cx, CR(x), I.W5, "jbac", false, C1(), X1, "jabc");
+    X2 = tnew(cx, {o, o, o, v}, false);
+    perm(cx, CR(-0.5), I.ooov, "jkib", false, C0(), X2, "jkib");
+    perm(cx, CR(-0.25 * x), I.W, "jkib", false, C1(), X2, "jkib");
+    perm(cx, CR(x), I.W6, "jbki", false, C1(), X2, "jkib");
+  } else if (I.kind == ADC_IP) {
+    X1 = tnew(cx, {o, o, o, v}, false);
+    perm(cx, CR(0.5), I.ooov, "IJiA", false, C0(), X1, "IJiA");
+    perm(cx, CR(0.25 * x), I.W, "IJiA", false, C1(), X1, "IJiA");
+    perm(cx, CR(-x), I.W6, "IAJi", false, C1(), X1, "IJiA");
+  } else {
+    X1 = tnew(cx, {o, v, v, v}, false);
+    perm(cx, CR(-0.5), I.ovvv, "IaAB", false, C0(), X1, "IaAB");
+    perm(cx, CR(x), I.W5, "IAaB", false, C1(), X1, "IaAB");
+  }
+}
+
 void ip_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   Ctx& cx = *I.cx;
   const int o = I.o;
@@ -655,6 +691,7 @@ void ip_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   ctr(cx, C1(), t, "IJcd", true, I.ovvv, "iBcd", true, C0(), I.W, "IJiB");
   I.W6 = tnew(cx, {o, I.v, o, o}, false);
   ctr(cx, C1(), t, "IkBc", true, I.ooov, "ikJc", true, C0(), I.W6, "IBJi");
+  build_sx(cx, I, I.x, I.X1, I.X2);
   // the sigma build of IP needs no three-external integrals
   tfree(cx, I.ovvv);
 }
@@ -672,6 +709,7 @@ void ea_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   const Tensor& t = I.t1;
   I.W5 = tnew(cx, {o, v, v, v}, false);
   ctr(cx, C1(), t, "JkAc", true, I.ovvv, "kBac", true, C0(), I.W5, "JAaB");
+  build_sx(cx, I, I.x, I.X1, I.X2);
 }
 
 void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
@@ -699,9 +737,11 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, C1(), M, "PQ", false, ysf, "zQ", false, C0(), s1f, "zP");
     cx.prec = prec;
   }
-  // M12(1): -1/2 <ja||bc>Y_ijbc - 1/2 <jk||ib> Y_jkab
-  ctr(cx, CR(-0.5), I.ovvv, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
-  ctr(cx, CR(-0.5), I.ooov, "jkib", false, Ya, "zjkab", false, C1(), s1, "zia");
+  // M12(1) -1/2 <ja||bc> Y_ijbc - 1/2 <jk||ib> Y_jkab with the M12(2) terms
+  // x W5_JAaB Y_iJAB - x/4 W_IJiB Y_IJaB + x W6_IBJi Y_IJaB, one contraction
+  // per layout of Y through the factors X1, X2
+  ctr(cx, C1(), I.X1, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
+  ctr(cx, C1(), I.X2, "jkib", false, Ya, "zjkab", false, C1(), s1, "zia");
   if (x != 0.0) {
     // M12(2), grouped with the antisymmetric Y
     Tensor rY = tnew(cx, {k, v, v}, false);
@@ -715,13 +755,10 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, CR(-1.0), t, "IkAB", true, Ya, "zJIAB", false, C0(), r2, "zkJ");
     ctr(cx, CR(0.5 * x), I.ooov, "ikJa", true, r2, "zkJ", false, C1(), s1, "zia");
     tfree(cx, r2);
-    ctr(cx, CR(x), I.W5, "JAaB", false, Ya, "ziJAB", false, C1(), s1, "zia");
     Tensor V2 = tnew(cx, {k, o, o, o, o}, false);
     ctr(cx, C1(), t, "klAB", true, Ya, "ziJAB", false, C0(), V2, "ziJkl");
     ctr(cx, CR(-0.25 * x), I.ooov, "klJa", true, V2, "ziJkl", false, C1(), s1, "zia");
     tfree(cx, V2);
-    ctr(cx, CR(-0.25 * x), I.W, "IJiB", false, Ya, "zIJaB", false, C1(), s1, "zia");
-    ctr(cx, CR(x), I.W6, "IBJi", false, Ya, "zIJaB", false, C1(), s1, "zia");
   }
   // ---------------- doubles output: every term goes, with its coefficient,
   // into the accumulator of the antisymmetriser it needs (P(ij): A0, P(ab):
@@ -798,12 +835,9 @@ void ip_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   cx.prec = 0;
   ctr(cx, C1(), I.M11x, "PQ", false, ys, "zQ", false, C0(), s1, "zP");
   cx.prec = prec;
-  // M12(1): 1/2 <IJ||iA> Y_IJA ;  M12(2): 1/4 W_IJiA Y_IJA - W6_IAJi Y_IJA
-  ctr(cx, CR(0.5), I.ooov, "IJiA", false, Ya, "zIJA", false, C1(), s1, "zi");
-  if (x != 0.0) {
-    ctr(cx, CR(0.25 * x), I.W, "IJiA", false, Ya, "zIJA", false, C1(), s1, "zi");
-    ctr(cx, CR(-x), I.W6, "IAJi", false, Ya, "zIJA", false, C1(), s1, "zi");
-  }
+  // M12(1): 1/2 <IJ||iA> Y_IJA ;  M12(2): x/4 W_IJiA Y_IJA - x W6_IAJi Y_IJA,
+  // summed into the factor X1
+  ctr(cx, C1(), I.X1, "IJiA", false, Ya, "zIJA", false, C1(), s1, "zi");
   Tensor s2 = tnew(cx, {k, o, o, v});
   // M21(1): conj(<IJ||iA>) y_i
   ctr(cx, C1(), I.ooov, "IJiA", true, ys, "zi", false, C1(), s2, "zIJA");
@@ -843,11 +877,11 @@ void ea_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   cx.prec = 0;
   ctr(cx, C1(), I.M11x, "PQ", false, ys, "zQ", false, C0(), s1, "zP");
   cx.prec = prec;
-  // M12(1): 1/2 <aI||AB> Y_IAB,  <aI||AB> = -ovvv[I,a,A,B]
-  ctr(cx, CR(-0.5), I.ovvv, "IaAB", false, Ya, "zIAB", false, C1(), s1, "za");
+  // M12(1): 1/2 <aI||AB> Y_IAB,  <aI||AB> = -ovvv[I,a,A,B], and the M12(2)
+  // term x W5_IAaB Y_IAB, summed into the factor X1
+  ctr(cx, C1(), I.X1, "IaAB", false, Ya, "zIAB", false, C1(), s1, "za");
   if (x != 0.0) {
-    // M12(2): W5_IAaB Y_IAB + 1/4 conj(<kl||Ia>)-term
-    ctr(cx, CR(x), I.W5, "IAaB", false, Ya, "zIAB", false, C1(), s1, "za");
+    // M12(2): the 1/4 conj(<kl||Ia>)-term
     Tensor Vk = tnew(cx, {k, o, o, o}, false);
     ctr(cx, C1(), t, "klAB", true, Ya, "zIAB", false, C0(), Vk, "zIkl");
     ctr(cx, CR(-0.25 * x), I.ooov, "klIa", true, Vk, "zIkl", false, C1(), s1, "za");
@@ -1003,7 +1037,8 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   // the trial-independent operands are frozen from here on: their split-bf16
   // planes are kept per layout (at most their own size in bytes) and reused
   // by every sigma build
-  for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1})
+  for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1,
+                    &I.X1, &I.X2})
     if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {
@@ -1556,7 +1591,7 @@ void ladder_backward(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY) 
 
 void inst_release_derived(Ctx& cx, Inst& J) {
   for (Tensor* t : {&J.oooo, &J.ooov, &J.oovv, &J.ovov, &J.ovvv, &J.ring, &J.t1, &J.M11x, &J.M11b, &J.W, &J.W5,
-                    &J.W6, &J.E0, &J.E1})
+                    &J.W6, &J.E0, &J.E1, &J.X1, &J.X2})
     if (t->p) tfree(cx, *t);
 }
 
@@ -1577,17 +1612,28 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     perm(cx, C1(), I.M11b, "pq", false, C1(), Mx, "pq");
     std::swap(I.M11x, Mx);
     const double x0 = I.x;
+    // the singles-coupling factors at x + 1 (the frozen ones stay untouched)
+    Tensor X1b, X2b;
+    build_sx(cx, I, x0 + 1.0, X1b, X2b);
+    std::swap(I.X1, X1b);
+    std::swap(I.X2, X2b);
+    auto restore = [&]() {
+      I.x = x0;
+      std::swap(I.M11x, Mx);
+      std::swap(I.X1, X1b);
+      std::swap(I.X2, X2b);
+    };
     I.x = x0 + 1.0;
     try {
       sigma_dispatch(h, I, Y, S1.p, k, 0);
     } catch (...) {
-      I.x = x0;
-      std::swap(I.M11x, Mx);
+      restore();
       throw;
     }
-    I.x = x0;
-    std::swap(I.M11x, Mx);
+    restore();
     tfree(cx, Mx);
+    for (Tensor* t : {&X1b, &X2b})
+      if (t->p) tfree(cx, *t);
     perm(cx, CR(-1), S0, "zp", false, C1(), S1, "zp");
     Tensor Sb = tensor_view(const_cast<double2*>(Sbar), {1, (int64_t)k * dim}, {});
     Tensor D = tensor_view(S1.p, {(int64_t)k * dim, 1}, {});
