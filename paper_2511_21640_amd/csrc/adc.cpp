@@ -239,12 +239,41 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     gbase += gfill;
     gfill = 0;
   };
-  for (int a0 = 0; a0 < v - 1; a0 += nb) {
-    const int a1 = std::min(v - 1, a0 + nb);
+  // The packed <ab||cd> matrix is Hermitian (L^Q Hermitian: <cd||ab> =
+  // conj <ab||cd>).  When all its rows fit one group, only the part cd >= ab
+  // is assembled, which needs (ac|bd) for c, d >= a0 alone (about half of
+  // the assembly work), and the rest is mirrored on the split planes.
+  const bool half = bf && grp >= Pv;
+  for (int a0 = 0; a0 < v - 1;) {
+    int nbc = nb;
+    if (half) {
+      // blocks grow as the ranges of c, d shrink, keeping W near its size
+      const int64_t m = v - a0;
+      int64_t want = ((int64_t)nb * v * v * v) / std::max<int64_t>(1, m * m * (m - 1));
+      want = std::min<int64_t>(want, std::max<int64_t>(nb, m / 4));
+      nbc = (int)std::max<int64_t>(nb, want);
+    }
+    const int a1 = std::min(v - 1, a0 + nbc);
     const int b0 = a0 + 1;
     const int64_t pbase = (int64_t)a0 * (2 * v - a0 - 1) / 2;
     const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
     const int64_t np = pend - pbase;
+    if (half) {
+      // W[(a-a0)*m + c-a0][(b-b0)*m + d-a0] = sum_Q L_ac L_bd, c, d >= a0
+      const int64_t m = v - a0;
+      const int64_t Mw = (int64_t)(a1 - a0) * m, Nw = (int64_t)(v - b0) * m;
+      BfGemm g{};
+      g.M = Mw; g.N = Nw; g.Kp = I.Kq;
+      g.A = I.Lq + ((int64_t)a0 * v + a0) * I.Kq; g.lda = (int64_t)v * v; g.amd = m; g.ams = v;
+      g.B = I.Lq + ((int64_t)b0 * v + a0) * I.Kq; g.ldb = (int64_t)v * v; g.bmd = m; g.bms = v;
+      g.C = Wbuf; g.scm = Nw; g.scn = 1;
+      g.alpha = C1(); g.beta = C0(); g.tag = 1;
+      gemm_bf16p(cx, g);
+      launch_ladder_pack_planes_upper(Wbuf, Nw, a0, b0, v, Vp, grp, pbase, np, I.pair_v, Kv, cx.stream);
+      gfill += np;
+      a0 = a1;
+      continue;
+    }
     if (gfill + np > grp) contract();
     // W[(a-a0)*v + c][(b-b0)*v + d] = sum_Q L_ac L_bd
     const int64_t Mw = (int64_t)(a1 - a0) * v, Nw = (int64_t)(v - b0) * v;
@@ -272,7 +301,9 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
       launch_ladder_pack(Wbuf, Nw, a0, b0, v, Vbuf + gfill * Pv, pbase, np, I.pair_v, cx.stream);
     }
     gfill += np;
+    a0 = a1;
   }
+  if (half) launch_ladder_mirror_planes(Vp, grp, Pv, Kv, cx.stream);
   contract();
   if (Yp) cx.pool.put((double2*)Yp);
   if (Vp) cx.pool.put((double2*)Vp);

@@ -65,6 +65,9 @@ struct BfGemm {
   double2* P;
   int tile;  // -1 heuristic, else a tile code of launch_bf16p
   OutMap om;
+  // optional row maps of the operands: row r of A is stored at plane row
+  // (r / amd) * ams + r % amd (amd = 0: row r); likewise B with bmd, bms
+  int64_t amd = 0, ams = 0, bmd = 0, bms = 0;
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);
 // the tile launch_bf16p takes for g.tile < 0
@@ -89,6 +92,16 @@ struct SplitNd {
 void launch_split_nd(const SplitNd& p, int tiled, hipStream_t s);
 void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V, int64_t ldv,
                                int64_t r0, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s);
+// Upper half of the packed <ab||cd> rows of one a-block, as split planes:
+// W[(a-a0)*(nv-a0) + c-a0][(b-b0)*(nv-a0) + d-a0] = sum_Q L_ac L_bd holds only
+// c, d >= a0; row ab (pair index p) gets <ab||cd> for pairs cd >= p and zero
+// below (filled by launch_ladder_mirror_planes)
+void launch_ladder_pack_planes_upper(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
+                                     int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
+                                     hipStream_t s);
+// V[p][q] = conj(V[q][p]) for q < p < n on split planes [4][ldv][Kp] (the
+// packed <ab||cd> matrix is Hermitian)
+void launch_ladder_mirror_planes(unsigned short* V, int64_t ldv, int64_t n, int64_t Kp, hipStream_t s);
 
 // ---------------------------------------------------------------- permute
 // out[sum_d idx_d * ostr[d]] = alpha * op(in[sum_d idx_d * istr[d]]) + beta * out[...]

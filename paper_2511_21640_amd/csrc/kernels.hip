@@ -576,15 +576,15 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16p_kernel(BfGemm p) {
     for (int r = 0; r < UA; ++r) {
       const int e = tid + NT * r;            // (plane, row, quarter)
       const int q = e & 3, rp = e >> 2, pl = rp / BM, row = rp % BM;
-      const int64_t gm = m0 + row;
-      ra[r] = gm < p.M ? *(const uint4*)(p.A + pl * planeA + gm * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
+      const int64_t gm = m0 + row, gr = p.amd ? (gm / p.amd) * p.ams + gm % p.amd : gm;
+      ra[r] = gm < p.M ? *(const uint4*)(p.A + pl * planeA + gr * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < UB; ++r) {
       const int e = tid + NT * r;
       const int q = e & 3, rp = e >> 2, pl = rp / BN, row = rp % BN;
-      const int64_t gn = n0 + row;
-      rb[r] = gn < p.N ? *(const uint4*)(p.B + pl * planeB + gn * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
+      const int64_t gn = n0 + row, gr = p.bmd ? (gn / p.bmd) * p.bms + gn % p.bmd : gn;
+      rb[r] = gn < p.N ? *(const uint4*)(p.B + pl * planeB + gr * p.Kp + k0 + 8 * q) : make_uint4(0, 0, 0, 0);
     }
   };
   auto sstore = [&]() {
@@ -718,12 +718,14 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
     const int rin = lane >> 2, slot = lane & 3;
     if (c < CA) {
       const int pl = c / (BM / 16), R = 16 * (c % (BM / 16)) + rin;
-      const int64_t gm = (m0 + R < p.M) ? m0 + R : p.M - 1;
+      int64_t gm = (m0 + R < p.M) ? m0 + R : p.M - 1;
+      if (p.amd) gm = (gm / p.amd) * p.ams + gm % p.amd;
       src[j] = p.A + pl * p.lda * p.Kp + gm * p.Kp + 8 * (slot ^ swz(R));
     } else {
       const int cb = c - CA;
       const int pl = cb / (BN / 16), R = 16 * (cb % (BN / 16)) + rin;
-      const int64_t gn = (n0 + R < p.N) ? n0 + R : p.N - 1;
+      int64_t gn = (n0 + R < p.N) ? n0 + R : p.N - 1;
+      if (p.bmd) gn = (gn / p.bmd) * p.bms + gn % p.bmd;
       src[j] = p.B + pl * p.ldb * p.Kp + gn * p.Kp + 8 * (slot ^ swz(R));
     }
     ldsoff[j] = c * 1024;
@@ -931,6 +933,81 @@ void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, in
   if (gx > 64) gx = 64;
   hipLaunchKernelGGL(ladder_pack_planes_kernel, dim3(gx, (unsigned)npairs), dim3(256), 0, s, W, ldw, a0, b0, nv, V,
                      ldv, r0, pbase, pv, Pv, Kp);
+}
+
+__global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const double2* W, int64_t ldw, int a0, int b0,
+                                                                       int nv, unsigned short* V, int64_t ldv,
+                                                                       int64_t pbase, const int2* pv, int64_t Pv,
+                                                                       int64_t Kp) {
+  const int64_t pr = blockIdx.y, prow = pbase + pr;
+  const int2 ab = pv[prow];
+  const int64_t m = nv - a0;
+  const int64_t ra = (int64_t)(ab.x - a0) * m, cb = (int64_t)(ab.y - b0) * m;
+  const int64_t plane = ldv * Kp;
+  for (int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < Kp; pc += (int64_t)gridDim.x * blockDim.x) {
+    unsigned short h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+    if (pc >= prow && pc < Pv) {
+      const int2 cd = pv[pc];  // c >= a >= a0 and d > c
+      const double2 w1 = W[(ra + cd.x - a0) * ldw + cb + cd.y - a0];
+      const double2 w2 = W[(ra + cd.y - a0) * ldw + cb + cd.x - a0];
+      split_bf16((float)(w1.x - w2.x), h0, l0);
+      split_bf16((float)(w1.y - w2.y), h1, l1);
+    }
+    const int64_t o = prow * Kp + pc;
+    V[o] = h0;
+    V[plane + o] = l0;
+    V[2 * plane + o] = h1;
+    V[3 * plane + o] = l1;
+  }
+}
+void launch_ladder_pack_planes_upper(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
+                                     int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
+                                     hipStream_t s) {
+  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+  if (npairs <= 0 || Pv <= 0) return;
+  unsigned gx = (unsigned)((Kp + 255) / 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(ladder_pack_planes_upper_kernel, dim3(gx, (unsigned)npairs), dim3(256), 0, s, W, ldw, a0, b0, nv,
+                     V, ldv, pbase, pv, Pv, Kp);
+}
+
+// 64 x 64 tiles (tp >= tq) of the strictly lower triangle: read block (q, p)
+// of the upper part through LDS, write its conjugate transpose at (p, q)
+__global__ __launch_bounds__(256) void ladder_mirror_planes_kernel(unsigned short* V, int64_t ldv, int64_t n,
+                                                                   int64_t Kp) {
+  __shared__ unsigned short t[64][66];
+  // blockIdx.x enumerates the lower-triangle tiles (tp, tq), tq <= tp
+  const int64_t L = blockIdx.x;
+  int64_t tp = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
+  while ((tp + 1) * (tp + 2) / 2 <= L) ++tp;
+  while (tp * (tp + 1) / 2 > L) --tp;
+  const int64_t tq = L - tp * (tp + 1) / 2;
+  const int64_t p0 = tp * 64, q0 = tq * 64;
+  const int64_t plane = ldv * Kp;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int pl = 0; pl < 4; ++pl) {
+    const unsigned short flip = pl >= 2 ? 0x8000 : 0;
+    // load rows q0.. (upper part), columns p0..
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = ty + 4 * e;
+      const int64_t q = q0 + r, p = p0 + tx;
+      t[r][tx] = (q < n && p < n && q < p) ? V[pl * plane + q * Kp + p] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = ty + 4 * e;
+      const int64_t p = p0 + r, q = q0 + tx;
+      if (p < n && q < p) V[pl * plane + p * Kp + q] = t[tx][r] ^ flip;
+    }
+    __syncthreads();
+  }
+}
+void launch_ladder_mirror_planes(unsigned short* V, int64_t ldv, int64_t n, int64_t Kp, hipStream_t s) {
+  if (n <= 1) return;
+  const int64_t nt = (n + 63) / 64;
+  hipLaunchKernelGGL(ladder_mirror_planes_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, V, ldv, n, Kp);
 }
 
 template <typename T, int WM, int WN>

@@ -41,6 +41,7 @@ def test_c2_full_sigma_doubles_input():
     Y[0, n1:] = rng.standard_normal(n2) + 1j * rng.standard_normal(n2)
     S64 = h.sigma(torch.from_numpy(Y).cuda(), precision="fp64").cpu().numpy()
     S32 = h.sigma(torch.from_numpy(Y).cuda(), precision="fp32").cpu().numpy()
+    Sbf = h.sigma(torch.from_numpy(Y).cuda(), precision="split_bf16").cpu().numpy()
     ints = Ints(P.eps, P.L, P.o)
     Y2 = Y[:, n1:]
     ref1 = sigma_block(ints, "EE", "12", 1, Y2) + P.x * sigma_block(ints, "EE", "12", 2, Y2)
@@ -48,9 +49,13 @@ def test_c2_full_sigma_doubles_input():
     ref = np.concatenate([ref1, ref2], axis=1)
     e64 = np.abs(S64 - ref).max() / np.abs(ref).max()
     e32 = np.abs(S32 - ref).max() / np.abs(ref).max()
-    print("C2 rel err fp64", e64, "fp32", e32)
+    ebf = np.abs(Sbf - ref).max() / np.abs(ref).max()
+    print("C2 rel err fp64", e64, "fp32", e32, "split-bf16", ebf)
     assert e64 < 1e-12
     assert e32 < 1e-5
+    # split-bf16 (the arithmetic bench.py times): 16 mantissa bits per
+    # operand, errors of a few 2^-17 sqrt(K) relative to the largest output
+    assert 1e-12 < ebf < 5e-5
 
 
 def test_c3_ea_ladder_rows_and_hermiticity():
@@ -60,12 +65,13 @@ def test_c3_ea_ladder_rows_and_hermiticity():
     rng = np.random.default_rng(32)
     Y = torch.from_numpy(rng.standard_normal((2, h.dim)) + 1j * rng.standard_normal((2, h.dim))).cuda()
     S = h.sigma_term("ladder", Y, precision="fp64").cpu().numpy()
+    Sbf = h.sigma_term("ladder", Y, precision="split_bf16").cpu().numpy()
     Yh = Y.cpu().numpy()
     o, v = P.o, P.v
     Lvv = P.L[:, o:, o:]
     iu = np.triu_indices(v, 1)
     Pv = len(iu[0])
-    worst = 0.0
+    worst = worst_bf = 0.0
     for (i, a, b) in [(0, 0, 1), (7, 3, 250), (59, 398, 399), (31, 100, 101), (12, 5, 377), (44, 250, 251)]:
         W = np.einsum("Qc,Qd->cd", Lvv[:, a, :], Lvv[:, b, :])
         g = (W - W.T)[iu]                       # <ab||cd>, c<d
@@ -73,8 +79,10 @@ def test_c3_ea_ladder_rows_and_hermiticity():
         ref = P.x * (Yh[:, v + i * Pv: v + (i + 1) * Pv] @ g)
         got = S[:, v + i * Pv + p]
         worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
-    print("C3-EA ladder sampled rel err", worst)
+        worst_bf = max(worst_bf, np.abs(Sbf[:, v + i * Pv + p] - ref).max() / np.abs(ref).max())
+    print("C3-EA ladder sampled rel err", worst, "split-bf16", worst_bf)
     assert worst < 1e-12
+    assert worst_bf < 5e-5
     assert _herm_check(h, rng) < 1e-13
 
 
