@@ -68,6 +68,7 @@ struct BfGemm {
   // optional row maps of the operands: row r of A is stored at plane row
   // (r / amd) * ams + r % amd (amd = 0: row r); likewise B with bmd, bms
   int64_t amd = 0, ams = 0, bmd = 0, bms = 0;
+  int colmajor = 0;  // set by launch_bf16p: tiles walk down columns (N > M)
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);
 // the tile launch_bf16p takes for g.tile < 0

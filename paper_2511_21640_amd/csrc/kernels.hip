@@ -564,7 +564,10 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16p_kernel(BfGemm p) {
     const int64_t q = ntile / 8, r = ntile % 8, x = L % 8, slot = L / 8;
     tile = x * q + (x < r ? x : r) + slot;
   }
-  const int64_t m0 = (tile / tilesN) * BM, n0 = (tile % tilesN) * BN;
+  // column-major walk when B is the larger operand: consecutive tiles of
+  // an XCD share a column block of B, which is then fetched once
+  const int64_t m0 = (p.colmajor ? tile % tilesM : tile / tilesN) * BM,
+                n0 = (p.colmajor ? tile / tilesM : tile % tilesN) * BN;
   const int64_t sidx = blockIdx.y;
   const int64_t kbeg = sidx * p.kchunk;
   const int64_t kend = (kbeg + p.kchunk < p.Kp) ? kbeg + p.kchunk : p.Kp;
@@ -702,7 +705,10 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
     const int64_t q = ntile / 8, r = ntile % 8, x = L % 8, slot = L / 8;
     tile = x * q + (x < r ? x : r) + slot;
   }
-  const int64_t m0 = (tile / tilesN) * BM, n0 = (tile % tilesN) * BN;
+  // column-major walk when B is the larger operand: consecutive tiles of
+  // an XCD share a column block of B, which is then fetched once
+  const int64_t m0 = (p.colmajor ? tile % tilesM : tile / tilesN) * BM,
+                n0 = (p.colmajor ? tile / tilesM : tile % tilesN) * BN;
   const int64_t sidx = blockIdx.y;
   const int64_t kbeg = sidx * p.kchunk;
   const int64_t kend = (kbeg + p.kchunk < p.Kp) ? kbeg + p.kchunk : p.Kp;
@@ -857,6 +863,7 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
   BfGemm h = g;
   if (h.nsplit < 1 || h.kchunk <= 0) { h.nsplit = 1; h.kchunk = h.Kp; }
+  h.colmajor = h.N > h.M ? 1 : 0;
   const int tile = h.tile < 0 ? bf16p_pick_tile(h) : h.tile;
   switch (tile) {
     case 1: launch_bf16p_tile<4, 4>(h, s); break;
