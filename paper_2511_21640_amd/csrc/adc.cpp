@@ -794,8 +794,12 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // ---------------- doubles output: every term goes, with its coefficient,
   // into the accumulator of the antisymmetriser it needs (P(ij): A0, P(ab):
   // A1, P(ij)P(ab): A2); one pass then antisymmetrises, packs and adds D Y
-  Tensor A0 = tnew(cx, {k, o, o, v, v}, false), A1 = tnew(cx, {k, o, o, v, v}, false);
-  Tensor A2 = x != 0.0 ? tnew(cx, {k, o, o, v, v}, false) : Tensor{};
+  // in reduced precision the accumulators hold complex64: every term reaching
+  // them is computed to FP32 accuracy, and it halves their traffic
+  const bool acc32 = prec != ADC_FP64 && !cx.tape;
+  auto acc = [&]() { return acc32 ? tnew32(cx, {k, o, o, v, v}) : tnew(cx, {k, o, o, v, v}, false); };
+  Tensor A0 = acc(), A1 = acc();
+  Tensor A2 = x != 0.0 ? acc() : Tensor{};
   // M21(1) and the M21(2) terms with the same output roles, one GEMM per
   // accumulator over the concatenated summed index (the factors E0, E1 are
   // built once; x goes on the trial-vector side):

@@ -351,7 +351,8 @@ void rec_pack_ee(Ctx& cx, const Tensor& A0, const Tensor& A1, const Tensor& A2, 
     }
     tape_record(cx, op);
   }
-  launch_pack_ee(A0.p, A1.p, A2.p, S, Y, ld, off, k, o, v, eps, po, pv, cx.stream);
+  if (A0.f32 != A1.f32 || (A2.p && A2.f32 != A0.f32)) throw std::logic_error("pack_ee: mixed accumulator types");
+  launch_pack_ee(A0.p, A1.p, A2.p, S, Y, ld, off, k, o, v, eps, po, pv, cx.stream, A0.f32 ? 1 : 0);
 }
 
 }  // namespace adc

@@ -382,6 +382,14 @@ Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero) {
   return t;
 }
 
+Tensor tnew32(Ctx& cx, std::vector<int64_t> d) {
+  Tensor t;
+  t.d = std::move(d);
+  t.p = cx.pool.get(std::max<int64_t>(1, (t.size() + 1) / 2));
+  t.f32 = true;
+  return t;
+}
+
 void tfree(Ctx& cx, Tensor& t) {
   cx.pool.put(t.p);
   t.p = nullptr;
@@ -603,8 +611,9 @@ Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi) {
   } else {
     v.st = t.st;
   }
-  v.p = t.p + lo * v.st[dim];
+  v.p = t.f32 ? (double2*)((float2*)t.p + lo * v.st[dim]) : t.p + lo * v.st[dim];
   v.d[dim] = hi - lo;
+  v.f32 = t.f32;
   return v;
 }
 
@@ -710,6 +719,7 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
     op.cA = cA; op.cB = cB; op.alpha = alpha; op.beta = beta;
     tape_record(cx, op);
   }
+  if (A.f32 || B.f32) throw std::logic_error("ctr: complex64 operands are not supported");
   Pause pause(cx);
   View va = view_of(A, la), vb = view_of(B, lb), vc = view_of(C, lc);
   std::string sa(la), sb(lb), sc(lc);
@@ -876,8 +886,10 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
     OutMap om{};
     if (group_map(vc, Ml, scm, om.nm, om.md, om.ms) && group_map(vc, Nl, scn, om.nn, om.nd, om.ns)) {
       g.C = C.p; g.scm = scm; g.scn = scn; g.om = om;
+      g.c32 = C.f32 ? 1 : 0;
       gemm_bf16p(cx, g);
     } else {
+      if (C.f32) throw std::logic_error("ctr: complex64 output needs a direct output map");
       double2* t = cx.pool.get(Mn * Nn);
       tmps.push_back(t);
       g.C = t; g.scm = Nn; g.scn = 1; g.alpha = C1(); g.beta = C0();
@@ -924,6 +936,7 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   }
   if (Kn == 0) {
     // empty sum: C = beta C
+    if (C.f32) throw std::logic_error("ctr: complex64 output of an empty sum");
     if (beta.re != 1.0 || beta.im != 0.0) perm(cx, beta, C, lc, false, C0(), C, lc);
   } else {
     // ---- output
@@ -932,8 +945,10 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
     OutMap om{};
     if (sbt >= 0 && group_map(vc, Ml, sm, om.nm, om.md, om.ms) && group_map(vc, Nl, sn, om.nn, om.nd, om.ns)) {
       g.C = C.p; g.scb = bat.empty() ? 0 : sbt; g.scm = sm; g.scn = sn; g.om = om;
+      g.c32 = C.f32 ? 1 : 0;
       gemm(cx, g);
     } else {
+      if (C.f32) throw std::logic_error("ctr: complex64 output needs a direct output map");
       double2* t = cx.pool.get(Bn * Mn * Nn);
       tmps.push_back(t);
       g.C = t; g.scb = Mn * Nn; g.scm = Nn; g.scn = 1;

@@ -44,6 +44,7 @@ struct GemmDesc {
   double2* P;
   int tile;  // -1 heuristic, 0 small tiles, 1 large tiles
   OutMap om;
+  int c32 = 0;  // C holds complex64 (float2) elements
 };
 void launch_splitk_reduce(const GemmDesc& g, hipStream_t s);
 // prec: 0 = FP64 MFMA, 1 = FP32 MFMA (operands rounded to fp32, fp32
@@ -69,6 +70,7 @@ struct BfGemm {
   // (r / amd) * ams + r % amd (amd = 0: row r); likewise B with bmd, bms
   int64_t amd = 0, ams = 0, bmd = 0, bms = 0;
   int colmajor = 0;  // set by launch_bf16p: tiles walk down columns (N > M)
+  int c32 = 0;       // C holds complex64 (float2) elements
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);
 // the tile launch_bf16p takes for g.tile < 0
@@ -151,7 +153,7 @@ void launch_ladder_pack(const double2* W, int64_t ldw, int a0, int b0, int nv, d
 // (i<j, a<b) + D Y (A2 may be null); A0..A2 are [k][o][o][v][v]
 void launch_pack_ee(const double2* A0, const double2* A1, const double2* A2, double2* S, const double2* Y, int64_t ld,
                     int64_t off, int k, int no, int nv, const double* eps, const int2* po, const int2* pv,
-                    hipStream_t s);
+                    hipStream_t s, int a32 = 0);
 
 // adjoint helpers
 // gf[a][A] += sum_i gX[(i,a),(i,A)] (which 0) or gf[i][I] += sum_a gX[(i,a),(I,a)] (which 1)
@@ -174,6 +176,9 @@ int row_dot_blocks(int64_t n);
 // ---------------------------------------------------------------- engine
 struct Tensor {
   double2* p = nullptr;
+  // complex64 elements (float2) at p: only as the output of ctr() GEMMs and
+  // the input of launch_pack_ee (accumulators of reduced-precision builds)
+  bool f32 = false;
   std::vector<int64_t> d;
   std::vector<int64_t> st;  // element strides; empty = contiguous row-major
   int64_t size() const {
@@ -316,6 +321,8 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
 void perm(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, cplx beta, Tensor& C, const char* lc);
 
 Tensor tnew(Ctx& cx, std::vector<int64_t> d, bool zero = true);
+// an uninitialised complex64 tensor (see Tensor::f32)
+Tensor tnew32(Ctx& cx, std::vector<int64_t> d);
 // record an op on the tape (no-op unless recording); marks the output as
 // requiring a gradient when any input does
 void tape_record(Ctx& cx, TapeOp op);

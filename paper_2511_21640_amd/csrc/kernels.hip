@@ -43,11 +43,13 @@ typedef double d2v __attribute__((ext_vector_type(2)));
 // the loads are in flight together; every access is one 16-byte vector.  P
 // (split-K partials of this split, row-major M x N) replaces the output when
 // given.
+typedef float f2v __attribute__((ext_vector_type(2)));
+
 template <int WM, int WN, class AccT>
 __device__ __forceinline__ void store_tile(int64_t M, int64_t N, double2* C, double2* P, const OutMap& om,
                                            int64_t scm, int64_t scn, cplx alpha, cplx beta,
                                            const int64_t (&rows)[WM][4], const int64_t (&cols)[WN],
-                                           const AccT (&accR)[WM][WN], const AccT (&accI)[WM][WN]) {
+                                           const AccT (&accR)[WM][WN], const AccT (&accI)[WM][WN], int c32) {
   if (P) {
 #pragma unroll
     for (int i = 0; i < WM; ++i)
@@ -74,7 +76,14 @@ __device__ __forceinline__ void store_tile(int64_t M, int64_t N, double2* C, dou
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         old[j][r] = d2v{0.0, 0.0};
-        if (has_beta && rows[i][r] < M && cols[j] < N) old[j][r] = *(const d2v*)(C + roff[r] + coff[j]);
+        if (has_beta && rows[i][r] < M && cols[j] < N) {
+          if (c32) {
+            const f2v f = *((const f2v*)C + roff[r] + coff[j]);
+            old[j][r] = d2v{(double)f.x, (double)f.y};
+          } else {
+            old[j][r] = *(const d2v*)(C + roff[r] + coff[j]);
+          }
+        }
       }
 #pragma unroll
     for (int j = 0; j < WN; ++j)
@@ -85,7 +94,8 @@ __device__ __forceinline__ void store_tile(int64_t M, int64_t N, double2* C, dou
           d2v o;
           o.x = alpha.re * cr - alpha.im * ci + beta.re * old[j][r].x - beta.im * old[j][r].y;
           o.y = alpha.re * ci + alpha.im * cr + beta.re * old[j][r].y + beta.im * old[j][r].x;
-          *(d2v*)(C + roff[r] + coff[j]) = o;
+          if (c32) *((f2v*)C + roff[r] + coff[j]) = f2v{(float)o.x, (float)o.y};
+          else *(d2v*)(C + roff[r] + coff[j]) = o;
         }
       }
   }
@@ -144,7 +154,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc p) {
   const int64_t kend = (kbeg + p.kchunk < p.K) ? kbeg + p.kchunk : p.K;
   const double2* A = p.A + bz * p.sab;
   const double2* B = p.B + bz * p.sbb;
-  double2* C = p.C + bz * p.scb;
+  double2* C = p.c32 ? (double2*)((float2*)p.C + bz * p.scb) : p.C + bz * p.scb;
   const int wr = wave >> 1, wc = wave & 1;
   const bool aK = (p.sak == 1), bK = (p.sbk == 1);
   const T sa = p.conjA ? T(-1) : T(1), sb = p.conjB ? T(-1) : T(1);
@@ -242,38 +252,68 @@ __global__ __launch_bounds__(256) void zgemm_kernel(GemmDesc p) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) cols[j] = n0 + 32 * WN / 2 * wc + 16 * j + (lane & 15);
     double2* P = p.nsplit > 1 ? p.P + (sidx * p.batch + bz) * p.M * p.N : nullptr;
-    store_tile<WM, WN>(p.M, p.N, C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+    store_tile<WM, WN>(p.M, p.N, C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
   }
 }
 
-__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmDesc p) {
-  const int64_t total = p.batch * p.M * p.N;
-  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b = idx / (p.M * p.N), r = idx - b * p.M * p.N, m = r / p.N, n = r - m * p.N;
-    double sr = 0.0, si = 0.0;
-    for (int s = 0; s < p.nsplit; ++s) {
-      const double2 v = p.P[(int64_t)s * total + idx];
+// Split-K reduction: out = alpha * sum_s P[s][idx] + beta * out for the
+// outputs idx = (batch, m, n).  64 outputs per block; the splits of each are
+// spread over four thread rows (independent loads in flight) and summed in LDS.
+struct ReduceArgs {
+  const double2* P;
+  int64_t total, MN, N;
+  int nsplit;
+  double2* C;
+  int64_t scb, scm, scn;
+  OutMap om;
+  cplx alpha, beta;
+  int c32;
+};
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(ReduceArgs a) {
+  __shared__ double2 red[4][64];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + tx;
+  double sr = 0.0, si = 0.0;
+  if (idx < a.total) {
+#pragma unroll 4
+    for (int s = ty; s < a.nsplit; s += 4) {
+      const double2 v = a.P[(int64_t)s * a.total + idx];
       sr += v.x;
       si += v.y;
     }
-    double2* dst = p.C + b * p.scb + omap(m, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(n, p.om.nn, p.om.nd, p.om.ns, p.scn);
-    double2 o;
-    o.x = p.alpha.re * sr - p.alpha.im * si;
-    o.y = p.alpha.re * si + p.alpha.im * sr;
-    if (has_beta) {
-      const double2 old = *dst;
-      o.x += p.beta.re * old.x - p.beta.im * old.y;
-      o.y += p.beta.re * old.y + p.beta.im * old.x;
-    }
-    *dst = o;
   }
+  red[ty][tx] = make_double2(sr, si);
+  __syncthreads();
+  if (ty != 0 || idx >= a.total) return;
+  sr = (red[0][tx].x + red[1][tx].x) + (red[2][tx].x + red[3][tx].x);
+  si = (red[0][tx].y + red[1][tx].y) + (red[2][tx].y + red[3][tx].y);
+  const int64_t b = idx / a.MN, r = idx - b * a.MN, m = r / a.N, n = r - m * a.N;
+  const int64_t off = b * a.scb + omap(m, a.om.nm, a.om.md, a.om.ms, a.scm) + omap(n, a.om.nn, a.om.nd, a.om.ns, a.scn);
+  double ox = a.alpha.re * sr - a.alpha.im * si, oy = a.alpha.re * si + a.alpha.im * sr;
+  if (a.beta.re != 0.0 || a.beta.im != 0.0) {
+    double px, py;
+    if (a.c32) {
+      const float2 f = ((const float2*)a.C)[off];
+      px = f.x; py = f.y;
+    } else {
+      const double2 d = a.C[off];
+      px = d.x; py = d.y;
+    }
+    ox += a.beta.re * px - a.beta.im * py;
+    oy += a.beta.re * py + a.beta.im * px;
+  }
+  if (a.c32) ((float2*)a.C)[off] = make_float2((float)ox, (float)oy);
+  else a.C[off] = make_double2(ox, oy);
+}
+static void launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  if (a.total <= 0) return;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)((a.total + 63) / 64)), dim3(256), 0, s, a);
 }
 
 void launch_splitk_reduce(const GemmDesc& g, hipStream_t s) {
-  const int64_t total = g.batch * g.M * g.N;
-  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, g);
+  ReduceArgs a{g.P, g.batch * g.M * g.N, g.M * g.N, g.N, g.nsplit, g.C, g.scb, g.scm, g.scn, g.om, g.alpha, g.beta,
+               g.c32};
+  launch_reduce(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -321,7 +361,7 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc p) {
   const int64_t kend = (kbeg + p.kchunk < p.K) ? kbeg + p.kchunk : p.K;
   const double2* A = p.A + bz * p.sab;
   const double2* B = p.B + bz * p.sbb;
-  double2* C = p.C + bz * p.scb;
+  double2* C = p.c32 ? (double2*)((float2*)p.C + bz * p.scb) : p.C + bz * p.scb;
   const int wr = wave >> 1, wc = wave & 1;
   const bool aK = (p.sak == 1), bK = (p.sbk == 1);
   const float sa = p.conjA ? -1.f : 1.f, sb = p.conjB ? -1.f : 1.f;
@@ -431,7 +471,7 @@ __global__ __launch_bounds__(256) void zgemm_bf16x3_kernel(GemmDesc p) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) cols[j] = n0 + 32 * wc + 16 * j + (lane & 15);
     double2* P = p.nsplit > 1 ? p.P + (sidx * p.batch + bz) * p.M * p.N : nullptr;
-    store_tile<2, 2>(p.M, p.N, C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+    store_tile<2, 2>(p.M, p.N, C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
   }
 }
 
@@ -670,7 +710,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16p_kernel(BfGemm p) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) cols[j] = n0 + 16 * WN * wc + 16 * j + (lane & 15);
     double2* P = p.nsplit > 1 ? p.P + sidx * p.M * p.N : nullptr;
-    store_tile<WM, WN>(p.M, p.N, p.C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+    store_tile<WM, WN>(p.M, p.N, p.C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
   }
 }
 
@@ -812,7 +852,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) cols[j] = n0 + 16 * WN * wc + 16 * j + (lane & 15);
     double2* P = p.nsplit > 1 ? p.P + sidx * p.M * p.N : nullptr;
-    store_tile<WM, WN>(p.M, p.N, p.C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI);
+    store_tile<WM, WN>(p.M, p.N, p.C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
   }
 }
 
@@ -878,32 +918,9 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
   }
 }
 
-__global__ void splitk_reduce_bf_kernel(BfGemm p) {
-  const int64_t total = p.M * p.N;
-  const bool has_beta = (p.beta.re != 0.0 || p.beta.im != 0.0);
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t m = idx / p.N, n = idx - m * p.N;
-    double sr = 0.0, si = 0.0;
-    for (int s = 0; s < p.nsplit; ++s) {
-      const double2 v = p.P[(int64_t)s * total + idx];
-      sr += v.x;
-      si += v.y;
-    }
-    double2* dst = p.C + omap(m, p.om.nm, p.om.md, p.om.ms, p.scm) + omap(n, p.om.nn, p.om.nd, p.om.ns, p.scn);
-    double2 o;
-    o.x = p.alpha.re * sr - p.alpha.im * si;
-    o.y = p.alpha.re * si + p.alpha.im * sr;
-    if (has_beta) {
-      const double2 old = *dst;
-      o.x += p.beta.re * old.x - p.beta.im * old.y;
-      o.y += p.beta.re * old.y + p.beta.im * old.x;
-    }
-    *dst = o;
-  }
-}
 void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s) {
-  hipLaunchKernelGGL(splitk_reduce_bf_kernel, dim3(nblocks(g.M * g.N, 256)), dim3(256), 0, s, g);
+  ReduceArgs a{g.P, g.M * g.N, g.M * g.N, g.N, g.nsplit, g.C, 0, g.scm, g.scn, g.om, g.alpha, g.beta, g.c32};
+  launch_reduce(a, s);
 }
 
 // packed <ab||cd> rows written directly as split planes [4][ldv][Kp], at rows
@@ -1573,10 +1590,10 @@ void launch_precondition(const double2* R, double2* N, const double* D, const do
 //        + A2[ij ab] - A2[ji ab] - A2[ij ba] + A2[ji ba]                    (P(ij)P(ab))
 //        + D_ijab Y[z][off + ...]
 // for i<j, a<b; A0..A2 are [k][o][o][v][v] (A2 may be null)
-__global__ __launch_bounds__(256) void pack_ee_kernel(const double2* A0, const double2* A1, const double2* A2,
-                                                      double2* S, const double2* Y, int64_t ld, int64_t off, int k,
-                                                      int no, int nv, const double* eps, const int2* po,
-                                                      const int2* pv) {
+template <class AT>
+__global__ __launch_bounds__(256) void pack_ee_kernel(const AT* A0, const AT* A1, const AT* A2, double2* S,
+                                                      const double2* Y, int64_t ld, int64_t off, int k, int no, int nv,
+                                                      const double* eps, const int2* po, const int2* pv) {
   const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
   const int64_t n2 = Po * Pv, per = (int64_t)no * no * nv * nv;
   const int64_t total = n2 * k;
@@ -1590,16 +1607,16 @@ __global__ __launch_bounds__(256) void pack_ee_kernel(const double2* A0, const d
     const int64_t o_jiab = (((int64_t)ij.y * no + ij.x) * nv + ab.x) * nv + ab.y;
     const int64_t o_ijba = (((int64_t)ij.x * no + ij.y) * nv + ab.y) * nv + ab.x;
     const int64_t o_jiba = (((int64_t)ij.y * no + ij.x) * nv + ab.y) * nv + ab.x;
-    double2 a = A0[b0 + o_ijab], c = A0[b0 + o_jiab];
-    double rx = a.x - c.x, ry = a.y - c.y;
+    AT a = A0[b0 + o_ijab], c = A0[b0 + o_jiab];
+    double rx = (double)a.x - (double)c.x, ry = (double)a.y - (double)c.y;
     a = A1[b0 + o_ijab];
     c = A1[b0 + o_ijba];
-    rx += a.x - c.x;
-    ry += a.y - c.y;
+    rx += (double)a.x - (double)c.x;
+    ry += (double)a.y - (double)c.y;
     if (A2) {
-      const double2 w1 = A2[b0 + o_ijab], w2 = A2[b0 + o_jiab], w3 = A2[b0 + o_ijba], w4 = A2[b0 + o_jiba];
-      rx += w1.x - w2.x - w3.x + w4.x;
-      ry += w1.y - w2.y - w3.y + w4.y;
+      const AT w1 = A2[b0 + o_ijab], w2 = A2[b0 + o_jiab], w3 = A2[b0 + o_ijba], w4 = A2[b0 + o_jiba];
+      rx += (double)w1.x - (double)w2.x - (double)w3.x + (double)w4.x;
+      ry += (double)w1.y - (double)w2.y - (double)w3.y + (double)w4.y;
     }
     const double D = eps[no + ab.x] + eps[no + ab.y] - eps[ij.x] - eps[ij.y];
     const double2 y = Y[z * ld + off + q];
@@ -1608,11 +1625,15 @@ __global__ __launch_bounds__(256) void pack_ee_kernel(const double2* A0, const d
 }
 void launch_pack_ee(const double2* A0, const double2* A1, const double2* A2, double2* S, const double2* Y, int64_t ld,
                     int64_t off, int k, int no, int nv, const double* eps, const int2* po, const int2* pv,
-                    hipStream_t s) {
+                    hipStream_t s, int a32) {
   const int64_t n2 = (int64_t)no * (no - 1) / 2 * ((int64_t)nv * (nv - 1) / 2);
   if (n2 * k == 0) return;
-  hipLaunchKernelGGL(pack_ee_kernel, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, A0, A1, A2, S, Y, ld, off, k, no,
-                     nv, eps, po, pv);
+  if (a32)
+    hipLaunchKernelGGL(pack_ee_kernel<float2>, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, (const float2*)A0,
+                       (const float2*)A1, (const float2*)A2, S, Y, ld, off, k, no, nv, eps, po, pv);
+  else
+    hipLaunchKernelGGL(pack_ee_kernel<double2>, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, A0, A1, A2, S, Y, ld,
+                       off, k, no, nv, eps, po, pv);
 }
 
 // ---------------------------------------------------------------------------
