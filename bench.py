@@ -25,16 +25,18 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
 # HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain 1 GiB copy) of one
 # split-bf16 ladder term at this workload, from the counter runs summarised in
 # profiles/ladder_c2_split_bf16.md; None for the other precisions (not measured)
-LADDER_TRAFFIC_BYTES = {"split_bf16": 17.061e9 + 3.398e9}
+LADDER_TRAFFIC_BYTES = {"split_bf16": 7.789e9 + 2.592e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}
 
 
 def core_flops(o, v, N, k):
     """Algorithmic (core) flop of one EE sigma build, 8 flop per complex MAC:
-    vvvv assembly 2 N Pv^2, pp-ladder k Po Pv^2, ring k (ov)^3, hh-ladder
-    k Po^2 Pv, first-order coupling k o^2 v^3 (three-external class stored)."""
+    vvvv assembly of the Hermitian upper part 2 N Pv (Pv + 1) / 2 (each
+    <ab||cd>, ab <= cd, is two Cholesky sums of N), pp-ladder k Po Pv^2, ring
+    k (ov)^3, hh-ladder k Po^2 Pv, first-order coupling k o^2 v^3
+    (three-external class stored)."""
     Po, Pv = o * (o - 1) // 2, v * (v - 1) // 2
-    assembly = 2 * N * Pv * Pv
+    assembly = N * Pv * (Pv + 1)
     ladder = k * Po * Pv * Pv
     ring = k * (o * v) ** 3
     hh = k * Po * Po * Pv

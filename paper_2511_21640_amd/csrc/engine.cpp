@@ -661,6 +661,16 @@ static unsigned short* split_cached(Ctx& cx, SplitNd sp, int64_t bytes, bool til
     if (same_layout(e.key, sp)) return e.planes;
   if (scope == 0 && c.persistent_bytes + bytes > c.limit) return nullptr;
   if (capturing(cx.stream)) return nullptr;
+  // a cached copy never takes the last eighth of the device memory, which
+  // the temporaries of the contractions need
+  {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    if ((int64_t)fr < bytes + (int64_t)(tot / 8)) return nullptr;
+  }
   unsigned short* dst = (unsigned short*)cx.pool.get((bytes + 15) / 16);
   sp.dst = dst;
   launch_split_nd(sp, tiled ? 1 : 0, cx.stream);
