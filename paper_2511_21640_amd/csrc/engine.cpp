@@ -620,9 +620,29 @@ Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi) {
 // ------------------------------------------------------------------ split cache
 namespace {
 
+// the digits (size, stride) of rows then K, merged where contiguous: when K
+// needs no padding, two splits with equal lists write identical planes
+std::vector<std::pair<int64_t, int64_t>> flat_digits(const SplitNd& a) {
+  std::vector<std::pair<int64_t, int64_t>> d;
+  auto add = [&](int64_t n, int64_t st) {
+    if (n == 1) return;
+    if (!d.empty() && d.back().second == n * st) {
+      d.back().first *= n;
+      d.back().second = st;
+    } else {
+      d.push_back({n, st});
+    }
+  };
+  for (int q = 0; q < a.nm; ++q) add(a.md[q], a.ms[q]);
+  for (int q = 0; q < a.nk; ++q) add(a.kd[q], a.ks[q]);
+  return d;
+}
+
 bool same_layout(const SplitNd& a, const SplitNd& b) {
-  if (a.src != b.src || a.conj != b.conj || a.rows != b.rows || a.K != b.K || a.Kp != b.Kp || a.nm != b.nm ||
-      a.nk != b.nk)
+  if (a.src != b.src || a.conj != b.conj) return false;
+  if (a.K == a.Kp && b.K == b.Kp && a.rows * a.Kp == b.rows * b.Kp)
+    return flat_digits(a) == flat_digits(b);
+  if (a.rows != b.rows || a.K != b.K || a.Kp != b.Kp || a.nm != b.nm || a.nk != b.nk)
     return false;
   for (int q = 0; q < a.nm; ++q)
     if (a.md[q] != b.md[q] || a.ms[q] != b.ms[q]) return false;

@@ -996,7 +996,9 @@ void launch_ladder_pack_planes_upper(const double2* W, int64_t ldw, int a0, int 
 }
 
 // 64 x 64 tiles (tp >= tq) of the strictly lower triangle: read block (q, p)
-// of the upper part through LDS, write its conjugate transpose at (p, q)
+// of the upper part through LDS, write its conjugate transpose at (p, q);
+// global accesses are pairs of bf16 (4 bytes), except where a pair straddles
+// the diagonal
 __global__ __launch_bounds__(256) void ladder_mirror_planes_kernel(unsigned short* V, int64_t ldv, int64_t n,
                                                                    int64_t Kp) {
   __shared__ unsigned short t[64][66];
@@ -1008,22 +1010,37 @@ __global__ __launch_bounds__(256) void ladder_mirror_planes_kernel(unsigned shor
   const int64_t tq = L - tp * (tp + 1) / 2;
   const int64_t p0 = tp * 64, q0 = tq * 64;
   const int64_t plane = ldv * Kp;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int c = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int pl = 0; pl < 4; ++pl) {
-    const unsigned short flip = pl >= 2 ? 0x8000 : 0;
-    // load rows q0.. (upper part), columns p0..
+    const unsigned flip = pl >= 2 ? 0x80008000u : 0u;
+    unsigned short* Vp = V + pl * plane;
+    // rows q0 + r of the upper part, columns p0 + 2c, p0 + 2c + 1
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r = ty + 4 * e;
-      const int64_t q = q0 + r, p = p0 + tx;
-      t[r][tx] = (q < n && p < n && q < p) ? V[pl * plane + q * Kp + p] : 0;
+    for (int e = 0; e < 8; ++e) {
+      const int r = ty + 8 * e;
+      const int64_t q = q0 + r, p = p0 + 2 * c;
+      unsigned w = 0;
+      if (q < n && p < n) {
+        // Kp and p are even: the pair is 4-byte aligned and inside the row
+        w = *(const unsigned*)(Vp + q * Kp + p);
+        if (!(q < p)) w &= 0xffff0000u;
+        if (!(q < p + 1) || p + 1 >= n) w &= 0x0000ffffu;
+      }
+      t[r][2 * c] = (unsigned short)(w & 0xffffu);
+      t[r][2 * c + 1] = (unsigned short)(w >> 16);
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r = ty + 4 * e;
-      const int64_t p = p0 + r, q = q0 + tx;
-      if (p < n && q < p) V[pl * plane + p * Kp + q] = t[tx][r] ^ flip;
+    for (int e = 0; e < 8; ++e) {
+      const int r = ty + 8 * e;
+      const int64_t p = p0 + r, q = q0 + 2 * c;
+      if (p >= n) continue;
+      const unsigned w = ((unsigned)t[2 * c][r] | ((unsigned)t[2 * c + 1][r] << 16)) ^ flip;
+      if (q + 1 < p) {
+        *(unsigned*)(Vp + p * Kp + q) = w;
+      } else if (q < p) {
+        Vp[p * Kp + q] = (unsigned short)(w & 0xffffu);
+      }
     }
     __syncthreads();
   }
