@@ -64,6 +64,9 @@ struct Inst {
   // the singles-output terms that read the unpacked trial vectors in one
   // layout, summed into one factor per layout (x enters them; see build_sx)
   Tensor X1, X2;
+  // EE outside a tape: E0 and t1 with the pair (a<b) packed, E1 with the
+  // pair (I<J) packed, for the half-stored accumulators (E0, E1 are freed)
+  Tensor E0h, E1h, th;
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
@@ -672,6 +675,19 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     perm(cx, C1(), I.W, "IJiA", true, C0(), g, "IJAi");
   }
   build_sx(cx, I, I.x, I.X1, I.X2);
+  if (!cx.tape) {
+    // A0 is antisymmetric in (a,b) and A1 in (I,J) (so are all their terms):
+    // their factors are kept with that pair packed
+    const int64_t Pv = I.Pv, Po = I.Po;
+    I.E0h = tnew(cx, {o, Pv, v + o}, false);
+    launch_pack_pairs(I.E0.p, I.E0h.p, o, v, v + o, I.pair_v, cx.stream);
+    I.E1h = tnew(cx, {Po, v, 2 * o + v}, false);
+    launch_pack_pairs(I.E1.p, I.E1h.p, 1, o, (int64_t)v * (2 * o + v), I.pair_o, cx.stream);
+    I.th = tnew(cx, {o, o, Pv}, false);
+    launch_pack_pairs(t.p, I.th.p, (int64_t)o * o, v, 1, I.pair_v, cx.stream);
+    tfree(cx, I.E0);
+    tfree(cx, I.E1);
+  }
 }
 
 // ============================================================================
@@ -797,9 +813,14 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // in reduced precision the accumulators hold complex64: every term reaching
   // them is computed to FP32 accuracy, and it halves their traffic
   const bool acc32 = prec != ADC_FP64 && !cx.tape;
-  auto acc = [&]() { return acc32 ? tnew32(cx, {k, o, o, v, v}) : tnew(cx, {k, o, o, v, v}, false); };
-  Tensor A0 = acc(), A1 = acc();
-  Tensor A2 = x != 0.0 ? acc() : Tensor{};
+  // outside a tape A0 keeps only the pairs a<b and A1 only I<J (each is
+  // antisymmetric there; the pack reads them accordingly)
+  const bool half = I.E0h.p && !cx.tape;
+  const int64_t Pv = I.Pv;
+  auto acc = [&](std::vector<int64_t> d) { return acc32 ? tnew32(cx, d) : tnew(cx, d, false); };
+  Tensor A0 = half ? acc({k, o, o, Pv}) : acc({k, o, o, v, v});
+  Tensor A1 = half ? acc({k, Po, v, v}) : acc({k, o, o, v, v});
+  Tensor A2 = x != 0.0 ? acc({k, o, o, v, v}) : Tensor{};
   // M21(1) and the M21(2) terms with the same output roles, one GEMM per
   // accumulator over the concatenated summed index (the factors E0, E1 are
   // built once; x goes on the trial-vector side):
@@ -826,24 +847,46 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       tfree(cx, Z1);
       perm(cx, CR(0.5 * x), ys, "ziB", false, C0(), b1i, "zBi");
     }
-    ctr(cx, C1(), I.E0, "iabq", false, B0, "zjq", false, C0(), A0, "zijab");
-    ctr(cx, C1(), I.E1, "IJAq", false, B1, "zBq", false, C0(), A1, "zIJAB");
+    if (half) {
+      ctr(cx, C1(), I.E0h, "iPq", false, B0, "zjq", false, C0(), A0, "zijP");
+      ctr(cx, C1(), I.E1h, "PAq", false, B1, "zBq", false, C0(), A1, "zPAB");
+    } else {
+      ctr(cx, C1(), I.E0, "iabq", false, B0, "zjq", false, C0(), A0, "zijab");
+      ctr(cx, C1(), I.E1, "IJAq", false, B1, "zBq", false, C0(), A1, "zIJAB");
+    }
     tfree(cx, B0);
     tfree(cx, B1);
   }
   if (x != 0.0) {
     Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
     ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
-    ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
+    if (half) ctr(cx, CR(-0.5 * x), I.th, "klP", false, Z4, "zklJI", false, C1(), A0, "zIJP");
+    else ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
     tfree(cx, Z4);
     ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C0(), A2, "zIJAB");
     ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
     // through P(ij)) and ring; the particle ladder runs packed below
-    ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
+    if (half) {
+      // the doubles unpacked in (k,l) only, pairs a<b kept
+      Tensor Yh = tnew(cx, {k, o, o, Pv}, false);
+      launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, Yh.p, nullptr, cx.stream);
+      {
+        SplitScope hs(cx, {{Yh.p, Yh.size()}});
+        ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Yh, "zklP", false, C1(), A0, "zijP");
+      }
+      tfree(cx, Yh);
+    } else {
+      ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
+    }
     ctr(cx, CR(-x), Ya, "zikac", false, I.ring, "kcjb", false, C1(), A2, "zijab");
   }
-  rec_pack_ee(cx, A0, A1, A2, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v);
+  if (half) {
+    launch_pack_ee_half(A0.p, A1.p, A2.p, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v, cx.stream,
+                        acc32 ? 1 : 0);
+  } else {
+    rec_pack_ee(cx, A0, A1, A2, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v);
+  }
   tfree(cx, A0);
   tfree(cx, A1);
   if (A2.p) tfree(cx, A2);
@@ -1073,7 +1116,7 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   // planes are kept per layout (at most their own size in bytes) and reused
   // by every sigma build
   for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1,
-                    &I.X1, &I.X2})
+                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th})
     if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {

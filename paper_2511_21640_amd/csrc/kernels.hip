@@ -1653,6 +1653,74 @@ void launch_pack_ee(const double2* A0, const double2* A1, const double2* A2, dou
                        off, k, no, nv, eps, po, pv);
 }
 
+// EE doubles output from accumulators that store only the half they need:
+// A0 is antisymmetric in (a,b) and kept as [k][o][o][P_v], A1 antisymmetric in
+// (i,j) and kept as [k][P_o][v][v]; A2 stays [k][o][o][v][v] (or null).
+//   S = A0[ij,ab] - A0[ji,ab] + A1[ij,ab] - A1[ij,ba] + P(ij)P(ab) A2 + D Y
+template <class AT>
+__global__ __launch_bounds__(256) void pack_ee_half_kernel(const AT* A0, const AT* A1, const AT* A2, double2* S,
+                                                           const double2* Y, int64_t ld, int64_t off, int k, int no,
+                                                           int nv, const double* eps, const int2* po,
+                                                           const int2* pv) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
+  const int64_t n2 = Po * Pv, total = n2 * k;
+  const int64_t per0 = (int64_t)no * no * Pv, per1 = Po * nv * nv, per2 = (int64_t)no * no * nv * nv;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = idx / n2, q = idx - z * n2;
+    const int64_t pij = q / Pv, pab = q - pij * Pv;
+    const int2 ij = po[pij], ab = pv[pab];
+    AT a = A0[z * per0 + ((int64_t)ij.x * no + ij.y) * Pv + pab], c = A0[z * per0 + ((int64_t)ij.y * no + ij.x) * Pv + pab];
+    double rx = (double)a.x - (double)c.x, ry = (double)a.y - (double)c.y;
+    a = A1[z * per1 + (pij * nv + ab.x) * nv + ab.y];
+    c = A1[z * per1 + (pij * nv + ab.y) * nv + ab.x];
+    rx += (double)a.x - (double)c.x;
+    ry += (double)a.y - (double)c.y;
+    if (A2) {
+      const int64_t b0 = z * per2;
+      const AT w1 = A2[b0 + (((int64_t)ij.x * no + ij.y) * nv + ab.x) * nv + ab.y];
+      const AT w2 = A2[b0 + (((int64_t)ij.y * no + ij.x) * nv + ab.x) * nv + ab.y];
+      const AT w3 = A2[b0 + (((int64_t)ij.x * no + ij.y) * nv + ab.y) * nv + ab.x];
+      const AT w4 = A2[b0 + (((int64_t)ij.y * no + ij.x) * nv + ab.y) * nv + ab.x];
+      rx += (double)w1.x - (double)w2.x - (double)w3.x + (double)w4.x;
+      ry += (double)w1.y - (double)w2.y - (double)w3.y + (double)w4.y;
+    }
+    const double D = eps[no + ab.x] + eps[no + ab.y] - eps[ij.x] - eps[ij.y];
+    const double2 y = Y[z * ld + off + q];
+    S[z * ld + off + q] = make_double2(rx + D * y.x, ry + D * y.y);
+  }
+}
+void launch_pack_ee_half(const double2* A0, const double2* A1, const double2* A2, double2* S, const double2* Y,
+                         int64_t ld, int64_t off, int k, int no, int nv, const double* eps, const int2* po,
+                         const int2* pv, hipStream_t s, int a32) {
+  const int64_t n2 = (int64_t)no * (no - 1) / 2 * ((int64_t)nv * (nv - 1) / 2);
+  if (n2 * k == 0) return;
+  if (a32)
+    hipLaunchKernelGGL(pack_ee_half_kernel<float2>, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, (const float2*)A0,
+                       (const float2*)A1, (const float2*)A2, S, Y, ld, off, k, no, nv, eps, po, pv);
+  else
+    hipLaunchKernelGGL(pack_ee_half_kernel<double2>, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, A0, A1, A2, S, Y,
+                       ld, off, k, no, nv, eps, po, pv);
+}
+
+// dst[o][p(a<b)][i] = src[o][a][b][i] for src [outer][n][n][inner]
+__global__ void pack_pairs_kernel(const double2* src, double2* dst, int64_t outer, int n, int64_t inner,
+                                  const int2* pairs) {
+  const int64_t P = (int64_t)n * (n - 1) / 2, total = outer * P * inner;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % inner, r = idx / inner, p = r % P, o = r / P;
+    const int2 ab = pairs[p];
+    dst[idx] = src[((o * n + ab.x) * n + ab.y) * inner + i];
+  }
+}
+void launch_pack_pairs(const double2* src, double2* dst, int64_t outer, int n, int64_t inner, const int2* pairs,
+                       hipStream_t s) {
+  const int64_t total = outer * ((int64_t)n * (n - 1) / 2) * inner;
+  if (total == 0) return;
+  hipLaunchKernelGGL(pack_pairs_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, src, dst, outer, n, inner, pairs);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint helpers
 // ---------------------------------------------------------------------------
