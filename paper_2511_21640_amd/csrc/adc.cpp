@@ -769,8 +769,15 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   Tensor ys = tnew(cx, {k, o, v}, false);
   rows_in(cx, Y, dim, 0, ys, k, n1);
   Tensor Ya = tnew(cx, {k, o, o, v, v}, false);
-  launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream);
   SplitScope scope(cx, {{Ya.p, Ya.size()}, {ys.p, ys.size()}});
+  // split-bf16: the unpack also writes the planes of Y in its own order (the
+  // layout of the contractions summing over (j,b,c) or (a,b) with rows
+  // (z,i[,j])), when that layout needs no K padding
+  unsigned short* yq = nullptr;
+  if (prec == ADC_SPLIT_BF16 && scope.id > 0 && ((int64_t)v * v) % 32 == 0)
+    yq = (unsigned short*)cx.pool.get(Ya.size() / 2);
+  launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream, yq);
+  if (yq) split_cache_put(cx, scope.id, Ya.p, Ya.size(), yq);
   const Tensor& t = I.t1;
 
   // ---------------- singles output

@@ -740,6 +740,15 @@ void split_scope_end(Ctx& cx, int scope) {
   if (scope > 0) drop_scope(cx, scope);
 }
 
+void split_cache_put(Ctx& cx, int scope, const double2* src, int64_t n, unsigned short* planes) {
+  SplitNd key{};
+  key.src = src;
+  key.rows = 1; key.K = n; key.Kp = n;
+  key.nm = 1; key.md[0] = 1; key.ms[0] = n;
+  key.nk = 1; key.kd[0] = n; key.ks[0] = 1;
+  cx.scache.entries.push_back({key, planes, n * 8, scope});
+}
+
 void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Tensor& B, const char* lb, bool cB,
          cplx beta, Tensor& C, const char* lc) {
   if (cx.tape && cx.tape->recording) {

@@ -132,8 +132,9 @@ void launch_div_d1(double2* t, const double* eps, int no, int nv, hipStream_t s)
 // Packed ISR vector <-> unpacked doubles tensor conversions.
 // kind: 0 EE [k][o][o][v][v], 1 IP [k][o][o][v], 2 EA [k][o][v][v].
 // unpack: Ya antisymmetric in every pair; Yp (optional) zero except packed positions.
+// planes (optional): split-bf16 planes [4][total] of Ya in its own order
 void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv,
-                           double2* Ya, double2* Yp, hipStream_t s);
+                           double2* Ya, double2* Yp, hipStream_t s, unsigned short* planes = nullptr);
 // S[z][off + packed] = alpha * U[z][...] + D[packed] * Y[z][off + packed] (+ S if accumulate)
 void launch_pack_doubles(int kind, const double2* U, double2* S, const double2* Y, int64_t ld, int64_t off,
                          int k, int no, int nv, const double* eps, cplx alpha, int accumulate,
@@ -318,6 +319,10 @@ void split_thaw_all(Ctx& cx);
 // open a scope over buffers that stay unchanged until split_scope_end
 int split_scope_begin(Ctx& cx, const std::vector<std::pair<const double2*, int64_t>>& bufs);
 void split_scope_end(Ctx& cx, int scope);
+// record planes [4][n] of the n elements at src, in their memory order, as a
+// cache entry of the scope (the cache then owns and frees them); they serve
+// every split that reads src in that order without K padding
+void split_cache_put(Ctx& cx, int scope, const double2* src, int64_t n, unsigned short* planes);
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);

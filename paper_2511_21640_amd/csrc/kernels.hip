@@ -1357,7 +1357,7 @@ __device__ __forceinline__ int64_t pidx(int64_t p, int64_t q, int64_t n) { retur
 
 // unpack: one thread per unpacked element
 __global__ void unpack_doubles_kernel(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv,
-                                      double2* Ya, double2* Yp) {
+                                      double2* Ya, double2* Yp, unsigned short* planes) {
   const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
   int64_t per;
   if (kind == 0) per = (int64_t)no * no * nv * nv;
@@ -1411,14 +1411,15 @@ __global__ void unpack_doubles_kernel(int kind, const double2* Y, int64_t ldY, i
     }
     if (Ya) Ya[idx] = v;
     if (Yp) Yp[idx] = (!zero && canon) ? v : make_double2(0.0, 0.0);
+    if (planes) put_planes(planes, total, idx, v, 0);
   }
   (void)Po;
 }
 void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, double2* Ya,
-                           double2* Yp, hipStream_t s) {
+                           double2* Yp, hipStream_t s, unsigned short* planes) {
   int64_t per = kind == 0 ? (int64_t)no * no * nv * nv : (kind == 1 ? (int64_t)no * no * nv : (int64_t)no * nv * nv);
   hipLaunchKernelGGL(unpack_doubles_kernel, dim3(nblocks(per * k, 256)), dim3(256), 0, s, kind, Y, ldY, off, k, no,
-                     nv, Ya, Yp);
+                     nv, Ya, Yp, planes);
 }
 
 // pack: one thread per packed element; po/pv are the pair tables of o and v
