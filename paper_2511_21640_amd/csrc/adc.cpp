@@ -67,6 +67,9 @@ struct Inst {
   // EE outside a tape: E0 and t1 with the pair (a<b) packed, E1 with the
   // pair (I<J) packed, for the half-stored accumulators (E0, E1 are freed)
   Tensor E0h, E1h, th;
+  // EE outside a tape: X1 antisymmetrised in (b,c) and packed, [o][v][P_v]
+  // (X1 itself is then dropped)
+  Tensor X1h;
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
@@ -513,7 +516,7 @@ void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector
 // ============================================================================
 // EE
 // ============================================================================
-void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2);
+void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* X1h);
 
 void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   Ctx& cx = *I.cx;
@@ -674,7 +677,7 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     Tensor g = tslice(I.E1, 3, o + v, 2 * o + v);
     perm(cx, C1(), I.W, "IJiA", true, C0(), g, "IJAi");
   }
-  build_sx(cx, I, I.x, I.X1, I.X2);
+  build_sx(cx, I, I.x, I.X1, I.X2, cx.tape ? nullptr : &I.X1h);
   if (!cx.tape) {
     // A0 is antisymmetric in (a,b) and A1 in (I,J) (so are all their terms):
     // their factors are kept with that pair packed
@@ -701,12 +704,18 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
 //   EA: X1_IaAB = -1/2 ovvv_IaAB + x W5_IAaB
 // (the M12(1) terms and the M12(2) terms in W, W5, W6).  x enters here, so a
 // change of x needs new factors.
-void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2) {
+void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* X1h) {
   const int o = I.o, v = I.v;
   if (I.kind == ADC_EE) {
     X1 = tnew(cx, {o, v, v, v}, false);
     perm(cx, CR(-0.5), I.ovvv, "jabc", false, C0(), X1, "jabc");
     perm(cx, CR(x), I.W5, "jbac", false, C1(), X1, "jabc");
+    if (X1h) {
+      // sum_bc X1_bc Y_bc = sum_{b<c} (X1_bc - X1_cb) Y_bc for antisymmetric Y
+      *X1h = tnew(cx, {o, v, I.Pv}, false);
+      launch_pack_pairs(X1.p, X1h->p, (int64_t)o * v, v, 1, I.pair_v, cx.stream, 1);
+      tfree(cx, X1);
+    }
     X2 = tnew(cx, {o, o, o, v}, false);
     perm(cx, CR(-0.5), I.ooov, "jkib", false, C0(), X2, "jkib");
     perm(cx, CR(-0.25 * x), I.W, "jkib", false, C1(), X2, "jkib");
@@ -738,7 +747,7 @@ void ip_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   ctr(cx, C1(), t, "IJcd", true, I.ovvv, "iBcd", true, C0(), I.W, "IJiB");
   I.W6 = tnew(cx, {o, I.v, o, o}, false);
   ctr(cx, C1(), t, "IkBc", true, I.ooov, "ikJc", true, C0(), I.W6, "IBJi");
-  build_sx(cx, I, I.x, I.X1, I.X2);
+  build_sx(cx, I, I.x, I.X1, I.X2, nullptr);
   // the sigma build of IP needs no three-external integrals
   tfree(cx, I.ovvv);
 }
@@ -756,7 +765,7 @@ void ea_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   const Tensor& t = I.t1;
   I.W5 = tnew(cx, {o, v, v, v}, false);
   ctr(cx, C1(), t, "JkAc", true, I.ovvv, "kBac", true, C0(), I.W5, "JAaB");
-  build_sx(cx, I, I.x, I.X1, I.X2);
+  build_sx(cx, I, I.x, I.X1, I.X2, nullptr);
 }
 
 void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
@@ -770,14 +779,25 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   rows_in(cx, Y, dim, 0, ys, k, n1);
   Tensor Ya = tnew(cx, {k, o, o, v, v}, false);
   SplitScope scope(cx, {{Ya.p, Ya.size()}, {ys.p, ys.size()}});
+  // outside a tape the terms that sum over an antisymmetric pair of Y take it
+  // once (pairs packed, factors antisymmetrised at init): see E0h, th, X1h
+  const bool half = I.E0h.p && !cx.tape;
+  const int64_t Pv = I.Pv;
   // split-bf16: the unpack also writes the planes of Y in its own order (the
   // layout of the contractions summing over (j,b,c) or (a,b) with rows
   // (z,i[,j])), when that layout needs no K padding
   unsigned short* yq = nullptr;
-  if (prec == ADC_SPLIT_BF16 && scope.id > 0 && ((int64_t)v * v) % 32 == 0)
+  if (!half && prec == ADC_SPLIT_BF16 && scope.id > 0 && ((int64_t)v * v) % 32 == 0)
     yq = (unsigned short*)cx.pool.get(Ya.size() / 2);
   launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream, yq);
   if (yq) split_cache_put(cx, scope.id, Ya.p, Ya.size(), yq);
+  // the doubles unpacked in the occupied pair only, virtual pairs a<b kept
+  Tensor Yh;
+  if (half) {
+    Yh = tnew(cx, {k, o, o, Pv}, false);
+    launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, Yh.p, nullptr, cx.stream);
+  }
+  SplitScope hscope(cx, {{Yh.p, Yh.size()}});
   const Tensor& t = I.t1;
 
   // ---------------- singles output
@@ -794,7 +814,8 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // M12(1) -1/2 <ja||bc> Y_ijbc - 1/2 <jk||ib> Y_jkab with the M12(2) terms
   // x W5_JAaB Y_iJAB - x/4 W_IJiB Y_IJaB + x W6_IBJi Y_IJaB, one contraction
   // per layout of Y through the factors X1, X2
-  ctr(cx, C1(), I.X1, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
+  if (half) ctr(cx, C1(), I.X1h, "jaP", false, Yh, "zijP", false, C1(), s1, "zia");
+  else ctr(cx, C1(), I.X1, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
   ctr(cx, C1(), I.X2, "jkib", false, Ya, "zjkab", false, C1(), s1, "zia");
   if (x != 0.0) {
     // M12(2), grouped with the antisymmetric Y
@@ -805,12 +826,24 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     ctr(cx, CR(0.5 * x), I.ovvv, "iBac", true, rY, "zcB", false, C1(), s1, "zia");
     tfree(cx, rY);
     Tensor r2 = tnew(cx, {k, o, o}, false);
-    // likewise Y_JIAB = -Y_IJAB (kept occupied first)
-    ctr(cx, CR(-1.0), t, "IkAB", true, Ya, "zJIAB", false, C0(), r2, "zkJ");
+    // likewise Y_JIAB = -Y_IJAB (kept occupied first); t and Y are both
+    // antisymmetric in (A,B), so the half form sums the pairs A<B twice
+    if (half) ctr(cx, CR(-2.0), I.th, "IkP", true, Yh, "zJIP", false, C0(), r2, "zkJ");
+    else ctr(cx, CR(-1.0), t, "IkAB", true, Ya, "zJIAB", false, C0(), r2, "zkJ");
     ctr(cx, CR(0.5 * x), I.ooov, "ikJa", true, r2, "zkJ", false, C1(), s1, "zia");
     tfree(cx, r2);
     Tensor V2 = tnew(cx, {k, o, o, o, o}, false);
-    ctr(cx, C1(), t, "klAB", true, Ya, "ziJAB", false, C0(), V2, "ziJkl");
+    if (half) {
+      // V2 is antisymmetric in (i,J): from the packed doubles (pairs i<J and
+      // A<B as stored) and unpacked in (i,J)
+      Tensor V2p = tnew(cx, {k, Po, o, o}, false);
+      Tensor Yp = tensor_view(const_cast<double2*>(Y) + n1, {k, Po, Pv}, {dim, Pv, 1});
+      ctr(cx, CR(2.0), I.th, "klP", true, Yp, "zpP", false, C0(), V2p, "zpkl");
+      launch_unpack_doubles(1, V2p.p, Po * o * o, 0, k, o, o * o, V2.p, nullptr, cx.stream);
+      tfree(cx, V2p);
+    } else {
+      ctr(cx, C1(), t, "klAB", true, Ya, "ziJAB", false, C0(), V2, "ziJkl");
+    }
     ctr(cx, CR(-0.25 * x), I.ooov, "klJa", true, V2, "ziJkl", false, C1(), s1, "zia");
     tfree(cx, V2);
   }
@@ -822,8 +855,6 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   const bool acc32 = prec != ADC_FP64 && !cx.tape;
   // outside a tape A0 keeps only the pairs a<b and A1 only I<J (each is
   // antisymmetric there; the pack reads them accordingly)
-  const bool half = I.E0h.p && !cx.tape;
-  const int64_t Pv = I.Pv;
   auto acc = [&](std::vector<int64_t> d) { return acc32 ? tnew32(cx, d) : tnew(cx, d, false); };
   Tensor A0 = half ? acc({k, o, o, Pv}) : acc({k, o, o, v, v});
   Tensor A1 = half ? acc({k, Po, v, v}) : acc({k, o, o, v, v});
@@ -875,14 +906,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
     // through P(ij)) and ring; the particle ladder runs packed below
     if (half) {
-      // the doubles unpacked in (k,l) only, pairs a<b kept
-      Tensor Yh = tnew(cx, {k, o, o, Pv}, false);
-      launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, Yh.p, nullptr, cx.stream);
-      {
-        SplitScope hs(cx, {{Yh.p, Yh.size()}});
-        ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Yh, "zklP", false, C1(), A0, "zijP");
-      }
-      tfree(cx, Yh);
+      ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Yh, "zklP", false, C1(), A0, "zijP");
     } else {
       ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
     }
@@ -899,6 +923,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   if (A2.p) tfree(cx, A2);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
   for (Tensor* p : {&ys, &Ya, &s1}) tfree(cx, *p);
+  if (Yh.p) tfree(cx, Yh);
   cx.prec = saved;
 }
 
@@ -1123,7 +1148,7 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   // planes are kept per layout (at most their own size in bytes) and reused
   // by every sigma build
   for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1,
-                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th})
+                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h})
     if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {
@@ -1698,15 +1723,17 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     std::swap(I.M11x, Mx);
     const double x0 = I.x;
     // the singles-coupling factors at x + 1 (the frozen ones stay untouched)
-    Tensor X1b, X2b;
-    build_sx(cx, I, x0 + 1.0, X1b, X2b);
+    Tensor X1b, X2b, X1hb;
+    build_sx(cx, I, x0 + 1.0, X1b, X2b, I.X1h.p ? &X1hb : nullptr);
     std::swap(I.X1, X1b);
     std::swap(I.X2, X2b);
+    std::swap(I.X1h, X1hb);
     auto restore = [&]() {
       I.x = x0;
       std::swap(I.M11x, Mx);
       std::swap(I.X1, X1b);
       std::swap(I.X2, X2b);
+      std::swap(I.X1h, X1hb);
     };
     I.x = x0 + 1.0;
     try {
@@ -1717,7 +1744,7 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     }
     restore();
     tfree(cx, Mx);
-    for (Tensor* t : {&X1b, &X2b})
+    for (Tensor* t : {&X1b, &X2b, &X1hb})
       if (t->p) tfree(cx, *t);
     perm(cx, CR(-1), S0, "zp", false, C1(), S1, "zp");
     Tensor Sb = tensor_view(const_cast<double2*>(Sbar), {1, (int64_t)k * dim}, {});

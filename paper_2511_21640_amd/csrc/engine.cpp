@@ -862,7 +862,8 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   std::vector<double2*> tmps;
   // split-bf16 mode: contractions over fewer than 32 summed elements with a
   // small output run in FP64 (one launch instead of two splits and a GEMM);
-  // large ones stay on the split-bf16 kernels, whose output path is faster
+  // large ones run on the pre-split planes with K padded to 32 (bound by
+  // their output, where that path is the fastest)
   struct PrecGuard {
     Ctx& cx;
     int saved;
@@ -870,7 +871,7 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   } pg{cx, cx.prec};
   if (cx.prec == 2 && Kn < 32 && Mn * Nn * Bn <= ((int64_t)1 << 20)) cx.prec = 0;
   // ---- split-bf16: unbatched contractions run on pre-split operand planes
-  if (cx.prec == 2 && bat.empty() && Kn >= 32) {
+  if (cx.prec == 2 && bat.empty() && Kn > 0) {
     const int64_t Kp = (Kn + 31) / 32 * 32;
     // K order: decreasing stride in the larger operand, so that its split
     // reads run along its unit stride where the K labels allow it

@@ -160,10 +160,11 @@ void launch_pack_ee(const double2* A0, const double2* A1, const double2* A2, dou
 void launch_pack_ee_half(const double2* A0, const double2* A1, const double2* A2, double2* S, const double2* Y,
                          int64_t ld, int64_t off, int k, int no, int nv, const double* eps, const int2* po,
                          const int2* pv, hipStream_t s, int a32);
-// dst[o][p][i] = src[o][a][b][i] over the pairs p = (a < b) of n: src is
-// [outer][n][n][inner], dst [outer][n(n-1)/2][inner]
+// dst[o][p][i] = src[o][a][b][i] over the pairs p = (a < b) of n (anti = 1:
+// src[o][a][b][i] - src[o][b][a][i]): src is [outer][n][n][inner], dst
+// [outer][n(n-1)/2][inner]
 void launch_pack_pairs(const double2* src, double2* dst, int64_t outer, int n, int64_t inner, const int2* pairs,
-                       hipStream_t s);
+                       hipStream_t s, int anti = 0);
 
 // adjoint helpers
 // gf[a][A] += sum_i gX[(i,a),(i,A)] (which 0) or gf[i][I] += sum_a gX[(i,a),(I,a)] (which 1)

@@ -1706,20 +1706,27 @@ void launch_pack_ee_half(const double2* A0, const double2* A1, const double2* A2
 
 // dst[o][p(a<b)][i] = src[o][a][b][i] for src [outer][n][n][inner]
 __global__ void pack_pairs_kernel(const double2* src, double2* dst, int64_t outer, int n, int64_t inner,
-                                  const int2* pairs) {
+                                  const int2* pairs, int anti) {
   const int64_t P = (int64_t)n * (n - 1) / 2, total = outer * P * inner;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx % inner, r = idx / inner, p = r % P, o = r / P;
     const int2 ab = pairs[p];
-    dst[idx] = src[((o * n + ab.x) * n + ab.y) * inner + i];
+    double2 v = src[((o * n + ab.x) * n + ab.y) * inner + i];
+    if (anti) {
+      const double2 w = src[((o * n + ab.y) * n + ab.x) * inner + i];
+      v.x -= w.x;
+      v.y -= w.y;
+    }
+    dst[idx] = v;
   }
 }
 void launch_pack_pairs(const double2* src, double2* dst, int64_t outer, int n, int64_t inner, const int2* pairs,
-                       hipStream_t s) {
+                       hipStream_t s, int anti) {
   const int64_t total = outer * ((int64_t)n * (n - 1) / 2) * inner;
   if (total == 0) return;
-  hipLaunchKernelGGL(pack_pairs_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, src, dst, outer, n, inner, pairs);
+  hipLaunchKernelGGL(pack_pairs_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, src, dst, outer, n, inner, pairs,
+                     anti);
 }
 
 // ---------------------------------------------------------------------------
