@@ -70,6 +70,12 @@ struct Inst {
   // EE outside a tape: X1 antisymmetrised in (b,c) and packed, [o][v][P_v]
   // (X1 itself is then dropped)
   Tensor X1h;
+  // ... X2 antisymmetrised in (j,k) and packed [P_o][o][v], t pair-packed in
+  // (I,J) [P_o][v][v], and the split-bf16 planes of the ring matrix with rows
+  // (j,b) and columns (k,c) (ringKp = o*v padded to 32)
+  Tensor X2h, tIJ;
+  unsigned short* ringq = nullptr;
+  int64_t ringKp = 0;
   int2* pair_o = nullptr;
   int2* pair_v = nullptr;
   double* diag = nullptr; // device zeroth-order diagonal [dim]
@@ -516,7 +522,7 @@ void small_m11(adc_handle* h, Inst& I, Tensor& f2, Tensor& f3, const std::vector
 // ============================================================================
 // EE
 // ============================================================================
-void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* X1h);
+void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* X1h, Tensor* X2h);
 
 void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   Ctx& cx = *I.cx;
@@ -677,7 +683,7 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     Tensor g = tslice(I.E1, 3, o + v, 2 * o + v);
     perm(cx, C1(), I.W, "IJiA", true, C0(), g, "IJAi");
   }
-  build_sx(cx, I, I.x, I.X1, I.X2, cx.tape ? nullptr : &I.X1h);
+  build_sx(cx, I, I.x, I.X1, I.X2, cx.tape ? nullptr : &I.X1h, cx.tape ? nullptr : &I.X2h);
   if (!cx.tape) {
     // A0 is antisymmetric in (a,b) and A1 in (I,J) (so are all their terms):
     // their factors are kept with that pair packed
@@ -688,6 +694,17 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     launch_pack_pairs(I.E1.p, I.E1h.p, 1, o, (int64_t)v * (2 * o + v), I.pair_o, cx.stream);
     I.th = tnew(cx, {o, o, Pv}, false);
     launch_pack_pairs(t.p, I.th.p, (int64_t)o * o, v, 1, I.pair_v, cx.stream);
+    I.tIJ = tnew(cx, {Po, v, v}, false);
+    launch_pack_pairs(t.p, I.tIJ.p, 1, o, (int64_t)v * v, I.pair_o, cx.stream);
+    // planes of the ring matrix [k][c][j][b]: rows (j,b), columns (k,c)
+    const int64_t ov = (int64_t)o * v;
+    I.ringKp = pad32(ov);
+    I.ringq = (unsigned short*)dmalloc(h, (size_t)ov * I.ringKp * 8);
+    SplitNd sp{};
+    sp.src = I.ring.p; sp.dst = I.ringq; sp.rows = ov; sp.K = ov; sp.Kp = I.ringKp; sp.conj = 0;
+    sp.nm = 2; sp.md[0] = o; sp.md[1] = v; sp.ms[0] = v; sp.ms[1] = 1;
+    sp.nk = 2; sp.kd[0] = o; sp.kd[1] = v; sp.ks[0] = (int64_t)v * o * v; sp.ks[1] = ov;
+    launch_split_nd(sp, 1, cx.stream);
     tfree(cx, I.E0);
     tfree(cx, I.E1);
   }
@@ -704,7 +721,7 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
 //   EA: X1_IaAB = -1/2 ovvv_IaAB + x W5_IAaB
 // (the M12(1) terms and the M12(2) terms in W, W5, W6).  x enters here, so a
 // change of x needs new factors.
-void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* X1h) {
+void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* X1h, Tensor* X2h) {
   const int o = I.o, v = I.v;
   if (I.kind == ADC_EE) {
     X1 = tnew(cx, {o, v, v, v}, false);
@@ -720,6 +737,12 @@ void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* 
     perm(cx, CR(-0.5), I.ooov, "jkib", false, C0(), X2, "jkib");
     perm(cx, CR(-0.25 * x), I.W, "jkib", false, C1(), X2, "jkib");
     perm(cx, CR(x), I.W6, "jbki", false, C1(), X2, "jkib");
+    if (X2h) {
+      // likewise sum_jk X2_jk Y_jk = sum_{j<k} (X2_jk - X2_kj) Y_jk
+      *X2h = tnew(cx, {I.Po, o, v}, false);
+      launch_pack_pairs(X2.p, X2h->p, 1, o, (int64_t)o * v, I.pair_o, cx.stream, 1);
+      tfree(cx, X2);
+    }
   } else if (I.kind == ADC_IP) {
     X1 = tnew(cx, {o, o, o, v}, false);
     perm(cx, CR(0.5), I.ooov, "IJiA", false, C0(), X1, "IJiA");
@@ -747,7 +770,7 @@ void ip_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   ctr(cx, C1(), t, "IJcd", true, I.ovvv, "iBcd", true, C0(), I.W, "IJiB");
   I.W6 = tnew(cx, {o, I.v, o, o}, false);
   ctr(cx, C1(), t, "IkBc", true, I.ooov, "ikJc", true, C0(), I.W6, "IBJi");
-  build_sx(cx, I, I.x, I.X1, I.X2, nullptr);
+  build_sx(cx, I, I.x, I.X1, I.X2, nullptr, nullptr);
   // the sigma build of IP needs no three-external integrals
   tfree(cx, I.ovvv);
 }
@@ -765,7 +788,7 @@ void ea_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
   const Tensor& t = I.t1;
   I.W5 = tnew(cx, {o, v, v, v}, false);
   ctr(cx, C1(), t, "JkAc", true, I.ovvv, "kBac", true, C0(), I.W5, "JAaB");
-  build_sx(cx, I, I.x, I.X1, I.X2, nullptr);
+  build_sx(cx, I, I.x, I.X1, I.X2, nullptr, nullptr);
 }
 
 void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
@@ -777,27 +800,34 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   cx.prec = prec;
   Tensor ys = tnew(cx, {k, o, v}, false);
   rows_in(cx, Y, dim, 0, ys, k, n1);
-  Tensor Ya = tnew(cx, {k, o, o, v, v}, false);
-  SplitScope scope(cx, {{Ya.p, Ya.size()}, {ys.p, ys.size()}});
   // outside a tape the terms that sum over an antisymmetric pair of Y take it
-  // once (pairs packed, factors antisymmetrised at init): see E0h, th, X1h
+  // once (pairs packed, factors antisymmetrised at init): see E0h, th, X1h;
+  // there the fully unpacked Y is needed only by the ring term outside
+  // split-bf16 (which forms its planes straight from the packed vectors)
   const bool half = I.E0h.p && !cx.tape;
   const int64_t Pv = I.Pv;
+  const bool ring_planes = half && prec == ADC_SPLIT_BF16 && I.ringq;
+  const bool need_Ya = !half || (x != 0.0 && !ring_planes);
+  Tensor Ya = need_Ya ? tnew(cx, {k, o, o, v, v}, false) : Tensor{};
+  SplitScope scope(cx, {{Ya.p, Ya.size()}, {ys.p, ys.size()}});
   // split-bf16: the unpack also writes the planes of Y in its own order (the
   // layout of the contractions summing over (j,b,c) or (a,b) with rows
   // (z,i[,j])), when that layout needs no K padding
   unsigned short* yq = nullptr;
   if (!half && prec == ADC_SPLIT_BF16 && scope.id > 0 && ((int64_t)v * v) % 32 == 0)
     yq = (unsigned short*)cx.pool.get(Ya.size() / 2);
-  launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream, yq);
+  if (need_Ya) launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream, yq);
   if (yq) split_cache_put(cx, scope.id, Ya.p, Ya.size(), yq);
-  // the doubles unpacked in the occupied pair only, virtual pairs a<b kept
-  Tensor Yh;
+  // the doubles unpacked in the occupied pair only (virtual pairs a<b kept),
+  // and in the virtual pair only (occupied pairs i<j kept)
+  Tensor Yh, Yij;
   if (half) {
     Yh = tnew(cx, {k, o, o, Pv}, false);
     launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, Yh.p, nullptr, cx.stream);
+    Yij = tnew(cx, {k, Po, v, v}, false);
+    launch_unpack_doubles(2, Y, dim, n1, k, (int)Po, v, Yij.p, nullptr, cx.stream);
   }
-  SplitScope hscope(cx, {{Yh.p, Yh.size()}});
+  SplitScope hscope(cx, {{Yh.p, Yh.size()}, {Yij.p, Yij.size()}});
   const Tensor& t = I.t1;
 
   // ---------------- singles output
@@ -814,15 +844,20 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // M12(1) -1/2 <ja||bc> Y_ijbc - 1/2 <jk||ib> Y_jkab with the M12(2) terms
   // x W5_JAaB Y_iJAB - x/4 W_IJiB Y_IJaB + x W6_IBJi Y_IJaB, one contraction
   // per layout of Y through the factors X1, X2
-  if (half) ctr(cx, C1(), I.X1h, "jaP", false, Yh, "zijP", false, C1(), s1, "zia");
-  else ctr(cx, C1(), I.X1, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
-  ctr(cx, C1(), I.X2, "jkib", false, Ya, "zjkab", false, C1(), s1, "zia");
+  if (half) {
+    ctr(cx, C1(), I.X1h, "jaP", false, Yh, "zijP", false, C1(), s1, "zia");
+    ctr(cx, C1(), I.X2h, "Pib", false, Yij, "zPab", false, C1(), s1, "zia");
+  } else {
+    ctr(cx, C1(), I.X1, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
+    ctr(cx, C1(), I.X2, "jkib", false, Ya, "zjkab", false, C1(), s1, "zia");
+  }
   if (x != 0.0) {
     // M12(2), grouped with the antisymmetric Y
     Tensor rY = tnew(cx, {k, v, v}, false);
     // Y is antisymmetric in its virtual pair: read it as Y_IJBA = -Y_IJAB so
     // that it shares the layout (kept virtual first) of the M12(1) term above
-    ctr(cx, CR(-1.0), t, "IJAc", true, Ya, "zIJBA", false, C0(), rY, "zcB");
+    if (half) ctr(cx, CR(-2.0), I.tIJ, "PAc", true, Yij, "zPBA", false, C0(), rY, "zcB");
+    else ctr(cx, CR(-1.0), t, "IJAc", true, Ya, "zIJBA", false, C0(), rY, "zcB");
     ctr(cx, CR(0.5 * x), I.ovvv, "iBac", true, rY, "zcB", false, C1(), s1, "zia");
     tfree(cx, rY);
     Tensor r2 = tnew(cx, {k, o, o}, false);
@@ -910,7 +945,25 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     } else {
       ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
     }
-    ctr(cx, CR(-x), Ya, "zikac", false, I.ring, "kcjb", false, C1(), A2, "zijab");
+    if (ring_planes) {
+      // A2[z][i][j][a][b] -= x sum_kc Y_ikac ring[k][c][j][b] on the planes
+      const int64_t ov = (int64_t)o * v, rows = (int64_t)k * ov;
+      unsigned short* Rq = (unsigned short*)cx.pool.get((rows * I.ringKp * 8 + 15) / 16);
+      launch_ee_ring_planes(Y, dim, n1, k, o, v, Rq, I.ringKp, cx.stream);
+      BfGemm g{};
+      g.M = rows; g.N = ov; g.Kp = I.ringKp;
+      g.A = Rq; g.lda = rows;
+      g.B = I.ringq; g.ldb = ov;
+      g.C = A2.p; g.c32 = A2.f32 ? 1 : 0;
+      g.om.nm = 3; g.om.md[0] = k; g.om.md[1] = o; g.om.md[2] = v;
+      g.om.ms[0] = (int64_t)o * o * v * v; g.om.ms[1] = (int64_t)o * v * v; g.om.ms[2] = v;
+      g.om.nn = 2; g.om.nd[0] = o; g.om.nd[1] = v; g.om.ns[0] = (int64_t)v * v; g.om.ns[1] = 1;
+      g.alpha = CR(-x); g.beta = C1(); g.tag = 0;
+      gemm_bf16p(cx, g);
+      cx.pool.put((double2*)Rq);
+    } else {
+      ctr(cx, CR(-x), Ya, "zikac", false, I.ring, "kcjb", false, C1(), A2, "zijab");
+    }
   }
   if (half) {
     launch_pack_ee_half(A0.p, A1.p, A2.p, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v, cx.stream,
@@ -922,8 +975,9 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   tfree(cx, A1);
   if (A2.p) tfree(cx, A2);
   rows_out(cx, s1, S, dim, 0, k, n1, C0());
-  for (Tensor* p : {&ys, &Ya, &s1}) tfree(cx, *p);
-  if (Yh.p) tfree(cx, Yh);
+  for (Tensor* p : {&ys, &s1}) tfree(cx, *p);
+  for (Tensor* p : {&Ya, &Yh, &Yij})
+    if (p->p) tfree(cx, *p);
   cx.prec = saved;
 }
 
@@ -1148,7 +1202,7 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   // planes are kept per layout (at most their own size in bytes) and reused
   // by every sigma build
   for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1,
-                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h})
+                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h, &I.X2h, &I.tIJ})
     if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {
@@ -1723,17 +1777,19 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     std::swap(I.M11x, Mx);
     const double x0 = I.x;
     // the singles-coupling factors at x + 1 (the frozen ones stay untouched)
-    Tensor X1b, X2b, X1hb;
-    build_sx(cx, I, x0 + 1.0, X1b, X2b, I.X1h.p ? &X1hb : nullptr);
-    std::swap(I.X1, X1b);
-    std::swap(I.X2, X2b);
-    std::swap(I.X1h, X1hb);
-    auto restore = [&]() {
-      I.x = x0;
-      std::swap(I.M11x, Mx);
+    Tensor X1b, X2b, X1hb, X2hb;
+    build_sx(cx, I, x0 + 1.0, X1b, X2b, I.X1h.p ? &X1hb : nullptr, I.X2h.p ? &X2hb : nullptr);
+    auto swap_all = [&]() {
       std::swap(I.X1, X1b);
       std::swap(I.X2, X2b);
       std::swap(I.X1h, X1hb);
+      std::swap(I.X2h, X2hb);
+    };
+    swap_all();
+    auto restore = [&]() {
+      I.x = x0;
+      std::swap(I.M11x, Mx);
+      swap_all();
     };
     I.x = x0 + 1.0;
     try {
@@ -1744,7 +1800,7 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     }
     restore();
     tfree(cx, Mx);
-    for (Tensor* t : {&X1b, &X2b, &X1hb})
+    for (Tensor* t : {&X1b, &X2b, &X1hb, &X2hb})
       if (t->p) tfree(cx, *t);
     perm(cx, CR(-1), S0, "zp", false, C1(), S1, "zp");
     Tensor Sb = tensor_view(const_cast<double2*>(Sbar), {1, (int64_t)k * dim}, {});

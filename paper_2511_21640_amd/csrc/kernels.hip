@@ -1422,6 +1422,39 @@ void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off,
                      nv, Ya, Yp, planes);
 }
 
+// Split-bf16 planes [4][rows][Kp] of the EE doubles unpacked in the ring
+// layout, straight from the packed vectors: row (z,i,a), column (k,c) holds
+// Y_ikac = sign * Y[z][pair(i,k)][pair(a,c)] (zero for i = k or a = c, and
+// for columns o*v <= q < Kp)
+__global__ __launch_bounds__(256) void ee_ring_planes_kernel(const double2* Y, int64_t ldY, int64_t off, int k,
+                                                             int no, int nv, unsigned short* dst, int64_t Kp) {
+  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+  const int64_t rows = (int64_t)k * no * nv, total = rows * Kp, ov = (int64_t)no * nv;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / Kp, q = idx - r * Kp;
+    double2 val = make_double2(0.0, 0.0);
+    if (q < ov) {
+      const int64_t a = r % nv, zi = r / nv, i = zi % no, z = zi / no;
+      const int64_t kk = q / nv, c = q - kk * nv;
+      if (i != kk && a != c) {
+        const int64_t i0 = i < kk ? i : kk, k0 = i < kk ? kk : i, a0 = a < c ? a : c, c0 = a < c ? c : a;
+        const double sgn = ((i > kk) != (a > c)) ? -1.0 : 1.0;
+        const double2 y = Y[z * ldY + off + pidx(i0, k0, no) * Pv + pidx(a0, c0, nv)];
+        val = make_double2(sgn * y.x, sgn * y.y);
+      }
+    }
+    put_planes(dst, total, idx, val, 0);
+  }
+}
+void launch_ee_ring_planes(const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, unsigned short* dst,
+                           int64_t Kp, hipStream_t s) {
+  const int64_t total = (int64_t)k * no * nv * Kp;
+  if (total == 0) return;
+  hipLaunchKernelGGL(ee_ring_planes_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Y, ldY, off, k, no, nv, dst,
+                     Kp);
+}
+
 // pack: one thread per packed element; po/pv are the pair tables of o and v
 __global__ void pack_doubles_kernel(int kind, const double2* U, double2* S, const double2* Y, int64_t ld, int64_t off,
                                     int k, int no, int nv, const double* eps, cplx alpha, int accumulate,
