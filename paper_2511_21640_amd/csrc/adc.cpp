@@ -74,6 +74,7 @@ struct Inst {
   // (I,J) [P_o][v][v], and the split-bf16 planes of the ring matrix with rows
   // (j,b) and columns (k,c) (ringKp = o*v padded to 32)
   Tensor X2h, tIJ;
+  Tensor oooo_p;  // <kl||ij> with the pair (k<l) packed, [P_o][o][o]
   unsigned short* ringq = nullptr;
   int64_t ringKp = 0;
   int2* pair_o = nullptr;
@@ -196,18 +197,20 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   nb = std::min(nb, std::max(16, (v + 7) / 8));
   nb = std::min(nb, v - 1);
   double2* Wbuf = cx.pool.get((int64_t)nb * v * v * v);
-  // the k vectors' rows are stacked into one [k*nrow][Pv] operand (M = k*nrow)
+  // the k vectors' rows are stacked into one [k*nrow][Pv] operand (M = k*nrow);
+  // split-bf16 splits them straight from Y and writes S through an output
+  // map, the other precisions stage them in Yc, Sc
   const int64_t R = (int64_t)k * nrow;
-  double2* Yc = cx.pool.get(R * Pv);
-  double2* Sc = cx.pool.get(R * Pv);
-  {
+  const bool bf = prec == ADC_SPLIT_BF16;
+  double2* Yc = bf ? nullptr : cx.pool.get(R * Pv);
+  double2* Sc = bf ? nullptr : cx.pool.get(R * Pv);
+  if (!bf) {
     int64_t od[2] = {k, nrow * Pv}, is[2] = {ldY, 1}, os[2] = {nrow * Pv, 1};
     launch_permute(2, od, is, os, Y + offY, Yc, C1(), C0(), 0, cx.stream);
   }
   // packed <ab||cd> rows of several a-blocks are collected (up to a quarter of
   // the workspace) and contracted with the trial vectors in one GEMM, so that
   // the contraction runs on large N even where the a-blocks are small
-  const bool bf = prec == ADC_SPLIT_BF16;
   const int64_t Kv = pad32(Pv);
   const int64_t row_bytes = bf ? Kv * 8 : Pv * (int64_t)sizeof(double2);
   const int64_t max_np = (int64_t)nb * (v - 1);
@@ -219,7 +222,11 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     ensure_planes(h, I);
     Yp = planes_alloc(cx, R, Kv);
     Vp = planes_alloc(cx, grp, Kv);
-    launch_split_planes(Yc, R, Pv, Pv, 1, 0, Yp, Kv, cx.stream);
+    SplitNd sp{};
+    sp.src = Y + offY; sp.dst = Yp; sp.rows = R; sp.K = Pv; sp.Kp = Kv; sp.conj = 0;
+    sp.nm = 2; sp.md[0] = k; sp.md[1] = nrow; sp.ms[0] = ldY; sp.ms[1] = Pv;
+    sp.nk = 1; sp.kd[0] = Pv; sp.ks[0] = 1;
+    launch_split_nd(sp, 0, cx.stream);
   } else {
     Vbuf = cx.pool.get(grp * Pv);
   }
@@ -231,8 +238,10 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
       c.M = R; c.N = gfill; c.Kp = Kv;
       c.A = Yp; c.lda = R;
       c.B = Vp; c.ldb = grp;
-      c.C = Sc + gbase; c.scm = Pv; c.scn = 1;
-      c.alpha = C1(); c.beta = C0(); c.tag = 2;
+      // S[z][offS + r*Pv + gbase + q] += alpha * (...)
+      c.C = S + offS + gbase; c.scn = 1;
+      c.om.nm = 2; c.om.md[0] = k; c.om.md[1] = nrow; c.om.ms[0] = ldS; c.om.ms[1] = Pv;
+      c.alpha = alpha; c.beta = C1(); c.tag = 2;
       gemm_bf16p(cx, c);
     } else {
       // Sc[r][gbase + q] = sum_cd Yc[r][cd] V[q][cd]
@@ -320,13 +329,13 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   if (Yp) cx.pool.put((double2*)Yp);
   if (Vp) cx.pool.put((double2*)Vp);
   if (Vbuf) cx.pool.put(Vbuf);
-  {
+  if (!bf) {
     int64_t od[2] = {k, nrow * Pv}, is[2] = {nrow * Pv, 1}, os[2] = {ldS, 1};
     launch_permute(2, od, is, os, Sc, S + offS, alpha, C1(), 0, cx.stream);
+    cx.pool.put(Yc);
+    cx.pool.put(Sc);
   }
   cx.pool.put(Wbuf);
-  cx.pool.put(Yc);
-  cx.pool.put(Sc);
 }
 
 // the unpacked trial vectors of one sigma build stay unchanged until the
@@ -696,6 +705,8 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     launch_pack_pairs(t.p, I.th.p, (int64_t)o * o, v, 1, I.pair_v, cx.stream);
     I.tIJ = tnew(cx, {Po, v, v}, false);
     launch_pack_pairs(t.p, I.tIJ.p, 1, o, (int64_t)v * v, I.pair_o, cx.stream);
+    I.oooo_p = tnew(cx, {Po, o, o}, false);
+    launch_pack_pairs(I.oooo.p, I.oooo_p.p, 1, o, (int64_t)o * o, I.pair_o, cx.stream);
     // planes of the ring matrix [k][c][j][b]: rows (j,b), columns (k,c)
     const int64_t ov = (int64_t)o * v;
     I.ringKp = pad32(ov);
@@ -941,7 +952,10 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
     // through P(ij)) and ring; the particle ladder runs packed below
     if (half) {
-      ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Yh, "zklP", false, C1(), A0, "zijP");
+      // both factors antisymmetric in (k,l): the pairs k<l twice, read from
+      // the packed doubles
+      Tensor Yp = tensor_view(const_cast<double2*>(Y) + n1, {k, Po, Pv}, {dim, Pv, 1});
+      ctr(cx, CR(0.5 * x), I.oooo_p, "Kij", false, Yp, "zKP", false, C1(), A0, "zijP");
     } else {
       ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
     }
@@ -1202,7 +1216,7 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   // planes are kept per layout (at most their own size in bytes) and reused
   // by every sigma build
   for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1,
-                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h, &I.X2h, &I.tIJ})
+                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h, &I.X2h, &I.tIJ, &I.oooo_p})
     if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {

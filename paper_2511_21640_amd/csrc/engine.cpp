@@ -976,8 +976,17 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   }
   if (Kn == 0) {
     // empty sum: C = beta C
-    if (C.f32) throw std::logic_error("ctr: complex64 output of an empty sum");
-    if (beta.re != 1.0 || beta.im != 0.0) perm(cx, beta, C, lc, false, C0(), C, lc);
+    if (C.f32) {
+      if (beta.re == 1.0 && beta.im == 0.0) {
+        // nothing to do
+      } else if (beta.re == 0.0 && beta.im == 0.0 && C.st.empty()) {
+        launch_fill(C.p, (C.size() + 1) / 2, C0(), cx.stream);
+      } else {
+        throw std::logic_error("ctr: complex64 output of an empty sum");
+      }
+    } else if (beta.re != 1.0 || beta.im != 0.0) {
+      perm(cx, beta, C, lc, false, C0(), C, lc);
+    }
   } else {
     // ---- output
     const int64_t sbt = fused_stride(vc, bat);
