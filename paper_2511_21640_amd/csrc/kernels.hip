@@ -897,7 +897,7 @@ int bf16p_pick_tile(const BfGemm& h) {
 }
 
 // tile: 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128 (rows x cols of C,
-// four waves), 4 = 128x128 and 5 = 128x64 with eight waves, 6-9 the direct-
+// four waves), 4 = 128x128 and 5 = 128x64 with eight waves, 6-11 the direct-
 // load kernels (zgemm_bf16d_kernel); negative = bf16p_pick_tile
 void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
@@ -915,6 +915,8 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
     case 7: launch_bf16d_tile<4, 2, 2, 2>(h, s); break;  // 128 x 64, 4 waves, direct LDS loads
     case 8: launch_bf16d_tile<4, 4, 2, 2>(h, s); break;  // 128 x 128, 4 waves, direct LDS loads
     case 9: launch_bf16d_tile<2, 2, 4, 4>(h, s); break;  // 128 x 128, 16 waves, direct LDS loads
+    case 10: launch_bf16d_tile<2, 2, 2, 2>(h, s); break;  // 64 x 64, 4 waves, direct LDS loads
+    case 11: launch_bf16d_tile<2, 2, 4, 2>(h, s); break;  // 128 x 64, 8 waves, direct LDS loads
     default: launch_bf16p_tile<2, 2>(h, s); break;
   }
 }
