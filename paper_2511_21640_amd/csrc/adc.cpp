@@ -75,6 +75,8 @@ struct Inst {
   // (j,b) and columns (k,c) (ringKp = o*v padded to 32)
   Tensor X2h, tIJ;
   Tensor oooo_p;  // <kl||ij> with the pair (k<l) packed, [P_o][o][o]
+  Tensor ooov_p;  // <kl||ja> with the pair (k<l) packed, [P_o][o][v]
+  Tensor tpp;     // t1 with both pairs packed, [P_o][P_v]
   unsigned short* ringq = nullptr;
   int64_t ringKp = 0;
   int2* pair_o = nullptr;
@@ -707,6 +709,10 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     launch_pack_pairs(t.p, I.tIJ.p, 1, o, (int64_t)v * v, I.pair_o, cx.stream);
     I.oooo_p = tnew(cx, {Po, o, o}, false);
     launch_pack_pairs(I.oooo.p, I.oooo_p.p, 1, o, (int64_t)o * o, I.pair_o, cx.stream);
+    I.ooov_p = tnew(cx, {Po, o, v}, false);
+    launch_pack_pairs(I.ooov.p, I.ooov_p.p, 1, o, (int64_t)o * v, I.pair_o, cx.stream);
+    I.tpp = tnew(cx, {Po, Pv}, false);
+    launch_pack_pairs(I.th.p, I.tpp.p, 1, o, Pv, I.pair_o, cx.stream);
     // planes of the ring matrix [k][c][j][b]: rows (j,b), columns (k,c)
     const int64_t ov = (int64_t)o * v;
     I.ringKp = pad32(ov);
@@ -942,11 +948,18 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     tfree(cx, B1);
   }
   if (x != 0.0) {
-    Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
-    ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
-    if (half) ctr(cx, CR(-0.5 * x), I.th, "klP", false, Z4, "zklJI", false, C1(), A0, "zIJP");
-    else ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
-    tfree(cx, Z4);
+    if (half) {
+      // Z4 and t are both antisymmetric in (k,l): the pairs k<l twice
+      Tensor Z4 = tnew(cx, {k, Po, o, o}, false);
+      ctr(cx, C1(), I.ooov_p, "KJa", false, ys, "zIa", false, C0(), Z4, "zKJI");
+      ctr(cx, CR(-x), I.tpp, "KP", false, Z4, "zKJI", false, C1(), A0, "zIJP");
+      tfree(cx, Z4);
+    } else {
+      Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
+      ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
+      ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
+      tfree(cx, Z4);
+    }
     ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C0(), A2, "zIJAB");
     ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
@@ -1216,7 +1229,7 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   // planes are kept per layout (at most their own size in bytes) and reused
   // by every sigma build
   for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1,
-                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h, &I.X2h, &I.tIJ, &I.oooo_p})
+                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h, &I.X2h, &I.tIJ, &I.oooo_p, &I.ooov_p, &I.tpp})
     if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {
