@@ -820,7 +820,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // outside a tape the terms that sum over an antisymmetric pair of Y take it
   // once (pairs packed, factors antisymmetrised at init): see E0h, th, X1h;
   // there the fully unpacked Y is needed only by the ring term outside
-  // split-bf16 (which forms its planes straight from the packed vectors)
+  // split-bf16 (which forms its planes from Yij below)
   const bool half = I.E0h.p && !cx.tape;
   const int64_t Pv = I.Pv;
   const bool ring_planes = half && prec == ADC_SPLIT_BF16 && I.ringq;
@@ -976,7 +976,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       // A2[z][i][j][a][b] -= x sum_kc Y_ikac ring[k][c][j][b] on the planes
       const int64_t ov = (int64_t)o * v, rows = (int64_t)k * ov;
       unsigned short* Rq = (unsigned short*)cx.pool.get((rows * I.ringKp * 8 + 15) / 16);
-      launch_ee_ring_planes(Y, dim, n1, k, o, v, Rq, I.ringKp, cx.stream);
+      launch_ee_ring_planes(Yij.p, k, o, v, Rq, I.ringKp, cx.stream);
       BfGemm g{};
       g.M = rows; g.N = ov; g.Kp = I.ringKp;
       g.A = Rq; g.lda = rows;

@@ -133,9 +133,10 @@ void launch_div_d1(double2* t, const double* eps, int no, int nv, hipStream_t s)
 // kind: 0 EE [k][o][o][v][v], 1 IP [k][o][o][v], 2 EA [k][o][v][v].
 // unpack: Ya antisymmetric in every pair; Yp (optional) zero except packed positions.
 // split-bf16 planes [4][k*o*v][Kp] of the EE doubles in the ring layout
-// (rows (z,i,a), columns (k,c) < o*v, zero beyond), from the packed vectors
-void launch_ee_ring_planes(const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, unsigned short* dst,
-                           int64_t Kp, hipStream_t s);
+// (rows (z,i,a), columns (k,c) < o*v, zero beyond), from the doubles with the
+// occupied pair packed, Yij [k][P_o][v][v]
+void launch_ee_ring_planes(const double2* Yij, int k, int no, int nv, unsigned short* dst, int64_t Kp,
+                           hipStream_t s);
 // planes (optional): split-bf16 planes [4][total] of Ya in its own order
 void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv,
                            double2* Ya, double2* Yp, hipStream_t s, unsigned short* planes = nullptr);

@@ -1426,12 +1426,13 @@ void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off,
 }
 
 // Split-bf16 planes [4][rows][Kp] of the EE doubles unpacked in the ring
-// layout, straight from the packed vectors: row (z,i,a), column (k,c) holds
-// Y_ikac = sign * Y[z][pair(i,k)][pair(a,c)] (zero for i = k or a = c, and
-// for columns o*v <= q < Kp)
-__global__ __launch_bounds__(256) void ee_ring_planes_kernel(const double2* Y, int64_t ldY, int64_t off, int k,
-                                                             int no, int nv, unsigned short* dst, int64_t Kp) {
-  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+// layout: row (z,i,a), column (k,c) holds Y_ikac (zero for i = k, and for
+// columns o*v <= q < Kp)
+// Yij [k][P_o][v][v] holds Y with the occupied pair packed: Y_ikac =
+// sign(i,k) * Yij[z][pair(i,k)][a][c], read along c
+__global__ __launch_bounds__(256) void ee_ring_planes_kernel(const double2* Yij, int k, int no, int nv,
+                                                             unsigned short* dst, int64_t Kp) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2;
   const int64_t rows = (int64_t)k * no * nv, total = rows * Kp, ov = (int64_t)no * nv;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
@@ -1440,22 +1441,20 @@ __global__ __launch_bounds__(256) void ee_ring_planes_kernel(const double2* Y, i
     if (q < ov) {
       const int64_t a = r % nv, zi = r / nv, i = zi % no, z = zi / no;
       const int64_t kk = q / nv, c = q - kk * nv;
-      if (i != kk && a != c) {
-        const int64_t i0 = i < kk ? i : kk, k0 = i < kk ? kk : i, a0 = a < c ? a : c, c0 = a < c ? c : a;
-        const double sgn = ((i > kk) != (a > c)) ? -1.0 : 1.0;
-        const double2 y = Y[z * ldY + off + pidx(i0, k0, no) * Pv + pidx(a0, c0, nv)];
-        val = make_double2(sgn * y.x, sgn * y.y);
+      if (i != kk) {
+        const int64_t i0 = i < kk ? i : kk, k0 = i < kk ? kk : i;
+        const double2 y = Yij[((z * Po + pidx(i0, k0, no)) * nv + a) * nv + c];
+        val = i > kk ? make_double2(-y.x, -y.y) : y;
       }
     }
     put_planes(dst, total, idx, val, 0);
   }
 }
-void launch_ee_ring_planes(const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, unsigned short* dst,
-                           int64_t Kp, hipStream_t s) {
+void launch_ee_ring_planes(const double2* Yij, int k, int no, int nv, unsigned short* dst, int64_t Kp,
+                           hipStream_t s) {
   const int64_t total = (int64_t)k * no * nv * Kp;
   if (total == 0) return;
-  hipLaunchKernelGGL(ee_ring_planes_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Y, ldY, off, k, no, nv, dst,
-                     Kp);
+  hipLaunchKernelGGL(ee_ring_planes_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Yij, k, no, nv, dst, Kp);
 }
 
 // pack: one thread per packed element; po/pv are the pair tables of o and v
@@ -1697,47 +1696,74 @@ void launch_pack_ee(const double2* A0, const double2* A1, const double2* A2, dou
 template <class AT>
 __global__ __launch_bounds__(256) void pack_ee_half_kernel(const AT* A0, const AT* A1, const AT* A2, double2* S,
                                                            const double2* Y, int64_t ld, int64_t off, int k, int no,
-                                                           int nv, const double* eps, const int2* po,
-                                                           const int2* pv) {
+                                                           int nv, const double* eps, const int2* po) {
+  // one block per (z, pair ij, 16x16 tile (ta <= tb) of (a, b)); the
+  // transposed reads A1[..][b][a], A2[..][b][a] go through LDS
+  __shared__ AT t1[16][17], t2[16][17], t3[16][17];
   const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
-  const int64_t n2 = Po * Pv, total = n2 * k;
-  const int64_t per0 = (int64_t)no * no * Pv, per1 = Po * nv * nv, per2 = (int64_t)no * no * nv * nv;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t z = idx / n2, q = idx - z * n2;
-    const int64_t pij = q / Pv, pab = q - pij * Pv;
-    const int2 ij = po[pij], ab = pv[pab];
-    AT a = A0[z * per0 + ((int64_t)ij.x * no + ij.y) * Pv + pab], c = A0[z * per0 + ((int64_t)ij.y * no + ij.x) * Pv + pab];
-    double rx = (double)a.x - (double)c.x, ry = (double)a.y - (double)c.y;
-    a = A1[z * per1 + (pij * nv + ab.x) * nv + ab.y];
-    c = A1[z * per1 + (pij * nv + ab.y) * nv + ab.x];
-    rx += (double)a.x - (double)c.x;
-    ry += (double)a.y - (double)c.y;
-    if (A2) {
-      const int64_t b0 = z * per2;
-      const AT w1 = A2[b0 + (((int64_t)ij.x * no + ij.y) * nv + ab.x) * nv + ab.y];
-      const AT w2 = A2[b0 + (((int64_t)ij.y * no + ij.x) * nv + ab.x) * nv + ab.y];
-      const AT w3 = A2[b0 + (((int64_t)ij.x * no + ij.y) * nv + ab.y) * nv + ab.x];
-      const AT w4 = A2[b0 + (((int64_t)ij.y * no + ij.x) * nv + ab.y) * nv + ab.x];
-      rx += (double)w1.x - (double)w2.x - (double)w3.x + (double)w4.x;
-      ry += (double)w1.y - (double)w2.y - (double)w3.y + (double)w4.y;
+  const int nt = (nv + 15) / 16;
+  const int64_t ntile = (int64_t)nt * (nt + 1) / 2;
+  const int64_t blk = blockIdx.x;
+  const int64_t tile = blk % ntile, zp = blk / ntile, pij = zp % Po, z = zp / Po;
+  int ta = 0;
+  {
+    int64_t rem = tile;
+    while (rem >= nt - ta) { rem -= nt - ta; ++ta; }
+    const int tb = ta + (int)rem;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int2 ij = po[pij];
+    const int64_t per0 = (int64_t)no * no * Pv, per1 = Po * nv * nv, per2 = (int64_t)no * no * nv * nv;
+    const int64_t b1 = z * per1 + pij * nv * nv;
+    const int64_t b2ij = z * per2 + ((int64_t)ij.x * no + ij.y) * nv * nv;
+    const int64_t b2ji = z * per2 + ((int64_t)ij.y * no + ij.x) * nv * nv;
+    // transposed blocks: rows b of tile tb, columns a of tile ta
+    {
+      const int bb = 16 * tb + ty, aa = 16 * ta + tx;
+      AT zero;
+      zero.x = 0; zero.y = 0;
+      const bool in = bb < nv && aa < nv;
+      t1[ty][tx] = in ? A1[b1 + (int64_t)bb * nv + aa] : zero;
+      if (A2) {
+        t2[ty][tx] = in ? A2[b2ij + (int64_t)bb * nv + aa] : zero;
+        t3[ty][tx] = in ? A2[b2ji + (int64_t)bb * nv + aa] : zero;
+      }
     }
-    const double D = eps[no + ab.x] + eps[no + ab.y] - eps[ij.x] - eps[ij.y];
-    const double2 y = Y[z * ld + off + q];
-    S[z * ld + off + q] = make_double2(rx + D * y.x, ry + D * y.y);
+    __syncthreads();
+    const int a = 16 * ta + ty, b = 16 * tb + tx;
+    if (a < nv && b < nv && a < b) {
+      const int64_t pab = (int64_t)a * (2 * nv - a - 1) / 2 + (b - a - 1);
+      const AT x0 = A0[z * per0 + ((int64_t)ij.x * no + ij.y) * Pv + pab];
+      const AT x1 = A0[z * per0 + ((int64_t)ij.y * no + ij.x) * Pv + pab];
+      const AT y0 = A1[b1 + (int64_t)a * nv + b];
+      const AT y1 = t1[tx][ty];
+      double rx = (double)x0.x - (double)x1.x + (double)y0.x - (double)y1.x;
+      double ry = (double)x0.y - (double)x1.y + (double)y0.y - (double)y1.y;
+      if (A2) {
+        const AT w1 = A2[b2ij + (int64_t)a * nv + b], w2 = A2[b2ji + (int64_t)a * nv + b];
+        const AT w3 = t2[tx][ty], w4 = t3[tx][ty];
+        rx += (double)w1.x - (double)w2.x - (double)w3.x + (double)w4.x;
+        ry += (double)w1.y - (double)w2.y - (double)w3.y + (double)w4.y;
+      }
+      const double D = eps[no + a] + eps[no + b] - eps[ij.x] - eps[ij.y];
+      const int64_t q = pij * Pv + pab;
+      const double2 y = Y[z * ld + off + q];
+      S[z * ld + off + q] = make_double2(rx + D * y.x, ry + D * y.y);
+    }
   }
 }
 void launch_pack_ee_half(const double2* A0, const double2* A1, const double2* A2, double2* S, const double2* Y,
                          int64_t ld, int64_t off, int k, int no, int nv, const double* eps, const int2* po,
                          const int2* pv, hipStream_t s, int a32) {
-  const int64_t n2 = (int64_t)no * (no - 1) / 2 * ((int64_t)nv * (nv - 1) / 2);
-  if (n2 * k == 0) return;
+  const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
+  if (Po * Pv * k == 0) return;
+  (void)pv;
+  const int64_t nt = (nv + 15) / 16, blocks = (int64_t)k * Po * (nt * (nt + 1) / 2);
   if (a32)
-    hipLaunchKernelGGL(pack_ee_half_kernel<float2>, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, (const float2*)A0,
-                       (const float2*)A1, (const float2*)A2, S, Y, ld, off, k, no, nv, eps, po, pv);
+    hipLaunchKernelGGL(pack_ee_half_kernel<float2>, dim3((unsigned)blocks), dim3(256), 0, s, (const float2*)A0,
+                       (const float2*)A1, (const float2*)A2, S, Y, ld, off, k, no, nv, eps, po);
   else
-    hipLaunchKernelGGL(pack_ee_half_kernel<double2>, dim3(nblocks(n2 * k, 256)), dim3(256), 0, s, A0, A1, A2, S, Y,
-                       ld, off, k, no, nv, eps, po, pv);
+    hipLaunchKernelGGL(pack_ee_half_kernel<double2>, dim3((unsigned)blocks), dim3(256), 0, s, A0, A1, A2, S, Y, ld,
+                       off, k, no, nv, eps, po);
 }
 
 // dst[o][p(a<b)][i] = src[o][a][b][i] for src [outer][n][n][inner]
