@@ -311,7 +311,8 @@ void gemm(Ctx& cx, GemmDesc g) {
 // partials written and read back); the matrix and operand terms overlap.
 static TuneChoice bf16_choice(int64_t M, int64_t N, int64_t Kp, bool beta) {
   struct Cand { int tile, bm, bn; double rate; int64_t slots; };
-  const Cand cand[3] = {{9, 128, 128, 0.41, 256}, {2, 128, 64, 0.35, 512}, {0, 64, 64, 0.31, 1024}};
+  const Cand cand[4] = {{9, 128, 128, 0.41, 256}, {13, 64, 256, 0.35, 256}, {2, 128, 64, 0.35, 512},
+                        {0, 64, 64, 0.31, 1024}};
   const double peak = 2.5e15, bw = 4.0e12, wbw = 3.5e12;
   TuneChoice best{0, 1};
   double tbest = -1.0;
@@ -366,7 +367,7 @@ void gemm_bf16p(Ctx& cx, BfGemm g) {
     t.C = scratch; t.scm = g.N; t.scn = 1;
     t.beta = {0.0, 0.0};
     t.om = OutMap{};
-    ch = tune(cx, candidates(heur, {0, 2, 9, 10, 11}), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
+    ch = tune(cx, candidates(heur, {0, 2, 9, 10, 11, 13}), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
     cx.pool.put(scratch);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[key] = ch;

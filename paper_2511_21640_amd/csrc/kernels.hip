@@ -882,7 +882,8 @@ int bf16p_pick_tile(const BfGemm& h) {
   // of its grid over the workgroups the chip holds at once; a tile is only
   // taken when its grid keeps at least half of those slots busy
   struct Cand { int tile, bm, bn; double rate; int64_t slots; };
-  const Cand cand[3] = {{9, 128, 128, 0.41, 256}, {2, 128, 64, 0.35, 512}, {0, 64, 64, 0.31, 1024}};
+  const Cand cand[4] = {{9, 128, 128, 0.41, 256}, {13, 64, 256, 0.35, 256}, {2, 128, 64, 0.35, 512},
+                        {0, 64, 64, 0.31, 1024}};
   const int64_t nsplit = h.nsplit < 1 ? 1 : h.nsplit;
   int tile = 0;
   double best = -1.0;
@@ -897,7 +898,7 @@ int bf16p_pick_tile(const BfGemm& h) {
 }
 
 // tile: 0 = 64x64, 1 = 128x128, 2 = 128x64, 3 = 64x128 (rows x cols of C,
-// four waves), 4 = 128x128 and 5 = 128x64 with eight waves, 6-11 the direct-
+// four waves), 4 = 128x128 and 5 = 128x64 with eight waves, 6-13 the direct-
 // load kernels (zgemm_bf16d_kernel); negative = bf16p_pick_tile
 void launch_bf16p(const BfGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.Kp <= 0) return;
@@ -917,6 +918,8 @@ void launch_bf16p(const BfGemm& g, hipStream_t s) {
     case 9: launch_bf16d_tile<2, 2, 4, 4>(h, s); break;  // 128 x 128, 16 waves, direct LDS loads
     case 10: launch_bf16d_tile<2, 2, 2, 2>(h, s); break;  // 64 x 64, 4 waves, direct LDS loads
     case 11: launch_bf16d_tile<2, 2, 4, 2>(h, s); break;  // 128 x 64, 8 waves, direct LDS loads
+    case 12: launch_bf16d_tile<2, 2, 2, 4>(h, s); break;  // 64 x 128, 8 waves, direct LDS loads
+    case 13: launch_bf16d_tile<2, 2, 2, 8>(h, s); break;  // 64 x 256, 16 waves, direct LDS loads
     default: launch_bf16p_tile<2, 2>(h, s); break;
   }
 }
