@@ -367,7 +367,7 @@ void gemm_bf16p(Ctx& cx, BfGemm g) {
     t.C = scratch; t.scm = g.N; t.scn = 1;
     t.beta = {0.0, 0.0};
     t.om = OutMap{};
-    ch = tune(cx, candidates(heur, {0, 2, 9, 10, 11, 13}), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
+    ch = tune(cx, candidates(heur, {0, 2, 9, 10, 11, 12, 13}), [&](const TuneChoice& c) { run_bf16p(cx, t, c.tile, c.nsplit); });
     cx.pool.put(scratch);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[key] = ch;
