@@ -835,16 +835,29 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     yq = (unsigned short*)cx.pool.get(Ya.size() / 2);
   if (need_Ya) launch_unpack_doubles(0, Y, dim, n1, k, o, v, Ya.p, nullptr, cx.stream, yq);
   if (yq) split_cache_put(cx, scope.id, Ya.p, Ya.size(), yq);
-  // the doubles unpacked in the occupied pair only (virtual pairs a<b kept),
-  // and in the virtual pair only (occupied pairs i<j kept)
+  // the doubles unpacked in the occupied pair only (virtual pairs a<b kept,
+  // [k][o][o][P_v]), and in the virtual pair only (occupied pairs i<j kept,
+  // [k][v][P_o][v]); every contraction reads each of them with rows (z, first
+  // index) and the rest summed, so in split-bf16 the unpack also writes those
+  // planes into the build's cache
   Tensor Yh, Yij;
   if (half) {
     Yh = tnew(cx, {k, o, o, Pv}, false);
-    launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, Yh.p, nullptr, cx.stream);
-    Yij = tnew(cx, {k, Po, v, v}, false);
-    launch_unpack_doubles(2, Y, dim, n1, k, (int)Po, v, Yij.p, nullptr, cx.stream);
+    Yij = tnew(cx, {k, v, Po, v}, false);
   }
   SplitScope hscope(cx, {{Yh.p, Yh.size()}, {Yij.p, Yij.size()}});
+  if (half) {
+    const bool fuse = prec == ADC_SPLIT_BF16 && hscope.id > 0;
+    const int64_t Kh = (int64_t)o * Pv, Kij = Po * v;
+    unsigned short* hq = fuse ? (unsigned short*)cx.pool.get(((int64_t)k * o * pad32(Kh) * 8 + 15) / 16) : nullptr;
+    unsigned short* iq = fuse ? (unsigned short*)cx.pool.get(((int64_t)k * v * pad32(Kij) * 8 + 15) / 16) : nullptr;
+    launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, Yh.p, nullptr, cx.stream, hq, Kh, pad32(Kh));
+    launch_unpack_doubles(3, Y, dim, n1, k, o, v, Yij.p, nullptr, cx.stream, iq, Kij, pad32(Kij));
+    if (fuse) {
+      split_cache_put_rows(cx, hscope.id, Yh.p, (int64_t)k * o, Kh, pad32(Kh), hq);
+      split_cache_put_rows(cx, hscope.id, Yij.p, (int64_t)k * v, Kij, pad32(Kij), iq);
+    }
+  }
   const Tensor& t = I.t1;
 
   // ---------------- singles output
@@ -863,7 +876,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   // per layout of Y through the factors X1, X2
   if (half) {
     ctr(cx, C1(), I.X1h, "jaP", false, Yh, "zijP", false, C1(), s1, "zia");
-    ctr(cx, C1(), I.X2h, "Pib", false, Yij, "zPab", false, C1(), s1, "zia");
+    ctr(cx, C1(), I.X2h, "Pib", false, Yij, "zaPb", false, C1(), s1, "zia");
   } else {
     ctr(cx, C1(), I.X1, "jabc", false, Ya, "zijbc", false, C1(), s1, "zia");
     ctr(cx, C1(), I.X2, "jkib", false, Ya, "zjkab", false, C1(), s1, "zia");
@@ -873,7 +886,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     Tensor rY = tnew(cx, {k, v, v}, false);
     // Y is antisymmetric in its virtual pair: read it as Y_IJBA = -Y_IJAB so
     // that it shares the layout (kept virtual first) of the M12(1) term above
-    if (half) ctr(cx, CR(-2.0), I.tIJ, "PAc", true, Yij, "zPBA", false, C0(), rY, "zcB");
+    if (half) ctr(cx, CR(-2.0), I.tIJ, "PAc", true, Yij, "zBPA", false, C0(), rY, "zcB");
     else ctr(cx, CR(-1.0), t, "IJAc", true, Ya, "zIJBA", false, C0(), rY, "zcB");
     ctr(cx, CR(0.5 * x), I.ovvv, "iBac", true, rY, "zcB", false, C1(), s1, "zia");
     tfree(cx, rY);

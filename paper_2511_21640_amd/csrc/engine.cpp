@@ -621,9 +621,9 @@ Tensor tslice(const Tensor& t, int dim, int64_t lo, int64_t hi) {
 // ------------------------------------------------------------------ split cache
 namespace {
 
-// the digits (size, stride) of rows then K, merged where contiguous: when K
-// needs no padding, two splits with equal lists write identical planes
-std::vector<std::pair<int64_t, int64_t>> flat_digits(const SplitNd& a) {
+// digits (size, stride), merged where contiguous
+std::vector<std::pair<int64_t, int64_t>> flat_digits(const int64_t* d0, const int64_t* s0, int n0, const int64_t* d1,
+                                                     const int64_t* s1, int n1) {
   std::vector<std::pair<int64_t, int64_t>> d;
   auto add = [&](int64_t n, int64_t st) {
     if (n == 1) return;
@@ -634,22 +634,21 @@ std::vector<std::pair<int64_t, int64_t>> flat_digits(const SplitNd& a) {
       d.push_back({n, st});
     }
   };
-  for (int q = 0; q < a.nm; ++q) add(a.md[q], a.ms[q]);
-  for (int q = 0; q < a.nk; ++q) add(a.kd[q], a.ks[q]);
+  for (int q = 0; q < n0; ++q) add(d0[q], s0[q]);
+  for (int q = 0; q < n1; ++q) add(d1[q], s1[q]);
   return d;
 }
 
+// two splits write identical planes when they read the same source in the
+// same order: rows then K as one traversal when K needs no padding, else
+// rows and K each (with equal row count, K and padding)
 bool same_layout(const SplitNd& a, const SplitNd& b) {
   if (a.src != b.src || a.conj != b.conj) return false;
   if (a.K == a.Kp && b.K == b.Kp && a.rows * a.Kp == b.rows * b.Kp)
-    return flat_digits(a) == flat_digits(b);
-  if (a.rows != b.rows || a.K != b.K || a.Kp != b.Kp || a.nm != b.nm || a.nk != b.nk)
-    return false;
-  for (int q = 0; q < a.nm; ++q)
-    if (a.md[q] != b.md[q] || a.ms[q] != b.ms[q]) return false;
-  for (int q = 0; q < a.nk; ++q)
-    if (a.kd[q] != b.kd[q] || a.ks[q] != b.ks[q]) return false;
-  return true;
+    return flat_digits(a.md, a.ms, a.nm, a.kd, a.ks, a.nk) == flat_digits(b.md, b.ms, b.nm, b.kd, b.ks, b.nk);
+  if (a.rows != b.rows || a.K != b.K || a.Kp != b.Kp) return false;
+  return flat_digits(a.md, a.ms, a.nm, nullptr, nullptr, 0) == flat_digits(b.md, b.ms, b.nm, nullptr, nullptr, 0) &&
+         flat_digits(a.kd, a.ks, a.nk, nullptr, nullptr, 0) == flat_digits(b.kd, b.ks, b.nk, nullptr, nullptr, 0);
 }
 
 // scope of the frozen range that holds every element the split reads, or -1
@@ -739,6 +738,16 @@ int split_scope_begin(Ctx& cx, const std::vector<std::pair<const double2*, int64
 
 void split_scope_end(Ctx& cx, int scope) {
   if (scope > 0) drop_scope(cx, scope);
+}
+
+void split_cache_put_rows(Ctx& cx, int scope, const double2* src, int64_t rows, int64_t K, int64_t Kp,
+                          unsigned short* planes) {
+  SplitNd key{};
+  key.src = src;
+  key.rows = rows; key.K = K; key.Kp = Kp;
+  key.nm = 1; key.md[0] = rows; key.ms[0] = K;
+  key.nk = 1; key.kd[0] = K; key.ks[0] = 1;
+  cx.scache.entries.push_back({key, planes, rows * Kp * 8, scope});
 }
 
 void split_cache_put(Ctx& cx, int scope, const double2* src, int64_t n, unsigned short* planes) {

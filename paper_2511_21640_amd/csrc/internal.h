@@ -137,9 +137,15 @@ void launch_div_d1(double2* t, const double* eps, int no, int nv, hipStream_t s)
 // occupied pair packed, Yij [k][P_o][v][v]
 void launch_ee_ring_planes(const double2* Yij, int k, int no, int nv, unsigned short* dst, int64_t Kp,
                            hipStream_t s);
-// planes (optional): split-bf16 planes [4][total] of Ya in its own order
+// kind 0: EE [k][o][o][v][v]; 1: IP [k][o][o][nv] (also EE with nv = P_v:
+// occupied pair unpacked); 2: EA [k][no][v][v] (also EE with no = P_o:
+// virtual pair unpacked); 3: EE [k][v][P_o][v] (virtual pair unpacked, the
+// occupied pair index in the middle).  planes (optional): split-bf16 planes
+// of the result read as row-major [rows][pK], written as [4][rows][pKp] with
+// zero columns beyond pK (pK = 0: the whole result as one row)
 void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv,
-                           double2* Ya, double2* Yp, hipStream_t s, unsigned short* planes = nullptr);
+                           double2* Ya, double2* Yp, hipStream_t s, unsigned short* planes = nullptr,
+                           int64_t pK = 0, int64_t pKp = 0);
 // S[z][off + packed] = alpha * U[z][...] + D[packed] * Y[z][off + packed] (+ S if accumulate)
 void launch_pack_doubles(int kind, const double2* U, double2* S, const double2* Y, int64_t ld, int64_t off,
                          int k, int no, int nv, const double* eps, cplx alpha, int accumulate,
@@ -329,6 +335,9 @@ void split_scope_end(Ctx& cx, int scope);
 // cache entry of the scope (the cache then owns and frees them); they serve
 // every split that reads src in that order without K padding
 void split_cache_put(Ctx& cx, int scope, const double2* src, int64_t n, unsigned short* planes);
+// the same for a row-major [rows][K] source whose planes are [4][rows][Kp]
+void split_cache_put_rows(Ctx& cx, int scope, const double2* src, int64_t rows, int64_t K, int64_t Kp,
+                          unsigned short* planes);
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);

@@ -7,6 +7,7 @@
 #include "internal.h"
 
 #include <hip/hip_bf16.h>
+#include <stdexcept>
 
 namespace adc {
 
@@ -1362,25 +1363,34 @@ void launch_div_d1(double2* t, const double* eps, int no, int nv, hipStream_t s)
 __device__ __forceinline__ int64_t pidx(int64_t p, int64_t q, int64_t n) { return p * (2 * n - p - 1) / 2 + (q - p - 1); }
 
 // unpack: one thread per unpacked element
+// one grid row (blockIdx.y) per vector z; the index arithmetic inside a
+// vector is 32-bit
 __global__ void unpack_doubles_kernel(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv,
-                                      double2* Ya, double2* Yp, unsigned short* planes) {
-  const int64_t Po = (int64_t)no * (no - 1) / 2, Pv = (int64_t)nv * (nv - 1) / 2;
-  int64_t per;
-  if (kind == 0) per = (int64_t)no * no * nv * nv;
-  else if (kind == 1) per = (int64_t)no * no * nv;
-  else per = (int64_t)no * nv * nv;
-  const int64_t total = per * k;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t z = idx / per;
-    int64_t r = idx - z * per;
+                                      double2* Ya, double2* Yp, unsigned short* planes, int64_t pK, int64_t pKp) {
+  const uint32_t uo = (uint32_t)no, uv = (uint32_t)nv;
+  const uint32_t Po = uo * (uo - 1) / 2;
+  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+  uint32_t per;
+  if (kind == 0) per = uo * uo * uv * uv;
+  else if (kind == 1) per = uo * uo * uv;
+  else if (kind == 2) per = uo * uv * uv;
+  else per = uv * Po * uv;
+  const int64_t total = (int64_t)per * k;
+  const int64_t z = blockIdx.y;
+  // planes: row-major [rows][pK] elements into [4][rows][pKp] (pK divides
+  // the per-vector size, or pK = total: one row)
+  const bool flat = pK >= total;
+  const uint32_t pK32 = flat ? 1u : (uint32_t)pK, rows_z = flat ? 0u : per / pK32;
+  const int64_t plane = flat ? pKp : (total / pK) * pKp;
+  for (uint32_t r0 = blockIdx.x * blockDim.x + threadIdx.x; r0 < per; r0 += gridDim.x * blockDim.x) {
+    uint32_t r = r0;
     double sgn = 1.0;
     bool zero = false, canon = true;
     int64_t pos = 0;
     if (kind == 0) {
-      const int64_t b = r % nv; r /= nv;
-      const int64_t a = r % nv; r /= nv;
-      const int64_t j = r % no; const int64_t i = r / no;
+      const uint32_t b = r % uv; r /= uv;
+      const uint32_t a = r % uv; r /= uv;
+      const uint32_t j = r % uo, i = r / uo;
       if (i == j || a == b) zero = true;
       else {
         const int64_t i0 = i < j ? i : j, j0 = i < j ? j : i, a0 = a < b ? a : b, b0 = a < b ? b : a;
@@ -1390,8 +1400,8 @@ __global__ void unpack_doubles_kernel(int kind, const double2* Y, int64_t ldY, i
         pos = pidx(i0, j0, no) * Pv + pidx(a0, b0, nv);
       }
     } else if (kind == 1) {
-      const int64_t a = r % nv; r /= nv;
-      const int64_t j = r % no; const int64_t i = r / no;
+      const uint32_t a = r % uv; r /= uv;
+      const uint32_t j = r % uo, i = r / uo;
       if (i == j) zero = true;
       else {
         const int64_t i0 = i < j ? i : j, j0 = i < j ? j : i;
@@ -1399,15 +1409,26 @@ __global__ void unpack_doubles_kernel(int kind, const double2* Y, int64_t ldY, i
         canon = i < j;
         pos = pidx(i0, j0, no) * nv + a;
       }
-    } else {
-      const int64_t b = r % nv; r /= nv;
-      const int64_t a = r % nv; const int64_t i = r / nv;
+    } else if (kind == 3) {
+      // EE doubles with the occupied pair packed, stored [z][a][pair ij][b]
+      const uint32_t b = r % uv; r /= uv;
+      const uint32_t p = r % Po, a = r / Po;
       if (a == b) zero = true;
       else {
         const int64_t a0 = a < b ? a : b, b0 = a < b ? b : a;
         if (a > b) sgn = -1.0;
         canon = a < b;
-        pos = i * Pv + pidx(a0, b0, nv);
+        pos = (int64_t)p * Pv + pidx(a0, b0, nv);
+      }
+    } else {
+      const uint32_t b = r % uv; r /= uv;
+      const uint32_t a = r % uv, i = r / uv;
+      if (a == b) zero = true;
+      else {
+        const int64_t a0 = a < b ? a : b, b0 = a < b ? b : a;
+        if (a > b) sgn = -1.0;
+        canon = a < b;
+        pos = (int64_t)i * Pv + pidx(a0, b0, nv);
       }
     }
     double2 v = make_double2(0.0, 0.0);
@@ -1415,24 +1436,41 @@ __global__ void unpack_doubles_kernel(int kind, const double2* Y, int64_t ldY, i
       const double2 y = Y[z * ldY + off + pos];
       v = make_double2(sgn * y.x, sgn * y.y);
     }
+    const int64_t idx = z * per + r0;
     if (Ya) Ya[idx] = v;
     if (Yp) Yp[idx] = (!zero && canon) ? v : make_double2(0.0, 0.0);
-    if (planes) put_planes(planes, total, idx, v, 0);
+    if (planes) {
+      if (flat) {
+        put_planes(planes, plane, idx, v, 0);
+      } else {
+        const uint32_t rr = r0 / pK32, col = r0 - rr * pK32;
+        const int64_t row = z * rows_z + rr;
+        put_planes(planes, plane, row * pKp + col, v, 0);
+        if ((int64_t)col < pKp - pK) put_planes(planes, plane, row * pKp + pK + col, make_double2(0.0, 0.0), 0);
+      }
+    }
   }
-  (void)Po;
 }
 void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, double2* Ya,
-                           double2* Yp, hipStream_t s, unsigned short* planes) {
-  int64_t per = kind == 0 ? (int64_t)no * no * nv * nv : (kind == 1 ? (int64_t)no * no * nv : (int64_t)no * nv * nv);
-  hipLaunchKernelGGL(unpack_doubles_kernel, dim3(nblocks(per * k, 256)), dim3(256), 0, s, kind, Y, ldY, off, k, no,
-                     nv, Ya, Yp, planes);
+                           double2* Yp, hipStream_t s, unsigned short* planes, int64_t pK, int64_t pKp) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2;
+  const int64_t per = kind == 0 ? (int64_t)no * no * nv * nv
+                                : (kind == 1 ? (int64_t)no * no * nv : (kind == 2 ? (int64_t)no * nv * nv : nv * Po * nv));
+  if (per * k == 0) return;
+  if (per >= ((int64_t)1 << 32)) throw std::invalid_argument("unpack_doubles: more than 2^32 elements per vector");
+  if (planes && pK <= 0) pK = pKp = per * k;
+  if (planes && pK < per * k && per % pK != 0) throw std::invalid_argument("unpack_doubles: plane rows across vectors");
+  unsigned gx = nblocks(per, 256);
+  if (gx > 65535) gx = 65535;
+  hipLaunchKernelGGL(unpack_doubles_kernel, dim3(gx, (unsigned)k), dim3(256), 0, s, kind, Y, ldY, off, k, no, nv, Ya,
+                     Yp, planes, pK, pKp);
 }
 
 // Split-bf16 planes [4][rows][Kp] of the EE doubles unpacked in the ring
 // layout: row (z,i,a), column (k,c) holds Y_ikac (zero for i = k, and for
 // columns o*v <= q < Kp)
-// Yij [k][P_o][v][v] holds Y with the occupied pair packed: Y_ikac =
-// sign(i,k) * Yij[z][pair(i,k)][a][c], read along c
+// Yij [k][v][P_o][v] holds Y with the occupied pair packed: Y_ikac =
+// sign(i,k) * Yij[z][a][pair(i,k)][c], read along c
 __global__ __launch_bounds__(256) void ee_ring_planes_kernel(const double2* Yij, int k, int no, int nv,
                                                              unsigned short* dst, int64_t Kp) {
   const int64_t Po = (int64_t)no * (no - 1) / 2;
@@ -1446,7 +1484,7 @@ __global__ __launch_bounds__(256) void ee_ring_planes_kernel(const double2* Yij,
       const int64_t kk = q / nv, c = q - kk * nv;
       if (i != kk) {
         const int64_t i0 = i < kk ? i : kk, k0 = i < kk ? kk : i;
-        const double2 y = Yij[((z * Po + pidx(i0, k0, no)) * nv + a) * nv + c];
+        const double2 y = Yij[((z * nv + a) * Po + pidx(i0, k0, no)) * nv + c];
         val = i > kk ? make_double2(-y.x, -y.y) : y;
       }
     }
