@@ -1473,29 +1473,36 @@ void launch_unpack_doubles(int kind, const double2* Y, int64_t ldY, int64_t off,
 // sign(i,k) * Yij[z][a][pair(i,k)][c], read along c
 __global__ __launch_bounds__(256) void ee_ring_planes_kernel(const double2* Yij, int k, int no, int nv,
                                                              unsigned short* dst, int64_t Kp) {
+  // one block row per output row (z,i,a); 32-bit column arithmetic
+  const uint32_t uo = (uint32_t)no, uv = (uint32_t)nv;
   const int64_t Po = (int64_t)no * (no - 1) / 2;
-  const int64_t rows = (int64_t)k * no * nv, total = rows * Kp, ov = (int64_t)no * nv;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = idx / Kp, q = idx - r * Kp;
-    double2 val = make_double2(0.0, 0.0);
-    if (q < ov) {
-      const int64_t a = r % nv, zi = r / nv, i = zi % no, z = zi / no;
-      const int64_t kk = q / nv, c = q - kk * nv;
-      if (i != kk) {
-        const int64_t i0 = i < kk ? i : kk, k0 = i < kk ? kk : i;
-        const double2 y = Yij[((z * nv + a) * Po + pidx(i0, k0, no)) * nv + c];
-        val = i > kk ? make_double2(-y.x, -y.y) : y;
+  const int64_t rows = (int64_t)k * no * nv, plane = rows * Kp;
+  const uint32_t ov = uo * uv;
+  for (int64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+    const int64_t a = r % nv, zi = r / nv, i = zi % no, z = zi / no;
+    const double2* src = Yij + (z * nv + a) * Po * nv;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < (uint32_t)Kp; q += gridDim.x * blockDim.x) {
+      double2 val = make_double2(0.0, 0.0);
+      if (q < ov) {
+        const uint32_t kk = q / uv, c = q - kk * uv;
+        if ((int64_t)kk != i) {
+          const int64_t i0 = i < kk ? i : kk, k0 = i < kk ? kk : i;
+          const double2 y = src[pidx(i0, k0, no) * nv + c];
+          val = i > kk ? make_double2(-y.x, -y.y) : y;
+        }
       }
+      put_planes(dst, plane, r * Kp + q, val, 0);
     }
-    put_planes(dst, total, idx, val, 0);
   }
 }
 void launch_ee_ring_planes(const double2* Yij, int k, int no, int nv, unsigned short* dst, int64_t Kp,
                            hipStream_t s) {
-  const int64_t total = (int64_t)k * no * nv * Kp;
-  if (total == 0) return;
-  hipLaunchKernelGGL(ee_ring_planes_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Yij, k, no, nv, dst, Kp);
+  const int64_t rows = (int64_t)k * no * nv;
+  if (rows * Kp == 0) return;
+  unsigned gx = (unsigned)((Kp + 255) / 256);
+  if (gx > 64) gx = 64;
+  const unsigned gy = (unsigned)(rows < 65535 ? rows : 65535);
+  hipLaunchKernelGGL(ee_ring_planes_kernel, dim3(gx, gy), dim3(256), 0, s, Yij, k, no, nv, dst, Kp);
 }
 
 // pack: one thread per packed element; po/pv are the pair tables of o and v
