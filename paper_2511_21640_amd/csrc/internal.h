@@ -98,7 +98,7 @@ void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, in
 // Upper half of the packed <ab||cd> rows of one a-block, as split planes:
 // W[(a-a0)*(nv-a0) + c-a0][(b-b0)*(nv-a0) + d-a0] = sum_Q L_ac L_bd holds only
 // c, d >= a0; row ab (pair index p) gets <ab||cd> for pairs cd >= p and zero
-// below (filled by launch_ladder_mirror_planes)
+// padding; the part below p is left for launch_ladder_mirror_planes
 void launch_ladder_pack_planes_upper(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
                                      int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
                                      hipStream_t s);

@@ -975,9 +975,11 @@ __global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const dou
   const int64_t m = nv - a0;
   const int64_t ra = (int64_t)(ab.x - a0) * m, cb = (int64_t)(ab.y - b0) * m;
   const int64_t plane = ldv * Kp;
-  for (int64_t pc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < Kp; pc += (int64_t)gridDim.x * blockDim.x) {
+  // columns pc < prow are the lower part, which the mirror writes
+  for (int64_t pc = prow + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < Kp;
+       pc += (int64_t)gridDim.x * blockDim.x) {
     unsigned short h0 = 0, l0 = 0, h1 = 0, l1 = 0;
-    if (pc >= prow && pc < Pv) {
+    if (pc < Pv) {
       const int2 cd = pv[pc];  // c >= a >= a0 and d > c
       const double2 w1 = W[(ra + cd.x - a0) * ldw + cb + cd.y - a0];
       const double2 w2 = W[(ra + cd.y - a0) * ldw + cb + cd.x - a0];
