@@ -289,10 +289,12 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
       g.M = Mw; g.N = Nw; g.Kp = I.Kq;
       g.A = I.Lq + ((int64_t)a0 * v + a0) * I.Kq; g.lda = (int64_t)v * v; g.amd = m; g.ams = v;
       g.B = I.Lq + ((int64_t)b0 * v + a0) * I.Kq; g.ldb = (int64_t)v * v; g.bmd = m; g.bms = v;
-      g.C = Wbuf; g.scm = Nw; g.scn = 1;
+      // W is stored as complex64: the GEMM accumulates in FP32 and the pack
+      // rounds <ab||cd> to FP32 before splitting it
+      g.C = Wbuf; g.scm = Nw; g.scn = 1; g.c32 = 1;
       g.alpha = C1(); g.beta = C0(); g.tag = 1;
       gemm_bf16p(cx, g);
-      launch_ladder_pack_planes_upper(Wbuf, Nw, a0, b0, v, Vp, grp, pbase, np, I.pair_v, Kv, cx.stream);
+      launch_ladder_pack_planes_upper(Wbuf, 1, Nw, a0, b0, v, Vp, grp, pbase, np, I.pair_v, Kv, cx.stream);
       gfill += np;
       a0 = a1;
       continue;
@@ -846,16 +848,31 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     Yij = tnew(cx, {k, v, Po, v}, false);
   }
   SplitScope hscope(cx, {{Yh.p, Yh.size()}, {Yij.p, Yij.size()}});
+  // ring-layout planes of Y (split-bf16 with the ring term)
+  unsigned short* Rq = nullptr;
   if (half) {
     const bool fuse = prec == ADC_SPLIT_BF16 && hscope.id > 0;
     const int64_t Kh = (int64_t)o * Pv, Kij = Po * v;
+    // with K >= 32 every contraction reading Yh or Yij takes their planes, so
+    // the complex copies are never written: the planes of Yij (and the ring
+    // planes) come straight from the packed vectors
+    const bool only = fuse && Kh >= 32 && Kij >= 32;
     unsigned short* hq = fuse ? (unsigned short*)cx.pool.get(((int64_t)k * o * pad32(Kh) * 8 + 15) / 16) : nullptr;
     unsigned short* iq = fuse ? (unsigned short*)cx.pool.get(((int64_t)k * v * pad32(Kij) * 8 + 15) / 16) : nullptr;
-    launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, Yh.p, nullptr, cx.stream, hq, Kh, pad32(Kh));
-    launch_unpack_doubles(3, Y, dim, n1, k, o, v, Yij.p, nullptr, cx.stream, iq, Kij, pad32(Kij));
+    launch_unpack_doubles(1, Y, dim, n1, k, o, (int)Pv, only ? nullptr : Yh.p, nullptr, cx.stream, hq, Kh, pad32(Kh));
+    if (only) {
+      if (ring_planes && x != 0.0) Rq = (unsigned short*)cx.pool.get(((int64_t)k * o * v * I.ringKp * 8 + 15) / 16);
+      launch_ee_pair_planes(Y, dim, n1, k, o, v, iq, pad32(Kij), Rq, I.ringKp, cx.stream);
+    } else {
+      launch_unpack_doubles(3, Y, dim, n1, k, o, v, Yij.p, nullptr, cx.stream, iq, Kij, pad32(Kij));
+    }
     if (fuse) {
       split_cache_put_rows(cx, hscope.id, Yh.p, (int64_t)k * o, Kh, pad32(Kh), hq);
       split_cache_put_rows(cx, hscope.id, Yij.p, (int64_t)k * v, Kij, pad32(Kij), iq);
+    }
+    if (only) {
+      split_cache_planes_only(cx, hscope.id, Yh.p);
+      split_cache_planes_only(cx, hscope.id, Yij.p);
     }
   }
   const Tensor& t = I.t1;
@@ -988,8 +1005,10 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     if (ring_planes) {
       // A2[z][i][j][a][b] -= x sum_kc Y_ikac ring[k][c][j][b] on the planes
       const int64_t ov = (int64_t)o * v, rows = (int64_t)k * ov;
-      unsigned short* Rq = (unsigned short*)cx.pool.get((rows * I.ringKp * 8 + 15) / 16);
-      launch_ee_ring_planes(Yij.p, k, o, v, Rq, I.ringKp, cx.stream);
+      if (!Rq) {
+        Rq = (unsigned short*)cx.pool.get((rows * I.ringKp * 8 + 15) / 16);
+        launch_ee_ring_planes(Yij.p, k, o, v, Rq, I.ringKp, cx.stream);
+      }
       BfGemm g{};
       g.M = rows; g.N = ov; g.Kp = I.ringKp;
       g.A = Rq; g.lda = rows;
@@ -1001,6 +1020,7 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       g.alpha = CR(-x); g.beta = C1(); g.tag = 0;
       gemm_bf16p(cx, g);
       cx.pool.put((double2*)Rq);
+      Rq = nullptr;
     } else {
       ctr(cx, CR(-x), Ya, "zikac", false, I.ring, "kcjb", false, C1(), A2, "zijab");
     }

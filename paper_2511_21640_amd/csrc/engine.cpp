@@ -721,6 +721,10 @@ static void drop_scope(Ctx& cx, int scope) {
   for (auto& r : c.frozen)
     if (r.scope != scope) fr.push_back(r);
   c.frozen.swap(fr);
+  std::vector<std::pair<const double2*, int>> only;
+  for (auto& o : c.only)
+    if (o.second != scope) only.push_back(o);
+  c.only.swap(only);
 }
 
 void split_thaw_all(Ctx& cx) {
@@ -748,6 +752,16 @@ void split_cache_put_rows(Ctx& cx, int scope, const double2* src, int64_t rows, 
   key.nm = 1; key.md[0] = rows; key.ms[0] = K;
   key.nk = 1; key.kd[0] = K; key.ks[0] = 1;
   cx.scache.entries.push_back({key, planes, rows * Kp * 8, scope});
+}
+
+void split_cache_planes_only(Ctx& cx, int scope, const double2* src) {
+  if (scope > 0 && src) cx.scache.only.push_back({src, scope});
+}
+
+bool split_planes_only(const Ctx& cx, const double2* src) {
+  for (const auto& o : cx.scache.only)
+    if (o.first == src) return true;
+  return false;
 }
 
 void split_cache_put(Ctx& cx, int scope, const double2* src, int64_t n, unsigned short* planes) {
@@ -881,6 +895,8 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
   } pg{cx, cx.prec};
   if (cx.prec == 2 && Kn < 32 && Mn * Nn * Bn <= ((int64_t)1 << 20)) cx.prec = 0;
   // ---- split-bf16: unbatched contractions run on pre-split operand planes
+  if ((split_planes_only(cx, A.p) || split_planes_only(cx, B.p)) && !(cx.prec == 2 && bat.empty() && Kn > 0))
+    throw std::logic_error("ctr: an operand held only as split-bf16 planes");
   if (cx.prec == 2 && bat.empty() && Kn > 0) {
     const int64_t Kp = (Kn + 31) / 32 * 32;
     // K order: decreasing stride in the larger operand, so that its split
@@ -906,6 +922,7 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
         sp.src = X.p;
         const bool tiled = sp.ks[sp.nk - 1] != 1 && sp.ms[sp.nm - 1] == 1;
         if (unsigned short* hit = split_cached(cx, sp, pbytes, tiled)) return hit;
+        if (split_planes_only(cx, X.p)) throw std::logic_error("ctr: planes of another layout from planes-only data");
         unsigned short* dst = (unsigned short*)cx.pool.get((pbytes + 15) / 16);
         planes_tmp.push_back((double2*)dst);
         sp.dst = dst;
@@ -913,6 +930,7 @@ void ctr(Ctx& cx, cplx alpha, const Tensor& A, const char* la, bool cA, const Te
         return dst;
       }
       // more than four digits: go through a contiguous copy
+      if (split_planes_only(cx, X.p)) throw std::logic_error("ctr: planes of another layout from planes-only data");
       unsigned short* dst = (unsigned short*)cx.pool.get((pbytes + 15) / 16);
       planes_tmp.push_back((double2*)dst);
       double2* t = cx.pool.get(X.size());

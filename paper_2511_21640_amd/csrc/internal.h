@@ -98,8 +98,9 @@ void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, in
 // Upper half of the packed <ab||cd> rows of one a-block, as split planes:
 // W[(a-a0)*(nv-a0) + c-a0][(b-b0)*(nv-a0) + d-a0] = sum_Q L_ac L_bd holds only
 // c, d >= a0; row ab (pair index p) gets <ab||cd> for pairs cd >= p and zero
-// padding; the part below p is left for launch_ladder_mirror_planes
-void launch_ladder_pack_planes_upper(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
+// padding; the part below p is left for launch_ladder_mirror_planes.  W holds
+// complex128 (w32 = 0) or complex64 (w32 = 1) elements
+void launch_ladder_pack_planes_upper(const void* W, int w32, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
                                      int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
                                      hipStream_t s);
 // V[p][q] = conj(V[q][p]) for q < p < n on split planes [4][ldv][Kp] (the
@@ -134,9 +135,16 @@ void launch_div_d1(double2* t, const double* eps, int no, int nv, hipStream_t s)
 // unpack: Ya antisymmetric in every pair; Yp (optional) zero except packed positions.
 // split-bf16 planes [4][k*o*v][Kp] of the EE doubles in the ring layout
 // (rows (z,i,a), columns (k,c) < o*v, zero beyond), from the doubles with the
-// occupied pair packed, Yij [k][P_o][v][v]
+// occupied pair packed, Yij [k][v][P_o][v]
 void launch_ee_ring_planes(const double2* Yij, int k, int no, int nv, unsigned short* dst, int64_t Kp,
                            hipStream_t s);
+// straight from the packed EE vectors Y (row z at Y + z*ldY + off): the
+// split-bf16 planes [4][k*v][Kpy] of Yij read as rows (z,a), columns
+// (pair ij, b) (zero beyond P_o*v), and, when rq is given, the ring-layout
+// planes above into rq [4][k*o*v][Kpr]; the same values as
+// launch_unpack_doubles(3) followed by the split (and launch_ee_ring_planes)
+void launch_ee_pair_planes(const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, unsigned short* yq,
+                           int64_t Kpy, unsigned short* rq, int64_t Kpr, hipStream_t s);
 // kind 0: EE [k][o][o][v][v]; 1: IP [k][o][o][nv] (also EE with nv = P_v:
 // occupied pair unpacked); 2: EA [k][no][v][v] (also EE with no = P_o:
 // virtual pair unpacked); 3: EE [k][v][P_o][v] (virtual pair unpacked, the
@@ -308,6 +316,9 @@ struct SplitCache {
   };
   std::vector<Range> frozen;
   std::vector<Entry> entries;
+  // buffers of a scope whose elements were never written: only their cached
+  // planes may be read (a contraction that would read them otherwise throws)
+  std::vector<std::pair<const double2*, int>> only;
   int64_t persistent_bytes = 0, limit = 0;
   int next_scope = 1;
 };
@@ -338,6 +349,9 @@ void split_cache_put(Ctx& cx, int scope, const double2* src, int64_t n, unsigned
 // the same for a row-major [rows][K] source whose planes are [4][rows][Kp]
 void split_cache_put_rows(Ctx& cx, int scope, const double2* src, int64_t rows, int64_t K, int64_t Kp,
                           unsigned short* planes);
+// mark src (a buffer of the scope) as held only by its cached planes
+void split_cache_planes_only(Ctx& cx, int scope, const double2* src);
+bool split_planes_only(const Ctx& cx, const double2* src);
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);

@@ -966,7 +966,8 @@ void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, in
                      ldv, r0, pbase, pv, Pv, Kp);
 }
 
-__global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const double2* W, int64_t ldw, int a0, int b0,
+template <typename WT>
+__global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const WT* W, int64_t ldw, int a0, int b0,
                                                                        int nv, unsigned short* V, int64_t ldv,
                                                                        int64_t pbase, const int2* pv, int64_t Pv,
                                                                        int64_t Kp) {
@@ -981,8 +982,8 @@ __global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const dou
     unsigned short h0 = 0, l0 = 0, h1 = 0, l1 = 0;
     if (pc < Pv) {
       const int2 cd = pv[pc];  // c >= a >= a0 and d > c
-      const double2 w1 = W[(ra + cd.x - a0) * ldw + cb + cd.y - a0];
-      const double2 w2 = W[(ra + cd.y - a0) * ldw + cb + cd.x - a0];
+      const WT w1 = W[(ra + cd.x - a0) * ldw + cb + cd.y - a0];
+      const WT w2 = W[(ra + cd.y - a0) * ldw + cb + cd.x - a0];
       split_bf16((float)(w1.x - w2.x), h0, l0);
       split_bf16((float)(w1.y - w2.y), h1, l1);
     }
@@ -993,15 +994,19 @@ __global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const dou
     V[3 * plane + o] = l1;
   }
 }
-void launch_ladder_pack_planes_upper(const double2* W, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
+void launch_ladder_pack_planes_upper(const void* W, int w32, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
                                      int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
                                      hipStream_t s) {
   const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
   if (npairs <= 0 || Pv <= 0) return;
   unsigned gx = (unsigned)((Kp + 255) / 256);
   if (gx > 64) gx = 64;
-  hipLaunchKernelGGL(ladder_pack_planes_upper_kernel, dim3(gx, (unsigned)npairs), dim3(256), 0, s, W, ldw, a0, b0, nv,
-                     V, ldv, pbase, pv, Pv, Kp);
+  if (w32)
+    hipLaunchKernelGGL(ladder_pack_planes_upper_kernel<float2>, dim3(gx, (unsigned)npairs), dim3(256), 0, s,
+                       (const float2*)W, ldw, a0, b0, nv, V, ldv, pbase, pv, Pv, Kp);
+  else
+    hipLaunchKernelGGL(ladder_pack_planes_upper_kernel<double2>, dim3(gx, (unsigned)npairs), dim3(256), 0, s,
+                       (const double2*)W, ldw, a0, b0, nv, V, ldv, pbase, pv, Pv, Kp);
 }
 
 // 64 x 64 tiles (tp >= tq) of the strictly lower triangle: read block (q, p)
@@ -1505,6 +1510,113 @@ void launch_ee_ring_planes(const double2* Yij, int k, int no, int nv, unsigned s
   if (gx > 64) gx = 64;
   const unsigned gy = (unsigned)(rows < 65535 ? rows : 65535);
   hipLaunchKernelGGL(ee_ring_planes_kernel, dim3(gx, gy), dim3(256), 0, s, Yij, k, no, nv, dst, Kp);
+}
+
+__device__ __forceinline__ void put_planes_f(unsigned short* dst, int64_t plane, int64_t at, float2 v) {
+  unsigned short h0, l0, h1, l1;
+  split_bf16(v.x, h0, l0);
+  split_bf16(v.y, h1, l1);
+  dst[at] = h0;
+  dst[plane + at] = l0;
+  dst[2 * plane + at] = h1;
+  dst[3 * plane + at] = l1;
+}
+
+// Split-bf16 planes of the EE doubles straight from the packed vectors
+// (Y[z][pair ij][pair ab], i<j, a<b):
+//  * yq [4][k*v][Kpy]: row (z,a), column (pair ij, b) = Y_ijab, zero for a = b
+//    and for the padding columns P_o*v <= q < Kpy;
+//  * rq [4][k*o*v][Kpr] (optional): row (z,i,a), column (k,c) = Y_ikac, zero
+//    for i = k and for the padding columns o*v <= q < Kpr.
+// Block (t, z): for t < P_o * npair one occupied pair and one pair A <= B of
+// 64-wide tiles of the virtual index; the upper triangle of the tile is read
+// once into LDS (as float2: every plane is split from the float value) and
+// both (A,B) and its mirror (B,A) are written along their rows.  The last o
+// blocks of a row z write the zero (i,i) blocks of rq and the padding.
+constexpr int EPT = 64;
+__global__ __launch_bounds__(256) void ee_pair_planes_kernel(const double2* Y, int64_t ldY, int64_t off, int no,
+                                                             int nv, unsigned short* yq, int64_t Kpy, int64_t plane_y,
+                                                             unsigned short* rq, int64_t Kpr, int64_t plane_r) {
+  __shared__ float2 s[EPT][EPT + 1];
+  const int z = blockIdx.y;
+  const int nt = (nv + EPT - 1) / EPT, npair = nt * (nt + 1) / 2;
+  const int Po = no * (no - 1) / 2;
+  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+  const int tc = threadIdx.x % EPT, tr = threadIdx.x / EPT;  // 4 rows per pass
+  constexpr int RP = 256 / EPT;
+  const float2 zero = make_float2(0.f, 0.f);
+  const int bid = blockIdx.x;
+  if (bid >= Po * npair) {
+    const int i = bid - Po * npair;
+    if (rq) {
+      for (int a = tr; a < nv; a += RP) {
+        const int64_t row = ((int64_t)z * no + i) * nv + a;
+        for (int c = tc; c < nv; c += EPT) put_planes_f(rq, plane_r, row * Kpr + (int64_t)i * nv + c, zero);
+        for (int64_t q = (int64_t)no * nv + tc; q < Kpr; q += EPT) put_planes_f(rq, plane_r, row * Kpr + q, zero);
+      }
+    }
+    if (i == 0) {
+      for (int a = tr; a < nv; a += RP) {
+        const int64_t row = (int64_t)z * nv + a;
+        for (int64_t q = (int64_t)Po * nv + tc; q < Kpy; q += EPT) put_planes_f(yq, plane_y, row * Kpy + q, zero);
+      }
+    }
+    return;
+  }
+  const int p = bid / npair;
+  int t = bid - p * npair, A = 0;
+  while (t >= nt - A) {
+    t -= nt - A;
+    ++A;
+  }
+  const int B = A + t;
+  int i = 0, rem = p;
+  while (rem >= no - 1 - i) {
+    rem -= no - 1 - i;
+    ++i;
+  }
+  const int kk = i + 1 + rem;
+  const double2* src = Y + (int64_t)z * ldY + off + (int64_t)p * Pv;
+  for (int r = tr; r < EPT; r += RP) {
+    const int a = A * EPT + r, b = B * EPT + tc;
+    float2 v = zero;
+    if (a < b && b < nv) {
+      const double2 y = src[pidx(a, b, nv)];
+      v = make_float2((float)y.x, (float)y.y);
+    }
+    s[r][tc] = v;
+  }
+  __syncthreads();
+  for (int g = 0; g < (A < B ? 2 : 1); ++g) {
+    const int R = g == 0 ? A : B, Cb = g == 0 ? B : A;
+    const int c = Cb * EPT + tc;
+    if (c >= nv) continue;
+    for (int r = tr; r < EPT; r += RP) {
+      const int a = R * EPT + r;
+      if (a >= nv) break;
+      float2 v;
+      if (g == 0 && (A < B || r < tc)) v = s[r][tc];
+      else if (g == 0 && r == tc) v = zero;
+      else v = make_float2(-s[tc][r].x, -s[tc][r].y);
+      put_planes_f(yq, plane_y, ((int64_t)z * nv + a) * Kpy + (int64_t)p * nv + c, v);
+      if (rq) {
+        put_planes_f(rq, plane_r, (((int64_t)z * no + i) * nv + a) * Kpr + (int64_t)kk * nv + c, v);
+        put_planes_f(rq, plane_r, (((int64_t)z * no + kk) * nv + a) * Kpr + (int64_t)i * nv + c,
+                     make_float2(-v.x, -v.y));
+      }
+    }
+  }
+}
+void launch_ee_pair_planes(const double2* Y, int64_t ldY, int64_t off, int k, int no, int nv, unsigned short* yq,
+                           int64_t Kpy, unsigned short* rq, int64_t Kpr, hipStream_t s) {
+  const int64_t Po = (int64_t)no * (no - 1) / 2, nt = (nv + EPT - 1) / EPT;
+  if (k <= 0 || nv <= 0 || no <= 0) return;
+  if (Kpy < Po * nv || (rq && Kpr < (int64_t)no * nv)) throw std::invalid_argument("ee_pair_planes: K padding");
+  if (!yq) throw std::invalid_argument("ee_pair_planes: no destination");
+  const int64_t gx = Po * (nt * (nt + 1) / 2) + no;
+  if (gx > 0x7fffffff || k > 65535) throw std::invalid_argument("ee_pair_planes: grid");
+  hipLaunchKernelGGL(ee_pair_planes_kernel, dim3((unsigned)gx, (unsigned)k), dim3(256), 0, s, Y, ldY, off, no, nv,
+                     yq, Kpy, (int64_t)k * nv * Kpy, rq, Kpr, (int64_t)k * no * nv * Kpr);
 }
 
 // pack: one thread per packed element; po/pv are the pair tables of o and v
