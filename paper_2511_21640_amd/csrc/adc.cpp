@@ -220,15 +220,24 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   unsigned short* Yp = nullptr;
   unsigned short* Vp = nullptr;
   double2* Vbuf = nullptr;
+  bool own_yp = false;
   if (bf) {
     ensure_planes(h, I);
-    Yp = planes_alloc(cx, R, Kv);
     Vp = planes_alloc(cx, grp, Kv);
     SplitNd sp{};
-    sp.src = Y + offY; sp.dst = Yp; sp.rows = R; sp.K = Pv; sp.Kp = Kv; sp.conj = 0;
+    sp.src = Y + offY; sp.rows = R; sp.K = Pv; sp.Kp = Kv; sp.conj = 0;
     sp.nm = 2; sp.md[0] = k; sp.md[1] = nrow; sp.ms[0] = ldY; sp.ms[1] = Pv;
     sp.nk = 1; sp.kd[0] = Pv; sp.ks[0] = 1;
-    launch_split_nd(sp, 0, cx.stream);
+    // inside a sigma build the trial rows' planes come from the build's
+    // cache, where a contraction reading the packed doubles in this layout
+    // may already have put them
+    Yp = split_planes_cached(cx, sp, 0);
+    if (!Yp) {
+      Yp = planes_alloc(cx, R, Kv);
+      own_yp = true;
+      sp.dst = Yp;
+      launch_split_nd(sp, 0, cx.stream);
+    }
   } else {
     Vbuf = cx.pool.get(grp * Pv);
   }
@@ -330,7 +339,7 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   }
   if (half) launch_ladder_mirror_planes(Vp, grp, Pv, Kv, cx.stream);
   contract();
-  if (Yp) cx.pool.put((double2*)Yp);
+  if (own_yp) cx.pool.put((double2*)Yp);
   if (Vp) cx.pool.put((double2*)Vp);
   if (Vbuf) cx.pool.put(Vbuf);
   if (!bf) {
@@ -1342,6 +1351,9 @@ void heevj(int n, std::vector<zc>& A, std::vector<double>& w, std::vector<zc>& V
 // runs once over all of them (it adds into the packed output).
 void sigma_dispatch(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
   if (k <= 0) return;
+  // Y stays unchanged during the build: splits of it are shared by the
+  // contractions (and the ladder) that read it in the same layout
+  SplitScope yscope(*I.cx, {{Y, (int64_t)k * I.dim}});
   const int64_t o = I.o, v = I.v;
   const int64_t unp = I.kind == ADC_EE ? o * o * v * v : (I.kind == ADC_IP ? o * o * v : o * v * v);
   const size_t ws = h->opt.mem_budget ? h->opt.mem_budget : (size_t)16 << 30;

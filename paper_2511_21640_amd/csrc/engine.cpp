@@ -699,6 +699,10 @@ static unsigned short* split_cached(Ctx& cx, SplitNd sp, int64_t bytes, bool til
   return dst;
 }
 
+unsigned short* split_planes_cached(Ctx& cx, const SplitNd& sp, int tiled) {
+  return split_cached(cx, sp, sp.rows * sp.Kp * 8, tiled != 0);
+}
+
 void split_freeze(Ctx& cx, const double2* p, int64_t n, int64_t extra_bytes) {
   if (!p || n <= 0) return;
   cx.scache.frozen.push_back({p, n, 0});

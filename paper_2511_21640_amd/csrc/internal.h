@@ -349,6 +349,10 @@ void split_cache_put(Ctx& cx, int scope, const double2* src, int64_t n, unsigned
 // the same for a row-major [rows][K] source whose planes are [4][rows][Kp]
 void split_cache_put_rows(Ctx& cx, int scope, const double2* src, int64_t rows, int64_t K, int64_t Kp,
                           unsigned short* planes);
+// planes of sp (dst unused) owned by the cache: found, or split into a new
+// entry of the scope whose frozen range holds the source; nullptr where
+// ctr() would not cache them (the caller then splits into its own buffer)
+unsigned short* split_planes_cached(Ctx& cx, const SplitNd& sp, int tiled);
 // mark src (a buffer of the scope) as held only by its cached planes
 void split_cache_planes_only(Ctx& cx, int scope, const double2* src);
 bool split_planes_only(const Ctx& cx, const double2* src);

@@ -147,3 +147,23 @@ def test_split_bf16_ladder_blocks(v, budget):
     err = np.abs(Sbf - S64).max() / np.abs(S64).max()
     print("ladder split-bf16 rel err", err)
     assert 1e-12 < err < 2e-5
+
+
+@pytest.mark.parametrize("o,v,x", [(2, 20, 1.0), (3, 70, 1.0), (3, 67, 0.5), (2, 66, 0.0)])
+def test_split_bf16_ee_pair_layouts(o, v, x):
+    """Split-bf16 EE sigma over the shapes that pick different forms of the
+    doubles' planes: few occupied pairs (P_o * v < 32: the unpacked copies are
+    split), one or two 64-wide virtual tiles with odd and even v (planes of the
+    pair-packed doubles and of the ring layout written straight from the
+    packed vectors), and x = 0 (no ring term)."""
+    print(f"case split-bf16 EE o={o} v={v} x={x}", flush=True)
+    P = make_problem("EE", o, v, 60, seed=47, n_roots=2, x=x, scale=0.2)
+    h = _handle(P, precision="split_bf16")
+    rng = np.random.default_rng(47)
+    Y = _rand(rng, 2, h.dim)
+    S = h.sigma(torch.from_numpy(Y).cuda()).cpu().numpy()
+    ref = osigma(Ints(P.eps, P.L, o), "EE", x, Y)
+    err = np.abs(S - ref).max() / np.abs(ref).max()
+    print("split-bf16 rel err", err)
+    assert 1e-12 < err < 2e-5
+    h.close()
