@@ -158,7 +158,8 @@ int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precis
  * Subspace algebra (Gram matrix, Ritz vectors, residuals, norms,
  * preconditioner, orthogonalisation) runs in FP64 device kernels; the small
  * subspace eigenproblem runs on the host.  Synchronous.  Returns
- * ADC_NOT_CONVERGED if any root missed the criteria. */
+ * ADC_NOT_CONVERGED if any root missed the criteria, ADC_ERR_NONFINITE_INPUT
+ * if a subspace matrix holds NaN or Inf (e.g. from a non-finite guess). */
 int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs,
                  double* resnorm, int* iters, int* converged);
 

@@ -1287,6 +1287,11 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
 // small Hermitian eigensolver (cyclic complex Jacobi), host
 // ============================================================================
 void heevj(int n, std::vector<zc>& A, std::vector<double>& w, std::vector<zc>& V) {
+  // a non-finite entry (a trial vector or sigma result gone bad) ends the
+  // solve with an error; the rotations and the ordering below need numbers
+  for (size_t i = 0; i < (size_t)n * n; ++i)
+    if (!std::isfinite(A[i].real()) || !std::isfinite(A[i].imag()))
+      throw Status{ADC_ERR_NONFINITE_INPUT, "non-finite subspace matrix"};
   V.assign((size_t)n * n, zc(0, 0));
   for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
   auto a = [&](int i, int j) -> zc& { return A[(size_t)i * n + j]; };
@@ -2210,7 +2215,7 @@ const char* adc_strerror(int code) {
     case ADC_OK: return "ok";
     case ADC_NOT_CONVERGED: return "Davidson did not converge for every root (outputs filled)";
     case ADC_ERR_INVALID_ARG: return "invalid argument";
-    case ADC_ERR_NONFINITE_INPUT: return "non-finite value in eps, L or x";
+    case ADC_ERR_NONFINITE_INPUT: return "non-finite value in eps, L or x, or in a Davidson subspace matrix";
     case ADC_ERR_NOT_HERMITIAN: return "a Cholesky vector L^Q is not Hermitian in (p,q)";
     case ADC_ERR_OUT_OF_MEMORY: return "out of device memory";
     case ADC_ERR_HIP: return "HIP runtime error";
