@@ -219,8 +219,8 @@ def main():
         run_c4(args)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU sharding is a "
-              f"design only, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on one GPU; "
+              f"sharding over several is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
