@@ -880,8 +880,8 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       split_cache_put_rows(cx, hscope.id, Yij.p, (int64_t)k * v, Kij, pad32(Kij), iq);
     }
     if (only) {
-      split_cache_planes_only(cx, hscope.id, Yh.p);
-      split_cache_planes_only(cx, hscope.id, Yij.p);
+      split_cache_planes_only(cx, hscope.id, Yh.p, Yh.size());
+      split_cache_planes_only(cx, hscope.id, Yij.p, Yij.size());
     }
   }
   const Tensor& t = I.t1;

@@ -725,9 +725,9 @@ static void drop_scope(Ctx& cx, int scope) {
   for (auto& r : c.frozen)
     if (r.scope != scope) fr.push_back(r);
   c.frozen.swap(fr);
-  std::vector<std::pair<const double2*, int>> only;
+  std::vector<SplitCache::Range> only;
   for (auto& o : c.only)
-    if (o.second != scope) only.push_back(o);
+    if (o.scope != scope) only.push_back(o);
   c.only.swap(only);
 }
 
@@ -758,13 +758,13 @@ void split_cache_put_rows(Ctx& cx, int scope, const double2* src, int64_t rows, 
   cx.scache.entries.push_back({key, planes, rows * Kp * 8, scope});
 }
 
-void split_cache_planes_only(Ctx& cx, int scope, const double2* src) {
-  if (scope > 0 && src) cx.scache.only.push_back({src, scope});
+void split_cache_planes_only(Ctx& cx, int scope, const double2* src, int64_t n) {
+  if (scope > 0 && src && n > 0) cx.scache.only.push_back({src, n, scope});
 }
 
-bool split_planes_only(const Ctx& cx, const double2* src) {
+bool split_planes_only(const Ctx& cx, const double2* p) {
   for (const auto& o : cx.scache.only)
-    if (o.first == src) return true;
+    if (p >= o.p && p < o.p + o.n) return true;
   return false;
 }
 

@@ -318,7 +318,7 @@ struct SplitCache {
   std::vector<Entry> entries;
   // buffers of a scope whose elements were never written: only their cached
   // planes may be read (a contraction that would read them otherwise throws)
-  std::vector<std::pair<const double2*, int>> only;
+  std::vector<Range> only;
   int64_t persistent_bytes = 0, limit = 0;
   int next_scope = 1;
 };
@@ -353,9 +353,10 @@ void split_cache_put_rows(Ctx& cx, int scope, const double2* src, int64_t rows, 
 // entry of the scope whose frozen range holds the source; nullptr where
 // ctr() would not cache them (the caller then splits into its own buffer)
 unsigned short* split_planes_cached(Ctx& cx, const SplitNd& sp, int tiled);
-// mark src (a buffer of the scope) as held only by its cached planes
-void split_cache_planes_only(Ctx& cx, int scope, const double2* src);
-bool split_planes_only(const Ctx& cx, const double2* src);
+// mark the n elements at src (a buffer of the scope) as held only by their
+// cached planes; split_planes_only tells whether p points into such a buffer
+void split_cache_planes_only(Ctx& cx, int scope, const double2* src, int64_t n);
+bool split_planes_only(const Ctx& cx, const double2* p);
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);
