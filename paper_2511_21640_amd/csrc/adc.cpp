@@ -714,6 +714,21 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     launch_pack_pairs(I.E0.p, I.E0h.p, o, v, v + o, I.pair_v, cx.stream);
     I.E1h = tnew(cx, {Po, v, 2 * o + v}, false);
     launch_pack_pairs(I.E1.p, I.E1h.p, 1, o, (int64_t)v * (2 * o + v), I.pair_o, cx.stream);
+    if (Po > 0) {
+      // the x W6 term of the doubles output joins the A1 product: after
+      // P(IJ)P(AB), x sum_i conj(W6_IBJi) y_iA equals P(AB) of
+      // -x sum_i conj(W6_IAJi - W6_JAIi) y_iB over I<J, i.e. the factor
+      // -2 conj(W6_IAJi - W6_JAIi) against the x/2 y_iB already on the trial
+      // side of the third block
+      Tensor w6t = tnew(cx, {v, o, o, o}, false);
+      perm(cx, C1(), I.W6, "IAJi", false, C0(), w6t, "AIJi");
+      Tensor w6h = tnew(cx, {v, Po, o}, false);
+      launch_pack_pairs(w6t.p, w6h.p, v, o, o, I.pair_o, cx.stream, 1);
+      tfree(cx, w6t);
+      Tensor e3 = tslice(I.E1h, 2, o + v, 2 * o + v);
+      perm(cx, CR(-2.0), w6h, "APi", true, C1(), e3, "PAi");
+      tfree(cx, w6h);
+    }
     I.th = tnew(cx, {o, o, Pv}, false);
     launch_pack_pairs(t.p, I.th.p, (int64_t)o * o, v, 1, I.pair_v, cx.stream);
     I.tIJ = tnew(cx, {Po, v, v}, false);
@@ -1000,7 +1015,8 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       tfree(cx, Z4);
     }
     ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C0(), A2, "zIJAB");
-    ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
+    // (outside a tape the W6 term is part of the E1h product into A1)
+    if (!half) ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
     // through P(ij)) and ring; the particle ladder runs packed below
     if (half) {
