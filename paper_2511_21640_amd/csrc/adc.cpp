@@ -65,7 +65,9 @@ struct Inst {
   // layout, summed into one factor per layout (x enters them; see build_sx)
   Tensor X1, X2;
   // EE outside a tape: E0 and t1 with the pair (a<b) packed, E1 with the
-  // pair (I<J) packed, for the half-stored accumulators (E0, E1 are freed)
+  // pair (I<J) packed, for the half-stored accumulators (E0, E1 are freed);
+  // E0h carries a third block for the W5 term and E1h's third block also
+  // holds the W6 term (see ee_init)
   Tensor E0h, E1h, th;
   // EE outside a tape: X1 antisymmetrised in (b,c) and packed, [o][v][P_v]
   // (X1 itself is then dropped)
@@ -710,8 +712,31 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     // A0 is antisymmetric in (a,b) and A1 in (I,J) (so are all their terms):
     // their factors are kept with that pair packed
     const int64_t Pv = I.Pv, Po = I.Po;
-    I.E0h = tnew(cx, {o, Pv, v + o}, false);
-    launch_pack_pairs(I.E0.p, I.E0h.p, o, v, v + o, I.pair_v, cx.stream);
+    // E0h [i][P_v][2v+o]: E0 packed in (a<b), and a third block that carries
+    // the x W5 term of the doubles output into the A0 product: after
+    // P(IJ)P(AB), x sum_a conj(W5_JAaB) y_Ia equals P(IJ) of
+    // -x sum_a conj(W5_IAaB - W5_IBaA) y_Ja over A<B, i.e. the factor
+    // -conj(W5_iAaB - W5_iBaA) against x y_ja on the trial side
+    const int64_t q0 = (int64_t)v + o, qw = 2 * (int64_t)v + o;
+    I.E0h = tnew(cx, {o, Pv, qw}, false);
+    if (Pv > 0) {
+      Tensor tmp = tnew(cx, {Pv, q0}, false);
+      Tensor w5t = tnew(cx, {v, v, v}, false);
+      Tensor w5h = tnew(cx, {Pv, v}, false);
+      for (int i = 0; i < o; ++i) {
+        launch_pack_pairs(I.E0.p + (int64_t)i * v * v * q0, tmp.p, 1, v, q0, I.pair_v, cx.stream);
+        Tensor d0 = tensor_view(I.E0h.p + (int64_t)i * Pv * qw, {Pv, q0}, {qw, 1});
+        perm(cx, C1(), tmp, "Pq", false, C0(), d0, "Pq");
+        Tensor w5i = tensor_view(I.W5.p + (int64_t)i * v * v * v, {v, v, v}, {});
+        perm(cx, C1(), w5i, "AaB", false, C0(), w5t, "ABa");
+        launch_pack_pairs(w5t.p, w5h.p, 1, v, v, I.pair_v, cx.stream, 1);
+        Tensor d1 = tensor_view(I.E0h.p + (int64_t)i * Pv * qw + q0, {Pv, v}, {qw, 1});
+        perm(cx, CR(-1.0), w5h, "Pa", true, C0(), d1, "Pa");
+      }
+      tfree(cx, w5h);
+      tfree(cx, w5t);
+      tfree(cx, tmp);
+    }
     I.E1h = tnew(cx, {Po, v, 2 * o + v}, false);
     launch_pack_pairs(I.E1.p, I.E1h.p, 1, o, (int64_t)v * (2 * o + v), I.pair_o, cx.stream);
     if (Po > 0) {
@@ -973,8 +998,9 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   //        Z1_bc = sum_ia <ib||ac> y_ia; the last term is -x/2 conj(W_IJiB) y_iA
   //        relabelled a <-> b, which P(ab) leaves unchanged up to the sign taken here
   {
-    // at x = 0 the x parts of B0, B1 stay zero
-    Tensor B0 = tnew(cx, {k, o, v + o}, x == 0.0);
+    // at x = 0 the x parts of B0, B1 stay zero; outside a tape B0 has a third
+    // block, x y_ja, for the W5 term folded into E0h
+    Tensor B0 = tnew(cx, {k, o, half ? 2 * v + o : v + o}, x == 0.0);
     Tensor B1 = tnew(cx, {k, v, 2 * o + v}, x == 0.0);
     Tensor b0c = tslice(B0, 2, 0, v), b0k = tslice(B0, 2, v, v + o);
     Tensor b1k = tslice(B1, 2, 0, o), b1c = tslice(B1, 2, o, o + v), b1i = tslice(B1, 2, o + v, 2 * o + v);
@@ -990,6 +1016,10 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       perm(cx, CR(x), Z1, "zBc", false, C0(), b1c, "zBc");
       tfree(cx, Z1);
       perm(cx, CR(0.5 * x), ys, "ziB", false, C0(), b1i, "zBi");
+      if (half) {
+        Tensor b0w = tslice(B0, 2, v + o, 2 * v + o);
+        perm(cx, CR(x), ys, "zja", false, C0(), b0w, "zja");
+      }
     }
     if (half) {
       ctr(cx, C1(), I.E0h, "iPq", false, B0, "zjq", false, C0(), A0, "zijP");
@@ -1014,9 +1044,13 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
       tfree(cx, Z4);
     }
-    ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C0(), A2, "zIJAB");
-    // (outside a tape the W6 term is part of the E1h product into A1)
-    if (!half) ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
+    // (outside a tape the W5 and W6 terms are part of the E0h and E1h
+    // products into A0 and A1, and the ring term below is the first to
+    // write A2)
+    if (!half) {
+      ctr(cx, CR(x), I.W5, "JAaB", true, ys, "zIa", false, C0(), A2, "zIJAB");
+      ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
+    }
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
     // through P(ij)) and ring; the particle ladder runs packed below
     if (half) {
@@ -1042,12 +1076,12 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       g.om.nm = 3; g.om.md[0] = k; g.om.md[1] = o; g.om.md[2] = v;
       g.om.ms[0] = (int64_t)o * o * v * v; g.om.ms[1] = (int64_t)o * v * v; g.om.ms[2] = v;
       g.om.nn = 2; g.om.nd[0] = o; g.om.nd[1] = v; g.om.ns[0] = (int64_t)v * v; g.om.ns[1] = 1;
-      g.alpha = CR(-x); g.beta = C1(); g.tag = 0;
+      g.alpha = CR(-x); g.beta = half ? C0() : C1(); g.tag = 0;
       gemm_bf16p(cx, g);
       cx.pool.put((double2*)Rq);
       Rq = nullptr;
     } else {
-      ctr(cx, CR(-x), Ya, "zikac", false, I.ring, "kcjb", false, C1(), A2, "zijab");
+      ctr(cx, CR(-x), Ya, "zikac", false, I.ring, "kcjb", false, half ? C0() : C1(), A2, "zijab");
     }
   }
   if (half) {
