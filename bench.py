@@ -25,7 +25,7 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
 # HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain 1 GiB copy) of one
 # split-bf16 ladder term at this workload, from the counter runs summarised in
 # profiles/ladder_c2_split_bf16.md; None for the other precisions (not measured)
-LADDER_TRAFFIC_BYTES = {"split_bf16": 7.175e9 + 1.511e9}
+LADDER_TRAFFIC_BYTES = {"split_bf16": 7.230e9 + 1.511e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}
 
 
