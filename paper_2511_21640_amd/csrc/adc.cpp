@@ -77,6 +77,7 @@ struct Inst {
   // (j,b) and columns (k,c) (ringKp = o*v padded to 32)
   Tensor X2h, tIJ;
   Tensor oooo_p;  // <kl||ij> with the pair (k<l) packed, [P_o][o][o]
+  Tensor oooo_pp; // <kl||ij> with both pairs packed, [P_o(kl)][P_o(ij)]
   Tensor ooov_p;  // <kl||ja> with the pair (k<l) packed, [P_o][o][v]
   Tensor tpp;     // t1 with both pairs packed, [P_o][P_v]
   unsigned short* ringq = nullptr;
@@ -760,6 +761,8 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     launch_pack_pairs(t.p, I.tIJ.p, 1, o, (int64_t)v * v, I.pair_o, cx.stream);
     I.oooo_p = tnew(cx, {Po, o, o}, false);
     launch_pack_pairs(I.oooo.p, I.oooo_p.p, 1, o, (int64_t)o * o, I.pair_o, cx.stream);
+    I.oooo_pp = tnew(cx, {Po, Po}, false);
+    launch_pack_pairs(I.oooo_p.p, I.oooo_pp.p, Po, o, 1, I.pair_o, cx.stream);
     I.ooov_p = tnew(cx, {Po, o, v}, false);
     launch_pack_pairs(I.ooov.p, I.ooov_p.p, 1, o, (int64_t)o * v, I.pair_o, cx.stream);
     I.tpp = tnew(cx, {Po, Pv}, false);
@@ -1052,13 +1055,10 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
       ctr(cx, CR(x), I.W6, "IBJi", true, ys, "ziA", false, C1(), A2, "zIJAB");
     }
     // M22(1): hole ladder (already antisymmetric in ij, so half of it goes
-    // through P(ij)) and ring; the particle ladder runs packed below
-    if (half) {
-      // both factors antisymmetric in (k,l): the pairs k<l twice, read from
-      // the packed doubles
-      Tensor Yp = tensor_view(const_cast<double2*>(Y) + n1, {k, Po, Pv}, {dim, Pv, 1});
-      ctr(cx, CR(0.5 * x), I.oooo_p, "Kij", false, Yp, "zKP", false, C1(), A0, "zijP");
-    } else {
+    // through P(ij)) and ring; the particle ladder runs packed below.  Outside
+    // a tape the hole ladder is antisymmetric in both pairs and goes straight
+    // into the packed sigma after the pack (below)
+    if (!half) {
       ctr(cx, CR(0.25 * x), I.oooo, "klij", false, Ya, "zklab", false, C1(), A0, "zijab");
     }
     if (ring_planes) {
@@ -1087,6 +1087,14 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
   if (half) {
     launch_pack_ee_half(A0.p, A1.p, A2.p, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v, cx.stream,
                         acc32 ? 1 : 0);
+    if (x != 0.0 && Po > 0) {
+      // hole ladder: sigma_ijab += x sum_{k<l} <kl||ij> Y_klab for i<j, a<b,
+      // both factors read pair-packed (P(ij) of the half sum over ordered
+      // (i,j) gives the same)
+      Tensor Yp = tensor_view(const_cast<double2*>(Y) + n1, {k, Po, Pv}, {dim, Pv, 1});
+      Tensor Sp = tensor_view(S + n1, {k, Po, Pv}, {dim, Pv, 1});
+      ctr(cx, CR(x), I.oooo_pp, "KI", false, Yp, "zKP", false, C1(), Sp, "zIP");
+    }
   } else {
     rec_pack_ee(cx, A0, A1, A2, S, Y, dim, n1, k, o, v, I.eps, I.pair_o, I.pair_v);
   }
@@ -1321,7 +1329,7 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   // planes are kept per layout (at most their own size in bytes) and reused
   // by every sigma build
   for (Tensor* t : {&I.oooo, &I.ooov, &I.oovv, &I.ovov, &I.ovvv, &I.ring, &I.t1, &I.W, &I.W5, &I.W6, &I.E0, &I.E1,
-                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h, &I.X2h, &I.tIJ, &I.oooo_p, &I.ooov_p, &I.tpp})
+                    &I.X1, &I.X2, &I.E0h, &I.E1h, &I.th, &I.X1h, &I.X2h, &I.tIJ, &I.oooo_p, &I.oooo_pp, &I.ooov_p, &I.tpp})
     if (t->p) split_freeze(cx, t->p, t->size(), t->size() * (int64_t)sizeof(double2));
   // host copy of diag(M11x) for the Davidson guesses
   {
