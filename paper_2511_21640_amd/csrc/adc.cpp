@@ -767,6 +767,19 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     launch_pack_pairs(I.ooov.p, I.ooov_p.p, 1, o, (int64_t)o * v, I.pair_o, cx.stream);
     I.tpp = tnew(cx, {Po, Pv}, false);
     launch_pack_pairs(I.th.p, I.tpp.p, 1, o, Pv, I.pair_o, cx.stream);
+    if (Po > 0 && Pv > 0) {
+      // the x t.Z4 term of the doubles output, -x sum_{k<l} t_klAB Z4_klJI
+      // with Z4_klJI = sum_a <kl||Ja> y_Ia, is -x sum_a U_JaP y_Ia with the
+      // trial-independent U_JaP = sum_{k<l} <kl||Ja> t_klP; under P(IJ) it
+      // equals +x sum_a U_iaP y_ja, so U joins the third block of E0h
+      // (already met by x y_ja)
+      Tensor U = tnew(cx, {o, v, Pv}, false);
+      ctr(cx, C1(), I.ooov_p, "KJa", false, I.tpp, "KP", false, C0(), U, "JaP");
+      const int64_t q0 = (int64_t)v + o, qw = 2 * (int64_t)v + o;
+      Tensor e3 = tensor_view(I.E0h.p + q0, {o, Pv, v}, {Pv * qw, qw, 1});
+      perm(cx, C1(), U, "iaP", false, C1(), e3, "iPa");
+      tfree(cx, U);
+    }
     // planes of the ring matrix [k][c][j][b]: rows (j,b), columns (k,c)
     const int64_t ov = (int64_t)o * v;
     I.ringKp = pad32(ov);
@@ -1035,13 +1048,8 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     tfree(cx, B1);
   }
   if (x != 0.0) {
-    if (half) {
-      // Z4 and t are both antisymmetric in (k,l): the pairs k<l twice
-      Tensor Z4 = tnew(cx, {k, Po, o, o}, false);
-      ctr(cx, C1(), I.ooov_p, "KJa", false, ys, "zIa", false, C0(), Z4, "zKJI");
-      ctr(cx, CR(-x), I.tpp, "KP", false, Z4, "zKJI", false, C1(), A0, "zIJP");
-      tfree(cx, Z4);
-    } else {
+    // (outside a tape the t.Z4 term is part of the E0h product into A0)
+    if (!half) {
       Tensor Z4 = tnew(cx, {k, o, o, o, o}, false);
       ctr(cx, C1(), I.ooov, "klJa", false, ys, "zIa", false, C0(), Z4, "zklJI");
       ctr(cx, CR(-0.5 * x), t, "klAB", false, Z4, "zklJI", false, C1(), A0, "zIJAB");
