@@ -708,7 +708,6 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     Tensor g = tslice(I.E1, 3, o + v, 2 * o + v);
     perm(cx, C1(), I.W, "IJiA", true, C0(), g, "IJAi");
   }
-  build_sx(cx, I, I.x, I.X1, I.X2, cx.tape ? nullptr : &I.X1h, cx.tape ? nullptr : &I.X2h);
   if (!cx.tape) {
     // A0 is antisymmetric in (a,b) and A1 in (I,J) (so are all their terms):
     // their factors are kept with that pair packed
@@ -792,6 +791,8 @@ void ee_init(adc_handle* h, Inst& I, Pre& P, const std::vector<double>& eps_h) {
     tfree(cx, I.E0);
     tfree(cx, I.E1);
   }
+  // after the pair-packed factors: X1h takes the V2 term through U
+  build_sx(cx, I, I.x, I.X1, I.X2, cx.tape ? nullptr : &I.X1h, cx.tape ? nullptr : &I.X2h);
 }
 
 // ============================================================================
@@ -816,6 +817,16 @@ void build_sx(Ctx& cx, const Inst& I, double x, Tensor& X1, Tensor& X2, Tensor* 
       *X1h = tnew(cx, {o, v, I.Pv}, false);
       launch_pack_pairs(X1.p, X1h->p, (int64_t)o * v, v, 1, I.pair_v, cx.stream, 1);
       tfree(cx, X1);
+      if (I.ooov_p.p && I.tpp.p && I.Po > 0) {
+        // the x V2 term of the singles output, -x/4 sum_{Jkl} conj(<kl||Ja>)
+        // V2_iJkl with V2_iJkl = sum_AB conj(t_klAB) Y_iJAB, equals
+        // -x sum_{J,A<B} conj(U_JaAB) Y_iJAB with the trial-independent
+        // U_JaP = sum_{k<l} <kl||Ja> t_klP: it joins X1h
+        Tensor U = tnew(cx, {o, v, I.Pv}, false);
+        ctr(cx, C1(), I.ooov_p, "KJa", false, I.tpp, "KP", false, C0(), U, "JaP");
+        perm(cx, CR(-x), U, "jaP", true, C1(), *X1h, "jaP");
+        tfree(cx, U);
+      }
     }
     X2 = tnew(cx, {o, o, o, v}, false);
     perm(cx, CR(-0.5), I.ooov, "jkib", false, C0(), X2, "jkib");
@@ -979,20 +990,13 @@ void ee_sigma(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int p
     else ctr(cx, CR(-1.0), t, "IkAB", true, Ya, "zJIAB", false, C0(), r2, "zkJ");
     ctr(cx, CR(0.5 * x), I.ooov, "ikJa", true, r2, "zkJ", false, C1(), s1, "zia");
     tfree(cx, r2);
-    Tensor V2 = tnew(cx, {k, o, o, o, o}, false);
-    if (half) {
-      // V2 is antisymmetric in (i,J): from the packed doubles (pairs i<J and
-      // A<B as stored) and unpacked in (i,J)
-      Tensor V2p = tnew(cx, {k, Po, o, o}, false);
-      Tensor Yp = tensor_view(const_cast<double2*>(Y) + n1, {k, Po, Pv}, {dim, Pv, 1});
-      ctr(cx, CR(2.0), I.th, "klP", true, Yp, "zpP", false, C0(), V2p, "zpkl");
-      launch_unpack_doubles(1, V2p.p, Po * o * o, 0, k, o, o * o, V2.p, nullptr, cx.stream);
-      tfree(cx, V2p);
-    } else {
+    // (outside a tape the V2 term is part of the X1h product above)
+    if (!half) {
+      Tensor V2 = tnew(cx, {k, o, o, o, o}, false);
       ctr(cx, C1(), t, "klAB", true, Ya, "ziJAB", false, C0(), V2, "ziJkl");
+      ctr(cx, CR(-0.25 * x), I.ooov, "klJa", true, V2, "ziJkl", false, C1(), s1, "zia");
+      tfree(cx, V2);
     }
-    ctr(cx, CR(-0.25 * x), I.ooov, "klJa", true, V2, "ziJkl", false, C1(), s1, "zia");
-    tfree(cx, V2);
   }
   // ---------------- doubles output: every term goes, with its coefficient,
   // into the accumulator of the antisymmetriser it needs (P(ij): A0, P(ab):
