@@ -334,10 +334,15 @@ def _eval(ints: Ints, term: str, out_labels: str, in_labels: str, Yu: np.ndarray
         subs.append("".join(sub.get(c, c) for c in lab))
     ysub = "z" + "".join(sub.get(c, c) for c in in_labels)
     spec = ",".join(subs + [ysub]) + "->z" + out_labels
-    return float(coef) * np.einsum(spec, *ops, Yu, optimize=True)
+    return float(coef) * np.einsum(spec, *ops, Yu, optimize=_PATH)
 
 
 _EXT = set("ijabIJAB")
+# contraction order of a term line: numpy's path search, allowed
+# intermediates of up to 2^28 elements (its default cap, the largest operand,
+# can leave no pairwise step and fall back to one nested loop over every
+# label); the order does not change what is summed
+_PATH = ("optimal", 1 << 28)
 
 
 def _dense_term(ints: Ints, term: str, out_labels: str, in_labels: str, swap: bool) -> np.ndarray:
@@ -364,7 +369,7 @@ def _dense_term(ints: Ints, term: str, out_labels: str, in_labels: str, swap: bo
     all_labels = out_labels + "".join(free_in)
     present = set("".join(subs))
     red_labels = "".join(c for c in all_labels if c in present)
-    red = np.einsum(",".join(subs) + "->" + red_labels, *ops, optimize=True)
+    red = np.einsum(",".join(subs) + "->" + red_labels, *ops, optimize=_PATH)
     size = {c: (ints.o if c in OCC else ints.v) for c in out_labels + in_labels}
     full = np.zeros([size[c] for c in out_labels + in_labels], dtype=np.complex128)
     grids = np.indices([size[c] for c in all_labels])
@@ -394,15 +399,27 @@ def m11_block(ints: Ints, kind: str, order: int) -> np.ndarray:
     return ints._amp[key]
 
 
-def sigma_block(ints: Ints, kind: str, block: str, order: int, Y_in: np.ndarray) -> np.ndarray:
+DENSE_SINGLES_MAX = 512
+
+
+def sigma_block(ints: Ints, kind: str, block: str, order: int, Y_in: np.ndarray,
+                dense_singles: bool | None = None) -> np.ndarray:
     """Contribution of block ``block`` ('11','12','21','22') at perturbation
     order ``order`` to sigma, for packed input vectors Y_in (k, n_in).
-    Returns packed (k, n_out)."""
+    Returns packed (k, n_out).
+
+    The singles block is applied either as the dense matrix of m11_block or
+    matrix-free, term line by term line like the other blocks (the same
+    lines; forming it densely costs far more than applying the lines to a few
+    vectors once n1 is in the thousands).  Default: dense for n1 <= 512."""
     o, v = ints.o, ints.v
     r, c = int(block[0]), int(block[1])
     k = Y_in.shape[0]
-    if block == "11":
-        return Y_in @ m11_block(ints, kind, order).T
+    if block == "11" and order > 0:
+        if dense_singles is None:
+            dense_singles = dims(kind, o, v)[0] <= DENSE_SINGLES_MAX
+        if dense_singles:
+            return Y_in @ m11_block(ints, kind, order).T
     if order == 0:
         if r != c:
             return np.zeros((k, dims(kind, o, v)[r - 1]), dtype=np.complex128)

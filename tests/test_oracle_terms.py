@@ -90,3 +90,17 @@ def test_c1_davidson_vs_dense_eigh():
     d = np.concatenate([diag0(ints, "EE", 1), diag0(ints, "EE", 2)])
     wd, X, rn, it, conv = davidson(lambda Y: sigma(ints, "EE", P.x, Y), d, np.diag(M).real[:n1], 4)
     assert np.abs(wd - w).max() < 1e-10
+
+
+@pytest.mark.parametrize("kind,o,v", [("EE", 3, 6), ("IP", 4, 6), ("EA", 3, 7)])
+def test_dense_singles_block_equals_matrix_free(kind, o, v):
+    """m11_block forms the singles block densely from the same term lines that
+    sigma applies matrix-free; both must agree (the dense form serves the
+    Davidson guesses of the tests)."""
+    from oracle.adc_terms import m11_block, sigma_block
+    P = make_problem(kind, o, v, 20, seed=31, scale=0.3)
+    ints = Ints(P.eps, P.L, o)
+    E = np.eye(dims(kind, o, v)[0], dtype=complex)
+    for od in range(4):
+        mf = sigma_block(ints, kind, "11", od, E, dense_singles=False).T
+        assert np.abs(m11_block(ints, kind, od) - mf).max() < 1e-14, od
