@@ -86,8 +86,12 @@ typedef struct adc_problem {
  *   conv_tol      residual norm threshold of the Davidson solver [1e-7]
  *   max_iter      Davidson iterations [200]
  *   max_subspace  subspace size before collapse to 2k [6k]
- *   refine_fp64   mixed precision only: after convergence, continue in FP64
- *                 until the FP64 residual meets conv_tol [1]
+ *   refine_fp64   mixed precision only: 0 or 1 = iterate in the reduced
+ *                 precision to a residual of 1e-4 (or conv_tol if larger),
+ *                 then restart from the Ritz vectors in FP64 until the FP64
+ *                 residual meets conv_tol [0 = 1]; -1 = no FP64 restart: the
+ *                 reduced-precision sweep itself iterates to conv_tol and
+ *                 the reported residuals are its own
  *   stream        hipStream_t to enqueue on; NULL = a library-owned stream
  *   mem_budget    bytes of device workspace: sizes the <ab||cd> batches,
  *                 the largest temporary copy a contraction may make before it
@@ -104,7 +108,19 @@ typedef struct adc_problem {
  *   graphs        1 = replay each small instance's sigma build from a
  *                 captured hipGraph inside adc_davidson [0]
  *   autotune      1 = time the tile and split-K candidates of every GEMM
- *                 shape class once and keep the fastest [0] */
+ *                 shape class once and keep the fastest [0]
+ *   tune_cache    path of a text file of tuned GEMM choices (one shape class
+ *                 per line) or NULL [NULL]: read at adc_init when it exists,
+ *                 so that with autotune on the shape classes it holds are not
+ *                 timed again; written back (every class tuned in the
+ *                 process) at adc_free when autotune is on; a file that
+ *                 cannot be read is ignored
+ *   deterministic 1 = every tile and split-K choice comes from the fixed
+ *                 cost model (autotune and tune_cache are ignored), so that
+ *                 repeated calls with the same inputs and options give
+ *                 bitwise identical results on the same device [0]; the
+ *                 library has no atomics in its arithmetic, so only timed
+ *                 choices can change rounding between runs */
 typedef struct adc_options {
   int precision;
   double conv_tol;
@@ -117,38 +133,64 @@ typedef struct adc_options {
   int n_streams;
   int graphs;
   int autotune;
+  const char* tune_cache;
+  int deterministic;
 } adc_options;
 
 typedef struct adc_handle adc_handle;
 
-/* Validate the problems (n_problems >= 1 independent instances, each of any
- * kind and size), copy eps (and L unless borrowed) to the device and run the
- * one-off work of every instance on the device: the stored integral classes <ij||kl>,
- * <ij||ka>, <ij||ab>, <ia||jb>, <ia||bc>; the MP amplitudes t(1), t(2) (with one pass
- * of the particle-particle ladder), the second-order singles; the dense
- * singles block M11 with its third-order part kept separate so that x scales
- * it.  Errors: INVALID_ARG (shapes, NULL pointers, n_problems < 1),
- * NONFINITE_INPUT (NaN/Inf in eps or L), NOT_HERMITIAN (max |L^Q - L^Q^H| >
- * 1e-12 max |L^Q| for some Q), OUT_OF_MEMORY, HIP_ERROR.  On error *out is
- * NULL and nothing is leaked.  Synchronous. */
+/* Set up n_problems >= 1 independent instances (each of any kind and size)
+ * for the secular problem of Section 2.1, eq. 10 with M(x) of eq. 11 and the
+ * sm-ADC scaling: validate them, copy eps (and L unless borrowed) to the
+ * device and run the one-off work of every instance on the device.  That is
+ * the stored antisymmetrised integral classes <ij||kl>, <ij||ka>, <ij||ab>,
+ * <ia||jb>, <ia||bc>, each a sum over Cholesky vectors (Section 2.5, eq. 43);
+ * the MP amplitudes t(1), t(2) (with one pass of the particle-particle ladder)
+ * and the second-order singles, on which the intermediate states are built
+ * (Section 2.1, the CES applied to the MP ground state); the dense singles
+ * block M11 through third order with its third-order part kept separate so
+ * that x scales it.
+ *   problems   host array of n_problems entries (read during the call only)
+ *   opts       NULL = all defaults
+ *   out        receives the handle; NULL on error
+ * Errors: INVALID_ARG (shapes, NULL pointers, n_problems < 1),
+ * NONFINITE_INPUT (NaN/Inf in eps, x or L), NOT_HERMITIAN (max |L^Q - L^Q^H| >
+ * 1e-12 max |L^Q| for some Q; L^Q is Hermitian as the MO transform of real AO
+ * Cholesky vectors, eq. 42), OUT_OF_MEMORY, HIP_ERROR.  A borrowed device L
+ * is checked on the device, a host L on the host.  On error *out is NULL and
+ * nothing is leaked.  Synchronous. */
 int adc_init(const adc_problem* problems, int n_problems, const adc_options* opts,
              adc_handle** out);
 
-/* Sizes n1 (singles) and n2 (doubles) of instance inst; dim = n1 + n2. */
+/* Sizes n1 (singles) and n2 (doubles) of the intermediate-state basis of
+ * instance inst (Section 2.1, the CES classes of each kind), packed as
+ * described above; dim = n1 + n2.  Errors: INVALID_ARG. */
 int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2);
 
-/* S = M(x) Y for k packed c128 vectors.  Y and S are device arrays
- * [k][dim], must not alias, and stay owned by the caller.  precision < 0
- * uses the handle's default.  Enqueued on the handle's stream
- * (asynchronous).  Errors: INVALID_ARG, HIP_ERROR. */
+/* The sigma build S = M(x) Y for k packed c128 vectors: the product of the
+ * secular matrix of Section 2.1 (eq. 10; blocks by order as in eq. 11, the
+ * third-order part scaled by x as in sm-ADC) with trial vectors, as the
+ * Davidson solver of eq. 10 needs it.  The four-external <ab||cd> are
+ * rebuilt from L batch by batch on every call (Section 2.5, eq. 43 and the
+ * on-the-fly generation of the four-external integrals), never stored.
+ * Y and S are device arrays [k][dim], must not alias, and stay owned by the
+ * caller.  precision < 0 uses the handle's default.  Enqueued on the
+ * handle's stream (asynchronous).  Workspace comes from the handle's device
+ * pool (allocated on first use and kept).  Errors: INVALID_ARG, HIP_ERROR,
+ * OUT_OF_MEMORY. */
 int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precision);
 
-/* Block Davidson for the n_roots lowest eigenpairs of every instance.  The
+/* Block Davidson for the n_roots lowest eigenpairs of every instance
+ * (Section 2.1, eq. 10: M X = X Omega, X^H X = 1, with sigma builds as
+ * above; the paper's Davidson settings are not printed, so the guess,
+ * preconditioner and convergence rules are this library's).  The
  * per-root outputs are concatenated over the instances in order (instance i
  * starts at the sum of n_roots of instances < i); the lanes solve their
  * instances concurrently.
  *   guess        NULL, or guess[inst] = NULL or device c128 [n_roots][dim]
- *                start vectors (resume)
+ *                start vectors (resume); when they span fewer than n_roots
+ *                directions the rest is filled with the default unit-vector
+ *                guesses outside their span (INVALID_ARG if that fails)
  *   omega        host float64 [sum n_roots], ascending per instance, hartree
  *   vecs         NULL, or vecs[inst] = NULL or device c128 [n_roots][dim]
  *                output Ritz vectors
@@ -166,7 +208,9 @@ int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* c
 /* One term of the sigma build, for per-term checks and timing:
  *   ADC_TERM_ALL      same as adc_sigma
  *   ADC_TERM_LADDER   S = x * (particle-particle ladder) Y: the doubles part
- *                     sum_{c<d} <ab||cd> Y_..cd built batch-wise from L
+ *                     sum_{c<d} <ab||cd> Y_..cd, the <ab||cd> built batch-wise
+ *                     from L (Section 2.5, eq. 43, generated on the fly), the
+ *                     term part of the first-order doubles block of eq. 11
  *                     (EE and EA; singles part of S set to zero)
  * Same argument rules as adc_sigma.  Errors: INVALID_ARG, UNSUPPORTED (the
  * term does not exist for the kind), HIP_ERROR. */

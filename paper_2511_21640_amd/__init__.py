@@ -40,7 +40,15 @@ class AdcOptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("conv_tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("max_subspace", ctypes.c_int), ("refine_fp64", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_budget", ctypes.c_size_t), ("verbose", ctypes.c_int), ("n_streams", ctypes.c_int),
-                ("graphs", ctypes.c_int), ("autotune", ctypes.c_int)]
+                ("graphs", ctypes.c_int), ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
+                ("deterministic", ctypes.c_int)]
+
+
+def _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose, n_streams,
+             graphs, autotune, tune_cache, deterministic):
+    return AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1 if refine_fp64 else -1,
+                      ctypes.c_void_p(stream), mem_budget, int(verbose), int(n_streams), 1 if graphs else 0,
+                      1 if autotune else 0, tune_cache.encode() if tune_cache else None, 1 if deterministic else 0)
 
 
 class AdcError(RuntimeError):
@@ -97,7 +105,8 @@ class Handle:
     """
 
     def __init__(self, kind, o, v, eps, L, n_roots, x=1.0, precision="fp64", conv_tol=1e-7, max_iter=200,
-                 max_subspace=0, stream=None, mem_budget=0, verbose=False, graphs=False, autotune=False):
+                 max_subspace=0, stream=None, mem_budget=0, verbose=False, graphs=False, autotune=False,
+                 refine_fp64=True, tune_cache=None, deterministic=False):
         import torch
         self._lib = load()
         self.kind, self.o, self.v = kind, int(o), int(v)
@@ -118,8 +127,8 @@ class Handle:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
-        opts = AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1, ctypes.c_void_p(stream),
-                          mem_budget, int(verbose), 0, 1 if graphs else 0, 1 if autotune else 0)
+        opts = _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose, 0,
+                        graphs, autotune, tune_cache, deterministic)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(ctypes.byref(prob), 1, ctypes.byref(opts), ctypes.byref(h))
         if rc != ADC_OK:
@@ -186,8 +195,14 @@ class Handle:
         return dL, (dx.value if want_dx else None)
 
     def davidson(self, guess=None, want_vectors=True):
+        """Lowest n_roots eigenpairs.  guess: optional complex128 cuda tensor
+        [n_roots][dim] of start vectors (contiguous)."""
         import torch
         k = self.n_roots
+        if guess is not None:
+            if not (hasattr(guess, "is_cuda") and guess.is_cuda and guess.dtype == torch.complex128
+                    and guess.is_contiguous() and tuple(guess.shape) == (k, self.dim)):
+                raise ValueError(f"guess must be a contiguous complex128 cuda tensor of shape ({k}, {self.dim})")
         omega = np.zeros(k)
         res = np.zeros(k)
         iters = (ctypes.c_int * 1)()
@@ -221,7 +236,8 @@ class Batch:
     n_streams lanes (longest first) and solved concurrently."""
 
     def __init__(self, problems, precision="fp64", conv_tol=1e-7, max_iter=200, max_subspace=0, stream=None,
-                 mem_budget=0, verbose=False, n_streams=0, graphs=False, autotune=False):
+                 mem_budget=0, verbose=False, n_streams=0, graphs=False, autotune=False, refine_fp64=True,
+                 tune_cache=None, deterministic=False):
         import torch
         self._lib = load()
         self._keep = []
@@ -235,8 +251,8 @@ class Batch:
                                 float(p.get("x", 1.0)))
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
-        opts = AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1, ctypes.c_void_p(stream), mem_budget,
-                          int(verbose), int(n_streams), 1 if graphs else 0, 1 if autotune else 0)
+        opts = _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose,
+                        n_streams, graphs, autotune, tune_cache, deterministic)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
         self._keep = []  # host copies are no longer needed

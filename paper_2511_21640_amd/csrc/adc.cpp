@@ -23,6 +23,7 @@
 #include <mutex>
 #include <new>
 #include <stdexcept>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -118,6 +119,7 @@ struct adc_handle {
   std::vector<void*> raw;                   // plain device allocations
   std::mutex mu;                            // guards raw
   int device = 0;
+  std::string tune_path;                    // autotuner cache file, if any
   Ctx& lane(int i) { return i == 0 ? cx : *extra[(size_t)i - 1]; }
   int n_lanes() const { return 1 + (int)extra.size(); }
 };
@@ -207,6 +209,7 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   // map, the other precisions stage them in Yc, Sc
   const int64_t R = (int64_t)k * nrow;
   const bool bf = prec == ADC_SPLIT_BF16;
+  const int64_t Kq = pad32(N);  // K of the L_vv planes
   double2* Yc = bf ? nullptr : cx.pool.get(R * Pv);
   double2* Sc = bf ? nullptr : cx.pool.get(R * Pv);
   if (!bf) {
@@ -224,8 +227,11 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   unsigned short* Vp = nullptr;
   double2* Vbuf = nullptr;
   bool own_yp = false;
+  // split-bf16 planes of L_vv, kept in the instance after their first use
+  const unsigned short* Lq = nullptr;
   if (bf) {
     ensure_planes(h, I);
+    Lq = I.Lq;
     Vp = planes_alloc(cx, grp, Kv);
     SplitNd sp{};
     sp.src = Y + offY; sp.rows = R; sp.K = Pv; sp.Kp = Kv; sp.conj = 0;
@@ -298,9 +304,9 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
       const int64_t m = v - a0;
       const int64_t Mw = (int64_t)(a1 - a0) * m, Nw = (int64_t)(v - b0) * m;
       BfGemm g{};
-      g.M = Mw; g.N = Nw; g.Kp = I.Kq;
-      g.A = I.Lq + ((int64_t)a0 * v + a0) * I.Kq; g.lda = (int64_t)v * v; g.amd = m; g.ams = v;
-      g.B = I.Lq + ((int64_t)b0 * v + a0) * I.Kq; g.ldb = (int64_t)v * v; g.bmd = m; g.bms = v;
+      g.M = Mw; g.N = Nw; g.Kp = Kq;
+      g.A = Lq + ((int64_t)a0 * v + a0) * Kq; g.lda = (int64_t)v * v; g.amd = m; g.ams = v;
+      g.B = Lq + ((int64_t)b0 * v + a0) * Kq; g.ldb = (int64_t)v * v; g.bmd = m; g.bms = v;
       // W is stored as complex64: the GEMM accumulates in FP32 and the pack
       // rounds <ab||cd> to FP32 before splitting it
       g.C = Wbuf; g.scm = Nw; g.scn = 1; g.c32 = 1;
@@ -316,9 +322,9 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     const int64_t Mw = (int64_t)(a1 - a0) * v, Nw = (int64_t)(v - b0) * v;
     if (bf) {
       BfGemm g{};
-      g.M = Mw; g.N = Nw; g.Kp = I.Kq;
-      g.A = I.Lq + (int64_t)a0 * v * I.Kq; g.lda = (int64_t)v * v;
-      g.B = I.Lq + (int64_t)b0 * v * I.Kq; g.ldb = (int64_t)v * v;
+      g.M = Mw; g.N = Nw; g.Kp = Kq;
+      g.A = Lq + (int64_t)a0 * v * Kq; g.lda = (int64_t)v * v;
+      g.B = Lq + (int64_t)b0 * v * Kq; g.ldb = (int64_t)v * v;
       g.C = Wbuf; g.scm = Nw; g.scn = 1;
       g.alpha = C1(); g.beta = C0(); g.tag = 1;
       gemm_bf16p(cx, g);
@@ -1281,6 +1287,18 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
   Tensor Lown;
   if (p->L_on_device) {
     Ld = (double2*)p->L;
+    // the checks adc_init makes on a host L, made on the device: finite
+    // values and Hermitian L^Q (max |L^Q - L^Q^H| <= 1e-12 max |L^Q|)
+    double* chk = (double*)cx.pool.get((3 * (int64_t)N + 1) / 2);
+    launch_check_L(Ld, N, n, chk, cx.stream);
+    std::vector<double> hc(3 * (size_t)N);
+    hipcheck(hipMemcpyAsync(hc.data(), chk, sizeof(double) * hc.size(), hipMemcpyDeviceToHost, cx.stream), "check L");
+    hipcheck(hipStreamSynchronize(cx.stream), "check L sync");
+    cx.pool.put((double2*)chk);
+    for (int q = 0; q < N; ++q)
+      if (hc[3 * (size_t)q + 2] > 0.0) throw Status{ADC_ERR_NONFINITE_INPUT, "non-finite L"};
+    for (int q = 0; q < N; ++q)
+      if (hc[3 * (size_t)q] > 1e-12 * hc[3 * (size_t)q + 1]) throw Status{ADC_ERR_NOT_HERMITIAN, "L not Hermitian"};
   } else {
     Lown = tnew(cx, {N, n, n}, false);
     hipcheck(hipMemcpyAsync(Lown.p, p->L, sizeof(double2) * (size_t)N * n * n, hipMemcpyHostToDevice, cx.stream),
@@ -1663,36 +1681,54 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   double2* R = cx.pool.get((int64_t)k * dim);
   double* wd = (double*)cx.pool.get(k);
   int m = 0;
-  // initial vectors
-  if (guess) {
-    hipcheck(hipMemcpyAsync(V, guess, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "guess");
-    m = orthonormalize(cx, V, 0, V, k, dim);
-  } else {
+  // default guesses: unit vectors on the lowest diagonal entries of M11, then
+  // (more roots than singles) of the doubles' zeroth-order diagonal; the
+  // positions in that order, as many as asked for
+  auto unit_positions = [&](int want) {
+    std::vector<int64_t> pos;
     std::vector<int> idx(I.n1);
     for (int i = 0; i < (int)I.n1; ++i) idx[i] = i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return I.m11diag[a] < I.m11diag[b]; });
-    launch_fill(V, (int64_t)k * dim, C0(), cx.stream);
-    const int ng = (int)std::min<int64_t>(k, I.n1);
-    for (int r = 0; r < ng; ++r) {
-      double2 one = make_double2(1.0, 0.0);
-      hipcheck(hipMemcpyAsync(V + (int64_t)r * dim + idx[r], &one, sizeof(double2), hipMemcpyHostToDevice, cx.stream),
-               "unit");
-      hipcheck(hipStreamSynchronize(cx.stream), "unit sync");
-    }
-    // more roots than singles: seed with the lowest doubles diagonal
-    if (ng < k) {
+    for (int i = 0; i < (int)I.n1 && (int)pos.size() < want; ++i) pos.push_back(idx[i]);
+    if ((int)pos.size() < want) {
       std::vector<double> dd(dim);
       hipcheck(hipMemcpy(dd.data(), I.diag, sizeof(double) * dim, hipMemcpyDeviceToHost), "dd");
       std::vector<int64_t> id2(dim - I.n1);
       for (int64_t i = 0; i < (int64_t)id2.size(); ++i) id2[i] = I.n1 + i;
       std::stable_sort(id2.begin(), id2.end(), [&](int64_t a, int64_t b) { return dd[a] < dd[b]; });
-      for (int r = ng; r < k; ++r) {
-        double2 one = make_double2(1.0, 0.0);
-        hipcheck(hipMemcpyAsync(V + (int64_t)r * dim + id2[r - ng], &one, sizeof(double2), hipMemcpyHostToDevice,
-                                cx.stream), "unit2");
-        hipcheck(hipStreamSynchronize(cx.stream), "unit2 sync");
-      }
+      for (size_t i = 0; i < id2.size() && (int)pos.size() < want; ++i) pos.push_back(id2[i]);
     }
+    return pos;
+  };
+  auto put_units = [&](double2* dst, const std::vector<int64_t>& pos) {
+    launch_fill(dst, (int64_t)pos.size() * dim, C0(), cx.stream);
+    const double2 one = make_double2(1.0, 0.0);
+    for (size_t r = 0; r < pos.size(); ++r)
+      hipcheck(hipMemcpyAsync(dst + (int64_t)r * dim + pos[r], &one, sizeof(double2), hipMemcpyHostToDevice,
+                              cx.stream), "unit");
+    hipcheck(hipStreamSynchronize(cx.stream), "unit sync");
+  };
+  if (guess) {
+    hipcheck(hipMemcpyAsync(V, guess, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "guess");
+    m = orthonormalize(cx, V, 0, V, k, dim);
+    // a guess of lower rank (repeated or zero rows) is topped up with the
+    // default unit vectors that are not in its span, lowest diagonal first
+    if (m < k) {
+      const auto pos = unit_positions((int)std::min<int64_t>(dim, 3 * (int64_t)k + 8));
+      double2* T = cx.pool.get((int64_t)pos.size() * dim);
+      put_units(T, pos);
+      const int nt = orthonormalize(cx, V, m, T, (int)pos.size(), dim);
+      const int take = std::min(k - m, nt);
+      if (take > 0)
+        hipcheck(hipMemcpyAsync(V + (int64_t)m * dim, T, sizeof(double2) * take * dim, hipMemcpyDeviceToDevice,
+                                cx.stream), "top up");
+      hipcheck(hipStreamSynchronize(cx.stream), "top up sync");
+      cx.pool.put(T);
+      m += take;
+      if (m < k) throw Status{ADC_ERR_INVALID_ARG, "guess spans fewer than n_roots directions"};
+    }
+  } else {
+    put_units(V, unit_positions(k));
     m = k;
   }
   auto now = []() { return std::chrono::steady_clock::now(); };
@@ -1709,7 +1745,10 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   std::vector<double> w_old(k, 1e300), w(k), rn(k);
   std::vector<int> conv(k, 0);
   int it = 0;
-  bool refined_phase = (prec == 0);
+  // refine_fp64 < 0: a mixed-precision solve iterates to conv_tol in its own
+  // precision and reports its own residuals (no FP64 restart)
+  const bool refine = h->opt.refine_fp64 >= 0;
+  bool refined_phase = (prec == 0) || !refine;
   for (it = 1; it <= max_iter; ++it) {
     auto t_it = now();
     auto G = gram(cx, V, m, S, m, dim);
@@ -2133,6 +2172,16 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
       h->extra.emplace_back(new Ctx());
       hipcheck(hipStreamCreateWithFlags(&h->extra.back()->stream, hipStreamNonBlocking), "lane stream");
     }
+    if (h->opt.deterministic) {
+      h->opt.autotune = 0;
+      h->opt.tune_cache = nullptr;
+    }
+    // the cache path is the caller's string: keep a copy for adc_free
+    if (h->opt.tune_cache) {
+      h->tune_path = h->opt.tune_cache;
+      h->opt.tune_cache = nullptr;
+      (void)tune_cache_load(h->tune_path.c_str());
+    }
     for (int l = 0; l < L; ++l) {
       Ctx& c = h->lane(l);
       c.autotune = h->opt.autotune != 0;
@@ -2263,6 +2312,7 @@ double adc_init_ms(const adc_handle* h) { return h ? h->init_ms : 0.0; }
 
 void adc_free(adc_handle* h) {
   if (!h) return;
+  if (!h->tune_path.empty() && h->opt.autotune) (void)tune_cache_save(h->tune_path.c_str());
   if (h->cx.stream) (void)hipStreamSynchronize(h->cx.stream);
   for (auto& I : h->inst)
     if (I.cx) {

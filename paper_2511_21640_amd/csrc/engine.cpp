@@ -273,6 +273,44 @@ TuneChoice tune(Ctx& cx, const std::vector<TuneChoice>& cand, F&& fn) {
 
 }  // namespace
 
+// Tuned choices as text, one shape class per line:
+//   fam prec tag lm ln lk lb tile nsplit
+// Loading merges the file into the process-wide table (entries already
+// present win); saving writes the whole table.  Returns the number of
+// entries read or written, or -1 if the file cannot be opened.
+int tune_cache_load(const char* path) {
+  if (!path || !*path) return 0;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return -1;
+  int n = 0;
+  TuneKey k{};
+  TuneChoice c{};
+  long long ns = 0;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  while (std::fscanf(f, "%d %d %d %d %d %d %d %d %lld", &k.fam, &k.prec, &k.tag, &k.lm, &k.ln, &k.lk, &k.lb,
+                     &c.tile, &ns) == 9) {
+    c.nsplit = std::max<int64_t>(1, (int64_t)ns);
+    if (g_tune.emplace(k, c).second) ++n;
+  }
+  std::fclose(f);
+  return n;
+}
+
+int tune_cache_save(const char* path) {
+  if (!path || !*path) return 0;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return -1;
+  int n = 0;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  for (const auto& e : g_tune) {
+    const TuneKey& k = e.first;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d %lld\n", k.fam, k.prec, k.tag, k.lm, k.ln, k.lk, k.lb, e.second.tile,
+                 (long long)e.second.nsplit);
+    ++n;
+  }
+  return std::fclose(f) == 0 ? n : -1;
+}
+
 void gemm(Ctx& cx, GemmDesc g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   const int64_t heur = heuristic_nsplit(g.M, g.N, g.K, g.batch, 128);

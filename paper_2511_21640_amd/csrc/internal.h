@@ -202,6 +202,10 @@ void launch_row_dots(const double2* X, int64_t ldx, const double2* Y, int64_t ld
 void launch_precondition(const double2* R, double2* N, const double* D, const double* w, int rows, int64_t n,
                          hipStream_t s);
 int row_dot_blocks(int64_t n);
+// per Cholesky vector Q of L [nq][n][n]: out[3Q] = max |Re L_pr - Re L_rp| +
+// |Im L_pr + Im L_rp|, out[3Q+1] = max |component|, out[3Q+2] = number of
+// non-finite components (one block per Q)
+void launch_check_L(const double2* L, int64_t nq, int64_t n, double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- engine
 struct Tensor {
@@ -357,6 +361,11 @@ unsigned short* split_planes_cached(Ctx& cx, const SplitNd& sp, int tiled);
 // cached planes; split_planes_only tells whether p points into such a buffer
 void split_cache_planes_only(Ctx& cx, int scope, const double2* src, int64_t n);
 bool split_planes_only(const Ctx& cx, const double2* p);
+
+// the autotuner's table of tuned shape classes, read from / written to a text
+// file (returns the entries read or written, -1 if the file cannot be opened)
+int tune_cache_load(const char* path);
+int tune_cache_save(const char* path);
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);

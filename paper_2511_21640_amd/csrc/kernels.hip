@@ -1782,6 +1782,48 @@ void launch_row_dots(const double2* X, int64_t ldx, const double2* Y, int64_t ld
   hipLaunchKernelGGL(row_dots_kernel, dim3(nb, rows), dim3(256), 0, s, X, ldx, Y, ldy, n, partial, nb);
 }
 
+// Input check of a device-resident L [nq][n][n]: per Cholesky vector Q, the
+// largest |Re L_pr - Re L_rp| + |Im L_pr + Im L_rp| (zero for Hermitian L^Q),
+// the largest |component| and the number of non-finite components, written
+// to out[3 Q .. 3 Q + 2]; one block per Q, rows of L read along r.
+__global__ __launch_bounds__(256) void check_L_kernel(const double2* L, int64_t n, double* out) {
+  const int64_t q = blockIdx.x;
+  const double2* Lq = L + q * n * n;
+  double dev = 0.0, mx = 0.0, bad = 0.0;
+  for (int64_t e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int64_t p = e / n, r = e - p * n;
+    const double2 a = Lq[e], b = Lq[r * n + p];
+    if (!isfinite(a.x) || !isfinite(a.y)) {
+      bad += 1.0;
+      continue;
+    }
+    mx = fmax(mx, fmax(fabs(a.x), fabs(a.y)));
+    if (isfinite(b.x) && isfinite(b.y)) dev = fmax(dev, fabs(a.x - b.x) + fabs(a.y + b.y));
+  }
+  __shared__ double sd[256], sm[256], sb[256];
+  sd[threadIdx.x] = dev;
+  sm[threadIdx.x] = mx;
+  sb[threadIdx.x] = bad;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + w]);
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[3 * q] = sd[0];
+    out[3 * q + 1] = sm[0];
+    out[3 * q + 2] = sb[0];
+  }
+}
+void launch_check_L(const double2* L, int64_t nq, int64_t n, double* out, hipStream_t s) {
+  if (nq <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(check_L_kernel, dim3((unsigned)nq), dim3(256), 0, s, L, n, out);
+}
+
 __global__ void precondition_kernel(const double2* R, double2* N, const double* D, const double* w, int rows,
                                     int64_t n) {
   const int64_t total = (int64_t)rows * n;

@@ -73,10 +73,18 @@ def test_validation_errors(lib):
     L[1, 2, 2] = np.inf
     p, keep = _problem(L=L)
     assert _init(lib, p)[0] == -2
-    # two problems: batched handles are not built
-    p, keep = _problem()
+    # a batch of two instances whose second entry is invalid is rejected on
+    # the host before any device work
+    p0, keep0 = _problem()
+    p1, keep1 = _problem(o=0)
+    arr = (adc.AdcProblem * 2)(p0, p1)
     h = ctypes.c_void_p()
-    assert lib.adc_init(ctypes.byref(p), 2, None, ctypes.byref(h)) == -1
+    assert lib.adc_init(arr, 2, None, ctypes.byref(h)) == -1
+    assert not h.value
+    # options out of range
+    opts = adc.AdcOptions()
+    opts.precision = 3
+    assert lib.adc_init(arr, 1, ctypes.byref(opts), ctypes.byref(h)) == -1
 
 
 def test_strerror(lib):

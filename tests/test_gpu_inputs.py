@@ -1,0 +1,99 @@
+"""Input handling on the device: start vectors given to the Davidson solver,
+checks of a borrowed device L, the no-refinement mixed solve, and
+deterministic builds.
+
+* a guess with repeated rows spans fewer than n_roots directions: the solver
+  tops it up with the default unit vectors outside its span and reaches the
+  same roots as the unguessed solve;
+* a valid guess (the converged vectors themselves) converges at once to the
+  same roots;
+* a borrowed (device) L that is not Hermitian, or holds a NaN, is refused with
+  the codes a host L gets (eq. 42: L^Q is Hermitian);
+* refine_fp64 off: the mixed sweep itself iterates to conv_tol;
+* deterministic: two builds on two handles are bitwise identical.
+"""
+import numpy as np
+import pytest
+
+from adcgen import make_problem
+
+torch = pytest.importorskip("torch")
+import paper_2511_21640_amd as adc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _h(P, **kw):
+    return adc.Handle(P.kind, P.o, P.v, P.eps, P.L, P.n_roots, x=P.x, **kw)
+
+
+def test_guess_with_repeated_rows_and_valid_guess():
+    P = make_problem("EE", 4, 12, 40, seed=61, n_roots=3, x=1.0, scale=0.2)
+    print("case guess EE 4/12/40 k=3", flush=True)
+    h = _h(P, conv_tol=1e-9)
+    ref = h.davidson()
+    assert ref["converged"].all()
+    rng = np.random.default_rng(61)
+    g = rng.standard_normal((3, h.dim)) + 1j * rng.standard_normal((3, h.dim))
+    g[2] = g[0]                      # rank 2
+    out = h.davidson(guess=torch.from_numpy(np.ascontiguousarray(g)).cuda())
+    assert out["converged"].all()
+    assert np.abs(out["omega"] - ref["omega"]).max() < 1e-9
+    # zero rows only: every direction comes from the top-up
+    out0 = h.davidson(guess=torch.zeros((3, h.dim), dtype=torch.complex128, device="cuda"))
+    assert np.abs(out0["omega"] - ref["omega"]).max() < 1e-9
+    # the converged vectors as the guess: converged in very few iterations
+    out2 = h.davidson(guess=ref["vectors"].contiguous())
+    assert out2["converged"].all()
+    assert out2["iters"] <= 3
+    assert np.abs(out2["omega"] - ref["omega"]).max() < 1e-9
+    # the binding refuses a guess of the wrong shape before any device work
+    with pytest.raises(ValueError):
+        h.davidson(guess=ref["vectors"][:2].contiguous())
+
+
+def test_borrowed_L_checks():
+    P = make_problem("EE", 3, 8, 20, seed=62, n_roots=2, scale=0.2)
+    print("case borrowed L checks", flush=True)
+    L = torch.from_numpy(P.L.copy()).cuda()
+    h = adc.Handle("EE", P.o, P.v, P.eps, L, 2, x=P.x)
+    hh = adc.Handle("EE", P.o, P.v, P.eps, P.L, 2, x=P.x)
+    Y = torch.from_numpy(np.random.default_rng(1).standard_normal((1, h.dim)) + 0j).cuda()
+    assert (h.sigma(Y) - hh.sigma(Y)).abs().max().item() == 0.0
+    h.close()
+    Lb = L.clone()
+    Lb[3, 1, 2] += 1e-6              # breaks L^Q = L^Q^H for Q = 3
+    with pytest.raises(adc.AdcError) as e:
+        adc.Handle("EE", P.o, P.v, P.eps, Lb, 2, x=P.x)
+    assert e.value.code == -3
+    Ln = L.clone()
+    Ln[5, 2, 2] = float("nan")
+    with pytest.raises(adc.AdcError) as e:
+        adc.Handle("EE", P.o, P.v, P.eps, Ln, 2, x=P.x)
+    assert e.value.code == -2
+
+
+def test_mixed_solve_without_refinement():
+    P = make_problem("EE", 5, 16, 60, seed=63, n_roots=3, x=0.5, scale=0.2)
+    print("case refine off", flush=True)
+    ref = _h(P, conv_tol=1e-9).davidson()
+    out = _h(P, precision="split_bf16", conv_tol=1e-6, refine_fp64=False).davidson()
+    assert out["converged"].all()
+    assert (out["resnorm"] <= 1e-6).all()
+    # eigenvalues of the split-bf16 matrix: its error is a few 1e-6 relative
+    # of the correlation part, far below the orbital-energy scale
+    assert np.abs(out["omega"] - ref["omega"]).max() < 1e-5
+
+
+def test_deterministic_builds_are_bitwise_identical():
+    P = make_problem("EE", 6, 40, 100, seed=64, n_roots=2, x=0.5, scale=0.1)
+    print("case deterministic", flush=True)
+    h1 = _h(P, precision="split_bf16", deterministic=True)
+    h2 = _h(P, precision="split_bf16", deterministic=True)
+    Y = torch.from_numpy(np.random.default_rng(2).standard_normal((4, h1.dim))
+                         + 1j * np.random.default_rng(3).standard_normal((4, h1.dim))).cuda()
+    for prec in ("split_bf16", "fp32", "fp64"):
+        a = h1.sigma(Y, precision=prec)
+        b = h1.sigma(Y, precision=prec)
+        c = h2.sigma(Y, precision=prec)
+        assert torch.equal(a, b) and torch.equal(a, c), prec
