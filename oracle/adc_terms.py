@@ -334,7 +334,7 @@ def _eval(ints: Ints, term: str, out_labels: str, in_labels: str, Yu: np.ndarray
         subs.append("".join(sub.get(c, c) for c in lab))
     ysub = "z" + "".join(sub.get(c, c) for c in in_labels)
     spec = ",".join(subs + [ysub]) + "->z" + out_labels
-    return float(coef) * np.einsum(spec, *ops, Yu, optimize=_PATH)
+    return float(coef) * contract(spec, *ops, Yu)
 
 
 _EXT = set("ijabIJAB")
@@ -343,6 +343,62 @@ _EXT = set("ijabIJAB")
 # can leave no pairwise step and fall back to one nested loop over every
 # label); the order does not change what is summed
 _PATH = ("optimal", 1 << 28)
+
+
+def contract(spec: str, *ops: np.ndarray) -> np.ndarray:
+    """np.einsum(spec, *ops) for a spec with explicit output, evaluated pair
+    by pair in the order numpy's path search picks, every pair as one batched
+    matrix product (labels shared by both factors and still needed later are
+    the batch; labels needed nowhere later are summed first).  The same sum
+    as einsum's, in another order; einsum itself runs a pair with a batch
+    label as an unthreaded loop."""
+    ins, out = spec.split("->")
+    labels = ins.split(",")
+    arrs = list(ops)
+    # repeated labels within one factor (a Kronecker delta substituted into
+    # it): take the diagonal first
+    for n, (a, la) in enumerate(zip(arrs, labels)):
+        if len(set(la)) < len(la):
+            u = "".join(dict.fromkeys(la))
+            arrs[n], labels[n] = np.einsum(f"{la}->{u}", a), u
+    if len(arrs) == 1:
+        return np.einsum(f"{labels[0]}->{out}", arrs[0])
+    path = np.einsum_path(",".join(labels) + "->" + out, *arrs, optimize=_PATH)[0][1:]
+    for i, j in path:
+        i, j = sorted((i, j))
+        A, la = arrs[i], labels[i]
+        B, lb = arrs[j], labels[j]
+        rest = "".join(labels[n] for n in range(len(labels)) if n not in (i, j)) + out
+        # labels of one factor needed nowhere else: summed out at once
+        for X, lx, ly in ((0, la, lb), (1, lb, la)):
+            drop = [c for c in lx if c not in ly and c not in rest]
+            if drop:
+                keep = "".join(c for c in lx if c not in drop)
+                if X == 0:
+                    A, la = np.einsum(f"{la}->{keep}", A), keep
+                else:
+                    B, lb = np.einsum(f"{lb}->{keep}", B), keep
+        bat = [c for c in la if c in lb and c in rest]
+        red = [c for c in la if c in lb and c not in rest]
+        ma = [c for c in la if c not in lb]
+        nb = [c for c in lb if c not in la]
+        size = {c: A.shape[la.index(c)] for c in la}
+        size.update({c: B.shape[lb.index(c)] for c in lb})
+        prod = lambda cs: int(np.prod([size[c] for c in cs])) if cs else 1  # noqa: E731
+        At = np.transpose(A, [la.index(c) for c in bat + ma + red]).reshape(prod(bat), prod(ma), prod(red))
+        Bt = np.transpose(B, [lb.index(c) for c in bat + red + nb]).reshape(prod(bat), prod(red), prod(nb))
+        C = np.matmul(At, Bt).reshape([size[c] for c in bat + ma + nb])
+        for n in (j, i):
+            del arrs[n], labels[n]
+        arrs.append(C)
+        labels.append("".join(bat + ma + nb))
+    (R,), (lr,) = arrs, labels
+    if lr != out:
+        drop = "".join(c for c in lr if c not in out)
+        if drop:
+            R, lr = np.einsum(f"{lr}->{''.join(c for c in lr if c in out)}", R), "".join(c for c in lr if c in out)
+        R = np.transpose(R, [lr.index(c) for c in out])
+    return R
 
 
 def _dense_term(ints: Ints, term: str, out_labels: str, in_labels: str, swap: bool) -> np.ndarray:
@@ -369,7 +425,7 @@ def _dense_term(ints: Ints, term: str, out_labels: str, in_labels: str, swap: bo
     all_labels = out_labels + "".join(free_in)
     present = set("".join(subs))
     red_labels = "".join(c for c in all_labels if c in present)
-    red = np.einsum(",".join(subs) + "->" + red_labels, *ops, optimize=_PATH)
+    red = contract(",".join(subs) + "->" + red_labels, *ops)
     size = {c: (ints.o if c in OCC else ints.v) for c in out_labels + in_labels}
     full = np.zeros([size[c] for c in out_labels + in_labels], dtype=np.complex128)
     grids = np.indices([size[c] for c in all_labels])

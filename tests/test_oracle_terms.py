@@ -104,3 +104,32 @@ def test_dense_singles_block_equals_matrix_free(kind, o, v):
     for od in range(4):
         mf = sigma_block(ints, kind, "11", od, E, dense_singles=False).T
         assert np.abs(m11_block(ints, kind, od) - mf).max() < 1e-14, od
+
+
+def test_pairwise_contraction_equals_einsum():
+    """The oracle evaluates each term line pair by pair as batched matrix
+    products (oracle.adc_terms.contract); on every line of the term table,
+    with random factors and the labels' delta substitutions, it must equal a
+    plain einsum of the same line."""
+    from oracle.adc_terms import TERMS, BRA, OCC, contract, parse_term
+    rng = np.random.default_rng(5)
+    o, v = 3, 4
+    for (kind, blk, od), lines in TERMS.items():
+        r, c = int(blk[0]), int(blk[1])
+        out_l, in_l = BRA[(kind, r)], BRA[(kind, c)].upper()
+        for line in lines:
+            _, factors, deltas = parse_term(line)
+            sub = {}
+            for a, b in deltas:
+                if a in out_l:
+                    sub[b] = a
+                else:
+                    sub[a] = b
+            subs = ["".join(sub.get(ch, ch) for ch in lab) for _, lab in factors]
+            ysub = "z" + "".join(sub.get(ch, ch) for ch in in_l)
+            spec = ",".join(subs + [ysub]) + "->z" + out_l
+            size = lambda ch: 2 if ch == "z" else (o if ch in OCC else v)  # noqa: E731
+            ops = [rng.standard_normal([size(ch) for ch in lab]) + 1j * rng.standard_normal([size(ch) for ch in lab])
+                   for lab in spec.split("->")[0].split(",")]
+            ref = np.einsum(spec, *ops)
+            assert np.abs(contract(spec, *ops) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (kind, line)
