@@ -27,21 +27,54 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
 # profiles/ladder_c2_split_bf16.md; None for the other precisions (not measured)
 LADDER_TRAFFIC_BYTES = {"split_bf16": 7.230e9 + 1.511e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}
+# SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x CUs) over the ladder term of
+# this workload, from the counter run summarised in
+# profiles/mfma_counters_ladder_c2.md; None where not measured
+MFMA_BUSY = {}
+
+
+def core_terms(o, v, N, k):
+    """Algorithmic work of one EE sigma build in complex MACs, per term, as
+    the cost model counts it: every unique <ab||cd> (a<b, c<d) formed once
+    from two Cholesky sums (assembly 2 N Pv^2, whatever symmetry the build
+    exploits), the pp-ladder k Po Pv^2, the ring k (ov)^3, the hh-ladder
+    k Po^2 Pv and the first-order coupling N o v^3 + k o^2 v^3 + k o^3 v^2
+    (three-external class assembled, contracted, plus the three-internal
+    terms).  8 flop per complex MAC."""
+    Po, Pv = o * (o - 1) // 2, v * (v - 1) // 2
+    return {"assembly": 2 * N * Pv * Pv, "pp_ladder": k * Po * Pv * Pv, "ring": k * (o * v) ** 3,
+            "hh_ladder": k * Po * Po * Pv, "coupling_a8": N * o * v ** 3 + k * o * o * v ** 3 + k * o ** 3 * v * v}
 
 
 def core_flops(o, v, N, k):
-    """Algorithmic (core) flop of one EE sigma build, 8 flop per complex MAC:
-    vvvv assembly of the Hermitian upper part 2 N Pv (Pv + 1) / 2 (each
-    <ab||cd>, ab <= cd, is two Cholesky sums of N), pp-ladder k Po Pv^2, ring
-    k (ov)^3, hh-ladder k Po^2 Pv, first-order coupling k o^2 v^3
-    (three-external class stored)."""
-    Po, Pv = o * (o - 1) // 2, v * (v - 1) // 2
-    assembly = N * Pv * (Pv + 1)
-    ladder = k * Po * Pv * Pv
-    ring = k * (o * v) ** 3
-    hh = k * Po * Po * Pv
-    coupling = k * o * o * v ** 3
-    return 8.0 * (assembly + ladder + ring + hh + coupling), 8.0 * (assembly + ladder)
+    """(core flop of one build, flop of the ladder term = assembly + pp-ladder)."""
+    t = core_terms(o, v, N, k)
+    return 8.0 * sum(t.values()), 8.0 * (t["assembly"] + t["pp_ladder"])
+
+
+def cpu_info():
+    """Host description for the CPU baseline: model, logical CPUs, the
+    threads this process may use, and numpy's BLAS."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas, threads = "", None
+    try:
+        from threadpoolctl import threadpool_info
+        info = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
+            threads = max(d.get("num_threads", 1) for d in info)
+    except Exception:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "blas": blas, "blas_threads": threads}
 
 
 def time_calls(fn, steps, warmup, stream):
@@ -59,30 +92,41 @@ def time_calls(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(P, k):
-    """The oracle's matrix-free FP64 sigma on the host, one of the k roots, M11
-    product and integral setup excluded (they are one-off)."""
-    from oracle.adc_terms import Ints, dims, sigma_block
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        cores = len(os.sched_getaffinity(0))
+def oracle_build(P, X):
+    """The oracle's matrix-free FP64 sigma (every block and order, M11
+    included) of the rows of X on the host: (S, seconds of the integral and
+    amplitude setup, seconds of the sigma itself)."""
+    from oracle.adc_terms import Ints, sigma
+    t0 = time.perf_counter()
     ints = Ints(P.eps, P.L, P.o)
     for c in ("vvvv", "ovvv", "vovv", "ovov", "oovv", "vvoo", "ooov", "oooo"):
         ints.g(c)
-    ints.amp("t")
-    n1, n2 = dims("EE", P.o, P.v)
-    rng = np.random.default_rng(5)
-    Y = rng.standard_normal((1, n1 + n2)) + 1j * rng.standard_normal((1, n1 + n2))
-    t0 = time.perf_counter()
-    for blk, od, f in [("12", 1, 1.0), ("12", 2, P.x), ("21", 1, 1.0), ("21", 2, P.x), ("22", 0, 1.0), ("22", 1, P.x)]:
-        src = Y[:, :n1] if blk[1] == "1" else Y[:, n1:]
-        sigma_block(ints, "EE", blk, od, src)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / (k * dt), "unit": "sigma builds/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"1 of {k} trial vectors of one build (numpy FP64 einsum, integrals precomputed, "
-                      f"M11 product excluded), {dt:.1f} s"}
+    for a in ("t", "t2", "ts"):
+        ints.amp(a)
+    t1 = time.perf_counter()
+    S = sigma(ints, P.kind, P.x, X)
+    return S, t1 - t0, time.perf_counter() - t1
+
+
+def certify(P, X, omega, spec, roots):
+    """Per-root certificate of GPU Ritz vectors X (rows) with eigenvalues
+    omega: theta = y^H M y and |r| = |M y - theta y| from the oracle's sigma of
+    the normalised rows; the Hermitian M has an eigenvalue within |r|^2 / gap
+    of theta, gap = distance from theta to the other eigenvalues (from spec,
+    a solve for more roots; roots[j] = the index of row j's root in spec).
+    Returns (per-root records, oracle timings)."""
+    nrm = np.sqrt(np.einsum("ki,ki->k", X.conj(), X).real)
+    Xn = X / nrm[:, None]
+    S, t_setup, t_sigma = oracle_build(P, Xn)
+    theta = np.einsum("ki,ki->k", Xn.conj(), S).real
+    rn = np.linalg.norm(S - theta[:, None] * Xn, axis=1)
+    out = []
+    for j in range(len(omega)):
+        gap = float(np.min(np.abs(np.delete(spec, roots[j]) - theta[j])))
+        out.append({"omega_gpu": float(omega[j]), "theta_oracle": float(theta[j]), "resnorm_oracle": float(rn[j]),
+                    "gap": gap, "abs_omega_minus_theta": float(abs(omega[j] - theta[j])),
+                    "bound_Eh": float(abs(omega[j] - theta[j]) + rn[j] ** 2 / gap)})
+    return out, t_setup, t_sigma
 
 
 def c4_device_gb(kind, o, v, N, k):
@@ -204,6 +248,8 @@ def main():
     ap.add_argument("--precision", default="split_bf16", choices=["fp32", "split_bf16", "fp64"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-eig", action="store_true")
+    ap.add_argument("--certify", default="both", choices=["none", "mixed", "both"],
+                    help="oracle certificate of the mixed (and FP64) Ritz vectors at the end (CPU)")
     ap.add_argument("--only-ladder", action="store_true",
                     help="time only the ladder term (for counter runs)")
     ap.add_argument("--only-sigma", action="store_true",
@@ -262,8 +308,10 @@ def main():
     ms_lad = time_calls(lambda: h.sigma_term("ladder", Y, S, precision=args.precision), args.steps, 1, stream)
     print(f"[bench] ladder term {ms_lad:.2f} ms", file=sys.stderr, flush=True)
 
+    terms = core_terms(P.o, P.v, P.n_chol, k)
     flops, lad_flops = core_flops(P.o, P.v, P.n_chol, k)
     peak = PEAK_TFLOPS[args.precision]
+    eff_peak = peak / 3.0 if args.precision == "split_bf16" else peak
     achieved = lad_flops / (ms_lad * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -283,6 +331,9 @@ def main():
                    "dim": h.dim, "precision": args.precision},
         "tflops_core": flops / (ms * 1e-3) / 1e12,
         "core_flop_per_build": flops,
+        "core_cmac_per_term": terms,
+        "core_count": "8 flop per complex MAC of: assembly 2 N Pv^2, pp-ladder k Po Pv^2, ring k (ov)^3, "
+                      "hh-ladder k Po^2 Pv, coupling N o v^3 + k o^2 v^3 + k o^3 v^2",
         "fp64": {"ms_per_build": ms64, "builds_per_s": 1000.0 / ms64,
                  "tflops_core": flops / (ms64 * 1e-3) / 1e12},
         "speedup_vs_fp64": ms64 / ms,
@@ -292,8 +343,10 @@ def main():
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": LADDER_TRAFFIC_BYTES.get(args.precision), "traffic_unit": "bytes per launch",
                      "ms_per_launch": ms_lad, "flop_per_launch": lad_flops,
-                     "effective_peak": peak / 3.0 if args.precision == "split_bf16" else peak,
-                     "frac_effective": achieved / (peak / 3.0 if args.precision == "split_bf16" else peak)},
+                     "flop_count": "8 (2 N Pv^2 + k Po Pv^2): every <ab||cd> (a<b, c<d) from two Cholesky sums, "
+                                   "plus the contraction",
+                     "effective_peak": eff_peak, "frac_effective": achieved / eff_peak,
+                     "mfma_busy_frac": MFMA_BUSY.get(args.precision)},
     }
     if not args.no_eig and args.precision != "fp64":
         # mixed: reduced-precision sweeps to |r| <= 1e-4, then FP64 until the
@@ -301,13 +354,14 @@ def main():
         # reference: FP64 throughout to |r| <= 1e-7
         hm = adc.Handle("EE", P.o, P.v, P.eps, P.L, k, x=P.x, precision=args.precision, conv_tol=3e-5)
         t0 = time.perf_counter()
-        r_mixed = hm.davidson(want_vectors=False)
+        r_mixed = hm.davidson()
         t_mixed = time.perf_counter() - t0
         hm.close()
         h64 = adc.Handle("EE", P.o, P.v, P.eps, P.L, k, x=P.x, precision="fp64", conv_tol=1e-7)
         t0 = time.perf_counter()
-        r64 = h64.davidson(want_vectors=False)
+        r64 = h64.davidson(want_vectors=args.certify == "both")
         t64 = time.perf_counter() - t0
+        h64.close()
         out["eigen"] = {"omega_fp64": r64["omega"].tolist(), "omega_mixed": r_mixed["omega"].tolist(),
                         "max_abs_diff_Eh": float(np.abs(r64["omega"] - r_mixed["omega"]).max()),
                         "per_root_diff_Eh": np.abs(r64["omega"] - r_mixed["omega"]).tolist(),
@@ -317,11 +371,50 @@ def main():
                         "converged": bool(r_mixed["converged"].all() and r64["converged"].all())}
         print(f"[bench] davidson mixed {t_mixed:.1f} s fp64 {t64:.1f} s, max |dw| "
               f"{out['eigen']['max_abs_diff_Eh']:.2e}", file=sys.stderr, flush=True)
-        h64.close()
+        if args.certify != "none" and not args.no_cpu:
+            # the gaps: the lowest k + 2 roots (loose mixed solve)
+            hw = adc.Handle("EE", P.o, P.v, P.eps, P.L, k + 2, x=P.x, precision=args.precision, conv_tol=1e-4,
+                            refine_fp64=False)
+            spec = hw.davidson(want_vectors=False)["omega"]
+            hw.close()
+            X = r_mixed["vectors"].cpu().numpy()
+            om = r_mixed["omega"]
+            if args.certify == "both":
+                X = np.concatenate([X, r64["vectors"].cpu().numpy()])
+                om = np.concatenate([om, r64["omega"]])
+            print(f"[bench] oracle certificate of {X.shape[0]} Ritz vectors (CPU) ...", file=sys.stderr, flush=True)
+            cert, t_setup, t_sigma = certify(P, X, om, spec, [j % k for j in range(X.shape[0])])
+            cm = cert[:k]
+            out["eigen"]["certificate"] = {
+                "method": "oracle FP64 sigma of the GPU Ritz vectors: |omega_gpu - theta| + |r|^2/gap per root",
+                "mixed": cm, "max_bound_mixed_Eh": max(c["bound_Eh"] for c in cm),
+                "fp64_vs_oracle_theta_of_mixed_Eh": [abs(r64["omega"][j] - cm[j]["theta_oracle"]) for j in range(k)]}
+            if args.certify == "both":
+                cf = cert[k:]
+                out["eigen"]["certificate"]["fp64"] = cf
+                out["eigen"]["certificate"]["max_bound_fp64_Eh"] = max(c["bound_Eh"] for c in cf)
+            print(f"[bench] certified mixed max error {out['eigen']['certificate']['max_bound_mixed_Eh']:.2e} Eh "
+                  f"(oracle sigma {t_sigma:.1f} s)", file=sys.stderr, flush=True)
+            # the oracle's sigma of these vectors is a full build (every block,
+            # M11 included) of X.shape[0] vectors: k of them make one build
+            info = cpu_info()
+            out["cpu_baseline"] = {"value": (X.shape[0] / k) / t_sigma, "unit": "sigma builds/s",
+                                   "cores": info["blas_threads"] or info["affinity"], "kind": "oracle",
+                                   "sample": f"oracle numpy FP64 matrix-free sigma (all blocks, M11 included) of "
+                                             f"the {X.shape[0]} certified Ritz vectors = {X.shape[0] / k:g} full "
+                                             f"builds of {k} vectors, {t_sigma:.1f} s; integral and amplitude "
+                                             f"setup {t_setup:.1f} s excluded",
+                                   **info}
     h.close()
-    if not args.no_cpu:
+    if "cpu_baseline" not in out and not args.no_cpu:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(P, k)
+        X = np.random.default_rng(5).standard_normal((1, h.dim)) + 0j
+        _, t_setup, t_sigma = oracle_build(P, X)
+        info = cpu_info()
+        out["cpu_baseline"] = {"value": (1.0 / k) / t_sigma, "unit": "sigma builds/s",
+                               "cores": info["blas_threads"] or info["affinity"], "kind": "oracle",
+                               "sample": f"oracle numpy FP64 matrix-free sigma (all blocks, M11 included) of 1 of "
+                                         f"{k} vectors, {t_sigma:.1f} s; setup {t_setup:.1f} s excluded", **info}
     print(json.dumps(out), flush=True)
 
 

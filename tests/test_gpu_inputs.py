@@ -9,7 +9,8 @@ deterministic builds.
   same roots;
 * a borrowed (device) L that is not Hermitian, or holds a NaN, is refused with
   the codes a host L gets (eq. 42: L^Q is Hermitian);
-* refine_fp64 off: the mixed sweep itself iterates to conv_tol;
+* refine_fp64 off: the mixed sweep itself iterates to conv_tol (1e-4, above
+  the split-bf16 noise floor of the residual);
 * deterministic: two builds on two handles are bitwise identical.
 """
 import numpy as np
@@ -77,11 +78,14 @@ def test_mixed_solve_without_refinement():
     P = make_problem("EE", 5, 16, 60, seed=63, n_roots=3, x=0.5, scale=0.2)
     print("case refine off", flush=True)
     ref = _h(P, conv_tol=1e-9).davidson()
-    out = _h(P, precision="split_bf16", conv_tol=1e-6, refine_fp64=False).davidson()
+    # a split-bf16 sigma carries rounding of a few 1e-6 relative, so its
+    # residuals cannot be driven far below ~1e-5: ask for 1e-4
+    out = _h(P, precision="split_bf16", conv_tol=1e-4, refine_fp64=False).davidson()
+    print("  residuals", out["resnorm"], "omega - fp64", out["omega"] - ref["omega"], flush=True)
     assert out["converged"].all()
-    assert (out["resnorm"] <= 1e-6).all()
-    # eigenvalues of the split-bf16 matrix: its error is a few 1e-6 relative
-    # of the correlation part, far below the orbital-energy scale
+    assert (out["resnorm"] <= 1e-4).all()
+    # eigenvalue error: |r|^2/gap from the residual plus the split-bf16
+    # perturbation of the correlation part of M
     assert np.abs(out["omega"] - ref["omega"]).max() < 1e-5
 
 
