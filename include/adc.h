@@ -60,7 +60,8 @@ enum adc_status {
   ADC_ERR_NOT_HERMITIAN = -3,
   ADC_ERR_OUT_OF_MEMORY = -4,
   ADC_ERR_HIP = -5,
-  ADC_ERR_UNSUPPORTED = -6
+  ADC_ERR_UNSUPPORTED = -6,
+  ADC_ERR_SCRATCH = -7
 };
 
 /* One problem (instance).
@@ -179,6 +180,28 @@ int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2);
  * pool (allocated on first use and kept).  Errors: INVALID_ARG, HIP_ERROR,
  * OUT_OF_MEMORY. */
 int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precision);
+
+/* The sigma build of adc_sigma (same arguments, same result) without any
+ * device allocation, for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Every
+ * temporary of the build comes from one fixed device array of 128 MiB per
+ * GPU (held from the library's load until the process ends); the build plans
+ * its passes, <ab||cd> batches and temporary copies for that size, times no
+ * GEMM variant, and makes no persistent cache entry (it still reads the
+ * handle's existing ones).  The handle's own state (integral classes,
+ * amplitudes, M11) was allocated by adc_init.
+ * A request that certainly needs more than the array (its doubles
+ * accumulators or one <ab||cd> block of one a alone) is rejected with
+ * ADC_ERR_SCRATCH before anything is enqueued.  A build that runs out of the
+ * array part-way also returns ADC_ERR_SCRATCH, after the work already
+ * enqueued has finished (S is then undefined), and later requests of that
+ * precision with at least as many vectors are rejected up front.
+ * Calls on one GPU share its array and it keeps the last call's contents:
+ * calls that overlap on one GPU (any handle, any stream) race, so serialise
+ * them; nothing relies on the array starting at zero.
+ * Errors: INVALID_ARG, SCRATCH, HIP_ERROR (also when the array's address
+ * could not be taken on this device). */
+int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, int precision);
 
 /* Block Davidson for the n_roots lowest eigenpairs of every instance
  * (Section 2.1, eq. 10: M X = X Omega, X^H X = 1, with sigma builds as

@@ -21,11 +21,11 @@ PREC = {"fp64": 0, "fp32": 1, "split_bf16": 2}
 ADC_OK = 0
 ADC_NOT_CONVERGED = 1
 ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE_INPUT", -3: "NOT_HERMITIAN", -4: "OUT_OF_MEMORY",
-          -5: "HIP_ERROR", -6: "UNSUPPORTED"}
+          -5: "HIP_ERROR", -6: "UNSUPPORTED", -7: "SCRATCH"}
 
 # Every symbol include/adc.h declares.
-EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_sigma_term", "adc_davidson", "adc_sigma_backward",
-           "adc_init_ms", "adc_free", "adc_strerror"]
+EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_sigma_term", "adc_sigma_noalloc", "adc_davidson",
+           "adc_sigma_backward", "adc_init_ms", "adc_free", "adc_strerror"]
 TERMS = {"all": 0, "ladder": 1}
 
 
@@ -77,6 +77,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                               ctypes.c_int]
     lib.adc_sigma_term.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int, ctypes.c_int]
+    lib.adc_sigma_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.c_int]
     lib.adc_davidson.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
@@ -155,6 +157,21 @@ class Handle:
                                  Y2.shape[0], p)
         if rc != ADC_OK:
             raise AdcError(rc, "adc_sigma")
+        return S.reshape(Y.shape)
+
+    def sigma_noalloc(self, Y, S=None, precision=None):
+        """adc_sigma_noalloc: the same build with every temporary in the
+        library's fixed device scratch (no allocation inside the call)."""
+        import torch
+        assert Y.is_cuda and Y.dtype == torch.complex128 and Y.is_contiguous() and Y.shape[-1] == self.dim
+        Y2 = Y.reshape(-1, self.dim)
+        if S is None:
+            S = torch.empty_like(Y2)
+        p = -1 if precision is None else PREC[precision]
+        rc = self._lib.adc_sigma_noalloc(self._h, 0, ctypes.c_void_p(Y2.data_ptr()), ctypes.c_void_p(S.data_ptr()),
+                                         Y2.shape[0], p)
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_sigma_noalloc")
         return S.reshape(Y.shape)
 
     def sigma_term(self, term, Y, S=None, precision=None):

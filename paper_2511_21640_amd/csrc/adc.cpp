@@ -100,6 +100,9 @@ struct Inst {
     std::vector<double2*> held;  // workspace blocks reserved for the graph
   };
   std::vector<Graph> graphs;
+  // allocation-free sigma builds: the smallest row count per precision that
+  // did not fit the scratch (0 = none seen)
+  int noalloc_too_big[3] = {0, 0, 0};
 };
 
 }  // namespace
@@ -120,6 +123,7 @@ struct adc_handle {
   std::mutex mu;                            // guards raw
   int device = 0;
   std::string tune_path;                    // autotuner cache file, if any
+  void* scratch = nullptr;                  // device address of the allocation-free entry point's scratch
   Ctx& lane(int i) { return i == 0 ? cx : *extra[(size_t)i - 1]; }
   int n_lanes() const { return 1 + (int)extra.size(); }
 };
@@ -194,7 +198,8 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   const int v = I.v;
   const int64_t Pv = I.Pv, N = I.N;
   if (Pv == 0 || nrow == 0 || k == 0) return;
-  const size_t budget = h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30;
+  const size_t budget = cx.ws_override ? cx.ws_override / 4
+                                       : (h->opt.mem_budget ? h->opt.mem_budget : (size_t)4 << 30);
   // W block: nb*v rows x (v-b0)*v cols, at most the workspace budget
   const int64_t per_a = (int64_t)v * v * v;
   int nb = (int)std::max<int64_t>(1, (int64_t)(budget / sizeof(double2)) / std::max<int64_t>(1, per_a));
@@ -227,11 +232,19 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   unsigned short* Vp = nullptr;
   double2* Vbuf = nullptr;
   bool own_yp = false;
-  // split-bf16 planes of L_vv, kept in the instance after their first use
+  // split-bf16 planes of L_vv: kept in the instance after their first use,
+  // or, inside an allocation-free call that finds none, split for this call
   const unsigned short* Lq = nullptr;
+  unsigned short* Lq_tmp = nullptr;
   if (bf) {
-    ensure_planes(h, I);
-    Lq = I.Lq;
+    if (!I.Lq && cx.pool.in_arena()) {
+      Lq_tmp = planes_alloc(cx, (int64_t)v * v, pad32(N));
+      launch_split_planes(I.Lvv.p, (int64_t)v * v, N, 1, (int64_t)v * v, 0, Lq_tmp, pad32(N), cx.stream);
+      Lq = Lq_tmp;
+    } else {
+      ensure_planes(h, I);
+      Lq = I.Lq;
+    }
     Vp = planes_alloc(cx, grp, Kv);
     SplitNd sp{};
     sp.src = Y + offY; sp.rows = R; sp.K = Pv; sp.Kp = Kv; sp.conj = 0;
@@ -348,6 +361,7 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   }
   if (half) launch_ladder_mirror_planes(Vp, grp, Pv, Kv, cx.stream);
   contract();
+  if (Lq_tmp) cx.pool.put((double2*)Lq_tmp);
   if (own_yp) cx.pool.put((double2*)Yp);
   if (Vp) cx.pool.put((double2*)Vp);
   if (Vbuf) cx.pool.put(Vbuf);
@@ -1442,6 +1456,13 @@ void heevj(int n, std::vector<zc>& A, std::vector<double>& w, std::vector<zc>& V
 // vectors, so they take the vectors in groups that fit the workspace budget.
 // The ladder, whose <ab||cd> assembly does not depend on the vectors, then
 // runs once over all of them (it adds into the packed output).
+// workspace bytes a build plans for: the allocation-free call's scratch, the
+// handle's budget, or the default
+size_t cx_ws(const adc_handle* h, const Ctx& cx, size_t dflt) {
+  if (cx.ws_override) return cx.ws_override;
+  return h->opt.mem_budget ? h->opt.mem_budget : dflt;
+}
+
 void sigma_dispatch(adc_handle* h, Inst& I, const double2* Y, double2* S, int k, int prec) {
   if (k <= 0) return;
   // Y stays unchanged during the build: splits of it are shared by the
@@ -1449,7 +1470,7 @@ void sigma_dispatch(adc_handle* h, Inst& I, const double2* Y, double2* S, int k,
   SplitScope yscope(*I.cx, {{Y, (int64_t)k * I.dim}});
   const int64_t o = I.o, v = I.v;
   const int64_t unp = I.kind == ADC_EE ? o * o * v * v : (I.kind == ADC_IP ? o * o * v : o * v * v);
-  const size_t ws = h->opt.mem_budget ? h->opt.mem_budget : (size_t)16 << 30;
+  const size_t ws = cx_ws(h, *I.cx, (size_t)16 << 30);
   // unpacked vectors, three accumulators, operand planes and temporaries
   const int64_t per_row = std::max<int64_t>(1, 6 * unp * (int64_t)sizeof(double2));
   const int rows = (int)std::max<int64_t>(1, std::min<int64_t>(k, (int64_t)ws / per_row));
@@ -2086,6 +2107,22 @@ int guarded(F&& f) {
   }
 }
 
+// Bytes that an allocation-free sigma build of k vectors certainly takes from
+// its scratch (a lower bound): the doubles accumulators of one vector and,
+// when the particle-particle ladder runs, one (ac|bd) block of one a.
+size_t noalloc_lower_bound(const Inst& I, int k, int prec) {
+  (void)k;
+  const double o = I.o, v = I.v, Po = (double)I.Po, Pv = (double)I.Pv;
+  const double esz = prec == ADC_FP64 ? 16.0 : 8.0;
+  double acc = 0.0;
+  if (I.kind == ADC_EE) acc = esz * (o * o * Pv + Po * v * v + (I.x != 0.0 ? o * o * v * v : 0.0));
+  else if (I.kind == ADC_IP) acc = 16.0 * o * o * v;
+  else acc = 16.0 * o * v * v;
+  const bool lad = I.x != 0.0 && I.kind != ADC_IP && Pv > 0 && (I.kind == ADC_EA || Po > 0);
+  const double w = lad ? 16.0 * v * v * v : 0.0;
+  return (size_t)std::max(acc, w);
+}
+
 // Rough cost of one sigma build (complex MACs), used to order instances
 // longest first and to balance them over the lanes.
 double sigma_cost(const adc_problem& p) {
@@ -2160,6 +2197,9 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
     h = new adc_handle();
     if (opts) h->opt = *opts;
     hipcheck(hipGetDevice(&h->device), "device");
+    // the allocation-free entry point's scratch on this device (its address
+    // is taken once per device; nullptr leaves that entry point unavailable)
+    h->scratch = scratch_address();
     if (h->opt.stream) {
       h->cx.stream = (hipStream_t)h->opt.stream;
     } else {
@@ -2263,6 +2303,57 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
   });
 }
 
+int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, int precision) {
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
+  if (precision > 2) return ADC_ERR_INVALID_ARG;
+  const int prec = precision < 0 ? h->opt.precision : precision;
+  if (prec == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
+  if (!h->scratch) return ADC_ERR_HIP;
+  Inst& I = h->inst[inst];
+  if (k == 0) return ADC_OK;
+  if (noalloc_lower_bound(I, k, prec) > kScratchBytes) return ADC_ERR_SCRATCH;
+  if (I.noalloc_too_big[prec] > 0 && k >= I.noalloc_too_big[prec]) return ADC_ERR_SCRATCH;
+  return guarded([&]() {
+    Ctx& cx = *I.cx;
+    // the build's temporaries come from the scratch; its passes, ladder
+    // batches and temporary copies are planned for the scratch size, and no
+    // GEMM is timed (the tuner would need extra buffers and host waits)
+    struct Arena {
+      Ctx& cx;
+      bool tune;
+      int64_t max_temp;
+      Arena(Ctx& c, void* base) : cx(c), tune(c.autotune), max_temp(c.max_temp) {
+        cx.pool.begin_arena(base, kScratchBytes);
+        cx.autotune = false;
+        cx.ws_override = kScratchBytes;
+        cx.max_temp = std::min<int64_t>(cx.max_temp, (int64_t)(kScratchBytes / sizeof(double2) / 8));
+      }
+      ~Arena() {
+        cx.pool.end_arena();
+        cx.autotune = tune;
+        cx.ws_override = 0;
+        cx.max_temp = max_temp;
+      }
+    } arena(cx, h->scratch);
+    lane_wait(h, cx, true);
+    try {
+      sigma_dispatch(h, I, (const double2*)Y, (double2*)S, k, prec);
+    } catch (const ArenaFull&) {
+      // kernels already enqueued use the scratch: let them finish (unless a
+      // capture is recording them) before another call may reuse it
+      I.noalloc_too_big[prec] = I.noalloc_too_big[prec] > 0 ? std::min(I.noalloc_too_big[prec], k) : k;
+      hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(cx.stream, &st) == hipSuccess && st == hipStreamCaptureStatusNone)
+        (void)hipStreamSynchronize(cx.stream);
+      (void)hipGetLastError();
+      return (int)ADC_ERR_SCRATCH;
+    }
+    lane_wait(h, cx, false);
+    hipcheck(hipGetLastError(), "sigma launch");
+    return (int)ADC_OK;
+  });
+}
+
 int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs, double* resnorm,
                  int* iters, int* converged) {
   if (!h || !omega || !resnorm || !iters || !converged) return ADC_ERR_INVALID_ARG;
@@ -2340,6 +2431,7 @@ const char* adc_strerror(int code) {
     case ADC_ERR_OUT_OF_MEMORY: return "out of device memory";
     case ADC_ERR_HIP: return "HIP runtime error";
     case ADC_ERR_UNSUPPORTED: return "unsupported request";
+    case ADC_ERR_SCRATCH: return "the build does not fit the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }

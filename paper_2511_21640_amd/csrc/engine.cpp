@@ -24,6 +24,21 @@ Pool::~Pool() { release_all(); }
 
 double2* Pool::get(int64_t n) {
   const size_t bytes = std::max<size_t>(256, (size_t)n * sizeof(double2));
+  if (arena_base_) {
+    const size_t need = (bytes + 255) / 256 * 256;
+    for (size_t i = 0; i < arena_free_.size(); ++i) {
+      Span& f = arena_free_[i];
+      if (f.len < need) continue;
+      const size_t off = f.off;
+      f.off += need;
+      f.len -= need;
+      if (f.len == 0) arena_free_.erase(arena_free_.begin() + i);
+      arena_used_.push_back({off, need});
+      arena_peak_ = std::max(arena_peak_, off + need);
+      return (double2*)(arena_base_ + off);
+    }
+    throw ArenaFull{need};
+  }
   if (hold_) {
     // reuse a block this capture has already released
     int cb = -1;
@@ -87,8 +102,47 @@ std::vector<double2*> Pool::end_hold() {
   return out;
 }
 
+void Pool::begin_arena(void* base, size_t bytes) {
+  arena_base_ = (char*)base;
+  arena_bytes_ = bytes / 256 * 256;
+  arena_peak_ = 0;
+  arena_free_.assign(1, Span{0, arena_bytes_});
+  arena_used_.clear();
+}
+
+size_t Pool::end_arena() {
+  const size_t peak = arena_peak_;
+  arena_base_ = nullptr;
+  arena_bytes_ = arena_peak_ = 0;
+  arena_free_.clear();
+  arena_used_.clear();
+  return peak;
+}
+
 void Pool::put(double2* p) {
   if (!p) return;
+  if (arena_base_ && (char*)p >= arena_base_ && (char*)p < arena_base_ + arena_bytes_) {
+    const size_t off = (size_t)((char*)p - arena_base_);
+    for (size_t i = 0; i < arena_used_.size(); ++i) {
+      if (arena_used_[i].off != off) continue;
+      Span sp = arena_used_[i];
+      arena_used_.erase(arena_used_.begin() + i);
+      // insert in offset order and merge with the neighbours
+      size_t j = 0;
+      while (j < arena_free_.size() && arena_free_[j].off < sp.off) ++j;
+      arena_free_.insert(arena_free_.begin() + j, sp);
+      if (j + 1 < arena_free_.size() && arena_free_[j].off + arena_free_[j].len == arena_free_[j + 1].off) {
+        arena_free_[j].len += arena_free_[j + 1].len;
+        arena_free_.erase(arena_free_.begin() + j + 1);
+      }
+      if (j > 0 && arena_free_[j - 1].off + arena_free_[j - 1].len == arena_free_[j].off) {
+        arena_free_[j - 1].len += arena_free_[j].len;
+        arena_free_.erase(arena_free_.begin() + j);
+      }
+      return;
+    }
+    return;
+  }
   if (hold_ && std::find(touched_.begin(), touched_.end(), (void*)p) != touched_.end()) {
     cap_free_.push_back(p);
     return;
@@ -718,6 +772,8 @@ static unsigned short* split_cached(Ctx& cx, SplitNd sp, int64_t bytes, bool til
   for (const auto& e : c.entries)
     if (same_layout(e.key, sp)) return e.planes;
   if (scope == 0 && c.persistent_bytes + bytes > c.limit) return nullptr;
+  // an arena block lives for one call only: no persistent entry from it
+  if (scope == 0 && cx.pool.in_arena()) return nullptr;
   if (capturing(cx.stream)) return nullptr;
   // a cached copy never takes the last eighth of the device memory, which
   // the temporaries of the contractions need

@@ -224,12 +224,24 @@ struct Tensor {
 
 struct Tape;
 
+// thrown by Pool::get in arena mode when a block does not fit the arena
+struct ArenaFull {
+  size_t need;
+};
+
 class Pool {
  public:
   ~Pool();
   Tape* tape = nullptr;  // while set, allocations are registered and frees deferred
   double2* get(int64_t n_complex);
   void put(double2* p);
+  // Arena mode: blocks come from the device range [base, base + bytes)
+  // (first fit, 256-byte aligned) instead of hipMalloc, and put() returns
+  // them to it; a block that does not fit throws ArenaFull.  end_arena()
+  // drops the arena's bookkeeping and returns the peak bytes in use.
+  void begin_arena(void* base, size_t bytes);
+  size_t end_arena();
+  bool in_arena() const { return arena_base_ != nullptr; }
   // Hold mode (for graph capture): blocks handed out from begin_hold() on
   // are recycled only among themselves, and end_hold() returns them; they
   // stay reserved (never handed out again) until passed to put() one by one.
@@ -245,6 +257,10 @@ class Pool {
   size_t in_use_ = 0;
   bool hold_ = false;
   std::vector<void*> touched_, cap_free_;
+  struct Span { size_t off, len; };
+  char* arena_base_ = nullptr;
+  size_t arena_bytes_ = 0, arena_peak_ = 0;
+  std::vector<Span> arena_free_, arena_used_;  // free spans sorted by offset
 };
 
 // ---------------------------------------------------------------- reverse mode
@@ -335,6 +351,9 @@ struct Ctx {
   bool autotune = false;  // time GEMM variants per shape class (see gemm())
   int verbose = 0;        // >= 2: one line per GEMM launch on stderr
   int64_t max_temp = (int64_t)1 << 29;  // largest permuted copy (complex elements) before ctr() splits
+  // nonzero: the workspace bytes a sigma build plans its passes and ladder
+  // batches for (instead of the handle's mem_budget)
+  size_t ws_override = 0;
   SplitCache scache;
 };
 
@@ -366,6 +385,13 @@ bool split_planes_only(const Ctx& cx, const double2* p);
 // file (returns the entries read or written, -1 if the file cannot be opened)
 int tune_cache_load(const char* path);
 int tune_cache_save(const char* path);
+
+// Device scratch of the allocation-free sigma entry point: a file-scope
+// __device__ array of kScratchBytes per device.  scratch_address() takes its
+// address on the current device (once per device, then cached) and returns
+// nullptr if that fails.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+void* scratch_address();
 
 // GEMM with automatic split-K when the output has too few tiles to fill the chip
 void gemm(Ctx& cx, GemmDesc g);

@@ -7,6 +7,7 @@
 #include "internal.h"
 
 #include <hip/hip_bf16.h>
+#include <mutex>
 #include <stdexcept>
 
 namespace adc {
@@ -1822,6 +1823,34 @@ __global__ __launch_bounds__(256) void check_L_kernel(const double2* L, int64_t 
 void launch_check_L(const double2* L, int64_t nq, int64_t n, double* out, hipStream_t s) {
   if (nq <= 0 || n <= 0) return;
   hipLaunchKernelGGL(check_L_kernel, dim3((unsigned)nq), dim3(256), 0, s, L, n, out);
+}
+
+// Workspace of the allocation-free sigma entry point: one array per device,
+// held from module load until the process ends.  Host code never passes the
+// name itself to a kernel (on the host it is only a stand-in); it takes the
+// device address once per device with hipGetSymbolAddress and uses that.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void* scratch_address() {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  static bool done[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!done[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      ptr = nullptr;
+    }
+    addr[dev] = ptr;
+    done[dev] = true;
+  }
+  return addr[dev];
 }
 
 __global__ void precondition_kernel(const double2* R, double2* N, const double* D, const double* w, int rows,
