@@ -27,10 +27,12 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
 # profiles/ladder_c2_split_bf16.md; None for the other precisions (not measured)
 LADDER_TRAFFIC_BYTES = {"split_bf16": 7.230e9 + 1.511e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}
-# SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x CUs) over the ladder term of
-# this workload, from the counter run summarised in
-# profiles/mfma_counters_ladder_c2.md; None where not measured
-MFMA_BUSY = {}
+# MFMA counters of one split-bf16 ladder term at this workload, from the
+# counter run summarised in profiles/ladder_c2_split_bf16.md: executed MFMA
+# flop (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512) / 2.5 PFLOP/s / kernel time, and
+# SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCC x 1024 SIMDs); None for
+# the precisions not measured
+MFMA_COUNTERS = {"split_bf16": {"exec_frac": 0.40, "busy_frac": 0.44}}
 
 
 def core_terms(o, v, N, k):
@@ -346,7 +348,8 @@ def main():
                      "flop_count": "8 (2 N Pv^2 + k Po Pv^2): every <ab||cd> (a<b, c<d) from two Cholesky sums, "
                                    "plus the contraction",
                      "effective_peak": eff_peak, "frac_effective": achieved / eff_peak,
-                     "mfma_busy_frac": MFMA_BUSY.get(args.precision)},
+                     "mfma_exec_frac_counters": MFMA_COUNTERS.get(args.precision, {}).get("exec_frac"),
+                     "mfma_busy_frac_counters": MFMA_COUNTERS.get(args.precision, {}).get("busy_frac")},
     }
     if not args.no_eig and args.precision != "fp64":
         # mixed: reduced-precision sweeps to |r| <= 1e-4, then FP64 until the

@@ -101,7 +101,7 @@ def test_ee_sigma_fp32_and_mixed_davidson():
     ref = osigma(Ints(P.eps, P.L, P.o), "EE", P.x, Y)
     err = np.abs(S32 - ref).max() / np.abs(ref).max()
     print("fp32 rel err", err)
-    assert err < 1e-5
+    assert err < 1e-6
     assert err > 1e-12  # really ran in reduced precision
     out = h.davidson()
     h64 = _handle(P, precision="fp64")
@@ -124,7 +124,7 @@ def test_split_bf16_sigma_and_mixed_davidson(kind):
     ref = osigma(Ints(P.eps, P.L, P.o), kind, P.x, Y)
     err = np.abs(S - ref).max() / np.abs(ref).max()
     print(kind, "split-bf16 rel err", err)
-    assert 1e-12 < err < 2e-5
+    assert 1e-12 < err < 1e-5
     out = h.davidson()
     out64 = _handle(P, precision="fp64").davidson()
     assert out["converged"].all()
@@ -146,7 +146,9 @@ def test_split_bf16_ladder_blocks(v, budget):
     Sbf = h.sigma_term("ladder", Y, precision="split_bf16").cpu().numpy()
     err = np.abs(Sbf - S64).max() / np.abs(S64).max()
     print("ladder split-bf16 rel err", err)
-    assert 1e-12 < err < 2e-5
+    # two split-bf16 products in a row (assembly, then contraction): about
+    # 2 * 2^-16 relative to the output scale
+    assert 1e-12 < err < 3e-5
 
 
 @pytest.mark.parametrize("o,v,x", [(2, 20, 1.0), (3, 70, 1.0), (3, 67, 0.5), (2, 66, 0.0)])
@@ -165,5 +167,5 @@ def test_split_bf16_ee_pair_layouts(o, v, x):
     ref = osigma(Ints(P.eps, P.L, o), "EE", x, Y)
     err = np.abs(S - ref).max() / np.abs(ref).max()
     print("split-bf16 rel err", err)
-    assert 1e-12 < err < 2e-5
+    assert 1e-12 < err < 1e-5
     h.close()

@@ -52,10 +52,10 @@ def test_c2_full_sigma_doubles_input():
     ebf = np.abs(Sbf - ref).max() / np.abs(ref).max()
     print("C2 rel err fp64", e64, "fp32", e32, "split-bf16", ebf)
     assert e64 < 1e-12
-    assert e32 < 1e-5
-    # split-bf16 (the arithmetic bench.py times): 16 mantissa bits per
-    # operand, errors of a few 2^-17 sqrt(K) relative to the largest output
-    assert 1e-12 < ebf < 5e-5
+    assert e32 < 1e-6
+    # split-bf16 (the arithmetic bench.py times): 16 significant bits per
+    # operand, one split product per term (see the ladder test below for two)
+    assert 1e-12 < ebf < 1e-5
 
 
 def test_c3_ea_ladder_rows_and_hermiticity():
@@ -82,7 +82,13 @@ def test_c3_ea_ladder_rows_and_hermiticity():
         worst_bf = max(worst_bf, np.abs(Sbf[:, v + i * Pv + p] - ref).max() / np.abs(ref).max())
     print("C3-EA ladder sampled rel err", worst, "split-bf16", worst_bf)
     assert worst < 1e-12
-    assert worst_bf < 5e-5
+    # two split-bf16 products in a row (the <ab||cd> assembly over N = 2400,
+    # then the contraction over P_v = 79,800): each operand split carries up
+    # to 2^-16 relative error and the three-product form drops lo*lo'
+    # (<= 2^-16), so each product term is off by ~2^-16 of its size at
+    # random; the two chained products give ~2 * 2^-16 = 3e-5 relative to the
+    # output scale
+    assert worst_bf < 3e-5
     assert _herm_check(h, rng) < 1e-13
 
 
