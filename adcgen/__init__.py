@@ -25,7 +25,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-__all__ = ["Problem", "make_problem", "CONFIGS", "config_problem", "c4_draw", "trial_vectors",
+__all__ = ["Problem", "make_problem", "CONFIGS", "config_problem", "c4_draw", "trial_vectors", "make_eri", "mo_coefficients",
            "hermitian_direction", "sample_indices"]
 
 
@@ -129,3 +129,31 @@ def sample_indices(size: int, n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(size, size=min(n, size), replace=False))
 
+
+
+def make_eri(n_ao: int, seed: int, rank: int | None = None, decay: float = 8.0) -> np.ndarray:
+    """A synthetic electron-repulsion matrix: (mu nu|kappa lambda) over the
+    packed pairs mu <= nu, real symmetric positive semidefinite,
+    V = sum_R s_R^2 b_R b_R^T with b_R the packed upper triangle of a real
+    symmetric Gaussian matrix and s_R = exp(-R / decay) (R = 0 .. rank-1;
+    default rank = the number of pairs).  Shape [n_pair][n_pair],
+    n_pair = n_ao (n_ao + 1) / 2."""
+    rng = np.random.default_rng(seed)
+    npair = n_ao * (n_ao + 1) // 2
+    rank = npair if rank is None else rank
+    iu = np.triu_indices(n_ao)
+    B = np.empty((rank, npair))
+    for r in range(rank):
+        G = rng.standard_normal((n_ao, n_ao))
+        B[r] = ((G + G.T) / 2.0)[iu] * math.exp(-r / decay)
+    return B.T @ B
+
+
+def mo_coefficients(n_ao: int, n_mo: int, seed: int) -> np.ndarray:
+    """n_mo orthonormal complex columns of length n_ao (the first columns of a
+    random unitary: QR of a complex Gaussian matrix), [n_ao][n_mo]."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((n_ao, n_ao)) + 1j * rng.standard_normal((n_ao, n_ao))
+    Q, R = np.linalg.qr(Z)
+    Q = Q * (np.diag(R) / np.abs(np.diag(R)))[None, :]
+    return np.ascontiguousarray(Q[:, :n_mo])
