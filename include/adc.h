@@ -252,13 +252,50 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
  * gradient d omega_r = y_r^H dM y_r (Hellmann-Feynman).  The gradient with
  * respect to Y is adc_sigma applied to Sbar (M is Hermitian).
  * The one-off work of adc_init and the sigma build are recomputed on the
- * device in FP64 with their intermediates kept, then differentiated in
- * reverse; the <ab||cd> gradient blocks of the particle-particle ladder are
- * formed per batch of a from L and never stored whole.  Device memory: about
+ * device with their intermediates kept, then differentiated in reverse,
+ * every reverse rule in the arithmetic of its forward operation: the one-off
+ * part in FP64 (as in adc_init), the sigma part in the handle's default
+ * precision (FP64, FP32 or split-bf16 contractions), with every gradient
+ * accumulated in complex128; dx is formed from two FP64 builds whatever the
+ * precision.  The <ab||cd> gradient blocks of the particle-particle ladder
+ * are formed per batch of a from L and never stored whole.  Device memory: about
  * twice that of adc_init plus one workspace batch.  Synchronous.  Errors:
  * INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR. */
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k,
                        void* dL, double* dx);
+
+/* One-step pivoted Cholesky of the electron-repulsion matrix (Section 2.5,
+ * eq. 41 and the one-step procedure): V is the symmetric positive
+ * semidefinite matrix (mu nu|kappa lambda) over m composite indices (for
+ * instance the pairs mu <= nu), device float64 [m][m] row-major, read only.
+ * Vector k is made at the largest remaining diagonal element d_p of
+ * V - sum_{q<k} L_q L_q^T (lowest index among equal ones):
+ * L_k[i] = (V[p][i] - sum_{q<k} L_q[i] L_q[p]) / sqrt(d_p); the procedure ends
+ * when d_p < tau (or d_p <= 0) or after max_vec vectors, so that
+ * V ~ sum_k L_k L_k^T with every remaining diagonal element below tau.
+ *   L       device float64 [max_vec][m] (caller-owned); rows >= n_vec unset
+ *   pivots  host int [max_vec]: p of each vector
+ *   n_vec   host: number of vectors made
+ *   stream  hipStream_t (NULL = the default stream)
+ * Temporaries (the remaining diagonal, the step state) are allocated and
+ * freed inside the call.  Synchronous.  Errors: INVALID_ARG (m < 1 or
+ * >= 2^31, tau < 0 or not finite, NULL outputs), NONFINITE_INPUT (a
+ * non-finite diagonal element), OUT_OF_MEMORY, HIP_ERROR. */
+int adc_cholesky(const double* V, long long m, double tau, int max_vec, double* L, int* pivots, int* n_vec,
+                 void* stream);
+
+/* The Cholesky vectors in the molecular spinor basis (Section 2.5, eq. 42):
+ * L^P_pq = sum_{mu nu} conj(C_mu p) L^P_mu nu C_nu q, Hermitian in (p, q)
+ * for real symmetric L^P_mu nu.
+ *   Lp    device float64 [n_vec][n_ao (n_ao + 1) / 2]: each vector over the
+ *         pairs mu <= nu in row-major upper-triangle order (as made by
+ *         adc_cholesky on a V over those pairs), read as symmetric
+ *   C     device c128 [n_ao][n_mo] MO coefficients
+ *   Lmo   device c128 [n_vec][n_mo][n_mo] (caller-owned): the L of
+ *         adc_problem for n_mo = o + v spinors ordered occupied first
+ * FP64 complex GEMMs on the matrix cores.  Synchronous.  Errors:
+ * INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR. */
+int adc_cholesky_mo(const double* Lp, int n_vec, int n_ao, const void* C, int n_mo, void* Lmo, void* stream);
 
 /* Milliseconds spent in adc_init on the device (one-off work). */
 double adc_init_ms(const adc_handle* h);

@@ -25,7 +25,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE_INPUT", -3: "NOT_HERMITIAN", -4: "OU
 
 # Every symbol include/adc.h declares.
 EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_sigma_term", "adc_sigma_noalloc", "adc_davidson",
-           "adc_sigma_backward", "adc_init_ms", "adc_free", "adc_strerror"]
+           "adc_sigma_backward", "adc_cholesky", "adc_cholesky_mo", "adc_init_ms", "adc_free", "adc_strerror"]
 TERMS = {"all": 0, "ladder": 1}
 
 
@@ -84,6 +84,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.adc_sigma_backward.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.adc_cholesky.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p]
+    lib.adc_cholesky_mo.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_void_p]
     lib.adc_init_ms.argtypes = [ctypes.c_void_p]
     lib.adc_init_ms.restype = ctypes.c_double
     lib.adc_free.argtypes = [ctypes.c_void_p]
@@ -244,6 +248,43 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+
+def cholesky(V, tau, max_vec=None):
+    """adc_cholesky: one-step pivoted Cholesky of a float64 cuda tensor V
+    [m][m] (symmetric positive semidefinite).  Returns (L [n_vec][m] cuda
+    tensor, pivots numpy int array)."""
+    import torch
+    lib = load()
+    assert V.is_cuda and V.dtype == torch.float64 and V.is_contiguous() and V.dim() == 2 and V.shape[0] == V.shape[1]
+    m = int(V.shape[0])
+    max_vec = m if max_vec is None else int(max_vec)
+    L = torch.empty((max(max_vec, 1), m), dtype=torch.float64, device=V.device)
+    piv = (ctypes.c_int * max(max_vec, 1))()
+    n = ctypes.c_int(0)
+    rc = lib.adc_cholesky(ctypes.c_void_p(V.data_ptr()), m, float(tau), max_vec, ctypes.c_void_p(L.data_ptr()), piv,
+                          ctypes.byref(n), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != ADC_OK:
+        raise AdcError(rc, "adc_cholesky")
+    return L[: n.value], np.array(piv[: n.value], dtype=np.int64)
+
+
+def cholesky_mo(Lp, n_ao, C):
+    """adc_cholesky_mo: vectors over the pairs mu <= nu (float64 cuda [n_vec]
+    [n_ao (n_ao+1)/2]) to the molecular basis with complex128 cuda C
+    [n_ao][n_mo]; returns complex128 cuda [n_vec][n_mo][n_mo]."""
+    import torch
+    lib = load()
+    assert Lp.is_cuda and Lp.dtype == torch.float64 and Lp.is_contiguous()
+    assert C.is_cuda and C.dtype == torch.complex128 and C.is_contiguous() and C.shape[0] == n_ao
+    assert Lp.shape[1] == n_ao * (n_ao + 1) // 2
+    n_vec, n_mo = int(Lp.shape[0]), int(C.shape[1])
+    out = torch.empty((n_vec, n_mo, n_mo), dtype=torch.complex128, device=Lp.device)
+    rc = lib.adc_cholesky_mo(ctypes.c_void_p(Lp.data_ptr()), n_vec, n_ao, ctypes.c_void_p(C.data_ptr()), n_mo,
+                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != ADC_OK:
+        raise AdcError(rc, "adc_cholesky_mo")
+    return out
 
 
 class Batch:

@@ -193,6 +193,7 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     op.inst = &I;
     op.owner = h;
     op.ladder_bw = ladder_backward;
+    op.prec = prec;
     tape_record(cx, op);
   }
   const int v = I.v;
@@ -1936,7 +1937,7 @@ void ladder_backward(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY) 
   const int64_t ldY = op.n[0], offY = op.n[1], ldS = op.n[2], offS = op.n[3], nrow = op.n[4];
   const int k = (int)op.n[5];
   if (Pv == 0 || nrow == 0 || k == 0) return;
-  if (gY) ladder(h, I, gS, ldS, offS, gY, ldY, offY, nrow, k, {op.alpha.re, -op.alpha.im}, 0);
+  if (gY) ladder(h, I, gS, ldS, offS, gY, ldY, offY, nrow, k, {op.alpha.re, -op.alpha.im}, op.prec);
   Tensor Gam = tnew(cx, {Pv, Pv}, false);
   {
     Tensor gSv = tensor_view(const_cast<double2*>(gS) + offS, {k, nrow, Pv}, {ldS, Pv, 1});
@@ -2048,6 +2049,9 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     J.n1 = I.n1; J.n2 = I.n2; J.dim = dim; J.Po = I.Po; J.Pv = I.Pv;
     J.eps = I.eps; J.Loo = I.Loo; J.Lov = I.Lov; J.Lvo = I.Lvo; J.Lvv = I.Lvv;
     J.pair_o = I.pair_o; J.pair_v = I.pair_v; J.diag = I.diag;
+    // a split-bf16 ladder reads the instance's planes of L_vv (the same L_vv)
+    if (h->opt.precision == ADC_SPLIT_BF16 && I.kind != ADC_IP) ensure_planes(h, I);
+    J.Lq = I.Lq; J.Kq = I.Kq;
     std::vector<double> eps_h(n);
     hipcheck(hipMemcpy(eps_h.data(), I.eps, sizeof(double) * n, hipMemcpyDeviceToHost), "bw eps");
     T.recording = true;
@@ -2060,7 +2064,9 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
       else ea_init(h, J, P, eps_h);
       for (Tensor* q : {&P.Lt, &P.Ht, &P.t2, &P.ts}) tfree(cx, *q);
     }
-    sigma_dispatch(h, J, Yc.p, Sg.p, k, 0);
+    // the sigma part in the handle's arithmetic (its reverse rules follow
+    // it); the one-off part above stays FP64, as in adc_init
+    sigma_dispatch(h, J, Yc.p, Sg.p, k, h->opt.precision);
     T.recording = false;
     {
       Tensor gS = grad_view(cx, Sg);

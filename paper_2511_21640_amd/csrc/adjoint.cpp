@@ -117,7 +117,22 @@ void bw_perm(Ctx& cx, const TapeOp& op) {
   scale_view(cx, GC, conjc(op.beta));
 }
 
+void bw_op_in(Ctx& cx, const TapeOp& op);
+
+// every reverse rule runs in the arithmetic of its forward op
 void bw_op(Ctx& cx, const TapeOp& op) {
+  const int saved = cx.prec;
+  cx.prec = op.prec;
+  try {
+    bw_op_in(cx, op);
+  } catch (...) {
+    cx.prec = saved;
+    throw;
+  }
+  cx.prec = saved;
+}
+
+void bw_op_in(Ctx& cx, const TapeOp& op) {
   Tape& T = *cx.tape;
   switch (op.kind) {
     case TapeOp::CTR: bw_ctr(cx, op); break;

@@ -633,6 +633,7 @@ void permute_into(Ctx& cx, const Tensor& src, const View& v, const std::string& 
 void tape_record(Ctx& cx, TapeOp op) {
   Tape* t = cx.tape;
   if (!t || !t->recording) return;
+  if (op.kind != TapeOp::LADDER) op.prec = cx.prec;
   bool rg = op.kind == TapeOp::LADDER;  // the ladder always reads L_vv
   for (const Tensor* x : {&op.A, &op.B}) rg = rg || (x->p && t->rg(x->p));
   const int ic = op.C.p ? t->find(op.C.p) : -1;

@@ -289,6 +289,9 @@ struct TapeOp {
   const int2* po = nullptr;
   const int2* pv = nullptr;
   Tensor extra;
+  // arithmetic the op ran in (ctr()'s precision, or the ladder's); its
+  // reverse rule runs in the same one
+  int prec = 0;
   void* inst = nullptr;     // LADDER: the instance whose L_vv the ladder reads
   void* owner = nullptr;    // LADDER: the library handle
   LadderBw ladder_bw = nullptr;

@@ -191,3 +191,44 @@ def test_c5_vjp_matches_oracle_gradient():
         assert abs(got - pr["value"]) <= 1e-10 * ref["fro"], (pr, got)
     assert abs(dx - ref["dx"]) <= 1e-11 * max(1.0, abs(ref["dx"])), (dx, ref["dx"])
     h.close()
+
+
+def test_c5_mixed_vjp_and_root_gradients():
+    """The adjoint configuration in mixed precision: a split-bf16 handle runs
+    the sigma part of the recomputation and its reverse in split-bf16 (the
+    one-off part, dx and the gradient accumulation stay FP64).  Its dL must
+    equal the FP64 handle's within 1e-4 relative (max |d dL| / max |dL|), and
+    the eigenvalue gradients of the mixed roots (split-bf16 Davidson with FP64
+    refinement, mixed backward) the FP64 ones within 1e-4 relative."""
+    from adcgen import trial_vectors
+
+    print("case C5 mixed vjp and root gradients", flush=True)
+    P = config_problem("C5")
+    h64 = adc.Handle(P.kind, P.o, P.v, P.eps, P.L, P.n_roots, x=P.x)
+    hbf = adc.Handle(P.kind, P.o, P.v, P.eps, P.L, P.n_roots, x=P.x, precision="split_bf16")
+    Y = torch.from_numpy(trial_vectors(2, h64.dim, 81)).cuda()
+    Sb = torch.from_numpy(trial_vectors(2, h64.dim, 82)).cuda()
+    dL64, dx64 = h64.sigma_backward(Sb, Y)
+    dLbf, dxbf = hbf.sigma_backward(Sb, Y)
+    err = ((dLbf - dL64).abs().max() / dL64.abs().max()).item()
+    print(f"  vjp dL mixed vs fp64 {err:.2e}, dx {dxbf:.12e} vs {dx64:.12e}", flush=True)
+    assert 1e-12 < err <= 1e-4
+    assert abs(dxbf - dx64) <= 1e-10 * max(1.0, abs(dx64))
+    h64.close()
+    hbf.close()
+    grads = {}
+    for prec in ("fp64", "split_bf16"):
+        # the gradient y^H dM y is first order in the eigenvector error
+        # (~|r|/gap), so both solves end with an FP64 residual of 1e-7
+        spec = dict(kind=P.kind, o=P.o, v=P.v, eps=P.eps, n_roots=P.n_roots, precision=prec, conv_tol=1e-7)
+        L = torch.from_numpy(P.L).cuda().requires_grad_(True)
+        x = torch.tensor(P.x, dtype=torch.float64, device="cuda", requires_grad=True)
+        w = ADCRoots.apply(L, x, spec)
+        grads[prec] = [torch.autograd.grad(w[r], (L, x), retain_graph=True) for r in range(P.n_roots)]
+    for r in range(P.n_roots):
+        g64, x64 = grads["fp64"][r]
+        gbf, xbf = grads["split_bf16"][r]
+        e = ((gbf - g64).abs().max() / g64.abs().max()).item()
+        ex = abs(xbf.item() - x64.item()) / max(1.0, abs(x64.item()))
+        print(f"  root {r}: dw/dL mixed vs fp64 {e:.2e}, dw/dx {ex:.2e}", flush=True)
+        assert e <= 1e-4 and ex <= 1e-4, (r, e, ex)
