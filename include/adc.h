@@ -121,7 +121,13 @@ typedef struct adc_problem {
  *                 repeated calls with the same inputs and options give
  *                 bitwise identical results on the same device [0]; the
  *                 library has no atomics in its arithmetic, so only timed
- *                 choices can change rounding between runs */
+ *                 choices can change rounding between runs
+ *   root_follow   1 = root-specific Davidson (Section 2.4, the root-specific
+ *                 solver of the SS-FNS scheme) for instances given a start
+ *                 block: root r is, in every iteration, the Ritz pair with the
+ *                 largest overlap with start vector r (among those not taken
+ *                 by an earlier root) instead of the r-th lowest; omega is
+ *                 then in the order of the start vectors [0] */
 typedef struct adc_options {
   int precision;
   double conv_tol;
@@ -136,6 +142,7 @@ typedef struct adc_options {
   int autotune;
   const char* tune_cache;
   int deterministic;
+  int root_follow;
 } adc_options;
 
 typedef struct adc_handle adc_handle;
@@ -263,6 +270,36 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
  * INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR. */
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k,
                        void* dL, double* dx);
+
+/* Frozen natural spinors of instance inst (Section 2.4, eqs. 25-30): the
+ * virtual-virtual density D_ab = 1/2 sum_{cij} <ac||ij><ij||bc> /
+ * (e_ij^ac e_ij^bc) (eq. 25), plus, when X is given, the state density of X
+ * through the zeroth-order intermediate states, D_ab += <X| a+_b a_a |X>
+ * (eq. 31, state-specific FNS; EE and EA only); its eigenvectors (natural
+ * spinors, eq. 26) with occupation >= eta_crit kept (eq. 27); the Fock block
+ * in that basis diagonalised (eqs. 28-29); B = V~ Z~ (eq. 30).  The problem is
+ * then given in the truncated basis: virtual spinor a' = sum_a a B_aa', and the
+ * Cholesky vectors follow (eq. 42 with the coefficients C B).
+ *   X        NULL, or device c128 [dim] a vector of the instance (normally an
+ *            ADC(2) eigenvector) for the state-specific density
+ *   eta_crit occupation threshold (finite)
+ *   n_vir    host: v', the number of kept virtual spinors (>= 2)
+ *   eps_out  host float64 [o + v]: the occupied energies, then the v'
+ *            semicanonical virtual energies (ascending)
+ *   L_out    device c128, room for [N][o+v][o+v]; receives [N][o+v'][o+v']
+ *            (Hermitian per Q), ready for adc_init with n_vir = v'
+ *   eta_out  NULL or host float64 [v]: the occupations, descending
+ *   B_out    NULL or device c128, room for [v][v]; receives B as [v][v']
+ *   X_out    NULL or device c128, room for X's size: X in the truncated basis
+ *            (every virtual index contracted with conj(B), packed for v'),
+ *            the start vector of the truncated problem
+ * The v x v and v' x v' Hermitian eigenproblems run on the host (cyclic
+ * Jacobi); the density, the vector and Cholesky transforms are device GEMMs
+ * in FP64.  Synchronous.  Errors: INVALID_ARG (NULL outputs, eta_crit keeping
+ * fewer than two spinors), UNSUPPORTED (X given for an IP instance),
+ * OUT_OF_MEMORY, HIP_ERROR. */
+int adc_fns(adc_handle* h, int inst, const void* X, double eta_crit, int* n_vir, double* eps_out, void* L_out,
+            double* eta_out, void* B_out, void* X_out);
 
 /* One-step pivoted Cholesky of the electron-repulsion matrix (Section 2.5,
  * eq. 41 and the one-step procedure): V is the symmetric positive

@@ -25,7 +25,8 @@ ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE_INPUT", -3: "NOT_HERMITIAN", -4: "OU
 
 # Every symbol include/adc.h declares.
 EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_sigma_term", "adc_sigma_noalloc", "adc_davidson",
-           "adc_sigma_backward", "adc_cholesky", "adc_cholesky_mo", "adc_init_ms", "adc_free", "adc_strerror"]
+           "adc_sigma_backward", "adc_fns", "adc_cholesky", "adc_cholesky_mo", "adc_init_ms", "adc_free",
+           "adc_strerror"]
 TERMS = {"all": 0, "ladder": 1}
 
 
@@ -41,14 +42,15 @@ class AdcOptions(ctypes.Structure):
                 ("max_subspace", ctypes.c_int), ("refine_fp64", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_budget", ctypes.c_size_t), ("verbose", ctypes.c_int), ("n_streams", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
-                ("deterministic", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("root_follow", ctypes.c_int)]
 
 
 def _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose, n_streams,
-             graphs, autotune, tune_cache, deterministic):
+             graphs, autotune, tune_cache, deterministic, root_follow=False):
     return AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1 if refine_fp64 else -1,
                       ctypes.c_void_p(stream), mem_budget, int(verbose), int(n_streams), 1 if graphs else 0,
-                      1 if autotune else 0, tune_cache.encode() if tune_cache else None, 1 if deterministic else 0)
+                      1 if autotune else 0, tune_cache.encode() if tune_cache else None, 1 if deterministic else 0,
+                      1 if root_follow else 0)
 
 
 class AdcError(RuntimeError):
@@ -84,6 +86,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.adc_sigma_backward.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.adc_fns.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                            ctypes.c_void_p, ctypes.c_void_p]
     lib.adc_cholesky.argtypes = [ctypes.c_void_p, ctypes.c_longlong, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.c_void_p]
     lib.adc_cholesky_mo.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
@@ -112,7 +117,7 @@ class Handle:
 
     def __init__(self, kind, o, v, eps, L, n_roots, x=1.0, precision="fp64", conv_tol=1e-7, max_iter=200,
                  max_subspace=0, stream=None, mem_budget=0, verbose=False, graphs=False, autotune=False,
-                 refine_fp64=True, tune_cache=None, deterministic=False):
+                 refine_fp64=True, tune_cache=None, deterministic=False, root_follow=False):
         import torch
         self._lib = load()
         self.kind, self.o, self.v = kind, int(o), int(v)
@@ -134,7 +139,7 @@ class Handle:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose, 0,
-                        graphs, autotune, tune_cache, deterministic)
+                        graphs, autotune, tune_cache, deterministic, root_follow)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(ctypes.byref(prob), 1, ctypes.byref(opts), ctypes.byref(h))
         if rc != ADC_OK:
@@ -238,6 +243,40 @@ class Handle:
         return dict(omega=omega, resnorm=res, iters=iters[0], converged=np.array(conv[:], dtype=bool),
                     vectors=vecs, status=rc)
 
+    def fns(self, eta_crit, X=None, want_B=False):
+        """adc_fns: frozen (or, with X, state-specific) natural spinors.
+        Returns dict(n_vir, eps (numpy [o + v']), L (complex128 cuda
+        [N][o+v'][o+v']), eta (numpy [v], descending), B (cuda [v][v'] or
+        None), X (X in the truncated basis, cuda [dim'], or None))."""
+        import torch
+        o, v = self.o, self.v
+        n = o + v
+        n_chol = int(self._L.shape[0])
+        Lbuf = torch.empty(n_chol * n * n, dtype=torch.complex128, device="cuda")
+        eps = np.zeros(n)
+        eta = np.zeros(v)
+        nv = ctypes.c_int(0)
+        Bbuf = torch.empty(v * v, dtype=torch.complex128, device="cuda") if want_B else None
+        Xin = Xbuf = None
+        if X is not None:
+            assert X.is_cuda and X.dtype == torch.complex128 and X.is_contiguous() and X.numel() == self.dim
+            Xin = X
+            Xbuf = torch.empty(self.dim, dtype=torch.complex128, device="cuda")
+        rc = self._lib.adc_fns(self._h, 0, ctypes.c_void_p(Xin.data_ptr()) if Xin is not None else None,
+                               float(eta_crit), ctypes.byref(nv), eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.c_void_p(Lbuf.data_ptr()), eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               ctypes.c_void_p(Bbuf.data_ptr()) if Bbuf is not None else None,
+                               ctypes.c_void_p(Xbuf.data_ptr()) if Xbuf is not None else None)
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_fns")
+        v2 = nv.value
+        n2 = o + v2
+        Po, Pv2 = o * (o - 1) // 2, v2 * (v2 - 1) // 2
+        dim2 = {"EE": o * v2 + Po * Pv2, "IP": o + Po * v2, "EA": v2 + o * Pv2}[self.kind]
+        return dict(n_vir=v2, eps=eps[:n2].copy(), L=Lbuf[: n_chol * n2 * n2].view(n_chol, n2, n2), eta=eta,
+                    B=Bbuf[: v * v2].view(v, v2) if Bbuf is not None else None,
+                    X=Xbuf[:dim2] if Xbuf is not None else None)
+
     def close(self):
         if getattr(self, "_h", None):
             self._lib.adc_free(self._h)
@@ -295,22 +334,30 @@ class Batch:
 
     def __init__(self, problems, precision="fp64", conv_tol=1e-7, max_iter=200, max_subspace=0, stream=None,
                  mem_budget=0, verbose=False, n_streams=0, graphs=False, autotune=False, refine_fp64=True,
-                 tune_cache=None, deterministic=False):
+                 tune_cache=None, deterministic=False, root_follow=False):
         import torch
         self._lib = load()
         self._keep = []
         arr = (AdcProblem * len(problems))()
+        self._dev = []  # borrowed device L tensors, kept alive with the handle
         for i, p in enumerate(problems):
             eps = np.ascontiguousarray(p["eps"], dtype=np.float64)
-            L = np.ascontiguousarray(p["L"], dtype=np.complex128)
+            L = p["L"]
+            if hasattr(L, "is_cuda") and L.is_cuda:
+                assert L.dtype == torch.complex128 and L.is_contiguous()
+                self._dev.append(L)
+                Lptr, on_dev = L.data_ptr(), 1
+            else:
+                L = np.ascontiguousarray(L, dtype=np.complex128)
+                Lptr, on_dev = L.ctypes.data, 0
             self._keep += [eps, L]
             arr[i] = AdcProblem(KINDS[p["kind"]], int(p["o"]), int(p["v"]), int(L.shape[0]), int(p["n_roots"]),
-                                eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), L.ctypes.data, 0,
+                                eps.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), Lptr, on_dev,
                                 float(p.get("x", 1.0)))
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         opts = _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose,
-                        n_streams, graphs, autotune, tune_cache, deterministic)
+                        n_streams, graphs, autotune, tune_cache, deterministic, root_follow)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
         self._keep = []  # host copies are no longer needed
@@ -340,9 +387,19 @@ class Batch:
             raise AdcError(rc, "adc_sigma")
         return S.reshape(Y.shape)
 
-    def davidson(self, want_vectors=False):
+    def davidson(self, want_vectors=False, guesses=None):
+        """Solve every instance.  guesses: None, or a list with, per
+        instance, None or a contiguous complex128 cuda tensor [n_roots][dim]."""
         import torch
         n = len(self.dims)
+        g_arr = None
+        if guesses is not None:
+            assert len(guesses) == n
+            for g, k, d in zip(guesses, self.n_roots, self.dims):
+                if g is not None and not (g.is_cuda and g.dtype == torch.complex128 and g.is_contiguous()
+                                          and tuple(g.shape) == (k, d)):
+                    raise ValueError(f"guess must be a contiguous complex128 cuda tensor of shape ({k}, {d})")
+            g_arr = (ctypes.c_void_p * n)(*[g.data_ptr() if g is not None else None for g in guesses])
         tot = sum(self.n_roots)
         omega, res = np.zeros(tot), np.zeros(tot)
         iters = (ctypes.c_int * n)()
@@ -350,7 +407,7 @@ class Batch:
         vecs = [torch.empty((k, d), dtype=torch.complex128, device="cuda") for k, d in zip(self.n_roots, self.dims)] \
             if want_vectors else None
         v_arr = (ctypes.c_void_p * n)(*[v.data_ptr() for v in vecs]) if vecs is not None else None
-        rc = self._lib.adc_davidson(self._h, None, omega.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), v_arr,
+        rc = self._lib.adc_davidson(self._h, g_arr, omega.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), v_arr,
                                     res.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), iters, conv)
         if rc not in (ADC_OK, ADC_NOT_CONVERGED):
             raise AdcError(rc, "adc_davidson")

@@ -1766,6 +1766,14 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   }
   std::vector<double> w_old(k, 1e300), w(k), rn(k);
   std::vector<int> conv(k, 0);
+  std::vector<int> sel(k);
+  // root following (a given start block, root_follow set): the start vectors
+  // are the references every iteration's Ritz vectors are matched against
+  double2* Gref = nullptr;
+  if (guess && h->opt.root_follow) {
+    Gref = cx.pool.get((int64_t)k * dim);
+    hipcheck(hipMemcpyAsync(Gref, V, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "ref");
+  }
   int it = 0;
   // refine_fp64 < 0: a mixed-precision solve iterates to conv_tol in its own
   // precision and reports its own residuals (no FP64 restart)
@@ -1783,12 +1791,34 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     std::vector<double> wall;
     std::vector<zc> U;
     heevj(m, G, wall, U);
+    // root r: the r-th lowest Ritz pair, or (root following) the one with the
+    // largest overlap with start vector r among those not yet taken
+    for (int r = 0; r < k; ++r) sel[r] = r;
+    if (Gref) {
+      const auto O = gram(cx, V, m, Gref, k, dim);  // O[a][r] = <V_a|g_r>
+      std::vector<char> used(m, 0);
+      for (int r = 0; r < k; ++r) {
+        int best = -1;
+        double bo = -1.0;
+        for (int j = 0; j < m; ++j) {
+          if (used[j]) continue;
+          zc s = 0.0;
+          for (int a = 0; a < m; ++a) s += std::conj(U[(size_t)a * m + j]) * O[(size_t)a * k + r];
+          if (std::norm(s) > bo) {
+            bo = std::norm(s);
+            best = j;
+          }
+        }
+        sel[r] = best;
+        used[best] = 1;
+      }
+    }
     std::vector<zc> Uk((size_t)m * k);
     for (int a = 0; a < m; ++a)
-      for (int r = 0; r < k; ++r) Uk[(size_t)a * k + r] = U[(size_t)a * m + r];
+      for (int r = 0; r < k; ++r) Uk[(size_t)a * k + r] = U[(size_t)a * m + sel[r]];
     combine(cx, Uk, m, k, V, X, dim, C1(), C0());
     combine(cx, Uk, m, k, S, AX, dim, C1(), C0());
-    for (int r = 0; r < k; ++r) w[r] = wall[r];
+    for (int r = 0; r < k; ++r) w[r] = wall[sel[r]];
     hipcheck(hipMemcpyAsync(wd, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, cx.stream), "w");
     launch_resid(AX, X, wd, R, k, dim, cx.stream);
     auto r2 = row_norms2(cx, R, k, dim);
@@ -1860,10 +1890,14 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     }
     if (m + nn > mmax) {
       // collapse onto the 2k lowest Ritz vectors of the current subspace
+      // (with root following: the followed ones first, then the lowest)
       const int mc = std::min(2 * k, m);
+      std::vector<int> keep(sel.begin(), sel.end());
+      for (int j = 0; j < m && (int)keep.size() < mc; ++j)
+        if (std::find(keep.begin(), keep.end(), j) == keep.end()) keep.push_back(j);
       std::vector<zc> Uc((size_t)m * mc);
       for (int a = 0; a < m; ++a)
-        for (int r = 0; r < mc; ++r) Uc[(size_t)a * mc + r] = U[(size_t)a * m + r];
+        for (int r = 0; r < mc; ++r) Uc[(size_t)a * mc + r] = U[(size_t)a * m + keep[r]];
       double2* T = cx.pool.get((int64_t)mc * dim);
       combine(cx, Uc, m, mc, V, T, dim, C1(), C0());
       hipcheck(hipMemcpyAsync(V, T, sizeof(double2) * mc * dim, hipMemcpyDeviceToDevice, cx.stream), "col");
@@ -1913,6 +1947,7 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   if (vecs) hipcheck(hipMemcpyAsync(vecs, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "vecs");
   hipcheck(hipStreamSynchronize(cx.stream), "dav end");
   for (double2* p : {V, S, X, AX, R}) cx.pool.put(p);
+  if (Gref) cx.pool.put(Gref);
   cx.pool.put((double2*)wd);
   for (int r = 0; r < k; ++r)
     if (!conv[r]) return ADC_NOT_CONVERGED;
@@ -2111,6 +2146,164 @@ int guarded(F&& f) {
   } catch (...) {
     return ADC_ERR_HIP;
   }
+}
+
+// ============================================================================
+// frozen natural spinors (Section 2.4, eqs. 25-31)
+// ============================================================================
+// The virtual density, its natural spinors and the truncated semicanonical
+// basis B; the problem (orbital energies, Cholesky vectors) and optionally a
+// vector of the instance's kind carried into that basis.
+void fns_build(adc_handle* h, Inst& I, const double2* X, double eta_crit, int* n_vir, double* eps_out,
+               double2* L_out, double* eta_out, double2* B_out, double2* X_out) {
+  Ctx& cx = *I.cx;
+  const int o = I.o, v = I.v, N = I.N;
+  const int saved = cx.prec;
+  cx.prec = 0;
+  // eq. 25: D_ab = 1/2 sum_{ijc} t_ij^ac conj(t_ij^bc)
+  Tensor D = tnew(cx, {v, v}, false);
+  ctr(cx, CR(0.5), I.t1, "ijac", false, I.t1, "ijbc", true, C0(), D, "ab");
+  if (X) {
+    // eq. 31: the state's virtual density through the zeroth-order
+    // intermediate states, D_ab += <Psi| a+_b a_a |Psi>
+    if (I.kind == ADC_EE) {
+      Tensor Xs = tensor_view(const_cast<double2*>(X), {o, v}, {});
+      ctr(cx, C1(), Xs, "ia", false, Xs, "ib", true, C1(), D, "ab");
+      Tensor Ya = tnew(cx, {1, o, o, v, v}, false);
+      launch_unpack_doubles(0, X, I.dim, I.n1, 1, o, v, Ya.p, nullptr, cx.stream);
+      ctr(cx, CR(0.5), Ya, "zijac", false, Ya, "zijbc", true, C1(), D, "ab");
+      tfree(cx, Ya);
+    } else {
+      Tensor Xs = tensor_view(const_cast<double2*>(X), {1, v}, {});
+      ctr(cx, C1(), Xs, "za", false, Xs, "zb", true, C1(), D, "ab");
+      Tensor Ya = tnew(cx, {1, o, v, v}, false);
+      launch_unpack_doubles(2, X, I.dim, I.n1, 1, o, v, Ya.p, nullptr, cx.stream);
+      ctr(cx, C1(), Ya, "zjac", false, Ya, "zjbc", true, C1(), D, "ab");
+      tfree(cx, Ya);
+    }
+  }
+  std::vector<double2> hD((size_t)v * v);
+  hipcheck(hipMemcpyAsync(hD.data(), D.p, sizeof(double2) * hD.size(), hipMemcpyDeviceToHost, cx.stream), "fns D");
+  hipcheck(hipStreamSynchronize(cx.stream), "fns D sync");
+  tfree(cx, D);
+  // eq. 26: natural spinors (the small Hermitian eigenproblem on the host)
+  std::vector<zc> A((size_t)v * v), U;
+  for (int a = 0; a < v; ++a)
+    for (int b = 0; b < v; ++b) {
+      const zc x(hD[(size_t)a * v + b].x, hD[(size_t)a * v + b].y), y(hD[(size_t)b * v + a].x, -hD[(size_t)b * v + a].y);
+      A[(size_t)a * v + b] = 0.5 * (x + y);
+    }
+  std::vector<double> w;
+  heevj(v, A, w, U);  // ascending
+  // occupations descending; eq. 27: keep eta >= eta_crit
+  std::vector<int> kept;
+  for (int c = v - 1; c >= 0; --c)
+    if (w[c] >= eta_crit) kept.push_back(c);
+  if (eta_out)
+    for (int c = 0; c < v; ++c) eta_out[c] = w[v - 1 - c];
+  const int v2 = (int)kept.size();
+  if (v2 < 2) throw Status{ADC_ERR_INVALID_ARG, "eta_crit keeps fewer than two virtual spinors"};
+  // eq. 28: F~ = V~^H diag(e_vir) V~
+  std::vector<double> ev(v);
+  {
+    std::vector<double> e(o + v);
+    hipcheck(hipMemcpy(e.data(), I.eps, sizeof(double) * (o + v), hipMemcpyDeviceToHost), "fns eps");
+    for (int a = 0; a < v; ++a) ev[a] = e[o + a];
+    for (int i = 0; i < o; ++i) eps_out[i] = e[i];
+  }
+  std::vector<zc> F((size_t)v2 * v2);
+  for (int p = 0; p < v2; ++p)
+    for (int q = 0; q < v2; ++q) {
+      zc s = 0.0;
+      for (int a = 0; a < v; ++a) s += std::conj(U[(size_t)a * v + kept[p]]) * ev[a] * U[(size_t)a * v + kept[q]];
+      F[(size_t)p * v2 + q] = s;
+    }
+  for (int p = 0; p < v2; ++p)
+    for (int q = p + 1; q < v2; ++q) {
+      const zc x = 0.5 * (F[(size_t)p * v2 + q] + std::conj(F[(size_t)q * v2 + p]));
+      F[(size_t)p * v2 + q] = x;
+      F[(size_t)q * v2 + p] = std::conj(x);
+    }
+  std::vector<double> et;
+  std::vector<zc> Z;
+  heevj(v2, F, et, Z);  // eq. 29, ascending
+  // eq. 30: B = V~ Z~
+  std::vector<double2> hB((size_t)v * v2);
+  for (int a = 0; a < v; ++a)
+    for (int c = 0; c < v2; ++c) {
+      zc s = 0.0;
+      for (int p = 0; p < v2; ++p) s += U[(size_t)a * v + kept[p]] * Z[(size_t)p * v2 + c];
+      hB[(size_t)a * v2 + c] = make_double2(s.real(), s.imag());
+    }
+  for (int c = 0; c < v2; ++c) eps_out[o + c] = et[c];
+  *n_vir = v2;
+  Tensor B = tnew(cx, {v, v2}, false);
+  hipcheck(hipMemcpyAsync(B.p, hB.data(), sizeof(double2) * hB.size(), hipMemcpyHostToDevice, cx.stream), "fns B");
+  if (B_out) hipcheck(hipMemcpyAsync(B_out, B.p, sizeof(double2) * hB.size(), hipMemcpyDeviceToDevice, cx.stream),
+                      "fns B out");
+  // the Cholesky vectors follow the spinors (eq. 42 with the coefficients C B)
+  const int64_t n2 = o + v2;
+  auto blk = [&](int r0, int nr, int c0, int nc) {
+    return tensor_view(L_out + (int64_t)r0 * n2 + c0, {N, nr, nc}, {n2 * n2, n2, 1});
+  };
+  {
+    Tensor oo = blk(0, o, 0, o), ov = blk(0, o, o, v2), vo = blk(o, v2, 0, o), vv = blk(o, v2, o, v2);
+    perm(cx, C1(), I.Loo, "Qij", false, C0(), oo, "Qij");
+    ctr(cx, C1(), I.Lov, "Qib", false, B, "bc", false, C0(), ov, "Qic");
+    ctr(cx, C1(), B, "ac", true, I.Lvo, "Qaj", false, C0(), vo, "Qcj");
+    Tensor T = tnew(cx, {N, v, v2}, false);
+    ctr(cx, C1(), I.Lvv, "Qab", false, B, "bd", false, C0(), T, "Qad");
+    ctr(cx, C1(), B, "ac", true, T, "Qad", false, C0(), vv, "Qcd");
+    tfree(cx, T);
+  }
+  if (X && X_out) {
+    // the vector in the new basis: every virtual index contracted with conj(B)
+    int64_t n1b, n2b;
+    dims_of(I.kind, o, v2, &n1b, &n2b);
+    const int64_t dimb = n1b + n2b;
+    if (I.kind == ADC_EE) {
+      Tensor Xs = tensor_view(const_cast<double2*>(X), {o, v}, {});
+      Tensor Os = tensor_view(X_out, {o, v2}, {});
+      ctr(cx, C1(), B, "ac", true, Xs, "ia", false, C0(), Os, "ic");
+      Tensor Ya = tnew(cx, {1, o, o, v, v}, false);
+      launch_unpack_doubles(0, X, I.dim, I.n1, 1, o, v, Ya.p, nullptr, cx.stream);
+      Tensor T1 = tnew(cx, {1, o, o, v, v2}, false), T2 = tnew(cx, {1, o, o, v2, v2}, false);
+      ctr(cx, C1(), B, "bd", true, Ya, "zijab", false, C0(), T1, "zijad");
+      ctr(cx, C1(), B, "ac", true, T1, "zijad", false, C0(), T2, "zijcd");
+      // pack (i<j, c<d) of the antisymmetric result
+      std::vector<int2> po = pair_table(o), pv = pair_table(v2);
+      int2* dpo = (int2*)cx.pool.get(((int64_t)std::max<size_t>(1, po.size()) + 1) / 2);
+      int2* dpv = (int2*)cx.pool.get(((int64_t)std::max<size_t>(1, pv.size()) + 1) / 2);
+      if (!po.empty()) hipcheck(hipMemcpyAsync(dpo, po.data(), sizeof(int2) * po.size(), hipMemcpyHostToDevice, cx.stream), "po");
+      if (!pv.empty()) hipcheck(hipMemcpyAsync(dpv, pv.data(), sizeof(int2) * pv.size(), hipMemcpyHostToDevice, cx.stream), "pv");
+      // (the kernel reads eps even without a diagonal term: the instance's
+      // energies cover the indices below o + v2 <= o + v)
+      launch_pack_doubles(0, T2.p, X_out, nullptr, dimb, n1b, 1, o, v2, I.eps, C1(), 0, dpo, dpv, cx.stream);
+      hipcheck(hipStreamSynchronize(cx.stream), "fns pack sync");
+      cx.pool.put((double2*)dpo);
+      cx.pool.put((double2*)dpv);
+      for (Tensor* t : {&Ya, &T1, &T2}) tfree(cx, *t);
+    } else {
+      Tensor Xs = tensor_view(const_cast<double2*>(X), {v}, {});
+      Tensor Os = tensor_view(X_out, {v2}, {});
+      ctr(cx, C1(), B, "ac", true, Xs, "a", false, C0(), Os, "c");
+      Tensor Ya = tnew(cx, {1, o, v, v}, false);
+      launch_unpack_doubles(2, X, I.dim, I.n1, 1, o, v, Ya.p, nullptr, cx.stream);
+      Tensor T1 = tnew(cx, {1, o, v, v2}, false), T2 = tnew(cx, {1, o, v2, v2}, false);
+      ctr(cx, C1(), B, "bd", true, Ya, "zjab", false, C0(), T1, "zjad");
+      ctr(cx, C1(), B, "ac", true, T1, "zjad", false, C0(), T2, "zjcd");
+      std::vector<int2> pv = pair_table(v2);
+      int2* dpv = (int2*)cx.pool.get(((int64_t)pv.size() + 1) / 2);
+      hipcheck(hipMemcpyAsync(dpv, pv.data(), sizeof(int2) * pv.size(), hipMemcpyHostToDevice, cx.stream), "pv");
+      launch_pack_doubles(2, T2.p, X_out, nullptr, dimb, n1b, 1, o, v2, I.eps, C1(), 0, I.pair_o, dpv, cx.stream);
+      hipcheck(hipStreamSynchronize(cx.stream), "fns pack sync");
+      cx.pool.put((double2*)dpv);
+      for (Tensor* t : {&Ya, &T1, &T2}) tfree(cx, *t);
+    }
+  }
+  hipcheck(hipStreamSynchronize(cx.stream), "fns end");
+  tfree(cx, B);
+  cx.prec = saved;
 }
 
 // Bytes that an allocation-free sigma build of k vectors certainly takes from
@@ -2356,6 +2549,23 @@ int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, in
     }
     lane_wait(h, cx, false);
     hipcheck(hipGetLastError(), "sigma launch");
+    return (int)ADC_OK;
+  });
+}
+
+int adc_fns(adc_handle* h, int inst, const void* X, double eta_crit, int* n_vir, double* eps_out, void* L_out,
+            double* eta_out, void* B_out, void* X_out) {
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !n_vir || !eps_out || !L_out || !std::isfinite(eta_crit))
+    return ADC_ERR_INVALID_ARG;
+  Inst& I = h->inst[inst];
+  if (X && I.kind == ADC_IP) return ADC_ERR_UNSUPPORTED;
+  if (X_out && !X) return ADC_ERR_INVALID_ARG;
+  return guarded([&]() {
+    lane_wait(h, *I.cx, true);
+    fns_build(h, I, (const double2*)X, eta_crit, n_vir, eps_out, (double2*)L_out, eta_out, (double2*)B_out,
+              (double2*)X_out);
+    lane_wait(h, *I.cx, false);
+    hipcheck(hipGetLastError(), "fns launch");
     return (int)ADC_OK;
   });
 }
