@@ -271,6 +271,24 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k,
                        void* dL, double* dx);
 
+/* ISR one-particle properties of EE states (Section 2.2): for the k packed
+ * vectors Y (device c128 [k][dim], each normalised by the library first)
+ *   tdm  = rho^{0->K}_pq = sum_I conj(Y_IK) f^I_pq,  f^I_pq = <Psi~_I|c+_p c_q|Psi_0>
+ *          through first order (the reading: the paper fixes no order);
+ *   rho  = rho^K_pq = Y_K^* g(0) Y_K + rho_GS(2)_pq, the zeroth-order ISR
+ *          density of the state plus the second-order ground-state
+ *          correlation density (the shifted form Y^* G Y + D_0 with D_0 through
+ *          second order);
+ * both device c128 [k][n][n] (caller-owned, n = o + v, element [p][q] for
+ * c+_p c_q, occupied spinors first), each optional.  With a one-particle
+ * operator d (device c128 [n][n]) the library also returns D_K = sum_pq d_pq
+ * rho^K_pq (dk) and T_{0->K} = sum_pq d_pq rho^{0->K}_pq (tk), host float64
+ * [2k] as (re, im) pairs.  FP64 device contractions.  Synchronous.
+ * Errors: INVALID_ARG (k < 1, dk or tk without d), UNSUPPORTED (not EE),
+ * OUT_OF_MEMORY, HIP_ERROR. */
+int adc_properties(adc_handle* h, int inst, const void* Y, int k, void* rho, void* tdm, const void* d, double* dk,
+                   double* tk);
+
 /* Frozen natural spinors of instance inst (Section 2.4, eqs. 25-30): the
  * virtual-virtual density D_ab = 1/2 sum_{cij} <ac||ij><ij||bc> /
  * (e_ij^ac e_ij^bc) (eq. 25), plus, when X is given, the state density of X

@@ -25,8 +25,8 @@ ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE_INPUT", -3: "NOT_HERMITIAN", -4: "OU
 
 # Every symbol include/adc.h declares.
 EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_sigma_term", "adc_sigma_noalloc", "adc_davidson",
-           "adc_sigma_backward", "adc_fns", "adc_cholesky", "adc_cholesky_mo", "adc_init_ms", "adc_free",
-           "adc_strerror"]
+           "adc_sigma_backward", "adc_properties", "adc_fns", "adc_cholesky", "adc_cholesky_mo", "adc_init_ms",
+           "adc_free", "adc_strerror"]
 TERMS = {"all": 0, "ladder": 1}
 
 
@@ -86,6 +86,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.adc_sigma_backward.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.adc_properties.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]
     lib.adc_fns.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(ctypes.c_int),
                             ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                             ctypes.c_void_p, ctypes.c_void_p]
@@ -242,6 +245,34 @@ class Handle:
             raise AdcError(rc, "adc_davidson")
         return dict(omega=omega, resnorm=res, iters=iters[0], converged=np.array(conv[:], dtype=bool),
                     vectors=vecs, status=rc)
+
+    def properties(self, Y, d=None):
+        """adc_properties for EE vectors Y (complex128 cuda [k][dim]): returns
+        dict(rho, tdm) as complex128 cuda [k][n][n], and with a one-particle
+        operator d (complex128 cuda [n][n]) also D (state expectation values)
+        and T (transition moments) as complex numpy arrays [k]."""
+        import torch
+        assert Y.is_cuda and Y.dtype == torch.complex128 and Y.is_contiguous() and Y.shape[-1] == self.dim
+        Y2 = Y.reshape(-1, self.dim)
+        k, n = Y2.shape[0], self.o + self.v
+        rho = torch.empty((k, n, n), dtype=torch.complex128, device="cuda")
+        tdm = torch.empty_like(rho)
+        dk = np.zeros(2 * k)
+        tk = np.zeros(2 * k)
+        if d is not None:
+            assert d.is_cuda and d.dtype == torch.complex128 and d.is_contiguous() and tuple(d.shape) == (n, n)
+        pd = ctypes.c_void_p(d.data_ptr()) if d is not None else None
+        rc = self._lib.adc_properties(self._h, 0, ctypes.c_void_p(Y2.data_ptr()), k, ctypes.c_void_p(rho.data_ptr()),
+                                      ctypes.c_void_p(tdm.data_ptr()), pd,
+                                      dk.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if d is not None else None,
+                                      tk.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if d is not None else None)
+        if rc != ADC_OK:
+            raise AdcError(rc, "adc_properties")
+        out = dict(rho=rho, tdm=tdm)
+        if d is not None:
+            out["D"] = dk[0::2] + 1j * dk[1::2]
+            out["T"] = tk[0::2] + 1j * tk[1::2]
+        return out
 
     def fns(self, eta_crit, X=None, want_B=False):
         """adc_fns: frozen (or, with X, state-specific) natural spinors.

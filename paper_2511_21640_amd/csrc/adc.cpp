@@ -52,6 +52,7 @@ struct Inst {
   Tensor oooo, ooov, oovv, ovov, ovvv;
   Tensor ring;            // [k][c][j][b] = <kb||jc>
   Tensor t1;              // [o][o][v][v]
+  Tensor ts;              // second-order singles [o][v] (properties: ground-state density)
   Tensor M11x;            // n1 x n1, M11(0..2) + x M11(3)
   Tensor M11b;            // n1 x n1, M11(3) (the x derivative of M11x)
   Tensor W;               // EE: [I][J][i][B] = sum_cd t*_IJcd <cd||iB>
@@ -1368,7 +1369,9 @@ void inst_init(adc_handle* h, const adc_problem* p, Inst& I) {
     if (I.kind == ADC_EE) ee_init(h, I, P, eps_h);
     else if (I.kind == ADC_IP) ip_init(h, I, P, eps_h);
     else ea_init(h, I, P, eps_h);
-    for (Tensor* q : {&P.Lt, &P.Ht, &P.t2, &P.ts}) tfree(cx, *q);
+    I.ts = P.ts;  // kept for the ground-state density of the properties
+    P.ts = Tensor{};
+    for (Tensor* q : {&P.Lt, &P.Ht, &P.t2}) tfree(cx, *q);
   }
   // the trial-independent operands are frozen from here on: their split-bf16
   // planes are kept per layout (at most their own size in bytes) and reused
@@ -2306,6 +2309,104 @@ void fns_build(adc_handle* h, Inst& I, const double2* X, double eta_crit, int* n
   cx.prec = saved;
 }
 
+// ============================================================================
+// ISR one-particle properties of EE states (Section 2.2)
+// ============================================================================
+// rho^{0->K} = Y^* f through first order and rho^K = Y^* g(0) Y + rho_GS(2)
+// for k normalised EE vectors (the rows of Y are normalised here first), as
+// [k][n][n] blocks; optionally D_K = sum d_pq rho^K_pq and T_K = sum d_pq
+// rho^{0->K}_pq for a one-particle operator d [n][n].
+void props_build(adc_handle* h, Inst& I, const double2* Y, int k, double2* rho, double2* tdm, const double2* d,
+                 double* dk, double* tk) {
+  (void)h;
+  Ctx& cx = *I.cx;
+  const int o = I.o, v = I.v, n = o + v;
+  const int64_t dim = I.dim, nn = (int64_t)n * n;
+  const int saved = cx.prec;
+  cx.prec = 0;
+  // normalised copy of the vectors
+  Tensor Yn = tnew(cx, {k, dim}, false);
+  {
+    const auto nr = row_norms2(cx, Y, k, dim);
+    for (int z = 0; z < k; ++z) {
+      const double s = nr[z] > 0.0 ? 1.0 / std::sqrt(nr[z]) : 0.0;
+      const int64_t od[1] = {dim}, st[1] = {1};
+      launch_permute(1, od, st, st, Y + (int64_t)z * dim, Yn.p + (int64_t)z * dim, CR(s), C0(), 0, cx.stream);
+    }
+  }
+  Tensor Ys = tensor_view(Yn.p, {k, o, v}, {dim, v, 1});
+  Tensor Ya = tnew(cx, {k, o, o, v, v}, false);
+  launch_unpack_doubles(0, Yn.p, dim, I.n1, k, o, v, Ya.p, nullptr, cx.stream);
+  auto blk = [&](double2* base, int r0, int nr, int c0, int nc) {
+    return tensor_view(base + (int64_t)r0 * n + c0, {k, nr, nc}, {nn, n, 1});
+  };
+  Tensor tdm_t, rho_t;
+  if (tdm || tk) {
+    tdm_t = tnew(cx, {k, n, n}, true);
+    Tensor vo = blk(tdm_t.p, o, v, 0, o), ov = blk(tdm_t.p, 0, o, o, v), vv = blk(tdm_t.p, o, v, o, v),
+           oo = blk(tdm_t.p, 0, o, 0, o);
+    perm(cx, C1(), Ys, "zia", true, C0(), vo, "zai");
+    ctr(cx, C1(), Ys, "zia", true, I.t1, "ijab", false, C0(), ov, "zjb");
+    ctr(cx, CR(0.5), Ya, "zijcb", true, I.t1, "ijdb", false, C0(), vv, "zcd");
+    ctr(cx, CR(-0.5), Ya, "zljab", true, I.t1, "kjab", false, C0(), oo, "zkl");
+  }
+  if (rho || dk) {
+    rho_t = tnew(cx, {k, n, n}, true);
+    Tensor vo = blk(rho_t.p, o, v, 0, o), ov = blk(rho_t.p, 0, o, o, v), vv = blk(rho_t.p, o, v, o, v),
+           oo = blk(rho_t.p, 0, o, 0, o);
+    ctr(cx, C1(), Ys, "zic", true, Ys, "zid", false, C0(), vv, "zcd");
+    ctr(cx, CR(0.5), Ya, "zijce", true, Ya, "zijde", false, C1(), vv, "zcd");
+    ctr(cx, CR(-1.0), Ys, "zla", true, Ys, "zka", false, C0(), oo, "zkl");
+    ctr(cx, CR(-0.5), Ya, "zljab", true, Ya, "zkjab", false, C1(), oo, "zkl");
+    ctr(cx, C1(), Ys, "zia", true, Ya, "zikad", false, C0(), ov, "zkd");
+    perm(cx, C1(), ov, "zkd", true, C0(), vo, "zdk");
+    // the ground-state correlation density rho_GS(2), added to every state
+    // together with the occupied identity (unit-norm vectors)
+    Tensor G = tnew(cx, {n, n}, true);
+    Tensor gvv = tensor_view(G.p + (int64_t)o * n + o, {v, v}, {n, 1});
+    Tensor goo = tensor_view(G.p, {o, o}, {n, 1});
+    Tensor gov = tensor_view(G.p + o, {o, v}, {n, 1});
+    Tensor gvo = tensor_view(G.p + (int64_t)o * n, {v, o}, {n, 1});
+    ctr(cx, CR(0.5), I.t1, "ijcb", true, I.t1, "ijdb", false, C0(), gvv, "cd");
+    ctr(cx, CR(-0.5), I.t1, "ljab", true, I.t1, "kjab", false, C0(), goo, "kl");
+    perm(cx, C1(), I.ts, "kd", false, C0(), gov, "kd");
+    perm(cx, C1(), I.ts, "kd", true, C0(), gvo, "dk");
+    std::vector<double> one(n, 0.0);
+    for (int i = 0; i < o; ++i) one[i] = 1.0;
+    double* dd = (double*)cx.pool.get((n + 1) / 2);
+    hipcheck(hipMemcpyAsync(dd, one.data(), sizeof(double) * n, hipMemcpyHostToDevice, cx.stream), "props diag");
+    launch_add_diag(G.p, dd, n, cx.stream);
+    for (int z = 0; z < k; ++z) {
+      Tensor Rz = tensor_view(rho_t.p + (int64_t)z * nn, {n, n}, {});
+      perm(cx, C1(), G, "pq", false, C1(), Rz, "pq");
+    }
+    hipcheck(hipStreamSynchronize(cx.stream), "props diag sync");
+    cx.pool.put((double2*)dd);
+    tfree(cx, G);
+  }
+  auto contract_d = [&](const Tensor& R, double* out) {
+    Tensor dv = tensor_view(const_cast<double2*>(d), {1, n, n}, {});
+    Tensor r = tnew(cx, {1, k}, false);
+    ctr(cx, C1(), dv, "ypq", false, R, "zpq", false, C0(), r, "yz");
+    std::vector<double2> hv(k);
+    hipcheck(hipMemcpyAsync(hv.data(), r.p, sizeof(double2) * k, hipMemcpyDeviceToHost, cx.stream), "props d");
+    hipcheck(hipStreamSynchronize(cx.stream), "props d sync");
+    for (int z = 0; z < k; ++z) {
+      out[2 * z] = hv[z].x;
+      out[2 * z + 1] = hv[z].y;
+    }
+    tfree(cx, r);
+  };
+  if (d && dk) contract_d(rho_t, dk);
+  if (d && tk) contract_d(tdm_t, tk);
+  if (rho) hipcheck(hipMemcpyAsync(rho, rho_t.p, sizeof(double2) * k * nn, hipMemcpyDeviceToDevice, cx.stream), "rho");
+  if (tdm) hipcheck(hipMemcpyAsync(tdm, tdm_t.p, sizeof(double2) * k * nn, hipMemcpyDeviceToDevice, cx.stream), "tdm");
+  hipcheck(hipStreamSynchronize(cx.stream), "props end");
+  for (Tensor* t : {&Yn, &Ya, &tdm_t, &rho_t})
+    if (t->p) tfree(cx, *t);
+  cx.prec = saved;
+}
+
 // Bytes that an allocation-free sigma build of k vectors certainly takes from
 // its scratch (a lower bound): the doubles accumulators of one vector and,
 // when the particle-particle ladder runs, one (ac|bd) block of one a.
@@ -2549,6 +2650,21 @@ int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, in
     }
     lane_wait(h, cx, false);
     hipcheck(hipGetLastError(), "sigma launch");
+    return (int)ADC_OK;
+  });
+}
+
+int adc_properties(adc_handle* h, int inst, const void* Y, int k, void* rho, void* tdm, const void* d, double* dk,
+                   double* tk) {
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || k < 1) return ADC_ERR_INVALID_ARG;
+  if ((dk || tk) && !d) return ADC_ERR_INVALID_ARG;
+  Inst& I = h->inst[inst];
+  if (I.kind != ADC_EE) return ADC_ERR_UNSUPPORTED;
+  return guarded([&]() {
+    lane_wait(h, *I.cx, true);
+    props_build(h, I, (const double2*)Y, k, (double2*)rho, (double2*)tdm, (const double2*)d, dk, tk);
+    lane_wait(h, *I.cx, false);
+    hipcheck(hipGetLastError(), "properties launch");
     return (int)ADC_OK;
   });
 }
