@@ -86,7 +86,8 @@ typedef struct adc_problem {
  *   precision     default arithmetic of adc_sigma / adc_davidson [ADC_FP64]
  *   conv_tol      residual norm threshold of the Davidson solver [1e-7]
  *   max_iter      Davidson iterations [200]
- *   max_subspace  subspace size before collapse to 2k [6k]
+ *   max_subspace  subspace size before collapse to 2k [6k; at least 3k,
+ *                 at most dim]
  *   refine_fp64   mixed precision only: 0 or 1 = iterate in the reduced
  *                 precision to a residual of 1e-4 (or conv_tol if larger),
  *                 then restart from the Ritz vectors in FP64 until the FP64
@@ -106,8 +107,17 @@ typedef struct adc_problem {
  *                 most expensive first [min(n_problems, 4)]; lane 0 is
  *                 `stream`, the others are library-owned non-blocking streams
  *                 of default priority
- *   graphs        1 = replay each small instance's sigma build from a
- *                 captured hipGraph inside adc_davidson [0]
+ *   graphs        inside adc_davidson: 1 = replay each small instance's
+ *                 sigma build from a captured hipGraph, and run the rest of
+ *                 each iteration on the device (Gram matrix, the subspace
+ *                 eigenproblem in one workgroup, Ritz vectors, residuals,
+ *                 convergence test, preconditioner with Olsen's correction,
+ *                 collapse, orthonormalisation of the new directions), from
+ *                 one captured hipGraph per subspace size, with one small
+ *                 device-to-host report per iteration; 2 = the same device
+ *                 iteration launched kernel by kernel, sigma builds eager;
+ *                 0 = host-driven iteration (subspace eigenproblem on the
+ *                 host) [0].  Root following always runs host-driven.
  *   autotune      1 = time the tile and split-K candidates of every GEMM
  *                 shape class once and keep the fastest [0]
  *   tune_cache    path of a text file of tuned GEMM choices (one shape class

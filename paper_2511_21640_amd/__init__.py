@@ -45,10 +45,16 @@ class AdcOptions(ctypes.Structure):
                 ("deterministic", ctypes.c_int), ("root_follow", ctypes.c_int)]
 
 
+GRAPHS = {False: 0, True: 1, "uncaptured": 2}
+
+
 def _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose, n_streams,
              graphs, autotune, tune_cache, deterministic, root_follow=False):
+    """graphs: False (host-driven iteration), True (captured sigma of small
+    instances and the device iteration from captured graphs) or 'uncaptured'
+    (the device iteration launched kernel by kernel)."""
     return AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1 if refine_fp64 else -1,
-                      ctypes.c_void_p(stream), mem_budget, int(verbose), int(n_streams), 1 if graphs else 0,
+                      ctypes.c_void_p(stream), mem_budget, int(verbose), int(n_streams), GRAPHS[graphs],
                       1 if autotune else 0, tune_cache.encode() if tune_cache else None, 1 if deterministic else 0,
                       1 if root_follow else 0)
 

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadc.so")
-SOURCES = ["kernels.hip", "engine.cpp", "adjoint.cpp", "adc.cpp", "cholesky.hip"]
+SOURCES = ["kernels.hip", "engine.cpp", "adjoint.cpp", "adc.cpp", "cholesky.hip", "davidson.hip"]
 # -amdgpu-mfma-vgpr-form: keep MFMA accumulators in ordinary VGPRs instead of
 # AGPRs; without it the GEMM main loops copy every accumulator between the two
 # register files on each K step and run at one wave per SIMD.

@@ -1510,7 +1510,7 @@ double inst_cost(const Inst& I) {
 void sigma_call(adc_handle* h, Inst& I, const double2* Y, double2* S, int rows, int prec) {
   Ctx& cx = *I.cx;
   if (rows <= 0) return;
-  if (!h->opt.graphs || inst_cost(I) > kGraphMaxCost) {
+  if (h->opt.graphs != 1 || inst_cost(I) > kGraphMaxCost) {
     sigma_dispatch(h, I, Y, S, rows, prec);
     return;
   }
@@ -1685,6 +1685,239 @@ std::vector<double> row_norms2(Ctx& cx, const double2* X, int rows, int64_t dim)
   return out;
 }
 
+// ---------------------------------------------------------------------------
+// device-side iteration (options.graphs): everything from the Gram matrix of
+// the subspace to the orthonormalised new directions runs on the device, in
+// FP64, and is captured once per subspace size as a hipGraph; the host reads
+// one small report per iteration and then enqueues the sigma build of the
+// directions it keeps.
+// ---------------------------------------------------------------------------
+// G[a][b] = sum_i conj(X[a][i]) Y[b][i] (ra x rb, row stride rb) on the device
+void gram_dev(Ctx& cx, const double2* X, int ra, const double2* Y, int rb, int64_t dim, double2* part,
+              double2* out) {
+  const int64_t chunk = 1 << 16;
+  const int64_t nsplit = dim / chunk;
+  const int64_t rem = dim - nsplit * chunk;
+  const int64_t nparts = nsplit + (rem ? 1 : 0);
+  const int sp = cx.prec;
+  cx.prec = 0;
+  if (nsplit) {
+    GemmDesc g{};
+    g.M = ra; g.N = rb; g.K = chunk; g.batch = nsplit;
+    g.A = X; g.sam = dim; g.sak = 1; g.sab = chunk; g.conjA = 1;
+    g.B = Y; g.sbk = 1; g.sbn = dim; g.sbb = chunk;
+    g.C = part; g.scm = rb; g.scn = 1; g.scb = (int64_t)ra * rb;
+    g.alpha = C1(); g.beta = C0();
+    gemm(cx, g);
+  }
+  if (rem) {
+    GemmDesc g{};
+    g.M = ra; g.N = rb; g.K = rem; g.batch = 1;
+    g.A = X + nsplit * chunk; g.sam = dim; g.sak = 1; g.sab = 0; g.conjA = 1;
+    g.B = Y + nsplit * chunk; g.sbk = 1; g.sbn = dim; g.sbb = 0;
+    g.C = part + nsplit * ra * rb; g.scm = rb; g.scn = 1; g.scb = 0;
+    g.alpha = C1(); g.beta = C0();
+    gemm(cx, g);
+  }
+  cx.prec = sp;
+  launch_sum_parts(part, (int)nparts, (int64_t)ra * rb, out, cx.stream);
+}
+
+// Out[r][i] = alpha sum_a C[a][r] In[a][i] + beta Out[r][i], C a device matrix
+// with row stride ldc (a < m, r < nr)
+void combine_dev(Ctx& cx, const double2* C, int ldc, int m, int nr, const double2* In, double2* Out, int64_t dim,
+                 cplx alpha, cplx beta) {
+  if (m == 0 || nr == 0) return;
+  GemmDesc g{};
+  g.M = nr; g.N = dim; g.K = m; g.batch = 1;
+  g.A = C; g.sam = 1; g.sak = ldc; g.sab = 0;
+  g.B = In; g.sbk = dim; g.sbn = 1; g.sbb = 0;
+  g.C = Out; g.scm = dim; g.scn = 1; g.scb = 0;
+  g.alpha = alpha; g.beta = beta;
+  const int sp = cx.prec;
+  cx.prec = 0;
+  gemm(cx, g);
+  cx.prec = sp;
+}
+
+struct DevDav {
+  int k = 0, mmax = 0, nb = 1;
+  int64_t dim = 0;
+  double2 *N = nullptr, *T = nullptr;                  // new directions [k][dim], temporary [2k][dim]
+  double2 *G = nullptr, *U = nullptr, *Aw = nullptr, *Vw = nullptr;  // [mmax][mmax]
+  double2 *gpart = nullptr, *rpart = nullptr;          // Gram and row-dot partial sums
+  double2 *rn2 = nullptr, *ra = nullptr, *rb = nullptr;  // row sums [k]
+  double2 *Cc = nullptr, *Gn = nullptr, *Un = nullptr;   // [mmax][k], [k][k], [k][k]
+  double *w = nullptr, *wn = nullptr, *wold = nullptr, *par = nullptr, *rep = nullptr;
+  double* rep_host = nullptr;  // the lane's page-locked buffer
+  int lds_max = 0;             // dynamic LDS bytes the eigensolver may take
+  struct Graph {
+    int m = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    std::vector<double2*> held;
+  };
+  std::vector<Graph> graphs;
+  std::vector<double2*> blocks;
+  int rep_len() const { return 4 + 3 * k; }
+  int mode(int n) const {
+    if (heev_lds_bytes(n, 2) <= (size_t)lds_max) return 2;
+    if (heev_lds_bytes(n, 1) <= (size_t)lds_max) return 1;
+    return 0;
+  }
+};
+
+void devdav_setup(Ctx& cx, DevDav& D, int k, int mmax, int64_t dim) {
+  D.k = k;
+  D.mmax = mmax;
+  D.dim = dim;
+  D.nb = row_dot_blocks(dim);
+  auto take = [&](int64_t n) {
+    double2* p = cx.pool.get(std::max<int64_t>(n, 1));
+    D.blocks.push_back(p);
+    return p;
+  };
+  const int64_t nparts = (dim + (1 << 16) - 1) >> 16;
+  const int64_t mm = (int64_t)mmax * mmax;
+  D.N = take((int64_t)k * dim);
+  D.T = take((int64_t)2 * k * dim);
+  D.G = take(mm);
+  D.U = take(mm);
+  D.Aw = take(mm);
+  D.Vw = take(mm);
+  D.gpart = take(nparts * mm);
+  D.rpart = take((int64_t)3 * k * D.nb);
+  D.rn2 = take(k);
+  D.ra = take(k);
+  D.rb = take(k);
+  D.Cc = take((int64_t)mmax * k);
+  D.Gn = take((int64_t)k * k);
+  D.Un = take((int64_t)k * k);
+  D.w = (double*)take(mmax);
+  D.wn = (double*)take(k);
+  D.wold = (double*)take(k);
+  D.par = (double*)take(2);
+  D.rep = (double*)take(D.rep_len());
+  // the report, then the two convergence thresholds sent with each step
+  D.rep_host = cx.pinned((size_t)D.rep_len() + 2);
+  int dev = 0, lds = 0;
+  hipcheck(hipGetDevice(&dev), "device");
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    lds = 0;
+  }
+  const int64_t avail = (int64_t)lds - (int64_t)heev_static_lds() - 1024;
+  D.lds_max = (int)std::max<int64_t>(0, avail);
+  if (D.lds_max > 0) heev_allow_lds((size_t)D.lds_max);
+}
+
+void devdav_release(Ctx& cx, DevDav& D) {
+  if (!D.graphs.empty() || !D.blocks.empty()) {
+    (void)hipStreamSynchronize(cx.stream);
+    (void)hipGetLastError();
+  }
+  for (auto& g : D.graphs) {
+    if (g.ex) (void)hipGraphExecDestroy(g.ex);
+    if (g.g) (void)hipGraphDestroy(g.g);
+    for (double2* p : g.held) cx.pool.put(p);
+  }
+  D.graphs.clear();
+  for (double2* p : D.blocks) cx.pool.put(p);
+  D.blocks.clear();
+  D.rep_host = nullptr;
+}
+
+// One iteration from the subspace V, S (m rows) to the new directions in N:
+//  G = V^H S and its eigenpairs; Ritz vectors X = U_k^T V, AX = U_k^T S;
+//  residuals R = AX - w X, their norms and the convergence test (report);
+//  N = Olsen-corrected preconditioned residuals, zero for converged roots;
+//  collapse of V, S onto the 2k lowest Ritz vectors when the subspace cannot
+//  take one direction per unconverged root (the host-driven rule);
+//  N orthonormalised against V and among themselves (two passes of
+//  projection and canonical orthonormalisation; kept directions first, their
+//  count in the report).
+void devdav_body(Ctx& cx, const Inst& I, DevDav& D, double2* V, double2* S, double2* X, double2* AX, double2* R,
+                 int m) {
+  const int k = D.k;
+  const int64_t dim = D.dim;
+  hipStream_t s = cx.stream;
+  gram_dev(cx, V, m, S, m, dim, D.gpart, D.G);
+  launch_heev_jacobi(D.G, m, m, D.Aw, D.Vw, D.mode(m), D.U, m, D.w, s);
+  combine_dev(cx, D.U, m, m, k, V, X, dim, C1(), C0());
+  combine_dev(cx, D.U, m, m, k, S, AX, dim, C1(), C0());
+  launch_resid(AX, X, D.w, R, k, dim, s);
+  launch_row_dots(R, dim, R, dim, k, dim, D.rpart, D.nb, s);
+  launch_row_sums(D.rpart, D.nb, k, D.rn2, s);
+  launch_dav_converge(D.w, D.rn2, D.wold, k, m, D.mmax, D.par, D.rep, s);
+  // Olsen's correction t = P (r - e x), e = <x|P r> / <x|P x>, P = (w - D)^-1
+  launch_precondition(R, D.N, I.diag, D.w, k, dim, s);
+  launch_precondition(X, D.T, I.diag, D.w, k, dim, s);
+  launch_row_dots(X, dim, D.N, dim, k, dim, D.rpart, D.nb, s);
+  launch_row_sums(D.rpart, D.nb, k, D.ra, s);
+  launch_row_dots(X, dim, D.T, dim, k, dim, D.rpart, D.nb, s);
+  launch_row_sums(D.rpart, D.nb, k, D.rb, s);
+  launch_olsen(D.N, D.T, D.ra, D.rb, D.rep + 1 + 2 * k, k, dim, s);
+  // collapse (decided on the device): rows past the kept 2k become zero, so
+  // the projection below may run over all m rows either way
+  const double* collapse = D.rep + 3 + 3 * k;
+  const int mc = std::min(2 * k, m);
+  launch_collapse(collapse, D.U, m, m, mc, V, D.T, V, dim, s);
+  launch_collapse(collapse, D.U, m, m, mc, S, D.T, S, dim, s);
+  for (int pass = 0; pass < 2; ++pass) {
+    gram_dev(cx, V, m, D.N, k, dim, D.gpart, D.Cc);  // Cc[a][b] = <V_a|N_b>
+    combine_dev(cx, D.Cc, k, m, k, V, D.N, dim, CR(-1), C1());
+    gram_dev(cx, D.N, k, D.N, k, dim, D.gpart, D.Gn);
+    launch_heev_jacobi(D.Gn, k, k, D.Aw, D.Vw, D.mode(k), D.Un, k, D.wn, s);
+    launch_canon(D.wn, D.Un, k, k, D.Cc, D.rep + 1 + 3 * k + pass, s);
+    combine_dev(cx, D.Cc, k, k, k, D.N, D.T, dim, C1(), C0());
+    hipcheck(hipMemcpyAsync(D.N, D.T, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, s), "orth");
+  }
+}
+
+// Runs the iteration for subspace size m (from its captured graph when
+// capture is on, capturing it on first use) and reads the report.
+void devdav_step(Ctx& cx, const Inst& I, DevDav& D, bool capture, double2* V, double2* S, double2* X, double2* AX,
+                 double2* R, int m) {
+  if (!capture) {
+    devdav_body(cx, I, D, V, S, X, AX, R, m);
+  } else {
+    DevDav::Graph* G = nullptr;
+    for (auto& g : D.graphs)
+      if (g.m == m) G = &g;
+    if (!G) {
+      DevDav::Graph ng;
+      ng.m = m;
+      cx.pool.begin_hold();
+      hipError_t e = hipStreamBeginCapture(cx.stream, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) {
+        try {
+          devdav_body(cx, I, D, V, S, X, AX, R, m);
+        } catch (...) {
+          hipGraph_t dead = nullptr;
+          (void)hipStreamEndCapture(cx.stream, &dead);
+          if (dead) (void)hipGraphDestroy(dead);
+          for (double2* p : cx.pool.end_hold()) cx.pool.put(p);
+          throw;
+        }
+        e = hipStreamEndCapture(cx.stream, &ng.g);
+      }
+      ng.held = cx.pool.end_hold();
+      if (e == hipSuccess) e = hipGraphInstantiate(&ng.ex, ng.g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (ng.g) (void)hipGraphDestroy(ng.g);
+        for (double2* p : ng.held) cx.pool.put(p);
+        hipcheck(e, "iteration capture");
+      }
+      D.graphs.push_back(std::move(ng));
+      G = &D.graphs.back();
+    }
+    hipcheck(hipGraphLaunch(G->ex, cx.stream), "iteration graph");
+  }
+  hipcheck(hipMemcpyAsync(D.rep_host, D.rep, sizeof(double) * D.rep_len(), hipMemcpyDeviceToHost, cx.stream),
+           "report");
+  hipcheck(hipStreamSynchronize(cx.stream), "report sync");
+}
+
 int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, double2* vecs, double* resnorm,
                  int* iters, int* conv_out) {
   Ctx& cx = *I.cx;
@@ -1693,7 +1926,8 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   const double tol = h->opt.conv_tol > 0 ? h->opt.conv_tol : 1e-7;
   const int max_iter = h->opt.max_iter > 0 ? h->opt.max_iter : 200;
   int mmax = h->opt.max_subspace > 0 ? h->opt.max_subspace : 6 * k;
-  mmax = std::max(mmax, 2 * k + 1);
+  // a collapse keeps 2k vectors and the next iteration adds up to k
+  mmax = std::max(mmax, 3 * k);
   if ((int64_t)mmax > dim) mmax = (int)dim;
   if (k > dim) throw Status{ADC_ERR_INVALID_ARG, "n_roots > dim"};
   const int prec_mixed = h->opt.precision;
@@ -1782,7 +2016,71 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   // precision and reports its own residuals (no FP64 restart)
   const bool refine = h->opt.refine_fp64 >= 0;
   bool refined_phase = (prec == 0) || !refine;
-  for (it = 1; it <= max_iter; ++it) {
+  // device-side iteration (graphs on, no root following); graphs = 2 runs
+  // it launch by launch instead of from captured graphs
+  const bool dev_iter = h->opt.graphs && !Gref && mmax <= heev_device_max();
+  DevDav D;
+  struct DevGuard {
+    Ctx& cx;
+    DevDav& D;
+    ~DevGuard() { devdav_release(cx, D); }
+  } dev_guard{cx, D};
+  auto reset_wold = [&]() { launch_fill((double2*)D.wold, k, {1e300, 1e300}, cx.stream); };
+  if (dev_iter) {
+    devdav_setup(cx, D, k, mmax, dim);
+    reset_wold();
+  }
+  for (it = 1; it <= max_iter && dev_iter; ++it) {
+    auto t_it = now();
+    const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
+    const double dw_tol = refined_phase ? std::max(1e-10, tol * tol) : 1e-7;
+    double* par_host = D.rep_host + D.rep_len();
+    par_host[0] = tol_now;
+    par_host[1] = dw_tol;
+    hipcheck(hipMemcpyAsync(D.par, par_host, sizeof(double) * 2, hipMemcpyHostToDevice, cx.stream), "par");
+    devdav_step(cx, I, D, h->opt.graphs == 1, V, S, X, AX, R, m);
+    const double* rp = D.rep_host;
+    if (rp[0] < 0 || rp[1 + 3 * k] < 0 || rp[2 + 3 * k] < 0)
+      throw Status{ADC_ERR_NONFINITE_INPUT, "non-finite subspace matrix"};
+    const bool all = rp[0] == 1.0;
+    for (int r = 0; r < k; ++r) {
+      w[r] = rp[1 + r];
+      rn[r] = rp[1 + k + r];
+      conv[r] = rp[1 + 2 * k + r] != 0.0 ? 1 : 0;
+    }
+    const int nk = (int)rp[2 + 3 * k];
+    if (rp[3 + 3 * k] != 0.0) m = std::min(2 * k, m);  // the step collapsed the subspace
+    t_sub += ms_since(t_it);
+    if (h->opt.verbose) {
+      std::fprintf(stderr, "[adc] it %3d m %3d prec %d dev (sigma %.0f sub %.0f ms)", it, m, prec, t_sigma, t_sub);
+      for (int r = 0; r < k; ++r) std::fprintf(stderr, "  %.10f (%.1e)", w[r], rn[r]);
+      std::fprintf(stderr, "\n");
+    }
+    if (all || nk == 0) {
+      if (!refined_phase) {
+        // mixed precision converged (or out of directions): restart from the
+        // Ritz vectors in FP64
+        refined_phase = true;
+        prec = 0;
+        hipcheck(hipMemcpyAsync(V, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "restart");
+        m = orthonormalize(cx, V, 0, V, k, dim);
+        sigma_call(h, I, V, S, m, prec);
+        reset_wold();
+        continue;
+      }
+      if (!all)
+        for (int r = 0; r < k; ++r) conv[r] = rn[r] <= tol_now ? 1 : 0;
+      break;
+    }
+    hipcheck(hipMemcpyAsync(V + (int64_t)m * dim, D.N, sizeof(double2) * nk * dim, hipMemcpyDeviceToDevice,
+                            cx.stream), "append");
+    auto t_s = now();
+    sigma_call(h, I, V + (int64_t)m * dim, S + (int64_t)m * dim, nk, prec);
+    if (h->opt.verbose) hipcheck(hipStreamSynchronize(cx.stream), "sigma sync");
+    t_sigma += ms_since(t_s);
+    m += nk;
+  }
+  for (it = dev_iter ? it : 1; it <= max_iter && !dev_iter; ++it) {
     auto t_it = now();
     auto G = gram(cx, V, m, S, m, dim);
     for (int a = 0; a < m; ++a)
@@ -2484,6 +2782,7 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
   if (opts && (opts->precision < 0 || opts->precision > 2)) return ADC_ERR_INVALID_ARG;
   if (opts && opts->precision == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
   if (opts && opts->n_streams < 0) return ADC_ERR_INVALID_ARG;
+  if (opts && (opts->graphs < 0 || opts->graphs > 2)) return ADC_ERR_INVALID_ARG;
   for (int i = 0; i < n_problems; ++i) {
     int rc = validate(&problems[i]);
     if (rc) return rc;

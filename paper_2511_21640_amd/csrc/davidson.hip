@@ -1,0 +1,399 @@
+// Device side of the Davidson iteration (Section 2.1, eq. 10): the small
+// Hermitian eigenproblems of the subspace and of the new directions, and the
+// per-root bookkeeping (convergence test, Olsen's correction, the choice of
+// the new directions), so that an iteration runs without the host and can be
+// captured as one hipGraph.
+//
+// Eigensolver: cyclic complex Jacobi in the round-robin ordering, one
+// workgroup.  Each round's n/2 index pairs are disjoint, so their rotations
+// are computed together and applied as A <- J^H A J (all row rotations, then
+// all column rotations) and U <- U J.  For a pair (p, q) with
+// a_pq = |a_pq| e^{i phi}, theta = atan2(2 |a_pq|, a_qq - a_pp) / 2,
+// c = cos theta and s = sin theta:
+//   rows     p' = c p - s e^{i phi} q,      q' = s e^{-i phi} p + c q
+//   columns  p' = c p - s e^{-i phi} q,     q' = s e^{i phi} p + c q
+// which zeroes a_pq.  Sweeps run until the off-diagonal weight is at most
+// 1e-30 of the total (at most 60 sweeps); the eigenvalues are then put in
+// ascending order (equal values keep their index order) with their columns.
+// A and the rotation accumulator live in LDS when both fit (mode 2), else A
+// alone (mode 1), else both in the global workspace the caller passes
+// (mode 0).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace adc {
+
+namespace {
+
+constexpr int kJacobiThreads = 1024;
+constexpr int kJacobiMaxN = 256;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// player in slot j of round r of the round-robin over m (even) players:
+// slot 0 keeps player 0, the others rotate
+__device__ __forceinline__ int rr_player(int slot, int r, int m) {
+  if (slot == 0) return 0;
+  return 1 + (slot - 1 + r) % (m - 1);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(kJacobiThreads) void heev_jacobi_kernel(const double2* G, int ldg, int n,
+                                                                      double2* Ag, double2* Vg, int mode,
+                                                                      double2* U, int ldu, double* w) {
+  extern __shared__ double2 dyn[];
+  __shared__ double cs[kJacobiMaxN / 2], ss[kJacobiMaxN / 2];
+  __shared__ double2 ph[kJacobiMaxN / 2];
+  __shared__ int pp[kJacobiMaxN / 2], qq[kJacobiMaxN / 2];
+  __shared__ double red[2][kJacobiThreads / 64];
+  __shared__ double dg[kJacobiMaxN];
+  __shared__ int order[kJacobiMaxN];
+  __shared__ int stop, bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nn = n * n;
+  double2* A = mode >= 1 ? dyn : Ag;
+  double2* V = mode == 2 ? dyn + nn : Vg;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  // A = (G + G^H) / 2, V = I
+  for (int e = tid; e < nn; e += nt) {
+    const int r = e / n, c = e - r * n;
+    const double2 a = G[(int64_t)r * ldg + c], b = G[(int64_t)c * ldg + r];
+    if (!isfinite(a.x) || !isfinite(a.y)) bad = 1;
+    A[e] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    V[e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+  }
+  __syncthreads();
+  if (bad) {
+    // a non-finite subspace matrix: NaN eigenvalues tell the caller
+    for (int c = tid; c < n; c += nt) w[c] = __builtin_nan("");
+    for (int e = tid; e < nn; e += nt) U[(int64_t)(e / n) * ldu + e % n] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int m = (n + 1) / 2 * 2;  // players; player n (n odd) sits out
+  const int half = m / 2;
+  for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < nn; e += nt) {
+      const int r = e / n, c = e - r * n;
+      const double x = A[e].x * A[e].x + A[e].y * A[e].y;
+      tot += x;
+      if (r != c) off += x;
+    }
+    off = wave_sum(off);
+    tot = wave_sum(tot);
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = off;
+      red[1][tid >> 6] = tot;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double so = 0.0, st = 0.0;
+      for (int i = 0; i < nt / 64; ++i) {
+        so += red[0][i];
+        st += red[1][i];
+      }
+      stop = !(so > 1e-30 * fmax(st, 1e-300));
+    }
+    __syncthreads();
+    if (stop) break;
+    for (int r = 0; r < m - 1; ++r) {
+      for (int j = tid; j < half; j += nt) {
+        int p = rr_player(j, r, m), q = rr_player(m - 1 - j, r, m);
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        pp[j] = p;
+        qq[j] = q;
+        double c = 1.0, s = 0.0;
+        double2 e = make_double2(1.0, 0.0);
+        if (q < n) {
+          const double2 apq = A[p * n + q];
+          const double mag = sqrt(apq.x * apq.x + apq.y * apq.y);
+          if (mag > 1e-300) {
+            e = make_double2(apq.x / mag, apq.y / mag);
+            const double th = 0.5 * atan2(2.0 * mag, A[q * n + q].x - A[p * n + p].x);
+            c = cos(th);
+            s = sin(th);
+          }
+        }
+        cs[j] = c;
+        ss[j] = s;
+        ph[j] = e;
+      }
+      __syncthreads();
+      // rows p and q of A
+      for (int t = tid; t < half * n; t += nt) {
+        const int j = t / n, x = t - j * n;
+        const int p = pp[j], q = qq[j];
+        if (q >= n || ss[j] == 0.0) continue;
+        const double c = cs[j], s = ss[j];
+        const double2 e = ph[j], ec = make_double2(e.x, -e.y);
+        const double2 ap = A[p * n + x], aq = A[q * n + x];
+        const double2 t1 = cmul(e, aq), t2 = cmul(ec, ap);
+        A[p * n + x] = make_double2(c * ap.x - s * t1.x, c * ap.y - s * t1.y);
+        A[q * n + x] = make_double2(s * t2.x + c * aq.x, s * t2.y + c * aq.y);
+      }
+      __syncthreads();
+      // columns p and q of A and of V
+      for (int t = tid; t < half * n; t += nt) {
+        const int j = t / n, x = t - j * n;
+        const int p = pp[j], q = qq[j];
+        if (q >= n || ss[j] == 0.0) continue;
+        const double c = cs[j], s = ss[j];
+        const double2 e = ph[j], ec = make_double2(e.x, -e.y);
+        const double2 ap = A[x * n + p], aq = A[x * n + q];
+        const double2 t1 = cmul(ec, aq), t2 = cmul(e, ap);
+        A[x * n + p] = make_double2(c * ap.x - s * t1.x, c * ap.y - s * t1.y);
+        A[x * n + q] = make_double2(s * t2.x + c * aq.x, s * t2.y + c * aq.y);
+        const double2 vp = V[x * n + p], vq = V[x * n + q];
+        const double2 u1 = cmul(ec, vq), u2 = cmul(e, vp);
+        V[x * n + p] = make_double2(c * vp.x - s * u1.x, c * vp.y - s * u1.y);
+        V[x * n + q] = make_double2(s * u2.x + c * vq.x, s * u2.y + c * vq.y);
+      }
+      __syncthreads();
+      for (int j = tid; j < half; j += nt) {
+        const int p = pp[j], q = qq[j];
+        if (q < n && ss[j] != 0.0) {
+          A[p * n + q] = make_double2(0.0, 0.0);
+          A[q * n + p] = make_double2(0.0, 0.0);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ascending order by rank (ties by index)
+  for (int c = tid; c < n; c += nt) dg[c] = A[c * n + c].x;
+  __syncthreads();
+  for (int c = tid; c < n; c += nt) {
+    const double x = dg[c];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += (dg[j] < x || (dg[j] == x && j < c)) ? 1 : 0;
+    order[rank] = c;
+  }
+  __syncthreads();
+  for (int c = tid; c < n; c += nt) w[c] = dg[order[c]];
+  for (int e = tid; e < nn; e += nt) {
+    const int r = e / n, c = e - r * n;
+    U[(int64_t)r * ldu + c] = V[r * n + order[c]];
+  }
+}
+
+// out[e] = sum_s part[s * n + e]
+__global__ void sum_parts_kernel(const double2* part, int nparts, int64_t n, double2* out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double sx = 0.0, sy = 0.0;
+  for (int s = 0; s < nparts; ++s) {
+    sx += part[(int64_t)s * n + e].x;
+    sy += part[(int64_t)s * n + e].y;
+  }
+  out[e] = make_double2(sx, sy);
+}
+
+// out[r] = sum_b partial[r * nb + b]
+__global__ void row_sums_kernel(const double2* partial, int nb, int rows, double2* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double sx = 0.0, sy = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    sx += partial[(int64_t)r * nb + b].x;
+    sy += partial[(int64_t)r * nb + b].y;
+  }
+  out[r] = make_double2(sx, sy);
+}
+
+// Convergence of the k roots: root r is converged when |r_r| <= par[0] and
+// |w_r - wold_r| <= par[1]; wold <- w.  rep = [status, w[k], |r|[k], conv[k],
+// (two counts written later), collapse] with status 1 (all converged), 0 (not
+// all) or -1 (a non-finite value), and collapse = 1 when the subspace of m
+// vectors cannot take one new direction per unconverged root (m + nn > mmax).
+__global__ void dav_converge_kernel(const double* w, const double2* rn2, double* wold, int k, int m, int mmax,
+                                    const double* par, double* rep) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double tol = par[0], dwtol = par[1];
+  int all = 1, finite = 1, nn = 0;
+  for (int r = 0; r < k; ++r) {
+    const double rn = sqrt(fmax(0.0, rn2[r].x));
+    if (!isfinite(w[r]) || !isfinite(rn)) finite = 0;
+    const int c = (rn <= tol && fabs(w[r] - wold[r]) <= dwtol) ? 1 : 0;
+    all = all && c;
+    nn += 1 - c;
+    rep[1 + r] = w[r];
+    rep[1 + k + r] = rn;
+    rep[1 + 2 * k + r] = c;
+    wold[r] = w[r];
+  }
+  rep[0] = finite ? all : -1;
+  rep[3 + 3 * k] = (finite && !all && m + nn > mmax) ? 1.0 : 0.0;
+}
+
+// Collapse onto the lowest mc Ritz vectors, when *flag is set:
+// T[r][i] = sum_a U[a][r] In[a][i] for r < mc, a < m.  One thread per
+// column i, outputs in groups of 16 (the U entries are uniform over the
+// block).
+__global__ __launch_bounds__(256) void collapse_kernel(const double* flag, const double2* U, int ldu, int m, int mc,
+                                                       const double2* In, double2* T, int64_t dim) {
+  if (*flag == 0.0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= dim) return;
+  for (int r0 = 0; r0 < mc; r0 += 16) {
+    const int nr = mc - r0 < 16 ? mc - r0 : 16;
+    double ax[16], ay[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) ax[j] = ay[j] = 0.0;
+    for (int a = 0; a < m; ++a) {
+      const double2 v = In[(int64_t)a * dim + i];
+      const double2* u = U + (int64_t)a * ldu + r0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (j < nr) {
+          const double2 c = u[j];
+          ax[j] += c.x * v.x - c.y * v.y;
+          ay[j] += c.x * v.y + c.y * v.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j < nr) T[(int64_t)(r0 + j) * dim + i] = make_double2(ax[j], ay[j]);
+  }
+}
+
+// when *flag is set: Out[r] = T[r] for r < mc, Out[r] = 0 for mc <= r < m
+__global__ void collapse_copy_kernel(const double* flag, const double2* T, double2* Out, int m, int mc, int64_t dim) {
+  if (*flag == 0.0) return;
+  const int64_t total = (int64_t)m * dim;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    Out[e] = e < (int64_t)mc * dim ? T[e] : make_double2(0.0, 0.0);
+}
+
+// Olsen's correction of the preconditioned residuals, N_r -= (a_r / b_r) P_r;
+// rows whose flag is set (converged roots) are zeroed instead
+__global__ void olsen_kernel(double2* N, const double2* P, const double2* a, const double2* b, const double* flags,
+                             int rows, int64_t dim) {
+  const int64_t total = (int64_t)rows * dim;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / dim);
+    if (flags[r] != 0.0) {
+      N[e] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double2 bb = b[r], aa = a[r];
+    const double den = bb.x * bb.x + bb.y * bb.y;
+    if (den < 1e-300) continue;
+    const double2 f = make_double2((aa.x * bb.x + aa.y * bb.y) / den, (aa.y * bb.x - aa.x * bb.y) / den);
+    const double2 p = P[e];
+    N[e].x -= f.x * p.x - f.y * p.y;
+    N[e].y -= f.x * p.y + f.y * p.x;
+  }
+}
+
+// Canonical orthonormalisation coefficients of k vectors from the
+// eigenpairs (lam ascending, columns of U) of their Gram matrix: the
+// eigenvalues above 1e-12 of the largest (and above 1e-20) are kept; kept
+// direction c (ascending) is sum_a U[a][j] / sqrt(lam_j) * vector a, so
+// C[a][c] = U[a][j] / sqrt(lam_j), and the columns past the kept count are
+// zero.  *count gets the kept count, or -1 for a non-finite eigenvalue.
+__global__ void canon_kernel(const double* lam, const double2* U, int ldu, int k, double2* C, double* count) {
+  __shared__ int nk, lo;
+  if (threadIdx.x == 0) {
+    double lmax = 0.0;
+    int finite = 1;
+    for (int j = 0; j < k; ++j) {
+      if (!isfinite(lam[j])) finite = 0;
+      lmax = fmax(lmax, lam[j]);
+    }
+    int c = 0;
+    for (int j = 0; j < k; ++j)
+      if (lam[j] > 1e-12 * fmax(lmax, 1e-300) && lam[j] > 1e-20) ++c;
+    nk = finite ? c : 0;
+    lo = k - nk;
+    *count = finite ? (double)c : -1.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int a = e / k, c = e - a * k;
+    double2 v = make_double2(0.0, 0.0);
+    if (c < nk) {
+      const int j = lo + c;
+      const double f = 1.0 / sqrt(lam[j]);
+      const double2 u = U[(int64_t)a * ldu + j];
+      v = make_double2(u.x * f, u.y * f);
+    }
+    C[e] = v;
+  }
+}
+
+}  // namespace
+
+int heev_device_max() { return kJacobiMaxN; }
+
+size_t heev_lds_bytes(int n, int mode) { return sizeof(double2) * (size_t)mode * n * n; }
+
+size_t heev_static_lds() {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, (const void*)heev_jacobi_kernel) != hipSuccess) {
+    (void)hipGetLastError();
+    return 16384;
+  }
+  return a.sharedSizeBytes;
+}
+
+void launch_heev_jacobi(const double2* G, int ldg, int n, double2* Aw, double2* Vw, int mode, double2* U, int ldu,
+                        double* w, hipStream_t s) {
+  hipLaunchKernelGGL(heev_jacobi_kernel, dim3(1), dim3(kJacobiThreads), heev_lds_bytes(n, mode), s, G, ldg, n, Aw,
+                     Vw, mode, U, ldu, w);
+}
+
+void heev_allow_lds(size_t bytes) {
+  (void)hipFuncSetAttribute((const void*)heev_jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  (void)hipGetLastError();
+}
+
+void launch_sum_parts(const double2* part, int nparts, int64_t n, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nparts, n, out);
+}
+
+void launch_row_sums(const double2* partial, int nb, int rows, double2* out, hipStream_t s) {
+  hipLaunchKernelGGL(row_sums_kernel, dim3((rows + 63) / 64), dim3(64), 0, s, partial, nb, rows, out);
+}
+
+void launch_dav_converge(const double* w, const double2* rn2, double* wold, int k, int m, int mmax,
+                         const double* par, double* rep, hipStream_t s) {
+  hipLaunchKernelGGL(dav_converge_kernel, dim3(1), dim3(64), 0, s, w, rn2, wold, k, m, mmax, par, rep);
+}
+
+void launch_collapse(const double* flag, const double2* U, int ldu, int m, int mc, const double2* In, double2* T,
+                     double2* Out, int64_t dim, hipStream_t s) {
+  hipLaunchKernelGGL(collapse_kernel, dim3((unsigned)((dim + 255) / 256)), dim3(256), 0, s, flag, U, ldu, m, mc, In,
+                     T, dim);
+  const int64_t total = (int64_t)m * dim;
+  int64_t g = (total + 255) / 256;
+  if (g > 65535LL * 16) g = 65535LL * 16;
+  hipLaunchKernelGGL(collapse_copy_kernel, dim3((unsigned)g), dim3(256), 0, s, flag, T, Out, m, mc, dim);
+}
+
+void launch_olsen(double2* N, const double2* P, const double2* a, const double2* b, const double* flags, int rows,
+                  int64_t dim, hipStream_t s) {
+  const int64_t total = (int64_t)rows * dim;
+  int64_t g = (total + 255) / 256;
+  if (g > 65535LL * 16) g = 65535LL * 16;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(olsen_kernel, dim3((unsigned)g), dim3(256), 0, s, N, P, a, b, flags, rows, dim);
+}
+
+void launch_canon(const double* lam, const double2* U, int ldu, int k, double2* C, double* count, hipStream_t s) {
+  hipLaunchKernelGGL(canon_kernel, dim3(1), dim3(256), 0, s, lam, U, ldu, k, C, count);
+}
+
+}  // namespace adc

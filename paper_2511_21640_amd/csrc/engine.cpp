@@ -365,6 +365,22 @@ int tune_cache_save(const char* path) {
   return std::fclose(f) == 0 ? n : -1;
 }
 
+double* Ctx::pinned(size_t n) {
+  if (n > pinned_n_) {
+    if (pinned_) (void)hipHostFree(pinned_);
+    pinned_ = nullptr;
+    pinned_n_ = 0;
+    const size_t want = std::max<size_t>(n, 256);
+    hipcheck(hipHostMalloc((void**)&pinned_, sizeof(double) * want), "pinned report buffer");
+    pinned_n_ = want;
+  }
+  return pinned_;
+}
+
+Ctx::~Ctx() {
+  if (pinned_) (void)hipHostFree(pinned_);
+}
+
 void gemm(Ctx& cx, GemmDesc g) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0 || g.K <= 0) return;
   const int64_t heur = heuristic_nsplit(g.M, g.N, g.K, g.batch, 128);

@@ -207,6 +207,39 @@ int row_dot_blocks(int64_t n);
 // non-finite components (one block per Q)
 void launch_check_L(const double2* L, int64_t nq, int64_t n, double* out, hipStream_t s);
 
+// device Davidson iteration (davidson.hip)
+// eigenpairs of the Hermitian part of G (n x n, row stride ldg, n at most
+// heev_device_max()) in one workgroup: w ascending, U [n][ldu] columns.
+// Aw, Vw are n*n workspaces for the matrix and the rotations; mode 2 keeps
+// both in LDS, mode 1 the matrix only, mode 0 neither (heev_lds_bytes(n,
+// mode) of dynamic LDS beside heev_static_lds()).  A non-finite G gives NaN
+// eigenvalues.
+int heev_device_max();
+size_t heev_lds_bytes(int n, int mode);
+size_t heev_static_lds();
+void heev_allow_lds(size_t bytes);
+void launch_heev_jacobi(const double2* G, int ldg, int n, double2* Aw, double2* Vw, int mode, double2* U, int ldu,
+                        double* w, hipStream_t s);
+// out[e] = sum_s part[s*n + e]
+void launch_sum_parts(const double2* part, int nparts, int64_t n, double2* out, hipStream_t s);
+// out[r] = sum_b partial[r*nb + b] (the partials of launch_row_dots)
+void launch_row_sums(const double2* partial, int nb, int rows, double2* out, hipStream_t s);
+// convergence test of k roots with par = {tol, dwtol}; rep = [status, w[k],
+// |r|[k], conv[k], -, -, collapse], status 1 all converged, 0 not, -1
+// non-finite; collapse = 1 when m + (unconverged roots) > mmax; wold <- w
+void launch_dav_converge(const double* w, const double2* rn2, double* wold, int k, int m, int mmax,
+                         const double* par, double* rep, hipStream_t s);
+// when *flag != 0: rows r < mc of Out become sum_a U[a][r] In[a] (a < m, via
+// the temporary T [mc][dim]; Out may be In) and rows mc .. m of Out zero
+void launch_collapse(const double* flag, const double2* U, int ldu, int m, int mc, const double2* In, double2* T,
+                     double2* Out, int64_t dim, hipStream_t s);
+// N_r -= (a_r / b_r) P_r, or N_r = 0 where flags[r] != 0
+void launch_olsen(double2* N, const double2* P, const double2* a, const double2* b, const double* flags, int rows,
+                  int64_t dim, hipStream_t s);
+// canonical orthonormalisation coefficients C [k][k] from Gram eigenpairs
+// (lam ascending, U): kept directions first, *count = kept (-1: non-finite)
+void launch_canon(const double* lam, const double2* U, int ldu, int k, double2* C, double* count, hipStream_t s);
+
 // ---------------------------------------------------------------- engine
 struct Tensor {
   double2* p = nullptr;
@@ -358,6 +391,18 @@ struct Ctx {
   // batches for (instead of the handle's mem_budget)
   size_t ws_override = 0;
   SplitCache scache;
+  // page-locked host buffer of at least n doubles for the small reports the
+  // device iteration sends back (kept and grown across calls, freed with the
+  // context)
+  double* pinned(size_t n);
+  Ctx() = default;
+  Ctx(const Ctx&) = delete;
+  Ctx& operator=(const Ctx&) = delete;
+  ~Ctx();
+
+ private:
+  double* pinned_ = nullptr;
+  size_t pinned_n_ = 0;
 };
 
 // register a trial-independent buffer of n complex elements (scope 0); the

@@ -95,3 +95,37 @@ def test_graphs_and_autotune_match_eager(precision):
         for r in (rg[i], rg2[i]):
             assert r["converged"].all()
             assert np.abs(r["omega"] - ra[i]["omega"]).max() <= 1e-8, (i, r["omega"], ra[i]["omega"])
+
+
+@pytest.mark.parametrize("graphs", [True, "uncaptured"])
+@pytest.mark.parametrize("max_subspace", [0, 1])
+def test_device_iteration_matches_eager(graphs, max_subspace):
+    """The device-side Davidson iteration (subspace eigenproblem in one
+    workgroup, convergence test, Olsen's correction and orthonormalisation on
+    the device, captured once per subspace size) gives the host-driven
+    solve's roots and the oracle's.  The instances take every storage of the
+    one-workgroup eigensolver (subspace of 96 and 120 vectors beside small
+    ones); max_subspace = 1 (raised to 3k) collapses every few iterations."""
+    probs = [make_problem("EE", 4, 12, 32, seed=811, n_roots=16, x=1.0),
+             make_problem("EE", 5, 14, 38, seed=812, n_roots=20, x=0.5),
+             make_problem("IP", 6, 20, 52, seed=813, n_roots=4, x=1.0),
+             make_problem("EA", 3, 16, 38, seed=814, n_roots=3, x=1.0)]
+    print(f"case device iteration graphs={graphs} max_subspace={max_subspace}", flush=True)
+    kw = dict(precision="fp64", conv_tol=1e-8, n_streams=2, max_subspace=max_subspace, max_iter=400)
+    A = adc.Batch([_spec(P) for P in probs], **kw)
+    ra, rca = A.davidson()
+    A.close()
+    G = adc.Batch([_spec(P) for P in probs], graphs=graphs, **kw)
+    rg, rcg = G.davidson()
+    rg2, _ = G.davidson()  # a second solve on the same handle (fresh graphs, cached sigma graphs)
+    G.close()
+    assert rca == 0 and rcg == 0
+    for i, P in enumerate(probs):
+        w = np.linalg.eigvalsh(dense_matrix(Ints(P.eps, P.L, P.o), P.kind, P.x))[: P.n_roots]
+        print(f"  instance {i} {P.kind} k={P.n_roots}: iters eager {ra[i]['iters']} device {rg[i]['iters']}, "
+              f"max |w - dense| {np.abs(rg[i]['omega'] - w).max():.1e}", flush=True)
+        for r in (rg[i], rg2[i]):
+            assert r["converged"].all(), (i, r)
+            assert np.abs(r["omega"] - ra[i]["omega"]).max() <= 1e-8, (i, r["omega"], ra[i]["omega"])
+            assert np.abs(r["omega"] - w).max() <= 1e-8, (i, r["omega"], w)
+            assert r["resnorm"].max() <= 1e-8
