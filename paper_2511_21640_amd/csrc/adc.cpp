@@ -1692,15 +1692,21 @@ std::vector<double> row_norms2(Ctx& cx, const double2* X, int rows, int64_t dim)
 // one small report per iteration and then enqueues the sigma build of the
 // directions it keeps.
 // ---------------------------------------------------------------------------
-// G[a][b] = sum_i conj(X[a][i]) Y[b][i] (ra x rb, row stride rb) on the device
+// K-chunks of a device Gram matrix over a vector length dim: about 512 parts
+// (enough workgroups for the chip), at least 4096 long
+int64_t gram_chunk(int64_t dim) { return std::max<int64_t>(4096, ((dim + 511) / 512 + 15) / 16 * 16); }
+int64_t gram_parts(int64_t dim) { return (dim + gram_chunk(dim) - 1) / gram_chunk(dim); }
+
+// out[a][b] (row stride ldo) = sum_i conj(X[a][i]) Y[b][i] (ra x rb) on the
+// device, in FP64: per-chunk products into part, then their sum
 void gram_dev(Ctx& cx, const double2* X, int ra, const double2* Y, int rb, int64_t dim, double2* part,
-              double2* out) {
-  const int64_t chunk = 1 << 16;
+              double2* out, int ldo) {
+  const int64_t chunk = gram_chunk(dim);
   const int64_t nsplit = dim / chunk;
   const int64_t rem = dim - nsplit * chunk;
   const int64_t nparts = nsplit + (rem ? 1 : 0);
-  const int sp = cx.prec;
-  cx.prec = 0;
+  // a few columns: the 32-wide tiles
+  const int tile = rb <= 32 ? (ra <= 64 ? 4 : 3) : 0;
   if (nsplit) {
     GemmDesc g{};
     g.M = ra; g.N = rb; g.K = chunk; g.batch = nsplit;
@@ -1708,7 +1714,8 @@ void gram_dev(Ctx& cx, const double2* X, int ra, const double2* Y, int rb, int64
     g.B = Y; g.sbk = 1; g.sbn = dim; g.sbb = chunk;
     g.C = part; g.scm = rb; g.scn = 1; g.scb = (int64_t)ra * rb;
     g.alpha = C1(); g.beta = C0();
-    gemm(cx, g);
+    g.tile = tile;
+    launch_zgemm(g, 0, cx.stream);
   }
   if (rem) {
     GemmDesc g{};
@@ -1717,27 +1724,17 @@ void gram_dev(Ctx& cx, const double2* X, int ra, const double2* Y, int rb, int64
     g.B = Y + nsplit * chunk; g.sbk = 1; g.sbn = dim; g.sbb = 0;
     g.C = part + nsplit * ra * rb; g.scm = rb; g.scn = 1; g.scb = 0;
     g.alpha = C1(); g.beta = C0();
-    gemm(cx, g);
+    g.tile = tile;
+    launch_zgemm(g, 0, cx.stream);
   }
-  cx.prec = sp;
-  launch_sum_parts(part, (int)nparts, (int64_t)ra * rb, out, cx.stream);
+  launch_sum_parts(part, (int)nparts, ra, rb, out, ldo, cx.stream);
 }
 
 // Out[r][i] = alpha sum_a C[a][r] In[a][i] + beta Out[r][i], C a device matrix
 // with row stride ldc (a < m, r < nr)
 void combine_dev(Ctx& cx, const double2* C, int ldc, int m, int nr, const double2* In, double2* Out, int64_t dim,
                  cplx alpha, cplx beta) {
-  if (m == 0 || nr == 0) return;
-  GemmDesc g{};
-  g.M = nr; g.N = dim; g.K = m; g.batch = 1;
-  g.A = C; g.sam = 1; g.sak = ldc; g.sab = 0;
-  g.B = In; g.sbk = dim; g.sbn = 1; g.sbb = 0;
-  g.C = Out; g.scm = dim; g.scn = 1; g.scb = 0;
-  g.alpha = alpha; g.beta = beta;
-  const int sp = cx.prec;
-  cx.prec = 0;
-  gemm(cx, g);
-  cx.prec = sp;
+  launch_combine_cols(nullptr, C, ldc, m, nr, In, Out, dim, alpha, beta, cx.stream);
 }
 
 struct DevDav {
@@ -1777,11 +1774,11 @@ void devdav_setup(Ctx& cx, DevDav& D, int k, int mmax, int64_t dim) {
     D.blocks.push_back(p);
     return p;
   };
-  const int64_t nparts = (dim + (1 << 16) - 1) >> 16;
+  const int64_t nparts = gram_parts(dim);
   const int64_t mm = (int64_t)mmax * mmax;
   D.N = take((int64_t)k * dim);
   D.T = take((int64_t)2 * k * dim);
-  D.G = take(mm);
+  D.G = take(mm);  // the subspace Gram matrix, kept across iterations, row stride mmax
   D.U = take(mm);
   D.Aw = take(mm);
   D.Vw = take(mm);
@@ -1827,8 +1824,18 @@ void devdav_release(Ctx& cx, DevDav& D) {
   D.rep_host = nullptr;
 }
 
-// One iteration from the subspace V, S (m rows) to the new directions in N:
-//  G = V^H S and its eigenpairs; Ritz vectors X = U_k^T V, AX = U_k^T S;
+// Columns c0 .. m of the kept Gram matrix G = V^H S (rows 0 .. m), and the
+// rows they mirror to (G is Hermitian up to the rounding of S, and only its
+// Hermitian part is diagonalised): after the sigma build of rows c0 .. m.
+void devdav_gram_cols(Ctx& cx, DevDav& D, const double2* V, const double2* S, int c0, int m) {
+  if (m <= c0) return;
+  gram_dev(cx, V, m, S + (int64_t)c0 * D.dim, m - c0, D.dim, D.gpart, D.G + c0, D.mmax);
+  launch_gram_mirror(D.G, D.mmax, c0, m, cx.stream);
+}
+
+// One iteration from the subspace V, S (m rows, Gram matrix G) to the new
+// directions in N:
+//  eigenpairs of G; Ritz vectors X = U_k^T V, AX = U_k^T S;
 //  residuals R = AX - w X, their norms and the convergence test (report);
 //  N = Olsen-corrected preconditioned residuals, zero for converged roots;
 //  collapse of V, S onto the 2k lowest Ritz vectors when the subspace cannot
@@ -1841,8 +1848,7 @@ void devdav_body(Ctx& cx, const Inst& I, DevDav& D, double2* V, double2* S, doub
   const int k = D.k;
   const int64_t dim = D.dim;
   hipStream_t s = cx.stream;
-  gram_dev(cx, V, m, S, m, dim, D.gpart, D.G);
-  launch_heev_jacobi(D.G, m, m, D.Aw, D.Vw, D.mode(m), D.U, m, D.w, s);
+  launch_heev_jacobi(D.G, D.mmax, m, D.Aw, D.Vw, D.mode(m), D.U, m, D.w, s);
   combine_dev(cx, D.U, m, m, k, V, X, dim, C1(), C0());
   combine_dev(cx, D.U, m, m, k, S, AX, dim, C1(), C0());
   launch_resid(AX, X, D.w, R, k, dim, s);
@@ -1863,10 +1869,11 @@ void devdav_body(Ctx& cx, const Inst& I, DevDav& D, double2* V, double2* S, doub
   const int mc = std::min(2 * k, m);
   launch_collapse(collapse, D.U, m, m, mc, V, D.T, V, dim, s);
   launch_collapse(collapse, D.U, m, m, mc, S, D.T, S, dim, s);
+  launch_gram_diag(collapse, D.w, mc, D.G, D.mmax, s);
   for (int pass = 0; pass < 2; ++pass) {
-    gram_dev(cx, V, m, D.N, k, dim, D.gpart, D.Cc);  // Cc[a][b] = <V_a|N_b>
+    gram_dev(cx, V, m, D.N, k, dim, D.gpart, D.Cc, k);  // Cc[a][b] = <V_a|N_b>
     combine_dev(cx, D.Cc, k, m, k, V, D.N, dim, CR(-1), C1());
-    gram_dev(cx, D.N, k, D.N, k, dim, D.gpart, D.Gn);
+    gram_dev(cx, D.N, k, D.N, k, dim, D.gpart, D.Gn, k);
     launch_heev_jacobi(D.Gn, k, k, D.Aw, D.Vw, D.mode(k), D.Un, k, D.wn, s);
     launch_canon(D.wn, D.Un, k, k, D.Cc, D.rep + 1 + 3 * k + pass, s);
     combine_dev(cx, D.Cc, k, k, k, D.N, D.T, dim, C1(), C0());
@@ -2029,6 +2036,7 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   if (dev_iter) {
     devdav_setup(cx, D, k, mmax, dim);
     reset_wold();
+    devdav_gram_cols(cx, D, V, S, 0, m);
   }
   for (it = 1; it <= max_iter && dev_iter; ++it) {
     auto t_it = now();
@@ -2065,6 +2073,7 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
         hipcheck(hipMemcpyAsync(V, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "restart");
         m = orthonormalize(cx, V, 0, V, k, dim);
         sigma_call(h, I, V, S, m, prec);
+        devdav_gram_cols(cx, D, V, S, 0, m);
         reset_wold();
         continue;
       }
@@ -2078,6 +2087,7 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     sigma_call(h, I, V + (int64_t)m * dim, S + (int64_t)m * dim, nk, prec);
     if (h->opt.verbose) hipcheck(hipStreamSynchronize(cx.stream), "sigma sync");
     t_sigma += ms_since(t_s);
+    devdav_gram_cols(cx, D, V, S, m, m + nk);
     m += nk;
   }
   for (it = dev_iter ? it : 1; it <= max_iter && !dev_iter; ++it) {

@@ -188,8 +188,9 @@ __global__ __launch_bounds__(kJacobiThreads) void heev_jacobi_kernel(const doubl
   }
 }
 
-// out[e] = sum_s part[s * n + e]
-__global__ void sum_parts_kernel(const double2* part, int nparts, int64_t n, double2* out) {
+// out[r][c] (row stride ldo) = sum_s part[s][r][c] over parts of rows x cols
+__global__ void sum_parts_kernel(const double2* part, int nparts, int rows, int cols, double2* out, int ldo) {
+  const int64_t n = (int64_t)rows * cols;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   double sx = 0.0, sy = 0.0;
@@ -197,7 +198,27 @@ __global__ void sum_parts_kernel(const double2* part, int nparts, int64_t n, dou
     sx += part[(int64_t)s * n + e].x;
     sy += part[(int64_t)s * n + e].y;
   }
-  out[e] = make_double2(sx, sy);
+  out[(e / cols) * ldo + e % cols] = make_double2(sx, sy);
+}
+
+// G[j][a] = conj(G[a][j]) for c0 <= j < m, a < c0 (the rows of new columns)
+__global__ void gram_mirror_kernel(double2* G, int ldg, int c0, int m) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nc = m - c0;
+  if (e >= nc * c0) return;
+  const int j = c0 + e / c0, a = e % c0;
+  const double2 g = G[(int64_t)a * ldg + j];
+  G[(int64_t)j * ldg + a] = make_double2(g.x, -g.y);
+}
+
+// when *flag is set: G[0:mc][0:mc] = diag(w[0:mc]) (the Gram matrix of the
+// subspace collapsed onto Ritz vectors)
+__global__ void gram_diag_kernel(const double* flag, const double* w, int mc, double2* G, int ldg) {
+  if (*flag == 0.0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mc * mc) return;
+  const int a = e / mc, b = e % mc;
+  G[(int64_t)a * ldg + b] = make_double2(a == b ? w[a] : 0.0, 0.0);
 }
 
 // out[r] = sum_b partial[r * nb + b]
@@ -237,35 +258,48 @@ __global__ void dav_converge_kernel(const double* w, const double2* rn2, double*
   rep[3 + 3 * k] = (finite && !all && m + nn > mmax) ? 1.0 : 0.0;
 }
 
-// Collapse onto the lowest mc Ritz vectors, when *flag is set:
-// T[r][i] = sum_a U[a][r] In[a][i] for r < mc, a < m.  One thread per
-// column i, outputs in groups of 16 (the U entries are uniform over the
-// block).
-__global__ __launch_bounds__(256) void collapse_kernel(const double* flag, const double2* U, int ldu, int m, int mc,
-                                                       const double2* In, double2* T, int64_t dim) {
-  if (*flag == 0.0) return;
+// Out[r][i] = alpha sum_a C[a][r] In[a][i] + beta Out[r][i] for r < nr,
+// a < m (C row stride ldc), skipped when flag is given and *flag is zero.
+// Tall and skinny (a few rows over a long dim): one thread per column i,
+// outputs in groups of 16 so that In is read once per group; the C entries
+// are the same for the whole block.
+__global__ __launch_bounds__(256) void combine_cols_kernel(const double* flag, const double2* C, int ldc, int m,
+                                                           int nr, const double2* In, double2* Out, int64_t dim,
+                                                           cplx alpha, cplx beta) {
+  if (flag && *flag == 0.0) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= dim) return;
-  for (int r0 = 0; r0 < mc; r0 += 16) {
-    const int nr = mc - r0 < 16 ? mc - r0 : 16;
+  const bool has_beta = beta.re != 0.0 || beta.im != 0.0;
+  for (int r0 = 0; r0 < nr; r0 += 16) {
+    const int nq = nr - r0 < 16 ? nr - r0 : 16;
     double ax[16], ay[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) ax[j] = ay[j] = 0.0;
     for (int a = 0; a < m; ++a) {
       const double2 v = In[(int64_t)a * dim + i];
-      const double2* u = U + (int64_t)a * ldu + r0;
+      const double2* c = C + (int64_t)a * ldc + r0;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        if (j < nr) {
-          const double2 c = u[j];
-          ax[j] += c.x * v.x - c.y * v.y;
-          ay[j] += c.x * v.y + c.y * v.x;
+        if (j < nq) {
+          const double2 u = c[j];
+          ax[j] += u.x * v.x - u.y * v.y;
+          ay[j] += u.x * v.y + u.y * v.x;
         }
       }
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (j < nr) T[(int64_t)(r0 + j) * dim + i] = make_double2(ax[j], ay[j]);
+    for (int j = 0; j < 16; ++j) {
+      if (j < nq) {
+        double2* o = Out + (int64_t)(r0 + j) * dim + i;
+        double2 r = make_double2(alpha.re * ax[j] - alpha.im * ay[j], alpha.re * ay[j] + alpha.im * ax[j]);
+        if (has_beta) {
+          const double2 b = *o;
+          r.x += beta.re * b.x - beta.im * b.y;
+          r.y += beta.re * b.y + beta.im * b.x;
+        }
+        *o = r;
+      }
+    }
   }
 }
 
@@ -360,8 +394,27 @@ void heev_allow_lds(size_t bytes) {
   (void)hipGetLastError();
 }
 
-void launch_sum_parts(const double2* part, int nparts, int64_t n, double2* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nparts, n, out);
+void launch_sum_parts(const double2* part, int nparts, int rows, int cols, double2* out, int ldo, hipStream_t s) {
+  const int64_t n = (int64_t)rows * cols;
+  hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nparts, rows, cols,
+                     out, ldo);
+}
+
+void launch_gram_mirror(double2* G, int ldg, int c0, int m, hipStream_t s) {
+  const int n = (m - c0) * c0;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(gram_mirror_kernel, dim3((n + 255) / 256), dim3(256), 0, s, G, ldg, c0, m);
+}
+
+void launch_gram_diag(const double* flag, const double* w, int mc, double2* G, int ldg, hipStream_t s) {
+  hipLaunchKernelGGL(gram_diag_kernel, dim3((mc * mc + 255) / 256), dim3(256), 0, s, flag, w, mc, G, ldg);
+}
+
+void launch_combine_cols(const double* flag, const double2* C, int ldc, int m, int nr, const double2* In,
+                         double2* Out, int64_t dim, cplx alpha, cplx beta, hipStream_t s) {
+  if (m <= 0 || nr <= 0 || dim <= 0) return;
+  hipLaunchKernelGGL(combine_cols_kernel, dim3((unsigned)((dim + 255) / 256)), dim3(256), 0, s, flag, C, ldc, m, nr,
+                     In, Out, dim, alpha, beta);
 }
 
 void launch_row_sums(const double2* partial, int nb, int rows, double2* out, hipStream_t s) {
@@ -375,8 +428,7 @@ void launch_dav_converge(const double* w, const double2* rn2, double* wold, int 
 
 void launch_collapse(const double* flag, const double2* U, int ldu, int m, int mc, const double2* In, double2* T,
                      double2* Out, int64_t dim, hipStream_t s) {
-  hipLaunchKernelGGL(collapse_kernel, dim3((unsigned)((dim + 255) / 256)), dim3(256), 0, s, flag, U, ldu, m, mc, In,
-                     T, dim);
+  launch_combine_cols(flag, U, ldu, m, mc, In, T, dim, {1.0, 0.0}, {0.0, 0.0}, s);
   const int64_t total = (int64_t)m * dim;
   int64_t g = (total + 255) / 256;
   if (g > 65535LL * 16) g = 65535LL * 16;

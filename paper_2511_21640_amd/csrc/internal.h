@@ -220,8 +220,17 @@ size_t heev_static_lds();
 void heev_allow_lds(size_t bytes);
 void launch_heev_jacobi(const double2* G, int ldg, int n, double2* Aw, double2* Vw, int mode, double2* U, int ldu,
                         double* w, hipStream_t s);
-// out[e] = sum_s part[s*n + e]
-void launch_sum_parts(const double2* part, int nparts, int64_t n, double2* out, hipStream_t s);
+// out[r][c] (row stride ldo) = sum_s part[s][r][c] over rows x cols parts
+void launch_sum_parts(const double2* part, int nparts, int rows, int cols, double2* out, int ldo, hipStream_t s);
+// G[j][a] = conj(G[a][j]) for c0 <= j < m, a < c0
+void launch_gram_mirror(double2* G, int ldg, int c0, int m, hipStream_t s);
+// when *flag != 0: G[0:mc][0:mc] = diag(w[0:mc])
+void launch_gram_diag(const double* flag, const double* w, int mc, double2* G, int ldg, hipStream_t s);
+// Out[r][i] = alpha sum_a C[a][r] In[a][i] + beta Out[r][i] (r < nr, a < m,
+// C row stride ldc; Out must not overlap In), a memory-bound kernel for a
+// few rows over a long dim; with flag, only when *flag != 0
+void launch_combine_cols(const double* flag, const double2* C, int ldc, int m, int nr, const double2* In,
+                         double2* Out, int64_t dim, cplx alpha, cplx beta, hipStream_t s);
 // out[r] = sum_b partial[r*nb + b] (the partials of launch_row_dots)
 void launch_row_sums(const double2* partial, int nb, int rows, double2* out, hipStream_t s);
 // convergence test of k roots with par = {tol, dwtol}; rep = [status, w[k],

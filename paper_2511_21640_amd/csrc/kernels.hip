@@ -1079,6 +1079,8 @@ static void launch_tile(const GemmDesc& g, hipStream_t s) {
 // Tile choice: 64x64 by default.  With the accumulators in VGPRs it runs two
 // (FP64) or three (FP32) waves per SIMD and measures faster than the larger
 // tiles (FP64 128x64, FP32 128x128 / 128x64), which stay selectable (tile 1, 2).
+// FP64 tiles 3 (128x32) and 4 (64x32) are for outputs only a few columns
+// wide (Gram blocks of a subspace against a few new vectors).
 void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0 || g0.K <= 0) return;
   GemmDesc g = g0;
@@ -1089,6 +1091,8 @@ void launch_zgemm(const GemmDesc& g0, int prec, hipStream_t s) {
     launch_bf16x3(g, s);
   } else if (prec == 0) {
     if (use_big) launch_tile<double, 4, 2>(g, s);
+    else if (g.tile == 3) launch_tile<double, 4, 1>(g, s);
+    else if (g.tile == 4) launch_tile<double, 2, 1>(g, s);
     else launch_tile<double, 2, 2>(g, s);
   } else {
     if (g.tile == 2) launch_tile<float, 4, 2>(g, s);
