@@ -82,6 +82,21 @@ struct Inst {
   Tensor oooo_pp; // <kl||ij> with both pairs packed, [P_o(kl)][P_o(ij)]
   Tensor ooov_p;  // <kl||ja> with the pair (k<l) packed, [P_o][o][v]
   Tensor tpp;     // t1 with both pairs packed, [P_o][P_v]
+  // the Hermitian-half <ab||cd> assembly as grouped GEMMs over small
+  // a-blocks (exact ranges up to a block), planned for one workspace size
+  struct LadPlan {
+    int64_t wbudget = -1;  // bytes of W the chunks were planned for
+    struct Chunk {
+      int a_begin = 0, a_end = 0, prob0 = 0, nprob = 0;
+      int64_t pbase = 0, npairs = 0, gtiles = 0;
+    };
+    std::vector<Chunk> chunks;
+    std::vector<GroupProb> probs;  // output offsets relative to the chunk's W
+    std::vector<LadBlk> blk;       // per a
+    int64_t wmax = 0;              // complex64 elements of the largest chunk's W
+    GroupProb* dprobs = nullptr;   // device copies (handle allocations)
+    LadBlk* dblk = nullptr;
+  } lplan;
   unsigned short* ringq = nullptr;
   int64_t ringKp = 0;
   int2* pair_o = nullptr;
@@ -180,6 +195,79 @@ void ensure_planes(adc_handle* h, Inst& I) {
 // for rows ij in [0, nrow), z in [0, k).  L_vv is [Q][v][v].
 // ----------------------------------------------------------------------------
 void ladder_backward(Ctx& cx, const TapeOp& op, const double2* gS, double2* gY);
+
+// Blocks of the half assembly: a block [a0, a0 + nb) computes
+// W[(a-a0)*m + c-a0][(b-a0-1)*m + d-a0] = sum_Q L_ac L_bd, m = v - a0, for
+// c, d >= a0 and b > a0, a superset of what its pairs need (c, d >= a,
+// b > a).  nb is chosen per block for the least padded 128 x 128 tile work
+// per needed element; the blocks are one grouped GEMM per chunk of at most
+// wbytes of W.
+void ladder_plan(adc_handle* h, Inst& I, int64_t wbytes, int64_t Kq) {
+  auto& P = I.lplan;
+  if (P.wbudget == wbytes && P.dprobs) return;
+  P = Inst::LadPlan{};
+  const int64_t v = I.v;
+  const int64_t T = 128;  // tile of the grouped GEMM (tile code 9)
+  auto tiles = [&](int64_t M, int64_t N) { return ((M + T - 1) / T) * ((N + T - 1) / T); };
+  P.blk.assign((size_t)v, LadBlk{0, 0, 0});
+  Inst::LadPlan::Chunk ch;
+  int64_t wfill = 0;
+  auto close_chunk = [&](int a_end) {
+    ch.a_end = a_end;
+    ch.nprob = (int)P.probs.size() - ch.prob0;
+    ch.pbase = (int64_t)ch.a_begin * (2 * v - ch.a_begin - 1) / 2;
+    ch.npairs = (int64_t)a_end * (2 * v - a_end - 1) / 2 - ch.pbase;
+    P.wmax = std::max(P.wmax, wfill);
+    P.chunks.push_back(ch);
+  };
+  ch.a_begin = 0;
+  ch.prob0 = 0;
+  for (int64_t a0 = 0; a0 < v - 1;) {
+    const int64_t m = v - a0;
+    int64_t best_nb = 1;
+    double best = -1.0;
+    for (int64_t nb = 1; nb <= std::min<int64_t>(32, v - 1 - a0); ++nb) {
+      double need = 0.0;
+      for (int64_t a = a0; a < a0 + nb; ++a) need += (double)(v - a) * (double)(v - a - 1) * (double)(v - a);
+      const double padded = (double)tiles(nb * m, (v - a0 - 1) * m) * (double)(T * T);
+      const double r = padded / need;
+      if (best < 0.0 || r < best * 0.99) {
+        best = r;
+        best_nb = nb;
+      }
+    }
+    const int64_t M = best_nb * m, N = (v - a0 - 1) * m;
+    if (wfill > 0 && (wfill + M * N) * 8 > wbytes) {
+      close_chunk((int)a0);
+      ch = Inst::LadPlan::Chunk{};
+      ch.a_begin = (int)a0;
+      ch.prob0 = (int)P.probs.size();
+      wfill = 0;
+    }
+    GroupProb g{};
+    g.tile0 = ch.gtiles;
+    g.M = M;
+    g.N = N;
+    g.arow = a0 * v + a0;
+    g.brow = (a0 + 1) * v + a0;
+    g.amd = m;
+    g.bmd = m;
+    g.coff = wfill;
+    g.ldc = N;
+    P.probs.push_back(g);
+    for (int64_t a = a0; a < a0 + best_nb; ++a) P.blk[(size_t)a] = LadBlk{a0, wfill, N};
+    ch.gtiles += tiles(M, N);
+    wfill += M * N;
+    a0 += best_nb;
+  }
+  close_chunk((int)(v - 1));
+  (void)Kq;
+  P.dprobs = (GroupProb*)dmalloc(h, sizeof(GroupProb) * P.probs.size());
+  P.dblk = (LadBlk*)dmalloc(h, sizeof(LadBlk) * P.blk.size());
+  hipcheck(hipMemcpy(P.dprobs, P.probs.data(), sizeof(GroupProb) * P.probs.size(), hipMemcpyHostToDevice), "plan");
+  hipcheck(hipMemcpy(P.dblk, P.blk.data(), sizeof(LadBlk) * P.blk.size(), hipMemcpyHostToDevice), "plan");
+  P.wbudget = wbytes;
+}
 
 void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY, double2* S, int64_t ldS,
             int64_t offS, int64_t nrow, int k, cplx alpha, int prec) {
@@ -300,7 +388,28 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   // is assembled, which needs (ac|bd) for c, d >= a0 alone (about half of
   // the assembly work), and the rest is mirrored on the split planes.
   const bool half = bf && grp >= Pv;
-  for (int a0 = 0; a0 < v - 1;) {
+  // the grouped exact-range assembly (planned once per instance and W size;
+  // not inside an allocation-free call, which plans nothing)
+  if (half && !cx.pool.in_arena() && !capturing(cx.stream)) ladder_plan(h, I, (int64_t)budget, Kq);
+  if (half && I.lplan.dprobs && I.lplan.wbudget == (int64_t)budget) {
+    const auto& P = I.lplan;
+    float2* Wall = (float2*)cx.pool.get((P.wmax + 1) / 2);
+    for (const auto& ch : P.chunks) {
+      BfGemm g{};
+      g.M = 1; g.N = 1; g.Kp = Kq;
+      g.A = Lq; g.lda = (int64_t)v * v; g.ams = v;
+      g.B = Lq; g.ldb = (int64_t)v * v; g.bms = v;
+      g.C = (double2*)Wall; g.c32 = 1;
+      g.alpha = C1(); g.beta = C0(); g.tag = 1; g.tile = 9;
+      g.probs = P.dprobs + ch.prob0; g.nprob = ch.nprob; g.gtiles = ch.gtiles;
+      g.nsplit = 1; g.kchunk = Kq;
+      launch_bf16p(g, cx.stream);
+      launch_ladder_pack_planes_grouped(Wall, P.dblk, v, Vp, grp, ch.pbase, ch.npairs, I.pair_v, Kv, cx.stream);
+    }
+    cx.pool.put((double2*)Wall);
+    gfill = Pv;
+  }
+  for (int a0 = (half && gfill == Pv) ? v - 1 : 0; a0 < v - 1;) {
     int nbc = nb;
     if (half) {
       // blocks grow as the ranges of c, d shrink, keeping W near its size

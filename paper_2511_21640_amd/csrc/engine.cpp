@@ -183,6 +183,15 @@ void Pool::release_all() {
 // ------------------------------------------------------------------ GEMM driver
 // Heuristic split-K: outputs with too few tiles to fill the 256 CUs split the
 // K loop into chunks whose partial sums a reduction kernel adds up.
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
 namespace {
 
 int64_t heuristic_nsplit(int64_t M, int64_t N, int64_t K, int64_t batch, int64_t kmin) {
@@ -276,15 +285,6 @@ int lg2(int64_t n) {
   int l = 0;
   while (((int64_t)1 << l) < n) ++l;
   return l;
-}
-
-bool capturing(hipStream_t s) {
-  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
-    (void)hipGetLastError();
-    return true;
-  }
-  return st != hipStreamCaptureStatusNone;
 }
 
 std::vector<TuneChoice> candidates(int64_t heur, const std::vector<int>& tiles) {

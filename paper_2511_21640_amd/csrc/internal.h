@@ -52,6 +52,17 @@ void launch_splitk_reduce(const GemmDesc& g, hipStream_t s);
 void launch_zgemm(const GemmDesc& g, int prec, hipStream_t s);
 
 // ---------------------------------------------------------------- split-bf16 planes
+// One problem of a grouped split-bf16 GEMM (BfGemm.probs): shape M x N, the
+// first tile of its range of the grid, the plane rows its A and B rows start
+// at (row r of A is plane row arow + (r / amd) * ams + r % amd with the
+// GEMM's ams, likewise B with bmd, bms), and its output at C + coff with row
+// stride ldc (unit column stride, in the GEMM's C element type).
+struct GroupProb {
+  int64_t tile0;
+  int64_t M, N;
+  int64_t arow, brow, amd, bmd;
+  int64_t coff, ldc;
+};
 // C(m,n) = alpha * sum_k A(m,k) B(n,k) + beta C (note: B is given row-major in n)
 // with A, B as bf16 split planes [4][rows][Kp] (re hi, re lo, im hi, im lo).
 struct BfGemm {
@@ -71,8 +82,16 @@ struct BfGemm {
   int64_t amd = 0, ams = 0, bmd = 0, bms = 0;
   int colmajor = 0;  // set by launch_bf16p: tiles walk down columns (N > M)
   int c32 = 0;       // C holds complex64 (float2) elements
+  // grouped GEMM (direct-load tiles, no split-K): nprob problems in device
+  // memory, gtiles tiles in all; M, N, C offsets and row maps come from the
+  // problems, the planes, Kp, ams, bms, alpha, beta and c32 from here
+  const GroupProb* probs = nullptr;
+  int nprob = 0;
+  int64_t gtiles = 0;
 };
 void launch_bf16p(const BfGemm& g, hipStream_t s);
+// true while work on stream s is being captured into a graph
+bool capturing(hipStream_t s);
 // the tile launch_bf16p takes for g.tile < 0
 int bf16p_pick_tile(const BfGemm& g);
 void launch_splitk_reduce_bf(const BfGemm& g, hipStream_t s);
@@ -106,6 +125,16 @@ void launch_ladder_pack_planes_upper(const void* W, int w32, int64_t ldw, int a0
 // V[p][q] = conj(V[q][p]) for q < p < n on split planes [4][ldv][Kp] (the
 // packed <ab||cd> matrix is Hermitian)
 void launch_ladder_mirror_planes(unsigned short* V, int64_t ldv, int64_t n, int64_t Kp, hipStream_t s);
+// The same upper-half pack for the pairs pbase .. pbase + npairs whose first
+// index a is spread over blocks of an exact-range assembly: blk[a] = {a0 of
+// a's block, complex64 offset of the block's W in Wall, its row stride}; a
+// block's W holds sum_Q L_ac L_bd at [(a-a0)*m + c-a0][(b-a0-1)*m + d-a0],
+// m = nv - a0, c, d >= a0
+struct LadBlk {
+  int64_t a0, woff, ldw;
+};
+void launch_ladder_pack_planes_grouped(const void* Wall, const LadBlk* blk, int nv, unsigned short* V, int64_t ldv,
+                                       int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s);
 
 // ---------------------------------------------------------------- permute
 // out[sum_d idx_d * ostr[d]] = alpha * op(in[sum_d idx_d * istr[d]]) + beta * out[...]

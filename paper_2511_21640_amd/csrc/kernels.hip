@@ -728,7 +728,11 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16p_kernel(BfGemm p) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 
-template <int WM, int WN, int TAG, int WR, int WC>
+// GRP: a grouped GEMM (BfGemm.probs); each workgroup takes the problem whose
+// tile range holds its tile and runs it with that problem's shape, operand
+// rows and output (a separate instantiation, so that the plain kernels keep
+// their code)
+template <int WM, int WN, int TAG, int WR, int WC, bool GRP = false>
 __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
   constexpr int NW = WR * WC;
   constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC;
@@ -740,17 +744,44 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN, ntile = tilesM * tilesN;
+  int64_t tilesM = (p.M + BM - 1) / BM, tilesN = (p.N + BN - 1) / BN;
+  const int64_t ntile = GRP ? p.gtiles : tilesM * tilesN;
   const int64_t L = blockIdx.x;
   int64_t tile;
   {
     const int64_t q = ntile / 8, r = ntile % 8, x = L % 8, slot = L / 8;
     tile = x * q + (x < r ? x : r) + slot;
   }
+  int64_t M = p.M, N = p.N, amd = p.amd, bmd = p.bmd, scm = p.scm;
+  const unsigned short* Ap = p.A;
+  const unsigned short* Bp = p.B;
+  double2* Cp = p.C;
+  int colmajor = p.colmajor;
+  if constexpr (GRP) {
+    int lo = 0, hi = p.nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (p.probs[mid].tile0 <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    const GroupProb& g = p.probs[lo];
+    tile -= g.tile0;
+    M = g.M;
+    N = g.N;
+    Ap += g.arow * p.Kp;
+    Bp += g.brow * p.Kp;
+    amd = g.amd;
+    bmd = g.bmd;
+    Cp = p.c32 ? (double2*)((float2*)p.C + g.coff) : p.C + g.coff;
+    scm = g.ldc;
+    colmajor = N > M ? 1 : 0;
+    tilesM = (M + BM - 1) / BM;
+    tilesN = (N + BN - 1) / BN;
+  }
   // column-major walk when B is the larger operand: consecutive tiles of
   // an XCD share a column block of B, which is then fetched once
-  const int64_t m0 = (p.colmajor ? tile % tilesM : tile / tilesN) * BM,
-                n0 = (p.colmajor ? tile / tilesM : tile % tilesN) * BN;
+  const int64_t m0 = (colmajor ? tile % tilesM : tile / tilesN) * BM,
+                n0 = (colmajor ? tile / tilesM : tile % tilesN) * BN;
   const int64_t sidx = blockIdx.y;
   const int64_t kbeg = sidx * p.kchunk;
   const int64_t kend = (kbeg + p.kchunk < p.Kp) ? kbeg + p.kchunk : p.Kp;
@@ -766,15 +797,15 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
     const int rin = lane >> 2, slot = lane & 3;
     if (c < CA) {
       const int pl = c / (BM / 16), R = 16 * (c % (BM / 16)) + rin;
-      int64_t gm = (m0 + R < p.M) ? m0 + R : p.M - 1;
-      if (p.amd) gm = (gm / p.amd) * p.ams + gm % p.amd;
-      src[j] = p.A + pl * p.lda * p.Kp + gm * p.Kp + 8 * (slot ^ swz(R));
+      int64_t gm = (m0 + R < M) ? m0 + R : M - 1;
+      if (amd) gm = (gm / amd) * p.ams + gm % amd;
+      src[j] = Ap + pl * p.lda * p.Kp + gm * p.Kp + 8 * (slot ^ swz(R));
     } else {
       const int cb = c - CA;
       const int pl = cb / (BN / 16), R = 16 * (cb % (BN / 16)) + rin;
-      int64_t gn = (n0 + R < p.N) ? n0 + R : p.N - 1;
-      if (p.bmd) gn = (gn / p.bmd) * p.bms + gn % p.bmd;
-      src[j] = p.B + pl * p.ldb * p.Kp + gn * p.Kp + 8 * (slot ^ swz(R));
+      int64_t gn = (n0 + R < N) ? n0 + R : N - 1;
+      if (bmd) gn = (gn / bmd) * p.bms + gn % bmd;
+      src[j] = Bp + pl * p.ldb * p.Kp + gn * p.Kp + 8 * (slot ^ swz(R));
     }
     ldsoff[j] = c * 1024;
   }
@@ -853,17 +884,19 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
       for (int r = 0; r < 4; ++r) rows[i][r] = m0 + 16 * WM * wr + 16 * i + 4 * (lane >> 4) + r;
 #pragma unroll
     for (int j = 0; j < WN; ++j) cols[j] = n0 + 16 * WN * wc + 16 * j + (lane & 15);
-    double2* P = p.nsplit > 1 ? p.P + sidx * p.M * p.N : nullptr;
-    store_tile<WM, WN>(p.M, p.N, p.C, P, p.om, p.scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
+    double2* P = p.nsplit > 1 ? p.P + sidx * M * N : nullptr;
+    store_tile<WM, WN>(M, N, Cp, P, p.om, scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
   }
 }
 
 template <int WM, int WN, int WR, int WC>
 static void launch_bf16d_tile(const BfGemm& h, hipStream_t s) {
   constexpr int BM = 16 * WM * WR, BN = 16 * WN * WC, NT = 64 * WR * WC;
-  const int64_t tiles = ((h.M + BM - 1) / BM) * ((h.N + BN - 1) / BN);
+  const int64_t tiles = h.nprob > 0 ? h.gtiles : ((h.M + BM - 1) / BM) * ((h.N + BN - 1) / BN);
   dim3 grid((unsigned)tiles, (unsigned)h.nsplit);
-  if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 1, WR, WC>), grid, dim3(NT), 0, s, h);
+  if (h.nprob > 0)
+    hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 1, WR, WC, true>), dim3((unsigned)tiles), dim3(NT), 0, s, h);
+  else if (h.tag == 1) hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 1, WR, WC>), grid, dim3(NT), 0, s, h);
   else if (h.tag == 2) hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 2, WR, WC>), grid, dim3(NT), 0, s, h);
   else hipLaunchKernelGGL((zgemm_bf16d_kernel<WM, WN, 0, WR, WC>), grid, dim3(NT), 0, s, h);
 }
@@ -995,6 +1028,46 @@ __global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const WT*
     V[3 * plane + o] = l1;
   }
 }
+// one block row per pair (a, b) of pbase + blockIdx.y, its block found from a
+__global__ __launch_bounds__(256) void ladder_pack_planes_grouped_kernel(const float2* Wall, const LadBlk* blk, int nv,
+                                                                         unsigned short* V, int64_t ldv,
+                                                                         int64_t pbase, const int2* pv, int64_t Pv,
+                                                                         int64_t Kp) {
+  const int64_t prow = pbase + blockIdx.y;
+  const int2 ab = pv[prow];
+  const LadBlk B = blk[ab.x];
+  const float2* W = Wall + B.woff;
+  const int64_t a0 = B.a0, ldw = B.ldw;
+  const int64_t m = nv - a0;
+  const int64_t ra = (int64_t)(ab.x - a0) * m, cb = (int64_t)(ab.y - a0 - 1) * m;
+  const int64_t plane = ldv * Kp;
+  for (int64_t pc = prow + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; pc < Kp;
+       pc += (int64_t)gridDim.x * blockDim.x) {
+    unsigned short h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+    if (pc < Pv) {
+      const int2 cd = pv[pc];  // c >= a >= a0 and d > c
+      const float2 w1 = W[(ra + cd.x - a0) * ldw + cb + cd.y - a0];
+      const float2 w2 = W[(ra + cd.y - a0) * ldw + cb + cd.x - a0];
+      split_bf16(w1.x - w2.x, h0, l0);
+      split_bf16(w1.y - w2.y, h1, l1);
+    }
+    const int64_t o = prow * Kp + pc;
+    V[o] = h0;
+    V[plane + o] = l0;
+    V[2 * plane + o] = h1;
+    V[3 * plane + o] = l1;
+  }
+}
+void launch_ladder_pack_planes_grouped(const void* Wall, const LadBlk* blk, int nv, unsigned short* V, int64_t ldv,
+                                       int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp, hipStream_t s) {
+  const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
+  if (npairs <= 0 || Pv <= 0) return;
+  unsigned gx = (unsigned)((Kp + 255) / 256);
+  if (gx > 64) gx = 64;
+  hipLaunchKernelGGL(ladder_pack_planes_grouped_kernel, dim3(gx, (unsigned)npairs), dim3(256), 0, s,
+                     (const float2*)Wall, blk, nv, V, ldv, pbase, pv, Pv, Kp);
+}
+
 void launch_ladder_pack_planes_upper(const void* W, int w32, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
                                      int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
                                      hipStream_t s) {
