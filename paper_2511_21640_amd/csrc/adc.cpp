@@ -399,7 +399,7 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
       g.M = 1; g.N = 1; g.Kp = Kq;
       g.A = Lq; g.lda = (int64_t)v * v; g.ams = v;
       g.B = Lq; g.ldb = (int64_t)v * v; g.bms = v;
-      g.C = (double2*)Wall; g.c32 = 1;
+      g.C = (double2*)Wall; g.scn = 1; g.c32 = 1;
       g.alpha = C1(); g.beta = C0(); g.tag = 1; g.tile = 9;
       g.probs = P.dprobs + ch.prob0; g.nprob = ch.nprob; g.gtiles = ch.gtiles;
       g.nsplit = 1; g.kchunk = Kq;

@@ -28,6 +28,7 @@ namespace {
 
 constexpr int kJacobiThreads = 1024;
 constexpr int kJacobiMaxN = 256;
+constexpr int kCombineMaxM = 256;  // rows a of a combination: 64 KB of staged coefficients at most
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -261,34 +262,55 @@ __global__ void dav_converge_kernel(const double* w, const double2* rn2, double*
 // Out[r][i] = alpha sum_a C[a][r] In[a][i] + beta Out[r][i] for r < nr,
 // a < m (C row stride ldc), skipped when flag is given and *flag is zero.
 // Tall and skinny (a few rows over a long dim): one thread per column i,
-// outputs in groups of 16 so that In is read once per group; the C entries
-// are the same for the whole block.
+// outputs in groups of NQ so that In is read once per group; the group's C
+// entries are staged in LDS, and four rows of In are loaded at once.
+template <int NQ>
 __global__ __launch_bounds__(256) void combine_cols_kernel(const double* flag, const double2* C, int ldc, int m,
                                                            int nr, const double2* In, double2* Out, int64_t dim,
                                                            cplx alpha, cplx beta) {
   if (flag && *flag == 0.0) return;
+  extern __shared__ double2 cs[];  // [m][NQ]
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= dim) return;
+  const bool live = i < dim;
   const bool has_beta = beta.re != 0.0 || beta.im != 0.0;
-  for (int r0 = 0; r0 < nr; r0 += 16) {
-    const int nq = nr - r0 < 16 ? nr - r0 : 16;
-    double ax[16], ay[16];
+  for (int r0 = 0; r0 < nr; r0 += NQ) {
+    const int nq = nr - r0 < NQ ? nr - r0 : NQ;
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * NQ; e += blockDim.x) {
+      const int a = e / NQ, j = e % NQ;
+      cs[e] = j < nq ? C[(int64_t)a * ldc + r0 + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (!live) continue;
+    double ax[NQ], ay[NQ];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) ax[j] = ay[j] = 0.0;
-    for (int a = 0; a < m; ++a) {
-      const double2 v = In[(int64_t)a * dim + i];
-      const double2* c = C + (int64_t)a * ldc + r0;
+    for (int j = 0; j < NQ; ++j) ax[j] = ay[j] = 0.0;
+    const double2* col = In + i;
+    int a = 0;
+    for (; a + 4 <= m; a += 4) {
+      double2 v[4];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        if (j < nq) {
-          const double2 u = c[j];
-          ax[j] += u.x * v.x - u.y * v.y;
-          ay[j] += u.x * v.y + u.y * v.x;
+      for (int u = 0; u < 4; ++u) v[u] = col[(int64_t)(a + u) * dim];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+          const double2 c = cs[(a + u) * NQ + j];
+          ax[j] += c.x * v[u].x - c.y * v[u].y;
+          ay[j] += c.x * v[u].y + c.y * v[u].x;
         }
+    }
+    for (; a < m; ++a) {
+      const double2 v = col[(int64_t)a * dim];
+#pragma unroll
+      for (int j = 0; j < NQ; ++j) {
+        const double2 c = cs[a * NQ + j];
+        ax[j] += c.x * v.x - c.y * v.y;
+        ay[j] += c.x * v.y + c.y * v.x;
       }
     }
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < NQ; ++j) {
       if (j < nq) {
         double2* o = Out + (int64_t)(r0 + j) * dim + i;
         double2 r = make_double2(alpha.re * ax[j] - alpha.im * ay[j], alpha.re * ay[j] + alpha.im * ax[j]);
@@ -413,8 +435,14 @@ void launch_gram_diag(const double* flag, const double* w, int mc, double2* G, i
 void launch_combine_cols(const double* flag, const double2* C, int ldc, int m, int nr, const double2* In,
                          double2* Out, int64_t dim, cplx alpha, cplx beta, hipStream_t s) {
   if (m <= 0 || nr <= 0 || dim <= 0) return;
-  hipLaunchKernelGGL(combine_cols_kernel, dim3((unsigned)((dim + 255) / 256)), dim3(256), 0, s, flag, C, ldc, m, nr,
-                     In, Out, dim, alpha, beta);
+  if (m > kCombineMaxM) throw HipError{hipErrorInvalidValue, "combination over more than 256 rows"};
+  const dim3 grid((unsigned)((dim + 255) / 256));
+  if (nr <= 8)
+    hipLaunchKernelGGL(combine_cols_kernel<8>, grid, dim3(256), sizeof(double2) * 8 * m, s, flag, C, ldc, m, nr, In,
+                       Out, dim, alpha, beta);
+  else
+    hipLaunchKernelGGL(combine_cols_kernel<16>, grid, dim3(256), sizeof(double2) * 16 * m, s, flag, C, ldc, m, nr,
+                       In, Out, dim, alpha, beta);
 }
 
 void launch_row_sums(const double2* partial, int nb, int rows, double2* out, hipStream_t s) {

@@ -885,7 +885,7 @@ __global__ __launch_bounds__(64 * WR * WC) void zgemm_bf16d_kernel(BfGemm p) {
 #pragma unroll
     for (int j = 0; j < WN; ++j) cols[j] = n0 + 16 * WN * wc + 16 * j + (lane & 15);
     double2* P = p.nsplit > 1 ? p.P + sidx * M * N : nullptr;
-    store_tile<WM, WN>(M, N, Cp, P, p.om, scm, p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
+    store_tile<WM, WN>(M, N, Cp, P, p.om, scm, GRP ? 1 : p.scn, p.alpha, p.beta, rows, cols, accR, accI, p.c32);
   }
 }
 
