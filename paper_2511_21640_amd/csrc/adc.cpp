@@ -298,7 +298,7 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   // wasted: keep blocks near v/8 when the GEMMs stay large enough
   nb = std::min(nb, std::max(16, (v + 7) / 8));
   nb = std::min(nb, v - 1);
-  double2* Wbuf = cx.pool.get((int64_t)nb * v * v * v);
+  double2* Wbuf = nullptr;  // per-block assembly output (not needed by the grouped assembly)
   // the k vectors' rows are stacked into one [k*nrow][Pv] operand (M = k*nrow);
   // split-bf16 splits them straight from Y and writes S through an output
   // map, the other precisions stage them in Yc, Sc
@@ -409,21 +409,60 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     cx.pool.put((double2*)Wall);
     gfill = Pv;
   }
+  // Several row groups in split-bf16 (the packed rows do not fit one
+  // group): each group still assembles only its upper part (pairs cd >= ab);
+  // the group's diagonal block is mirrored, its rows are contracted over all
+  // columns (the columns of earlier groups zeroed), and the conjugate
+  // transpose of its rows right of the block is contracted into the later
+  // columns of S, which the later groups' rows would otherwise need.
+  const bool mg = bf && !half;
+  auto flush_mg = [&]() {
+    if (gfill == 0) return;
+    const int64_t g0 = gbase, n = gfill, g1 = g0 + n;
+    launch_planes_zero_cols(Vp, grp, n, g0, Kv, cx.stream);
+    launch_ladder_mirror_block(Vp, grp, n, Kv, g0, cx.stream);
+    contract();
+    if (g1 < Pv) {
+      const int64_t g0a = g0 / 32 * 32, Kg = pad32(g1 - g0a), nc = Pv - g1;
+      unsigned short* T = planes_alloc(cx, nc, Kg);
+      launch_ladder_transpose_planes(Vp, grp, n, g1, nc, Kv, T, Kg, g0 - g0a, cx.stream);
+      unsigned short* Yw = planes_alloc(cx, R, Kg);
+      launch_planes_copy_cols(Yp, R, Kv, g0a, Yw, Kg, cx.stream);
+      // S[z][offS + r*Pv + q] += alpha sum_{ab in group} Y[z][r][ab] conj <ab||q>, q >= g1
+      BfGemm c{};
+      c.M = R; c.N = nc; c.Kp = Kg;
+      c.A = Yw; c.lda = R;
+      c.B = T; c.ldb = nc;
+      c.C = S + offS + g1; c.scn = 1;
+      c.om.nm = 2; c.om.md[0] = k; c.om.md[1] = nrow; c.om.ms[0] = ldS; c.om.ms[1] = Pv;
+      c.alpha = alpha; c.beta = C1(); c.tag = 2;
+      gemm_bf16p(cx, c);
+      cx.pool.put((double2*)Yw);
+      cx.pool.put((double2*)T);
+    }
+  };
+  if (!(half && gfill == Pv)) Wbuf = cx.pool.get((int64_t)nb * v * v * v);
   for (int a0 = (half && gfill == Pv) ? v - 1 : 0; a0 < v - 1;) {
     int nbc = nb;
-    if (half) {
+    if (half || mg) {
       // blocks grow as the ranges of c, d shrink, keeping W near its size
       const int64_t m = v - a0;
       int64_t want = ((int64_t)nb * v * v * v) / std::max<int64_t>(1, m * m * (m - 1));
       want = std::min<int64_t>(want, std::max<int64_t>(nb, m / 4));
       nbc = (int)std::max<int64_t>(nb, want);
+      // a block's rows fit one group
+      while (mg && nbc > 1 &&
+             (int64_t)std::min(v - 1, a0 + nbc) * (2 * v - std::min(v - 1, a0 + nbc) - 1) / 2 -
+                     (int64_t)a0 * (2 * v - a0 - 1) / 2 > grp)
+        --nbc;
     }
     const int a1 = std::min(v - 1, a0 + nbc);
     const int b0 = a0 + 1;
     const int64_t pbase = (int64_t)a0 * (2 * v - a0 - 1) / 2;
     const int64_t pend = (int64_t)a1 * (2 * v - a1 - 1) / 2;
     const int64_t np = pend - pbase;
-    if (half) {
+    if (mg && gfill + np > grp) flush_mg();
+    if (half || mg) {
       // W[(a-a0)*m + c-a0][(b-b0)*m + d-a0] = sum_Q L_ac L_bd, c, d >= a0
       const int64_t m = v - a0;
       const int64_t Mw = (int64_t)(a1 - a0) * m, Nw = (int64_t)(v - b0) * m;
@@ -436,7 +475,8 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
       g.C = Wbuf; g.scm = Nw; g.scn = 1; g.c32 = 1;
       g.alpha = C1(); g.beta = C0(); g.tag = 1;
       gemm_bf16p(cx, g);
-      launch_ladder_pack_planes_upper(Wbuf, 1, Nw, a0, b0, v, Vp, grp, pbase, np, I.pair_v, Kv, cx.stream);
+      launch_ladder_pack_planes_upper(Wbuf, 1, Nw, a0, b0, v, Vp, grp, pbase, np, I.pair_v, Kv, cx.stream,
+                                      mg ? gbase : 0);
       gfill += np;
       a0 = a1;
       continue;
@@ -470,8 +510,12 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     gfill += np;
     a0 = a1;
   }
-  if (half) launch_ladder_mirror_planes(Vp, grp, Pv, Kv, cx.stream);
-  contract();
+  if (mg) {
+    flush_mg();
+  } else {
+    if (half) launch_ladder_mirror_planes(Vp, grp, Pv, Kv, cx.stream);
+    contract();
+  }
   if (Lq_tmp) cx.pool.put((double2*)Lq_tmp);
   if (own_yp) cx.pool.put((double2*)Yp);
   if (Vp) cx.pool.put((double2*)Vp);
@@ -482,7 +526,7 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
     cx.pool.put(Yc);
     cx.pool.put(Sc);
   }
-  cx.pool.put(Wbuf);
+  if (Wbuf) cx.pool.put(Wbuf);
 }
 
 // the unpacked trial vectors of one sigma build stay unchanged until the

@@ -121,7 +121,18 @@ void launch_ladder_pack_planes(const double2* W, int64_t ldw, int a0, int b0, in
 // complex128 (w32 = 0) or complex64 (w32 = 1) elements
 void launch_ladder_pack_planes_upper(const void* W, int w32, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
                                      int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
-                                     hipStream_t s);
+                                     hipStream_t s, int64_t vrow0 = 0);
+// (vrow0: pair p goes to V row p - vrow0, for a group of rows starting there)
+// split planes [4][ldv][Kp]: V[pl][r][0:c1] = 0 for r < rows
+void launch_planes_zero_cols(unsigned short* V, int64_t ldv, int64_t rows, int64_t c1, int64_t Kp, hipStream_t s);
+// lower part of a row group's diagonal block: V[r][col0 + c] = conj V[c][col0 + r], c < r < n
+void launch_ladder_mirror_block(unsigned short* V, int64_t ldv, int64_t n, int64_t Kp, int64_t col0, hipStream_t s);
+// T [4][ncols][Kt] with T[q][koff + r] = conj V[r][c0 + q] (r < rows, q < ncols), zero elsewhere
+void launch_ladder_transpose_planes(const unsigned short* V, int64_t ldv, int64_t rows, int64_t c0, int64_t ncols,
+                                    int64_t Kp, unsigned short* T, int64_t Kt, int64_t koff, hipStream_t s);
+// dst [4][rows][Kt] = columns c0 .. c0 + Kt of src [4][rows][Kp]
+void launch_planes_copy_cols(const unsigned short* src, int64_t rows, int64_t Kp, int64_t c0, unsigned short* dst,
+                             int64_t Kt, hipStream_t s);
 // V[p][q] = conj(V[q][p]) for q < p < n on split planes [4][ldv][Kp] (the
 // packed <ab||cd> matrix is Hermitian)
 void launch_ladder_mirror_planes(unsigned short* V, int64_t ldv, int64_t n, int64_t Kp, hipStream_t s);

@@ -1004,7 +1004,7 @@ template <typename WT>
 __global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const WT* W, int64_t ldw, int a0, int b0,
                                                                        int nv, unsigned short* V, int64_t ldv,
                                                                        int64_t pbase, const int2* pv, int64_t Pv,
-                                                                       int64_t Kp) {
+                                                                       int64_t Kp, int64_t vrow0) {
   const int64_t pr = blockIdx.y, prow = pbase + pr;
   const int2 ab = pv[prow];
   const int64_t m = nv - a0;
@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(256) void ladder_pack_planes_upper_kernel(const WT*
       split_bf16((float)(w1.x - w2.x), h0, l0);
       split_bf16((float)(w1.y - w2.y), h1, l1);
     }
-    const int64_t o = prow * Kp + pc;
+    const int64_t o = (prow - vrow0) * Kp + pc;
     V[o] = h0;
     V[plane + o] = l0;
     V[2 * plane + o] = h1;
@@ -1070,18 +1070,129 @@ void launch_ladder_pack_planes_grouped(const void* Wall, const LadBlk* blk, int 
 
 void launch_ladder_pack_planes_upper(const void* W, int w32, int64_t ldw, int a0, int b0, int nv, unsigned short* V,
                                      int64_t ldv, int64_t pbase, int64_t npairs, const int2* pv, int64_t Kp,
-                                     hipStream_t s) {
+                                     hipStream_t s, int64_t vrow0) {
   const int64_t Pv = (int64_t)nv * (nv - 1) / 2;
   if (npairs <= 0 || Pv <= 0) return;
   unsigned gx = (unsigned)((Kp + 255) / 256);
   if (gx > 64) gx = 64;
   if (w32)
     hipLaunchKernelGGL(ladder_pack_planes_upper_kernel<float2>, dim3(gx, (unsigned)npairs), dim3(256), 0, s,
-                       (const float2*)W, ldw, a0, b0, nv, V, ldv, pbase, pv, Pv, Kp);
+                       (const float2*)W, ldw, a0, b0, nv, V, ldv, pbase, pv, Pv, Kp, vrow0);
   else
     hipLaunchKernelGGL(ladder_pack_planes_upper_kernel<double2>, dim3(gx, (unsigned)npairs), dim3(256), 0, s,
-                       (const double2*)W, ldw, a0, b0, nv, V, ldv, pbase, pv, Pv, Kp);
+                       (const double2*)W, ldw, a0, b0, nv, V, ldv, pbase, pv, Pv, Kp, vrow0);
 }
+// V[pl][r][0:c1] = 0 for r < rows (planes [4][ldv][Kp])
+__global__ __launch_bounds__(256) void planes_zero_cols_kernel(unsigned short* V, int64_t ldv, int64_t rows,
+                                                               int64_t c1, int64_t Kp) {
+  const int64_t total = 4 * rows * c1;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pl = e / (rows * c1), rem = e - pl * rows * c1, r = rem / c1, c = rem - r * c1;
+    V[pl * ldv * Kp + r * Kp + c] = 0;
+  }
+}
+void launch_planes_zero_cols(unsigned short* V, int64_t ldv, int64_t rows, int64_t c1, int64_t Kp, hipStream_t s) {
+  const int64_t total = 4 * rows * c1;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(planes_zero_cols_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65535 * 16)),
+                     dim3(256), 0, s, V, ldv, rows, c1, Kp);
+}
+
+// Lower part of the diagonal block of a row group: local row r holds pair
+// col0 + r, so V[pl][r][col0 + c] = conj V[pl][c][col0 + r] for c < r < n
+// (the imaginary planes change sign).  64 x 64 tiles of the lower triangle
+// through LDS, one bf16 per access.
+__global__ __launch_bounds__(256) void ladder_mirror_block_kernel(unsigned short* V, int64_t ldv, int64_t n,
+                                                                  int64_t Kp, int64_t col0) {
+  __shared__ unsigned short t[64][65];
+  const int64_t L = blockIdx.x;
+  int64_t tp = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
+  while ((tp + 1) * (tp + 2) / 2 <= L) ++tp;
+  while (tp * (tp + 1) / 2 > L) --tp;
+  const int64_t tq = L - tp * (tp + 1) / 2;
+  const int64_t p0 = tp * 64, q0 = tq * 64;  // rows p0 .. take columns col0 + q0 ..
+  const int64_t plane = ldv * Kp;
+  const int c = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int pl = 0; pl < 4; ++pl) {
+    const unsigned short flip = pl >= 2 ? 0x8000 : 0;
+    unsigned short* Vp = V + pl * plane;
+    // the upper part: rows q0 + r, columns col0 + p0 + c
+    for (int r = ty; r < 64; r += 4) {
+      const int64_t q = q0 + r, p = p0 + c;
+      t[r][c] = (q < n && p < n && q < p) ? Vp[q * Kp + col0 + p] : (unsigned short)0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+      const int64_t p = p0 + r, q = q0 + c;
+      if (p < n && q < p) {
+        const unsigned short w = t[c][r];
+        Vp[p * Kp + col0 + q] = (w & 0x7fff) ? (unsigned short)(w ^ flip) : w;
+      }
+    }
+    __syncthreads();
+  }
+}
+void launch_ladder_mirror_block(unsigned short* V, int64_t ldv, int64_t n, int64_t Kp, int64_t col0, hipStream_t s) {
+  if (n <= 1) return;
+  const int64_t nt = (n + 63) / 64;
+  hipLaunchKernelGGL(ladder_mirror_block_kernel, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(256), 0, s, V, ldv, n, Kp,
+                     col0);
+}
+
+// T[pl][q][koff + r] = conj V[pl][r][c0 + q] for r < rows, q < ncols (planes
+// of V: [4][ldv][Kp]; of T: [4][ncols][Kt]), zero in T's other columns;
+// 64 x 64 tiles through LDS
+__global__ __launch_bounds__(256) void ladder_transpose_planes_kernel(const unsigned short* V, int64_t ldv,
+                                                                      int64_t rows, int64_t c0, int64_t ncols,
+                                                                      int64_t Kp, unsigned short* T, int64_t Kt,
+                                                                      int64_t koff) {
+  __shared__ unsigned short t[64][65];
+  const int64_t q0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 64;  // rows, columns of T
+  const int c = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int pl = 0; pl < 4; ++pl) {
+    const unsigned short flip = pl >= 2 ? 0x8000 : 0;
+    for (int e = ty; e < 64; e += 4) {
+      const int64_t r = k0 + e - koff, q = q0 + c;
+      unsigned short w = 0;
+      if (r >= 0 && r < rows && q < ncols) {
+        w = V[pl * ldv * Kp + r * Kp + c0 + q];
+        if (w & 0x7fff) w ^= flip;
+      }
+      t[e][c] = w;
+    }
+    __syncthreads();
+    for (int e = ty; e < 64; e += 4) {
+      const int64_t q = q0 + e, kk = k0 + c;
+      if (q < ncols && kk < Kt) T[pl * ncols * Kt + q * Kt + kk] = t[c][e];
+    }
+    __syncthreads();
+  }
+}
+void launch_ladder_transpose_planes(const unsigned short* V, int64_t ldv, int64_t rows, int64_t c0, int64_t ncols,
+                                    int64_t Kp, unsigned short* T, int64_t Kt, int64_t koff, hipStream_t s) {
+  if (ncols <= 0 || Kt <= 0) return;
+  hipLaunchKernelGGL(ladder_transpose_planes_kernel, dim3((unsigned)((ncols + 63) / 64), (unsigned)((Kt + 63) / 64)),
+                     dim3(256), 0, s, V, ldv, rows, c0, ncols, Kp, T, Kt, koff);
+}
+
+// dst[pl][r][kk] = src[pl][r][c0 + kk] for kk < Kt (planes [4][rows][Kp] and
+// [4][rows][Kt])
+__global__ __launch_bounds__(256) void planes_copy_cols_kernel(const unsigned short* src, int64_t rows, int64_t Kp,
+                                                               int64_t c0, unsigned short* dst, int64_t Kt) {
+  const int64_t total = 4 * rows * Kt;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t pr = e / Kt, kk = e - pr * Kt;  // pr = plane * rows + r
+    dst[e] = src[pr * Kp + c0 + kk];
+  }
+}
+void launch_planes_copy_cols(const unsigned short* src, int64_t rows, int64_t Kp, int64_t c0, unsigned short* dst,
+                             int64_t Kt, hipStream_t s) {
+  const int64_t total = 4 * rows * Kt;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(planes_copy_cols_kernel, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65535 * 16)),
+                     dim3(256), 0, s, src, rows, Kp, c0, dst, Kt);
+}
+
 
 // 64 x 64 tiles (tp >= tq) of the strictly lower triangle: read block (q, p)
 // of the upper part through LDS, write its conjugate transpose at (p, q);

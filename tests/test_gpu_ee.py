@@ -131,14 +131,17 @@ def test_split_bf16_sigma_and_mixed_davidson(kind):
     assert np.abs(out["omega"] - out64["omega"]).max() < 1e-8
 
 
-@pytest.mark.parametrize("v,budget", [(40, 0), (40, 1 << 20)])
-def test_split_bf16_ladder_blocks(v, budget):
+@pytest.mark.parametrize("kind,v,budget", [("EE", 40, 0), ("EE", 40, 1 << 20), ("EA", 40, 1 << 20),
+                                            ("EE", 37, 3 << 19), ("EA", 53, 1 << 21)])
+def test_split_bf16_ladder_blocks(kind, v, budget):
     """The split-bf16 particle-particle ladder over several a-blocks: with the
     default workspace only the Hermitian upper part of <ab||cd> is assembled
-    and mirrored; a 1 MiB workspace forces several row groups of the full
-    assembly.  Both equal the FP64 ladder to split-bf16 accuracy."""
-    P = make_problem("EE", 4, v, 120, seed=41, n_roots=2, x=1.0)
-    print(f"case split-bf16 ladder v={v} budget={budget}", flush=True)
+    (grouped over exact-range blocks) and mirrored; a workspace of 1-2 MiB
+    forces many row groups, each assembling its upper part, mirroring its
+    diagonal block and contracting the conjugate transpose of its rows into
+    the later columns.  All equal the FP64 ladder to split-bf16 accuracy."""
+    P = make_problem(kind, 4, v, 120, seed=41, n_roots=2, x=1.0)
+    print(f"case split-bf16 ladder {kind} v={v} budget={budget}", flush=True)
     h = _handle(P, precision="split_bf16", mem_budget=budget)
     rng = np.random.default_rng(41)
     Y = torch.from_numpy(_rand(rng, 3, h.dim)).cuda()
