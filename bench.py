@@ -25,14 +25,14 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
 # HBM bytes (FETCH_SIZE + WRITE_SIZE, scaled by a plain 1 GiB copy) of one
 # split-bf16 ladder term at this workload, from the counter runs summarised in
 # profiles/ladder_c2_split_bf16.md; None for the other precisions (not measured)
-LADDER_TRAFFIC_BYTES = {"split_bf16": 7.230e9 + 1.511e9}
+LADDER_TRAFFIC_BYTES = {"split_bf16": 6.372e9 + 1.323e9}
 DTYPE = {"fp64": "f64", "fp32": "f32", "split_bf16": "bf16x3"}
 # MFMA counters of one split-bf16 ladder term at this workload, from the
 # counter run summarised in profiles/ladder_c2_split_bf16.md: executed MFMA
 # flop (SQ_INSTS_VALU_MFMA_MOPS_BF16 x 512) / 2.5 PFLOP/s / kernel time, and
 # SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE per XCC x 1024 SIMDs); None for
 # the precisions not measured
-MFMA_COUNTERS = {"split_bf16": {"exec_frac": 0.40, "busy_frac": 0.44}}
+MFMA_COUNTERS = {"split_bf16": {"exec_frac": 0.42, "busy_frac": 0.49}}
 
 
 def core_terms(o, v, N, k):
