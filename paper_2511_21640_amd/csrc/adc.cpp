@@ -119,6 +119,19 @@ struct Inst {
   // allocation-free sigma builds: the smallest row count per precision that
   // did not fit the scratch (0 = none seen)
   int noalloc_too_big[3] = {0, 0, 0};
+  // reverse mode: the recorded one-off part of the first adc_sigma_backward
+  // call, kept for the later calls (see BwCache)
+  std::shared_ptr<struct BwCache> bw;
+};
+
+// The tape of the one-off work (integrals, amplitudes, intermediates) that
+// adc_sigma_backward recomputes from L, and the instance copy J it recorded
+// into: the first call records it, later calls record only the sigma build
+// on top and cut the tape back to this length after their sweep.
+struct BwCache {
+  Tape T;
+  Inst J;
+  size_t n_ops = 0, n_allocs = 0, n_deferred = 0;
 };
 
 }  // namespace
@@ -2521,50 +2534,85 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     for (Tensor* t : {&S0, &S1, &r}) tfree(cx, *t);
   }
   if (dL) {
-    Tape T;
-    Inst J;
+    // the one-off part is recorded by the first call and kept (with every
+    // buffer it wrote) for the later ones
+    const bool fresh = !I.bw;
+    if (fresh) I.bw = std::make_shared<BwCache>();
+    BwCache& B = *I.bw;
+    Tape& T = B.T;
+    Inst& J = B.J;
+    bool done = false;
     struct Cleanup {
       Ctx& cx;
-      Inst& J;
+      Inst& I;
+      BwCache& B;
       int prec;
+      bool& done;
       ~Cleanup() {
-        tape_release(cx);
-        inst_release_derived(cx, J);
+        if (done) {
+          // cut the tape back to the one-off part: the sigma part's ops,
+          // buffers and postponed frees go, every gradient is dropped
+          for (auto& a : B.T.allocs)
+            if (a.grad) {
+              cx.pool.put(a.grad);
+              a.grad = nullptr;
+            }
+          for (size_t i = B.n_deferred; i < B.T.deferred.size(); ++i) cx.pool.put(B.T.deferred[i]);
+          B.T.deferred.resize(B.n_deferred);
+          B.T.allocs.resize(B.n_allocs);
+          B.T.ops.resize(B.n_ops);
+          B.T.recording = false;
+          cx.pool.tape = nullptr;
+          cx.tape = nullptr;
+        } else {
+          cx.tape = &B.T;
+          tape_release(cx);
+          inst_release_derived(cx, B.J);
+          I.bw.reset();
+        }
         cx.pool.trim();
         cx.prec = prec;
       }
-    } cleanup{cx, J, saved_prec};
+    } cleanup{cx, I, B, saved_prec, done};
     cx.tape = &T;
     cx.pool.tape = &T;
-    for (Tensor* leaf : {&I.Loo, &I.Lov, &I.Lvo, &I.Lvv}) {
-      T.add(leaf->p, sizeof(double2) * (size_t)leaf->size(), true);
-      T.allocs.back().ref = true;
+    // a split-bf16 ladder reads the instance's planes of L_vv (the same L_vv)
+    if (h->opt.precision == ADC_SPLIT_BF16 && I.kind != ADC_IP) ensure_planes(h, I);
+    if (fresh) {
+      for (Tensor* leaf : {&I.Loo, &I.Lov, &I.Lvo, &I.Lvv}) {
+        T.add(leaf->p, sizeof(double2) * (size_t)leaf->size(), true);
+        T.allocs.back().ref = true;
+      }
+      J.cx = I.cx;
+      J.kind = I.kind; J.o = o; J.v = v; J.N = N; J.k = I.k; J.x = I.x;
+      J.n1 = I.n1; J.n2 = I.n2; J.dim = dim; J.Po = I.Po; J.Pv = I.Pv;
+      J.eps = I.eps; J.Loo = I.Loo; J.Lov = I.Lov; J.Lvo = I.Lvo; J.Lvv = I.Lvv;
+      J.pair_o = I.pair_o; J.pair_v = I.pair_v; J.diag = I.diag;
+      std::vector<double> eps_h(n);
+      hipcheck(hipMemcpy(eps_h.data(), I.eps, sizeof(double) * n, hipMemcpyDeviceToHost), "bw eps");
+      T.recording = true;
+      init_integrals(h, J);
+      {
+        Pre P;
+        init_amplitudes(h, J, P);
+        if (J.kind == ADC_EE) ee_init(h, J, P, eps_h);
+        else if (J.kind == ADC_IP) ip_init(h, J, P, eps_h);
+        else ea_init(h, J, P, eps_h);
+        for (Tensor* q : {&P.Lt, &P.Ht, &P.t2, &P.ts}) tfree(cx, *q);
+      }
+      T.recording = false;
+      B.n_ops = T.ops.size();
+      B.n_allocs = T.allocs.size();
+      B.n_deferred = T.deferred.size();
     }
+    J.Lq = I.Lq;
+    J.Kq = I.Kq;
     // fresh copies of the constant operands, so every recorded pointer is tracked
     Tensor Yc = tnew(cx, {k, dim}, false), Sg = tnew(cx, {k, dim}, false);
     hipcheck(hipMemcpyAsync(Yc.p, Y, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "bw Y");
-    J.cx = I.cx;
-    J.kind = I.kind; J.o = o; J.v = v; J.N = N; J.k = I.k; J.x = I.x;
-    J.n1 = I.n1; J.n2 = I.n2; J.dim = dim; J.Po = I.Po; J.Pv = I.Pv;
-    J.eps = I.eps; J.Loo = I.Loo; J.Lov = I.Lov; J.Lvo = I.Lvo; J.Lvv = I.Lvv;
-    J.pair_o = I.pair_o; J.pair_v = I.pair_v; J.diag = I.diag;
-    // a split-bf16 ladder reads the instance's planes of L_vv (the same L_vv)
-    if (h->opt.precision == ADC_SPLIT_BF16 && I.kind != ADC_IP) ensure_planes(h, I);
-    J.Lq = I.Lq; J.Kq = I.Kq;
-    std::vector<double> eps_h(n);
-    hipcheck(hipMemcpy(eps_h.data(), I.eps, sizeof(double) * n, hipMemcpyDeviceToHost), "bw eps");
-    T.recording = true;
-    init_integrals(h, J);
-    {
-      Pre P;
-      init_amplitudes(h, J, P);
-      if (J.kind == ADC_EE) ee_init(h, J, P, eps_h);
-      else if (J.kind == ADC_IP) ip_init(h, J, P, eps_h);
-      else ea_init(h, J, P, eps_h);
-      for (Tensor* q : {&P.Lt, &P.Ht, &P.t2, &P.ts}) tfree(cx, *q);
-    }
     // the sigma part in the handle's arithmetic (its reverse rules follow
     // it); the one-off part above stays FP64, as in adc_init
+    T.recording = true;
     sigma_dispatch(h, J, Yc.p, Sg.p, k, h->opt.precision);
     T.recording = false;
     {
@@ -2590,6 +2638,7 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
     tfree(cx, Yc);
     tfree(cx, Sg);
     hipcheck(hipStreamSynchronize(cx.stream), "bw end");
+    done = true;
   }
   cx.prec = saved_prec;
 }

@@ -232,3 +232,36 @@ def test_c5_mixed_vjp_and_root_gradients():
         ex = abs(xbf.item() - x64.item()) / max(1.0, abs(x64.item()))
         print(f"  root {r}: dw/dL mixed vs fp64 {e:.2e}, dw/dx {ex:.2e}", flush=True)
         assert e <= 1e-4 and ex <= 1e-4, (r, e, ex)
+
+
+@pytest.mark.parametrize("kind,precision", [("EE", "fp64"), ("EA", "fp64"), ("IP", "fp64"), ("EE", "split_bf16")])
+def test_repeated_backward_reuses_the_recorded_setup(kind, precision):
+    """The first adc_sigma_backward call records the one-off part (integrals,
+    amplitudes, intermediates) and keeps it; later calls on the same handle
+    record only the sigma build on top.  Each of three calls with different
+    (Sbar, Y), and of different k, equals the single call of a fresh handle
+    (deterministic tile choices), and the FP64 ones equal the oracle."""
+    P = make_problem(kind, 4, 9, 30, seed=61, n_roots=2, x=0.6)
+    print(f"case repeated backward {kind} {precision}", flush=True)
+    kw = dict(x=P.x, precision=precision, deterministic=True)
+    h = adc.Handle(P.kind, P.o, P.v, P.eps, P.L, P.n_roots, **kw)
+    rng = np.random.default_rng(62)
+    import time
+    for call, k in enumerate((2, 3, 1)):
+        Y, Sb = _rand(rng, k, h.dim), _rand(rng, k, h.dim)
+        Yd, Sd = torch.from_numpy(Y).cuda(), torch.from_numpy(Sb).cuda()
+        t0 = time.perf_counter()
+        dL, dx = h.sigma_backward(Sd, Yd)
+        t1 = time.perf_counter()
+        f = adc.Handle(P.kind, P.o, P.v, P.eps, P.L, P.n_roots, **kw)
+        dL1, dx1 = f.sigma_backward(Sd, Yd)
+        f.close()
+        print(f"  call {call}: {1e3 * (t1 - t0):.1f} ms on the kept setup", flush=True)
+        dL, dL1 = dL.cpu().numpy(), dL1.cpu().numpy()
+        assert np.abs(dL - dL1).max() <= 1e-14 * np.abs(dL1).max(), call
+        assert abs(dx - dx1) <= 1e-14 * max(1.0, abs(dx1)), call
+        if precision == "fp64":
+            ref, rdx = vjp(P.kind, P.eps, P.L, P.o, P.x, Y, Sb)
+            assert np.abs(dL - ref).max() <= 1e-11 * np.abs(ref).max(), call
+            assert abs(dx - rdx) <= 1e-11 * max(1.0, abs(rdx)), call
+    h.close()
