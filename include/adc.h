@@ -274,10 +274,15 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
  * part in FP64 (as in adc_init), the sigma part in the handle's default
  * precision (FP64, FP32 or split-bf16 contractions), with every gradient
  * accumulated in complex128; dx is formed from two FP64 builds whatever the
- * precision.  The <ab||cd> gradient blocks of the particle-particle ladder
- * are formed per batch of a from L and never stored whole.  Device memory: about
- * twice that of adc_init plus one workspace batch.  Synchronous.  Errors:
- * INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR. */
+ * precision.  The first call on an instance keeps its recorded one-off part
+ * (with every buffer it wrote) until adc_free, so later calls record and
+ * differentiate only the sigma build on top of it; the kept part reflects L
+ * as the first call read it.  The <ab||cd> gradient blocks of the
+ * particle-particle ladder are formed per batch of a from L and never stored
+ * whole.  Device memory: about twice that of adc_init plus one workspace
+ * batch, the one-off part staying allocated between calls.  Synchronous.
+ * Errors: INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR (after an error the kept
+ * part is dropped and the next call records it again). */
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k,
                        void* dL, double* dx);
 
