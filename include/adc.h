@@ -117,7 +117,8 @@ typedef struct adc_problem {
  *                 device-to-host report per iteration; 2 = the same device
  *                 iteration launched kernel by kernel, sigma builds eager;
  *                 0 = host-driven iteration (subspace eigenproblem on the
- *                 host) [0].  Root following always runs host-driven.
+ *                 host) [0].  Root following, and subspaces of more than
+ *                 256 vectors, always run host-driven.
  *   autotune      1 = time the tile and split-K candidates of every GEMM
  *                 shape class once and keep the fastest [0]
  *   tune_cache    path of a text file of tuned GEMM choices (one shape class
