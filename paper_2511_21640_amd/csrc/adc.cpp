@@ -1858,42 +1858,54 @@ std::vector<double> row_norms2(Ctx& cx, const double2* X, int rows, int64_t dim)
 // one small report per iteration and then enqueues the sigma build of the
 // directions it keeps.
 // ---------------------------------------------------------------------------
-// K-chunks of a device Gram matrix over a vector length dim: about 512 parts
-// (enough workgroups for the chip), at least 4096 long
-int64_t gram_chunk(int64_t dim) { return std::max<int64_t>(4096, ((dim + 511) / 512 + 15) / 16 * 16); }
-int64_t gram_parts(int64_t dim) { return (dim + gram_chunk(dim) - 1) / gram_chunk(dim); }
+// K-chunks of a device Gram matrix over a vector length dim.  The products
+// are short (a few dozen rows) and long (dim), so one workgroup per chunk
+// walks its chunk with little in flight: about 2048 chunks keep ~6 of them on
+// every compute unit.  What is left after the whole chunks is cut again into
+// at most 64 pieces, and the last few elements make one more part, so no
+// single workgroup walks a long remainder.
+struct GramSplit {
+  int64_t chunk = 0, n1 = 0, chunk2 = 0, n2 = 0, tail = 0;
+  int64_t parts() const { return n1 + n2 + (tail ? 1 : 0); }
+};
+GramSplit gram_split(int64_t dim) {
+  GramSplit g;
+  g.chunk = std::max<int64_t>(256, ((dim + 2047) / 2048 + 15) / 16 * 16);
+  g.n1 = dim / g.chunk;
+  const int64_t rem = dim - g.n1 * g.chunk;
+  g.chunk2 = std::max<int64_t>(16, ((rem + 63) / 64 + 15) / 16 * 16);
+  g.n2 = rem / g.chunk2;
+  g.tail = rem - g.n2 * g.chunk2;
+  return g;
+}
+int64_t gram_parts(int64_t dim) { return gram_split(dim).parts(); }
 
 // out[a][b] (row stride ldo) = sum_i conj(X[a][i]) Y[b][i] (ra x rb) on the
-// device, in FP64: per-chunk products into part, then their sum
+// device, in FP64: per-chunk products into part, then their sum (through
+// stage when there are many parts)
 void gram_dev(Ctx& cx, const double2* X, int ra, const double2* Y, int rb, int64_t dim, double2* part,
-              double2* out, int ldo) {
-  const int64_t chunk = gram_chunk(dim);
-  const int64_t nsplit = dim / chunk;
-  const int64_t rem = dim - nsplit * chunk;
-  const int64_t nparts = nsplit + (rem ? 1 : 0);
+              double2* stage, double2* out, int ldo) {
+  const GramSplit sp = gram_split(dim);
   // a few columns: the 32-wide tiles
   const int tile = rb <= 32 ? (ra <= 64 ? 4 : 3) : 0;
-  if (nsplit) {
+  int64_t at = 0, p0 = 0;
+  auto launch = [&](int64_t len, int64_t nb) {
+    if (nb <= 0 || len <= 0) return;
     GemmDesc g{};
-    g.M = ra; g.N = rb; g.K = chunk; g.batch = nsplit;
-    g.A = X; g.sam = dim; g.sak = 1; g.sab = chunk; g.conjA = 1;
-    g.B = Y; g.sbk = 1; g.sbn = dim; g.sbb = chunk;
-    g.C = part; g.scm = rb; g.scn = 1; g.scb = (int64_t)ra * rb;
+    g.M = ra; g.N = rb; g.K = len; g.batch = nb;
+    g.A = X + at; g.sam = dim; g.sak = 1; g.sab = len; g.conjA = 1;
+    g.B = Y + at; g.sbk = 1; g.sbn = dim; g.sbb = len;
+    g.C = part + p0 * ra * rb; g.scm = rb; g.scn = 1; g.scb = (int64_t)ra * rb;
     g.alpha = C1(); g.beta = C0();
     g.tile = tile;
     launch_zgemm(g, 0, cx.stream);
-  }
-  if (rem) {
-    GemmDesc g{};
-    g.M = ra; g.N = rb; g.K = rem; g.batch = 1;
-    g.A = X + nsplit * chunk; g.sam = dim; g.sak = 1; g.sab = 0; g.conjA = 1;
-    g.B = Y + nsplit * chunk; g.sbk = 1; g.sbn = dim; g.sbb = 0;
-    g.C = part + nsplit * ra * rb; g.scm = rb; g.scn = 1; g.scb = 0;
-    g.alpha = C1(); g.beta = C0();
-    g.tile = tile;
-    launch_zgemm(g, 0, cx.stream);
-  }
-  launch_sum_parts(part, (int)nparts, ra, rb, out, ldo, cx.stream);
+    at += len * nb;
+    p0 += nb;
+  };
+  launch(sp.chunk, sp.n1);
+  launch(sp.chunk2, sp.n2);
+  launch(sp.tail, sp.tail ? 1 : 0);
+  launch_sum_parts(part, (int)p0, ra, rb, stage, out, ldo, cx.stream);
 }
 
 // Out[r][i] = alpha sum_a C[a][r] In[a][i] + beta Out[r][i], C a device matrix
@@ -1908,7 +1920,7 @@ struct DevDav {
   int64_t dim = 0;
   double2 *N = nullptr, *T = nullptr;                  // new directions [k][dim], temporary [2k][dim]
   double2 *G = nullptr, *U = nullptr, *Aw = nullptr, *Vw = nullptr;  // [mmax][mmax]
-  double2 *gpart = nullptr, *rpart = nullptr;          // Gram and row-dot partial sums
+  double2 *gpart = nullptr, *gstage = nullptr, *rpart = nullptr;  // Gram partial sums, their first-stage sums, row dots
   double2 *rn2 = nullptr, *ra = nullptr, *rb = nullptr;  // row sums [k]
   double2 *Cc = nullptr, *Gn = nullptr, *Un = nullptr;   // [mmax][k], [k][k], [k][k]
   double *w = nullptr, *wn = nullptr, *wold = nullptr, *par = nullptr, *rep = nullptr;
@@ -1948,7 +1960,9 @@ void devdav_setup(Ctx& cx, DevDav& D, int k, int mmax, int64_t dim) {
   D.U = take(mm);
   D.Aw = take(mm);
   D.Vw = take(mm);
-  D.gpart = take(nparts * mm);
+  // every Gram product here has at most mmax rows and k columns
+  D.gpart = take(nparts * mmax * k);
+  D.gstage = take((int64_t)sum_parts_slices((int)nparts) * mmax * k);
   D.rpart = take((int64_t)3 * k * D.nb);
   D.rn2 = take(k);
   D.ra = take(k);
@@ -1995,7 +2009,7 @@ void devdav_release(Ctx& cx, DevDav& D) {
 // Hermitian part is diagonalised): after the sigma build of rows c0 .. m.
 void devdav_gram_cols(Ctx& cx, DevDav& D, const double2* V, const double2* S, int c0, int m) {
   if (m <= c0) return;
-  gram_dev(cx, V, m, S + (int64_t)c0 * D.dim, m - c0, D.dim, D.gpart, D.G + c0, D.mmax);
+  gram_dev(cx, V, m, S + (int64_t)c0 * D.dim, m - c0, D.dim, D.gpart, D.gstage, D.G + c0, D.mmax);
   launch_gram_mirror(D.G, D.mmax, c0, m, cx.stream);
 }
 
@@ -2036,14 +2050,17 @@ void devdav_body(Ctx& cx, const Inst& I, DevDav& D, double2* V, double2* S, doub
   launch_collapse(collapse, D.U, m, m, mc, V, D.T, V, dim, s);
   launch_collapse(collapse, D.U, m, m, mc, S, D.T, S, dim, s);
   launch_gram_diag(collapse, D.w, mc, D.G, D.mmax, s);
+  // the first pass projects N and writes its orthonormal rows to T, the
+  // second projects T and writes them back to N
   for (int pass = 0; pass < 2; ++pass) {
-    gram_dev(cx, V, m, D.N, k, dim, D.gpart, D.Cc, k);  // Cc[a][b] = <V_a|N_b>
-    combine_dev(cx, D.Cc, k, m, k, V, D.N, dim, CR(-1), C1());
-    gram_dev(cx, D.N, k, D.N, k, dim, D.gpart, D.Gn, k);
+    double2* A = pass == 0 ? D.N : D.T;
+    double2* B = pass == 0 ? D.T : D.N;
+    gram_dev(cx, V, m, A, k, dim, D.gpart, D.gstage, D.Cc, k);  // Cc[a][b] = <V_a|A_b>
+    combine_dev(cx, D.Cc, k, m, k, V, A, dim, CR(-1), C1());
+    gram_dev(cx, A, k, A, k, dim, D.gpart, D.gstage, D.Gn, k);
     launch_heev_jacobi(D.Gn, k, k, D.Aw, D.Vw, D.mode(k), D.Un, k, D.wn, s);
     launch_canon(D.wn, D.Un, k, k, D.Cc, D.rep + 1 + 3 * k + pass, s);
-    combine_dev(cx, D.Cc, k, k, k, D.N, D.T, dim, C1(), C0());
-    hipcheck(hipMemcpyAsync(D.N, D.T, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, s), "orth");
+    combine_dev(cx, D.Cc, k, k, k, A, B, dim, C1(), C0());
   }
 }
 

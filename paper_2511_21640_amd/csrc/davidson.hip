@@ -202,6 +202,35 @@ __global__ void sum_parts_kernel(const double2* part, int nparts, int rows, int 
   out[(e / cols) * ldo + e % cols] = make_double2(sx, sy);
 }
 
+// First stage of a sum over many parts of n elements: slice ps of the grid's
+// y dimension sums parts ps, ps + nsl, ps + 2 nsl, ... into out[ps][e]; the
+// four waves of a workgroup take every fourth of them for the same 64
+// elements and are added in a fixed order
+__global__ __launch_bounds__(256) void sum_parts_stage_kernel(const double2* part, int nparts, int64_t n,
+                                                              double2* out) {
+  __shared__ double2 acc[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ps = blockIdx.y, nsl = gridDim.y;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  double sx = 0.0, sy = 0.0;
+  if (e < n)
+    for (int s = ps + nsl * wave; s < nparts; s += 4 * nsl) {
+      const double2 v = part[(int64_t)s * n + e];
+      sx += v.x;
+      sy += v.y;
+    }
+  acc[wave][lane] = make_double2(sx, sy);
+  __syncthreads();
+  if (wave == 0 && e < n) {
+    double2 r = acc[0][lane];
+    for (int w = 1; w < 4; ++w) {
+      r.x += acc[w][lane].x;
+      r.y += acc[w][lane].y;
+    }
+    out[(int64_t)ps * n + e] = r;
+  }
+}
+
 // G[j][a] = conj(G[a][j]) for c0 <= j < m, a < c0 (the rows of new columns)
 __global__ void gram_mirror_kernel(double2* G, int ldg, int c0, int m) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,16 +251,27 @@ __global__ void gram_diag_kernel(const double* flag, const double* w, int mc, do
   G[(int64_t)a * ldg + b] = make_double2(a == b ? w[a] : 0.0, 0.0);
 }
 
-// out[r] = sum_b partial[r * nb + b]
-__global__ void row_sums_kernel(const double2* partial, int nb, int rows, double2* out) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  double sx = 0.0, sy = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    sx += partial[(int64_t)r * nb + b].x;
-    sy += partial[(int64_t)r * nb + b].y;
+// out[r] = sum_b partial[r * nb + b]: one workgroup per row, a strided sum
+// per thread and a fixed-order tree over the workgroup
+__global__ __launch_bounds__(256) void row_sums_kernel(const double2* partial, int nb, double2* out) {
+  __shared__ double sx[256], sy[256];
+  const int r = blockIdx.x, t = threadIdx.x;
+  double ax = 0.0, ay = 0.0;
+  for (int b = t; b < nb; b += 256) {
+    ax += partial[(int64_t)r * nb + b].x;
+    ay += partial[(int64_t)r * nb + b].y;
   }
-  out[r] = make_double2(sx, sy);
+  sx[t] = ax;
+  sy[t] = ay;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      sx[t] += sx[t + w];
+      sy[t] += sy[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[r] = make_double2(sx[0], sy[0]);
 }
 
 // Convergence of the k roots: root r is converged when |r_r| <= par[0] and
@@ -416,8 +456,20 @@ void heev_allow_lds(size_t bytes) {
   (void)hipGetLastError();
 }
 
-void launch_sum_parts(const double2* part, int nparts, int rows, int cols, double2* out, int ldo, hipStream_t s) {
+int sum_parts_slices(int nparts) { return nparts > 64 ? 32 : 1; }
+
+void launch_sum_parts(const double2* part, int nparts, int rows, int cols, double2* stage, double2* out, int ldo,
+                      hipStream_t s) {
   const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return;
+  const int nsl = sum_parts_slices(nparts);
+  if (nsl > 1) {
+    if (!stage) throw HipError{hipErrorInvalidValue, "sum_parts: no staging buffer"};
+    hipLaunchKernelGGL(sum_parts_stage_kernel, dim3((unsigned)((n + 63) / 64), (unsigned)nsl), dim3(256), 0, s, part,
+                       nparts, n, stage);
+    part = stage;
+    nparts = nsl;
+  }
   hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nparts, rows, cols,
                      out, ldo);
 }
@@ -446,7 +498,8 @@ void launch_combine_cols(const double* flag, const double2* C, int ldc, int m, i
 }
 
 void launch_row_sums(const double2* partial, int nb, int rows, double2* out, hipStream_t s) {
-  hipLaunchKernelGGL(row_sums_kernel, dim3((rows + 63) / 64), dim3(64), 0, s, partial, nb, rows, out);
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(row_sums_kernel, dim3((unsigned)rows), dim3(256), 0, s, partial, nb, out);
 }
 
 void launch_dav_converge(const double* w, const double2* rn2, double* wold, int k, int m, int mmax,
@@ -459,7 +512,9 @@ void launch_collapse(const double* flag, const double2* U, int ldu, int m, int m
   launch_combine_cols(flag, U, ldu, m, mc, In, T, dim, {1.0, 0.0}, {0.0, 0.0}, s);
   const int64_t total = (int64_t)m * dim;
   int64_t g = (total + 255) / 256;
-  if (g > 65535LL * 16) g = 65535LL * 16;
+  // a grid-stride copy: a few thousand workgroups keep HBM busy when the
+  // flag is set and cost little to launch when it is not (the usual case)
+  if (g > 8192) g = 8192;
   hipLaunchKernelGGL(collapse_copy_kernel, dim3((unsigned)g), dim3(256), 0, s, flag, T, Out, m, mc, dim);
 }
 

@@ -260,8 +260,12 @@ size_t heev_static_lds();
 void heev_allow_lds(size_t bytes);
 void launch_heev_jacobi(const double2* G, int ldg, int n, double2* Aw, double2* Vw, int mode, double2* U, int ldu,
                         double* w, hipStream_t s);
-// out[r][c] (row stride ldo) = sum_s part[s][r][c] over rows x cols parts
-void launch_sum_parts(const double2* part, int nparts, int rows, int cols, double2* out, int ldo, hipStream_t s);
+// out[r][c] (row stride ldo) = sum_s part[s][r][c] over rows x cols parts;
+// above 64 parts in two stages through stage [sum_parts_slices(nparts)][rows
+// x cols] (a fixed summation order either way)
+int sum_parts_slices(int nparts);
+void launch_sum_parts(const double2* part, int nparts, int rows, int cols, double2* stage, double2* out, int ldo,
+                      hipStream_t s);
 // G[j][a] = conj(G[a][j]) for c0 <= j < m, a < c0
 void launch_gram_mirror(double2* G, int ldg, int c0, int m, hipStream_t s);
 // when *flag != 0: G[0:mc][0:mc] = diag(w[0:mc])
