@@ -98,8 +98,11 @@ typedef struct adc_problem {
  *   mem_budget    bytes of device workspace: sizes the <ab||cd> batches,
  *                 the largest temporary copy a contraction may make before it
  *                 is split into pieces, and how many trial vectors one pass
- *                 of the unpacked-doubles terms takes [0 = 4 GiB batches,
- *                 8 GiB copies, 16 GiB per pass]; results do not depend on it
+ *                 of the unpacked-doubles terms takes, and a quarter of it
+ *                 the packed <ab||cd> rows contracted at once [0 = 4 GiB
+ *                 batches, 8 GiB copies, 16 GiB per pass, and in split-bf16
+ *                 all packed rows at once when they take at most 16 GiB];
+ *                 results do not depend on it beyond rounding
  *   verbose       1 = one line per Davidson iteration on stderr; 2 = also
  *                 one line per GEMM launch (shape, tile, split, output map)
  *   n_streams     several instances: number of lanes (device streams, each
@@ -376,6 +379,12 @@ void adc_free(adc_handle* h);
 
 /* Static message for a status code. */
 const char* adc_strerror(int code);
+
+/* Detail of the calling thread's most recent failed call on a handle
+ * (adc_init .. adc_sigma_backward): the check or step that failed and, for
+ * HIP errors, the runtime's message; "" when that call succeeded or gave no
+ * detail.  The text stays valid until the thread's next such call. */
+const char* adc_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -26,7 +26,7 @@ ERRORS = {-1: "INVALID_ARG", -2: "NONFINITE_INPUT", -3: "NOT_HERMITIAN", -4: "OU
 # Every symbol include/adc.h declares.
 EXPORTS = ["adc_init", "adc_dims", "adc_sigma", "adc_sigma_term", "adc_sigma_noalloc", "adc_davidson",
            "adc_sigma_backward", "adc_properties", "adc_fns", "adc_cholesky", "adc_cholesky_mo", "adc_init_ms",
-           "adc_free", "adc_strerror"]
+           "adc_free", "adc_strerror", "adc_last_error"]
 TERMS = {"all": 0, "ladder": 1}
 
 
@@ -62,7 +62,11 @@ def _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, m
 class AdcError(RuntimeError):
     def __init__(self, code, what=""):
         self.code = code
-        super().__init__(f"{what}: {ERRORS.get(code, code)}")
+        detail = ""
+        if _lib is not None:
+            d = _lib.adc_last_error()
+            detail = f" ({d.decode(errors='replace')})" if d else ""
+        super().__init__(f"{what}: {ERRORS.get(code, code)}{detail}")
 
 
 _lib = None
@@ -108,6 +112,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.adc_free.restype = None
     lib.adc_strerror.argtypes = [ctypes.c_int]
     lib.adc_strerror.restype = ctypes.c_char_p
+    lib.adc_last_error.argtypes = []
+    lib.adc_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 

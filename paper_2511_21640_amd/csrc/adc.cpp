@@ -116,6 +116,7 @@ struct Inst {
     std::vector<double2*> held;  // workspace blocks reserved for the graph
   };
   std::vector<Graph> graphs;
+  bool graphs_off = false;  // a capture failed: sigma builds run eagerly
   // allocation-free sigma builds: the smallest row count per precision that
   // did not fit the scratch (0 = none seen)
   int noalloc_too_big[3] = {0, 0, 0};
@@ -326,11 +327,15 @@ void ladder(adc_handle* h, Inst& I, const double2* Y, int64_t ldY, int64_t offY,
   }
   // packed <ab||cd> rows of several a-blocks are collected (up to a quarter of
   // the workspace) and contracted with the trial vectors in one GEMM, so that
-  // the contraction runs on large N even where the a-blocks are small
+  // the contraction runs on large N even where the a-blocks are small; in
+  // split-bf16 without an explicit budget, all rows are taken as one group
+  // whenever their planes fit 16 GiB, which enables the Hermitian half below
   const int64_t Kv = pad32(Pv);
   const int64_t row_bytes = bf ? Kv * 8 : Pv * (int64_t)sizeof(double2);
   const int64_t max_np = (int64_t)nb * (v - 1);
-  const int64_t grp = std::min<int64_t>(Pv, std::max<int64_t>(max_np, (int64_t)(budget / 4) / row_bytes));
+  const bool one_group = bf && !cx.ws_override && !h->opt.mem_budget && Pv * row_bytes <= ((int64_t)16 << 30);
+  const size_t gbudget = one_group ? (size_t)(Pv * row_bytes) : budget / 4;
+  const int64_t grp = std::min<int64_t>(Pv, std::max<int64_t>(max_np, (int64_t)gbudget / row_bytes));
   unsigned short* Yp = nullptr;
   unsigned short* Vp = nullptr;
   double2* Vbuf = nullptr;
@@ -1676,7 +1681,7 @@ double inst_cost(const Inst& I) {
 void sigma_call(adc_handle* h, Inst& I, const double2* Y, double2* S, int rows, int prec) {
   Ctx& cx = *I.cx;
   if (rows <= 0) return;
-  if (h->opt.graphs != 1 || inst_cost(I) > kGraphMaxCost) {
+  if (h->opt.graphs != 1 || inst_cost(I) > kGraphMaxCost || I.graphs_off) {
     sigma_dispatch(h, I, Y, S, rows, prec);
     return;
   }
@@ -1694,29 +1699,44 @@ void sigma_call(adc_handle* h, Inst& I, const double2* Y, double2* S, int rows, 
     sigma_dispatch(h, I, ng.Yin, ng.Sout, rows, prec);  // warm-up: workspace, planes, tuning
     hipcheck(hipStreamSynchronize(cx.stream), "graph warm");
     cx.pool.begin_hold();
-    hipError_t e = hipStreamBeginCapture(cx.stream, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) {
-      try {
-        sigma_dispatch(h, I, ng.Yin, ng.Sout, rows, prec);
-      } catch (...) {
-        hipGraph_t dead = nullptr;
-        (void)hipStreamEndCapture(cx.stream, &dead);
-        if (dead) (void)hipGraphDestroy(dead);
-        for (double2* p : cx.pool.end_hold()) cx.pool.put(p);
-        throw;
+    hipError_t e;
+    {
+      std::shared_lock<std::shared_mutex> gate(capture_gate());
+      e = hipStreamBeginCapture(cx.stream, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) {
+        try {
+          sigma_dispatch(h, I, ng.Yin, ng.Sout, rows, prec);
+        } catch (const HipError& err) {
+          e = err.e;
+        } catch (...) {
+          hipGraph_t dead = nullptr;
+          (void)hipStreamEndCapture(cx.stream, &dead);
+          if (dead) (void)hipGraphDestroy(dead);
+          for (double2* p : cx.pool.end_hold()) cx.pool.put(p);
+          throw;
+        }
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cx.stream, &g);
+        if (e == hipSuccess) e = ee;
+        if (e == hipSuccess) ng.g = g;
+        else if (g) (void)hipGraphDestroy(g);
       }
-      e = hipStreamEndCapture(cx.stream, &ng.g);
     }
     ng.held = cx.pool.end_hold();
     if (e == hipSuccess) e = hipGraphInstantiate(&ng.ex, ng.g, nullptr, nullptr, 0);
+    // the warm-up already holds this call's result
     if (e != hipSuccess) {
+      // no graph (e.g. no memory for the capture's own blocks): this
+      // instance's sigma builds run eagerly from now on
+      (void)hipGetLastError();
       if (ng.g) (void)hipGraphDestroy(ng.g);
       for (double2* p : ng.held) cx.pool.put(p);
-      hipcheck(e, "graph capture");
+      I.graphs_off = true;
+      hipcheck(hipMemcpyAsync(S, ng.Sout, bytes, hipMemcpyDeviceToDevice, cx.stream), "graph out");
+      return;
     }
     I.graphs.push_back(std::move(ng));
     G = &I.graphs.back();
-    // the warm-up already holds this call's result
     hipcheck(hipMemcpyAsync(S, G->Sout, bytes, hipMemcpyDeviceToDevice, cx.stream), "graph out");
     return;
   }
@@ -1926,6 +1946,7 @@ struct DevDav {
   double *w = nullptr, *wn = nullptr, *wold = nullptr, *par = nullptr, *rep = nullptr;
   double* rep_host = nullptr;  // the lane's page-locked buffer
   int lds_max = 0;             // dynamic LDS bytes the eigensolver may take
+  bool capture_off = false;    // a capture failed: iterate launch by launch
   struct Graph {
     int m = 0;
     hipGraph_t g = nullptr;
@@ -2068,7 +2089,7 @@ void devdav_body(Ctx& cx, const Inst& I, DevDav& D, double2* V, double2* S, doub
 // capture is on, capturing it on first use) and reads the report.
 void devdav_step(Ctx& cx, const Inst& I, DevDav& D, bool capture, double2* V, double2* S, double2* X, double2* AX,
                  double2* R, int m) {
-  if (!capture) {
+  if (!capture || D.capture_off) {
     devdav_body(cx, I, D, V, S, X, AX, R, m);
   } else {
     DevDav::Graph* G = nullptr;
@@ -2078,30 +2099,44 @@ void devdav_step(Ctx& cx, const Inst& I, DevDav& D, bool capture, double2* V, do
       DevDav::Graph ng;
       ng.m = m;
       cx.pool.begin_hold();
-      hipError_t e = hipStreamBeginCapture(cx.stream, hipStreamCaptureModeRelaxed);
-      if (e == hipSuccess) {
-        try {
-          devdav_body(cx, I, D, V, S, X, AX, R, m);
-        } catch (...) {
-          hipGraph_t dead = nullptr;
-          (void)hipStreamEndCapture(cx.stream, &dead);
-          if (dead) (void)hipGraphDestroy(dead);
-          for (double2* p : cx.pool.end_hold()) cx.pool.put(p);
-          throw;
+      hipError_t e;
+      {
+        std::shared_lock<std::shared_mutex> gate(capture_gate());
+        e = hipStreamBeginCapture(cx.stream, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+          try {
+            devdav_body(cx, I, D, V, S, X, AX, R, m);
+          } catch (const HipError& err) {
+            e = err.e;
+          } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(cx.stream, &dead);
+            if (dead) (void)hipGraphDestroy(dead);
+            for (double2* p : cx.pool.end_hold()) cx.pool.put(p);
+            throw;
+          }
+          hipGraph_t g = nullptr;
+          const hipError_t ee = hipStreamEndCapture(cx.stream, &g);
+          if (e == hipSuccess) e = ee;
+          if (e == hipSuccess) ng.g = g;
+          else if (g) (void)hipGraphDestroy(g);
         }
-        e = hipStreamEndCapture(cx.stream, &ng.g);
       }
       ng.held = cx.pool.end_hold();
       if (e == hipSuccess) e = hipGraphInstantiate(&ng.ex, ng.g, nullptr, nullptr, 0);
       if (e != hipSuccess) {
+        // no graph: this solve's iterations run launch by launch from now on
+        (void)hipGetLastError();
         if (ng.g) (void)hipGraphDestroy(ng.g);
         for (double2* p : ng.held) cx.pool.put(p);
-        hipcheck(e, "iteration capture");
+        D.capture_off = true;
+        devdav_body(cx, I, D, V, S, X, AX, R, m);
+      } else {
+        D.graphs.push_back(std::move(ng));
+        G = &D.graphs.back();
       }
-      D.graphs.push_back(std::move(ng));
-      G = &D.graphs.back();
     }
-    hipcheck(hipGraphLaunch(G->ex, cx.stream), "iteration graph");
+    if (G) hipcheck(hipGraphLaunch(G->ex, cx.stream), "iteration graph");
   }
   hipcheck(hipMemcpyAsync(D.rep_host, D.rep, sizeof(double) * D.rep_len(), hipMemcpyDeviceToHost, cx.stream),
            "report");
@@ -2660,20 +2695,32 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
   cx.prec = saved_prec;
 }
 
+// detail of the calling thread's last failed call (adc_last_error)
+thread_local std::string g_last_error;
+
 template <class F>
 int guarded(F&& f) {
   try {
+    g_last_error.clear();
     return f();
   } catch (const Status& s) {
+    g_last_error = s.msg ? s.msg : "";
     return s.code;
   } catch (const HipError& e) {
     (void)hipGetLastError();
+    g_last_error = std::string(e.where ? e.where : "") + ": " + hipGetErrorString(e.e);
     return e.e == hipErrorOutOfMemory ? ADC_ERR_OUT_OF_MEMORY : ADC_ERR_HIP;
   } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
     return ADC_ERR_OUT_OF_MEMORY;
-  } catch (const std::invalid_argument&) {
+  } catch (const std::invalid_argument& e) {
+    g_last_error = e.what();
     return ADC_ERR_INVALID_ARG;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return ADC_ERR_HIP;
   } catch (...) {
+    g_last_error = "unknown exception";
     return ADC_ERR_HIP;
   }
 }
@@ -3005,19 +3052,26 @@ void lane_wait(adc_handle* h, Ctx& lane, bool before) {
 extern "C" {
 
 int adc_init(const adc_problem* problems, int n_problems, const adc_options* opts, adc_handle** out) {
-  if (!out) return ADC_ERR_INVALID_ARG;
+  g_last_error.clear();
+  auto fail = [](int code, const char* msg) {
+    g_last_error = msg;
+    return code;
+  };
+  if (!out) return fail(ADC_ERR_INVALID_ARG, "no output handle");
   *out = nullptr;
-  if (!problems || n_problems < 1) return ADC_ERR_INVALID_ARG;
-  if (opts && (opts->precision < 0 || opts->precision > 2)) return ADC_ERR_INVALID_ARG;
-  if (opts && opts->precision == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
-  if (opts && opts->n_streams < 0) return ADC_ERR_INVALID_ARG;
-  if (opts && (opts->graphs < 0 || opts->graphs > 2)) return ADC_ERR_INVALID_ARG;
+  if (!problems || n_problems < 1) return fail(ADC_ERR_INVALID_ARG, "no problems");
+  if (opts && (opts->precision < 0 || opts->precision > 2))
+    return fail(ADC_ERR_INVALID_ARG, "precision must be ADC_FP64, ADC_FP32 or ADC_SPLIT_BF16");
+  if (opts && opts->precision == ADC_SPLIT_BF16 && !kSplitBf16Built)
+    return fail(ADC_ERR_UNSUPPORTED, "split-bf16 kernels not built");
+  if (opts && opts->n_streams < 0) return fail(ADC_ERR_INVALID_ARG, "n_streams < 0");
+  if (opts && (opts->graphs < 0 || opts->graphs > 2)) return fail(ADC_ERR_INVALID_ARG, "graphs must be 0, 1 or 2");
   for (int i = 0; i < n_problems; ++i) {
     int rc = validate(&problems[i]);
-    if (rc) return rc;
+    if (rc) return fail(rc, "problem description rejected (kind, sizes, eps, L or x)");
     if (!problems[i].L_on_device) {
       rc = validate_L_host((const double*)problems[i].L, problems[i].n_chol, problems[i].n_occ + problems[i].n_vir);
-      if (rc) return rc;
+      if (rc) return fail(rc, "host L is non-finite or not Hermitian in (p,q)");
     }
   }
   adc_handle* h = nullptr;
@@ -3092,6 +3146,7 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
 }
 
 int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2) {
+  g_last_error.clear();
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !n1 || !n2) return ADC_ERR_INVALID_ARG;
   *n1 = h->inst[inst].n1;
   *n2 = h->inst[inst].n2;
@@ -3099,6 +3154,7 @@ int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2) {
 }
 
 int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precision) {
+  g_last_error.clear();
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
   if (precision > 2) return ADC_ERR_INVALID_ARG;
   const int prec = precision < 0 ? h->opt.precision : precision;
@@ -3114,6 +3170,7 @@ int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precis
 }
 
 int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, int k, int precision) {
+  g_last_error.clear();
   if (term == ADC_TERM_ALL) return adc_sigma(h, inst, Y, S, k, precision);
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
   if (precision > 2 || term != ADC_TERM_LADDER) return ADC_ERR_INVALID_ARG;
@@ -3132,6 +3189,7 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
 }
 
 int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, int precision) {
+  g_last_error.clear();
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
   if (precision > 2) return ADC_ERR_INVALID_ARG;
   const int prec = precision < 0 ? h->opt.precision : precision;
@@ -3184,6 +3242,7 @@ int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, in
 
 int adc_properties(adc_handle* h, int inst, const void* Y, int k, void* rho, void* tdm, const void* d, double* dk,
                    double* tk) {
+  g_last_error.clear();
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || k < 1) return ADC_ERR_INVALID_ARG;
   if ((dk || tk) && !d) return ADC_ERR_INVALID_ARG;
   Inst& I = h->inst[inst];
@@ -3199,6 +3258,7 @@ int adc_properties(adc_handle* h, int inst, const void* Y, int k, void* rho, voi
 
 int adc_fns(adc_handle* h, int inst, const void* X, double eta_crit, int* n_vir, double* eps_out, void* L_out,
             double* eta_out, void* B_out, void* X_out) {
+  g_last_error.clear();
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !n_vir || !eps_out || !L_out || !std::isfinite(eta_crit))
     return ADC_ERR_INVALID_ARG;
   Inst& I = h->inst[inst];
@@ -3216,6 +3276,7 @@ int adc_fns(adc_handle* h, int inst, const void* X, double eta_crit, int* n_vir,
 
 int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs, double* resnorm,
                  int* iters, int* converged) {
+  g_last_error.clear();
   if (!h || !omega || !resnorm || !iters || !converged) return ADC_ERR_INVALID_ARG;
   // offsets of each instance's roots in the concatenated outputs
   std::vector<int64_t> off(h->inst.size() + 1, 0);
@@ -3240,6 +3301,7 @@ int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* c
 }
 
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k, void* dL, double* dx) {
+  g_last_error.clear();
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !Sbar || !Y || k < 0) return ADC_ERR_INVALID_ARG;
   return guarded([&]() {
     Inst& I = h->inst[inst];
@@ -3276,10 +3338,15 @@ void adc_free(adc_handle* h) {
     if (c->stream) (void)hipStreamDestroy(c->stream);
   }
   h->cx.pool.release_all();
-  for (void* p : h->raw) (void)hipFree(p);
+  if (!h->raw.empty()) {
+    std::unique_lock<std::shared_mutex> gate(capture_gate());
+    for (void* p : h->raw) (void)hipFree(p);
+  }
   if (h->own_stream && h->cx.stream) (void)hipStreamDestroy(h->cx.stream);
   delete h;
 }
+
+const char* adc_last_error(void) { return g_last_error.c_str(); }
 
 const char* adc_strerror(int code) {
   switch (code) {

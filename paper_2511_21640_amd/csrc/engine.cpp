@@ -20,6 +20,11 @@
 namespace adc {
 
 // ------------------------------------------------------------------ pool
+std::shared_mutex& capture_gate() {
+  static std::shared_mutex gate;
+  return gate;
+}
+
 Pool::~Pool() { release_all(); }
 
 double2* Pool::get(int64_t n) {
@@ -70,10 +75,16 @@ double2* Pool::get(int64_t n) {
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
-      // drop cached blocks and retry once
       (void)hipGetLastError();
-      (void)hipDeviceSynchronize();
-      for (auto& f : free_) (void)hipFree(f.p);
+      // while this pool's stream is being captured nothing may wait on the
+      // device: report the shortage (the caller then runs the step eagerly)
+      if (hold_) throw HipError{hipErrorOutOfMemory, "pool (during graph capture)"};
+      // drop cached blocks and retry once
+      {
+        std::unique_lock<std::shared_mutex> lk(capture_gate());
+        (void)hipDeviceSynchronize();
+        for (auto& f : free_) (void)hipFree(f.p);
+      }
       free_.clear();
       e = hipMalloc(&p, bytes);
       if (e != hipSuccess) throw HipError{hipErrorOutOfMemory, "pool"};
@@ -168,13 +179,19 @@ void Pool::put(double2* p) {
 }
 
 void Pool::trim() {
-  for (auto& b : free_) (void)hipFree(b.p);
+  if (!free_.empty()) {
+    std::unique_lock<std::shared_mutex> lk(capture_gate());
+    for (auto& b : free_) (void)hipFree(b.p);
+  }
   free_.clear();
 }
 
 void Pool::release_all() {
-  for (auto& b : free_) (void)hipFree(b.p);
-  for (auto& b : used_) (void)hipFree(b.p);
+  if (!free_.empty() || !used_.empty()) {
+    std::unique_lock<std::shared_mutex> lk(capture_gate());
+    for (auto& b : free_) (void)hipFree(b.p);
+    for (auto& b : used_) (void)hipFree(b.p);
+  }
   free_.clear();
   used_.clear();
   in_use_ = 0;

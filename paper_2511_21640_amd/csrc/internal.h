@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -314,6 +315,13 @@ struct Tape;
 struct ArenaFull {
   size_t need;
 };
+
+// Calls that synchronise the whole device (hipDeviceSynchronize, hipFree)
+// must not run while another thread records a stream into a graph: such a
+// call would wait on the capturing stream and break its capture.  Captures
+// hold this gate shared (several lanes may capture at once), those calls
+// hold it exclusively.
+std::shared_mutex& capture_gate();
 
 class Pool {
  public:

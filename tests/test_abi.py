@@ -85,6 +85,8 @@ def test_validation_errors(lib):
     opts = adc.AdcOptions()
     opts.precision = 3
     assert lib.adc_init(arr, 1, ctypes.byref(opts), ctypes.byref(h)) == -1
+    # the failed call leaves its detail for the calling thread
+    assert isinstance(lib.adc_last_error(), bytes) and len(lib.adc_last_error()) > 0
 
 
 def test_strerror(lib):
