@@ -94,6 +94,37 @@ def time_calls(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+# The three largest split-bf16 products of the C2 build as complex shapes
+# (M, N, K): a complex MAC in split-bf16 is 12 real bf16 products, i.e. the
+# same flop as one real bf16 GEMM of M x 2N x 6K
+VENDOR_SHAPES = [("ring product", 19200, 2400, 2400),
+                 ("ladder contraction", 1520, 7140, 7168),
+                 ("ladder assembly, largest block", 1920, 14280, 928)]
+
+
+def vendor_gemm(steps, warmup):
+    """Times torch's bf16 matmul (hipBLASLt) on the real GEMMs with the flop of
+    the build's largest split-bf16 products, for comparison with this
+    library's kernels in the same run (a measurement aid; no part of the
+    library uses it)."""
+    import torch
+    out = []
+    stream = torch.cuda.current_stream()
+    for name, M, N, K in VENDOR_SHAPES:
+        A = torch.randn(M, 6 * K, device="cuda", dtype=torch.bfloat16)
+        Bt = torch.randn(2 * N, 6 * K, device="cuda", dtype=torch.bfloat16)
+        C = torch.empty(M, 2 * N, device="cuda", dtype=torch.bfloat16)
+        ms = time_calls(lambda: torch.matmul(A, Bt.t(), out=C), steps, warmup, stream)
+        fl = 24.0 * M * N * K
+        out.append({"product": name, "complex_MNK": [M, N, K], "real_bf16_MNK": [M, 2 * N, 6 * K],
+                    "ms": ms, "tflops": fl / ms / 1e9})
+        print(f"[bench] vendor bf16 GEMM for the {name} ({M}x{2 * N}x{6 * K}): {ms:.3f} ms, "
+              f"{fl / ms / 1e9:.0f} TFLOP/s", file=sys.stderr, flush=True)
+        del A, Bt, C
+    torch.cuda.empty_cache()
+    return out
+
+
 def oracle_build(P, X):
     """The oracle's matrix-free FP64 sigma (every block and order, M11
     included) of the rows of X on the host: (S, seconds of the integral and
@@ -327,6 +358,9 @@ def main():
                     help="time only the sigma build at --precision (for kernel traces)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--vendor-gemm", action="store_true",
+                    help="with --only-sigma: also time torch's bf16 GEMM (hipBLASLt) on the flop of the build's "
+                         "largest split-bf16 products")
     ap.add_argument("--c4", type=int, default=0,
                     help="instead: batched solve of the first N instances of the 64-instance draw")
     ap.add_argument("--c4-budget-gb", type=float, default=200.0)
@@ -375,6 +409,8 @@ def main():
     print(f"[bench] {args.precision} sigma {ms:.2f} ms/build", file=sys.stderr, flush=True)
     if args.only_sigma:
         h.close()
+        if args.vendor_gemm:
+            print(json.dumps({"vendor_gemm": vendor_gemm(args.steps, args.warmup)}))
         return
     ms64 = time_calls(lambda: h.sigma(Y, S, precision="fp64"), max(3, args.steps // 2), 1, stream)
     print(f"[bench] fp64 sigma {ms64:.2f} ms/build", file=sys.stderr, flush=True)

@@ -129,3 +129,28 @@ def test_device_iteration_matches_eager(graphs, max_subspace):
             assert np.abs(r["omega"] - ra[i]["omega"]).max() <= 1e-8, (i, r["omega"], ra[i]["omega"])
             assert np.abs(r["omega"] - w).max() <= 1e-8, (i, r["omega"], w)
             assert r["resnorm"].max() <= 1e-8
+
+
+def test_device_iteration_long_vectors():
+    """Vectors long enough for the device Gram products to take more than 64
+    parts (their partial sums then add up in two stages) and a cut remainder:
+    the captured device iteration gives the host-driven solve's roots."""
+    probs = [make_problem("EE", 8, 40, 96, seed=815, n_roots=4, x=0.5),
+             make_problem("EA", 14, 50, 128, seed=816, n_roots=3, x=1.0)]
+    for P in probs:
+        print(f"case device iteration long vectors {P.kind} o={P.o} v={P.v}", flush=True)
+    kw = dict(precision="fp64", conv_tol=1e-8, n_streams=2, max_iter=300)
+    A = adc.Batch([_spec(P) for P in probs], **kw)
+    ra, rca = A.davidson()
+    A.close()
+    G = adc.Batch([_spec(P) for P in probs], graphs=True, **kw)
+    assert min(G.dims) > 16 * 1024
+    rg, rcg = G.davidson()
+    G.close()
+    assert rca == 0 and rcg == 0
+    for i in range(len(probs)):
+        print(f"  instance {i}: dim {G.dims[i]}, iters eager {ra[i]['iters']} device {rg[i]['iters']}, "
+              f"max |dw| {np.abs(rg[i]['omega'] - ra[i]['omega']).max():.1e}", flush=True)
+        assert rg[i]["converged"].all()
+        assert np.abs(rg[i]["omega"] - ra[i]["omega"]).max() <= 1e-8
+        assert rg[i]["resnorm"].max() <= 1e-8
