@@ -9,7 +9,10 @@ size.
   bench.py times;
 * C3-EA: sampled rows of the particle-particle ladder, each <ab||cd> row formed
   by the oracle from L on its own; Hermiticity of the whole sigma;
-* C3-IP: Hermiticity of the whole sigma.
+* C3-IP: Hermiticity of the whole sigma, and at x = 0 whole columns of M
+  (unit doubles vectors: the first-order coupling in the singles, the
+  diagonal in the doubles), each from the oracle on the sub-problem of the
+  orbitals that column involves.
 """
 import numpy as np
 import pytest
@@ -123,3 +126,55 @@ def test_c3_ip_hermiticity():
     print("case C3-IP hermiticity", flush=True)
     h = adc.Handle("IP", P.o, P.v, P.eps, P.L, P.n_roots, x=P.x)
     assert _herm_check(h, np.random.default_rng(31)) < 1e-13
+
+
+def _pidx(k, l, n):
+    """Packed position of the pair k < l among n orbitals."""
+    return k * (2 * n - k - 1) // 2 + (l - k - 1)
+
+
+def test_c3_ip_coupling_columns_at_x0():
+    """C3-IP at x = 0 (ADC(2), Section 2.1 eq. 10): for a unit doubles vector
+    e_d, d = (k<l, b), the build returns column d of M: the first-order
+    coupling M12[:, d] in the singles, D_d = e_b - e_k - e_l at d and zero in
+    the rest of the doubles.  That column involves only the occupied orbitals
+    and the virtual b (each element one antisymmetrised integral, eq. 43), so
+    the oracle computes it on the sub-problem of those orbitals: all o
+    occupied and b alone as the virtual space."""
+    P = config_problem("C3-IP")
+    o, v = P.o, P.v
+    print("case C3-IP coupling columns at x=0", flush=True)
+    h = adc.Handle("IP", o, v, P.eps, P.L, P.n_roots, x=0.0)
+    cols = [(0, 1, 0), (17, 42, 399), (58, 59, 200), (3, 31, 123)]
+    pos = [o + _pidx(k, l, o) * v + b for (k, l, b) in cols]
+    Y = torch.zeros((len(cols), h.dim), dtype=torch.complex128)
+    for r, q in enumerate(pos):
+        Y[r, q] = 1.0
+    Y = Y.cuda()
+    S64 = h.sigma(Y, precision="fp64").cpu().numpy()
+    Sbf = h.sigma(Y, precision="split_bf16").cpu().numpy()
+    n1s, n2s = dims("IP", o, 1)
+    worst = worst_bf = 0.0
+    for r, (k, l, b) in enumerate(cols):
+        idx = list(range(o)) + [o + b]
+        sub = Ints(P.eps[idx], P.L[:, idx][:, :, idx], o)
+        Ys = np.zeros((1, n1s + n2s), dtype=np.complex128)
+        Ys[0, n1s + _pidx(k, l, o)] = 1.0
+        ref = sigma(sub, "IP", 0.0, Ys)[0]
+        D = P.eps[o + b] - P.eps[k] - P.eps[l]
+        # the oracle's own column: its diagonal entry is D_d
+        assert abs(ref[n1s + _pidx(k, l, o)] - D) < 1e-14 * abs(D)
+        scale = np.abs(ref[:o]).max()
+        assert scale > 0
+        worst = max(worst, np.abs(S64[r, :o] - ref[:o]).max() / scale)
+        worst_bf = max(worst_bf, np.abs(Sbf[r, :o] - ref[:o]).max() / scale)
+        for S in (S64, Sbf):
+            assert abs(S[r, pos[r]] - D) < 1e-12 * abs(D)
+            rest = S[r, o:].copy()
+            rest[pos[r] - o] = 0.0
+            assert np.abs(rest).max() == 0.0
+    print(f"C3-IP coupling columns: rel err fp64 {worst:.1e}, split-bf16 {worst_bf:.1e}", flush=True)
+    assert worst < 1e-12
+    # one split-bf16 product per coupling element (the stored integral class
+    # times the unit vector): each split carries at most 2^-16 relative error
+    assert worst_bf < 3e-5

@@ -133,3 +133,31 @@ def test_pairwise_contraction_equals_einsum():
                    for lab in spec.split("->")[0].split(",")]
             ref = np.einsum(spec, *ops)
             assert np.abs(contract(spec, *ops) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (kind, line)
+
+
+def test_ip_adc2_column_depends_only_on_its_orbitals():
+    """At x = 0 the IP column of a doubles basis state (k<l, b) holds the
+    first-order coupling and the zeroth-order diagonal only, so it is the
+    same column of the sub-problem with all occupied orbitals and b alone as
+    the virtual space (the reading the full-size C3-IP parity test relies
+    on).  Checked against the full problem at a small size."""
+    o, v = 5, 6
+    P = make_problem("IP", o, v, 30, seed=77, n_roots=2, x=0.0)
+    full = Ints(P.eps, P.L, o)
+    n1, n2 = dims("IP", o, v)
+    n1s, n2s = dims("IP", o, 1)
+    for (k, l, b) in [(0, 1, 0), (1, 4, 5), (2, 3, 2)]:
+        pk = k * (2 * o - k - 1) // 2 + (l - k - 1)
+        Y = np.zeros((1, n1 + n2), dtype=np.complex128)
+        Y[0, n1 + pk * v + b] = 1.0
+        col = sigma(full, "IP", 0.0, Y)[0]
+        idx = list(range(o)) + [o + b]
+        sub = Ints(P.eps[idx], P.L[:, idx][:, :, idx], o)
+        Ys = np.zeros((1, n1s + n2s), dtype=np.complex128)
+        Ys[0, n1s + pk] = 1.0
+        ref = sigma(sub, "IP", 0.0, Ys)[0]
+        assert np.abs(col[:o] - ref[:o]).max() <= 1e-13 * np.abs(col[:o]).max()
+        assert np.abs(col[:o]).max() > 1e-6
+        d = np.zeros(n2, dtype=np.complex128)
+        d[pk * v + b] = P.eps[o + b] - P.eps[k] - P.eps[l]
+        assert np.abs(col[n1:] - d).max() <= 1e-14
