@@ -9,10 +9,10 @@ size.
   bench.py times;
 * C3-EA: sampled rows of the particle-particle ladder, each <ab||cd> row formed
   by the oracle from L on its own; Hermiticity of the whole sigma;
-* C3-IP: Hermiticity of the whole sigma, and at x = 0 whole columns of M
-  (unit doubles vectors: the first-order coupling in the singles, the
-  diagonal in the doubles), each from the oracle on the sub-problem of the
-  orbitals that column involves.
+* C3-IP: Hermiticity of the whole sigma;
+* C3-IP and C3-EA at x = 0: whole columns of M (unit doubles vectors: the
+  first-order coupling in the singles, the diagonal in the doubles), each
+  from the oracle on the sub-problem of the orbitals that column involves.
 """
 import numpy as np
 import pytest
@@ -177,4 +177,52 @@ def test_c3_ip_coupling_columns_at_x0():
     assert worst < 1e-12
     # one split-bf16 product per coupling element (the stored integral class
     # times the unit vector): each split carries at most 2^-16 relative error
+    assert worst_bf < 3e-5
+
+
+def test_c3_ea_coupling_columns_at_x0():
+    """C3-EA at x = 0 (ADC(2), Section 2.1 eq. 10): for a unit doubles vector
+    e_d, d = (i, a<b), the build returns column d of M: the first-order
+    coupling M12[:, d] in the singles (from the stored three-external class),
+    D_d = e_a + e_b - e_i at d and zero in the rest of the doubles.  That
+    column involves only the occupied orbital i and the virtual orbitals, so
+    the oracle computes it on the sub-problem with i alone as the occupied
+    space (no <vv||vv> class is needed there)."""
+    P = config_problem("C3-EA")
+    o, v = P.o, P.v
+    Pv = v * (v - 1) // 2
+    print("case C3-EA coupling columns at x=0", flush=True)
+    h = adc.Handle("EA", o, v, P.eps, P.L, P.n_roots, x=0.0)
+    cols = [(0, 0, 1), (31, 17, 398), (59, 200, 201)]
+    pos = [v + i * Pv + _pidx(a, b, v) for (i, a, b) in cols]
+    Y = torch.zeros((len(cols), h.dim), dtype=torch.complex128)
+    for r, q in enumerate(pos):
+        Y[r, q] = 1.0
+    Y = Y.cuda()
+    S64 = h.sigma(Y, precision="fp64").cpu().numpy()
+    Sbf = h.sigma(Y, precision="split_bf16").cpu().numpy()
+    h.close()
+    n1s, n2s = dims("EA", 1, v)
+    worst = worst_bf = 0.0
+    for r, (i, a, b) in enumerate(cols):
+        idx = [i] + list(range(o, o + v))
+        sub = Ints(P.eps[idx], P.L[:, idx][:, :, idx], 1)
+        Ys = np.zeros((1, n1s + n2s), dtype=np.complex128)
+        Ys[0, n1s + _pidx(a, b, v)] = 1.0
+        ref = sigma(sub, "EA", 0.0, Ys)[0]
+        D = P.eps[o + a] + P.eps[o + b] - P.eps[i]
+        assert abs(ref[n1s + _pidx(a, b, v)] - D) < 1e-14 * abs(D)
+        scale = np.abs(ref[:v]).max()
+        assert scale > 0
+        worst = max(worst, np.abs(S64[r, :v] - ref[:v]).max() / scale)
+        worst_bf = max(worst_bf, np.abs(Sbf[r, :v] - ref[:v]).max() / scale)
+        for S in (S64, Sbf):
+            assert abs(S[r, pos[r]] - D) < 1e-12 * abs(D)
+            rest = S[r, v:].copy()
+            rest[pos[r] - v] = 0.0
+            assert np.abs(rest).max() == 0.0
+    print(f"C3-EA coupling columns: rel err fp64 {worst:.1e}, split-bf16 {worst_bf:.1e}", flush=True)
+    assert worst < 1e-12
+    # one split-bf16 product per coupling element: at most 2^-16 relative
+    # error per split
     assert worst_bf < 3e-5

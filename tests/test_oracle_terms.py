@@ -135,29 +135,45 @@ def test_pairwise_contraction_equals_einsum():
             assert np.abs(contract(spec, *ops) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (kind, line)
 
 
-def test_ip_adc2_column_depends_only_on_its_orbitals():
-    """At x = 0 the IP column of a doubles basis state (k<l, b) holds the
-    first-order coupling and the zeroth-order diagonal only, so it is the
-    same column of the sub-problem with all occupied orbitals and b alone as
-    the virtual space (the reading the full-size C3-IP parity test relies
-    on).  Checked against the full problem at a small size."""
-    o, v = 5, 6
-    P = make_problem("IP", o, v, 30, seed=77, n_roots=2, x=0.0)
+@pytest.mark.parametrize("kind", ["IP", "EA"])
+def test_adc2_column_depends_only_on_its_orbitals(kind):
+    """At x = 0 the column of a doubles basis state holds the first-order
+    coupling and the zeroth-order diagonal only, so it is the same column of
+    the sub-problem of the orbitals it involves: IP (k<l, b) all occupied
+    orbitals and b alone as the virtual space, EA (i, a<b) i alone as the
+    occupied space and all virtual orbitals (the reading the full-size C3
+    parity tests rely on).  Checked against the full problem at small sizes,
+    where the sub-problem must not need the <vv||vv> class."""
+    o, v = (5, 6) if kind == "IP" else (4, 7)
+    P = make_problem(kind, o, v, 30, seed=77, n_roots=2, x=0.0)
     full = Ints(P.eps, P.L, o)
-    n1, n2 = dims("IP", o, v)
-    n1s, n2s = dims("IP", o, 1)
-    for (k, l, b) in [(0, 1, 0), (1, 4, 5), (2, 3, 2)]:
-        pk = k * (2 * o - k - 1) // 2 + (l - k - 1)
+    n1, n2 = dims(kind, o, v)
+    Pv = v * (v - 1) // 2
+    # IP (k, l, b) with k < l; EA (i, a, b) with a < b
+    states = [(0, 1, 0), (1, 3, 5), (2, 3, 2)] if kind == "IP" else [(0, 2, 3), (1, 4, 6), (2, 4, 5)]
+    for (p, q, r) in states:
+        if kind == "IP":
+            pk = p * (2 * o - p - 1) // 2 + (q - p - 1)
+            pos, pos_sub = pk * v + r, pk
+            idx, o_sub = list(range(o)) + [o + r], o
+            D = P.eps[o + r] - P.eps[p] - P.eps[q]
+        else:
+            i, a, b = p, q, r
+            pab = a * (2 * v - a - 1) // 2 + (b - a - 1)
+            pos, pos_sub = i * Pv + pab, pab
+            idx, o_sub = [i] + list(range(o, o + v)), 1
+            D = P.eps[o + a] + P.eps[o + b] - P.eps[i]
         Y = np.zeros((1, n1 + n2), dtype=np.complex128)
-        Y[0, n1 + pk * v + b] = 1.0
-        col = sigma(full, "IP", 0.0, Y)[0]
-        idx = list(range(o)) + [o + b]
-        sub = Ints(P.eps[idx], P.L[:, idx][:, :, idx], o)
+        Y[0, n1 + pos] = 1.0
+        col = sigma(full, kind, 0.0, Y)[0]
+        sub = Ints(P.eps[idx], P.L[:, idx][:, :, idx], o_sub)
+        n1s, n2s = dims(kind, o_sub, len(idx) - o_sub)
         Ys = np.zeros((1, n1s + n2s), dtype=np.complex128)
-        Ys[0, n1s + pk] = 1.0
-        ref = sigma(sub, "IP", 0.0, Ys)[0]
-        assert np.abs(col[:o] - ref[:o]).max() <= 1e-13 * np.abs(col[:o]).max()
-        assert np.abs(col[:o]).max() > 1e-6
+        Ys[0, n1s + pos_sub] = 1.0
+        ref = sigma(sub, kind, 0.0, Ys)[0]
+        assert np.abs(col[:n1] - ref[:n1]).max() <= 1e-13 * np.abs(col[:n1]).max()
+        assert np.abs(col[:n1]).max() > 1e-6
         d = np.zeros(n2, dtype=np.complex128)
-        d[pk * v + b] = P.eps[o + b] - P.eps[k] - P.eps[l]
+        d[pos] = D
         assert np.abs(col[n1:] - d).max() <= 1e-14
+        assert "vvvv" not in sub._g
