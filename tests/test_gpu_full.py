@@ -153,6 +153,7 @@ def test_c3_ip_coupling_columns_at_x0():
     Y = Y.cuda()
     S64 = h.sigma(Y, precision="fp64").cpu().numpy()
     Sbf = h.sigma(Y, precision="split_bf16").cpu().numpy()
+    h.close()
     n1s, n2s = dims("IP", o, 1)
     worst = worst_bf = 0.0
     for r, (k, l, b) in enumerate(cols):
