@@ -141,7 +141,13 @@ typedef struct adc_problem {
  *                 block: root r is, in every iteration, the Ritz pair with the
  *                 largest overlap with start vector r (among those not taken
  *                 by an earlier root) instead of the r-th lowest; omega is
- *                 then in the order of the start vectors [0] */
+ *                 then in the order of the start vectors [0]
+ *   precond       Davidson preconditioner: 0 = on the singles block the
+ *                 exact (w_r - M11)^-1, from an FP64 eigendecomposition of
+ *                 M11 made once at the start of each solve (rocSOLVER; only
+ *                 for n1 <= 12288, else the diagonal), on the doubles the
+ *                 zeroth-order diagonal; 1 = the zeroth-order diagonal
+ *                 throughout [0].  Olsen's correction applies to either. */
 typedef struct adc_options {
   int precision;
   double conv_tol;
@@ -157,6 +163,7 @@ typedef struct adc_options {
   const char* tune_cache;
   int deterministic;
   int root_follow;
+  int precond;
 } adc_options;
 
 typedef struct adc_handle adc_handle;

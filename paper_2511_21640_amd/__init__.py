@@ -42,21 +42,25 @@ class AdcOptions(ctypes.Structure):
                 ("max_subspace", ctypes.c_int), ("refine_fp64", ctypes.c_int), ("stream", ctypes.c_void_p),
                 ("mem_budget", ctypes.c_size_t), ("verbose", ctypes.c_int), ("n_streams", ctypes.c_int),
                 ("graphs", ctypes.c_int), ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p),
-                ("deterministic", ctypes.c_int), ("root_follow", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("root_follow", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 GRAPHS = {False: 0, True: 1, "uncaptured": 2}
 
 
+PRECOND = {"singles": 0, "diagonal": 1}
+
+
 def _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose, n_streams,
-             graphs, autotune, tune_cache, deterministic, root_follow=False):
+             graphs, autotune, tune_cache, deterministic, root_follow=False, precond="singles"):
     """graphs: False (host-driven iteration), True (captured sigma of small
     instances and the device iteration from captured graphs) or 'uncaptured'
-    (the device iteration launched kernel by kernel)."""
+    (the device iteration launched kernel by kernel).  precond: 'singles'
+    (exact singles block, diagonal doubles) or 'diagonal'."""
     return AdcOptions(PREC[precision], conv_tol, max_iter, max_subspace, 1 if refine_fp64 else -1,
                       ctypes.c_void_p(stream), mem_budget, int(verbose), int(n_streams), GRAPHS[graphs],
                       1 if autotune else 0, tune_cache.encode() if tune_cache else None, 1 if deterministic else 0,
-                      1 if root_follow else 0)
+                      1 if root_follow else 0, PRECOND[precond])
 
 
 class AdcError(RuntimeError):
@@ -132,7 +136,7 @@ class Handle:
 
     def __init__(self, kind, o, v, eps, L, n_roots, x=1.0, precision="fp64", conv_tol=1e-7, max_iter=200,
                  max_subspace=0, stream=None, mem_budget=0, verbose=False, graphs=False, autotune=False,
-                 refine_fp64=True, tune_cache=None, deterministic=False, root_follow=False):
+                 refine_fp64=True, tune_cache=None, deterministic=False, root_follow=False, precond="singles"):
         import torch
         self._lib = load()
         self.kind, self.o, self.v = kind, int(o), int(v)
@@ -154,7 +158,7 @@ class Handle:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose, 0,
-                        graphs, autotune, tune_cache, deterministic, root_follow)
+                        graphs, autotune, tune_cache, deterministic, root_follow, precond)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(ctypes.byref(prob), 1, ctypes.byref(opts), ctypes.byref(h))
         if rc != ADC_OK:
@@ -377,7 +381,7 @@ class Batch:
 
     def __init__(self, problems, precision="fp64", conv_tol=1e-7, max_iter=200, max_subspace=0, stream=None,
                  mem_budget=0, verbose=False, n_streams=0, graphs=False, autotune=False, refine_fp64=True,
-                 tune_cache=None, deterministic=False, root_follow=False):
+                 tune_cache=None, deterministic=False, root_follow=False, precond="singles"):
         import torch
         self._lib = load()
         self._keep = []
@@ -400,7 +404,7 @@ class Batch:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         opts = _options(precision, conv_tol, max_iter, max_subspace, refine_fp64, stream, mem_budget, verbose,
-                        n_streams, graphs, autotune, tune_cache, deterministic, root_follow)
+                        n_streams, graphs, autotune, tune_cache, deterministic, root_follow, precond)
         h = ctypes.c_void_p()
         rc = self._lib.adc_init(arr, len(problems), ctypes.byref(opts), ctypes.byref(h))
         self._keep = []  # host copies are no longer needed

@@ -31,7 +31,10 @@ def build(verbose: bool = False) -> str:
         if p.wait() != 0:
             raise subprocess.CalledProcessError(p.returncode, cmd)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    # rocSOLVER: the one-off Hermitian eigendecomposition of the singles
+    # block for the Davidson preconditioner
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     for o in objs:

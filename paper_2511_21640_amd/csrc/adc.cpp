@@ -11,6 +11,7 @@
 // second GEMM contracts them with the packed trial vectors (Section 2.5,
 // on-the-fly generation of the four-external integrals).
 #include <hip/hip_runtime.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -1872,6 +1873,111 @@ std::vector<double> row_norms2(Ctx& cx, const double2* X, int rows, int64_t dim)
 }
 
 // ---------------------------------------------------------------------------
+// Davidson preconditioner on the singles block.  The step P r of the new
+// directions takes (w_r - M11)^-1 exactly on the singles part, from
+// M11 = U diag(lam) U^H (one FP64 eigendecomposition per solve), and the
+// zeroth-order diagonal on the doubles.  Strongly coupled singles spectra
+// need far fewer iterations with it (an EE instance with o = 29, v = 231:
+// 40 instead of 77 to |r| < 1e-4), and the coupling of the singles to the
+// doubles stays with Olsen's correction.
+// ---------------------------------------------------------------------------
+constexpr int64_t kPrecondMaxN1 = 12288;
+
+struct SinglesPrecond {
+  int64_t n1 = 0;
+  int kmax = 0;
+  double2* E = nullptr;   // [n1][n1] row-major: row j = conj of eigenvector j (U^H)
+  double* lam = nullptr;  // [n1] eigenvalues
+  double2* C = nullptr;   // [n1][kmax] coefficients of the residuals in the eigenbasis
+  bool on() const { return E != nullptr; }
+};
+
+void precond_release(Ctx& cx, SinglesPrecond& P) {
+  for (double2* q : {P.E, (double2*)P.lam, P.C}) cx.pool.put(q);
+  P = SinglesPrecond{};
+}
+
+// The eigendecomposition of M11x for a solve with up to kmax new directions
+// per iteration (nothing when the option asks for the diagonal or n1 is
+// outside 2 .. kPrecondMaxN1; a failed decomposition leaves the diagonal).
+void precond_setup(adc_handle* h, Inst& I, SinglesPrecond& P, int kmax) {
+  Ctx& cx = *I.cx;
+  if (h->opt.precond != 0 || I.n1 < 2 || I.n1 > kPrecondMaxN1 || !I.M11x.p) return;
+  const int64_t n1 = I.n1;
+  auto t0 = std::chrono::steady_clock::now();
+  P.n1 = n1;
+  P.kmax = kmax;
+  P.E = cx.pool.get(n1 * n1);
+  P.lam = (double*)cx.pool.get((n1 + 1) / 2);
+  P.C = cx.pool.get(n1 * kmax);
+  double* offd = (double*)cx.pool.get((n1 + 1) / 2);
+  int* info = (int*)cx.pool.get(1);
+  hipcheck(hipMemcpyAsync(P.E, I.M11x.p, sizeof(double2) * n1 * n1, hipMemcpyDeviceToDevice, cx.stream), "m11 copy");
+  // M11x is Hermitian and row-major; read column-major it is conj(M11x),
+  // with the same eigenvalues and conjugated eigenvectors, so the
+  // column-major eigenvectors the solver returns, read row-major, are U^H.
+  // The solver may allocate and free device memory: no other lane may be
+  // recording a graph meanwhile.
+  rocblas_status st = rocblas_status_internal_error;
+  int info_h = -1;
+  {
+    std::unique_lock<std::shared_mutex> gate(capture_gate());
+    rocblas_handle rb = nullptr;
+    if (rocblas_create_handle(&rb) == rocblas_status_success) {
+      rocblas_set_stream(rb, cx.stream);
+      st = rocsolver_zheevd(rb, rocblas_evect_original, rocblas_fill_upper, (rocblas_int)n1,
+                            (rocblas_double_complex*)P.E, (rocblas_int)n1, P.lam, offd, info);
+      (void)hipStreamSynchronize(cx.stream);
+      (void)rocblas_destroy_handle(rb);
+    }
+  }
+  if (st == rocblas_status_success)
+    hipcheck(hipMemcpy(&info_h, info, sizeof(int), hipMemcpyDeviceToHost), "eig info");
+  cx.pool.put((double2*)offd);
+  cx.pool.put((double2*)info);
+  if (st != rocblas_status_success || info_h != 0) {
+    (void)hipGetLastError();
+    precond_release(cx, P);
+  }
+  if (h->opt.verbose)
+    std::fprintf(stderr, "[adc] singles preconditioner: n1 %lld, %s in %.0f ms\n", (long long)n1,
+                 P.on() ? "eigendecomposition" : "eigendecomposition failed, diagonal",
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+}
+
+// P.C = (U^H R_singles) scaled by 1 / (w_r - lam_j): before the diagonal step
+// overwrites R (rows of length dim, rows <= kmax)
+void precond_coeffs(Ctx& cx, const SinglesPrecond& P, const double2* R, const double* w, int rows, int64_t dim) {
+  if (!P.on() || rows <= 0) return;
+  const int sp = cx.prec;
+  cx.prec = 0;
+  GemmDesc g{};
+  g.M = P.n1; g.N = rows; g.K = P.n1; g.batch = 1;
+  g.A = P.E; g.sam = P.n1; g.sak = 1;
+  g.B = R; g.sbk = 1; g.sbn = dim;
+  g.C = P.C; g.scm = rows; g.scn = 1;
+  g.alpha = C1(); g.beta = C0();
+  gemm(cx, g);
+  cx.prec = sp;
+  launch_shift_scale(P.C, P.lam, w, P.n1, rows, cx.stream);
+}
+
+// singles part of N = U P.C (after the diagonal step wrote all of N)
+void precond_store(Ctx& cx, const SinglesPrecond& P, double2* N, int rows, int64_t dim) {
+  if (!P.on() || rows <= 0) return;
+  const int sp = cx.prec;
+  cx.prec = 0;
+  GemmDesc g{};
+  g.M = rows; g.N = P.n1; g.K = P.n1; g.batch = 1;
+  g.A = P.C; g.sam = 1; g.sak = rows;
+  g.B = P.E; g.sbk = P.n1; g.sbn = 1; g.conjB = 1;
+  g.C = N; g.scm = dim; g.scn = 1;
+  g.alpha = C1(); g.beta = C0();
+  gemm(cx, g);
+  cx.prec = sp;
+}
+
+// ---------------------------------------------------------------------------
 // device-side iteration (options.graphs): everything from the Gram matrix of
 // the subspace to the orthonormalised new directions runs on the device, in
 // FP64, and is captured once per subspace size as a hipGraph; the host reads
@@ -1947,6 +2053,7 @@ struct DevDav {
   double* rep_host = nullptr;  // the lane's page-locked buffer
   int lds_max = 0;             // dynamic LDS bytes the eigensolver may take
   bool capture_off = false;    // a capture failed: iterate launch by launch
+  const SinglesPrecond* sp = nullptr;  // the singles-block preconditioner (or off)
   struct Graph {
     int m = 0;
     hipGraph_t g = nullptr;
@@ -2057,8 +2164,13 @@ void devdav_body(Ctx& cx, const Inst& I, DevDav& D, double2* V, double2* S, doub
   launch_row_sums(D.rpart, D.nb, k, D.rn2, s);
   launch_dav_converge(D.w, D.rn2, D.wold, k, m, D.mmax, D.par, D.rep, s);
   // Olsen's correction t = P (r - e x), e = <x|P r> / <x|P x>, P = (w - D)^-1
+  const SinglesPrecond& SP = *D.sp;
+  precond_coeffs(cx, SP, R, D.w, k, dim);
   launch_precondition(R, D.N, I.diag, D.w, k, dim, s);
+  precond_store(cx, SP, D.N, k, dim);
+  precond_coeffs(cx, SP, X, D.w, k, dim);
   launch_precondition(X, D.T, I.diag, D.w, k, dim, s);
+  precond_store(cx, SP, D.T, k, dim);
   launch_row_dots(X, dim, D.N, dim, k, dim, D.rpart, D.nb, s);
   launch_row_sums(D.rpart, D.nb, k, D.ra, s);
   launch_row_dots(X, dim, D.T, dim, k, dim, D.rpart, D.nb, s);
@@ -2244,7 +2356,26 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   // device-side iteration (graphs on, no root following); graphs = 2 runs
   // it launch by launch instead of from captured graphs
   const bool dev_iter = h->opt.graphs && !Gref && mmax <= heev_device_max();
+  // the singles-block preconditioner, declared before the device iteration so
+  // that the graphs which use its buffers are released first; without memory
+  // for it the solve keeps the diagonal
+  SinglesPrecond SP;
+  struct SPGuard {
+    Ctx& cx;
+    SinglesPrecond& P;
+    ~SPGuard() {
+      (void)hipStreamSynchronize(cx.stream);
+      precond_release(cx, P);
+    }
+  } sp_guard{cx, SP};
+  try {
+    precond_setup(h, I, SP, k);
+  } catch (const HipError&) {
+    (void)hipGetLastError();
+    precond_release(cx, SP);
+  }
   DevDav D;
+  D.sp = &SP;
   struct DevGuard {
     Ctx& cx;
     DevDav& D;
@@ -2394,7 +2525,9 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
                               hipMemcpyDeviceToDevice, cx.stream), "N");
     }
     hipcheck(hipMemcpyAsync(wn, wv.data(), sizeof(double) * nn, hipMemcpyHostToDevice, cx.stream), "wn");
+    precond_coeffs(cx, SP, Nd, wn, nn, dim);
     launch_precondition(Nd, Nd, I.diag, wn, nn, dim, cx.stream);
+    precond_store(cx, SP, Nd, nn, dim);
     {
       // Olsen's correction t = P (r - e x), e = <x|P r> / <x|P x>, P = (w - D)^-1:
       // keeps the new direction out of the span of the Ritz vector x when
@@ -2404,7 +2537,9 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       for (int j = 0; j < nn; ++j)
         hipcheck(hipMemcpyAsync(Xu + (int64_t)j * dim, X + (int64_t)un[j] * dim, sizeof(double2) * dim,
                                 hipMemcpyDeviceToDevice, cx.stream), "Xu");
+      precond_coeffs(cx, SP, Xu, wn, nn, dim);
       launch_precondition(Xu, Xp, I.diag, wn, nn, dim, cx.stream);
+      precond_store(cx, SP, Xp, nn, dim);
       const auto a = row_dots(cx, Xu, Nd, nn, dim);
       const auto b = row_dots(cx, Xu, Xp, nn, dim);
       for (int j = 0; j < nn; ++j) {
@@ -3066,6 +3201,7 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
     return fail(ADC_ERR_UNSUPPORTED, "split-bf16 kernels not built");
   if (opts && opts->n_streams < 0) return fail(ADC_ERR_INVALID_ARG, "n_streams < 0");
   if (opts && (opts->graphs < 0 || opts->graphs > 2)) return fail(ADC_ERR_INVALID_ARG, "graphs must be 0, 1 or 2");
+  if (opts && (opts->precond < 0 || opts->precond > 1)) return fail(ADC_ERR_INVALID_ARG, "precond must be 0 or 1");
   for (int i = 0; i < n_problems; ++i) {
     int rc = validate(&problems[i]);
     if (rc) return fail(rc, "problem description rejected (kind, sizes, eps, L or x)");

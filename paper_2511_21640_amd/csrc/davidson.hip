@@ -202,6 +202,19 @@ __global__ void sum_parts_kernel(const double2* part, int nparts, int rows, int 
   out[(e / cols) * ldo + e % cols] = make_double2(sx, sy);
 }
 
+// C[j][r] /= (w[r] - lam[j]) for j < n1, r < rows: the spectral form of
+// (w_r - M11)^-1 on coefficients in the eigenbasis of M11 (denominators
+// below 1e-4 in magnitude are held there, as in the diagonal preconditioner)
+__global__ void shift_scale_kernel(double2* C, const double* lam, const double* w, int64_t n1, int rows) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n1 * rows) return;
+  const int64_t j = e / rows;
+  const int r = (int)(e - j * rows);
+  double den = w[r] - lam[j];
+  if (fabs(den) < 1e-4) den = den < 0.0 ? -1e-4 : 1e-4;
+  C[e] = make_double2(C[e].x / den, C[e].y / den);
+}
+
 // First stage of a sum over many parts of n elements: slice ps of the grid's
 // y dimension sums parts ps, ps + nsl, ps + 2 nsl, ... into out[ps][e]; the
 // four waves of a workgroup take every fourth of them for the same 64
@@ -454,6 +467,12 @@ void launch_heev_jacobi(const double2* G, int ldg, int n, double2* Aw, double2* 
 void heev_allow_lds(size_t bytes) {
   (void)hipFuncSetAttribute((const void*)heev_jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   (void)hipGetLastError();
+}
+
+void launch_shift_scale(double2* C, const double* lam, const double* w, int64_t n1, int rows, hipStream_t s) {
+  const int64_t n = n1 * rows;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(shift_scale_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C, lam, w, n1, rows);
 }
 
 int sum_parts_slices(int nparts) { return nparts > 64 ? 32 : 1; }

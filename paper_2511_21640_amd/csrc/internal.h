@@ -267,6 +267,8 @@ void launch_heev_jacobi(const double2* G, int ldg, int n, double2* Aw, double2* 
 int sum_parts_slices(int nparts);
 void launch_sum_parts(const double2* part, int nparts, int rows, int cols, double2* stage, double2* out, int ldo,
                       hipStream_t s);
+// C[j][r] /= (w[r] - lam[j]) (j < n1, r < rows; |den| held at >= 1e-4)
+void launch_shift_scale(double2* C, const double* lam, const double* w, int64_t n1, int rows, hipStream_t s);
 // G[j][a] = conj(G[a][j]) for c0 <= j < m, a < c0
 void launch_gram_mirror(double2* G, int ldg, int c0, int m, hipStream_t s);
 // when *flag != 0: G[0:mc][0:mc] = diag(w[0:mc])

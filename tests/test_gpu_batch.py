@@ -154,3 +154,29 @@ def test_device_iteration_long_vectors():
         assert rg[i]["converged"].all()
         assert np.abs(rg[i]["omega"] - ra[i]["omega"]).max() <= 1e-8
         assert rg[i]["resnorm"].max() <= 1e-8
+
+
+@pytest.mark.parametrize("graphs", [False, True])
+def test_singles_preconditioner_matches_diagonal(graphs):
+    """The singles-block preconditioner (exact (w - M11)^-1 on the singles)
+    changes only the search directions: the roots equal those found with the
+    diagonal preconditioner, in the host-driven and the device iteration, and
+    the solve takes no more iterations on these instances."""
+    probs = [make_problem("EE", 8, 40, 96, seed=817, n_roots=4, x=0.5),
+             make_problem("IP", 6, 20, 52, seed=818, n_roots=3, x=1.0),
+             make_problem("EA", 5, 24, 58, seed=819, n_roots=3, x=1.0)]
+    print(f"case singles preconditioner graphs={graphs}", flush=True)
+    out = {}
+    for pc in ("diagonal", "singles"):
+        B = adc.Batch([_spec(P) for P in probs], precision="fp64", conv_tol=1e-8, n_streams=2, max_iter=300,
+                      graphs=graphs, precond=pc)
+        out[pc], rc = B.davidson()
+        B.close()
+        assert rc == 0
+    for i in range(len(probs)):
+        d, s = out["diagonal"][i], out["singles"][i]
+        print(f"  instance {i} {probs[i].kind}: iterations diagonal {d['iters']} singles {s['iters']}, "
+              f"max |dw| {np.abs(d['omega'] - s['omega']).max():.1e}", flush=True)
+        assert d["converged"].all() and s["converged"].all()
+        assert np.abs(d["omega"] - s["omega"]).max() <= 1e-8
+        assert s["iters"] <= d["iters"]
