@@ -250,7 +250,9 @@ int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, in
  *   converged    host int [sum n_roots]       1 if the root met the criteria
  * Subspace algebra (Gram matrix, Ritz vectors, residuals, norms,
  * preconditioner, orthogonalisation) runs in FP64 device kernels; the small
- * subspace eigenproblem runs on the host.  Synchronous.  Returns
+ * subspace eigenproblem runs on the host (or, with graphs, on the device);
+ * with precond = 0 each solve starts with one FP64 eigendecomposition of
+ * the singles block M11 on the device.  Synchronous.  Returns
  * ADC_NOT_CONVERGED if any root missed the criteria, ADC_ERR_NONFINITE_INPUT
  * if a subspace matrix holds NaN or Inf (e.g. from a non-finite guess). */
 int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs,
