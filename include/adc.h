@@ -145,9 +145,10 @@ typedef struct adc_problem {
  *   precond       Davidson preconditioner: 0 = on the singles block the
  *                 exact (w_r - M11)^-1, from an FP64 eigendecomposition of
  *                 M11 made once at the start of each solve (rocSOLVER; only
- *                 for n1 <= 12288, else the diagonal), on the doubles the
- *                 zeroth-order diagonal; 1 = the zeroth-order diagonal
- *                 throughout [0].  Olsen's correction applies to either. */
+ *                 for n1 <= 12288 and without deterministic, else the
+ *                 diagonal), on the doubles the zeroth-order diagonal; 1 =
+ *                 the zeroth-order diagonal throughout [0].  Olsen's
+ *                 correction applies to either. */
 typedef struct adc_options {
   int precision;
   double conv_tol;

@@ -1902,7 +1902,9 @@ void precond_release(Ctx& cx, SinglesPrecond& P) {
 // outside 2 .. kPrecondMaxN1; a failed decomposition leaves the diagonal).
 void precond_setup(adc_handle* h, Inst& I, SinglesPrecond& P, int kmax) {
   Ctx& cx = *I.cx;
-  if (h->opt.precond != 0 || I.n1 < 2 || I.n1 > kPrecondMaxN1 || !I.M11x.p) return;
+  // deterministic solves keep the diagonal: the solver library's own
+  // reduction order is not part of the library's bitwise guarantee
+  if (h->opt.precond != 0 || h->opt.deterministic || I.n1 < 2 || I.n1 > kPrecondMaxN1 || !I.M11x.p) return;
   const int64_t n1 = I.n1;
   auto t0 = std::chrono::steady_clock::now();
   P.n1 = n1;
