@@ -168,9 +168,8 @@ def c4_device_gb(kind, o, v, N, k):
     amplitudes and intermediates, M11, the cached split-bf16 planes.
     Transient (while its lane solves it): Davidson subspace (6k vectors of V and S, three k-blocks), the sigma
     workspace of one pass (unpacked doubles, at most 16 GiB), the ladder
-    batch (4 GiB), the planes of all packed <ab||cd> rows where they take
-    at most 16 GiB, and the eigenvectors of the singles block (the Davidson
-    preconditioner)."""
+    batch (4 GiB) and the planes of all packed <ab||cd> rows where they take
+    at most 16 GiB."""
     n = o + v
     Po, Pv = o * (o - 1) // 2, v * (v - 1) // 2
     n1 = {"EE": o * v, "IP": o, "EA": v}[kind]
@@ -189,8 +188,6 @@ def c4_device_gb(kind, o, v, N, k):
     # their own size in bytes)
     res += (res - N * n * n - 2 * n1 * n1)
     tr = (2 * 6 * k + 3 * k) * dim + min(k * 6 * unp, (16 << 30) // 16) + (4 << 30) // 16
-    if n1 <= 12288:  # the singles-block preconditioner's eigenvectors
-        tr += n1 * n1
     planes = 8 * Pv * (-(-Pv // 32) * 32)
     if kind != "IP" and planes <= (16 << 30):  # split-bf16 planes of all packed <ab||cd> rows
         tr += planes // 16
