@@ -279,8 +279,14 @@ void ladder_plan(adc_handle* h, Inst& I, int64_t wbytes, int64_t Kq) {
   (void)Kq;
   P.dprobs = (GroupProb*)dmalloc(h, sizeof(GroupProb) * P.probs.size());
   P.dblk = (LadBlk*)dmalloc(h, sizeof(LadBlk) * P.blk.size());
-  hipcheck(hipMemcpy(P.dprobs, P.probs.data(), sizeof(GroupProb) * P.probs.size(), hipMemcpyHostToDevice), "plan");
-  hipcheck(hipMemcpy(P.dblk, P.blk.data(), sizeof(LadBlk) * P.blk.size(), hipMemcpyHostToDevice), "plan");
+  // on the instance's own stream: a copy on the legacy default stream would
+  // wait on (and break) another lane's stream capture
+  Ctx& cx = *I.cx;
+  hipcheck(hipMemcpyAsync(P.dprobs, P.probs.data(), sizeof(GroupProb) * P.probs.size(), hipMemcpyHostToDevice,
+                          cx.stream), "plan");
+  hipcheck(hipMemcpyAsync(P.dblk, P.blk.data(), sizeof(LadBlk) * P.blk.size(), hipMemcpyHostToDevice, cx.stream),
+           "plan");
+  hipcheck(hipStreamSynchronize(cx.stream), "plan sync");
   P.wbudget = wbytes;
 }
 
@@ -1679,6 +1685,18 @@ double inst_cost(const Inst& I) {
   return 2 * N * Pv * Pv + k * (o * Pv * Pv + v * std::pow(o * v, 2));
 }
 
+// After a capture that failed: make sure the stream has left capture mode
+// (an invalidated capture can survive a failed end) and clear the error.
+void end_failed_capture(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  (void)hipGetLastError();
+}
+
 void sigma_call(adc_handle* h, Inst& I, const double2* Y, double2* S, int rows, int prec) {
   Ctx& cx = *I.cx;
   if (rows <= 0) return;
@@ -1729,7 +1747,7 @@ void sigma_call(adc_handle* h, Inst& I, const double2* Y, double2* S, int rows, 
     if (e != hipSuccess) {
       // no graph (e.g. no memory for the capture's own blocks): this
       // instance's sigma builds run eagerly from now on
-      (void)hipGetLastError();
+      end_failed_capture(cx.stream);
       if (ng.g) (void)hipGraphDestroy(ng.g);
       for (double2* p : ng.held) cx.pool.put(p);
       I.graphs_off = true;
@@ -1933,8 +1951,10 @@ void precond_setup(adc_handle* h, Inst& I, SinglesPrecond& P, int kmax) {
       (void)rocblas_destroy_handle(rb);
     }
   }
-  if (st == rocblas_status_success)
-    hipcheck(hipMemcpy(&info_h, info, sizeof(int), hipMemcpyDeviceToHost), "eig info");
+  if (st == rocblas_status_success) {
+    hipcheck(hipMemcpyAsync(&info_h, info, sizeof(int), hipMemcpyDeviceToHost, cx.stream), "eig info");
+    hipcheck(hipStreamSynchronize(cx.stream), "eig info sync");
+  }
   cx.pool.put((double2*)offd);
   cx.pool.put((double2*)info);
   if (st != rocblas_status_success || info_h != 0) {
@@ -2240,7 +2260,7 @@ void devdav_step(Ctx& cx, const Inst& I, DevDav& D, bool capture, double2* V, do
       if (e == hipSuccess) e = hipGraphInstantiate(&ng.ex, ng.g, nullptr, nullptr, 0);
       if (e != hipSuccess) {
         // no graph: this solve's iterations run launch by launch from now on
-        (void)hipGetLastError();
+        end_failed_capture(cx.stream);
         if (ng.g) (void)hipGraphDestroy(ng.g);
         for (double2* p : ng.held) cx.pool.put(p);
         D.capture_off = true;
@@ -2290,7 +2310,8 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     for (int i = 0; i < (int)I.n1 && (int)pos.size() < want; ++i) pos.push_back(idx[i]);
     if ((int)pos.size() < want) {
       std::vector<double> dd(dim);
-      hipcheck(hipMemcpy(dd.data(), I.diag, sizeof(double) * dim, hipMemcpyDeviceToHost), "dd");
+      hipcheck(hipMemcpyAsync(dd.data(), I.diag, sizeof(double) * dim, hipMemcpyDeviceToHost, cx.stream), "dd");
+      hipcheck(hipStreamSynchronize(cx.stream), "dd sync");
       std::vector<int64_t> id2(dim - I.n1);
       for (int64_t i = 0; i < (int64_t)id2.size(); ++i) id2[i] = I.n1 + i;
       std::stable_sort(id2.begin(), id2.end(), [&](int64_t a, int64_t b) { return dd[a] < dd[b]; });

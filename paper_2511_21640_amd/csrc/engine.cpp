@@ -384,6 +384,8 @@ int tune_cache_save(const char* path) {
 
 double* Ctx::pinned(size_t n) {
   if (n > pinned_n_) {
+    // freeing page-locked memory synchronises the device
+    std::unique_lock<std::shared_mutex> gate(capture_gate());
     if (pinned_) (void)hipHostFree(pinned_);
     pinned_ = nullptr;
     pinned_n_ = 0;
@@ -395,7 +397,10 @@ double* Ctx::pinned(size_t n) {
 }
 
 Ctx::~Ctx() {
-  if (pinned_) (void)hipHostFree(pinned_);
+  if (pinned_) {
+    std::unique_lock<std::shared_mutex> gate(capture_gate());
+    (void)hipHostFree(pinned_);
+  }
 }
 
 void gemm(Ctx& cx, GemmDesc g) {
