@@ -180,3 +180,26 @@ def test_singles_preconditioner_matches_diagonal(graphs):
         assert d["converged"].all() and s["converged"].all()
         assert np.abs(d["omega"] - s["omega"]).max() <= 1e-8
         assert s["iters"] <= d["iters"]
+
+
+def test_many_lanes_capture_while_others_plan_and_tune():
+    """Twelve uneven instances on four lanes with captured graphs and the
+    autotuner: while one lane records a graph, the others plan their ladder
+    assembly, tune GEMM shapes, decompose their singles block and grow their
+    report buffers.  Those steps never wait on a recording stream (copies on
+    the lane's own stream, device-wide syncs behind the capture gate), so
+    every solve, repeated on the same handle, gives the eager roots."""
+    probs = _draw(12, 23)
+    print("case twelve instances on four lanes, graphs + autotune", flush=True)
+    A = adc.Batch([_spec(P) for P in probs], precision="split_bf16", conv_tol=1e-7, n_streams=4)
+    ra, rca = A.davidson()
+    A.close()
+    G = adc.Batch([_spec(P) for P in probs], precision="split_bf16", conv_tol=1e-7, n_streams=4, graphs=True,
+                  autotune=True)
+    for rep in range(2):
+        rg, rcg = G.davidson()
+        assert rca == 0 and rcg == 0
+        for i in range(len(probs)):
+            assert rg[i]["converged"].all()
+            assert np.abs(rg[i]["omega"] - ra[i]["omega"]).max() <= 1e-7, (rep, i)
+    G.close()
