@@ -236,6 +236,43 @@ def c4_certify(draw, res, vec_host, budget_s):
             "per_instance": per}
 
 
+def run_c3(args):
+    """IP and EA on the large configuration (o=60, v=400, N_chol=2400, 6 roots,
+    x as configured): the split-bf16 solve (reduced-precision sweeps, then FP64
+    to the tolerance) against the FP64 solve, per root, each on its own handle
+    (one instance of this size at a time fits the device)."""
+    import torch
+    import paper_2511_21640_amd as adc
+    from adcgen import config_problem
+
+    out = {"metric": "eigenvalues, split-bf16 vs FP64 GPU solve", "data": "synthetic", "conv_tol": 3e-5,
+           "iteration": "device (captured graphs)", "kinds": {}}
+    for kind in ("IP", "EA"):
+        P = config_problem("C3-" + kind)
+        rec = {"o": P.o, "v": P.v, "n_chol": P.L.shape[0], "roots": P.n_roots, "x": P.x}
+        for prec in ("split_bf16", "fp64"):
+            t0 = time.perf_counter()
+            h = adc.Handle(kind, P.o, P.v, P.eps, P.L, P.n_roots, x=P.x, precision=prec, conv_tol=3e-5, graphs=True,
+                           verbose=args.verbose)
+            t_init = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            r = h.davidson(want_vectors=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            h.close()
+            torch.cuda.empty_cache()
+            rec[prec] = {"omega": r["omega"].tolist(), "iters": int(r["iters"]), "solve_s": t, "init_s": t_init,
+                         "converged": bool(r["converged"].all()), "max_resnorm": float(r["resnorm"].max())}
+            print(f"[c3] {kind} {prec}: init {t_init:.1f} s, solve {t:.1f} s, {r['iters']} iterations", file=sys.stderr,
+                  flush=True)
+        d = np.abs(np.array(rec["split_bf16"]["omega"]) - np.array(rec["fp64"]["omega"]))
+        rec["per_root_diff_Eh"] = d.tolist()
+        rec["max_abs_diff_Eh"] = float(d.max())
+        out["kinds"][kind] = rec
+        print(f"[c3] {kind}: max |omega mixed - omega fp64| {d.max():.2e} Eh", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
 def run_c4(args):
     """Batched workload: uneven EE/IP/EA instances (the 64-instance draw),
     solved in waves whose estimated device memory fits the budget; each wave
@@ -361,6 +398,8 @@ def main():
     ap.add_argument("--vendor-gemm", action="store_true",
                     help="with --only-sigma: also time torch's bf16 GEMM (hipBLASLt) on the flop of the build's "
                          "largest split-bf16 products")
+    ap.add_argument("--c3", action="store_true",
+                    help="IP and EA on the large configuration: split-bf16 vs FP64 solves, per root")
     ap.add_argument("--c4", type=int, default=0,
                     help="instead: batched solve of the first N instances of the 64-instance draw")
     ap.add_argument("--c4-budget-gb", type=float, default=200.0)
@@ -368,6 +407,9 @@ def main():
                     help="with --c4: CPU seconds for oracle certificates of the roots (cheapest instances first)")
     ap.add_argument("--verbose", action="store_true", help="one line per Davidson iteration on stderr")
     args = ap.parse_args()
+    if args.c3:
+        run_c3(args)
+        return
     if args.c4:
         run_c4(args)
         return

@@ -89,11 +89,13 @@ typedef struct adc_problem {
  *   max_subspace  subspace size before collapse to 2k [6k; at least 3k,
  *                 at most dim]
  *   refine_fp64   mixed precision only: 0 or 1 = iterate in the reduced
- *                 precision to a residual of 1e-4 (or conv_tol if larger),
- *                 then restart from the Ritz vectors in FP64 until the FP64
- *                 residual meets conv_tol [0 = 1]; -1 = no FP64 restart: the
- *                 reduced-precision sweep itself iterates to conv_tol and
- *                 the reported residuals are its own
+ *                 precision to a residual of max(1e-4, 1e-6 max|omega|) (or
+ *                 conv_tol if larger; the reduced precision leaves a residual
+ *                 floor of about 1e-7 |omega|), then restart from the Ritz
+ *                 vectors in FP64 until the FP64 residual meets conv_tol
+ *                 [0 = 1]; -1 = no FP64 restart: the reduced-precision sweep
+ *                 itself iterates to conv_tol and the reported residuals are
+ *                 its own
  *   stream        hipStream_t to enqueue on; NULL = a library-owned stream
  *   mem_budget    bytes of device workspace: sizes the <ab||cd> batches,
  *                 the largest temporary copy a contraction may make before it

@@ -2292,6 +2292,18 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   const int prec_mixed = h->opt.precision;
   int prec = prec_mixed;
   const double tol_mixed = 1e-4;
+  // The reduced-precision sweep ends where its own rounding puts a floor
+  // under the residual: about 1e-7 |omega| in split-bf16 (the rounding of
+  // M y, with |M y| ~ |omega| for a Ritz pair), which passes 1e-4 for roots
+  // beyond ~1000 Eh.  Its thresholds therefore scale with the largest root
+  // (the FP64 phase that follows iterates to conv_tol either way).
+  auto mixed_tols = [&](const std::vector<double>& wv, double& rt, double& dt) {
+    double wmax = 0.0;
+    for (double x : wv)
+      if (std::isfinite(x)) wmax = std::max(wmax, std::fabs(x));
+    rt = std::max({tol, tol_mixed, 1e-6 * wmax});
+    dt = std::max(1e-7, 1e-9 * wmax);
+  };
   double2* V = cx.pool.get((int64_t)mmax * dim);
   double2* S = cx.pool.get((int64_t)mmax * dim);
   double2* X = cx.pool.get((int64_t)k * dim);
@@ -2412,8 +2424,8 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   }
   for (it = 1; it <= max_iter && dev_iter; ++it) {
     auto t_it = now();
-    const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
-    const double dw_tol = refined_phase ? std::max(1e-10, tol * tol) : 1e-7;
+    double tol_now = tol, dw_tol = std::max(1e-10, tol * tol);
+    if (!refined_phase) mixed_tols(w, tol_now, dw_tol);  // w: the previous report's roots
     double* par_host = D.rep_host + D.rep_len();
     par_host[0] = tol_now;
     par_host[1] = dw_tol;
@@ -2506,12 +2518,12 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     launch_resid(AX, X, wd, R, k, dim, cx.stream);
     auto r2 = row_norms2(cx, R, k, dim);
     bool all = true;
-    const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
+    // |d omega| between iterations: 1e-10 Eh, or tol^2 when that is looser
+    // (the eigenvalue error of a residual r is at most |r|^2 / gap)
+    double tol_now = tol, dw_tol = std::max(1e-10, tol * tol);
+    if (!refined_phase) mixed_tols(w, tol_now, dw_tol);
     for (int r = 0; r < k; ++r) {
       rn[r] = std::sqrt(std::max(0.0, r2[r]));
-      // |d omega| between iterations: 1e-10 Eh, or tol^2 when that is looser
-      // (the eigenvalue error of a residual r is at most |r|^2 / gap)
-      const double dw_tol = refined_phase ? std::max(1e-10, tol * tol) : 1e-7;
       conv[r] = (rn[r] <= tol_now && std::fabs(w[r] - w_old[r]) <= dw_tol) ? 1 : 0;
       all = all && conv[r];
     }
