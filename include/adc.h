@@ -89,9 +89,11 @@ typedef struct adc_problem {
  *   max_subspace  subspace size before collapse to 2k [6k; at least 3k,
  *                 at most dim]
  *   refine_fp64   mixed precision only: 0 or 1 = iterate in the reduced
- *                 precision to a residual of max(1e-4, 1e-6 max|omega|) (or
- *                 conv_tol if larger; the reduced precision leaves a residual
- *                 floor of about 1e-7 |omega|), then restart from the Ritz
+ *                 precision to a residual of 1e-4 (or conv_tol if larger),
+ *                 or, once the largest residual is below 1e-6 max|omega|,
+ *                 until it has not come down by 10% for 15 iterations (the
+ *                 reduced precision leaves a residual floor of about 1e-7
+ *                 |omega|), then restart from the Ritz
  *                 vectors in FP64 until the FP64 residual meets conv_tol
  *                 [0 = 1]; -1 = no FP64 restart: the reduced-precision sweep
  *                 itself iterates to conv_tol and the reported residuals are

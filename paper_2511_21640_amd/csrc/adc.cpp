@@ -2292,17 +2292,28 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   const int prec_mixed = h->opt.precision;
   int prec = prec_mixed;
   const double tol_mixed = 1e-4;
-  // The reduced-precision sweep ends where its own rounding puts a floor
-  // under the residual: about 1e-7 |omega| in split-bf16 (the rounding of
-  // M y, with |M y| ~ |omega| for a Ritz pair), which passes 1e-4 for roots
-  // beyond ~1000 Eh.  Its thresholds therefore scale with the largest root
-  // (the FP64 phase that follows iterates to conv_tol either way).
-  auto mixed_tols = [&](const std::vector<double>& wv, double& rt, double& dt) {
-    double wmax = 0.0;
-    for (double x : wv)
-      if (std::isfinite(x)) wmax = std::max(wmax, std::fabs(x));
-    rt = std::max({tol, tol_mixed, 1e-6 * wmax});
-    dt = std::max(1e-7, 1e-9 * wmax);
+  // The reduced-precision sweep hands over at 1e-4, or when its largest
+  // residual, once below ten times its rounding floor, has not come down by
+  // 10% for 15 iterations: the sweep's own rounding puts a floor of about
+  // 1e-7 |omega| under the residual (the rounding of M y, |M y| ~ |omega|
+  // for a Ritz pair), above 1e-4 for roots beyond ~1000 Eh.  Above 1e-6
+  // |omega| a slow stretch is the iteration's own (strongly coupled roots),
+  // which the reduced precision still serves, so the window is not armed
+  double best_res = 1e300;
+  int best_it = 0;
+  auto mixed_stalled = [&](const std::vector<double>& rv, const std::vector<double>& wv, int itn) {
+    double mx = 0.0, wmax = 0.0;
+    for (double x : rv) mx = std::max(mx, x);
+    for (double x : wv) wmax = std::max(wmax, std::fabs(x));
+    if (mx < 0.9 * best_res || mx > 1e-6 * wmax) {
+      best_res = mx;
+      best_it = itn;
+    }
+    const bool st = itn - best_it >= 15;
+    if (st && h->opt.verbose)
+      std::fprintf(stderr, "[adc] it %3d: residual %.1e stalled near the reduced-precision floor, FP64 from here\n",
+                   itn, mx);
+    return st;
   };
   double2* V = cx.pool.get((int64_t)mmax * dim);
   double2* S = cx.pool.get((int64_t)mmax * dim);
@@ -2424,8 +2435,8 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
   }
   for (it = 1; it <= max_iter && dev_iter; ++it) {
     auto t_it = now();
-    double tol_now = tol, dw_tol = std::max(1e-10, tol * tol);
-    if (!refined_phase) mixed_tols(w, tol_now, dw_tol);  // w: the previous report's roots
+    const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
+    const double dw_tol = refined_phase ? std::max(1e-10, tol * tol) : 1e-7;
     double* par_host = D.rep_host + D.rep_len();
     par_host[0] = tol_now;
     par_host[1] = dw_tol;
@@ -2448,10 +2459,11 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       for (int r = 0; r < k; ++r) std::fprintf(stderr, "  %.10f (%.1e)", w[r], rn[r]);
       std::fprintf(stderr, "\n");
     }
-    if (all || nk == 0) {
+    const bool stalled = !refined_phase && mixed_stalled(rn, w, it);
+    if (all || nk == 0 || stalled) {
       if (!refined_phase) {
-        // mixed precision converged (or out of directions): restart from the
-        // Ritz vectors in FP64
+        // mixed precision converged (or out of directions, or stalled):
+        // restart from the Ritz vectors in FP64
         refined_phase = true;
         prec = 0;
         hipcheck(hipMemcpyAsync(V, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "restart");
@@ -2520,8 +2532,8 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
     bool all = true;
     // |d omega| between iterations: 1e-10 Eh, or tol^2 when that is looser
     // (the eigenvalue error of a residual r is at most |r|^2 / gap)
-    double tol_now = tol, dw_tol = std::max(1e-10, tol * tol);
-    if (!refined_phase) mixed_tols(w, tol_now, dw_tol);
+    const double tol_now = refined_phase ? tol : std::max(tol, tol_mixed);
+    const double dw_tol = refined_phase ? std::max(1e-10, tol * tol) : 1e-7;
     for (int r = 0; r < k; ++r) {
       rn[r] = std::sqrt(std::max(0.0, r2[r]));
       conv[r] = (rn[r] <= tol_now && std::fabs(w[r] - w_old[r]) <= dw_tol) ? 1 : 0;
@@ -2535,9 +2547,11 @@ int davidson_one(adc_handle* h, Inst& I, const double2* guess, double* omega, do
       std::fprintf(stderr, "\n");
     }
     w_old = w;
-    if (all) {
+    const bool stalled = !refined_phase && mixed_stalled(rn, w, it);
+    if (all || stalled) {
       if (refined_phase) break;
-      // mixed precision converged: restart from the Ritz vectors in FP64
+      // mixed precision converged (or stalled): restart from the Ritz
+      // vectors in FP64
       refined_phase = true;
       prec = 0;
       hipcheck(hipMemcpyAsync(V, X, sizeof(double2) * k * dim, hipMemcpyDeviceToDevice, cx.stream), "restart");
