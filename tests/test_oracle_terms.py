@@ -177,3 +177,32 @@ def test_adc2_column_depends_only_on_its_orbitals(kind):
         d[pos] = D
         assert np.abs(col[n1:] - d).max() <= 1e-14
         assert "vvvv" not in sub._g
+
+
+@pytest.mark.parametrize("kind,sign", [("EE", 0.0), ("IP", -1.0), ("EA", 1.0)])
+def test_uniform_orbital_energy_shift(kind, sign):
+    """Every denominator of the perturbation series (§2.1, the MP amplitudes
+    and the ADC blocks order by order) is a difference with as many occupied
+    as virtual energies, so eps -> eps + c shifts the Hamiltonian by c times
+    the particle number and leaves all of them alone: M moves by the change of
+    particle number times c (EE 0, IP -c, EA +c), all of it in the zeroth-order
+    diagonal blocks.  Checked on the Fock-space construction (O1) and block by
+    block, order by order on the matrix-free terms, where a wrong sign or
+    index in any energy denominator breaks it."""
+    o, v, c = 3, 5, 0.731
+    P = make_problem(kind, o, v, 20, seed=314, scale=0.3)
+    n1, n2 = dims(kind, o, v)
+    g = antisym_integrals(P.L)
+    for x in (0.0, 1.0):
+        dM = ISR(kind, P.eps + c, g, o).matrix(x) - ISR(kind, P.eps, g, o).matrix(x)
+        assert np.abs(dM - sign * c * np.eye(n1 + n2)).max() < 1e-12, x
+    ints, ints_c = Ints(P.eps, P.L, o), Ints(P.eps + c, P.L, o)
+    for blk, orders in [("11", (0, 1, 2, 3)), ("12", (0, 1, 2)), ("21", (0, 1, 2)), ("22", (0, 1))]:
+        for od in orders:
+            a, b = block_matrix(ints, kind, blk, od), block_matrix(ints_c, kind, blk, od)
+            if a.size == 0:
+                continue
+            ref = sign * c * np.eye(a.shape[0]) if (od == 0 and blk[0] == blk[1]) else 0.0
+            assert np.abs(b - a - ref).max() < 1e-12, (blk, od)
+            if od >= 2 or (od == 1 and blk != "11"):
+                assert np.abs(a).max() > 1e-6, (blk, od)  # the block is not trivially zero
