@@ -187,7 +187,10 @@ typedef struct adc_handle adc_handle;
  *   problems   host array of n_problems entries (read during the call only)
  *   opts       NULL = all defaults
  *   out        receives the handle; NULL on error
- * Errors: INVALID_ARG (shapes, NULL pointers, n_problems < 1),
+ * Errors: INVALID_ARG (shapes, NULL pointers, n_problems < 1, an option out
+ * of its documented range: negative or non-finite conv_tol, negative max_iter
+ * or max_subspace, refine_fp64 outside -1..1, an unknown precision, graphs or
+ * precond value; adc_last_error names it),
  * NONFINITE_INPUT (NaN/Inf in eps, x or L), NOT_HERMITIAN (max |L^Q - L^Q^H| >
  * 1e-12 max |L^Q| for some Q; L^Q is Hermitian as the MO transform of real AO
  * Cholesky vectors, eq. 42), OUT_OF_MEMORY, HIP_ERROR.  A borrowed device L

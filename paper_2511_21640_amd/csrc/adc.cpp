@@ -3251,6 +3251,12 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
   if (opts && opts->n_streams < 0) return fail(ADC_ERR_INVALID_ARG, "n_streams < 0");
   if (opts && (opts->graphs < 0 || opts->graphs > 2)) return fail(ADC_ERR_INVALID_ARG, "graphs must be 0, 1 or 2");
   if (opts && (opts->precond < 0 || opts->precond > 1)) return fail(ADC_ERR_INVALID_ARG, "precond must be 0 or 1");
+  if (opts && !(opts->conv_tol >= 0.0 && std::isfinite(opts->conv_tol)))
+    return fail(ADC_ERR_INVALID_ARG, "conv_tol must be finite and >= 0 (0 = default)");
+  if (opts && (opts->max_iter < 0 || opts->max_subspace < 0))
+    return fail(ADC_ERR_INVALID_ARG, "max_iter and max_subspace must be >= 0 (0 = default)");
+  if (opts && (opts->refine_fp64 < -1 || opts->refine_fp64 > 1))
+    return fail(ADC_ERR_INVALID_ARG, "refine_fp64 must be -1, 0 or 1");
   for (int i = 0; i < n_problems; ++i) {
     int rc = validate(&problems[i]);
     if (rc) return fail(rc, "problem description rejected (kind, sizes, eps, L or x)");

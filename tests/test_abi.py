@@ -87,6 +87,20 @@ def test_validation_errors(lib):
     assert lib.adc_init(arr, 1, ctypes.byref(opts), ctypes.byref(h)) == -1
     # the failed call leaves its detail for the calling thread
     assert isinstance(lib.adc_last_error(), bytes) and len(lib.adc_last_error()) > 0
+    # every option out of its documented range is rejected before any device
+    # work, and the detail names the option
+    for field, value, word in [("precision", 3, b"precision"), ("n_streams", -1, b"n_streams"),
+                               ("graphs", 3, b"graphs"), ("precond", 2, b"precond"),
+                               ("conv_tol", -1e-6, b"conv_tol"), ("conv_tol", float("nan"), b"conv_tol"),
+                               ("conv_tol", float("inf"), b"conv_tol"), ("max_iter", -1, b"max_iter"),
+                               ("max_subspace", -4, b"max_subspace"), ("refine_fp64", 2, b"refine_fp64"),
+                               ("refine_fp64", -2, b"refine_fp64")]:
+        opts = adc.AdcOptions()
+        setattr(opts, field, value)
+        h = ctypes.c_void_p()
+        assert lib.adc_init(arr, 1, ctypes.byref(opts), ctypes.byref(h)) == -1, field
+        assert not h.value
+        assert word in lib.adc_last_error(), (field, lib.adc_last_error())
 
 
 def test_strerror(lib):
