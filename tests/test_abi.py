@@ -103,6 +103,23 @@ def test_validation_errors(lib):
         assert word in lib.adc_last_error(), (field, lib.adc_last_error())
 
 
+def test_null_handle(lib):
+    """Every entry point that takes a handle rejects NULL with INVALID_ARG
+    before touching the device (the other arguments are NULL or 1)."""
+    for name in ("adc_dims", "adc_sigma", "adc_sigma_term", "adc_sigma_noalloc", "adc_properties", "adc_fns",
+                 "adc_davidson", "adc_sigma_backward"):
+        f = getattr(lib, name)
+        args = []
+        for t in f.argtypes:
+            if t in (ctypes.c_int, ctypes.c_longlong):
+                args.append(1)
+            elif t is ctypes.c_double:
+                args.append(0.5)
+            else:
+                args.append(None)
+        assert f(*args) == -1, name
+
+
 def test_strerror(lib):
     for c in (0, 1, -1, -2, -3, -4, -5, -6, 99):
         assert isinstance(lib.adc_strerror(c), bytes)
