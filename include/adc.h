@@ -398,9 +398,10 @@ void adc_free(adc_handle* h);
 const char* adc_strerror(int code);
 
 /* Detail of the calling thread's most recent failed call on a handle
- * (adc_init .. adc_sigma_backward): the check or step that failed and, for
- * HIP errors, the runtime's message; "" when that call succeeded or gave no
- * detail.  The text stays valid until the thread's next such call. */
+ * (adc_init .. adc_sigma_backward): the check or step that failed (an
+ * argument rejected up front names its entry point, "adc_sigma: ...") and,
+ * for HIP errors, the runtime's message; "" when that call succeeded.  The
+ * text stays valid until the thread's next such call. */
 const char* adc_last_error(void);
 
 #ifdef __cplusplus

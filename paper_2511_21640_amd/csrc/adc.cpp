@@ -2882,6 +2882,12 @@ void sigma_backward(adc_handle* h, Inst& I, const double2* Sbar, const double2* 
 // detail of the calling thread's last failed call (adc_last_error)
 thread_local std::string g_last_error;
 
+// an early rejection, with its detail for adc_last_error
+int reject(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
 template <class F>
 int guarded(F&& f) {
   try {
@@ -3338,7 +3344,8 @@ int adc_init(const adc_problem* problems, int n_problems, const adc_options* opt
 
 int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2) {
   g_last_error.clear();
-  if (!h || inst < 0 || inst >= (int)h->inst.size() || !n1 || !n2) return ADC_ERR_INVALID_ARG;
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !n1 || !n2)
+    return reject(ADC_ERR_INVALID_ARG, "adc_dims: NULL handle or output, or instance out of range");
   *n1 = h->inst[inst].n1;
   *n2 = h->inst[inst].n2;
   return ADC_OK;
@@ -3346,10 +3353,11 @@ int adc_dims(const adc_handle* h, int inst, long long* n1, long long* n2) {
 
 int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precision) {
   g_last_error.clear();
-  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
-  if (precision > 2) return ADC_ERR_INVALID_ARG;
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S)
+    return reject(ADC_ERR_INVALID_ARG, "adc_sigma: NULL handle, Y or S, instance out of range, k < 0 or Y == S");
+  if (precision > 2) return reject(ADC_ERR_INVALID_ARG, "adc_sigma: unknown precision");
   const int prec = precision < 0 ? h->opt.precision : precision;
-  if (prec == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
+  if (prec == ADC_SPLIT_BF16 && !kSplitBf16Built) return reject(ADC_ERR_UNSUPPORTED, "split-bf16 kernels not built");
   return guarded([&]() {
     Inst& I = h->inst[inst];
     lane_wait(h, *I.cx, true);
@@ -3363,10 +3371,13 @@ int adc_sigma(adc_handle* h, int inst, const void* Y, void* S, int k, int precis
 int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, int k, int precision) {
   g_last_error.clear();
   if (term == ADC_TERM_ALL) return adc_sigma(h, inst, Y, S, k, precision);
-  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
-  if (precision > 2 || term != ADC_TERM_LADDER) return ADC_ERR_INVALID_ARG;
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S)
+    return reject(ADC_ERR_INVALID_ARG,
+                  "adc_sigma_term: NULL handle, Y or S, instance out of range, k < 0 or Y == S");
+  if (precision > 2 || term != ADC_TERM_LADDER)
+    return reject(ADC_ERR_INVALID_ARG, "adc_sigma_term: unknown precision or term");
   Inst& I = h->inst[inst];
-  if (I.kind == ADC_IP) return ADC_ERR_UNSUPPORTED;
+  if (I.kind == ADC_IP) return reject(ADC_ERR_UNSUPPORTED, "adc_sigma_term: IP has no particle-particle ladder");
   const int prec = precision < 0 ? h->opt.precision : precision;
   return guarded([&]() {
     lane_wait(h, *I.cx, true);
@@ -3381,11 +3392,13 @@ int adc_sigma_term(adc_handle* h, int inst, int term, const void* Y, void* S, in
 
 int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, int precision) {
   g_last_error.clear();
-  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S) return ADC_ERR_INVALID_ARG;
-  if (precision > 2) return ADC_ERR_INVALID_ARG;
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || !S || k < 0 || Y == S)
+    return reject(ADC_ERR_INVALID_ARG,
+                  "adc_sigma_noalloc: NULL handle, Y or S, instance out of range, k < 0 or Y == S");
+  if (precision > 2) return reject(ADC_ERR_INVALID_ARG, "adc_sigma_noalloc: unknown precision");
   const int prec = precision < 0 ? h->opt.precision : precision;
-  if (prec == ADC_SPLIT_BF16 && !kSplitBf16Built) return ADC_ERR_UNSUPPORTED;
-  if (!h->scratch) return ADC_ERR_HIP;
+  if (prec == ADC_SPLIT_BF16 && !kSplitBf16Built) return reject(ADC_ERR_UNSUPPORTED, "split-bf16 kernels not built");
+  if (!h->scratch) return reject(ADC_ERR_HIP, "adc_sigma_noalloc: the fixed device scratch is not available");
   Inst& I = h->inst[inst];
   if (k == 0) return ADC_OK;
   if (noalloc_lower_bound(I, k, prec) > kScratchBytes) return ADC_ERR_SCRATCH;
@@ -3434,10 +3447,11 @@ int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, in
 int adc_properties(adc_handle* h, int inst, const void* Y, int k, void* rho, void* tdm, const void* d, double* dk,
                    double* tk) {
   g_last_error.clear();
-  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || k < 1) return ADC_ERR_INVALID_ARG;
-  if ((dk || tk) && !d) return ADC_ERR_INVALID_ARG;
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Y || k < 1)
+    return reject(ADC_ERR_INVALID_ARG, "adc_properties: NULL handle or Y, instance out of range or k < 1");
+  if ((dk || tk) && !d) return reject(ADC_ERR_INVALID_ARG, "adc_properties: dk or tk needs the operator d");
   Inst& I = h->inst[inst];
-  if (I.kind != ADC_EE) return ADC_ERR_UNSUPPORTED;
+  if (I.kind != ADC_EE) return reject(ADC_ERR_UNSUPPORTED, "adc_properties: EE instances only");
   return guarded([&]() {
     lane_wait(h, *I.cx, true);
     props_build(h, I, (const double2*)Y, k, (double2*)rho, (double2*)tdm, (const double2*)d, dk, tk);
@@ -3451,10 +3465,10 @@ int adc_fns(adc_handle* h, int inst, const void* X, double eta_crit, int* n_vir,
             double* eta_out, void* B_out, void* X_out) {
   g_last_error.clear();
   if (!h || inst < 0 || inst >= (int)h->inst.size() || !n_vir || !eps_out || !L_out || !std::isfinite(eta_crit))
-    return ADC_ERR_INVALID_ARG;
+    return reject(ADC_ERR_INVALID_ARG, "adc_fns: NULL handle or output, instance out of range or non-finite eta_crit");
   Inst& I = h->inst[inst];
-  if (X && I.kind == ADC_IP) return ADC_ERR_UNSUPPORTED;
-  if (X_out && !X) return ADC_ERR_INVALID_ARG;
+  if (X && I.kind == ADC_IP) return reject(ADC_ERR_UNSUPPORTED, "adc_fns: no state-specific density for IP");
+  if (X_out && !X) return reject(ADC_ERR_INVALID_ARG, "adc_fns: X_out needs X");
   return guarded([&]() {
     lane_wait(h, *I.cx, true);
     fns_build(h, I, (const double2*)X, eta_crit, n_vir, eps_out, (double2*)L_out, eta_out, (double2*)B_out,
@@ -3468,7 +3482,8 @@ int adc_fns(adc_handle* h, int inst, const void* X, double eta_crit, int* n_vir,
 int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* const* vecs, double* resnorm,
                  int* iters, int* converged) {
   g_last_error.clear();
-  if (!h || !omega || !resnorm || !iters || !converged) return ADC_ERR_INVALID_ARG;
+  if (!h || !omega || !resnorm || !iters || !converged)
+    return reject(ADC_ERR_INVALID_ARG, "adc_davidson: NULL handle or output array");
   // offsets of each instance's roots in the concatenated outputs
   std::vector<int64_t> off(h->inst.size() + 1, 0);
   for (size_t i = 0; i < h->inst.size(); ++i) off[i + 1] = off[i] + h->inst[i].k;
@@ -3493,7 +3508,8 @@ int adc_davidson(adc_handle* h, const void* const* guess, double* omega, void* c
 
 int adc_sigma_backward(adc_handle* h, int inst, const void* Sbar, const void* Y, int k, void* dL, double* dx) {
   g_last_error.clear();
-  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Sbar || !Y || k < 0) return ADC_ERR_INVALID_ARG;
+  if (!h || inst < 0 || inst >= (int)h->inst.size() || !Sbar || !Y || k < 0)
+    return reject(ADC_ERR_INVALID_ARG, "adc_sigma_backward: NULL handle, Sbar or Y, instance out of range or k < 0");
   return guarded([&]() {
     Inst& I = h->inst[inst];
     hipcheck(hipStreamSynchronize(h->cx.stream), "bw start");

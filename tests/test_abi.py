@@ -118,6 +118,7 @@ def test_null_handle(lib):
             else:
                 args.append(None)
         assert f(*args) == -1, name
+        assert lib.adc_last_error().startswith(name.encode() + b":"), (name, lib.adc_last_error())
 
 
 def test_strerror(lib):
