@@ -3401,8 +3401,10 @@ int adc_sigma_noalloc(adc_handle* h, int inst, const void* Y, void* S, int k, in
   if (!h->scratch) return reject(ADC_ERR_HIP, "adc_sigma_noalloc: the fixed device scratch is not available");
   Inst& I = h->inst[inst];
   if (k == 0) return ADC_OK;
-  if (noalloc_lower_bound(I, k, prec) > kScratchBytes) return ADC_ERR_SCRATCH;
-  if (I.noalloc_too_big[prec] > 0 && k >= I.noalloc_too_big[prec]) return ADC_ERR_SCRATCH;
+  if (noalloc_lower_bound(I, k, prec) > kScratchBytes)
+    return reject(ADC_ERR_SCRATCH, "adc_sigma_noalloc: the build needs more than the fixed device scratch");
+  if (I.noalloc_too_big[prec] > 0 && k >= I.noalloc_too_big[prec])
+    return reject(ADC_ERR_SCRATCH, "adc_sigma_noalloc: a build with this many vectors already exceeded the scratch");
   return guarded([&]() {
     Ctx& cx = *I.cx;
     // the build's temporaries come from the scratch; its passes, ladder
