@@ -206,3 +206,22 @@ def test_uniform_orbital_energy_shift(kind, sign):
             assert np.abs(b - a - ref).max() < 1e-12, (blk, od)
             if od >= 2 or (od == 1 and blk != "11"):
                 assert np.abs(a).max() > 1e-6, (blk, od)  # the block is not trivially zero
+
+
+@pytest.mark.parametrize("kind", ["EE", "IP", "EA"])
+def test_block_order_is_its_degree_in_the_integrals(kind):
+    """L -> s L scales every antisymmetrised integral by s^2 (eq. 43) and
+    leaves the orbital energies alone, so the order-n part of each block
+    (section 2.1: n powers of the fluctuation potential, counting each MP
+    amplitude by its own order) scales as s^(2n) exactly.  A term filed under
+    the wrong order, or missing or repeating an integral or amplitude
+    factor, breaks it."""
+    o, v, s = 3, 5, 1.7
+    P = make_problem(kind, o, v, 20, seed=2718, scale=0.3)
+    ints, ints_s = Ints(P.eps, P.L, o), Ints(P.eps, s * P.L, o)
+    for blk, orders in [("11", (0, 1, 2, 3)), ("12", (1, 2)), ("21", (1, 2)), ("22", (0, 1))]:
+        for od in orders:
+            a, b = block_matrix(ints, kind, blk, od), block_matrix(ints_s, kind, blk, od)
+            if a.size == 0 or np.abs(a).max() == 0.0:
+                continue
+            assert np.abs(b - s ** (2 * od) * a).max() <= 1e-12 * np.abs(b).max(), (blk, od)
