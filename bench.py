@@ -412,16 +412,20 @@ def main():
                     help="with --c4: CPU seconds for oracle certificates of the roots (cheapest instances first)")
     ap.add_argument("--verbose", action="store_true", help="one line per Davidson iteration on stderr")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on one GPU; "
+              f"sharding over several is not built)", file=sys.stderr)
+        sys.exit(2)
+    for opt, val, allowed in (("--c3-kinds", args.c3_kinds, ("IP", "EA")),
+                              ("--c3-precisions", args.c3_precisions, ("split_bf16", "fp64"))):
+        if not val or any(v not in allowed for v in val.split(",")):
+            ap.error(f"{opt} takes a comma-separated subset of {','.join(allowed)}")
     if args.c3:
         run_c3(args)
         return
     if args.c4:
         run_c4(args)
         return
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on one GPU; "
-              f"sharding over several is not built)", file=sys.stderr)
-        sys.exit(2)
 
     import torch
     import paper_2511_21640_amd as adc
